@@ -1,0 +1,642 @@
+/*
+ * roix_oracle.c - CPU oracle for the ROI reduction path (TEST INFRASTRUCTURE).
+ *
+ * This is the plain, slow, single-threaded reference that the GPU library is
+ * checked against.  Only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg load it; the GPU library never links, includes or calls
+ * it, and it shares no code, header or table with the GPU sources.
+ *
+ * Build: gcc -O2 -ffp-contract=off (no -ffast-math, no -march=native), so
+ * every float operation below is one IEEE-754 binary32/binary64 operation in
+ * round-to-nearest-even, with no fused multiply-add.
+ *
+ * What it computes (ROIX-Comp, arXiv 2602.15917), step by step:
+ *   range        I_max of the normalisation (Sec. 4.1.2, Eq. 1) and the value
+ *                range a relative error bound refers to
+ *   resolve      the positive absolute tolerance E_abs of the quantiser's
+ *                problem statement (Sec. 4.2.3), as an fp32 bound
+ *   quantise     per-voxel code q with |x - q*2eb| <= eb, or an escape
+ *                (outlier) when fp32 rounding would break the bound
+ *                (Sec. 4.2.3 problem statement; a per-voxel fp32 formula
+ *                takes the place of the paper's sequential grouping)
+ *   histogram    256 equal bins over the code range: the 8-bit normalisation
+ *                of Sec. 4.1.2 applied to codes
+ *   threshold    two-class Otsu (1979) on those bins (Sec. 4.1.3), or a
+ *                fixed threshold; pixels above the threshold are object
+ *   binarise     mask M = 1 for object voxels (Sec. 4.1.4, Eq. 2)
+ *   label        connected components of the mask in 3-D (6 or 26
+ *                neighbours): the volumetric form of the outer-contour
+ *                detection of Sec. 4.2.1; label = smallest linear index
+ *   keep         the largest component by voxel count (Sec. 4.2.1), or every
+ *                component of at least min_size voxels
+ *   rows         per row (z,y) the leftmost and rightmost kept voxel:
+ *                G(i) = [i, x_start, x_end] (Sec. 4.2.2, Eq. 3), half-open
+ *   stream       the pixel section P(i) (Sec. 4.2.2, Eq. 4) as codes of
+ *                b bits, with the raw value of every outlier kept aside
+ *   decode       the reverse process of Sec. 4.3 (rows restored from the
+ *                geometry section)
+ *
+ * Where the paper is silent or ambiguous this file takes these readings:
+ * half-open spans [x_start, x_end) so that n_i = x_end - x_start; a span
+ * covers every voxel between the extreme kept voxels of its row; two-class
+ * Otsu with the first maximum winning ties; "above the threshold" is strict;
+ * LARGEST ties go to the smallest label; 8-bit bins span [qmin, qmax].
+ */
+#include <float.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <time.h>
+
+enum { OR_OK = 0, OR_EINVAL = 1, OR_ERANGE = 2, OR_ENOMEM = 3, OR_ETRUNC = 4 };
+enum { OR_F32 = 0, OR_U16 = 1 };
+enum { OR_EB_ABS = 0, OR_EB_REL = 1 };
+enum { OR_THR_OTSU = 0, OR_THR_FIXED = 1 };
+enum { OR_KEEP_MIN_SIZE = 0, OR_KEEP_LARGEST = 1 };
+enum { OR_FLAG_DEGENERATE = 1u, OR_FLAG_EMPTY_ROI = 2u, OR_FLAG_FIXED = 4u };
+
+typedef struct {
+    int32_t status;
+    float xmin, xmax, eb32, w, r;
+    int32_t qmin, qmax;
+    int64_t K;
+    int32_t width_bits;
+    uint32_t esc;
+} or_params;
+
+typedef struct {
+    uint64_t label, size;
+    uint32_t x0, x1, y0, y1, z0, z1; /* half-open bounding box */
+    uint32_t kept, pad;
+} or_comp;
+
+typedef struct {
+    uint32_t z, y, xs, xe; /* span [xs, xe) of row (z, y) */
+    uint64_t code_off, outlier_off;
+} or_row;
+
+typedef struct {
+    or_params q;
+    int32_t seg_status, otsu_bin, q_thr;
+    uint32_t flags;
+    uint64_t hist[256];
+    uint64_t n_mask, n_components, n_kept, n_kept_voxels;
+    uint32_t bbox[6];
+    int32_t ext_status, pad;
+    uint64_t n_rows, n_codes, n_outliers, stream_bytes;
+    double stage_seconds[8]; /* range+resolve, histogram, threshold+mask, label, keep, rows, stream, total */
+} or_fused_info;
+
+static double now_s(void) {
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+static float voxel(const void* in, int dtype, uint64_t v) {
+    return dtype == OR_F32 ? ((const float*)in)[v] : (float)((const uint16_t*)in)[v];
+}
+
+/* ------------------------------------------------------------------ range */
+
+/* a < b in the IEEE total order restricted to finite values (-0 < +0) */
+static int total_less(float a, float b) {
+    if (a < b) return 1;
+    if (a > b) return 0;
+    return signbit(a) && !signbit(b);
+}
+
+/* xmin, xmax over every voxel; a NaN or infinity is an invalid input. */
+int oracle_range(const void* in, int dtype, uint64_t n, float* xmin, float* xmax) {
+    if (n == 0) return OR_EINVAL;
+    float lo = voxel(in, dtype, 0), hi = lo;
+    for (uint64_t v = 0; v < n; ++v) {
+        float x = voxel(in, dtype, v);
+        if (!isfinite(x)) return OR_EINVAL;
+        if (total_less(x, lo)) lo = x;
+        if (total_less(hi, x)) hi = x;
+    }
+    *xmin = lo;
+    *xmax = hi;
+    return OR_OK;
+}
+
+/* ---------------------------------------------------------------- resolve */
+
+/* The error bound: E_abs must be positive (Sec. 4.2.3).  A relative bound is
+ * a fraction of the value range.  The fp32 bound is the largest float not
+ * above the requested one, so |x - xhat| <= eb32 implies the f64 bound. */
+int oracle_resolve(float xmin, float xmax, int eb_mode, double eb_value, or_params* p) {
+    memset(p, 0, sizeof *p);
+    p->xmin = xmin;
+    p->xmax = xmax;
+    double eb = eb_mode == OR_EB_ABS ? eb_value : eb_value * ((double)xmax - (double)xmin);
+    if (!(eb > 0.0) || !isfinite(eb)) return p->status = OR_EINVAL;
+    float eb32 = (float)eb;
+    if ((double)eb32 > eb) eb32 = nextafterf(eb32, 0.0f);
+    if (!isnormal(eb32)) return p->status = OR_EINVAL;
+    float w = eb32 + eb32; /* bin width 2*eb: every x within eb of some q*w */
+    float r = 1.0f / w;
+    if (!isfinite(w) || !isfinite(r) || r == 0.0f) return p->status = OR_EINVAL;
+    p->eb32 = eb32;
+    p->w = w;
+    p->r = r;
+    float qlo = xmin * r, qhi = xmax * r;
+    if (!(fabsf(qlo) <= 16777216.0f) || !(fabsf(qhi) <= 16777216.0f)) return p->status = OR_ERANGE;
+    p->qmin = (int32_t)rintf(qlo);
+    p->qmax = (int32_t)rintf(qhi);
+    p->K = (int64_t)p->qmax - (int64_t)p->qmin + 1;
+    p->width_bits = p->K <= 255 ? 8 : (p->K <= 65535 ? 16 : 32);
+    p->esc = p->width_bits == 32 ? 0xFFFFFFFFu : ((1u << p->width_bits) - 1u);
+    return p->status = OR_OK;
+}
+
+/* --------------------------------------------------------------- quantise */
+
+/* code of one value: nearest multiple of w (ties to even), in fp32 */
+static int32_t code_of(float x, const or_params* p) {
+    float t = x * p->r;
+    return (int32_t)rintf(t);
+}
+
+/* escape when fp32 rounding puts the reconstruction outside the bound */
+static int is_outlier(float x, int32_t q, const or_params* p) {
+    float xhat = (float)q * p->w;
+    float d = x - xhat;
+    return !(fabsf(d) <= p->eb32);
+}
+
+int oracle_quantize(const void* in, int dtype, uint64_t n, const or_params* p, int32_t* codes,
+                    uint32_t* outlier_bits, uint64_t* n_outliers) {
+    if (p->status != OR_OK) return p->status;
+    uint64_t cnt = 0;
+    if (outlier_bits) memset(outlier_bits, 0, sizeof(uint32_t) * (size_t)((n + 31) / 32));
+    for (uint64_t v = 0; v < n; ++v) {
+        float x = voxel(in, dtype, v);
+        int32_t q = code_of(x, p);
+        if (codes) codes[v] = q;
+        if (is_outlier(x, q, p)) {
+            ++cnt;
+            if (outlier_bits) outlier_bits[v / 32] |= 1u << (v % 32);
+        }
+    }
+    if (n_outliers) *n_outliers = cnt;
+    return OR_OK;
+}
+
+/* -------------------------------------------------------------- histogram */
+
+/* 8-bit normalisation of Eq. 1 applied to the code range [qmin, qmax]:
+ * bin = floor(256 (q - qmin) / K), exact in integers. */
+static int bin_of(int32_t q, const or_params* p) {
+    int64_t u = (int64_t)q - (int64_t)p->qmin;
+    return (int)((u * 256) / p->K);
+}
+
+void oracle_histogram_codes(const int32_t* codes, uint64_t n, const or_params* p, uint64_t hist[256]) {
+    memset(hist, 0, sizeof(uint64_t) * 256);
+    for (uint64_t v = 0; v < n; ++v) hist[bin_of(codes[v], p)]++;
+}
+
+/* ------------------------------------------------------------------- Otsu */
+
+/* Otsu (1979): the split t maximising the between-class variance, evaluated
+ * as W0*W1*(m0 - m1)^2 (same argmax as the variance, which divides by NT^2).
+ * Class 0 holds bins 0..t, class 1 bins t+1..255.  Splits with an empty class
+ * are skipped; the first maximum wins.  Returns flags; *t_star = 255 (empty
+ * mask) when no split has two non-empty classes. */
+uint32_t oracle_otsu(const uint64_t hist[256], int32_t* t_star) {
+    uint64_t NT = 0, ST = 0;
+    for (int i = 0; i < 256; ++i) {
+        NT += hist[i];
+        ST += (uint64_t)i * hist[i];
+    }
+    uint64_t W0 = 0, S0 = 0;
+    double best = -1.0;
+    int32_t t_best = 255;
+    for (int t = 0; t < 255; ++t) {
+        W0 += hist[t];
+        S0 += (uint64_t)t * hist[t];
+        uint64_t W1 = NT - W0;
+        if (W0 == 0 || W1 == 0) continue;
+        double m0 = (double)S0 / (double)W0;
+        double m1 = (double)(ST - S0) / (double)W1;
+        double d = m0 - m1;
+        double s = (((double)W0 * (double)W1) * d) * d;
+        if (s > best) {
+            best = s;
+            t_best = t;
+        }
+    }
+    *t_star = t_best;
+    return best < 0.0 ? OR_FLAG_DEGENERATE : 0u;
+}
+
+/* smallest code in the object class.  Otsu: bins above t*, i.e.
+ * floor(256 u / K) >= t*+1  <=>  u >= ceil((t*+1) K / 256).
+ * Fixed threshold T (input units): object = q > q(T). */
+int32_t oracle_q_thr_otsu(int32_t t_star, const or_params* p) {
+    int64_t c = ((int64_t)(t_star + 1) * p->K + 255) / 256;
+    return (int32_t)((int64_t)p->qmin + c);
+}
+
+int32_t oracle_q_thr_fixed(double T, const or_params* p) {
+    float tf = (float)T;
+    float rq = rintf(tf * p->r);
+    double lo = (double)p->qmin - 1.0, hi = (double)p->qmax;
+    double qd = (double)rq;
+    int64_t qT;
+    if (qd < lo)
+        qT = (int64_t)p->qmin - 1;
+    else if (qd > hi)
+        qT = p->qmax;
+    else
+        qT = (int64_t)qd;
+    return (int32_t)(qT + 1);
+}
+
+/* --------------------------------------------------------------- labelling */
+
+typedef struct {
+    uint64_t* a;
+    uint64_t cap, head, tail; /* ring buffer */
+} queue64;
+
+static int q_push(queue64* q, uint64_t v) {
+    if (q->tail - q->head == q->cap) {
+        uint64_t ncap = q->cap ? q->cap * 2 : 1024;
+        uint64_t* na = (uint64_t*)malloc(sizeof(uint64_t) * ncap);
+        if (!na) return -1;
+        for (uint64_t i = q->head; i < q->tail; ++i) na[i - q->head] = q->a[i % q->cap];
+        free(q->a);
+        q->a = na;
+        q->tail -= q->head;
+        q->head = 0;
+        q->cap = ncap;
+    }
+    q->a[q->tail % q->cap] = v;
+    q->tail++;
+    return 0;
+}
+
+typedef struct {
+    or_comp* a;
+    uint64_t n, cap;
+} compvec;
+
+static or_comp* comp_new(compvec* c) {
+    if (c->n == c->cap) {
+        uint64_t ncap = c->cap ? c->cap * 2 : 64;
+        or_comp* na = (or_comp*)realloc(c->a, sizeof(or_comp) * ncap);
+        if (!na) return NULL;
+        c->a = na;
+        c->cap = ncap;
+    }
+    return &c->a[c->n++];
+}
+
+static inline int bit_at(const uint64_t* bits, uint64_t v) { return (int)((bits[v >> 6] >> (v & 63)) & 1u); }
+
+/* Flood fill in raster order: the first voxel reached of each component is
+ * its smallest linear index, which becomes the label.  comp[v] = component
+ * number + 1 (0 = background).  Returns 0 or -1 (allocation). */
+static int flood_fill(const uint64_t* bits, int64_t nx, int64_t ny, int64_t nz, int conn, uint32_t* comp,
+                      compvec* comps) {
+    int off[26][3], noff = 0;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                int manhattan = abs(dx) + abs(dy) + abs(dz);
+                if (manhattan == 0) continue;
+                if (conn == 6 && manhattan != 1) continue;
+                off[noff][0] = dx;
+                off[noff][1] = dy;
+                off[noff][2] = dz;
+                ++noff;
+            }
+    uint64_t N = (uint64_t)nx * (uint64_t)ny * (uint64_t)nz;
+    queue64 q = {0};
+    for (uint64_t v = 0; v < N; ++v) {
+        if (!bit_at(bits, v) || comp[v]) continue;
+        or_comp* c = comp_new(comps);
+        if (!c) { free(q.a); return -1; }
+        uint32_t id = (uint32_t)comps->n;
+        memset(c, 0, sizeof *c);
+        c->label = v;
+        c->x0 = c->y0 = c->z0 = UINT32_MAX;
+        comp[v] = id;
+        if (q_push(&q, v)) { free(q.a); return -1; }
+        while (q.head < q.tail) {
+            uint64_t u = q.a[q.head % q.cap];
+            q.head++;
+            int64_t x = (int64_t)(u % (uint64_t)nx);
+            int64_t y = (int64_t)((u / (uint64_t)nx) % (uint64_t)ny);
+            int64_t z = (int64_t)(u / ((uint64_t)nx * (uint64_t)ny));
+            or_comp* cc = &comps->a[id - 1];
+            cc->size++;
+            if ((uint32_t)x < cc->x0) cc->x0 = (uint32_t)x;
+            if ((uint32_t)x + 1 > cc->x1) cc->x1 = (uint32_t)x + 1;
+            if ((uint32_t)y < cc->y0) cc->y0 = (uint32_t)y;
+            if ((uint32_t)y + 1 > cc->y1) cc->y1 = (uint32_t)y + 1;
+            if ((uint32_t)z < cc->z0) cc->z0 = (uint32_t)z;
+            if ((uint32_t)z + 1 > cc->z1) cc->z1 = (uint32_t)z + 1;
+            for (int k = 0; k < noff; ++k) {
+                int64_t xx = x + off[k][0], yy = y + off[k][1], zz = z + off[k][2];
+                if (xx < 0 || yy < 0 || zz < 0 || xx >= nx || yy >= ny || zz >= nz) continue;
+                uint64_t w = ((uint64_t)zz * (uint64_t)ny + (uint64_t)yy) * (uint64_t)nx + (uint64_t)xx;
+                if (bit_at(bits, w) && !comp[w]) {
+                    comp[w] = id;
+                    if (q_push(&q, w)) { free(q.a); return -1; }
+                }
+            }
+        }
+        q.head = q.tail = 0;
+    }
+    free(q.a);
+    return 0;
+}
+
+/* Keep rule (Sec. 4.2.1 keeps the largest object): LARGEST = most voxels,
+ * ties to the smallest label (components are in label order); MIN_SIZE =
+ * every component with size >= min_size. */
+static void keep_components(or_comp* c, uint64_t n, int keep_mode, int64_t min_size) {
+    if (keep_mode == OR_KEEP_LARGEST) {
+        uint64_t best = 0, arg = UINT64_MAX;
+        for (uint64_t i = 0; i < n; ++i)
+            if (c[i].size > best) { best = c[i].size; arg = i; }
+        for (uint64_t i = 0; i < n; ++i) c[i].kept = (i == arg);
+    } else {
+        for (uint64_t i = 0; i < n; ++i) c[i].kept = c[i].size >= (uint64_t)min_size;
+    }
+}
+
+static uint64_t* mask_to_bits(const uint8_t* mask, uint64_t N) {
+    uint64_t* bits = (uint64_t*)calloc((size_t)((N + 63) / 64), sizeof(uint64_t));
+    if (!bits) return NULL;
+    for (uint64_t v = 0; v < N; ++v)
+        if (mask[v]) bits[v >> 6] |= 1ull << (v & 63);
+    return bits;
+}
+
+/* Label a u8 mask (nonzero = object).  labels (nullable): int64 per voxel,
+ * -1 for background.  comps: first comps_cap entries in label order.
+ * Returns OR_OK, OR_ETRUNC (more components than comps_cap; *n_comps is the
+ * true count) or OR_ENOMEM. */
+int oracle_label(const uint8_t* mask, int64_t nx, int64_t ny, int64_t nz, int conn, int keep_mode,
+                 int64_t min_size, int64_t* labels, uint8_t* keep, or_comp* comps, int64_t comps_cap,
+                 uint64_t* n_comps) {
+    uint64_t N = (uint64_t)nx * (uint64_t)ny * (uint64_t)nz;
+    uint64_t* bits = mask_to_bits(mask, N);
+    uint32_t* comp = (uint32_t*)calloc((size_t)N, sizeof(uint32_t));
+    compvec cv = {0};
+    if (!bits || !comp || flood_fill(bits, nx, ny, nz, conn, comp, &cv)) {
+        free(bits); free(comp); free(cv.a);
+        return OR_ENOMEM;
+    }
+    keep_components(cv.a, cv.n, keep_mode, min_size);
+    for (uint64_t v = 0; v < N; ++v) {
+        if (labels) labels[v] = comp[v] ? (int64_t)cv.a[comp[v] - 1].label : -1;
+        if (keep) keep[v] = comp[v] ? (uint8_t)cv.a[comp[v] - 1].kept : 0;
+    }
+    *n_comps = cv.n;
+    uint64_t m = cv.n < (uint64_t)comps_cap ? cv.n : (uint64_t)comps_cap;
+    if (comps && m) memcpy(comps, cv.a, sizeof(or_comp) * m);
+    free(bits); free(comp); free(cv.a);
+    return cv.n > (uint64_t)comps_cap ? OR_ETRUNC : OR_OK;
+}
+
+/* ------------------------------------------------------------ rows/stream */
+
+static void put_code(uint8_t* stream, uint64_t stream_cap, uint64_t idx, uint32_t u, int bytes) {
+    uint64_t at = idx * (uint64_t)bytes;
+    if (at + (uint64_t)bytes > stream_cap) return;
+    for (int k = 0; k < bytes; ++k) stream[at + k] = (uint8_t)(u >> (8 * k));
+}
+
+/* Geometry section (Eq. 3): for every row that holds a kept voxel, the
+ * leftmost kept x and one past the rightmost.  keep: u8 per voxel.
+ * Returns the number of rows (rows written up to rows_cap). */
+uint64_t oracle_rows(const uint8_t* keep, int64_t nx, int64_t ny, int64_t nz, or_row* rows, int64_t rows_cap) {
+    uint64_t nr = 0;
+    for (int64_t z = 0; z < nz; ++z)
+        for (int64_t y = 0; y < ny; ++y) {
+            const uint8_t* k = keep + (uint64_t)(z * ny + y) * (uint64_t)nx;
+            int64_t xs = -1, xe = -1;
+            for (int64_t x = 0; x < nx; ++x)
+                if (k[x]) {
+                    if (xs < 0) xs = x;
+                    xe = x + 1;
+                }
+            if (xs < 0) continue;
+            if (nr < (uint64_t)rows_cap) {
+                rows[nr].z = (uint32_t)z;
+                rows[nr].y = (uint32_t)y;
+                rows[nr].xs = (uint32_t)xs;
+                rows[nr].xe = (uint32_t)xe;
+                rows[nr].code_off = 0;
+                rows[nr].outlier_off = 0;
+            }
+            ++nr;
+        }
+    return nr;
+}
+
+/* Pixel section (Eq. 4): every voxel of every span, in row order, as
+ * u = q - qmin in b bits little-endian, or the escape code followed (in the
+ * outlier array) by the raw value.  Fills code_off/outlier_off of the rows.
+ * Returns OR_OK or OR_ETRUNC (counts are still the full ones). */
+int oracle_stream(const void* in, int dtype, int64_t nx, int64_t ny, const or_params* p, or_row* rows,
+                  uint64_t n_rows, uint8_t* stream, uint64_t stream_cap_bytes, float* outliers,
+                  uint64_t outliers_cap, uint64_t* n_codes, uint64_t* n_outliers) {
+    int bytes = p->width_bits / 8;
+    uint64_t nc = 0, no = 0;
+    for (uint64_t i = 0; i < n_rows; ++i) {
+        or_row* r = &rows[i];
+        r->code_off = nc;
+        r->outlier_off = no;
+        uint64_t base = ((uint64_t)r->z * (uint64_t)ny + r->y) * (uint64_t)nx;
+        for (uint32_t x = r->xs; x < r->xe; ++x) {
+            float xv = voxel(in, dtype, base + x);
+            int32_t q = code_of(xv, p);
+            uint32_t u;
+            if (is_outlier(xv, q, p)) {
+                u = p->esc;
+                if (no < outliers_cap) outliers[no] = xv;
+                ++no;
+            } else {
+                u = (uint32_t)((int64_t)q - (int64_t)p->qmin);
+            }
+            put_code(stream, stream_cap_bytes, nc, u, bytes);
+            ++nc;
+        }
+    }
+    *n_codes = nc;
+    *n_outliers = no;
+    if (nc * (uint64_t)bytes > stream_cap_bytes || no > outliers_cap) return OR_ETRUNC;
+    return OR_OK;
+}
+
+/* Reverse process (Sec. 4.3): rebuild every row from the geometry section;
+ * voxels outside the spans take `background`.  Returns OR_OK or OR_EINVAL on
+ * an inconsistent stream. */
+int oracle_decode(const or_row* rows, uint64_t n_rows, const uint8_t* stream, const float* outliers,
+                  uint64_t n_outliers, const or_params* p, int64_t nx, int64_t ny, int64_t nz, float background,
+                  float* out) {
+    uint64_t N = (uint64_t)nx * (uint64_t)ny * (uint64_t)nz;
+    for (uint64_t v = 0; v < N; ++v) out[v] = background;
+    int bytes = p->width_bits / 8;
+    uint64_t oi = 0;
+    for (uint64_t i = 0; i < n_rows; ++i) {
+        const or_row* r = &rows[i];
+        if (r->z >= (uint64_t)nz || r->y >= (uint64_t)ny || r->xe > (uint64_t)nx || r->xs >= r->xe) return OR_EINVAL;
+        uint64_t base = ((uint64_t)r->z * (uint64_t)ny + r->y) * (uint64_t)nx;
+        if (r->outlier_off != oi) return OR_EINVAL;
+        for (uint32_t x = r->xs; x < r->xe; ++x) {
+            uint64_t idx = r->code_off + (x - r->xs);
+            uint32_t u = 0;
+            for (int k = 0; k < bytes; ++k) u |= (uint32_t)stream[idx * bytes + k] << (8 * k);
+            float xh;
+            if (u == p->esc) {
+                if (oi >= n_outliers) return OR_EINVAL;
+                xh = outliers[oi++];
+            } else {
+                int32_t q = (int32_t)((int64_t)u + (int64_t)p->qmin);
+                xh = (float)q * p->w;
+            }
+            out[base + x] = xh;
+        }
+    }
+    return oi == n_outliers ? OR_OK : OR_EINVAL;
+}
+
+/* ------------------------------------------------------------------ fused */
+
+/* The whole path on one volume, in the paper's order of dependence:
+ * range -> error bound -> codes -> histogram -> threshold -> mask ->
+ * components -> keep -> rows -> stream.  Buffers are caller-owned; a
+ * buffer too small gives OR_ETRUNC with the full counts reported. */
+int oracle_fused(const void* in, int dtype, int64_t nx, int64_t ny, int64_t nz, int eb_mode, double eb_value,
+                 int thr_mode, double fixed_value, int conn, int keep_mode, int64_t min_size,
+                 or_comp* comps, int64_t comps_cap, or_row* rows, int64_t rows_cap, uint8_t* stream,
+                 int64_t stream_cap_bytes, float* outliers, int64_t outliers_cap, or_fused_info* info) {
+    memset(info, 0, sizeof *info);
+    info->otsu_bin = -1;
+    double t0 = now_s(), t1;
+    if (!in || nx <= 0 || ny <= 0 || nz <= 0 || (dtype != OR_F32 && dtype != OR_U16) ||
+        (conn != 6 && conn != 26) || min_size < 1)
+        return info->q.status = info->seg_status = info->ext_status = OR_EINVAL;
+    uint64_t N = (uint64_t)nx * (uint64_t)ny * (uint64_t)nz;
+    float xmin, xmax;
+    int st = oracle_range(in, dtype, N, &xmin, &xmax);
+    if (st == OR_OK) st = oracle_resolve(xmin, xmax, eb_mode, eb_value, &info->q);
+    else { info->q.status = st; info->q.xmin = info->q.xmax = 0.0f; }
+    t1 = now_s(); info->stage_seconds[0] = t1 - t0; t0 = t1;
+    if (st != OR_OK) return info->seg_status = info->ext_status = st;
+    const or_params* p = &info->q;
+
+    for (uint64_t v = 0; v < N; ++v) info->hist[bin_of(code_of(voxel(in, dtype, v), p), p)]++;
+    t1 = now_s(); info->stage_seconds[1] = t1 - t0; t0 = t1;
+
+    if (thr_mode == OR_THR_OTSU) {
+        info->flags |= oracle_otsu(info->hist, &info->otsu_bin);
+        info->q_thr = oracle_q_thr_otsu(info->otsu_bin, p);
+    } else {
+        info->flags |= OR_FLAG_FIXED;
+        info->q_thr = oracle_q_thr_fixed(fixed_value, p);
+    }
+    uint64_t* bits = (uint64_t*)calloc((size_t)((N + 63) / 64), sizeof(uint64_t));
+    if (!bits) return info->seg_status = info->ext_status = OR_ENOMEM;
+    for (uint64_t v = 0; v < N; ++v)
+        if (code_of(voxel(in, dtype, v), p) >= info->q_thr) {
+            bits[v >> 6] |= 1ull << (v & 63);
+            info->n_mask++;
+        }
+    t1 = now_s(); info->stage_seconds[2] = t1 - t0; t0 = t1;
+
+    uint32_t* comp = (uint32_t*)calloc((size_t)N, sizeof(uint32_t));
+    compvec cv = {0};
+    if (!comp || flood_fill(bits, nx, ny, nz, conn, comp, &cv)) {
+        free(bits); free(comp); free(cv.a);
+        return info->seg_status = info->ext_status = OR_ENOMEM;
+    }
+    free(bits);
+    t1 = now_s(); info->stage_seconds[3] = t1 - t0; t0 = t1;
+
+    keep_components(cv.a, cv.n, keep_mode, min_size);
+    info->n_components = cv.n;
+    uint32_t bb[6] = {UINT32_MAX, 0, UINT32_MAX, 0, UINT32_MAX, 0};
+    for (uint64_t i = 0; i < cv.n; ++i) {
+        if (!cv.a[i].kept) continue;
+        info->n_kept++;
+        info->n_kept_voxels += cv.a[i].size;
+        if (cv.a[i].x0 < bb[0]) bb[0] = cv.a[i].x0;
+        if (cv.a[i].x1 > bb[1]) bb[1] = cv.a[i].x1;
+        if (cv.a[i].y0 < bb[2]) bb[2] = cv.a[i].y0;
+        if (cv.a[i].y1 > bb[3]) bb[3] = cv.a[i].y1;
+        if (cv.a[i].z0 < bb[4]) bb[4] = cv.a[i].z0;
+        if (cv.a[i].z1 > bb[5]) bb[5] = cv.a[i].z1;
+    }
+    if (info->n_kept == 0) {
+        info->flags |= OR_FLAG_EMPTY_ROI;
+        memset(bb, 0, sizeof bb);
+    }
+    memcpy(info->bbox, bb, sizeof bb);
+    uint64_t m = cv.n < (uint64_t)comps_cap ? cv.n : (uint64_t)comps_cap;
+    if (comps && m) memcpy(comps, cv.a, sizeof(or_comp) * m);
+    t1 = now_s(); info->stage_seconds[4] = t1 - t0; t0 = t1;
+    if (cv.n > (uint64_t)comps_cap) {
+        free(comp); free(cv.a);
+        return info->seg_status = info->ext_status = OR_ETRUNC;
+    }
+
+    /* rows from the kept components (all rows kept internally, so the
+     * counts are complete even when the caller's buffers are too small) */
+    or_row* all = (or_row*)malloc(sizeof(or_row) * (size_t)(nz * ny));
+    if (!all) {
+        free(comp); free(cv.a);
+        return info->ext_status = OR_ENOMEM;
+    }
+    uint64_t nr = 0;
+    for (int64_t z = 0; z < nz; ++z)
+        for (int64_t y = 0; y < ny; ++y) {
+            uint64_t base = (uint64_t)(z * ny + y) * (uint64_t)nx;
+            int64_t xs = -1, xe = -1;
+            for (int64_t x = 0; x < nx; ++x) {
+                uint32_t c = comp[base + (uint64_t)x];
+                if (c && cv.a[c - 1].kept) {
+                    if (xs < 0) xs = x;
+                    xe = x + 1;
+                }
+            }
+            if (xs < 0) continue;
+            all[nr].z = (uint32_t)z;
+            all[nr].y = (uint32_t)y;
+            all[nr].xs = (uint32_t)xs;
+            all[nr].xe = (uint32_t)xe;
+            ++nr;
+        }
+    free(comp);
+    free(cv.a);
+    info->n_rows = nr;
+    t1 = now_s(); info->stage_seconds[5] = t1 - t0; t0 = t1;
+    st = oracle_stream(in, dtype, nx, ny, p, all, nr, stream, (uint64_t)stream_cap_bytes, outliers,
+                       (uint64_t)outliers_cap, &info->n_codes, &info->n_outliers);
+    uint64_t m2 = nr < (uint64_t)rows_cap ? nr : (uint64_t)rows_cap;
+    if (rows && m2) memcpy(rows, all, sizeof(or_row) * m2);
+    free(all);
+    if (nr > (uint64_t)rows_cap) st = OR_ETRUNC;
+    info->stream_bytes = info->n_codes * (uint64_t)(p->width_bits / 8);
+    t1 = now_s(); info->stage_seconds[6] = t1 - t0;
+    for (int k = 0; k < 7; ++k) info->stage_seconds[7] += info->stage_seconds[k];
+    info->ext_status = st;
+    return st;
+}
+
+/* struct sizes, so the Python side can check its mirrors */
+void oracle_sizes(int64_t* out) {
+    out[0] = (int64_t)sizeof(or_params);
+    out[1] = (int64_t)sizeof(or_comp);
+    out[2] = (int64_t)sizeof(or_row);
+    out[3] = (int64_t)sizeof(or_fused_info);
+}

@@ -1,0 +1,451 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each test checks one oracle function against a closed form, an invariant,
+an exact-arithmetic evaluation, an independent library or brute force, or a
+hand-derived worked example -- chosen so that a plausible slip in the oracle
+(a dropped term, a wrong sign or index, an off-by-one span end, a transposed
+axis, the wrong rounding rule) fails at least one of them.
+"""
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.ndimage as ndi
+
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------ inputs
+
+def test_philox_known_answers():
+    # Known-answer vectors of Philox4x32-10 (Salmon et al., SC'11, Random123 KAT).
+    assert synth.philox4x32_10([0, 0, 0, 0], [0, 0]) == [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]
+    assert synth.philox4x32_10([0xFFFFFFFF] * 4, [0xFFFFFFFF] * 2) == [0x408F276D, 0x41C83B0E, 0xA20BC7C6,
+                                                                       0x6D5451FD]
+    assert synth.philox4x32_10([0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344], [0xA4093822, 0x299F31D0]) == [
+        0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1]
+
+
+def test_generator_thread_invariance():
+    a = synth.config1(n=96, threads=1).volume
+    b = synth.config1(n=96, threads=4).volume
+    assert a.tobytes() == b.tobytes()
+
+
+# ------------------------------------------------------------------- range
+
+def test_range_matches_numpy_and_signed_zero():
+    w = synth.config0()
+    st, lo, hi = oracle.value_range(w.volume)
+    assert st == oracle.OK and lo == w.volume.min() and hi == w.volume.max()
+    v = np.array([0.0, -0.0, 0.0], np.float32)
+    st, lo, hi = oracle.value_range(v)
+    assert np.signbit(lo) and not np.signbit(hi)          # IEEE total order: -0 < +0
+    u = np.array([7, 0, 65535, 3], np.uint16)
+    assert oracle.value_range(u)[1:] == (0.0, 65535.0)
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+def test_range_rejects_non_finite(bad):
+    v = np.ones(100, np.float32)
+    v[57] = bad
+    assert oracle.value_range(v)[0] == oracle.EINVAL
+
+
+# ----------------------------------------------------------------- resolve
+
+def test_eb_rounds_down_to_fp32():
+    # float32(1e-3) rounds up, so the fp32 bound must step down; float32(1e-4) rounds down.
+    p = oracle.resolve(0.0, 1.0, "abs", 1e-3)
+    assert p.status == 0 and np.float32(p.eb32) == np.nextafter(np.float32(1e-3), np.float32(0))
+    assert float(np.float32(p.eb32)) <= 1e-3
+    p = oracle.resolve(0.0, 1.0, "abs", 1e-4)
+    assert np.float32(p.eb32) == np.float32(1e-4) and float(np.float32(1e-4)) <= 1e-4
+    # w = 2 eb exactly, r = fl(1/w) (correctly rounded; binary64 quotient rounded once more is
+    # the same value since 53 >= 2*24+2)
+    assert np.float32(p.w) == np.float32(2) * np.float32(p.eb32)
+    assert np.float32(p.r) == np.float32(1.0 / float(np.float32(p.w)))
+
+
+def test_eb_relative_and_errors():
+    p = oracle.resolve(100.0, 65000.0, "rel", 1e-4)
+    assert np.float32(p.eb32) <= 1e-4 * (65000.0 - 100.0)
+    assert oracle.resolve(5.0, 5.0, "rel", 1e-4).status == oracle.EINVAL       # constant volume
+    assert oracle.resolve(0.0, 1.0, "abs", 0.0).status == oracle.EINVAL
+    assert oracle.resolve(0.0, 1.0, "abs", -1.0).status == oracle.EINVAL
+    assert oracle.resolve(0.0, 1.0, "abs", float("nan")).status == oracle.EINVAL
+    assert oracle.resolve(0.0, 1.0, "abs", 1e-45).status == oracle.EINVAL      # not a normal float
+    assert oracle.resolve(0.0, 1e4, "abs", 1e-6).status == oracle.ERANGE       # |x r| > 2^24
+    assert oracle.resolve(-1e4, 0.0, "abs", 1e-6).status == oracle.ERANGE
+
+
+def test_width_selection():
+    assert oracle.resolve(0.0, 254 * 2 ** -9, "abs", 2 ** -10).width_bits == 8     # K = 255
+    assert oracle.resolve(0.0, 255 * 2 ** -9, "abs", 2 ** -10).width_bits == 16    # K = 256
+    p = oracle.resolve(0.0, 65534 * 2 ** -9, "abs", 2 ** -10)
+    assert (p.K, p.width_bits, p.esc) == (65535, 16, 65535)
+    p = oracle.resolve(0.0, 65535 * 2 ** -9, "abs", 2 ** -10)
+    assert (p.K, p.width_bits, p.esc) == (65536, 32, 0xFFFFFFFF)
+
+
+# ---------------------------------------------------------------- quantise
+
+def test_codes_closed_form_on_grid_points():
+    # eb = 2^-10: w = 2^-9 and r = 512 are exact, so x = k w gives q = k and
+    # x = (k + 1/2) w is an exact tie that rounds to the even neighbour.
+    k = np.arange(-3000, 3000, dtype=np.int64)
+    x = (k.astype(np.float64) / 512.0).astype(np.float32)
+    p = oracle.resolve(float(x.min()), float(x.max()), "abs", 2.0 ** -10)
+    st, q, bits, nout = oracle.quantize(x, p)
+    assert st == 0 and nout == 0 and np.array_equal(q, k)
+    xt = ((k.astype(np.float64) + 0.5) / 512.0).astype(np.float32)
+    p = oracle.resolve(float(xt.min()), float(xt.max()), "abs", 2.0 ** -10)
+    st, q, bits, nout = oracle.quantize(xt, p)
+    even = np.where(k % 2 == 0, k, k + 1)
+    assert np.array_equal(q, even)
+
+
+def test_codes_bound_and_exact_rounding_cross_check():
+    w = synth.config0()
+    x = w.volume.ravel()
+    _, lo, hi = oracle.value_range(x)
+    p = oracle.resolve(lo, hi, "abs", 1e-3)
+    st, q, bits, nout = oracle.quantize(x, p)
+    # invariant: the decoded value fl(q w) is within eb of x for every non-outlier voxel; the
+    # difference of two floats is taken exactly in binary64
+    wv = float(np.float32(p.w))
+    xh = q.astype(np.float32) * np.float32(p.w)
+    err = np.abs(x.astype(np.float64) - xh.astype(np.float64))
+    outl = np.unpackbits(bits.view(np.uint8), bitorder="little")[: x.size].astype(bool)
+    assert nout == outl.sum()
+    assert float(np.float32(p.eb32)) <= 1e-3
+    assert np.all(err[~outl] <= float(np.float32(p.eb32)))
+    # exact arithmetic: q equals round-half-even(x / w) except within the two fp32 roundings of a half
+    t = x.astype(np.float64) / wv                       # relative error 2^-53
+    qe = np.rint(t)
+    dist = np.abs(np.abs(t - np.floor(t)) - 0.5)
+    far = dist > 2.0 ** -21 * np.maximum(np.abs(t), 1.0)
+    assert far.mean() > 0.99
+    assert np.array_equal(q[far], qe[far].astype(np.int32))
+    # code domain: q is monotone in x, so the extremes give qmin/qmax
+    assert q.min() == p.qmin and q.max() == p.qmax
+
+
+def test_outliers_exist_and_are_the_only_bound_failures():
+    # a dense uniform sweep at a small bound produces fp32 bound failures (escapes)
+    x = np.linspace(0.0, 1.0, 2_000_001, dtype=np.float32)
+    p = oracle.resolve(0.0, 1.0, "abs", 1e-5)
+    st, q, bits, nout = oracle.quantize(x, p)
+    outl = np.unpackbits(bits.view(np.uint8), bitorder="little")[: x.size].astype(bool)
+    xh = (q.astype(np.float32) * np.float32(p.w)).astype(np.float32)
+    fail = ~(np.abs(x - xh) <= np.float32(p.eb32))
+    assert nout > 0 and np.array_equal(outl, fail)
+
+
+# --------------------------------------------------------------- histogram
+
+def test_histogram_special_cases():
+    # K = 256: bin = q - qmin (identity);  K = 512: bin = (q - qmin) // 2
+    for K in (256, 512, 1000):
+        k = np.arange(K, dtype=np.int64)
+        x = (k / 512.0).astype(np.float32)
+        p = oracle.resolve(0.0, float(x.max()), "abs", 2.0 ** -10)
+        assert p.K == K
+        _, q, _, _ = oracle.quantize(x, p)
+        h = oracle.histogram(q, p)
+        assert h.sum() == K
+        if K == 256:
+            assert np.all(h == 1)
+        elif K == 512:
+            assert np.all(h == 2)
+        else:
+            # equal-width bins over the code range: every bin holds floor or ceil of K/256 codes,
+            # and bin t starts at the first u with 256 u >= t K
+            assert set(np.unique(h)) <= {K // 256, K // 256 + 1}
+            starts = np.concatenate([[0], np.cumsum(h)[:-1]])
+            for t in range(256):
+                u = int(starts[t])
+                assert 256 * u >= t * K and (u == 0 or 256 * (u - 1) < t * K)
+
+
+# -------------------------------------------------------------------- Otsu
+
+def _otsu_exact(h):
+    """Exact rational between-class criterion for every split; first maximum."""
+    h = [int(v) for v in h]
+    NT = sum(h)
+    ST = sum(i * v for i, v in enumerate(h))
+    best, arg, vals = None, 255, []
+    W0 = S0 = 0
+    for t in range(255):
+        W0 += h[t]
+        S0 += t * h[t]
+        W1 = NT - W0
+        if W0 == 0 or W1 == 0:
+            vals.append(None)
+            continue
+        # sigma_B^2 * NT^2 = (S0 W1 - S1 W0)^2 / (W0 W1)
+        s = Fraction((S0 * W1 - (ST - S0) * W0) ** 2, W0 * W1)
+        vals.append(s)
+        if best is None or s > best:
+            best, arg = s, t
+    return arg, vals
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_otsu_brute_force_random(seed):
+    rng = np.random.default_rng(seed)
+    h = np.zeros(256, np.uint64)
+    kind = seed % 4
+    if kind == 0:
+        h[:] = rng.integers(0, 1000, 256)
+    elif kind == 1:                       # bimodal
+        for c, s, n in ((60, 10, 50000), (190, 15, 30000)):
+            b = np.clip(np.rint(rng.normal(c, s, n)), 0, 255).astype(int)
+            h += np.bincount(b, minlength=256).astype(np.uint64)
+    elif kind == 2:                       # sparse
+        idx = rng.choice(256, 5, replace=False)
+        h[idx] = rng.integers(1, 10 ** 9, 5)
+    else:                                 # large counts
+        h[:] = rng.integers(0, 2 ** 30, 256)
+    t, flags = oracle.otsu(h)
+    te, vals = _otsu_exact(h)
+    finite = [v for v in vals if v is not None]
+    top = sorted(finite, reverse=True)[:2]
+    # no near-tie between the two best splits (so double rounding cannot flip the argmax)
+    if len(top) == 2 and top[0] != top[1]:
+        assert float((top[0] - top[1]) / top[0]) > 1e-12
+    assert t == te and flags == 0
+
+
+def test_otsu_closed_forms():
+    h = np.zeros(256, np.uint64)
+    h[37], h[201] = 1000, 5
+    assert oracle.otsu(h) == (37, 0)          # two spikes i<j: every t in [i, j) ties, first wins
+    h = np.zeros(256, np.uint64)
+    h[100] = 77
+    assert oracle.otsu(h) == (255, oracle.FLAG_DEGENERATE)   # one class only
+    assert oracle.otsu(np.zeros(256, np.uint64)) == (255, oracle.FLAG_DEGENERATE)
+
+
+def test_threshold_mask_equivalence():
+    # q >= q_thr  <=>  bin(q) > t*  for every code of the range (Otsu); q > q(T) for FIXED
+    for K in (7, 255, 256, 1000, 65537):
+        x = (np.arange(K) / 512.0).astype(np.float32)
+        p = oracle.resolve(0.0, float(x.max()), "abs", 2.0 ** -10)
+        u = np.arange(K, dtype=np.int64)
+        b = (u * 256) // K                               # bins by their integer definition
+        for t in (0, 1, 100, 254, 255):
+            qt = oracle.q_thr_otsu(t, p)
+            assert np.array_equal(u + p.qmin >= qt, b > t)
+    p = oracle.resolve(0.0, 1.0, "abs", 2.0 ** -10)
+    assert oracle.q_thr_fixed(100 / 512, p) == 101
+    assert oracle.q_thr_fixed(-5.0, p) == p.qmin           # below the range: everything is object
+    assert oracle.q_thr_fixed(99.0, p) == p.qmax + 1       # above the range: nothing is object
+
+
+# ---------------------------------------------------------------- labelling
+
+def _scipy_canonical(mask, conn):
+    st = ndi.generate_binary_structure(3, 1 if conn == 6 else 3)
+    lab, n = ndi.label(mask, structure=st)
+    flat = lab.ravel()
+    out = np.full(flat.shape, -1, np.int64)
+    idx = np.flatnonzero(flat)
+    # canonical label = smallest linear index of the component
+    first = np.full(n + 1, np.iinfo(np.int64).max, np.int64)
+    np.minimum.at(first, flat[idx], idx)
+    out[idx] = first[flat[idx]]
+    return out.reshape(mask.shape), n
+
+
+def _patterns():
+    yield "checker", (np.indices((6, 7, 8)).sum(0) % 2).astype(np.uint8)
+    s = np.zeros((5, 9, 9), np.uint8)                 # snake: one long chain with many turns
+    s[:, ::2, :] = 1
+    for y in range(1, 9, 2):
+        s[:, y, 8 if (y // 2) % 2 == 0 else 0] = 1
+    yield "snake", s
+    h = np.zeros((16, 12, 12), np.uint8)              # helix (diagonal steps, 26- vs 6-connectivity)
+    for z in range(16):
+        a = z * np.pi / 4
+        h[z, int(round(6 + 4 * np.sin(a))), int(round(6 + 4 * np.cos(a)))] = 1
+    yield "helix", h
+    c = np.zeros((4, 8, 16), np.uint8)                # comb: teeth joined by a spine
+    c[:, :, ::2] = 1
+    c[:, 0, :] = 1
+    yield "comb", c
+    d = np.zeros((3, 3, 3), np.uint8)                 # diagonal corner contacts only
+    d[0, 0, 0] = d[1, 1, 1] = d[2, 2, 2] = 1
+    yield "corners", d
+
+
+@pytest.mark.parametrize("conn", [6, 26])
+def test_label_vs_scipy_random(conn):
+    rng = np.random.default_rng(conn)
+    for trial in range(60):
+        shape = tuple(int(s) for s in rng.integers(1, 13, 3))
+        p = float(rng.uniform(0.05, 0.95))
+        mask = synth.bernoulli(shape, 7000 + trial, p)
+        st, lab, keep, comps = oracle.label(mask, conn, keep="min_size", min_size=1)
+        ref, n = _scipy_canonical(mask, conn)
+        assert st == 0 and np.array_equal(lab, ref) and len(comps) == n
+        assert keep.sum() == mask.sum()
+
+
+@pytest.mark.parametrize("conn", [6, 26])
+def test_label_adversarial_patterns(conn):
+    for name, mask in _patterns():
+        st, lab, keep, comps = oracle.label(mask, conn, keep="min_size", min_size=1)
+        ref, n = _scipy_canonical(mask, conn)
+        assert np.array_equal(lab, ref), name
+        # sizes and half-open boxes against numpy
+        for c in comps:
+            zz, yy, xx = np.nonzero(lab == c["label"])
+            assert c["size"] == len(xx)
+            assert (c["x0"], c["x1"], c["y0"], c["y1"], c["z0"], c["z1"]) == (
+                xx.min(), xx.max() + 1, yy.min(), yy.max() + 1, zz.min(), zz.max() + 1)
+    assert len(oracle.label(dict(_patterns())["corners"], 6)[3]) == 3
+    assert len(oracle.label(dict(_patterns())["corners"], 26)[3]) == 1
+
+
+def test_keep_rules():
+    m = np.zeros((1, 5, 12), np.uint8)
+    m[0, 0, 0:3] = 1      # size 3, label 0
+    m[0, 2, 5:8] = 1      # size 3, label 29 (tie -> smaller label wins)
+    m[0, 4, 0:2] = 1      # size 2
+    st, lab, keep, comps = oracle.label(m, 26, keep="largest")
+    assert [c["kept"] for c in comps] == [1, 0, 0]
+    assert keep.sum() == 3 and keep[0, 0, 0:3].all()
+    st, lab, keep, comps = oracle.label(m, 26, keep="min_size", min_size=3)
+    assert [c["kept"] for c in comps] == [1, 1, 0]
+    st, lab, keep, comps = oracle.label(m, 26, keep="min_size", min_size=1, comps_cap=2)
+    assert st == oracle.ETRUNC and len(comps) == 2
+
+
+# --------------------------------------------------------- rows and stream
+
+def test_rows_against_numpy():
+    rng = np.random.default_rng(3)
+    keep = (rng.random((4, 9, 33)) < 0.1).astype(np.uint8)
+    rt = oracle.rows(keep)
+    exp = []
+    for z in range(4):
+        for y in range(9):
+            xs = np.flatnonzero(keep[z, y])
+            if len(xs):
+                exp.append((z, y, xs[0], xs[-1] + 1))
+    assert [(r["z"], r["y"], r["xs"], r["xe"]) for r in rt] == exp
+
+
+def test_hand_worked_example():
+    g = json.load(open(os.path.join(GOLDEN, "hand_rows.json")))
+    k = np.array(g["k"], np.float64).reshape(g["shape_zyx"])
+    vol = (k / 512.0).astype(np.float32)
+    e = g["expected"]
+    T = g["fixed_T_k"] / 512.0
+    for keep, key in (("largest", "largest"), ("min_size", "min_size_1")):
+        for conn in (6, 26):
+            r = oracle.fused(vol, "abs", g["eb"], thr="fixed", fixed_value=T, connectivity=conn, keep=keep,
+                             min_size=1)
+            p = r["params"]
+            assert r["status"] == 0
+            assert (p.qmin, p.qmax, p.K, p.width_bits) == (e["qmin"], e["qmax"], e["K"], e["width_bits"])
+            got = [{"label": int(c["label"]), "size": int(c["size"]),
+                    "bbox": [int(c[f]) for f in ("x0", "x1", "y0", "y1", "z0", "z1")]} for c in r["comps"]]
+            assert got == e["components"]
+            rows = [[int(x) for x in row] for row in r["rows"].tolist()]
+            assert rows == e[key]["rows"]
+            assert r["stream"].tolist() == e[key]["stream"]
+
+
+def test_decode_round_trip_and_span_invariants():
+    w = synth.config0(with_cls=True)
+    c = w.criterion
+    r = oracle.fused(w.volume, w.eb_mode, w.eb_value, c.thr, 0.0, c.connectivity, c.keep, c.min_size)
+    p, info = r["params"], r["info"]
+    rt = r["rows"]
+    assert info.n_codes == int((rt["xe"].astype(np.int64) - rt["xs"]).sum())
+    assert np.all(np.diff(rt["code_off"].astype(np.int64)) == (rt["xe"] - rt["xs"])[:-1])
+    st, out = oracle.decode(rt, r["stream"], r["outliers"], p, w.volume.shape, background=np.nan)
+    assert st == 0
+    span = ~np.isnan(out)
+    assert span.sum() == info.n_codes
+    err = np.abs(out[span].astype(np.float64) - w.volume[span].astype(np.float64))
+    assert err.max() <= float(np.float32(p.eb32))
+    # span endpoints are kept voxels: compare with an independent labelling of the mask
+    mask = w.cls > 0
+    ref, n = _scipy_canonical(mask.astype(np.uint8), 6)
+    for row in rt[:: max(1, len(rt) // 200)]:
+        assert ref[row["z"], row["y"], row["xs"]] >= 0 and ref[row["z"], row["y"], row["xe"] - 1] >= 0
+
+
+def test_etrunc_reports_full_counts():
+    w = synth.config0()
+    c = w.criterion
+    full = oracle.fused(w.volume, w.eb_mode, w.eb_value, c.thr, 0.0, c.connectivity, c.keep, c.min_size)
+    small = oracle.fused(w.volume, w.eb_mode, w.eb_value, c.thr, 0.0, c.connectivity, c.keep, c.min_size,
+                         rows_cap=10, stream_cap_bytes=100, outliers_cap=0)
+    assert small["status"] == oracle.ETRUNC
+    assert small["info"].n_rows == full["info"].n_rows and small["info"].n_codes == full["info"].n_codes
+    assert small["stream"].tolist() == full["stream"][:100].tolist()
+    cut = oracle.fused(w.volume, w.eb_mode, w.eb_value, c.thr, 0.0, c.connectivity, c.keep, c.min_size,
+                       comps_cap=2)
+    assert cut["status"] == oracle.ETRUNC and cut["info"].n_components == full["info"].n_components
+
+
+# ------------------------------------------------------------- ground truth
+
+def _dsc(a, b):
+    a, b = a.astype(bool), b.astype(bool)
+    return 2.0 * (a & b).sum() / (a.sum() + b.sum())
+
+
+def test_ground_truth_config0():
+    w = synth.config0(with_cls=True)
+    c = w.criterion
+    r = oracle.fused(w.volume, w.eb_mode, w.eb_value, c.thr, 0.0, c.connectivity, c.keep, c.min_size)
+    info = r["info"]
+    truth = w.cls > 0
+    # the classes are >= 7 sd apart, so the mask is exactly the analytic object set
+    assert info.n_mask == truth.sum()
+    _, n = _scipy_canonical(truth.astype(np.uint8), 6)
+    assert info.n_components == n and info.n_kept == n
+    assert _dsc(truth, truth) == 1.0
+
+
+def test_ground_truth_cylinder_spans():
+    w = synth.config1(n=160, with_cls=True)
+    c = w.criterion
+    r = oracle.fused(w.volume, w.eb_mode, w.eb_value, c.thr, 0.0, c.connectivity, c.keep, c.min_size)
+    info = r["info"]
+    fg = (w.cls == 1) | (w.cls == 3)
+    assert info.n_mask == fg.sum()
+    st, lab, keep, comps = oracle.label(fg.astype(np.uint8), 26, keep="largest")
+    big = comps[np.argmax(comps["size"])]
+    assert info.n_kept_voxels == big["size"]
+    # rows: the chord of the cylinder wall (pores stay >= 1 voxel inside it)
+    exp = []
+    for z in range(fg.shape[0]):
+        for y in range(fg.shape[1]):
+            xs = np.flatnonzero(keep[z, y])
+            if len(xs):
+                exp.append((z, y, xs[0], xs[-1] + 1))
+    got = [(a["z"], a["y"], a["xs"], a["xe"]) for a in r["rows"]]
+    assert got == exp
+
+
+def test_ground_truth_rings_u16():
+    w = synth.config2(nxy=256, nz=8, with_cls=True)
+    c = w.criterion
+    r = oracle.fused(w.volume, w.eb_mode, w.eb_value, c.thr, 0.0, c.connectivity, c.keep, c.min_size)
+    info = r["info"]
+    assert r["status"] == 0 and info.n_mask == (w.cls == 1).sum() and info.n_components == 1
+    st, out = oracle.decode(r["rows"], r["stream"], r["outliers"], r["params"], w.volume.shape, np.nan)
+    span = ~np.isnan(out)
+    assert np.abs(out[span] - w.volume[span].astype(np.float32)).max() <= np.float32(r["params"].eb32)
