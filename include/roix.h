@@ -1,0 +1,267 @@
+/*
+ * roix.h - C ABI of the MI355X ROI reduction library (libroix.so).
+ *
+ * The library runs the data-parallel reduction stage of ROIX-Comp
+ * (arXiv 2602.15917) on one gfx950 GPU, for a 3-D volume of float32 or
+ * uint16 voxels:
+ *
+ *   quantise  error-bounded codes, |x - xhat| <= E_abs for every voxel
+ *             (Sec. 4.2.3, problem statement of the absolute error-bounded
+ *             quantiser: input pixels and a positive tolerance E_abs)
+ *   segment   8-bit normalisation to a 256-bin histogram (Sec. 4.1.2, Eq. 1),
+ *             Otsu threshold (Sec. 4.1.3), binary mask (Sec. 4.1.4, Eq. 2),
+ *             3-D connected components and the largest object / a minimum
+ *             size (Sec. 4.2.1, volumetric form of the contour step)
+ *   extract   per row the leftmost and rightmost retained voxel,
+ *             G(i) = [i, x_start, x_end] (Sec. 4.2.2, Eq. 3), and the codes of
+ *             the voxels in between, P(i) (Sec. 4.2.2, Eq. 4), as one packed
+ *             stream with an index table (the 1-D array of Sec. 4.3)
+ *
+ * Conventions shared by every call:
+ *  - Volumes are C-contiguous [nz][ny][nx]; linear index v = (z*ny + y)*nx + x.
+ *  - d_* arguments are device pointers (hipMalloc'ed memory of the current
+ *    device, e.g. torch tensors); every input and output buffer is owned by
+ *    the caller.  The context owns only its scratch arena, allocated once in
+ *    roix_ctx_create.  No call allocates device memory.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Calls
+ *    are asynchronous: they validate their arguments, enqueue kernels and
+ *    return.  Results, including the status fields of the info structs, are
+ *    valid after the stream is synchronised.
+ *  - Argument errors are returned synchronously and enqueue nothing.  Data
+ *    errors are written to the `status` field of the device info structs:
+ *      ROIX_EINVAL  a NaN/Inf voxel; an error bound that is not a positive
+ *                   normal float32 after resolution (e.g. a relative bound
+ *                   on a constant volume); a code outside [qmin, qmax]
+ *                   given to roix_segment
+ *      ROIX_ERANGE  |x / (2 eb)| exceeds 2^24 (codes would not be exact)
+ *      ROIX_ENOMEM  more foreground runs than the scratch arena can hold
+ *      ROIX_ETRUNC  an output buffer is too small; the counts still report
+ *                   the required sizes (the component table is needed by
+ *                   the keep rule, so a short component table stops the
+ *                   path after labelling)
+ *    On a data error the contents of output buffers are unspecified, except
+ *    the info structs.
+ *  - A context is not thread-safe: use one context per host thread (or
+ *    serialise), and do not run two calls on one context concurrently on
+ *    different streams.
+ *  - No C++ exception crosses this interface.
+ */
+#ifndef ROIX_H
+#define ROIX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ROIX_OK = 0,
+    ROIX_EINVAL = 1,
+    ROIX_ERANGE = 2,
+    ROIX_ENOMEM = 3,
+    ROIX_ETRUNC = 4,
+    ROIX_EDEVICE = 5,
+    ROIX_EBUSY = 6,
+    ROIX_ESEQ = 7
+} roix_status;
+
+typedef enum { ROIX_F32 = 0, ROIX_U16 = 1 } roix_dtype;
+
+typedef struct {
+    int64_t nx, ny, nz; /* each >= 1; nx*ny*nz <= 2^33 */
+} roix_dims;
+
+/* Error bound (Sec. 4.2.3: a positive absolute tolerance).  REL means
+ * value * (xmax - xmin) of the volume.  The bound actually enforced, eb32,
+ * is the largest float32 not above the requested one. */
+typedef enum { ROIX_EB_ABS = 0, ROIX_EB_REL = 1 } roix_eb_mode;
+typedef struct {
+    int32_t mode; /* roix_eb_mode */
+    int32_t pad;
+    double value; /* > 0, finite */
+} roix_eb;
+
+/* ROI criterion.  OTSU: two-class Otsu (1979) on the 256-bin histogram of
+ * the codes (Sec. 4.1.3); the object class is the bins strictly above the
+ * split.  FIXED: voxels whose code is above the code of `fixed_value`
+ * (input units) are object.  Connectivity 6 or 26.  LARGEST keeps the
+ * component with the most voxels (ties: smallest label); MIN_SIZE keeps
+ * every component of at least `min_size` voxels. */
+typedef enum { ROIX_THR_OTSU = 0, ROIX_THR_FIXED = 1 } roix_thr_mode;
+typedef enum { ROIX_KEEP_MIN_SIZE = 0, ROIX_KEEP_LARGEST = 1 } roix_keep_mode;
+typedef struct {
+    int32_t thr;          /* roix_thr_mode */
+    int32_t connectivity; /* 6 | 26 */
+    double fixed_value;   /* FIXED only; finite */
+    int32_t keep;         /* roix_keep_mode */
+    int32_t pad;
+    int64_t min_size;     /* MIN_SIZE only; >= 1 */
+} roix_criterion;
+
+/* Resolved quantiser: q(x) = rint(x * r) (float32 multiply, ties to even),
+ * xhat = (float)q * w, outlier <=> !(|x - xhat| <= eb32); w = 2*eb32,
+ * r = 1/w rounded once.  Codes are stored as u = q - qmin in width_bits
+ * (8 if K <= 255, 16 if K <= 65535, else 32, K = qmax - qmin + 1); the
+ * escape code esc = 2^width_bits - 1 marks an outlier.
+ * n_outliers counts every voxel (roix_quantize); roix_fused does not
+ * compute it and sets ROIX_NOT_COMPUTED. */
+#define ROIX_NOT_COMPUTED UINT64_MAX
+typedef struct {
+    int32_t status;
+    float xmin, xmax; /* value range; xmin <= xmax in IEEE total order */
+    float eb32, w, r;
+    int32_t qmin, qmax;
+    int64_t K;
+    int32_t width_bits;
+    uint32_t esc;
+    uint64_t n_outliers;
+} roix_quant_info; /* 56 bytes */
+
+#define ROIX_FLAG_DEGENERATE_HISTOGRAM 1u /* no Otsu split has two non-empty classes */
+#define ROIX_FLAG_EMPTY_ROI 2u            /* no component kept */
+#define ROIX_FLAG_FIXED_THRESHOLD 4u
+
+/* hist[t] counts voxels with floor(256 (q - qmin) / K) == t.  otsu_bin = t*
+ * (-1 for FIXED); the mask is q >= q_thr.  bbox is the half-open box
+ * [x0,x1) x [y0,y1) x [z0,z1) of the kept components (all 0 when none). */
+typedef struct {
+    int32_t status;
+    int32_t otsu_bin;
+    int32_t q_thr;
+    uint32_t flags;
+    uint64_t hist[256];
+    uint64_t n_mask;        /* object voxels */
+    uint64_t n_components;
+    uint64_t n_kept;        /* kept components */
+    uint64_t n_kept_voxels;
+    uint32_t bbox[6];       /* x0, x1, y0, y1, z0, z1 */
+} roix_seg_info;
+
+/* One connected component, in ascending label order.  label = smallest
+ * linear voxel index of the component. */
+typedef struct {
+    uint64_t label;
+    uint64_t size;
+    uint32_t x0, x1, y0, y1, z0, z1; /* half-open */
+    uint32_t kept;
+    uint32_t pad;
+} roix_component; /* 48 bytes */
+
+/* Geometry section entry (Eq. 3) of row (z, y): the span [xs, xe) covers
+ * every voxel between the leftmost and the rightmost kept voxel, so
+ * n_i = xe - xs.  Its codes are stream[code_off .. code_off + n_i) (in
+ * codes, not bytes); its outliers start at outliers[outlier_off].  Rows
+ * without a kept voxel are omitted; rows are in raster order (z, then y). */
+typedef struct {
+    uint32_t z, y, xs, xe;
+    uint64_t code_off, outlier_off;
+} roix_row; /* 32 bytes */
+
+typedef struct {
+    int32_t status;
+    int32_t pad;
+    uint64_t n_rows;
+    uint64_t n_codes;
+    uint64_t n_outliers;
+    uint64_t stream_bytes; /* n_codes * width_bits / 8 */
+} roix_extract_info;
+
+/* Outputs of roix_extract / roix_fused.  Any info pointer may be NULL.
+ * Caps are element counts (bytes for the stream). */
+typedef struct {
+    roix_row* d_rows;
+    int64_t rows_cap;
+    void* d_stream;
+    int64_t stream_cap_bytes;
+    float* d_outliers;
+    int64_t outliers_cap;
+    roix_component* d_comps;
+    int64_t comps_cap;
+    roix_quant_info* d_qinfo;
+    roix_seg_info* d_sinfo;
+    roix_extract_info* d_einfo;
+} roix_fused_out;
+
+typedef struct roix_ctx roix_ctx;
+
+/* Create a context on `device` with a scratch arena of `scratch_bytes`
+ * (0 = 1 GiB).  The arena holds the per-voxel 8-bit bin proxy (N bytes),
+ * the row bitmask (N/8 bytes), per-row tables and the run tables of the
+ * labelling (17 bytes per foreground run); roix_scratch_bytes gives the size
+ * that never yields ROIX_ENOMEM for a volume.  Errors: ROIX_EINVAL (bad
+ * device / NULL out), ROIX_ENOMEM (allocation failed), ROIX_EDEVICE. */
+roix_status roix_ctx_create(int device, size_t scratch_bytes, roix_ctx** out);
+roix_status roix_ctx_destroy(roix_ctx* ctx);
+
+/* Worst-case scratch for a volume (every row holding ceil(nx/2) runs).
+ * Returns 0 for invalid dims. */
+size_t roix_scratch_bytes(roix_dims dims, roix_dtype dtype, const roix_criterion* crit);
+
+/* Worst-case output capacities: rows <= nz*ny, stream <= 4*N bytes,
+ * outliers <= N, components <= N (6-connectivity) or
+ * ceil(nx/2)*ceil(ny/2)*ceil(nz/2) (26-connectivity).  Any pointer may be
+ * NULL.  A caller that allocates these never sees ROIX_ETRUNC. */
+roix_status roix_bounds(roix_dims dims, roix_dtype dtype, const roix_criterion* crit, int64_t* max_rows,
+                        int64_t* max_stream_bytes, int64_t* max_outliers, int64_t* max_components);
+
+/* Quantise only (Sec. 4.2.3): d_codes[v] = q(x_v) (int32, N entries);
+ * d_outlier_bits (nullable) bit v%32 of word v/32 set for outliers
+ * (ceil(N/32) words); d_qinfo receives the resolved quantiser and the
+ * outlier count.  Errors: ROIX_EINVAL (NULL ctx/d_in/d_codes/d_qinfo, bad
+ * dims/dtype/eb). */
+roix_status roix_quantize(roix_ctx* ctx, const void* d_in, roix_dtype dtype, roix_dims dims, roix_eb eb,
+                          int32_t* d_codes, uint32_t* d_outlier_bits, roix_quant_info* d_qinfo, void* stream);
+
+/* Segment codes (Sec. 4.1.2-4.2.1): histogram, threshold, mask, 3-D
+ * components, keep rule.  d_codes and d_qinfo as written by roix_quantize.
+ * d_keep (N bytes): 1 for voxels of kept components.  d_labels (nullable,
+ * N int64): component label, -1 for background.  d_comps: components in
+ * label order (comps_cap entries).  Errors: ROIX_EINVAL (NULL
+ * ctx/d_codes/d_qinfo/crit/d_keep/d_sinfo, bad dims or criterion). */
+roix_status roix_segment(roix_ctx* ctx, const int32_t* d_codes, roix_dims dims, const roix_quant_info* d_qinfo,
+                         const roix_criterion* crit, uint8_t* d_keep, int64_t* d_labels, roix_component* d_comps,
+                         int64_t comps_cap, roix_seg_info* d_sinfo, void* stream);
+
+/* Extract (Sec. 4.2.2): rows of d_keep and the packed codes of the voxels of
+ * d_in inside each span, recomputed with the quantiser in d_qinfo.  Uses
+ * out->d_rows, d_stream, d_outliers and d_einfo (the component and
+ * segmentation fields are ignored).  Errors: ROIX_EINVAL (NULL arguments,
+ * bad dims/dtype). */
+roix_status roix_extract(roix_ctx* ctx, const void* d_in, roix_dtype dtype, const uint8_t* d_keep,
+                         roix_dims dims, const roix_quant_info* d_qinfo, const roix_fused_out* out,
+                         void* stream);
+
+/* The whole path in one call: range, bound, codes, histogram, threshold,
+ * components, keep, rows, stream.  No per-voxel code, mask or label array
+ * is materialised.  Output equals roix_quantize + roix_segment +
+ * roix_extract on the same input.  Errors: ROIX_EINVAL (NULL ctx/d_in/out,
+ * bad dims/dtype/eb/criterion), ROIX_ENOMEM (scratch arena smaller than the
+ * fixed per-voxel part), ROIX_EDEVICE (launch failure). */
+roix_status roix_fused(roix_ctx* ctx, const void* d_in, roix_dtype dtype, roix_dims dims, roix_eb eb,
+                       const roix_criterion* crit, const roix_fused_out* out, void* stream);
+
+/* Per-stage GPU timing.  When enabled, every kernel of the fused, staged
+ * and batched paths is bracketed by HIP events on its stream;
+ * roix_ctx_read_timing synchronises those events and returns, per stage,
+ * the accumulated milliseconds and launch counts since the last read
+ * (arrays of roix_stage_count() entries), then clears them. */
+int roix_stage_count(void);
+const char* roix_stage_name(int stage);
+roix_status roix_ctx_set_timing(roix_ctx* ctx, int enable);
+roix_status roix_ctx_read_timing(roix_ctx* ctx, double* ms, int64_t* launches);
+
+const char* roix_status_string(roix_status st);
+
+/* sizeof of a public struct by name ("roix_quant_info", "roix_seg_info",
+ * "roix_extract_info", "roix_component", "roix_row", "roix_fused_out",
+ * "roix_criterion", "roix_eb", "roix_dims"), 0 if unknown: lets bindings
+ * check their mirrors of this header. */
+size_t roix_sizeof(const char* type_name);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ROIX_H */

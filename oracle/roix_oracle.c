@@ -563,8 +563,14 @@ int oracle_fused(const void* in, int dtype, int64_t nx, int64_t ny, int64_t nz, 
     free(bits);
     t1 = now_s(); info->stage_seconds[3] = t1 - t0; t0 = t1;
 
-    keep_components(cv.a, cv.n, keep_mode, min_size);
     info->n_components = cv.n;
+    if (cv.n > (uint64_t)comps_cap) {
+        /* the keep rule needs the whole component table: stop after labelling,
+         * reporting the number of components the table must hold */
+        free(comp); free(cv.a);
+        return info->seg_status = info->ext_status = OR_ETRUNC;
+    }
+    keep_components(cv.a, cv.n, keep_mode, min_size);
     uint32_t bb[6] = {UINT32_MAX, 0, UINT32_MAX, 0, UINT32_MAX, 0};
     for (uint64_t i = 0; i < cv.n; ++i) {
         if (!cv.a[i].kept) continue;
@@ -582,13 +588,8 @@ int oracle_fused(const void* in, int dtype, int64_t nx, int64_t ny, int64_t nz, 
         memset(bb, 0, sizeof bb);
     }
     memcpy(info->bbox, bb, sizeof bb);
-    uint64_t m = cv.n < (uint64_t)comps_cap ? cv.n : (uint64_t)comps_cap;
-    if (comps && m) memcpy(comps, cv.a, sizeof(or_comp) * m);
+    if (comps && cv.n) memcpy(comps, cv.a, sizeof(or_comp) * cv.n);
     t1 = now_s(); info->stage_seconds[4] = t1 - t0; t0 = t1;
-    if (cv.n > (uint64_t)comps_cap) {
-        free(comp); free(cv.a);
-        return info->seg_status = info->ext_status = OR_ETRUNC;
-    }
 
     /* rows from the kept components (all rows kept internally, so the
      * counts are complete even when the caller's buffers are too small) */

@@ -1,0 +1,442 @@
+// api.hip - the C ABI of libroix.so: context and scratch arena, argument
+// checks, the launch sequences of the quantise / segment / extract / fused
+// calls, and per-stage event timing.
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "common.h"
+
+namespace roix {
+
+struct Timer {
+    bool on = false;
+    struct Open {
+        hipEvent_t a = nullptr;
+    } open[ST_COUNT];
+    struct Pending {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+};
+
+void timer_begin(Timer* t, int stage, hipStream_t s) {
+    if (!t || !t->on) return;
+    hipEvent_t e = t->get();
+    if (!e) return;
+    hipEventRecord(e, s);
+    t->open[stage].a = e;
+}
+
+void timer_end(Timer* t, int stage, hipStream_t s) {
+    if (!t || !t->on || !t->open[stage].a) return;
+    hipEvent_t e = t->get();
+    if (!e) return;
+    hipEventRecord(e, s);
+    t->pending.push_back({stage, t->open[stage].a, e});
+    t->open[stage].a = nullptr;
+}
+
+static const char* kStageNames[ST_COUNT] = {
+    "init", "range", "resolve", "quantize", "quant_hist", "otsu", "mask_runs", "scan", "runs_write",
+    "union", "flatten", "comp_stats", "keep", "spans", "emit", "voxel_out", "finalize"};
+
+}  // namespace roix
+
+using namespace roix;
+
+struct roix_ctx {
+    int device = 0;
+    int cus = 0;
+    void* arena = nullptr;
+    size_t arena_bytes = 0;
+    Timer timer;
+    int grid_stream = 2048;
+};
+
+// ----------------------------------------------------------------- layout
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static bool geom_of(roix_dims d, Geom* g) {
+    if (d.nx < 1 || d.ny < 1 || d.nz < 1) return false;
+    if (d.nx > (1ll << 31) - 64 || d.ny > (1ll << 31) || d.nz > (1ll << 31)) return false;
+    const unsigned __int128 n = (unsigned __int128)d.nx * d.ny * d.nz;
+    if (n > ((unsigned __int128)1 << 33)) return false;
+    if ((unsigned __int128)d.ny * d.nz >= ((unsigned __int128)1 << 31)) return false;
+    g->nx = d.nx;
+    g->ny = d.ny;
+    g->nz = d.nz;
+    g->N = (uint64_t)n;
+    g->nrows = d.ny * d.nz;
+    g->W = (d.nx + 63) / 64;
+    return true;
+}
+
+static constexpr uint64_t kRunBytes = 17;  // xs, xe, parent, comp id (4 B each) + kept flag (1 B)
+
+static uint64_t worst_runs(const Geom& g) {
+    uint64_t w = (uint64_t)g.nrows * (uint64_t)((g.nx + 1) / 2);
+    const uint64_t cap = (1ull << 31) - 1;
+    return w < cap ? w : cap;
+}
+
+// bytes of the per-voxel and per-row part of the arena
+static size_t fixed_bytes(const Geom& g) {
+    size_t b = 0;
+    b += align256(sizeof(DevState));
+    b += align256(g.N + 16);                              // proxy
+    b += align256((size_t)g.nrows * g.W * 8);             // mask bits
+    b += align256((size_t)g.nrows * 4);                   // row_nruns
+    b += align256((size_t)(g.nrows + 1) * 4);             // run_off
+    b += 2 * align256((size_t)g.nrows * 4);               // row_xs, row_xe
+    b += align256((size_t)g.nrows * 8);                   // row_packed
+    b += align256((size_t)((g.nrows + kEmitRows - 1) / kEmitRows) * 8);  // look-back
+    b += align256((size_t)(kScanBlocks + 1) * 8);         // scan tmp
+    b += 5 * 256;                                         // run-array alignment slack
+    return b;
+}
+
+static bool carve(roix_ctx* c, const Geom& g, Layout* L) {
+    const size_t fb = fixed_bytes(g);
+    if (c->arena_bytes < fb + kRunBytes) return false;
+    uint8_t* p = (uint8_t*)c->arena;
+    auto take = [&](size_t n) {
+        uint8_t* q = p;
+        p += align256(n);
+        return q;
+    };
+    L->S = (DevState*)take(sizeof(DevState));
+    L->proxy_alloc = take(g.N + 16);
+    L->proxy = L->proxy_alloc;
+    L->maskbits = (uint64_t*)take((size_t)g.nrows * g.W * 8);
+    L->row_nruns = (uint32_t*)take((size_t)g.nrows * 4);
+    L->run_off = (uint32_t*)take((size_t)(g.nrows + 1) * 4);
+    L->row_xs = (uint32_t*)take((size_t)g.nrows * 4);
+    L->row_xe = (uint32_t*)take((size_t)g.nrows * 4);
+    L->row_packed = (uint64_t*)take((size_t)g.nrows * 8);
+    L->lookback = (uint64_t*)take((size_t)((g.nrows + kEmitRows - 1) / kEmitRows) * 8);
+    L->scan_tmp = (uint64_t*)take((size_t)(kScanBlocks + 1) * 8);
+    const size_t used = (size_t)(p - (uint8_t*)c->arena) + 5 * 256;
+    uint64_t cap = (c->arena_bytes - used) / kRunBytes;
+    const uint64_t w = worst_runs(g);
+    if (cap > w) cap = w;
+    if (cap < 1) return false;
+    L->run_cap = cap;
+    L->run_xs = (uint32_t*)take(cap * 4);
+    L->run_xe = (uint32_t*)take(cap * 4);
+    L->parent = (uint32_t*)take(cap * 4);
+    L->comp_id = (uint32_t*)take(cap * 4);
+    L->kept_flag = (uint8_t*)take(cap);
+    return (size_t)(p - (uint8_t*)c->arena) <= c->arena_bytes;
+}
+
+static LaunchCtx lctx(roix_ctx* c, void* stream) {
+    LaunchCtx lc;
+    lc.stream = (hipStream_t)stream;
+    lc.timer = c->timer.on ? &c->timer : nullptr;
+    lc.grid_stream = c->grid_stream;
+    return lc;
+}
+
+static bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+static bool eb_ok(roix_eb eb) {
+    return (eb.mode == ROIX_EB_ABS || eb.mode == ROIX_EB_REL) && eb.value > 0.0 && eb.value <= 1.7976931348623157e308;
+}
+
+static bool crit_ok(const roix_criterion* c) {
+    if (!c) return false;
+    if (c->thr != ROIX_THR_OTSU && c->thr != ROIX_THR_FIXED) return false;
+    if (c->thr == ROIX_THR_FIXED && !(c->fixed_value >= -1.7976931348623157e308 && c->fixed_value <= 1.7976931348623157e308))
+        return false;
+    if (c->connectivity != 6 && c->connectivity != 26) return false;
+    if (c->keep != ROIX_KEEP_MIN_SIZE && c->keep != ROIX_KEEP_LARGEST) return false;
+    if (c->keep == ROIX_KEEP_MIN_SIZE && c->min_size < 1) return false;
+    return true;
+}
+
+static bool out_ok(const roix_fused_out* o, bool need_comps) {
+    if (!o) return false;
+    if (o->rows_cap < 0 || o->stream_cap_bytes < 0 || o->outliers_cap < 0 || o->comps_cap < 0) return false;
+    if (o->rows_cap > 0 && (!o->d_rows || !aligned(o->d_rows, 8))) return false;
+    if (o->stream_cap_bytes > 0 && (!o->d_stream || !aligned(o->d_stream, 4))) return false;
+    if (o->outliers_cap > 0 && (!o->d_outliers || !aligned(o->d_outliers, 4))) return false;
+    if (need_comps && o->comps_cap > 0 && (!o->d_comps || !aligned(o->d_comps, 8))) return false;
+    return true;
+}
+
+static roix_status dev_err(hipError_t e) { return e == hipSuccess ? ROIX_OK : ROIX_EDEVICE; }
+
+#define ROIX_TRY(x)                                   \
+    do {                                              \
+        hipError_t _e = (x);                          \
+        if (_e != hipSuccess) return ROIX_EDEVICE;    \
+    } while (0)
+
+// --------------------------------------------------------- shared stages
+
+// mask -> runs -> components -> stats -> keep (everything after the proxy)
+static hipError_t label_and_keep(const LaunchCtx& lc, const Geom& g, const Layout& L, const roix_criterion* crit,
+                                 roix_component* comps, int64_t comps_cap) {
+    hipError_t e;
+    if ((e = launch_mask_runs(lc, g, L)) != hipSuccess) return e;
+    if ((e = launch_scan_u32(lc, L.row_nruns, L.run_off, g.nrows, nullptr, &L.S->n_runs, L.run_off + g.nrows,
+                             L.scan_tmp)) != hipSuccess)
+        return e;
+    if ((e = launch_check_cap(lc, L.S, L.scan_tmp + kScanBlocks, L.run_cap, ROIX_ENOMEM)) != hipSuccess) return e;
+    if ((e = launch_runs_write(lc, g, L)) != hipSuccess) return e;
+    if ((e = launch_union(lc, g, L, crit->connectivity)) != hipSuccess) return e;
+    if ((e = launch_flatten(lc, L)) != hipSuccess) return e;
+    if ((e = launch_scan_u32(lc, L.comp_id, L.comp_id, (int64_t)L.run_cap, &L.S->n_runs, &L.S->n_comps, nullptr,
+                             L.scan_tmp)) != hipSuccess)
+        return e;
+    if ((e = launch_check_cap(lc, L.S, L.scan_tmp + kScanBlocks, (uint64_t)(comps ? comps_cap : 0), ROIX_ETRUNC)) !=
+        hipSuccess)
+        return e;
+    if ((e = launch_comp_stats(lc, g, L, comps)) != hipSuccess) return e;
+    return launch_keep(lc, L, comps, crit);
+}
+
+static hipError_t spans_and_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, const void* in, roix_dtype dt,
+                                 const roix_fused_out* out) {
+    hipError_t e;
+    if ((e = launch_scan_u64(lc, L.row_packed, L.row_packed, g.nrows, &L.S->span_total, L.scan_tmp)) != hipSuccess)
+        return e;
+    return launch_emit(lc, g, L, in, dt, out);
+}
+
+// ------------------------------------------------------------------- ABI
+
+extern "C" {
+
+const char* roix_status_string(roix_status st) {
+    switch (st) {
+        case ROIX_OK: return "ok";
+        case ROIX_EINVAL: return "invalid argument or input";
+        case ROIX_ERANGE: return "codes out of exact fp32 range";
+        case ROIX_ENOMEM: return "out of memory (scratch arena)";
+        case ROIX_ETRUNC: return "output buffer too small";
+        case ROIX_EDEVICE: return "device error";
+        case ROIX_EBUSY: return "busy";
+        case ROIX_ESEQ: return "out-of-sequence request";
+    }
+    return "unknown status";
+}
+
+size_t roix_sizeof(const char* t) {
+    if (!t) return 0;
+    struct {
+        const char* n;
+        size_t s;
+    } const tab[] = {{"roix_quant_info", sizeof(roix_quant_info)},   {"roix_seg_info", sizeof(roix_seg_info)},
+                     {"roix_extract_info", sizeof(roix_extract_info)}, {"roix_component", sizeof(roix_component)},
+                     {"roix_row", sizeof(roix_row)},                   {"roix_fused_out", sizeof(roix_fused_out)},
+                     {"roix_criterion", sizeof(roix_criterion)},       {"roix_eb", sizeof(roix_eb)},
+                     {"roix_dims", sizeof(roix_dims)}};
+    for (const auto& e : tab)
+        if (strcmp(e.n, t) == 0) return e.s;
+    return 0;
+}
+
+int roix_stage_count(void) { return ST_COUNT; }
+
+const char* roix_stage_name(int stage) { return (stage >= 0 && stage < ST_COUNT) ? kStageNames[stage] : nullptr; }
+
+size_t roix_scratch_bytes(roix_dims dims, roix_dtype dtype, const roix_criterion* crit) {
+    (void)crit;
+    Geom g;
+    if ((dtype != ROIX_F32 && dtype != ROIX_U16) || !geom_of(dims, &g)) return 0;
+    return fixed_bytes(g) + (size_t)worst_runs(g) * kRunBytes;
+}
+
+roix_status roix_bounds(roix_dims dims, roix_dtype dtype, const roix_criterion* crit, int64_t* max_rows,
+                        int64_t* max_stream_bytes, int64_t* max_outliers, int64_t* max_components) {
+    Geom g;
+    if ((dtype != ROIX_F32 && dtype != ROIX_U16) || !geom_of(dims, &g)) return ROIX_EINVAL;
+    if (max_rows) *max_rows = g.nrows;
+    if (max_stream_bytes) *max_stream_bytes = (int64_t)(g.N * 4);
+    if (max_outliers) *max_outliers = (int64_t)g.N;
+    if (max_components) {
+        const bool c26 = crit && crit->connectivity == 26;
+        *max_components = c26 ? ((g.nx + 1) / 2) * ((g.ny + 1) / 2) * ((g.nz + 1) / 2) : (int64_t)g.N;
+    }
+    return ROIX_OK;
+}
+
+roix_status roix_ctx_create(int device, size_t scratch_bytes, roix_ctx** out) {
+    if (!out) return ROIX_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return ROIX_EINVAL;
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess) return ROIX_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return ROIX_EDEVICE;
+    roix_ctx* c = new (std::nothrow) roix_ctx();
+    if (!c) return ROIX_ENOMEM;
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->cus = prop.multiProcessorCount;
+    if (c->cus <= 0) c->cus = 256;
+    c->grid_stream = c->cus * 8;
+    if (const char* s = getenv("ROIX_GRID_STREAM")) {
+        int v = atoi(s);
+        if (v > 0 && v <= 1 << 20) c->grid_stream = v;
+    }
+    c->arena_bytes = scratch_bytes ? scratch_bytes : ((size_t)1 << 30);
+    if (hipMalloc(&c->arena, c->arena_bytes) != hipSuccess) {
+        hipSetDevice(prev);
+        delete c;
+        return ROIX_ENOMEM;
+    }
+    hipSetDevice(prev);
+    *out = c;
+    return ROIX_OK;
+}
+
+roix_status roix_ctx_destroy(roix_ctx* ctx) {
+    if (!ctx) return ROIX_EINVAL;
+    int prev = 0;
+    hipGetDevice(&prev);
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    for (auto& p : ctx->timer.pending) {
+        hipEventDestroy(p.a);
+        hipEventDestroy(p.b);
+    }
+    for (auto e : ctx->timer.pool) hipEventDestroy(e);
+    hipFree(ctx->arena);
+    hipSetDevice(prev);
+    delete ctx;
+    return ROIX_OK;
+}
+
+roix_status roix_ctx_set_timing(roix_ctx* ctx, int enable) {
+    if (!ctx) return ROIX_EINVAL;
+    ctx->timer.on = enable != 0;
+    return ROIX_OK;
+}
+
+roix_status roix_ctx_read_timing(roix_ctx* ctx, double* ms, int64_t* launches) {
+    if (!ctx) return ROIX_EINVAL;
+    if (ms)
+        for (int i = 0; i < ST_COUNT; ++i) ms[i] = 0.0;
+    if (launches)
+        for (int i = 0; i < ST_COUNT; ++i) launches[i] = 0;
+    roix_status st = ROIX_OK;
+    for (auto& p : ctx->timer.pending) {
+        float t = 0.0f;
+        if (hipEventSynchronize(p.b) != hipSuccess || hipEventElapsedTime(&t, p.a, p.b) != hipSuccess)
+            st = ROIX_EDEVICE;
+        if (ms) ms[p.stage] += (double)t;
+        if (launches) launches[p.stage] += 1;
+        ctx->timer.pool.push_back(p.a);
+        ctx->timer.pool.push_back(p.b);
+    }
+    ctx->timer.pending.clear();
+    return st;
+}
+
+roix_status roix_quantize(roix_ctx* ctx, const void* d_in, roix_dtype dtype, roix_dims dims, roix_eb eb,
+                          int32_t* d_codes, uint32_t* d_outlier_bits, roix_quant_info* d_qinfo, void* stream) {
+    Geom g;
+    if (!ctx || !d_in || !d_codes || !d_qinfo || !geom_of(dims, &g) || !eb_ok(eb)) return ROIX_EINVAL;
+    if (dtype != ROIX_F32 && dtype != ROIX_U16) return ROIX_EINVAL;
+    if (!aligned(d_in, dtype == ROIX_F32 ? 4 : 2) || !aligned(d_codes, 4) ||
+        (d_outlier_bits && !aligned(d_outlier_bits, 4)))
+        return ROIX_EINVAL;
+    Layout L;
+    if (!carve(ctx, g, &L)) return ROIX_ENOMEM;
+    LaunchCtx lc = lctx(ctx, stream);
+    ROIX_TRY(launch_init(lc, L.S, L.lookback, 0));
+    ROIX_TRY(launch_range(lc, d_in, dtype, g.N, L.S));
+    ROIX_TRY(launch_resolve_dt(lc, L.S, dtype, eb, nullptr));
+    ROIX_TRY(launch_quantize(lc, d_in, dtype, g.N, L.S, d_codes, d_outlier_bits));
+    ROIX_TRY(launch_finalize(lc, L.S, d_qinfo, nullptr, nullptr, false));
+    return ROIX_OK;
+}
+
+roix_status roix_segment(roix_ctx* ctx, const int32_t* d_codes, roix_dims dims, const roix_quant_info* d_qinfo,
+                         const roix_criterion* crit, uint8_t* d_keep, int64_t* d_labels, roix_component* d_comps,
+                         int64_t comps_cap, roix_seg_info* d_sinfo, void* stream) {
+    Geom g;
+    if (!ctx || !d_codes || !d_qinfo || !d_keep || !d_sinfo || !geom_of(dims, &g) || !crit_ok(crit))
+        return ROIX_EINVAL;
+    if (comps_cap < 0 || (comps_cap > 0 && (!d_comps || !aligned(d_comps, 8))) || !aligned(d_codes, 4) ||
+        (d_labels && !aligned(d_labels, 8)))
+        return ROIX_EINVAL;
+    Layout L;
+    if (!carve(ctx, g, &L)) return ROIX_ENOMEM;
+    LaunchCtx lc = lctx(ctx, stream);
+    const bool fixed = crit->thr == ROIX_THR_FIXED;
+    ROIX_TRY(launch_init(lc, L.S, L.lookback, 0));
+    ROIX_TRY(launch_seg_init(lc, L.S, d_qinfo, crit));
+    L.proxy = proxy_base(L.proxy_alloc, d_codes, 2, g.N);
+    ROIX_TRY(launch_quant_hist(lc, d_codes, 2, g.N, L.S, L.proxy_alloc, fixed));
+    ROIX_TRY(launch_otsu(lc, L.S, fixed));
+    ROIX_TRY(label_and_keep(lc, g, L, crit, d_comps, comps_cap));
+    ROIX_TRY(launch_voxel_out(lc, g, L, d_comps, d_keep, d_labels));
+    ROIX_TRY(launch_finalize(lc, L.S, nullptr, d_sinfo, nullptr, false));
+    return ROIX_OK;
+}
+
+roix_status roix_extract(roix_ctx* ctx, const void* d_in, roix_dtype dtype, const uint8_t* d_keep, roix_dims dims,
+                         const roix_quant_info* d_qinfo, const roix_fused_out* out, void* stream) {
+    Geom g;
+    if (!ctx || !d_in || !d_keep || !d_qinfo || !geom_of(dims, &g) || !out_ok(out, false)) return ROIX_EINVAL;
+    if (dtype != ROIX_F32 && dtype != ROIX_U16) return ROIX_EINVAL;
+    if (!aligned(d_in, dtype == ROIX_F32 ? 4 : 2)) return ROIX_EINVAL;
+    Layout L;
+    if (!carve(ctx, g, &L)) return ROIX_ENOMEM;
+    LaunchCtx lc = lctx(ctx, stream);
+    roix_criterion none;
+    memset(&none, 0, sizeof none);
+    none.thr = ROIX_THR_OTSU;
+    ROIX_TRY(launch_init(lc, L.S, L.lookback, (g.nrows + kEmitRows - 1) / kEmitRows));
+    ROIX_TRY(launch_seg_init(lc, L.S, d_qinfo, &none));
+    ROIX_TRY(launch_spans_from_keep(lc, g, L, d_keep));
+    ROIX_TRY(spans_and_emit(lc, g, L, d_in, dtype, out));
+    ROIX_TRY(launch_finalize(lc, L.S, nullptr, nullptr, out->d_einfo, false));
+    return ROIX_OK;
+}
+
+roix_status roix_fused(roix_ctx* ctx, const void* d_in, roix_dtype dtype, roix_dims dims, roix_eb eb,
+                       const roix_criterion* crit, const roix_fused_out* out, void* stream) {
+    Geom g;
+    if (!ctx || !d_in || !geom_of(dims, &g) || !eb_ok(eb) || !crit_ok(crit) || !out_ok(out, true))
+        return ROIX_EINVAL;
+    if (dtype != ROIX_F32 && dtype != ROIX_U16) return ROIX_EINVAL;
+    if (!aligned(d_in, dtype == ROIX_F32 ? 4 : 2)) return ROIX_EINVAL;
+    Layout L;
+    if (!carve(ctx, g, &L)) return ROIX_ENOMEM;
+    LaunchCtx lc = lctx(ctx, stream);
+    const bool fixed = crit->thr == ROIX_THR_FIXED;
+    const int kind = dtype == ROIX_F32 ? 0 : 1;
+    ROIX_TRY(launch_init(lc, L.S, L.lookback, (g.nrows + kEmitRows - 1) / kEmitRows));
+    ROIX_TRY(launch_range(lc, d_in, dtype, g.N, L.S));
+    ROIX_TRY(launch_resolve_dt(lc, L.S, dtype, eb, crit));
+    L.proxy = proxy_base(L.proxy_alloc, d_in, kind, g.N);
+    ROIX_TRY(launch_quant_hist(lc, d_in, kind, g.N, L.S, L.proxy_alloc, fixed));
+    ROIX_TRY(launch_otsu(lc, L.S, fixed));
+    ROIX_TRY(label_and_keep(lc, g, L, crit, out->d_comps, out->comps_cap));
+    ROIX_TRY(launch_spans_from_runs(lc, g, L));
+    ROIX_TRY(spans_and_emit(lc, g, L, d_in, dtype, out));
+    ROIX_TRY(launch_finalize(lc, L.S, out->d_qinfo, out->d_sinfo, out->d_einfo, true));
+    return ROIX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,224 @@
+// common.h - device state, scratch layout and launcher declarations shared by
+// the HIP translation units of libroix.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/roix.h"
+
+namespace roix {
+
+constexpr int kBlock = 256;          // threads per workgroup for streaming kernels
+constexpr int kWave = 64;            // CDNA wavefront width
+constexpr int kHistCopies = 32;      // LDS-privatised histogram copies (one per half-wave lane)
+constexpr int kHistStride = 257;     // copy stride: lane c + bin b lands in bank (c + b) mod 32
+constexpr int kScanBlocks = 1024;    // fixed block count of the device-sized scans
+constexpr int kEmitRows = 16;        // rows per workgroup of the emit kernel (look-back unit)
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+// Everything the kernels of one call share, reset by k_init at the start of
+// the call (no memset: the sequence can be captured into a graph).
+struct DevState {
+    int32_t status;   // first fatal data error (ROIX_EINVAL/ERANGE/ENOMEM/ETRUNC/EDEVICE)
+    int32_t trunc;    // an output buffer was too small (counts still complete)
+    int32_t qstatus;  // error of the quantiser resolution alone
+    int32_t pad3;
+    uint32_t kmin, kmax;
+    uint32_t nonfinite;
+    uint32_t pad0;
+    // resolved quantiser
+    float xmin, xmax, eb32, w, r, binscale;
+    int32_t qmin, qmax, width_bits;
+    uint32_t esc;
+    int64_t K;
+    // threshold
+    int32_t otsu_bin, q_thr, proxy_thr;
+    uint32_t flags;
+    unsigned long long hist[256];
+    unsigned long long n_mask;
+    // labelling
+    uint32_t n_runs, n_comps;
+    unsigned long long max_size;
+    uint32_t largest_cid, pad1;
+    uint32_t bbox[6];
+    unsigned long long n_kept, n_kept_voxels;
+    // extraction
+    unsigned long long span_total;  // (rows with a span) << 40 | (codes)
+    unsigned long long n_outliers, q_outliers;
+    uint32_t emit_ticket, pad2;
+};
+
+// Per-call view of the scratch arena.
+struct Layout {
+    DevState* S;
+    uint8_t* proxy_alloc;   // N + 16 bytes
+    uint8_t* proxy;         // proxy_alloc + alignment shift of this call
+    uint64_t* maskbits;     // nrows * W words
+    uint32_t* row_nruns;    // nrows
+    uint32_t* run_off;      // nrows + 1
+    uint32_t* run_xs;       // run_cap
+    uint32_t* run_xe;       // run_cap
+    uint32_t* parent;       // run_cap
+    uint32_t* comp_id;      // run_cap (root flags, then component ids)
+    uint8_t* kept_flag;     // run_cap (per component)
+    uint32_t* row_xs;       // nrows
+    uint32_t* row_xe;       // nrows
+    uint64_t* row_packed;   // nrows (has_span << 40 | span length), scanned in place
+    uint64_t* lookback;     // emit look-back words, one per emit workgroup
+    uint64_t* scan_tmp;     // kScanBlocks + 1
+    uint64_t run_cap;
+};
+
+struct Geom {
+    int64_t nx, ny, nz;
+    uint64_t N;
+    int64_t nrows;  // ny * nz
+    int64_t W;      // 64-bit words per row of the bitmask
+};
+
+// ------------------------------------------------------------ device helpers
+
+__device__ __forceinline__ void fail(DevState* S, int32_t st) { atomicCAS(&S->status, 0, st); }
+
+__device__ __forceinline__ uint32_t f2key(float f) {
+    uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float key2f(uint32_t k) {
+    uint32_t b = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+    return __uint_as_float(b);
+}
+
+// code of a value: fp32 multiply (no contraction: built with -ffp-contract=off),
+// round to nearest even.
+__device__ __forceinline__ int32_t qcode(float x, float r) { return (int32_t)__builtin_rintf(x * r); }
+
+__device__ __forceinline__ bool outlier(float x, int32_t q, float w, float eb32) {
+    float xh = (float)q * w;
+    float d = x - xh;
+    return !(__builtin_fabsf(d) <= eb32);
+}
+
+// exact bin = floor(256 u / K) for 0 <= u < K <= 2^25 + 1: a float estimate,
+// off by at most one near a bin edge, then one integer correction.
+__device__ __forceinline__ uint32_t bin_of(uint32_t u, uint32_t K, float binscale) {
+    uint32_t t = (uint32_t)((float)u * binscale);
+    t = t > 255u ? 255u : t;
+    uint64_t u256 = (uint64_t)u << 8;
+    if ((uint64_t)t * K > u256) t -= 1u;
+    else if ((uint64_t)(t + 1u) * K <= u256) t += 1u;
+    return t;
+}
+
+__device__ __forceinline__ uint32_t ld_relaxed(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        T u = __shfl_xor(v, o);
+        v = u < v ? u : v;
+    }
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        T u = __shfl_xor(v, o);
+        v = u > v ? u : v;
+    }
+    return v;
+}
+
+// ------------------------------------------------------------ stage timing
+
+enum Stage {
+    ST_INIT = 0,
+    ST_RANGE,
+    ST_RESOLVE,
+    ST_QUANTIZE,
+    ST_HIST,
+    ST_OTSU,
+    ST_MASK_RUNS,
+    ST_SCAN,
+    ST_RUNS,
+    ST_UNION,
+    ST_FLATTEN,
+    ST_COMPS,
+    ST_KEEP,
+    ST_SPANS,
+    ST_EMIT,
+    ST_VOXEL_OUT,
+    ST_FINALIZE,
+    ST_COUNT
+};
+
+struct Timer;  // defined in api.hip
+void timer_begin(Timer* t, int stage, hipStream_t s);
+void timer_end(Timer* t, int stage, hipStream_t s);
+
+struct LaunchCtx {
+    hipStream_t stream;
+    Timer* timer;  // may be null
+    int grid_stream;  // workgroups of the grid-stride streaming kernels
+};
+
+// ------------------------------------------------------------ launchers
+// Each returns hipSuccess or the launch error.
+
+hipError_t launch_init(const LaunchCtx& lc, DevState* S, uint64_t* lookback, int64_t n_lookback);
+hipError_t launch_range(const LaunchCtx& lc, const void* in, roix_dtype dt, uint64_t N, DevState* S);
+hipError_t launch_resolve_dt(const LaunchCtx& lc, DevState* S, roix_dtype dt, roix_eb eb,
+                             const roix_criterion* crit);
+// 16-byte-vector alignment of the proxy to the input: byte v of the proxy
+// belongs to voxel v, and the vector part of the input maps to aligned words.
+uint8_t* proxy_base(uint8_t* proxy_alloc, const void* in, int src_kind, uint64_t N);
+hipError_t launch_seg_init(const LaunchCtx& lc, DevState* S, const roix_quant_info* qinfo,
+                           const roix_criterion* crit);
+hipError_t launch_quantize(const LaunchCtx& lc, const void* in, roix_dtype dt, uint64_t N, DevState* S,
+                           int32_t* codes, uint32_t* outlier_bits);
+// src_kind: 0 = f32 values, 1 = u16 values, 2 = int32 codes
+hipError_t launch_quant_hist(const LaunchCtx& lc, const void* in, int src_kind, uint64_t N, DevState* S,
+                             uint8_t* proxy_alloc, bool fixed);
+hipError_t launch_otsu(const LaunchCtx& lc, DevState* S, bool fixed);
+
+hipError_t launch_mask_runs(const LaunchCtx& lc, const Geom& g, const Layout& L);
+// Exclusive scans (in place allowed).  n from the host, or from *n_dev when
+// n_dev is not null (then n_host is only an upper bound).  total_out and
+// out_end (nullable) receive the sum of all elements.
+hipError_t launch_scan_u32(const LaunchCtx& lc, const uint32_t* in, uint32_t* out, int64_t n_host,
+                           const uint32_t* n_dev, uint32_t* total_out, uint32_t* out_end, uint64_t* tmp);
+hipError_t launch_scan_u64(const LaunchCtx& lc, const uint64_t* in, uint64_t* out, int64_t n_host,
+                           unsigned long long* total_out, uint64_t* tmp);
+// fail with `err` when *val > cap (val: the 64-bit total of the last scan)
+hipError_t launch_check_cap(const LaunchCtx& lc, DevState* S, const uint64_t* val, uint64_t cap, int err);
+hipError_t launch_runs_write(const LaunchCtx& lc, const Geom& g, const Layout& L);
+hipError_t launch_union(const LaunchCtx& lc, const Geom& g, const Layout& L, int conn);
+hipError_t launch_flatten(const LaunchCtx& lc, const Layout& L);
+hipError_t launch_comp_stats(const LaunchCtx& lc, const Geom& g, const Layout& L, roix_component* comps);
+hipError_t launch_keep(const LaunchCtx& lc, const Layout& L, roix_component* comps, const roix_criterion* crit);
+hipError_t launch_voxel_out(const LaunchCtx& lc, const Geom& g, const Layout& L, const roix_component* comps,
+                            uint8_t* keep, int64_t* labels);
+
+hipError_t launch_spans_from_runs(const LaunchCtx& lc, const Geom& g, const Layout& L);
+hipError_t launch_spans_from_keep(const LaunchCtx& lc, const Geom& g, const Layout& L, const uint8_t* keep);
+hipError_t launch_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, const void* in, roix_dtype dt,
+                       const roix_fused_out* out);
+// mode bits: 1 = quant info, 2 = seg info, 4 = extract info; fused marks n_outliers not computed
+hipError_t launch_finalize(const LaunchCtx& lc, DevState* S, roix_quant_info* qi, roix_seg_info* si,
+                           roix_extract_info* ei, bool fused_q);
+
+}  // namespace roix

@@ -1,0 +1,599 @@
+// k_quant.hip - range, quantiser resolution, codes, histogram + bin proxy, Otsu.
+//
+// Streaming kernels read the volume with 16-byte loads, one contiguous
+// 256 x 16 B x kUnroll block slice per workgroup iteration, grid-stride over
+// the volume.  Misaligned heads/tails (volume pointer not 16-byte aligned or
+// N not a multiple of the vector width) are handled element-wise.
+#include "common.h"
+
+namespace roix {
+
+constexpr int kUnroll = 4;
+
+template <typename T>
+struct VecN;
+template <>
+struct VecN<float> {
+    static constexpr int n = 4;
+};
+template <>
+struct VecN<uint16_t> {
+    static constexpr int n = 8;
+};
+template <>
+struct VecN<int32_t> {
+    static constexpr int n = 4;
+};
+
+template <typename T>
+__device__ __forceinline__ void unpack16(uint4 raw, T (&v)[VecN<T>::n]);
+template <>
+__device__ __forceinline__ void unpack16<float>(uint4 raw, float (&v)[4]) {
+    v[0] = __uint_as_float(raw.x);
+    v[1] = __uint_as_float(raw.y);
+    v[2] = __uint_as_float(raw.z);
+    v[3] = __uint_as_float(raw.w);
+}
+template <>
+__device__ __forceinline__ void unpack16<int32_t>(uint4 raw, int32_t (&v)[4]) {
+    v[0] = (int32_t)raw.x;
+    v[1] = (int32_t)raw.y;
+    v[2] = (int32_t)raw.z;
+    v[3] = (int32_t)raw.w;
+}
+template <>
+__device__ __forceinline__ void unpack16<uint16_t>(uint4 raw, uint16_t (&v)[8]) {
+    v[0] = (uint16_t)(raw.x & 0xFFFFu);
+    v[1] = (uint16_t)(raw.x >> 16);
+    v[2] = (uint16_t)(raw.y & 0xFFFFu);
+    v[3] = (uint16_t)(raw.y >> 16);
+    v[4] = (uint16_t)(raw.z & 0xFFFFu);
+    v[5] = (uint16_t)(raw.z >> 16);
+    v[6] = (uint16_t)(raw.w & 0xFFFFu);
+    v[7] = (uint16_t)(raw.w >> 16);
+}
+
+// Elements [0, head) are before the first 16-byte boundary; vectors cover
+// [head, head + nvec * VN); the rest is the tail.
+template <typename T>
+static void split_vec(const void* p, uint64_t N, uint64_t* head, uint64_t* nvec) {
+    constexpr int VN = VecN<T>::n;
+    uintptr_t a = (uintptr_t)p;
+    uint64_t h = (a % 16) ? (16 - a % 16) / sizeof(T) : 0;
+    if (h > N) h = N;
+    *head = h;
+    *nvec = (N - h) / VN;
+}
+
+__device__ __forceinline__ bool block_exit(const DevState* S) {
+    __shared__ int s_exit;
+    if (threadIdx.x == 0) s_exit = __hip_atomic_load(&S->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    __syncthreads();
+    return s_exit != 0;
+}
+
+// ------------------------------------------------------------------ init
+
+__global__ __launch_bounds__(kBlock) void k_init(DevState* S, uint64_t* lookback, int64_t n_lookback) {
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) {
+            S->status = 0;
+            S->trunc = 0;
+            S->kmin = 0xFFFFFFFFu;
+            S->kmax = 0u;
+            S->nonfinite = 0u;
+            S->xmin = S->xmax = S->eb32 = S->w = S->r = S->binscale = 0.0f;
+            S->qmin = S->qmax = S->width_bits = 0;
+            S->esc = 0u;
+            S->K = 0;
+            S->otsu_bin = -1;
+            S->q_thr = 0;
+            S->proxy_thr = 0;
+            S->flags = 0u;
+            S->n_mask = 0ull;
+            S->n_runs = 0u;
+            S->n_comps = 0u;
+            S->max_size = 0ull;
+            S->largest_cid = kNone;
+            S->bbox[0] = S->bbox[2] = S->bbox[4] = 0xFFFFFFFFu;
+            S->bbox[1] = S->bbox[3] = S->bbox[5] = 0u;
+            S->n_kept = S->n_kept_voxels = 0ull;
+            S->span_total = S->n_outliers = S->q_outliers = 0ull;
+            S->qstatus = 0;
+            S->emit_ticket = 0u;
+        }
+        S->hist[threadIdx.x] = 0ull;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_lookback;
+         i += (int64_t)gridDim.x * blockDim.x)
+        lookback[i] = 0ull;
+}
+
+hipError_t launch_init(const LaunchCtx& lc, DevState* S, uint64_t* lookback, int64_t n_lookback) {
+    int64_t g = (n_lookback + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    if (g > 1024) g = 1024;
+    timer_begin(lc.timer, ST_INIT, lc.stream);
+    hipLaunchKernelGGL(k_init, dim3((unsigned)g), dim3(kBlock), 0, lc.stream, S, lookback, n_lookback);
+    timer_end(lc.timer, ST_INIT, lc.stream);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- range
+
+template <typename T>
+__device__ __forceinline__ uint32_t range_key(T x, uint32_t& nonfinite);
+template <>
+__device__ __forceinline__ uint32_t range_key<float>(float x, uint32_t& nonfinite) {
+    uint32_t b = __float_as_uint(x);
+    nonfinite |= ((b & 0x7F800000u) == 0x7F800000u) ? 1u : 0u;
+    return f2key(x);
+}
+template <>
+__device__ __forceinline__ uint32_t range_key<uint16_t>(uint16_t x, uint32_t& nonfinite) {
+    return (uint32_t)x;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_range(const T* __restrict__ in, uint64_t N, uint64_t head,
+                                                  uint64_t nvec, DevState* S) {
+    constexpr int VN = VecN<T>::n;
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u, nf = 0u;
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t nthreads = (uint64_t)gridDim.x * blockDim.x;
+    // scalar head and tail
+    const uint64_t tail0 = head + nvec * VN;
+    for (uint64_t i = tid; i < head + (N - tail0); i += nthreads) {
+        uint64_t v = i < head ? i : tail0 + (i - head);
+        uint32_t k = range_key<T>(in[v], nf);
+        lo = k < lo ? k : lo;
+        hi = k > hi ? k : hi;
+    }
+    const uint4* vin = reinterpret_cast<const uint4*>(in + head);
+    const uint64_t per_iter = nthreads * kUnroll;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x * kUnroll; base < nvec; base += per_iter) {
+        uint4 raw[kUnroll];
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) {
+            uint64_t vi = base + (uint64_t)k * blockDim.x + threadIdx.x;
+            raw[k] = vi < nvec ? vin[vi] : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) {
+            uint64_t vi = base + (uint64_t)k * blockDim.x + threadIdx.x;
+            if (vi >= nvec) continue;
+            T v[VN];
+            unpack16<T>(raw[k], v);
+#pragma unroll
+            for (int j = 0; j < VN; ++j) {
+                uint32_t key = range_key<T>(v[j], nf);
+                lo = key < lo ? key : lo;
+                hi = key > hi ? key : hi;
+            }
+        }
+    }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    nf = wave_max(nf);
+    __shared__ uint32_t s_lo[kBlock / kWave], s_hi[kBlock / kWave], s_nf[kBlock / kWave];
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    if (lane == 0) {
+        s_lo[w] = lo;
+        s_hi[w] = hi;
+        s_nf[w] = nf;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < kBlock / kWave; ++k) {
+            lo = s_lo[k] < lo ? s_lo[k] : lo;
+            hi = s_hi[k] > hi ? s_hi[k] : hi;
+            nf |= s_nf[k];
+        }
+        atomicMin(&S->kmin, lo);
+        atomicMax(&S->kmax, hi);
+        if (nf) atomicOr(&S->nonfinite, 1u);
+    }
+}
+
+static int stream_grid(const LaunchCtx& lc, uint64_t nvec) {
+    uint64_t need = (nvec + (uint64_t)kBlock * kUnroll - 1) / ((uint64_t)kBlock * kUnroll);
+    if (need < 1) need = 1;
+    return (int)(need < (uint64_t)lc.grid_stream ? need : (uint64_t)lc.grid_stream);
+}
+
+hipError_t launch_range(const LaunchCtx& lc, const void* in, roix_dtype dt, uint64_t N, DevState* S) {
+    uint64_t head, nvec;
+    timer_begin(lc.timer, ST_RANGE, lc.stream);
+    if (dt == ROIX_F32) {
+        split_vec<float>(in, N, &head, &nvec);
+        hipLaunchKernelGGL(k_range<float>, dim3(stream_grid(lc, nvec)), dim3(kBlock), 0, lc.stream,
+                           (const float*)in, N, head, nvec, S);
+    } else {
+        split_vec<uint16_t>(in, N, &head, &nvec);
+        hipLaunchKernelGGL(k_range<uint16_t>, dim3(stream_grid(lc, nvec)), dim3(kBlock), 0, lc.stream,
+                           (const uint16_t*)in, N, head, nvec, S);
+    }
+    timer_end(lc.timer, ST_RANGE, lc.stream);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------- resolve
+
+__device__ __forceinline__ bool is_normal_f32(float f) {
+    uint32_t e = (__float_as_uint(f) >> 23) & 0xFFu;
+    return e != 0u && e != 0xFFu;
+}
+
+// fixed threshold T (input units): object = q > q(T), q(T) clamped to [qmin-1, qmax]
+__device__ void resolve_fixed(DevState* S, double T) {
+    float tf = (float)T;
+    float rq = __builtin_rintf(tf * S->r);
+    double qd = (double)rq;
+    int64_t qT;
+    if (qd < (double)S->qmin - 1.0)
+        qT = (int64_t)S->qmin - 1;
+    else if (qd > (double)S->qmax)
+        qT = S->qmax;
+    else
+        qT = (int64_t)qd;
+    S->q_thr = (int32_t)(qT + 1);
+    S->proxy_thr = 0;  // the proxy holds the mask bit itself
+    S->flags |= ROIX_FLAG_FIXED_THRESHOLD;
+}
+
+__device__ void set_width(DevState* S) {
+    S->K = (int64_t)S->qmax - (int64_t)S->qmin + 1;
+    S->width_bits = S->K <= 255 ? 8 : (S->K <= 65535 ? 16 : 32);
+    S->esc = S->width_bits == 32 ? 0xFFFFFFFFu : ((1u << S->width_bits) - 1u);
+    S->binscale = (float)(256.0 / (double)S->K);
+}
+
+__device__ __forceinline__ void qfail(DevState* S, int32_t st) {
+    S->qstatus = st;
+    fail(S, st);
+}
+
+__global__ void k_resolve(DevState* S, int is_f32, int eb_mode, double eb_value, int fixed, double fixed_value) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (S->nonfinite) {
+        qfail(S, ROIX_EINVAL);
+        return;
+    }
+    float xmin = is_f32 ? key2f(S->kmin) : (float)S->kmin;
+    float xmax = is_f32 ? key2f(S->kmax) : (float)S->kmax;
+    S->xmin = xmin;
+    S->xmax = xmax;
+    double eb = eb_mode == ROIX_EB_ABS ? eb_value : eb_value * ((double)xmax - (double)xmin);
+    if (!(eb > 0.0) || !(eb <= 1.7976931348623157e308)) {
+        qfail(S, ROIX_EINVAL);
+        return;
+    }
+    float eb32 = (float)eb;
+    if ((double)eb32 > eb) eb32 = __uint_as_float(__float_as_uint(eb32) - 1u);  // next float toward zero
+    if (!is_normal_f32(eb32)) {
+        qfail(S, ROIX_EINVAL);
+        return;
+    }
+    float w = eb32 + eb32;
+    // 1/w correctly rounded: the binary64 quotient rounded to binary32 (double
+    // rounding is harmless for division since 53 >= 2*24 + 2)
+    float r = (float)(1.0 / (double)w);
+    if (!is_normal_f32(w) || !is_normal_f32(r)) {
+        qfail(S, ROIX_EINVAL);
+        return;
+    }
+    S->eb32 = eb32;
+    S->w = w;
+    S->r = r;
+    float qlo = xmin * r, qhi = xmax * r;
+    if (!(__builtin_fabsf(qlo) <= 16777216.0f) || !(__builtin_fabsf(qhi) <= 16777216.0f)) {
+        qfail(S, ROIX_ERANGE);
+        return;
+    }
+    S->qmin = (int32_t)__builtin_rintf(qlo);
+    S->qmax = (int32_t)__builtin_rintf(qhi);
+    set_width(S);
+    if (fixed) resolve_fixed(S, fixed_value);
+}
+
+hipError_t launch_resolve_dt(const LaunchCtx& lc, DevState* S, roix_dtype dt, roix_eb eb,
+                             const roix_criterion* crit) {
+    int fixed = crit && crit->thr == ROIX_THR_FIXED;
+    timer_begin(lc.timer, ST_RESOLVE, lc.stream);
+    hipLaunchKernelGGL(k_resolve, dim3(1), dim3(64), 0, lc.stream, S, dt == ROIX_F32 ? 1 : 0, (int)eb.mode,
+                       eb.value, fixed, fixed ? crit->fixed_value : 0.0);
+    timer_end(lc.timer, ST_RESOLVE, lc.stream);
+    return hipGetLastError();
+}
+
+// segment from codes: the quantiser comes from a quant info written earlier
+__global__ void k_seg_init(DevState* S, const roix_quant_info* qi, int fixed, double fixed_value) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (qi->status != 0) {
+        fail(S, qi->status);
+        return;
+    }
+    S->xmin = qi->xmin;
+    S->xmax = qi->xmax;
+    S->eb32 = qi->eb32;
+    S->w = qi->w;
+    S->r = qi->r;
+    S->qmin = qi->qmin;
+    S->qmax = qi->qmax;
+    if (qi->qmax < qi->qmin || !is_normal_f32(qi->w) || !is_normal_f32(qi->r)) {
+        fail(S, ROIX_EINVAL);
+        return;
+    }
+    set_width(S);
+    if (fixed) resolve_fixed(S, fixed_value);
+}
+
+hipError_t launch_seg_init(const LaunchCtx& lc, DevState* S, const roix_quant_info* qinfo,
+                           const roix_criterion* crit) {
+    int fixed = crit->thr == ROIX_THR_FIXED;
+    timer_begin(lc.timer, ST_RESOLVE, lc.stream);
+    hipLaunchKernelGGL(k_seg_init, dim3(1), dim3(64), 0, lc.stream, S, qinfo, fixed,
+                       fixed ? crit->fixed_value : 0.0);
+    timer_end(lc.timer, ST_RESOLVE, lc.stream);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------- standalone codes
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_quantize(const T* __restrict__ in, uint64_t N, DevState* S,
+                                                     int32_t* __restrict__ codes, uint32_t* __restrict__ bits) {
+    if (block_exit(S)) return;
+    const float r = S->r, w = S->w, eb32 = S->eb32;
+    const int lane = threadIdx.x % kWave;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = (uint64_t)gridDim.x * blockDim.x / kWave;
+    uint32_t cnt = 0;
+    for (uint64_t b = wave * kWave; b < N; b += nwaves * kWave) {
+        uint64_t v = b + lane;
+        bool o = false;
+        if (v < N) {
+            float x = (float)in[v];
+            int32_t q = qcode(x, r);
+            o = outlier(x, q, w, eb32);
+            codes[v] = q;
+        }
+        uint64_t m = __ballot(o);
+        if (lane == 0) {
+            cnt += (uint32_t)__popcll(m);
+            if (bits) {
+                bits[b / 32] = (uint32_t)m;
+                if (b + 32 < N) bits[b / 32 + 1] = (uint32_t)(m >> 32);
+            }
+        }
+    }
+    if (lane == 0 && cnt) atomicAdd(&S->q_outliers, (unsigned long long)cnt);
+}
+
+hipError_t launch_quantize(const LaunchCtx& lc, const void* in, roix_dtype dt, uint64_t N, DevState* S,
+                           int32_t* codes, uint32_t* outlier_bits) {
+    uint64_t need = (N + kBlock - 1) / kBlock;
+    int g = (int)(need < (uint64_t)lc.grid_stream * 4 ? need : (uint64_t)lc.grid_stream * 4);
+    if (g < 1) g = 1;
+    timer_begin(lc.timer, ST_QUANTIZE, lc.stream);
+    if (dt == ROIX_F32)
+        hipLaunchKernelGGL(k_quantize<float>, dim3(g), dim3(kBlock), 0, lc.stream, (const float*)in, N, S, codes,
+                           outlier_bits);
+    else
+        hipLaunchKernelGGL(k_quantize<uint16_t>, dim3(g), dim3(kBlock), 0, lc.stream, (const uint16_t*)in, N, S,
+                           codes, outlier_bits);
+    timer_end(lc.timer, ST_QUANTIZE, lc.stream);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------- histogram + 1-byte proxy
+
+struct QH {
+    float r;
+    int32_t qmin, q_thr;
+    uint32_t K;
+    float binscale;
+};
+
+template <typename T, bool CODES, bool FIXED>
+__device__ __forceinline__ uint8_t qh_one(T x, const QH& p, uint32_t* lh_copy, bool& bad) {
+    int32_t q;
+    if constexpr (CODES)
+        q = (int32_t)x;
+    else
+        q = qcode((float)x, p.r);
+    uint32_t u = (uint32_t)(q - p.qmin);
+    if constexpr (CODES) {
+        if (u >= p.K) {
+            bad = true;
+            u = 0u;
+        }
+    }
+    uint32_t b = bin_of(u, p.K, p.binscale);
+    atomicAdd(&lh_copy[b], 1u);
+    if constexpr (FIXED)
+        return (uint8_t)(q >= p.q_thr ? 1 : 0);
+    else
+        return (uint8_t)b;
+}
+
+template <typename T, bool CODES, bool FIXED>
+__global__ __launch_bounds__(kBlock) void k_quant_hist(const T* __restrict__ in, uint64_t N, uint64_t head,
+                                                       uint64_t nvec, DevState* S, uint8_t* __restrict__ proxy) {
+    constexpr int VN = VecN<T>::n;
+    __shared__ uint32_t lh[kHistCopies * kHistStride];
+    for (int i = threadIdx.x; i < kHistCopies * kHistStride; i += blockDim.x) lh[i] = 0u;
+    if (block_exit(S)) return;  // contains a barrier, so lh is zeroed for every thread
+    QH p;
+    p.r = S->r;
+    p.qmin = S->qmin;
+    p.q_thr = S->q_thr;
+    p.K = (uint32_t)S->K;
+    p.binscale = S->binscale;
+    uint32_t* mine = lh + (threadIdx.x % kHistCopies) * kHistStride;
+    bool bad = false;
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t nthreads = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t tail0 = head + nvec * VN;
+    for (uint64_t i = tid; i < head + (N - tail0); i += nthreads) {
+        uint64_t v = i < head ? i : tail0 + (i - head);
+        proxy[v] = qh_one<T, CODES, FIXED>(in[v], p, mine, bad);
+    }
+    const uint4* vin = reinterpret_cast<const uint4*>(in + head);
+    uint8_t* pout = proxy + head;  // VN-aligned by construction of the proxy base
+    const uint64_t per_iter = nthreads * kUnroll;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x * kUnroll; base < nvec; base += per_iter) {
+        uint4 raw[kUnroll];
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) {
+            uint64_t vi = base + (uint64_t)k * blockDim.x + threadIdx.x;
+            raw[k] = vi < nvec ? vin[vi] : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) {
+            uint64_t vi = base + (uint64_t)k * blockDim.x + threadIdx.x;
+            if (vi >= nvec) continue;
+            T v[VN];
+            unpack16<T>(raw[k], v);
+            if constexpr (VN == 4) {
+                uint32_t pk = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) pk |= (uint32_t)qh_one<T, CODES, FIXED>(v[j], p, mine, bad) << (8 * j);
+                *reinterpret_cast<uint32_t*>(pout + vi * 4) = pk;
+            } else {
+                uint64_t pk = 0;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) pk |= (uint64_t)qh_one<T, CODES, FIXED>(v[j], p, mine, bad) << (8 * j);
+                *reinterpret_cast<uint64_t*>(pout + vi * 8) = pk;
+            }
+        }
+    }
+    if constexpr (CODES) {
+        if (bad) fail(S, ROIX_EINVAL);
+    }
+    __syncthreads();
+    {
+        const int b = threadIdx.x;  // kBlock == 256 bins
+        uint32_t s = 0;
+#pragma unroll 8
+        for (int c = 0; c < kHistCopies; ++c) s += lh[c * kHistStride + b];
+        if (s) atomicAdd(&S->hist[b], (unsigned long long)s);
+    }
+}
+
+template <typename T, bool CODES>
+static void qh_dispatch(const LaunchCtx& lc, const void* in, uint64_t N, DevState* S, uint8_t* proxy_alloc,
+                        bool fixed) {
+    uint64_t head, nvec;
+    split_vec<T>(in, N, &head, &nvec);
+    constexpr int VN = VecN<T>::n;
+    uint8_t* proxy = proxy_alloc + ((VN - head % VN) % VN);
+    dim3 g(stream_grid(lc, nvec));
+    if (fixed)
+        hipLaunchKernelGGL((k_quant_hist<T, CODES, true>), g, dim3(kBlock), 0, lc.stream, (const T*)in, N, head,
+                           nvec, S, proxy);
+    else
+        hipLaunchKernelGGL((k_quant_hist<T, CODES, false>), g, dim3(kBlock), 0, lc.stream, (const T*)in, N, head,
+                           nvec, S, proxy);
+}
+
+hipError_t launch_quant_hist(const LaunchCtx& lc, const void* in, int src_kind, uint64_t N, DevState* S,
+                             uint8_t* proxy_alloc, bool fixed) {
+    timer_begin(lc.timer, ST_HIST, lc.stream);
+    if (src_kind == 0)
+        qh_dispatch<float, false>(lc, in, N, S, proxy_alloc, fixed);
+    else if (src_kind == 1)
+        qh_dispatch<uint16_t, false>(lc, in, N, S, proxy_alloc, fixed);
+    else
+        qh_dispatch<int32_t, true>(lc, in, N, S, proxy_alloc, fixed);
+    timer_end(lc.timer, ST_HIST, lc.stream);
+    return hipGetLastError();
+}
+
+uint8_t* proxy_base(uint8_t* proxy_alloc, const void* in, int src_kind, uint64_t N) {
+    uint64_t head, nvec;
+    int VN;
+    if (src_kind == 1) {
+        split_vec<uint16_t>(in, N, &head, &nvec);
+        VN = 8;
+    } else if (src_kind == 0) {
+        split_vec<float>(in, N, &head, &nvec);
+        VN = 4;
+    } else {
+        split_vec<int32_t>(in, N, &head, &nvec);
+        VN = 4;
+    }
+    return proxy_alloc + ((VN - head % VN) % VN);
+}
+
+// ------------------------------------------------------------------ Otsu
+
+// Otsu (1979) on the 256 bins: maximise W0 W1 (m0 - m1)^2 over the split t
+// (class 0 = bins 0..t), first maximum on ties, splits with an empty class
+// skipped.  Every thread evaluates one split with the same binary64
+// expression and operation order.
+__global__ __launch_bounds__(256) void k_otsu(DevState* S, int fixed) {
+    __shared__ unsigned long long sh_w[256], sh_s[256];
+    __shared__ double sh_v[256];
+    __shared__ int sh_t[256];
+    const int t = threadIdx.x;
+    if (block_exit(S)) return;
+    unsigned long long h = S->hist[t];
+    sh_w[t] = h;
+    sh_s[t] = (unsigned long long)t * h;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        unsigned long long aw = t >= o ? sh_w[t - o] : 0ull, as = t >= o ? sh_s[t - o] : 0ull;
+        __syncthreads();
+        sh_w[t] += aw;
+        sh_s[t] += as;
+        __syncthreads();
+    }
+    if (fixed) {
+        if (t == 0) S->otsu_bin = -1;
+        return;
+    }
+    const unsigned long long NT = sh_w[255], ST = sh_s[255];
+    const unsigned long long W0 = sh_w[t], S0 = sh_s[t], W1 = NT - W0;
+    double s = -1.0;
+    if (t < 255 && W0 != 0ull && W1 != 0ull) {
+        double m0 = (double)S0 / (double)W0;
+        double m1 = (double)(ST - S0) / (double)W1;
+        double d = m0 - m1;
+        s = (((double)W0 * (double)W1) * d) * d;
+    }
+    sh_v[t] = s;
+    sh_t[t] = t;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) {
+            double a = sh_v[t], b = sh_v[t + o];
+            int ta = sh_t[t], tb = sh_t[t + o];
+            if (b > a || (b == a && tb < ta)) {
+                sh_v[t] = b;
+                sh_t[t] = tb;
+            }
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        int ts = 255;
+        if (sh_v[0] < 0.0)
+            S->flags |= ROIX_FLAG_DEGENERATE_HISTOGRAM;
+        else
+            ts = sh_t[0];
+        S->otsu_bin = ts;
+        S->proxy_thr = ts;
+        long long c = ((long long)(ts + 1) * S->K + 255) / 256;
+        S->q_thr = (int32_t)((long long)S->qmin + c);
+    }
+}
+
+hipError_t launch_otsu(const LaunchCtx& lc, DevState* S, bool fixed) {
+    timer_begin(lc.timer, ST_OTSU, lc.stream);
+    hipLaunchKernelGGL(k_otsu, dim3(1), dim3(256), 0, lc.stream, S, fixed ? 1 : 0);
+    timer_end(lc.timer, ST_OTSU, lc.stream);
+    return hipGetLastError();
+}
+
+}  // namespace roix

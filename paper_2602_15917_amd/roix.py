@@ -1,0 +1,285 @@
+"""Python binding of libroix.so (ctypes).
+
+Argument marshalling only: torch tensors provide device memory and the HIP
+stream; every step of the reduction runs in the library's HIP kernels.  If
+the library is not built, every call raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libroix.so")
+
+OK, EINVAL, ERANGE, ENOMEM, ETRUNC, EDEVICE, EBUSY, ESEQ = range(8)
+F32, U16 = 0, 1
+EB_ABS, EB_REL = 0, 1
+THR_OTSU, THR_FIXED = 0, 1
+KEEP_MIN_SIZE, KEEP_LARGEST = 0, 1
+FLAG_DEGENERATE_HISTOGRAM, FLAG_EMPTY_ROI, FLAG_FIXED_THRESHOLD = 1, 2, 4
+NOT_COMPUTED = (1 << 64) - 1
+
+
+class RoixError(RuntimeError):
+    def __init__(self, status, what):
+        super().__init__(f"{what}: status {status}")
+        self.status = status
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64)]
+
+
+class Eb(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("pad", ctypes.c_int32), ("value", ctypes.c_double)]
+
+
+class CCriterion(ctypes.Structure):
+    _fields_ = [("thr", ctypes.c_int32), ("connectivity", ctypes.c_int32), ("fixed_value", ctypes.c_double),
+                ("keep", ctypes.c_int32), ("pad", ctypes.c_int32), ("min_size", ctypes.c_int64)]
+
+
+class QuantInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("xmin", ctypes.c_float), ("xmax", ctypes.c_float),
+                ("eb32", ctypes.c_float), ("w", ctypes.c_float), ("r", ctypes.c_float), ("qmin", ctypes.c_int32),
+                ("qmax", ctypes.c_int32), ("K", ctypes.c_int64), ("width_bits", ctypes.c_int32),
+                ("esc", ctypes.c_uint32), ("n_outliers", ctypes.c_uint64)]
+
+
+class SegInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("otsu_bin", ctypes.c_int32), ("q_thr", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("hist", ctypes.c_uint64 * 256), ("n_mask", ctypes.c_uint64),
+                ("n_components", ctypes.c_uint64), ("n_kept", ctypes.c_uint64), ("n_kept_voxels", ctypes.c_uint64),
+                ("bbox", ctypes.c_uint32 * 6)]
+
+
+class ExtractInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("pad", ctypes.c_int32), ("n_rows", ctypes.c_uint64),
+                ("n_codes", ctypes.c_uint64), ("n_outliers", ctypes.c_uint64), ("stream_bytes", ctypes.c_uint64)]
+
+
+class FusedOut(ctypes.Structure):
+    _fields_ = [("d_rows", ctypes.c_void_p), ("rows_cap", ctypes.c_int64), ("d_stream", ctypes.c_void_p),
+                ("stream_cap_bytes", ctypes.c_int64), ("d_outliers", ctypes.c_void_p),
+                ("outliers_cap", ctypes.c_int64), ("d_comps", ctypes.c_void_p), ("comps_cap", ctypes.c_int64),
+                ("d_qinfo", ctypes.c_void_p), ("d_sinfo", ctypes.c_void_p), ("d_einfo", ctypes.c_void_p)]
+
+
+COMP_BYTES, ROW_BYTES = 48, 32
+STAGE_MAX = 64
+
+_lib = None
+
+
+def load():
+    """Load libroix.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, ci, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
+    P = ctypes.POINTER
+    lib.roix_ctx_create.argtypes = [ci, sz, P(vp)]
+    lib.roix_ctx_destroy.argtypes = [vp]
+    lib.roix_scratch_bytes.argtypes = [Dims, ci, P(CCriterion)]
+    lib.roix_scratch_bytes.restype = sz
+    lib.roix_bounds.argtypes = [Dims, ci, P(CCriterion), P(i64), P(i64), P(i64), P(i64)]
+    lib.roix_quantize.argtypes = [vp, vp, ci, Dims, Eb, vp, vp, vp, vp]
+    lib.roix_segment.argtypes = [vp, vp, Dims, vp, P(CCriterion), vp, vp, vp, i64, vp, vp]
+    lib.roix_extract.argtypes = [vp, vp, ci, vp, Dims, vp, P(FusedOut), vp]
+    lib.roix_fused.argtypes = [vp, vp, ci, Dims, Eb, P(CCriterion), P(FusedOut), vp]
+    lib.roix_stage_count.restype = ci
+    lib.roix_stage_name.argtypes = [ci]
+    lib.roix_stage_name.restype = ctypes.c_char_p
+    lib.roix_ctx_set_timing.argtypes = [vp, ci]
+    lib.roix_ctx_read_timing.argtypes = [vp, P(ctypes.c_double), P(i64)]
+    lib.roix_status_string.argtypes = [ci]
+    lib.roix_status_string.restype = ctypes.c_char_p
+    for f in ("roix_ctx_create", "roix_ctx_destroy", "roix_bounds", "roix_quantize", "roix_segment",
+              "roix_extract", "roix_fused", "roix_ctx_set_timing", "roix_ctx_read_timing"):
+        getattr(lib, f).restype = ci
+    _lib = lib
+    return lib
+
+
+@dataclass
+class Criterion:
+    """ROI criterion (mirrors roix_criterion)."""
+    thr: str = "otsu"          # "otsu" | "fixed"
+    fixed_value: float = 0.0
+    connectivity: int = 26     # 6 | 26
+    keep: str = "largest"      # "largest" | "min_size"
+    min_size: int = 1
+
+    def c(self) -> CCriterion:
+        return CCriterion(THR_OTSU if self.thr == "otsu" else THR_FIXED, int(self.connectivity),
+                          float(self.fixed_value), KEEP_LARGEST if self.keep == "largest" else KEEP_MIN_SIZE, 0,
+                          int(self.min_size))
+
+
+def dims_of(vol: torch.Tensor) -> Dims:
+    nz, ny, nx = vol.shape
+    return Dims(nx, ny, nz)
+
+
+def dtype_of(vol: torch.Tensor) -> int:
+    if vol.dtype == torch.float32:
+        return F32
+    if vol.dtype == torch.uint16:
+        return U16
+    raise TypeError(f"unsupported dtype {vol.dtype}")
+
+
+def eb_of(mode: str, value: float) -> Eb:
+    return Eb(EB_ABS if mode == "abs" else EB_REL, 0, float(value))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(st, what):
+    if st != OK:
+        raise RoixError(st, what)
+
+
+def scratch_bytes(dims: Dims, dtype: int, crit: Criterion | None = None) -> int:
+    c = crit.c() if crit is not None else CCriterion()
+    return int(load().roix_scratch_bytes(dims, dtype, ctypes.byref(c)))
+
+
+def bounds(dims: Dims, dtype: int, crit: Criterion | None = None):
+    c = crit.c() if crit is not None else CCriterion()
+    r, s, o, k = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load().roix_bounds(dims, dtype, ctypes.byref(c), ctypes.byref(r), ctypes.byref(s), ctypes.byref(o),
+                              ctypes.byref(k)), "roix_bounds")
+    return {"rows": r.value, "stream_bytes": s.value, "outliers": o.value, "components": k.value}
+
+
+def stage_names():
+    lib = load()
+    return [lib.roix_stage_name(i).decode() for i in range(lib.roix_stage_count())]
+
+
+def _info(buf: torch.Tensor, cls):
+    return cls.from_buffer_copy(bytes(buf.cpu().numpy().tobytes()))
+
+
+class Outputs:
+    """Caller-owned output buffers of extract/fused (device tensors)."""
+
+    def __init__(self, device, rows_cap, stream_cap_bytes, outliers_cap, comps_cap):
+        self.rows = torch.empty(max(rows_cap, 1) * ROW_BYTES, dtype=torch.uint8, device=device)
+        self.stream = torch.empty(max(stream_cap_bytes, 4), dtype=torch.uint8, device=device)
+        self.outliers = torch.empty(max(outliers_cap, 1), dtype=torch.float32, device=device)
+        self.comps = torch.empty(max(comps_cap, 1) * COMP_BYTES, dtype=torch.uint8, device=device)
+        self.qinfo = torch.zeros(ctypes.sizeof(QuantInfo), dtype=torch.uint8, device=device)
+        self.sinfo = torch.zeros(ctypes.sizeof(SegInfo), dtype=torch.uint8, device=device)
+        self.einfo = torch.zeros(ctypes.sizeof(ExtractInfo), dtype=torch.uint8, device=device)
+        self.caps = (rows_cap, stream_cap_bytes, outliers_cap, comps_cap)
+        self.c = FusedOut(self.rows.data_ptr(), rows_cap, self.stream.data_ptr(), stream_cap_bytes,
+                          self.outliers.data_ptr(), outliers_cap, self.comps.data_ptr(), comps_cap,
+                          self.qinfo.data_ptr(), self.sinfo.data_ptr(), self.einfo.data_ptr())
+
+    def collect(self):
+        """Host copies of the infos and the outputs trimmed to the counts
+        (call after the stream has been synchronised)."""
+        q, s, e = _info(self.qinfo, QuantInfo), _info(self.sinfo, SegInfo), _info(self.einfo, ExtractInfo)
+        rows_cap, stream_cap, outl_cap, comps_cap = self.caps
+        nr = min(int(e.n_rows), rows_cap)
+        nb = min(int(e.stream_bytes), stream_cap)
+        no = min(int(e.n_outliers), outl_cap)
+        nc = min(int(s.n_components), comps_cap)
+        return {
+            "qinfo": q, "sinfo": s, "einfo": e,
+            "rows": self.rows[: nr * ROW_BYTES].cpu().numpy(),
+            "stream": self.stream[:nb].cpu().numpy(),
+            "outliers": self.outliers[:no].cpu().numpy(),
+            "comps": self.comps[: nc * COMP_BYTES].cpu().numpy(),
+        }
+
+
+class Context:
+    """A library context (scratch arena) on one device."""
+
+    def __init__(self, device: int = 0, scratch_bytes: int = 0):
+        lib = load()
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(lib.roix_ctx_create(device, scratch_bytes, ctypes.byref(h)), "roix_ctx_create")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            load().roix_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------- timing
+    def set_timing(self, on: bool):
+        _check(load().roix_ctx_set_timing(self.h, 1 if on else 0), "roix_ctx_set_timing")
+
+    def read_timing(self):
+        lib = load()
+        n = lib.roix_stage_count()
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        _check(lib.roix_ctx_read_timing(self.h, ms, cnt), "roix_ctx_read_timing")
+        names = stage_names()
+        return {names[i]: (ms[i], cnt[i]) for i in range(n)}
+
+    # ----------------------------------------------------------- calls
+    def fused(self, vol: torch.Tensor, eb_mode: str, eb_value: float, crit: Criterion, out: Outputs,
+              stream=None):
+        """Enqueue the fused path; returns after launching (sync, then out.collect())."""
+        c = crit.c()
+        st = load().roix_fused(self.h, _ptr(vol), dtype_of(vol), dims_of(vol), eb_of(eb_mode, eb_value),
+                               ctypes.byref(c), ctypes.byref(out.c), _stream(stream))
+        _check(st, "roix_fused")
+
+    def quantize(self, vol: torch.Tensor, eb_mode: str, eb_value: float, with_bits: bool = True, stream=None):
+        n = vol.numel()
+        codes = torch.empty(vol.shape, dtype=torch.int32, device=vol.device)
+        bits = torch.empty(((n + 31) // 32,), dtype=torch.int32, device=vol.device) if with_bits else None
+        qinfo = torch.zeros(ctypes.sizeof(QuantInfo), dtype=torch.uint8, device=vol.device)
+        st = load().roix_quantize(self.h, _ptr(vol), dtype_of(vol), dims_of(vol), eb_of(eb_mode, eb_value),
+                                  _ptr(codes), _ptr(bits), _ptr(qinfo), _stream(stream))
+        _check(st, "roix_quantize")
+        return codes, bits, qinfo
+
+    def segment(self, codes: torch.Tensor, qinfo: torch.Tensor, crit: Criterion, comps_cap: int,
+                want_labels: bool = False, stream=None):
+        keep = torch.empty(codes.shape, dtype=torch.uint8, device=codes.device)
+        labels = torch.empty(codes.shape, dtype=torch.int64, device=codes.device) if want_labels else None
+        comps = torch.empty(max(comps_cap, 1) * COMP_BYTES, dtype=torch.uint8, device=codes.device)
+        sinfo = torch.zeros(ctypes.sizeof(SegInfo), dtype=torch.uint8, device=codes.device)
+        c = crit.c()
+        st = load().roix_segment(self.h, _ptr(codes), dims_of(codes), _ptr(qinfo), ctypes.byref(c), _ptr(keep),
+                                 _ptr(labels), _ptr(comps), comps_cap, _ptr(sinfo), _stream(stream))
+        _check(st, "roix_segment")
+        return keep, labels, comps, sinfo
+
+    def extract(self, vol: torch.Tensor, keep: torch.Tensor, qinfo: torch.Tensor, out: Outputs, stream=None):
+        st = load().roix_extract(self.h, _ptr(vol), dtype_of(vol), _ptr(keep), dims_of(vol), _ptr(qinfo),
+                                 ctypes.byref(out.c), _stream(stream))
+        _check(st, "roix_extract")
+
+
+def parse_info(buf: torch.Tensor, cls):
+    return _info(buf, cls)

@@ -1,0 +1,223 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Bit-exact on every output: quantiser fields, histogram, threshold, component
+table, row table, code stream and outlier values.  Inputs are the seeded
+synthetic volumes of ``synth`` plus hand-made edge cases.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from roixtest import (compare_fused, criterion, default_caps, gpu_fused, log, oracle_fused)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    from paper_2602_15917_amd import roix
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    roix.load()
+    ctx = roix.Context(0, 1 << 30)
+    yield ctx, roix, torch
+    ctx.close()
+
+
+def run_case(env, name, vol, eb_mode, eb_value, crit_o, caps=None):
+    ctx, roix, torch = env
+    log(f"[case] {name} shape={vol.shape} dtype={vol.dtype} eb={eb_mode}:{eb_value} crit={crit_o}")
+    crit = criterion(roix, crit_o)
+    g = gpu_fused(ctx, roix, torch, vol, eb_mode, eb_value, crit, caps)
+    o = oracle_fused(vol, eb_mode, eb_value, crit_o, caps)
+    compare_fused(g, o)
+    return g, o
+
+
+def test_config0_full(env):
+    w = synth.config0()
+    g, o = run_case(env, "config0", w.volume, w.eb_mode, w.eb_value, w.criterion)
+    assert o["info"].n_components == 3 and g["einfo"].n_codes > 0
+
+
+SHAPES = [(1, 1, 1), (1, 1, 7), (1, 5, 3), (3, 1, 1), (2, 3, 64), (4, 9, 65), (5, 7, 130), (3, 4, 200),
+          (17, 13, 33), (9, 40, 64), (6, 6, 127), (2, 2, 1000), (40, 3, 5)]
+
+
+@pytest.mark.parametrize("k", range(len(SHAPES)))
+@pytest.mark.parametrize("conn", [6, 26])
+def test_small_ellipsoid_volumes(env, k, conn):
+    nz, ny, nx = SHAPES[k]
+    vol, _ = synth.ellipsoids(nx, ny, nz, 4000 + k, n_ell=3, ax=(0.5, 6.0))
+    for keep, ms in (("largest", 1), ("min_size", 3)):
+        c = synth.Criterion("otsu", 0.0, conn, keep, ms)
+        run_case(env, f"ellipsoids{SHAPES[k]}", vol, "abs", 1e-3, c)
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("conn", [6, 26])
+def test_noise_many_components(env, seed, conn):
+    # threshold inside the noise: thousands of small components and long union chains
+    vol = synth.normal((11, 37, 70 + seed), 5000 + seed, 0.5, 0.1)
+    for keep, ms in (("min_size", 1), ("min_size", 5), ("largest", 1)):
+        c = synth.Criterion("fixed", 0.55, conn, keep, ms)
+        run_case(env, f"noise seed={seed}", vol, "abs", 1e-3, c)
+    c = synth.Criterion("otsu", 0.0, conn, "min_size", 2)
+    run_case(env, f"noise-otsu seed={seed}", vol, "abs", 1e-4, c)
+
+
+def test_uint16_rings_small(env):
+    w = synth.config2(nxy=256, nz=12)
+    run_case(env, "rings u16 small", w.volume, w.eb_mode, w.eb_value, w.criterion)
+
+
+def test_cylinder_medium(env):
+    w = synth.config1(n=192)
+    run_case(env, "cylinder 192^3", w.volume, w.eb_mode, w.eb_value, w.criterion)
+
+
+@pytest.mark.parametrize("eb", [1e-2, 1e-3, 1e-4, 1e-5, 3.3e-6])
+def test_code_widths_and_outliers(env, eb):
+    # K spans the 8/16/32-bit widths; small bounds give fp32 escapes
+    vol = synth.normal((6, 20, 97), 77, 0.5, 0.2)
+    c = synth.Criterion("fixed", 0.5, 26, "min_size", 1)
+    g, o = run_case(env, f"widths eb={eb}", vol, "abs", eb, c)
+
+
+def test_edge_cases(env):
+    c6 = synth.Criterion("otsu", 0.0, 6, "min_size", 1)
+    # constant volume: degenerate histogram, empty ROI, no rows
+    run_case(env, "constant", np.full((4, 5, 66), 0.25, np.float32), "abs", 1e-3, c6)
+    # relative bound on a constant volume: invalid bound
+    run_case(env, "constant rel", np.full((2, 3, 4), 7.0, np.float32), "rel", 1e-4, c6)
+    # everything is object
+    v = synth.normal((3, 9, 70), 5, 1.0, 0.1)
+    run_case(env, "all object", v, "abs", 1e-3, synth.Criterion("fixed", -100.0, 26, "largest", 1))
+    # nothing is object
+    run_case(env, "no object", v, "abs", 1e-3, synth.Criterion("fixed", 100.0, 26, "largest", 1))
+    # negative values and signed zeros
+    v = synth.normal((3, 8, 40), 6, -0.2, 0.3)
+    v[0, 0, 0], v[1, 1, 1] = -0.0, 0.0
+    run_case(env, "negative", v, "abs", 1e-3, c6)
+    # denormal inputs
+    v = (synth.normal((2, 4, 64), 8, 0.0, 1.0) * np.float32(1e-38)).astype(np.float32)
+    assert (np.abs(v) < np.finfo(np.float32).tiny).any()
+    run_case(env, "denormals", v, "abs", 1e-37, c6)
+    run_case(env, "denormal bound", v, "abs", 1e-39, c6)
+    # non-finite input
+    for bad in (np.nan, np.inf, -np.inf):
+        v = synth.normal((2, 3, 50), 9, 0.0, 1.0)
+        v[1, 2, 33] = bad
+        run_case(env, f"non-finite {bad}", v, "abs", 1e-3, c6)
+    # codes beyond 2^24
+    run_case(env, "erange", synth.normal((2, 3, 10), 10, 0.0, 1e4), "abs", 1e-6, c6)
+    # uint16 extremes
+    u = np.zeros((3, 4, 70), np.uint16)
+    u[1, 1:3, 5:60] = 65535
+    run_case(env, "u16 extremes", u, "abs", 0.5, synth.Criterion("otsu", 0.0, 26, "largest", 1))
+    run_case(env, "u16 rel", u, "rel", 1e-4, synth.Criterion("otsu", 0.0, 6, "largest", 1))
+
+
+def test_misaligned_input(env):
+    # volumes that do not start on a 16-byte boundary: element-wise head/tail paths
+    ctx, roix, torch = env
+    for w, offs in ((synth.config0(), (1, 2, 3)), (synth.config2(nxy=64, nz=5), (1, 3, 5, 7))):
+        n = w.volume.size
+        flat = torch.from_numpy(np.ascontiguousarray(w.volume).ravel()).to("cuda:0")
+        base = torch.zeros(n + 8, dtype=flat.dtype, device="cuda:0")
+        crit = criterion(roix, w.criterion)
+        o = oracle_fused(w.volume, w.eb_mode, w.eb_value, w.criterion)
+        for off in offs:
+            log(f"[case] misaligned {w.name} offset={off}")
+            base[off: off + n] = flat
+            t = base[off: off + n].view(w.volume.shape)
+            out = roix.Outputs("cuda:0", *default_caps(roix, w.volume, crit))
+            ctx.fused(t, w.eb_mode, w.eb_value, crit, out)
+            torch.cuda.synchronize()
+            compare_fused(out.collect(), o)
+
+
+def test_truncation_reports_full_counts(env):
+    w = synth.config0()
+    c = w.criterion
+    caps = (10, 100, 0, 3)
+    run_case(env, "etrunc rows/stream", w.volume, w.eb_mode, w.eb_value, c, caps)
+    run_case(env, "etrunc comps", w.volume, w.eb_mode, w.eb_value, c, (16384, 1 << 24, 1 << 20, 2))
+
+
+def test_scratch_too_small_for_runs(env):
+    _, roix, torch = env
+    vol = synth.normal((8, 32, 128), 11, 0.5, 0.1)
+    nz, ny, nx = vol.shape
+    dims = roix.Dims(nx, ny, nz)
+    crit = roix.Criterion("fixed", 0.5, 6, "min_size", 1)
+    need = roix.scratch_bytes(dims, roix.F32, crit)
+    worst_run_bytes = 17 * ny * nz * (nx // 2)
+    small = roix.Context(0, need - worst_run_bytes + 17 * 100)  # room for 100 runs only
+    log("[case] enomem")
+    g = gpu_fused(small, roix, torch, vol, "abs", 1e-3, crit)
+    small.close()
+    assert g["sinfo"].status == roix.ENOMEM and g["einfo"].status == roix.ENOMEM
+    tiny = roix.Context(0, 4096)
+    with pytest.raises(roix.RoixError) as ei:
+        gpu_fused(tiny, roix, torch, vol, "abs", 1e-3, crit)
+    assert ei.value.status == roix.ENOMEM
+    tiny.close()
+
+
+def test_staged_equals_fused_and_oracle(env):
+    ctx, roix, torch = env
+    for name, w in (("config0", synth.config0()), ("rings", synth.config2(nxy=128, nz=6)),
+                    ("cyl", synth.config1(n=96))):
+        for conn in (6, 26):
+            c = synth.Criterion(w.criterion.thr, 0.0, conn, w.criterion.keep, w.criterion.min_size)
+            crit = criterion(roix, c)
+            log(f"[case] staged {name} conn={conn}")
+            t = torch.from_numpy(w.volume).to("cuda:0")
+            codes, bits, qinfo = ctx.quantize(t, w.eb_mode, w.eb_value)
+            caps = default_caps(roix, w.volume, crit)
+            keep, labels, comps, sinfo = ctx.segment(codes, qinfo, crit, caps[3], want_labels=True)
+            out = roix.Outputs("cuda:0", *caps)
+            ctx.extract(t, keep, qinfo, out)
+            torch.cuda.synchronize()
+            # quantiser
+            st, lo, hi = oracle.value_range(w.volume)
+            p = oracle.resolve(lo, hi, w.eb_mode, w.eb_value)
+            _, oc, ob, on = oracle.quantize(w.volume, p)
+            q = roix.parse_info(qinfo, roix.QuantInfo)
+            assert q.status == 0 and q.n_outliers == on
+            assert np.array_equal(codes.cpu().numpy(), oc)
+            assert np.array_equal(bits.cpu().numpy().view(np.uint32), ob)
+            # segmentation: per-voxel keep and labels against the oracle's labelling of its own mask
+            f = oracle_fused(w.volume, w.eb_mode, w.eb_value, c)
+            mask = (oc >= f["info"].q_thr).astype(np.uint8)
+            _, olab, okeep, ocomps = oracle.label(mask, conn, c.keep, c.min_size)
+            assert np.array_equal(labels.cpu().numpy(), olab)
+            assert np.array_equal(keep.cpu().numpy(), okeep)
+            s = roix.parse_info(sinfo, roix.SegInfo)
+            assert s.n_components == len(ocomps)
+            assert comps[: len(ocomps) * 48].cpu().numpy().tobytes() == ocomps.tobytes()
+            # extraction: identical to the fused oracle outputs
+            g = out.collect()
+            e = g["einfo"]
+            oi = f["info"]
+            assert (e.status, e.n_rows, e.n_codes, e.n_outliers) == (0, oi.n_rows, oi.n_codes, oi.n_outliers)
+            assert g["rows"].tobytes() == f["rows"].tobytes()
+            assert g["stream"].tobytes() == f["stream"].tobytes()
+            assert g["outliers"].tobytes() == f["outliers"].tobytes()
+
+
+def test_repeat_determinism(env):
+    ctx, roix, torch = env
+    w = synth.config1(n=128)
+    crit = criterion(roix, w.criterion)
+    ref = None
+    for i in range(5):
+        log(f"[case] repeat {i}")
+        g = gpu_fused(ctx, roix, torch, w.volume, w.eb_mode, w.eb_value, crit)
+        cur = (g["rows"].tobytes(), g["stream"].tobytes(), g["comps"].tobytes(), g["outliers"].tobytes())
+        if ref is None:
+            ref = cur
+        assert cur == ref
