@@ -243,12 +243,20 @@ hipError_t launch_union(const LaunchCtx& lc, const Geom& g, const Layout& L, int
 }
 
 // Full compression: parent[i] = root(i); root flags for the component scan.
+// The walk only reads: a halving store by one thread could otherwise put an
+// intermediate ancestor back into an entry another thread has already set to
+// its root.  Each entry is written by its own thread only, so every entry
+// ends at its root.
 __global__ __launch_bounds__(kBlock) void k_flatten(uint32_t* parent, uint32_t* root_flag, const DevState* S) {
     if (thread_exit(S)) return;
     const uint32_t n = S->n_runs;
     const uint32_t nthreads = gridDim.x * blockDim.x;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += nthreads) {
-        uint32_t r = find_root(parent, i);
+        uint32_t r = i, p = ld_relaxed(&parent[i]);
+        while (p != r) {
+            r = p;
+            p = ld_relaxed(&parent[r]);
+        }
         st_relaxed(&parent[i], r);
         root_flag[i] = (r == i) ? 1u : 0u;
     }
