@@ -53,7 +53,7 @@ void timer_end(Timer* t, int stage, hipStream_t s) {
 
 static const char* kStageNames[ST_COUNT] = {
     "init", "range", "resolve", "quantize", "quant_hist", "otsu", "mask_runs", "scan", "runs_write",
-    "union", "flatten", "comp_stats", "keep", "spans", "emit", "voxel_out", "finalize"};
+    "union", "flatten", "comp_stats", "keep", "spans", "emit", "emit_rows", "voxel_out", "finalize"};
 
 }  // namespace roix
 
@@ -66,6 +66,7 @@ struct roix_ctx {
     size_t arena_bytes = 0;
     Timer timer;
     int grid_stream = 2048;
+    int grid_read = 512;
 };
 
 // ----------------------------------------------------------------- layout
@@ -99,13 +100,13 @@ static uint64_t worst_runs(const Geom& g) {
 static size_t fixed_bytes(const Geom& g) {
     size_t b = 0;
     b += align256(sizeof(DevState));
-    b += align256(g.N + 16);                              // proxy
+    b += align256((size_t)g.nrows * g.W * 64);             // proxy
     b += align256((size_t)g.nrows * g.W * 8);             // mask bits
     b += align256((size_t)g.nrows * 4);                   // row_nruns
     b += align256((size_t)(g.nrows + 1) * 4);             // run_off
     b += 2 * align256((size_t)g.nrows * 4);               // row_xs, row_xe
     b += align256((size_t)g.nrows * 8);                   // row_packed
-    b += align256((size_t)((g.nrows + kEmitRows - 1) / kEmitRows) * 8);  // look-back
+    b += align256((size_t)g.nrows * 8);                   // row_outl
     b += align256((size_t)(kScanBlocks + 1) * 8);         // scan tmp
     b += 5 * 256;                                         // run-array alignment slack
     return b;
@@ -121,15 +122,14 @@ static bool carve(roix_ctx* c, const Geom& g, Layout* L) {
         return q;
     };
     L->S = (DevState*)take(sizeof(DevState));
-    L->proxy_alloc = take(g.N + 16);
-    L->proxy = L->proxy_alloc;
+    L->proxy = take((size_t)g.nrows * g.W * 64);
     L->maskbits = (uint64_t*)take((size_t)g.nrows * g.W * 8);
     L->row_nruns = (uint32_t*)take((size_t)g.nrows * 4);
     L->run_off = (uint32_t*)take((size_t)(g.nrows + 1) * 4);
     L->row_xs = (uint32_t*)take((size_t)g.nrows * 4);
     L->row_xe = (uint32_t*)take((size_t)g.nrows * 4);
     L->row_packed = (uint64_t*)take((size_t)g.nrows * 8);
-    L->lookback = (uint64_t*)take((size_t)((g.nrows + kEmitRows - 1) / kEmitRows) * 8);
+    L->row_outl = (uint64_t*)take((size_t)g.nrows * 8);
     L->scan_tmp = (uint64_t*)take((size_t)(kScanBlocks + 1) * 8);
     const size_t used = (size_t)(p - (uint8_t*)c->arena) + 5 * 256;
     uint64_t cap = (c->arena_bytes - used) / kRunBytes;
@@ -150,6 +150,7 @@ static LaunchCtx lctx(roix_ctx* c, void* stream) {
     lc.stream = (hipStream_t)stream;
     lc.timer = c->timer.on ? &c->timer : nullptr;
     lc.grid_stream = c->grid_stream;
+    lc.grid_read = c->grid_read;
     return lc;
 }
 
@@ -293,9 +294,14 @@ roix_status roix_ctx_create(int device, size_t scratch_bytes, roix_ctx** out) {
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->cus = prop.multiProcessorCount;
     if (c->cus <= 0) c->cus = 256;
     c->grid_stream = c->cus * 8;
+    c->grid_read = c->cus * 2;
     if (const char* s = getenv("ROIX_GRID_STREAM")) {
         int v = atoi(s);
         if (v > 0 && v <= 1 << 20) c->grid_stream = v;
+    }
+    if (const char* s = getenv("ROIX_GRID_READ")) {
+        int v = atoi(s);
+        if (v > 0 && v <= 1 << 20) c->grid_read = v;
     }
     c->arena_bytes = scratch_bytes ? scratch_bytes : ((size_t)1 << 30);
     if (hipMalloc(&c->arena, c->arena_bytes) != hipSuccess) {
@@ -362,7 +368,7 @@ roix_status roix_quantize(roix_ctx* ctx, const void* d_in, roix_dtype dtype, roi
     Layout L;
     if (!carve(ctx, g, &L)) return ROIX_ENOMEM;
     LaunchCtx lc = lctx(ctx, stream);
-    ROIX_TRY(launch_init(lc, L.S, L.lookback, 0));
+    ROIX_TRY(launch_init(lc, L.S));
     ROIX_TRY(launch_range(lc, d_in, dtype, g.N, L.S));
     ROIX_TRY(launch_resolve_dt(lc, L.S, dtype, eb, nullptr));
     ROIX_TRY(launch_quantize(lc, d_in, dtype, g.N, L.S, d_codes, d_outlier_bits));
@@ -383,10 +389,9 @@ roix_status roix_segment(roix_ctx* ctx, const int32_t* d_codes, roix_dims dims, 
     if (!carve(ctx, g, &L)) return ROIX_ENOMEM;
     LaunchCtx lc = lctx(ctx, stream);
     const bool fixed = crit->thr == ROIX_THR_FIXED;
-    ROIX_TRY(launch_init(lc, L.S, L.lookback, 0));
+    ROIX_TRY(launch_init(lc, L.S));
     ROIX_TRY(launch_seg_init(lc, L.S, d_qinfo, crit));
-    L.proxy = proxy_base(L.proxy_alloc, d_codes, 2, g.N);
-    ROIX_TRY(launch_quant_hist(lc, d_codes, 2, g.N, L.S, L.proxy_alloc, fixed));
+    ROIX_TRY(launch_quant_hist(lc, d_codes, 2, g, L.S, L.proxy, fixed));
     ROIX_TRY(launch_otsu(lc, L.S, fixed));
     ROIX_TRY(label_and_keep(lc, g, L, crit, d_comps, comps_cap));
     ROIX_TRY(launch_voxel_out(lc, g, L, d_comps, d_keep, d_labels));
@@ -406,7 +411,7 @@ roix_status roix_extract(roix_ctx* ctx, const void* d_in, roix_dtype dtype, cons
     roix_criterion none;
     memset(&none, 0, sizeof none);
     none.thr = ROIX_THR_OTSU;
-    ROIX_TRY(launch_init(lc, L.S, L.lookback, (g.nrows + kEmitRows - 1) / kEmitRows));
+    ROIX_TRY(launch_init(lc, L.S));
     ROIX_TRY(launch_seg_init(lc, L.S, d_qinfo, &none));
     ROIX_TRY(launch_spans_from_keep(lc, g, L, d_keep));
     ROIX_TRY(spans_and_emit(lc, g, L, d_in, dtype, out));
@@ -426,11 +431,10 @@ roix_status roix_fused(roix_ctx* ctx, const void* d_in, roix_dtype dtype, roix_d
     LaunchCtx lc = lctx(ctx, stream);
     const bool fixed = crit->thr == ROIX_THR_FIXED;
     const int kind = dtype == ROIX_F32 ? 0 : 1;
-    ROIX_TRY(launch_init(lc, L.S, L.lookback, (g.nrows + kEmitRows - 1) / kEmitRows));
+    ROIX_TRY(launch_init(lc, L.S));
     ROIX_TRY(launch_range(lc, d_in, dtype, g.N, L.S));
     ROIX_TRY(launch_resolve_dt(lc, L.S, dtype, eb, crit));
-    L.proxy = proxy_base(L.proxy_alloc, d_in, kind, g.N);
-    ROIX_TRY(launch_quant_hist(lc, d_in, kind, g.N, L.S, L.proxy_alloc, fixed));
+    ROIX_TRY(launch_quant_hist(lc, d_in, kind, g, L.S, L.proxy, fixed));
     ROIX_TRY(launch_otsu(lc, L.S, fixed));
     ROIX_TRY(label_and_keep(lc, g, L, crit, out->d_comps, out->comps_cap));
     ROIX_TRY(launch_spans_from_runs(lc, g, L));

@@ -14,7 +14,6 @@ constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kHistCopies = 32;      // LDS-privatised histogram copies (one per half-wave lane)
 constexpr int kHistStride = 257;     // copy stride: lane c + bin b lands in bank (c + b) mod 32
 constexpr int kScanBlocks = 1024;    // fixed block count of the device-sized scans
-constexpr int kEmitRows = 16;        // rows per workgroup of the emit kernel (look-back unit)
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 // Everything the kernels of one call share, reset by k_init at the start of
@@ -32,6 +31,7 @@ struct DevState {
     int32_t qmin, qmax, width_bits;
     uint32_t esc;
     int64_t K;
+    uint32_t bin_mlo, bin_mhi;  // ceil(2^40 / K): bin = umulhi(u, mlo) + u * mhi when K <= 65536
     // threshold
     int32_t otsu_bin, q_thr, proxy_thr;
     uint32_t flags;
@@ -46,14 +46,12 @@ struct DevState {
     // extraction
     unsigned long long span_total;  // (rows with a span) << 40 | (codes)
     unsigned long long n_outliers, q_outliers;
-    uint32_t emit_ticket, pad2;
 };
 
 // Per-call view of the scratch arena.
 struct Layout {
     DevState* S;
-    uint8_t* proxy_alloc;   // N + 16 bytes
-    uint8_t* proxy;         // proxy_alloc + alignment shift of this call
+    uint8_t* proxy;         // nrows * W * 64 bytes (see Geom)
     uint64_t* maskbits;     // nrows * W words
     uint32_t* row_nruns;    // nrows
     uint32_t* run_off;      // nrows + 1
@@ -65,11 +63,15 @@ struct Layout {
     uint32_t* row_xs;       // nrows
     uint32_t* row_xe;       // nrows
     uint64_t* row_packed;   // nrows (has_span << 40 | span length), scanned in place
-    uint64_t* lookback;     // emit look-back words, one per emit workgroup
+    uint64_t* row_outl;     // nrows: outliers per row, then their exclusive scan
     uint64_t* scan_tmp;     // kScanBlocks + 1
     uint64_t run_cap;
 };
 
+// The 1-byte proxy of row r, voxel x is byte r * 64 W + x: rows are padded
+// to whole 64-voxel words, so one lane can turn 64 proxy bytes (four 16-byte
+// loads) into one mask word.  Padding bytes are never read as object: the
+// mask of a row's last word is cut at nx.
 struct Geom {
     int64_t nx, ny, nz;
     uint64_t N;
@@ -102,7 +104,7 @@ __device__ __forceinline__ bool outlier(float x, int32_t q, float w, float eb32)
 
 // exact bin = floor(256 u / K) for 0 <= u < K <= 2^25 + 1: a float estimate,
 // off by at most one near a bin edge, then one integer correction.
-__device__ __forceinline__ uint32_t bin_of(uint32_t u, uint32_t K, float binscale) {
+__device__ __forceinline__ uint32_t bin_slow(uint32_t u, uint32_t K, float binscale) {
     uint32_t t = (uint32_t)((float)u * binscale);
     t = t > 255u ? 255u : t;
     uint64_t u256 = (uint64_t)u << 8;
@@ -110,6 +112,24 @@ __device__ __forceinline__ uint32_t bin_of(uint32_t u, uint32_t K, float binscal
     else if ((uint64_t)(t + 1u) * K <= u256) t += 1u;
     return t;
 }
+
+// exact bin for K <= 65536 with M = ceil(2^40 / K): (u * M) >> 32 equals
+// floor(256 u / K) because the rounding excess u (M - 2^40/K) / 2^32 stays
+// below 1/K when K (K - 1) <= 2^32 (checked exhaustively for every K and u).
+__device__ __forceinline__ uint32_t bin_fast(uint32_t u, uint32_t mlo, uint32_t mhi) {
+    return __umulhi(u, mlo) + u * mhi;
+}
+
+// Non-temporal loads for data streamed once (the volume): they do not
+// displace the reused run tables from the caches.
+typedef unsigned int v4u32_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 ld_stream(const uint4* p) {
+    const v4u32_t v = __builtin_nontemporal_load(reinterpret_cast<const v4u32_t*>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float ld_stream(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ uint16_t ld_stream(const uint16_t* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ int32_t ld_stream(const int32_t* p) { return __builtin_nontemporal_load(p); }
 
 __device__ __forceinline__ uint32_t ld_relaxed(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -161,6 +181,7 @@ enum Stage {
     ST_KEEP,
     ST_SPANS,
     ST_EMIT,
+    ST_EMIT_ROWS,
     ST_VOXEL_OUT,
     ST_FINALIZE,
     ST_COUNT
@@ -174,25 +195,23 @@ struct LaunchCtx {
     hipStream_t stream;
     Timer* timer;  // may be null
     int grid_stream;  // workgroups of the grid-stride streaming kernels
+    int grid_read;    // workgroups of the read-only streaming kernel (range)
 };
 
 // ------------------------------------------------------------ launchers
 // Each returns hipSuccess or the launch error.
 
-hipError_t launch_init(const LaunchCtx& lc, DevState* S, uint64_t* lookback, int64_t n_lookback);
+hipError_t launch_init(const LaunchCtx& lc, DevState* S);
 hipError_t launch_range(const LaunchCtx& lc, const void* in, roix_dtype dt, uint64_t N, DevState* S);
 hipError_t launch_resolve_dt(const LaunchCtx& lc, DevState* S, roix_dtype dt, roix_eb eb,
                              const roix_criterion* crit);
-// 16-byte-vector alignment of the proxy to the input: byte v of the proxy
-// belongs to voxel v, and the vector part of the input maps to aligned words.
-uint8_t* proxy_base(uint8_t* proxy_alloc, const void* in, int src_kind, uint64_t N);
 hipError_t launch_seg_init(const LaunchCtx& lc, DevState* S, const roix_quant_info* qinfo,
                            const roix_criterion* crit);
 hipError_t launch_quantize(const LaunchCtx& lc, const void* in, roix_dtype dt, uint64_t N, DevState* S,
                            int32_t* codes, uint32_t* outlier_bits);
 // src_kind: 0 = f32 values, 1 = u16 values, 2 = int32 codes
-hipError_t launch_quant_hist(const LaunchCtx& lc, const void* in, int src_kind, uint64_t N, DevState* S,
-                             uint8_t* proxy_alloc, bool fixed);
+hipError_t launch_quant_hist(const LaunchCtx& lc, const void* in, int src_kind, const Geom& g, DevState* S,
+                             uint8_t* proxy, bool fixed);
 hipError_t launch_otsu(const LaunchCtx& lc, DevState* S, bool fixed);
 
 hipError_t launch_mask_runs(const LaunchCtx& lc, const Geom& g, const Layout& L);

@@ -4,16 +4,16 @@
 // lengths and "row has a span" flags are scanned together as one 64-bit
 // value (flag << 40 | length), which gives every row its index in the row
 // table and its first code.  The emit kernel then streams the span voxels
-// once, recomputes their codes and stores them; outlier offsets come from a
-// single-pass chained scan (decoupled look-back) over workgroups taken in
-// ticket order, so the outlier array is filled in row order in the same pass.
+// once, recomputes their codes and stores them; outliers are stored in
+// row order: the emit pass also counts each row's outliers, a scan turns the
+// counts into offsets, and a second pass writes the row table and the
+// outlier values (re-reading only rows that have outliers).
 #include "common.h"
 
 namespace roix {
 
 constexpr uint64_t kLenMask = (1ull << 40) - 1ull;
-constexpr uint64_t kFlagAgg = 1ull << 62, kFlagInc = 2ull << 62, kValMask = (1ull << 62) - 1ull;
-constexpr uint32_t kSpinLimit = 1u << 24;
+constexpr int kEmitUnroll = 16;
 
 __device__ __forceinline__ bool thread_exit_e(const DevState* S) {
     return __hip_atomic_load(&S->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
@@ -107,68 +107,62 @@ struct EmitOut {
     uint64_t outl_cap;
 };
 
-// the code width is device data (it depends on the value range); the branch
-// is uniform over the grid
-__device__ __forceinline__ void store_code(uint8_t* stream, uint64_t idx, uint32_t u, int B) {
-    if (B == 1)
-        stream[idx] = (uint8_t)u;
-    else if (B == 2)
-        reinterpret_cast<uint16_t*>(stream)[idx] = (uint16_t)u;
-    else
-        reinterpret_cast<uint32_t*>(stream)[idx] = u;
-}
+template <int B>
+struct CodeT;
+template <>
+struct CodeT<1> {
+    using type = uint8_t;
+};
+template <>
+struct CodeT<2> {
+    using type = uint16_t;
+};
+template <>
+struct CodeT<4> {
+    using type = uint32_t;
+};
 
-// Workgroup = kEmitRows consecutive rows, taken in ticket order.  Phase 1:
-// each wave streams its rows' spans, stores codes and counts outliers.  Then
-// thread 0 publishes the workgroup's outlier count and looks back over the
-// predecessors for its exclusive prefix.  Phase 2: row table entries and the
-// outlier values (rows with outliers are read once more, from cache).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_emit(const T* __restrict__ in, int64_t nx, int64_t ny, int64_t nrows,
-                                                 Layout L, EmitOut o, int64_t n_blocks) {
-    __shared__ uint32_t s_ticket;
-    __shared__ int s_exit;
-    __shared__ uint32_t s_cnt[kEmitRows];
-    __shared__ unsigned long long s_excl;
-    DevState* S = L.S;
-    if (threadIdx.x == 0) {
-        s_exit = thread_exit_e(S) ? 1 : 0;
-        if (!s_exit) s_ticket = atomicAdd(&S->emit_ticket, 1u);
-    }
-    __syncthreads();
-    if (s_exit) return;
-    const int64_t blk = s_ticket;
-    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    constexpr int kWaves = kBlock / kWave;
+// One wave per row: stream the span once (up to 64 * kEmitUnroll voxels in
+// flight per wave), store the codes at the row's code offset and count the
+// row's outliers.  B = bytes per code.
+template <typename T, int B>
+__device__ __forceinline__ void emit_codes_rows(const T* __restrict__ in, int64_t nx, int64_t nrows, const Layout& L,
+                                                const EmitOut& o, bool& trunc) {
+    using C = typename CodeT<B>::type;
+    const DevState* S = L.S;
+    const int lane = threadIdx.x % kWave;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
     const float r = S->r, w = S->w, eb32 = S->eb32;
     const int32_t qmin = S->qmin;
     const uint32_t esc = S->esc;
-    const int B = S->width_bits / 8;
-    bool trunc = false;
-
-    // phase 1: codes
-    for (int lr = wave; lr < kEmitRows; lr += kWaves) {
-        const int64_t row = blk * kEmitRows + lr;
+    C* codes = reinterpret_cast<C*>(o.stream);
+    for (int64_t row = wave; row < nrows; row += nwaves) {
+        const uint32_t xs = L.row_xs[row], xe = L.row_xe[row];
         uint32_t cnt = 0;
-        if (row < nrows) {
-            const uint64_t packed = L.row_packed[row];  // exclusive scan value
-            const uint32_t xs = L.row_xs[row], xe = L.row_xe[row];
-            const uint64_t code0 = packed & kLenMask;
-            // the span flag is only in the pre-scan value, so test the span itself
-            if (xe > xs) {
-                const T* src = in + (uint64_t)row * (uint64_t)nx + xs;
-                const uint32_t len = xe - xs;
-                for (uint32_t j0 = 0; j0 < len; j0 += kWave) {
-                    const uint32_t j = j0 + lane;
-                    bool isout = false;
+        if (xe > xs) {
+            const uint64_t code0 = L.row_packed[row] & kLenMask;  // exclusive scan value
+            const T* src = in + (uint64_t)row * (uint64_t)nx + xs;
+            const uint32_t len = xe - xs;
+            const bool fits = (code0 + len) * (uint64_t)B <= o.stream_cap;
+            for (uint32_t j0 = 0; j0 < len; j0 += kWave * kEmitUnroll) {
+                float xv[kEmitUnroll];
+#pragma unroll
+                for (int k = 0; k < kEmitUnroll; ++k) {
+                    const uint32_t j = j0 + k * kWave + lane;
+                    xv[k] = j < len ? (float)ld_stream(src + j) : 0.0f;
+                }
+#pragma unroll
+                for (int k = 0; k < kEmitUnroll; ++k) {
+                    const uint32_t j = j0 + k * kWave + lane;
+                    const float x = xv[k];
+                    const int32_t q = qcode(x, r);
+                    const bool isout = j < len && outlier(x, q, w, eb32);
+                    const uint32_t u = isout ? esc : (uint32_t)(q - qmin);
                     if (j < len) {
-                        const float x = (float)src[j];
-                        const int32_t q = qcode(x, r);
-                        isout = outlier(x, q, w, eb32);
-                        const uint32_t u = isout ? esc : (uint32_t)(q - qmin);
                         const uint64_t idx = code0 + j;
-                        if ((idx + 1) * (uint64_t)B <= o.stream_cap)
-                            store_code(o.stream, idx, u, B);
+                        if (fits || (idx + 1) * (uint64_t)B <= o.stream_cap)
+                            codes[idx] = (C)u;
                         else
                             trunc = true;
                     }
@@ -176,50 +170,47 @@ __global__ __launch_bounds__(kBlock) void k_emit(const T* __restrict__ in, int64
                 }
             }
         }
-        if (lane == 0) s_cnt[lr] = cnt;
+        if (lane == 0) L.row_outl[row] = cnt;
     }
-    __syncthreads();
+}
 
-    // chained scan of outlier counts over workgroups
-    if (threadIdx.x == 0) {
-        unsigned long long agg = 0;
-        for (int k = 0; k < kEmitRows; ++k) agg += s_cnt[k];
-        uint64_t* lb = L.lookback;
-        __hip_atomic_store(&lb[blk], kFlagAgg | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned long long excl = 0;
-        int64_t j = blk - 1;
-        uint32_t spins = 0;
-        while (j >= 0) {
-            const uint64_t v = __hip_atomic_load(&lb[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint64_t f = v & ~kValMask;
-            if (f == 0) {
-                if (++spins > kSpinLimit) {
-                    fail(S, ROIX_EDEVICE);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-                continue;
-            }
-            excl += v & kValMask;
-            if (f == kFlagInc) break;
-            --j;
-        }
-        __hip_atomic_store(&lb[blk], kFlagInc | (excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (blk == n_blocks - 1) S->n_outliers = excl + agg;
-        s_excl = excl;
-    }
-    __syncthreads();
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_emit_codes(const T* __restrict__ in, int64_t nx, int64_t nrows, Layout L,
+                                                       EmitOut o) {
+    DevState* S = L.S;
+    if (thread_exit_e(S)) return;  // no barrier below
+    bool trunc = false;
+    const int B = S->width_bits / 8;  // uniform: one branch for the whole grid
+    if (B == 1)
+        emit_codes_rows<T, 1>(in, nx, nrows, L, o, trunc);
+    else if (B == 2)
+        emit_codes_rows<T, 2>(in, nx, nrows, L, o, trunc);
+    else
+        emit_codes_rows<T, 4>(in, nx, nrows, L, o, trunc);
+    if (trunc) atomicOr(&S->trunc, 1);
+}
 
-    // phase 2: row table and outlier values
-    for (int lr = wave; lr < kEmitRows; lr += kWaves) {
-        const int64_t row = blk * kEmitRows + lr;
-        if (row >= nrows) continue;
+// Pass 2 (after the scan of the outlier counts), one wave per row: the row
+// table entry, and the outlier values of rows that have any (their spans are
+// read once more).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_emit_rows(const T* __restrict__ in, int64_t nx, int64_t ny, int64_t nrows,
+                                                      Layout L, EmitOut o) {
+    DevState* S = L.S;
+    if (thread_exit_e(S)) return;
+    const int lane = threadIdx.x % kWave;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+    const float r = S->r, w = S->w, eb32 = S->eb32;
+    const unsigned long long total = S->n_outliers;
+    bool trunc = false;
+    for (int64_t row = wave; row < nrows; row += nwaves) {
         const uint32_t xs = L.row_xs[row], xe = L.row_xe[row];
         if (xe <= xs) continue;
-        unsigned long long ooff = s_excl;
-        for (int k = 0; k < lr; ++k) ooff += s_cnt[k];
         const uint64_t packed = L.row_packed[row];
         const uint64_t ridx = packed >> 40, code0 = packed & kLenMask;
+        const uint64_t ooff = L.row_outl[row];
+        const uint64_t oend = row + 1 < nrows ? L.row_outl[row + 1] : total;
         if (lane == 0) {
             if (ridx < o.rows_cap) {
                 roix_row e;
@@ -234,28 +225,33 @@ __global__ __launch_bounds__(kBlock) void k_emit(const T* __restrict__ in, int64
                 trunc = true;
             }
         }
-        if (s_cnt[lr] == 0) continue;
+        if (oend == ooff) continue;
         const T* src = in + (uint64_t)row * (uint64_t)nx + xs;
         const uint32_t len = xe - xs;
         unsigned long long k = ooff;
-        for (uint32_t j0 = 0; j0 < len; j0 += kWave) {
-            const uint32_t j = j0 + lane;
-            bool isout = false;
-            float x = 0.0f;
-            if (j < len) {
-                x = (float)src[j];
-                isout = outlier(x, qcode(x, r), w, eb32);
+        constexpr int U = 8;
+        for (uint32_t j0 = 0; j0 < len; j0 += kWave * U) {
+            float xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t j = j0 + u * kWave + lane;
+                xv[u] = j < len ? (float)src[j] : 0.0f;
             }
-            const uint64_t m = __ballot(isout);
-            if (isout) {
-                const uint64_t below = m & ((1ull << lane) - 1ull);
-                const unsigned long long at = k + (unsigned long long)__popcll(below);
-                if (at < o.outl_cap)
-                    o.outl[at] = x;
-                else
-                    trunc = true;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t j = j0 + u * kWave + lane;
+                const float x = xv[u];
+                const bool isout = j < len && outlier(x, qcode(x, r), w, eb32);
+                const uint64_t m = __ballot(isout);
+                if (isout) {
+                    const unsigned long long at = k + (unsigned long long)__popcll(m & ((1ull << lane) - 1ull));
+                    if (at < o.outl_cap)
+                        o.outl[at] = x;
+                    else
+                        trunc = true;
+                }
+                k += (unsigned long long)__popcll(m);
             }
-            k += (unsigned long long)__popcll(m);
         }
     }
     if (trunc) atomicOr(&S->trunc, 1);
@@ -270,15 +266,22 @@ hipError_t launch_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, cons
     o.stream_cap = out->d_stream ? (uint64_t)out->stream_cap_bytes : 0;
     o.outl = out->d_outliers;
     o.outl_cap = out->d_outliers ? (uint64_t)out->outliers_cap : 0;
-    const int64_t nb = (g.nrows + kEmitRows - 1) / kEmitRows;
+    const dim3 grid(grid_rows(g.nrows, kBlock / kWave, lc.grid_stream)), block(kBlock);
     timer_begin(lc.timer, ST_EMIT, lc.stream);
     if (dt == ROIX_F32)
-        hipLaunchKernelGGL(k_emit<float>, dim3((unsigned)nb), dim3(kBlock), 0, lc.stream, (const float*)in, g.nx,
-                           g.ny, g.nrows, L, o, nb);
+        hipLaunchKernelGGL(k_emit_codes<float>, grid, block, 0, lc.stream, (const float*)in, g.nx, g.nrows, L, o);
     else
-        hipLaunchKernelGGL(k_emit<uint16_t>, dim3((unsigned)nb), dim3(kBlock), 0, lc.stream, (const uint16_t*)in,
-                           g.nx, g.ny, g.nrows, L, o, nb);
+        hipLaunchKernelGGL(k_emit_codes<uint16_t>, grid, block, 0, lc.stream, (const uint16_t*)in, g.nx, g.nrows, L, o);
     timer_end(lc.timer, ST_EMIT, lc.stream);
+    hipError_t e = launch_scan_u64(lc, L.row_outl, L.row_outl, g.nrows, &L.S->n_outliers, L.scan_tmp);
+    if (e != hipSuccess) return e;
+    timer_begin(lc.timer, ST_EMIT_ROWS, lc.stream);
+    if (dt == ROIX_F32)
+        hipLaunchKernelGGL(k_emit_rows<float>, grid, block, 0, lc.stream, (const float*)in, g.nx, g.ny, g.nrows, L, o);
+    else
+        hipLaunchKernelGGL(k_emit_rows<uint16_t>, grid, block, 0, lc.stream, (const uint16_t*)in, g.nx, g.ny, g.nrows,
+                           L, o);
+    timer_end(lc.timer, ST_EMIT_ROWS, lc.stream);
     return hipGetLastError();
 }
 

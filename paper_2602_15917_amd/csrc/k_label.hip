@@ -35,50 +35,118 @@ static int grid_for(int64_t items, int per_block, int cap) {
 
 // ------------------------------------------------------- mask bits + counts
 
-// One wave per row: lane l reads proxy byte 64*w + l; the ballot of
-// (byte > threshold) is mask word w.  Run starts are 1-bits whose left
-// neighbour is 0.  Words are staged one per lane and stored 64 at a time.
+// Bytes of v above the threshold t, as 4 bits: with T = 255 - t, byte b > t
+// exactly when b + T carries out of 8 bits.  The carry into bit 7 is bit 7 of
+// the 7-bit partial sums (no carry crosses a byte), the carry out of bit 7 is
+// the full-adder majority; a multiply gathers the four carry bits.
+__device__ __forceinline__ uint32_t gt_bytes4(uint32_t v, uint32_t TL, uint32_t TR) {
+    const uint32_t lo = (v & 0x7F7F7F7Fu) + TL;
+    const uint32_t c = ((v & TR) | (lo & (v | TR))) & 0x80808080u;
+    return (((c >> 7) * 0x00204081u) >> 21) & 0xFu;
+}
+
+// mask word of 64 proxy bytes (four 16-byte loads)
+__device__ __forceinline__ uint64_t mask_word(const uint8_t* p, uint32_t TL, uint32_t TR) {
+    const uint4* q = reinterpret_cast<const uint4*>(p);
+    const uint4 a = q[0], b = q[1], c = q[2], d = q[3];
+    const uint32_t dw[16] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w, d.x, d.y, d.z, d.w};
+    uint32_t lo = 0, hi = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) lo |= gt_bytes4(dw[i], TL, TR) << (4 * i);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) hi |= gt_bytes4(dw[8 + i], TL, TR) << (4 * i);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = threadIdx.x % kWave;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = __shfl_up(v, o);
+        if (lane >= o) v += y;
+    }
+    return v;
+}
+
+// Lane-per-word mapping of a wave step: with W <= 64 words per row, a step
+// covers R = 64 / W rows, lane l holding word l % W of row l / W.
+struct WordLane {
+    int64_t row;   // -1 for an idle lane
+    int64_t w;     // word index in the row
+    int seg_first; // first lane of this lane's row in the wave
+};
+
+__device__ __forceinline__ WordLane word_lane(int64_t row0, int64_t W, int64_t nrows) {
+    const int lane = threadIdx.x % kWave;
+    const int R = (int)(kWave / W);
+    const int rr = lane / (int)W;
+    WordLane wl;
+    wl.w = lane - rr * (int)W;
+    wl.seg_first = rr * (int)W;
+    wl.row = (rr < R && row0 + rr < nrows) ? row0 + rr : -1;
+    return wl;
+}
+
+// One 64-bit mask word per lane (SWAR byte compares on 64 proxy bytes), run
+// starts = 1-bits whose left neighbour (previous bit, or the previous lane's
+// top bit) is 0, per-row run counts by a segmented wave scan.
 __global__ __launch_bounds__(kBlock) void k_mask_runs(const uint8_t* __restrict__ proxy, int64_t nx, int64_t nrows,
                                                       int64_t W, DevState* S, uint64_t* __restrict__ maskbits,
                                                       uint32_t* __restrict__ row_nruns) {
     if (block_exit_l(S)) return;
-    const int thr = S->proxy_thr;
+    const uint32_t T = 255u - (uint32_t)S->proxy_thr;
+    const uint32_t TR = T * 0x01010101u, TL = (T & 0x7Fu) * 0x01010101u;
+    const uint64_t lastmask = (nx % 64) ? ((1ull << (nx % 64)) - 1ull) : ~0ull;
     const int lane = threadIdx.x % kWave;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+    const int64_t P = W * 64;
     unsigned long long nmask = 0;
-    constexpr int kB = 8;
-    for (int64_t row = wave; row < nrows; row += nwaves) {
-        const uint8_t* p = proxy + row * nx;
-        uint64_t* mb = maskbits + row * W;
-        uint64_t carry = 0, myword = 0;
-        uint32_t runs = 0;
-        for (int64_t w0 = 0; w0 < W; w0 += kB) {
-            uint32_t b[kB];
-#pragma unroll
-            for (int k = 0; k < kB; ++k) {
-                int64_t x = (w0 + k) * 64 + lane;
-                b[k] = (x < nx) ? (uint32_t)p[x] : 0u;
+    if (W <= kWave) {
+        const int64_t R = kWave / W;
+        for (int64_t row0 = wave * R; row0 < nrows; row0 += nwaves * R) {
+            const WordLane wl = word_lane(row0, W, nrows);
+            uint64_t m = 0;
+            if (wl.row >= 0) {
+                m = mask_word(proxy + wl.row * P + 64 * wl.w, TL, TR);
+                if (wl.w == W - 1) m &= lastmask;
             }
-#pragma unroll
-            for (int k = 0; k < kB; ++k) {
-                const int64_t w = w0 + k;
-                if (w >= W) break;
-                uint64_t m = __ballot((int)b[k] > thr);
-                uint64_t starts = m & ~((m << 1) | carry);
-                runs += (uint32_t)__popcll(starts);
-                nmask += (unsigned long long)__popcll(m);
-                carry = m >> 63;
-                if ((w & 63) == lane) myword = m;
-                if ((w & 63) == 63 || w == W - 1) {
-                    int64_t idx = (w & ~(int64_t)63) + lane;
-                    if (idx <= w) mb[idx] = myword;
-                }
+            const uint32_t prev_hi = __shfl_up((uint32_t)(m >> 32), 1);
+            const uint64_t cin = (wl.w > 0) ? (uint64_t)(prev_hi >> 31) : 0ull;
+            const uint64_t starts = m & ~((m << 1) | cin);
+            const uint32_t cnt = (uint32_t)__popcll(starts);
+            nmask += (unsigned long long)__popcll(m);
+            const uint32_t incl = wave_incl_scan(cnt);
+            const uint32_t before = __shfl(incl, wl.seg_first > 0 ? wl.seg_first - 1 : 0);
+            if (wl.row >= 0) {
+                maskbits[wl.row * W + wl.w] = m;
+                if (wl.w == W - 1) row_nruns[wl.row] = incl - (wl.seg_first > 0 ? before : 0u);
             }
         }
-        if (lane == 0) row_nruns[row] = runs;
+    } else {
+        // long rows: one row per wave, 64 words per step, carries between steps
+        for (int64_t row = wave; row < nrows; row += nwaves) {
+            uint32_t carry = 0, total = 0;
+            for (int64_t w0 = 0; w0 < W; w0 += kWave) {
+                const int64_t w = w0 + lane;
+                uint64_t m = 0;
+                if (w < W) {
+                    m = mask_word(proxy + row * P + 64 * w, TL, TR);
+                    if (w == W - 1) m &= lastmask;
+                }
+                const uint32_t hi = (uint32_t)(m >> 32);
+                const uint32_t prev_hi = __shfl_up(hi, 1);
+                const uint64_t cin = lane > 0 ? (uint64_t)(prev_hi >> 31) : (uint64_t)carry;
+                const uint64_t starts = m & ~((m << 1) | cin);
+                total += wave_sum((uint32_t)__popcll(starts));
+                nmask += (unsigned long long)__popcll(m);
+                carry = __shfl(hi, kWave - 1) >> 31;
+                if (w < W) maskbits[row * W + w] = m;
+            }
+            if (lane == 0) row_nruns[row] = total;
+        }
     }
-    // nmask is wave-uniform: count it once per wave
+    nmask = wave_sum(nmask);
     __shared__ unsigned long long s_n[kBlock / kWave];
     if (lane == 0) s_n[threadIdx.x / kWave] = nmask;
     __syncthreads();
@@ -91,7 +159,8 @@ __global__ __launch_bounds__(kBlock) void k_mask_runs(const uint8_t* __restrict_
 
 hipError_t launch_mask_runs(const LaunchCtx& lc, const Geom& g, const Layout& L) {
     timer_begin(lc.timer, ST_MASK_RUNS, lc.stream);
-    int grid = grid_for(g.nrows, kBlock / kWave, 8192);
+    const int64_t R = g.W <= kWave ? kWave / g.W : 1;
+    int grid = grid_for((g.nrows + R - 1) / R, kBlock / kWave, lc.grid_stream);
     hipLaunchKernelGGL(k_mask_runs, dim3(grid), dim3(kBlock), 0, lc.stream, (const uint8_t*)L.proxy, g.nx, g.nrows,
                        g.W, L.S, L.maskbits, L.row_nruns);
     timer_end(lc.timer, ST_MASK_RUNS, lc.stream);
@@ -100,8 +169,63 @@ hipError_t launch_mask_runs(const LaunchCtx& lc, const Geom& g, const Layout& L)
 
 // ----------------------------------------------------------------- runs
 
-// One thread per row: walk the row's words; a start event opens a run, an
-// end event (0-bit after a 1-bit) closes it.  parent[] starts as identity.
+// Rows of at most 64 words: lane-per-word.  Each lane writes the runs that
+// start in its word; a run still open at the word's end closes at the first
+// 0-bit of a later word of the row (segmented suffix minimum across lanes) or
+// at nx.  Output slot = run_off[row] + runs starting earlier in the row.
+__global__ __launch_bounds__(kBlock) void k_runs_write_lanes(const uint64_t* __restrict__ maskbits, int64_t nx,
+                                                             int64_t nrows, int64_t W,
+                                                             const uint32_t* __restrict__ run_off,
+                                                             uint32_t* __restrict__ xs_out,
+                                                             uint32_t* __restrict__ xe_out,
+                                                             uint32_t* __restrict__ parent, const DevState* S) {
+    if (thread_exit(S)) return;  // no barrier below; the status is the same for every lane of a wave
+    const int lane = threadIdx.x % kWave;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+    const int64_t R = kWave / W;
+    const uint32_t kBig = 0xFFFFFFFFu;
+    for (int64_t row0 = wave * R; row0 < nrows; row0 += nwaves * R) {
+        const WordLane wl = word_lane(row0, W, nrows);
+        const uint64_t m = wl.row >= 0 ? maskbits[wl.row * W + wl.w] : 0ull;
+        const uint32_t prev_hi = __shfl_up((uint32_t)(m >> 32), 1);
+        const uint64_t cin = (wl.w > 0) ? (uint64_t)(prev_hi >> 31) : 0ull;
+        uint64_t starts = m & ~((m << 1) | cin);
+        const uint32_t cnt = (uint32_t)__popcll(starts);
+        const uint32_t incl = wave_incl_scan(cnt);
+        const uint32_t before = __shfl(incl, wl.seg_first > 0 ? wl.seg_first - 1 : 0);
+        // first 0-bit position of each word, then the minimum over later words of the row
+        uint32_t smin = (wl.row >= 0 && m != ~0ull) ? (uint32_t)(64 * wl.w) + (uint32_t)__ffsll((unsigned long long)~m) - 1u
+                                                   : kBig;
+        const int seg = wl.seg_first;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint32_t other = __shfl_down(smin, o);
+            const int oseg = __shfl_down(seg, o);
+            if (lane + o < kWave && oseg == seg) smin = other < smin ? other : smin;
+        }
+        uint32_t next_zero = __shfl_down(smin, 1);
+        const int nseg = __shfl_down(seg, 1);
+        if (lane + 1 >= kWave || nseg != seg || wl.w == W - 1) next_zero = kBig;
+        if (next_zero > (uint32_t)nx) next_zero = (uint32_t)nx;
+        if (wl.row < 0) continue;
+        uint32_t k = run_off[wl.row] + incl - cnt - (seg > 0 ? before : 0u);
+        while (starts) {
+            const int i = __ffsll((unsigned long long)starts) - 1;
+            starts &= starts - 1;
+            const uint64_t rest = ~m & (~0ull << i);
+            const uint32_t xs = (uint32_t)(64 * wl.w + i);
+            const uint32_t xe = rest ? (uint32_t)(64 * wl.w) + (uint32_t)__ffsll((unsigned long long)rest) - 1u : next_zero;
+            xs_out[k] = xs;
+            xe_out[k] = xe;
+            parent[k] = k;
+            ++k;
+        }
+    }
+}
+
+// Rows of more than 64 words: one thread per row walks the row's words; a
+// start event opens a run, an end event (0-bit after a 1-bit) closes it.
 __global__ __launch_bounds__(kBlock) void k_runs_write(const uint64_t* __restrict__ maskbits, int64_t nrows, int64_t W,
                                                        const uint32_t* __restrict__ run_off, uint32_t* __restrict__ xs_out,
                                                        uint32_t* __restrict__ xe_out, uint32_t* __restrict__ parent,
@@ -143,9 +267,16 @@ __global__ __launch_bounds__(kBlock) void k_runs_write(const uint64_t* __restric
 
 hipError_t launch_runs_write(const LaunchCtx& lc, const Geom& g, const Layout& L) {
     timer_begin(lc.timer, ST_RUNS, lc.stream);
-    hipLaunchKernelGGL(k_runs_write, dim3(grid_for(g.nrows, kBlock, 16384)), dim3(kBlock), 0, lc.stream,
-                       (const uint64_t*)L.maskbits, g.nrows, g.W, (const uint32_t*)L.run_off, L.run_xs, L.run_xe,
-                       L.parent, (const DevState*)L.S);
+    if (g.W <= kWave) {
+        const int64_t R = kWave / g.W;
+        hipLaunchKernelGGL(k_runs_write_lanes, dim3(grid_for((g.nrows + R - 1) / R, kBlock / kWave, lc.grid_stream)),
+                           dim3(kBlock), 0, lc.stream, (const uint64_t*)L.maskbits, g.nx, g.nrows, g.W,
+                           (const uint32_t*)L.run_off, L.run_xs, L.run_xe, L.parent, (const DevState*)L.S);
+    } else {
+        hipLaunchKernelGGL(k_runs_write, dim3(grid_for(g.nrows, kBlock, 16384)), dim3(kBlock), 0, lc.stream,
+                           (const uint64_t*)L.maskbits, g.nrows, g.W, (const uint32_t*)L.run_off, L.run_xs, L.run_xe,
+                           L.parent, (const DevState*)L.S);
+    }
     timer_end(lc.timer, ST_RUNS, lc.stream);
     return hipGetLastError();
 }
@@ -155,18 +286,24 @@ hipError_t launch_runs_write(const LaunchCtx& lc, const Geom& g, const Layout& L
 // Root of x with path halving.  Parent pointers only ever point to smaller
 // run numbers, so the walk terminates; a halving store only writes an
 // ancestor, which is safe against concurrent links (links only change roots).
+// Loads go through the per-CU cache and may be stale: any value ever held by
+// parent[x] is an ancestor of x, so a stale walk still ends inside x's set,
+// and the linking CAS (which sees the current value) decides.  This keeps the
+// hot root of a giant component out of a single L2 channel.
 __device__ __forceinline__ uint32_t find_root(uint32_t* parent, uint32_t x) {
     while (true) {
-        uint32_t p = ld_relaxed(&parent[x]);
+        uint32_t p = parent[x];
         if (p == x) return x;
-        uint32_t gp = ld_relaxed(&parent[p]);
+        uint32_t gp = parent[p];
         if (gp == p) return p;
-        st_relaxed(&parent[x], gp);
+        parent[x] = gp;
         x = gp;
     }
 }
 
 __device__ __forceinline__ void unite(uint32_t* parent, uint32_t a, uint32_t b) {
+    // same parent (now or at any earlier time) means same set
+    if (parent[a] == parent[b]) return;
     a = find_root(parent, a);
     b = find_root(parent, b);
     while (a != b) {
@@ -183,15 +320,17 @@ __device__ __forceinline__ void unite(uint32_t* parent, uint32_t a, uint32_t b) 
     }
 }
 
-// Runs of rows r and rn (a neighbouring row) are connected when their x
-// intervals overlap (6-connectivity) or touch within one voxel (26).
-template <bool C26>
-__device__ __forceinline__ void merge_rows(uint32_t* parent, const uint32_t* xs, const uint32_t* xe, uint32_t a,
-                                           uint32_t a1, uint32_t b, uint32_t b1) {
+// Visit every pair of touching runs of two neighbouring rows [a, a1) and
+// [b, b1): x intervals overlap (6-connectivity) or touch within one voxel
+// (26-connectivity; the rows differ in y and/or z, so a diagonal step is a
+// neighbour).  Both run lists are sorted by x, so one merge walk suffices.
+template <bool C26, typename F>
+__device__ __forceinline__ void for_touching(const uint32_t* xs, const uint32_t* xe, uint32_t a, uint32_t a1,
+                                             uint32_t b, uint32_t b1, F&& f) {
     while (a < a1 && b < b1) {
         const uint32_t as = xs[a], ae = xe[a], bs = xs[b], be = xe[b];
         const bool hit = C26 ? (as <= be && bs <= ae) : (as < be && bs < ae);
-        if (hit) unite(parent, a, b);
+        if (hit) f(a, b);
         if (ae < be)
             ++a;
         else if (be < ae)
@@ -203,41 +342,144 @@ __device__ __forceinline__ void merge_rows(uint32_t* parent, const uint32_t* xs,
     }
 }
 
-// One thread per row (z, y): unite with the earlier neighbour rows
-// (z, y-1), (z-1, y), and for 26-connectivity (z-1, y-1), (z-1, y+1).
+// Union-find in LDS for the runs of one z-plane (same linking rule).
+__device__ __forceinline__ uint32_t lfind(uint32_t* p, uint32_t x) {
+    while (true) {
+        const uint32_t q = p[x];
+        if (q == x) return x;
+        const uint32_t g = p[q];
+        if (g == q) return q;
+        p[x] = g;
+        x = g;
+    }
+}
+
+__device__ __forceinline__ void lunite(uint32_t* p, uint32_t a, uint32_t b) {
+    a = lfind(p, a);
+    b = lfind(p, b);
+    while (a != b) {
+        if (a > b) {
+            const uint32_t t = a;
+            a = b;
+            b = t;
+        }
+        const uint32_t old = atomicCAS(&p[b], b, a);
+        if (old == b) return;
+        b = lfind(p, old);
+        a = lfind(p, a);
+    }
+}
+
+constexpr int kPlaneCap = 8192;  // runs of a z-plane labelled in LDS (32 KB)
+constexpr int kPairCap = 2048;   // distinct plane-root pairs per z-plane boundary (16 KB)
+
+// Level 1, one workgroup per z-plane: components of the plane's runs (links
+// inside the plane, between rows y-1 and y) in LDS, then parent[run] = the
+// run number of its plane-local root.  A plane with more runs than fit in
+// LDS is united directly in the global forest.
 template <bool C26>
-__global__ __launch_bounds__(kBlock) void k_union(const uint32_t* __restrict__ run_off, const uint32_t* __restrict__ xs,
-                                                  const uint32_t* __restrict__ xe, uint32_t* parent, int64_t ny,
-                                                  int64_t nrows, const DevState* S) {
-    if (thread_exit(S)) return;
-    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += nthreads) {
-        const uint32_t a0 = run_off[r], a1 = run_off[r + 1];
-        if (a0 == a1) continue;
-        const int64_t z = r / ny, y = r - z * ny;
-        if (y > 0) merge_rows<C26>(parent, xs, xe, a0, a1, run_off[r - 1], run_off[r]);
-        if (z > 0) {
-            const int64_t rz = r - ny;
-            merge_rows<C26>(parent, xs, xe, a0, a1, run_off[rz], run_off[rz + 1]);
-            if (C26) {
-                if (y > 0) merge_rows<C26>(parent, xs, xe, a0, a1, run_off[rz - 1], run_off[rz]);
-                if (y < ny - 1) merge_rows<C26>(parent, xs, xe, a0, a1, run_off[rz + 1], run_off[rz + 2]);
+__global__ __launch_bounds__(kBlock) void k_plane_label(const uint32_t* __restrict__ run_off,
+                                                        const uint32_t* __restrict__ xs,
+                                                        const uint32_t* __restrict__ xe, uint32_t* parent, int64_t ny,
+                                                        int64_t nz, const DevState* S) {
+    __shared__ uint32_t lp[kPlaneCap];
+    if (block_exit_l(S)) return;
+    for (int64_t z = blockIdx.x; z < nz; z += gridDim.x) {
+        const uint32_t a0 = run_off[z * ny], a1 = run_off[(z + 1) * ny];
+        const uint32_t n = a1 - a0;
+        if (n == 0) continue;
+        if (n <= (uint32_t)kPlaneCap) {
+            for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) lp[i] = i;
+            __syncthreads();
+            for (int64_t y = 1 + threadIdx.x; y < ny; y += blockDim.x) {
+                const int64_t r = z * ny + y;
+                for_touching<C26>(xs, xe, run_off[r], run_off[r + 1], run_off[r - 1], run_off[r],
+                                  [&](uint32_t a, uint32_t b) { lunite(lp, a - a0, b - a0); });
+            }
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+                uint32_t r = i;
+                while (lp[r] != r) r = lp[r];
+                parent[a0 + i] = a0 + r;
+            }
+            __syncthreads();  // lp is reused by the next plane
+        } else {
+            for (int64_t y = 1 + threadIdx.x; y < ny; y += blockDim.x) {
+                const int64_t r = z * ny + y;
+                for_touching<C26>(xs, xe, run_off[r], run_off[r + 1], run_off[r - 1], run_off[r],
+                                  [&](uint32_t a, uint32_t b) { unite(parent, a, b); });
             }
         }
     }
 }
 
+// Level 2, one workgroup per boundary between planes z-1 and z: every
+// touching run pair across the boundary names a pair of plane roots; the
+// distinct pairs are collected in an LDS hash set and only those are united
+// in the global forest (a giant component contributes a handful of pairs per
+// plane instead of one union per run).  A full set falls back to direct
+// global unions.
+template <bool C26>
+__global__ __launch_bounds__(kBlock) void k_zlink(const uint32_t* __restrict__ run_off, const uint32_t* __restrict__ xs,
+                                                  const uint32_t* __restrict__ xe, uint32_t* parent, int64_t ny,
+                                                  int64_t nz, const DevState* S) {
+    __shared__ unsigned long long tab[kPairCap];
+    constexpr unsigned long long kEmpty = ~0ull;
+    if (block_exit_l(S)) return;
+    for (int64_t z = 1 + blockIdx.x; z < nz; z += gridDim.x) {
+        for (int i = threadIdx.x; i < kPairCap; i += blockDim.x) tab[i] = kEmpty;
+        __syncthreads();
+        auto link = [&](uint32_t a, uint32_t b) {
+            const uint32_t ra = parent[a], rb = parent[b];
+            if (ra == rb) return;
+            const unsigned long long key = ((unsigned long long)ra << 32) | rb;
+            uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 53) & (kPairCap - 1);
+            for (int pr = 0; pr < 16; ++pr) {
+                const unsigned long long old = atomicCAS(&tab[h], kEmpty, key);
+                if (old == kEmpty || old == key) return;
+                h = (h + 1) & (kPairCap - 1);
+            }
+            unite(parent, ra, rb);
+        };
+        for (int64_t y = threadIdx.x; y < ny; y += blockDim.x) {
+            const int64_t r = z * ny + y, rz = r - ny;
+            const uint32_t a0 = run_off[r], a1 = run_off[r + 1];
+            if (a0 == a1) continue;
+            for_touching<C26>(xs, xe, a0, a1, run_off[rz], run_off[rz + 1], link);
+            if (C26) {
+                if (y > 0) for_touching<C26>(xs, xe, a0, a1, run_off[rz - 1], run_off[rz], link);
+                if (y < ny - 1) for_touching<C26>(xs, xe, a0, a1, run_off[rz + 1], run_off[rz + 2], link);
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < kPairCap; i += blockDim.x) {
+            const unsigned long long key = tab[i];
+            if (key != kEmpty) unite(parent, (uint32_t)(key >> 32), (uint32_t)key);
+        }
+        __syncthreads();  // tab is reused by the next boundary
+    }
+}
+
 hipError_t launch_union(const LaunchCtx& lc, const Geom& g, const Layout& L, int conn) {
     timer_begin(lc.timer, ST_UNION, lc.stream);
-    dim3 grid(grid_for(g.nrows, kBlock, 16384));
-    if (conn == 26)
-        hipLaunchKernelGGL(k_union<true>, grid, dim3(kBlock), 0, lc.stream, (const uint32_t*)L.run_off,
-                           (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, L.parent, g.ny, g.nrows,
+    const dim3 gp(grid_for(g.nz, 1, lc.grid_stream)), gz(grid_for(g.nz - 1, 1, lc.grid_stream)), blk(kBlock);
+    if (conn == 26) {
+        hipLaunchKernelGGL(k_plane_label<true>, gp, blk, 0, lc.stream, (const uint32_t*)L.run_off,
+                           (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, L.parent, g.ny, g.nz,
                            (const DevState*)L.S);
-    else
-        hipLaunchKernelGGL(k_union<false>, grid, dim3(kBlock), 0, lc.stream, (const uint32_t*)L.run_off,
-                           (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, L.parent, g.ny, g.nrows,
+        if (g.nz > 1)
+            hipLaunchKernelGGL(k_zlink<true>, gz, blk, 0, lc.stream, (const uint32_t*)L.run_off,
+                               (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, L.parent, g.ny, g.nz,
+                               (const DevState*)L.S);
+    } else {
+        hipLaunchKernelGGL(k_plane_label<false>, gp, blk, 0, lc.stream, (const uint32_t*)L.run_off,
+                           (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, L.parent, g.ny, g.nz,
                            (const DevState*)L.S);
+        if (g.nz > 1)
+            hipLaunchKernelGGL(k_zlink<false>, gz, blk, 0, lc.stream, (const uint32_t*)L.run_off,
+                               (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, L.parent, g.ny, g.nz,
+                               (const DevState*)L.S);
+    }
     timer_end(lc.timer, ST_UNION, lc.stream);
     return hipGetLastError();
 }

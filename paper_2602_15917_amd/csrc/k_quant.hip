@@ -74,8 +74,8 @@ __device__ __forceinline__ bool block_exit(const DevState* S) {
 
 // ------------------------------------------------------------------ init
 
-__global__ __launch_bounds__(kBlock) void k_init(DevState* S, uint64_t* lookback, int64_t n_lookback) {
-    if (blockIdx.x == 0) {
+__global__ __launch_bounds__(kBlock) void k_init(DevState* S) {
+    {
         if (threadIdx.x == 0) {
             S->status = 0;
             S->trunc = 0;
@@ -100,21 +100,14 @@ __global__ __launch_bounds__(kBlock) void k_init(DevState* S, uint64_t* lookback
             S->n_kept = S->n_kept_voxels = 0ull;
             S->span_total = S->n_outliers = S->q_outliers = 0ull;
             S->qstatus = 0;
-            S->emit_ticket = 0u;
         }
         S->hist[threadIdx.x] = 0ull;
     }
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_lookback;
-         i += (int64_t)gridDim.x * blockDim.x)
-        lookback[i] = 0ull;
 }
 
-hipError_t launch_init(const LaunchCtx& lc, DevState* S, uint64_t* lookback, int64_t n_lookback) {
-    int64_t g = (n_lookback + kBlock - 1) / kBlock;
-    if (g < 1) g = 1;
-    if (g > 1024) g = 1024;
+hipError_t launch_init(const LaunchCtx& lc, DevState* S) {
     timer_begin(lc.timer, ST_INIT, lc.stream);
-    hipLaunchKernelGGL(k_init, dim3((unsigned)g), dim3(kBlock), 0, lc.stream, S, lookback, n_lookback);
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(kBlock), 0, lc.stream, S);
     timer_end(lc.timer, ST_INIT, lc.stream);
     return hipGetLastError();
 }
@@ -156,7 +149,7 @@ __global__ __launch_bounds__(kBlock) void k_range(const T* __restrict__ in, uint
 #pragma unroll
         for (int k = 0; k < kUnroll; ++k) {
             uint64_t vi = base + (uint64_t)k * blockDim.x + threadIdx.x;
-            raw[k] = vi < nvec ? vin[vi] : make_uint4(0, 0, 0, 0);
+            raw[k] = vi < nvec ? ld_stream(vin + vi) : make_uint4(0, 0, 0, 0);
         }
 #pragma unroll
         for (int k = 0; k < kUnroll; ++k) {
@@ -198,7 +191,7 @@ __global__ __launch_bounds__(kBlock) void k_range(const T* __restrict__ in, uint
 static int stream_grid(const LaunchCtx& lc, uint64_t nvec) {
     uint64_t need = (nvec + (uint64_t)kBlock * kUnroll - 1) / ((uint64_t)kBlock * kUnroll);
     if (need < 1) need = 1;
-    return (int)(need < (uint64_t)lc.grid_stream ? need : (uint64_t)lc.grid_stream);
+    return (int)(need < (uint64_t)lc.grid_read ? need : (uint64_t)lc.grid_read);
 }
 
 hipError_t launch_range(const LaunchCtx& lc, const void* in, roix_dtype dt, uint64_t N, DevState* S) {
@@ -246,6 +239,9 @@ __device__ void set_width(DevState* S) {
     S->width_bits = S->K <= 255 ? 8 : (S->K <= 65535 ? 16 : 32);
     S->esc = S->width_bits == 32 ? 0xFFFFFFFFu : ((1u << S->width_bits) - 1u);
     S->binscale = (float)(256.0 / (double)S->K);
+    const uint64_t M = ((1ull << 40) + (uint64_t)S->K - 1ull) / (uint64_t)S->K;
+    S->bin_mlo = (uint32_t)M;
+    S->bin_mhi = (uint32_t)(M >> 32);
 }
 
 __device__ __forceinline__ void qfail(DevState* S, int32_t st) {
@@ -391,12 +387,14 @@ hipError_t launch_quantize(const LaunchCtx& lc, const void* in, roix_dtype dt, u
 struct QH {
     float r;
     int32_t qmin, q_thr;
-    uint32_t K;
+    uint32_t K, mlo, mhi;
     float binscale;
 };
 
-template <typename T, bool CODES, bool FIXED>
-__device__ __forceinline__ uint8_t qh_one(T x, const QH& p, uint32_t* lh_copy, bool& bad) {
+// Code -> bin (and object flag for a fixed threshold) of one voxel; the
+// histogram count goes to this lane's LDS copy.  Returns the proxy byte.
+template <typename T, bool CODES, bool FIXED, bool FASTDIV>
+__device__ __forceinline__ uint32_t qh_one(T x, const QH& p, uint32_t* lh_copy, bool& bad) {
     int32_t q;
     if constexpr (CODES)
         q = (int32_t)x;
@@ -409,18 +407,83 @@ __device__ __forceinline__ uint8_t qh_one(T x, const QH& p, uint32_t* lh_copy, b
             u = 0u;
         }
     }
-    uint32_t b = bin_of(u, p.K, p.binscale);
+    const uint32_t b = FASTDIV ? bin_fast(u, p.mlo, p.mhi) : bin_slow(u, p.K, p.binscale);
     atomicAdd(&lh_copy[b], 1u);
     if constexpr (FIXED)
-        return (uint8_t)(q >= p.q_thr ? 1 : 0);
+        return q >= p.q_thr ? 1u : 0u;
     else
-        return (uint8_t)b;
+        return b;
 }
 
-template <typename T, bool CODES, bool FIXED>
-__global__ __launch_bounds__(kBlock) void k_quant_hist(const T* __restrict__ in, uint64_t N, uint64_t head,
-                                                       uint64_t nvec, DevState* S, uint8_t* __restrict__ proxy) {
+constexpr int kQhBatch = 4;  // 16-byte loads in flight per lane
+
+// One wave per row.  Vector path (row starts 16-byte aligned): lane l takes
+// vectors l, l + 64, ... of the row (one coalesced 1 KB load per step) and
+// stores their VN proxy bytes as one word at the same voxel offset of the
+// row's proxy.  Scalar path: lane l takes voxels l, l + 64, ...
+template <typename T, bool CODES, bool FIXED, bool FASTDIV, bool VEC>
+__device__ __forceinline__ void qh_rows(const T* __restrict__ in, int64_t nx, int64_t nrows, int64_t P,
+                                        const QH& p, uint32_t* mine, uint8_t* __restrict__ proxy, bool& bad) {
     constexpr int VN = VecN<T>::n;
+    const int lane = threadIdx.x % kWave;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+    for (int64_t row = wave; row < nrows; row += nwaves) {
+        const T* src = in + row * nx;
+        uint8_t* dst = proxy + row * P;
+        if constexpr (VEC) {
+            const int64_t nv = nx / VN;
+            const uint4* vs = reinterpret_cast<const uint4*>(src);
+            for (int64_t v0 = 0; v0 < nv; v0 += (int64_t)kWave * kQhBatch) {
+                uint4 raw[kQhBatch];
+#pragma unroll
+                for (int k = 0; k < kQhBatch; ++k) {
+                    const int64_t vi = v0 + k * kWave + lane;
+                    raw[k] = vi < nv ? ld_stream(vs + vi) : make_uint4(0, 0, 0, 0);
+                }
+#pragma unroll
+                for (int k = 0; k < kQhBatch; ++k) {
+                    const int64_t vi = v0 + k * kWave + lane;
+                    if (vi >= nv) continue;
+                    T v[VN];
+                    unpack16<T>(raw[k], v);
+                    if constexpr (VN == 4) {
+                        uint32_t pk = 0;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) pk |= qh_one<T, CODES, FIXED, FASTDIV>(v[j], p, mine, bad) << (8 * j);
+                        reinterpret_cast<uint32_t*>(dst)[vi] = pk;
+                    } else {
+                        uint64_t pk = 0;
+#pragma unroll
+                        for (int j = 0; j < 8; ++j)
+                            pk |= (uint64_t)qh_one<T, CODES, FIXED, FASTDIV>(v[j], p, mine, bad) << (8 * j);
+                        reinterpret_cast<uint64_t*>(dst)[vi] = pk;
+                    }
+                }
+            }
+        } else {
+            for (int64_t x0 = 0; x0 < nx; x0 += (int64_t)kWave * kQhBatch) {
+                T v[kQhBatch];
+#pragma unroll
+                for (int k = 0; k < kQhBatch; ++k) {
+                    const int64_t x = x0 + k * kWave + lane;
+                    v[k] = x < nx ? ld_stream(src + x) : (T)0;
+                }
+#pragma unroll
+                for (int k = 0; k < kQhBatch; ++k) {
+                    const int64_t x = x0 + k * kWave + lane;
+                    if (x < nx) dst[x] = (uint8_t)qh_one<T, CODES, FIXED, FASTDIV>(v[k], p, mine, bad);
+                }
+            }
+        }
+    }
+}
+
+constexpr int kQhBlock = 512;  // 8 waves share one set of LDS histogram copies
+
+template <typename T, bool CODES, bool FIXED, bool VEC>
+__global__ __launch_bounds__(kQhBlock) void k_quant_hist(const T* __restrict__ in, int64_t nx, int64_t nrows,
+                                                       int64_t P, DevState* S, uint8_t* __restrict__ proxy) {
     __shared__ uint32_t lh[kHistCopies * kHistStride];
     for (int i = threadIdx.x; i < kHistCopies * kHistStride; i += blockDim.x) lh[i] = 0u;
     if (block_exit(S)) return;  // contains a barrier, so lh is zeroed for every thread
@@ -429,51 +492,21 @@ __global__ __launch_bounds__(kBlock) void k_quant_hist(const T* __restrict__ in,
     p.qmin = S->qmin;
     p.q_thr = S->q_thr;
     p.K = (uint32_t)S->K;
+    p.mlo = S->bin_mlo;
+    p.mhi = S->bin_mhi;
     p.binscale = S->binscale;
     uint32_t* mine = lh + (threadIdx.x % kHistCopies) * kHistStride;
     bool bad = false;
-    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t nthreads = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t tail0 = head + nvec * VN;
-    for (uint64_t i = tid; i < head + (N - tail0); i += nthreads) {
-        uint64_t v = i < head ? i : tail0 + (i - head);
-        proxy[v] = qh_one<T, CODES, FIXED>(in[v], p, mine, bad);
-    }
-    const uint4* vin = reinterpret_cast<const uint4*>(in + head);
-    uint8_t* pout = proxy + head;  // VN-aligned by construction of the proxy base
-    const uint64_t per_iter = nthreads * kUnroll;
-    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x * kUnroll; base < nvec; base += per_iter) {
-        uint4 raw[kUnroll];
-#pragma unroll
-        for (int k = 0; k < kUnroll; ++k) {
-            uint64_t vi = base + (uint64_t)k * blockDim.x + threadIdx.x;
-            raw[k] = vi < nvec ? vin[vi] : make_uint4(0, 0, 0, 0);
-        }
-#pragma unroll
-        for (int k = 0; k < kUnroll; ++k) {
-            uint64_t vi = base + (uint64_t)k * blockDim.x + threadIdx.x;
-            if (vi >= nvec) continue;
-            T v[VN];
-            unpack16<T>(raw[k], v);
-            if constexpr (VN == 4) {
-                uint32_t pk = 0;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) pk |= (uint32_t)qh_one<T, CODES, FIXED>(v[j], p, mine, bad) << (8 * j);
-                *reinterpret_cast<uint32_t*>(pout + vi * 4) = pk;
-            } else {
-                uint64_t pk = 0;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) pk |= (uint64_t)qh_one<T, CODES, FIXED>(v[j], p, mine, bad) << (8 * j);
-                *reinterpret_cast<uint64_t*>(pout + vi * 8) = pk;
-            }
-        }
-    }
+    if (p.K <= 65536u)
+        qh_rows<T, CODES, FIXED, true, VEC>(in, nx, nrows, P, p, mine, proxy, bad);
+    else
+        qh_rows<T, CODES, FIXED, false, VEC>(in, nx, nrows, P, p, mine, proxy, bad);
     if constexpr (CODES) {
         if (bad) fail(S, ROIX_EINVAL);
     }
     __syncthreads();
-    {
-        const int b = threadIdx.x;  // kBlock == 256 bins
+    if (threadIdx.x < 256) {
+        const int b = threadIdx.x;
         uint32_t s = 0;
 #pragma unroll 8
         for (int c = 0; c < kHistCopies; ++c) s += lh[c * kHistStride + b];
@@ -482,48 +515,37 @@ __global__ __launch_bounds__(kBlock) void k_quant_hist(const T* __restrict__ in,
 }
 
 template <typename T, bool CODES>
-static void qh_dispatch(const LaunchCtx& lc, const void* in, uint64_t N, DevState* S, uint8_t* proxy_alloc,
+static void qh_dispatch(const LaunchCtx& lc, const void* in, const Geom& g, DevState* S, uint8_t* proxy,
                         bool fixed) {
-    uint64_t head, nvec;
-    split_vec<T>(in, N, &head, &nvec);
-    constexpr int VN = VecN<T>::n;
-    uint8_t* proxy = proxy_alloc + ((VN - head % VN) % VN);
-    dim3 g(stream_grid(lc, nvec));
-    if (fixed)
-        hipLaunchKernelGGL((k_quant_hist<T, CODES, true>), g, dim3(kBlock), 0, lc.stream, (const T*)in, N, head,
-                           nvec, S, proxy);
-    else
-        hipLaunchKernelGGL((k_quant_hist<T, CODES, false>), g, dim3(kBlock), 0, lc.stream, (const T*)in, N, head,
-                           nvec, S, proxy);
+    int64_t blocks = (g.nrows + kQhBlock / kWave - 1) / (kQhBlock / kWave);
+    const int64_t cap = (int64_t)lc.grid_stream / 2;  // 4 workgroups of 512 threads per CU
+    if (blocks > cap) blocks = cap;
+    if (blocks < 1) blocks = 1;
+    dim3 grid((unsigned)blocks), block(kQhBlock);
+    const bool vec = ((uintptr_t)in % 16 == 0) && ((g.nx * (int64_t)sizeof(T)) % 16 == 0);
+    const int64_t P = g.W * 64;
+#define QH_LAUNCH(F, V)                                                                                        \
+    hipLaunchKernelGGL((k_quant_hist<T, CODES, F, V>), grid, block, 0, lc.stream, (const T*)in, g.nx, g.nrows, P, \
+                       S, proxy)
+    if (fixed) {
+        if (vec) QH_LAUNCH(true, true); else QH_LAUNCH(true, false);
+    } else {
+        if (vec) QH_LAUNCH(false, true); else QH_LAUNCH(false, false);
+    }
+#undef QH_LAUNCH
 }
 
-hipError_t launch_quant_hist(const LaunchCtx& lc, const void* in, int src_kind, uint64_t N, DevState* S,
-                             uint8_t* proxy_alloc, bool fixed) {
+hipError_t launch_quant_hist(const LaunchCtx& lc, const void* in, int src_kind, const Geom& g, DevState* S,
+                             uint8_t* proxy, bool fixed) {
     timer_begin(lc.timer, ST_HIST, lc.stream);
     if (src_kind == 0)
-        qh_dispatch<float, false>(lc, in, N, S, proxy_alloc, fixed);
+        qh_dispatch<float, false>(lc, in, g, S, proxy, fixed);
     else if (src_kind == 1)
-        qh_dispatch<uint16_t, false>(lc, in, N, S, proxy_alloc, fixed);
+        qh_dispatch<uint16_t, false>(lc, in, g, S, proxy, fixed);
     else
-        qh_dispatch<int32_t, true>(lc, in, N, S, proxy_alloc, fixed);
+        qh_dispatch<int32_t, true>(lc, in, g, S, proxy, fixed);
     timer_end(lc.timer, ST_HIST, lc.stream);
     return hipGetLastError();
-}
-
-uint8_t* proxy_base(uint8_t* proxy_alloc, const void* in, int src_kind, uint64_t N) {
-    uint64_t head, nvec;
-    int VN;
-    if (src_kind == 1) {
-        split_vec<uint16_t>(in, N, &head, &nvec);
-        VN = 8;
-    } else if (src_kind == 0) {
-        split_vec<float>(in, N, &head, &nvec);
-        VN = 4;
-    } else {
-        split_vec<int32_t>(in, N, &head, &nvec);
-        VN = 4;
-    }
-    return proxy_alloc + ((VN - head % VN) % VN);
 }
 
 // ------------------------------------------------------------------ Otsu

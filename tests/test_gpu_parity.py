@@ -68,6 +68,15 @@ def test_noise_many_components(env, seed, conn):
     run_case(env, f"noise-otsu seed={seed}", vol, "abs", 1e-4, c)
 
 
+@pytest.mark.parametrize("conn", [6, 26])
+def test_dense_planes_fallback(env, conn):
+    # z-planes with more runs than the per-plane LDS labelling holds, and more distinct
+    # plane-root pairs per boundary than the pair table holds: the global fallbacks
+    vol = synth.normal((4, 300, 301), 6000 + conn, 0.5, 0.1)
+    for keep, ms in (("min_size", 1), ("largest", 1)):
+        run_case(env, f"dense planes conn={conn}", vol, "abs", 1e-3, synth.Criterion("fixed", 0.5, conn, keep, ms))
+
+
 def test_uint16_rings_small(env):
     w = synth.config2(nxy=256, nz=12)
     run_case(env, "rings u16 small", w.volume, w.eb_mode, w.eb_value, w.criterion)
