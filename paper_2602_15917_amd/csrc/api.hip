@@ -107,6 +107,8 @@ static size_t fixed_bytes(const Geom& g) {
     b += 2 * align256((size_t)g.nrows * 4);               // row_xs, row_xe
     b += align256((size_t)g.nrows * 8);                   // row_packed
     b += align256((size_t)g.nrows * 8);                   // row_outl
+    b += 2 * align256((size_t)g.nrows * 4);               // nz_rows, out_list
+    b += align256((size_t)(g.N / kEmitChunk + 2) * 4);    // chunk_row
     b += align256((size_t)(kScanBlocks + 1) * 8);         // scan tmp
     b += 5 * 256;                                         // run-array alignment slack
     return b;
@@ -130,6 +132,9 @@ static bool carve(roix_ctx* c, const Geom& g, Layout* L) {
     L->row_xe = (uint32_t*)take((size_t)g.nrows * 4);
     L->row_packed = (uint64_t*)take((size_t)g.nrows * 8);
     L->row_outl = (uint64_t*)take((size_t)g.nrows * 8);
+    L->nz_rows = (uint32_t*)take((size_t)g.nrows * 4);
+    L->out_list = (uint32_t*)take((size_t)g.nrows * 4);
+    L->chunk_row = (uint32_t*)take((size_t)(g.N / kEmitChunk + 2) * 4);
     L->scan_tmp = (uint64_t*)take((size_t)(kScanBlocks + 1) * 8);
     const size_t used = (size_t)(p - (uint8_t*)c->arena) + 5 * 256;
     uint64_t cap = (c->arena_bytes - used) / kRunBytes;

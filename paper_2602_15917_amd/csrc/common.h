@@ -15,6 +15,10 @@ constexpr int kHistCopies = 32;      // LDS-privatised histogram copies (one per
 constexpr int kHistStride = 257;     // copy stride: lane c + bin b lands in bank (c + b) mod 32
 constexpr int kScanBlocks = 1024;    // fixed block count of the device-sized scans
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr int kEmitSlice = 256;  // codes per emit slice: 4 consecutive codes per lane
+constexpr int kEmitSlices = 8;   // slices per emit step (16-byte loads in flight per lane)
+constexpr int kEmitSteps = 2;
+constexpr uint64_t kEmitChunk = (uint64_t)kEmitSlice * kEmitSlices * kEmitSteps;  // codes per emit work item
 
 // Everything the kernels of one call share, reset by k_init at the start of
 // the call (no memset: the sequence can be captured into a graph).
@@ -46,6 +50,7 @@ struct DevState {
     // extraction
     unsigned long long span_total;  // (rows with a span) << 40 | (codes)
     unsigned long long n_outliers, q_outliers;
+    uint32_t n_outl_rows, pad2;
 };
 
 // Per-call view of the scratch arena.
@@ -64,6 +69,9 @@ struct Layout {
     uint32_t* row_xe;       // nrows
     uint64_t* row_packed;   // nrows (has_span << 40 | span length), scanned in place
     uint64_t* row_outl;     // nrows: outliers per row, then their exclusive scan
+    uint32_t* nz_rows;      // nrows: row of the i-th span
+    uint32_t* chunk_row;    // N / kEmitChunk + 2: span holding the first code of each emit chunk
+    uint32_t* out_list;     // nrows: rows whose span has outliers
     uint64_t* scan_tmp;     // kScanBlocks + 1
     uint64_t run_cap;
 };

@@ -13,7 +13,6 @@
 namespace roix {
 
 constexpr uint64_t kLenMask = (1ull << 40) - 1ull;
-constexpr int kEmitUnroll = 16;
 
 __device__ __forceinline__ bool thread_exit_e(const DevState* S) {
     return __hip_atomic_load(&S->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
@@ -122,113 +121,334 @@ struct CodeT<4> {
     using type = uint32_t;
 };
 
-// One wave per row: stream the span once (up to 64 * kEmitUnroll voxels in
-// flight per wave), store the codes at the row's code offset and count the
-// row's outliers.  B = bytes per code.
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t lane) {
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, lane);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Index of the flat code space, one thread per row: nz_rows[ridx] = row of
+// the ridx-th span, chunk_row[q] = ridx of the span holding code q * chunk.
+// Also clears the per-row outlier counters.
+__global__ __launch_bounds__(kBlock) void k_emit_index(Layout L, int64_t nrows) {
+    if (thread_exit_e(L.S)) return;
+    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += nthreads) {
+        L.row_outl[r] = 0ull;
+        const uint32_t xs = L.row_xs[r], xe = L.row_xe[r];
+        if (xe <= xs) continue;
+        const uint64_t packed = L.row_packed[r];
+        const uint32_t ridx = (uint32_t)(packed >> 40);
+        const uint64_t code0 = packed & kLenMask, code1 = code0 + (xe - xs);
+        L.nz_rows[ridx] = (uint32_t)r;
+        for (uint64_t q = (code0 + kEmitChunk - 1) / kEmitChunk; q * kEmitChunk < code1; ++q) L.chunk_row[q] = ridx;
+    }
+}
+
+// Codes of one chunk [c0, c1) whose spans are rows j0 .. j0 + nr - 1 of the
+// span list, nr <= 64: lane l holds span j0 + l (first code, voxel offset).
+// Each 64-code slice is consecutive codes; the uniform cursor jr walks the
+// span starts falling inside the slice, so every lane knows its voxel with
+// a few scalar reads, and all loads of a step are issued before any use.
+// Four consecutive input values starting at voxel v.  float: one 16-byte
+// load (the ISA needs only 4-byte alignment for multi-dword loads).  uint16:
+// one 12-byte load from the 4-byte-aligned voxel at or before v.
+__device__ __forceinline__ void load_quad(const float* in, uint64_t v, float (&x)[4]) {
+    const v4u32_t q = __builtin_nontemporal_load(reinterpret_cast<const v4u32_t*>(in + v));
+    x[0] = __uint_as_float(q.x);
+    x[1] = __uint_as_float(q.y);
+    x[2] = __uint_as_float(q.z);
+    x[3] = __uint_as_float(q.w);
+}
+typedef unsigned int v3u32_t __attribute__((ext_vector_type(3)));
+__device__ __forceinline__ void load_quad(const uint16_t* in, uint64_t v, float (&x)[4]) {
+    const uint64_t v0 = v & ~1ull;
+    const v3u32_t q = __builtin_nontemporal_load(reinterpret_cast<const v3u32_t*>(in + v0));
+    const uint32_t sh = (uint32_t)(v - v0) * 16u;
+    const uint64_t lo = ((uint64_t)q.y << 32) | q.x, hi = ((uint64_t)q.z << 32) | q.y;
+    const uint64_t a = sh ? (lo >> 16) | ((uint64_t)q.z << 48) : lo;  // values v .. v+3
+    (void)hi;
+    x[0] = (float)(uint32_t)(a & 0xFFFFu);
+    x[1] = (float)(uint32_t)((a >> 16) & 0xFFFFu);
+    x[2] = (float)(uint32_t)((a >> 32) & 0xFFFFu);
+    x[3] = (float)(uint32_t)(a >> 48);
+}
+
+template <int B>
+__device__ __forceinline__ void store_quad(uint8_t* stream, uint64_t c, const uint32_t (&u)[4]) {
+    if constexpr (B == 1) {
+        *reinterpret_cast<uint32_t*>(stream + c) = u[0] | (u[1] << 8) | (u[2] << 16) | (u[3] << 24);
+    } else if constexpr (B == 2) {
+        *reinterpret_cast<uint2*>(stream + 2 * c) = make_uint2(u[0] | (u[1] << 16), u[2] | (u[3] << 16));
+    } else {
+        *reinterpret_cast<uint4*>(stream + 4 * c) = make_uint4(u[0], u[1], u[2], u[3]);
+    }
+}
+
+// Codes of one chunk [c0, c1) whose spans are entries j0 .. j0 + nr - 1 of
+// the span list, nr <= 64: lane l holds span j0 + l (first code, voxel
+// offset).  A step is kEmitSlices slices of 256 consecutive codes, 4 per
+// lane.  One uniform walk over the spans starting inside the step gives each
+// lane the voxel of the first code of each of its quads, and flags quads
+// that a span start splits.  An unsplit quad is one 16-byte load; all loads
+// of a step are issued before any use; codes are stored 4 at a time
+// (aligned: chunks start at multiples of kEmitChunk codes).
 template <typename T, int B>
-__device__ __forceinline__ void emit_codes_rows(const T* __restrict__ in, int64_t nx, int64_t nrows, const Layout& L,
-                                                const EmitOut& o, bool& trunc) {
+__device__ __forceinline__ void emit_chunk_fast(const T* __restrict__ in, int64_t nx, const Layout& L,
+                                                const EmitOut& o, uint64_t c0, uint64_t c1, uint32_t j0, uint32_t nr,
+                                                bool& trunc) {
     using C = typename CodeT<B>::type;
     const DevState* S = L.S;
     const int lane = threadIdx.x % kWave;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
     const float r = S->r, w = S->w, eb32 = S->eb32;
     const int32_t qmin = S->qmin;
     const uint32_t esc = S->esc;
     C* codes = reinterpret_cast<C*>(o.stream);
-    for (int64_t row = wave; row < nrows; row += nwaves) {
-        const uint32_t xs = L.row_xs[row], xe = L.row_xe[row];
-        uint32_t cnt = 0;
-        if (xe > xs) {
-            const uint64_t code0 = L.row_packed[row] & kLenMask;  // exclusive scan value
-            const T* src = in + (uint64_t)row * (uint64_t)nx + xs;
-            const uint32_t len = xe - xs;
-            const bool fits = (code0 + len) * (uint64_t)B <= o.stream_cap;
-            for (uint32_t j0 = 0; j0 < len; j0 += kWave * kEmitUnroll) {
-                float xv[kEmitUnroll];
+    const bool fits = c1 * (uint64_t)B <= o.stream_cap;
+    uint32_t rid = 0;
+    uint64_t code0 = ~0ull, off = 0;
+    if ((uint32_t)lane < nr) {
+        rid = L.nz_rows[j0 + lane];
+        code0 = L.row_packed[rid] & kLenMask;
+        off = (uint64_t)rid * (uint64_t)nx + L.row_xs[rid] - code0;  // voxel = code + off
+    }
+    constexpr uint32_t kStep = (uint32_t)kEmitSlice * kEmitSlices;
+    uint32_t jr = 0;  // span holding the step's first code (uniform)
+    for (int s = 0; s < kEmitSteps; ++s) {
+        const uint64_t tb = c0 + (uint64_t)s * kStep;
+        const uint64_t t0 = tb + 4 * lane;  // first code of this lane's quad in slice 0
+        const uint32_t jr_step = jr;
+        uint64_t ok[kEmitSlices];
+        uint32_t split = 0;
+        {
+            const uint64_t o0 = readlane64(off, jr);
 #pragma unroll
-                for (int k = 0; k < kEmitUnroll; ++k) {
-                    const uint32_t j = j0 + k * kWave + lane;
-                    xv[k] = j < len ? (float)ld_stream(src + j) : 0.0f;
+            for (int k = 0; k < kEmitSlices; ++k) ok[k] = o0;
+        }
+        for (uint32_t jj = jr + 1; jj < nr; ++jj) {
+            const uint64_t nc0 = readlane64(code0, jj);
+            if (nc0 >= tb + kStep) break;
+            const uint64_t on = readlane64(off, jj);
+#pragma unroll
+            for (int k = 0; k < kEmitSlices; ++k) {
+                const uint64_t t = t0 + (uint64_t)k * kEmitSlice;
+                if (t >= nc0)
+                    ok[k] = on;
+                else if (t + 3 >= nc0)
+                    split |= 1u << k;
+            }
+            jr = jj;
+        }
+        float xv[kEmitSlices][4];
+#pragma unroll
+        for (int k = 0; k < kEmitSlices; ++k) {
+            const uint64_t t = t0 + (uint64_t)k * kEmitSlice;
+            if (!((split >> k) & 1u) && t + 3 < c1) {
+                load_quad(in, t + ok[k], xv[k]);
+            } else {
+                // a span starts inside this quad (or the chunk ends in it):
+                // per-code voxels from the same walk (readlane ignores exec)
+                uint64_t vj[4];
+                const uint64_t o0 = readlane64(off, jr_step);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) vj[j] = t + j + o0;
+                for (uint32_t jj = jr_step + 1; jj < nr; ++jj) {
+                    const uint64_t nc0 = readlane64(code0, jj);
+                    if (nc0 >= tb + kStep) break;
+                    const uint64_t on = readlane64(off, jj);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (t + j >= nc0) vj[j] = t + j + on;
                 }
 #pragma unroll
-                for (int k = 0; k < kEmitUnroll; ++k) {
-                    const uint32_t j = j0 + k * kWave + lane;
-                    const float x = xv[k];
-                    const int32_t q = qcode(x, r);
-                    const bool isout = j < len && outlier(x, q, w, eb32);
-                    const uint32_t u = isout ? esc : (uint32_t)(q - qmin);
-                    if (j < len) {
-                        const uint64_t idx = code0 + j;
-                        if (fits || (idx + 1) * (uint64_t)B <= o.stream_cap)
-                            codes[idx] = (C)u;
-                        else
-                            trunc = true;
-                    }
-                    cnt += (uint32_t)__popcll(__ballot(isout));
+                for (int j = 0; j < 4; ++j) xv[k][j] = t + j < c1 ? (float)ld_stream(in + vj[j]) : 0.0f;
+            }
+        }
+        uint32_t anyout = 0;
+        uint32_t outm[kEmitSlices];
+#pragma unroll
+        for (int k = 0; k < kEmitSlices; ++k) {
+            const uint64_t t = t0 + (uint64_t)k * kEmitSlice;
+            uint32_t u[4];
+            uint32_t om = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float x = xv[k][j];
+                const int32_t q = qcode(x, r);
+                const bool ob = t + j < c1 && outlier(x, q, w, eb32);
+                om |= ob ? (1u << j) : 0u;
+                u[j] = ob ? esc : (uint32_t)(q - qmin);
+            }
+            outm[k] = om;
+            anyout |= om;
+            if (t + 3 < c1 && (fits || (t + 4) * (uint64_t)B <= o.stream_cap)) {
+                store_quad<B>(o.stream, t, u);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (t + j >= c1) continue;
+                    if ((t + j + 1) * (uint64_t)B <= o.stream_cap)
+                        codes[t + j] = (C)u[j];
+                    else
+                        trunc = true;
                 }
             }
         }
-        if (lane == 0) L.row_outl[row] = cnt;
+        if (__ballot(anyout != 0)) {  // rare: count the step's outliers per span
+            for (uint32_t jj = jr_step; jj < nr; ++jj) {
+                const uint64_t cj = readlane64(code0, jj);
+                if (cj >= tb + kStep) break;
+                const uint64_t cn = jj + 1 < nr ? readlane64(code0, jj + 1) : ~0ull;
+                uint32_t n = 0;
+                for (int k = 0; k < kEmitSlices; ++k) {
+                    const uint64_t t = t0 + (uint64_t)k * kEmitSlice;
+                    for (int j = 0; j < 4; ++j)
+                        n += (uint32_t)__popcll(__ballot(((outm[k] >> j) & 1u) && t + j >= cj && t + j < cn));
+                }
+                if (n && lane == 0)
+                    atomicAdd((unsigned long long*)&L.row_outl[__builtin_amdgcn_readlane(rid, jj)],
+                              (unsigned long long)n);
+            }
+        }
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_emit_codes(const T* __restrict__ in, int64_t nx, int64_t nrows, Layout L,
-                                                       EmitOut o) {
+// Chunks touching more than 64 spans (short spans): one span at a time.
+template <typename T, int B>
+__device__ __forceinline__ void emit_chunk_slow(const T* __restrict__ in, int64_t nx, const Layout& L,
+                                                const EmitOut& o, uint64_t c0, uint64_t c1, uint32_t j0, uint32_t j1,
+                                                bool& trunc) {
+    using C = typename CodeT<B>::type;
+    const DevState* S = L.S;
+    const int lane = threadIdx.x % kWave;
+    const float r = S->r, w = S->w, eb32 = S->eb32;
+    const int32_t qmin = S->qmin;
+    const uint32_t esc = S->esc;
+    C* codes = reinterpret_cast<C*>(o.stream);
+    for (uint32_t j = j0; j <= j1; ++j) {
+        const uint32_t rid = L.nz_rows[j];
+        const uint64_t code0 = L.row_packed[rid] & kLenMask;
+        const uint64_t code1 = code0 + (L.row_xe[rid] - L.row_xs[rid]);
+        const uint64_t off = (uint64_t)rid * (uint64_t)nx + L.row_xs[rid] - code0;
+        const uint64_t lo = code0 > c0 ? code0 : c0, hi = code1 < c1 ? code1 : c1;
+        uint32_t cnt = 0;
+        for (uint64_t cb = lo; cb < hi; cb += kWave) {
+            const uint64_t c = cb + lane;
+            bool isout = false;
+            if (c < hi) {
+                const float x = (float)ld_stream(in + (c + off));
+                const int32_t q = qcode(x, r);
+                isout = outlier(x, q, w, eb32);
+                const uint32_t u = isout ? esc : (uint32_t)(q - qmin);
+                if ((c + 1) * (uint64_t)B <= o.stream_cap)
+                    codes[c] = (C)u;
+                else
+                    trunc = true;
+            }
+            cnt += (uint32_t)__popcll(__ballot(isout));
+        }
+        if (cnt && lane == 0) atomicAdd((unsigned long long*)&L.row_outl[rid], (unsigned long long)cnt);
+    }
+}
+
+template <typename T, int B>
+__device__ __forceinline__ void emit_chunks(const T* __restrict__ in, int64_t nx, const Layout& L, const EmitOut& o,
+                                            bool& trunc) {
+    const DevState* S = L.S;
+    const uint64_t n_codes = S->span_total & kLenMask;
+    const uint32_t n_rows = (uint32_t)(S->span_total >> 40);
+    const uint64_t nchunks = (n_codes + kEmitChunk - 1) / kEmitChunk;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+    for (uint64_t q = (uint64_t)wave; q < nchunks; q += (uint64_t)nwaves) {
+        const uint64_t c0 = q * kEmitChunk;
+        const uint64_t c1 = c0 + kEmitChunk < n_codes ? c0 + kEmitChunk : n_codes;
+        const uint32_t j0 = L.chunk_row[q];
+        const uint32_t j1 = q + 1 < nchunks ? L.chunk_row[q + 1] : n_rows - 1;
+        if (j1 - j0 < (uint32_t)kWave)
+            emit_chunk_fast<T, B>(in, nx, L, o, c0, c1, j0, j1 - j0 + 1, trunc);
+        else
+            emit_chunk_slow<T, B>(in, nx, L, o, c0, c1, j0, j1, trunc);
+    }
+}
+
+// The codes of every span voxel, in row order, as one flat stream: each wave
+// takes whole kEmitChunk-code chunks, so loads and stores are contiguous and
+// no lane idles on a short row.  B = bytes per code (uniform branch).
+// The code width is device data, so one kernel per width is launched and
+// the two that do not match return at once (keeps each kernel's registers
+// to its own width).
+template <typename T, int B>
+__global__ __launch_bounds__(kBlock) void k_emit_codes(const T* __restrict__ in, int64_t nx, Layout L, EmitOut o) {
     DevState* S = L.S;
-    if (thread_exit_e(S)) return;  // no barrier below
+    if (thread_exit_e(S) || S->width_bits != 8 * B) return;  // no barrier below
     bool trunc = false;
-    const int B = S->width_bits / 8;  // uniform: one branch for the whole grid
-    if (B == 1)
-        emit_codes_rows<T, 1>(in, nx, nrows, L, o, trunc);
-    else if (B == 2)
-        emit_codes_rows<T, 2>(in, nx, nrows, L, o, trunc);
-    else
-        emit_codes_rows<T, 4>(in, nx, nrows, L, o, trunc);
+    emit_chunks<T, B>(in, nx, L, o, trunc);
     if (trunc) atomicOr(&S->trunc, 1);
 }
 
-// Pass 2 (after the scan of the outlier counts), one wave per row: the row
-// table entry, and the outlier values of rows that have any (their spans are
-// read once more).
+// After the scan of the per-row outlier counts, one thread per span: its row
+// table entry (coalesced), and the span is queued when it has outliers.
+__global__ __launch_bounds__(kBlock) void k_emit_rows(Layout L, int64_t ny, int64_t nrows, EmitOut o) {
+    DevState* S = L.S;
+    if (thread_exit_e(S)) return;
+    const uint32_t n_rows = (uint32_t)(S->span_total >> 40);
+    const unsigned long long total = S->n_outliers;
+    bool trunc = false;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t jb = blockIdx.x * blockDim.x; jb < n_rows; jb += stride) {
+        const uint32_t j = jb + threadIdx.x;
+        if (jb + (threadIdx.x & ~(uint32_t)(kWave - 1)) >= n_rows) break;  // whole wave past the end
+        const bool valid = j < n_rows;
+        const uint32_t rid = valid ? L.nz_rows[j] : 0u;
+        const uint64_t ooff = L.row_outl[rid];
+        const uint64_t oend = (int64_t)rid + 1 < nrows ? L.row_outl[rid + 1] : total;
+        if (!valid) {
+        } else if (j < o.rows_cap) {
+            roix_row e;
+            e.z = (uint32_t)(rid / ny);
+            e.y = (uint32_t)(rid - (int64_t)e.z * ny);
+            e.xs = L.row_xs[rid];
+            e.xe = L.row_xe[rid];
+            e.code_off = L.row_packed[rid] & kLenMask;
+            e.outlier_off = ooff;
+            o.rows[j] = e;
+        } else {
+            trunc = true;
+        }
+        // queue spans with outliers: one atomic per wave (a single counter
+        // hit once per span would serialise)
+        const bool has = valid && oend != ooff;
+        const uint64_t m = __ballot(has);
+        if (m) {
+            const int lane = threadIdx.x % kWave;
+            const int leader = __ffsll((unsigned long long)m) - 1;
+            uint32_t basei = 0;
+            if (lane == leader) basei = atomicAdd(&S->n_outl_rows, (uint32_t)__popcll(m));
+            basei = (uint32_t)__shfl((int)basei, leader);
+            if (has) L.out_list[basei + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = rid;
+        }
+    }
+    if (trunc) atomicOr(&S->trunc, 1);
+}
+
+// One wave per queued span: read it once more and store its outlier values
+// in order at the span's outlier offset.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_emit_rows(const T* __restrict__ in, int64_t nx, int64_t ny, int64_t nrows,
-                                                      Layout L, EmitOut o) {
+__global__ __launch_bounds__(kBlock) void k_emit_outliers(const T* __restrict__ in, int64_t nx, Layout L, EmitOut o) {
     DevState* S = L.S;
     if (thread_exit_e(S)) return;
     const int lane = threadIdx.x % kWave;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
     const float r = S->r, w = S->w, eb32 = S->eb32;
-    const unsigned long long total = S->n_outliers;
+    const uint32_t nl = S->n_outl_rows;
     bool trunc = false;
-    for (int64_t row = wave; row < nrows; row += nwaves) {
-        const uint32_t xs = L.row_xs[row], xe = L.row_xe[row];
-        if (xe <= xs) continue;
-        const uint64_t packed = L.row_packed[row];
-        const uint64_t ridx = packed >> 40, code0 = packed & kLenMask;
-        const uint64_t ooff = L.row_outl[row];
-        const uint64_t oend = row + 1 < nrows ? L.row_outl[row + 1] : total;
-        if (lane == 0) {
-            if (ridx < o.rows_cap) {
-                roix_row e;
-                e.z = (uint32_t)(row / ny);
-                e.y = (uint32_t)(row - (int64_t)e.z * ny);
-                e.xs = xs;
-                e.xe = xe;
-                e.code_off = code0;
-                e.outlier_off = ooff;
-                o.rows[ridx] = e;
-            } else {
-                trunc = true;
-            }
-        }
-        if (oend == ooff) continue;
-        const T* src = in + (uint64_t)row * (uint64_t)nx + xs;
-        const uint32_t len = xe - xs;
-        unsigned long long k = ooff;
+    for (int64_t i = wave; i < (int64_t)nl; i += nwaves) {
+        const uint32_t rid = L.out_list[i];
+        const uint32_t xs = L.row_xs[rid], len = L.row_xe[rid] - xs;
+        const T* src = in + (uint64_t)rid * (uint64_t)nx + xs;
+        unsigned long long k = L.row_outl[rid];
         constexpr int U = 8;
         for (uint32_t j0 = 0; j0 < len; j0 += kWave * U) {
             float xv[U];
@@ -266,21 +486,32 @@ hipError_t launch_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, cons
     o.stream_cap = out->d_stream ? (uint64_t)out->stream_cap_bytes : 0;
     o.outl = out->d_outliers;
     o.outl_cap = out->d_outliers ? (uint64_t)out->outliers_cap : 0;
-    const dim3 grid(grid_rows(g.nrows, kBlock / kWave, lc.grid_stream)), block(kBlock);
+    const dim3 block(kBlock);
+    const dim3 grid_rows_t(grid_rows(g.nrows, kBlock, lc.grid_stream));
+    const dim3 grid_waves(lc.grid_stream);
     timer_begin(lc.timer, ST_EMIT, lc.stream);
-    if (dt == ROIX_F32)
-        hipLaunchKernelGGL(k_emit_codes<float>, grid, block, 0, lc.stream, (const float*)in, g.nx, g.nrows, L, o);
-    else
-        hipLaunchKernelGGL(k_emit_codes<uint16_t>, grid, block, 0, lc.stream, (const uint16_t*)in, g.nx, g.nrows, L, o);
+    hipLaunchKernelGGL(k_emit_index, grid_rows_t, block, 0, lc.stream, L, g.nrows);
+    if (dt == ROIX_F32) {
+        hipLaunchKernelGGL((k_emit_codes<float, 2>), grid_waves, block, 0, lc.stream, (const float*)in, g.nx, L, o);
+        hipLaunchKernelGGL((k_emit_codes<float, 1>), grid_waves, block, 0, lc.stream, (const float*)in, g.nx, L, o);
+        hipLaunchKernelGGL((k_emit_codes<float, 4>), grid_waves, block, 0, lc.stream, (const float*)in, g.nx, L, o);
+    } else {
+        hipLaunchKernelGGL((k_emit_codes<uint16_t, 2>), grid_waves, block, 0, lc.stream, (const uint16_t*)in, g.nx, L,
+                           o);
+        hipLaunchKernelGGL((k_emit_codes<uint16_t, 1>), grid_waves, block, 0, lc.stream, (const uint16_t*)in, g.nx, L,
+                           o);
+        hipLaunchKernelGGL((k_emit_codes<uint16_t, 4>), grid_waves, block, 0, lc.stream, (const uint16_t*)in, g.nx, L,
+                           o);
+    }
     timer_end(lc.timer, ST_EMIT, lc.stream);
     hipError_t e = launch_scan_u64(lc, L.row_outl, L.row_outl, g.nrows, &L.S->n_outliers, L.scan_tmp);
     if (e != hipSuccess) return e;
     timer_begin(lc.timer, ST_EMIT_ROWS, lc.stream);
+    hipLaunchKernelGGL(k_emit_rows, grid_rows_t, block, 0, lc.stream, L, g.ny, g.nrows, o);
     if (dt == ROIX_F32)
-        hipLaunchKernelGGL(k_emit_rows<float>, grid, block, 0, lc.stream, (const float*)in, g.nx, g.ny, g.nrows, L, o);
+        hipLaunchKernelGGL(k_emit_outliers<float>, grid_waves, block, 0, lc.stream, (const float*)in, g.nx, L, o);
     else
-        hipLaunchKernelGGL(k_emit_rows<uint16_t>, grid, block, 0, lc.stream, (const uint16_t*)in, g.nx, g.ny, g.nrows,
-                           L, o);
+        hipLaunchKernelGGL(k_emit_outliers<uint16_t>, grid_waves, block, 0, lc.stream, (const uint16_t*)in, g.nx, L, o);
     timer_end(lc.timer, ST_EMIT_ROWS, lc.stream);
     return hipGetLastError();
 }
