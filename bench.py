@@ -27,6 +27,81 @@ def log(msg):
     sys.stderr.flush()
 
 
+# source file of each stage's kernels: a traffic figure measured by the
+# counters is only reported while that file is unchanged
+STAGE_SOURCE = {"range": "k_quant.hip", "quant_hist": "k_quant.hip", "mask_runs": "k_label.hip",
+                "emit": "k_extract.hip"}
+STAGE_KERNEL = {"range": "k_range<float>", "quant_hist": "k_quant_hist<float, false, false, true>",
+                "mask_runs": "k_mask_runs", "emit": "k_emit_codes<float, 2>"}
+CALIB_BYTES = 1 << 30
+
+
+def source_sha(stage):
+    import hashlib
+    f = os.path.join(ROOT, "paper_2602_15917_amd", "csrc", STAGE_SOURCE[stage])
+    return hashlib.sha256(open(f, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(stage):
+    """(fetch, write) HBM bytes per launch from the committed counter summary,
+    or None when there is none or the kernel source has changed since."""
+    f = os.path.join(ROOT, "profiles", "traffic_config1_1024cubed_f32.txt")
+    if not os.path.exists(f):
+        return None
+    vals = {}
+    for line in open(f):
+        parts = line.split()
+        if len(parts) >= 5 and parts[0] == "stage" and parts[1] == stage:
+            vals = {"fetch": float(parts[2]), "write": float(parts[3]), "sha": parts[4]}
+    if not vals or vals["sha"] != source_sha(stage):
+        return None
+    return vals["fetch"], vals["write"]
+
+
+def pmc_summary(fetch_csv, write_csv, kt_csv):
+    """Summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per
+    dispatch) into per-launch HBM bytes, scaled by what the same counters
+    read for a device copy of CALIB_BYTES (the bench's --calibrate-copy)."""
+    import csv
+    import re
+
+    def per_kernel(fn, counter):
+        acc = {}
+        for r in csv.DictReader(open(fn)):
+            if r["Counter_Name"] != counter:
+                continue
+            k = re.sub(r"\(.*", "", r["Kernel_Name"]).replace("void ", "").replace("roix::", "")
+            acc.setdefault(k, []).append(float(r["Counter_Value"]) * 1024.0)
+        return acc
+
+    fetch, write = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    calib = [k for k in fetch if "copy" in k.lower() or "elementwise" in k.lower()]
+    cf = max((max(fetch[k]) for k in calib), default=0.0)
+    cw = max((max(write.get(k, [0.0])) for k in calib), default=0.0)
+    sf = CALIB_BYTES / cf if cf else float("nan")
+    sw = CALIB_BYTES / cw if cw else float("nan")
+    dur = {}
+    if kt_csv:
+        for r in csv.DictReader(open(kt_csv)):
+            k = re.sub(r"\(.*", "", r["Name"]).replace("void ", "").replace("roix::", "")
+            dur[k] = float(r["AverageNs"])
+    print(f"calibration: device copy of {CALIB_BYTES} B reads FETCH_SIZE {cf:.0f} B, WRITE_SIZE {cw:.0f} B "
+          f"-> scale fetch x{sf:.4f}, write x{sw:.4f}")
+    print("# kernel  fetch_bytes_per_launch  write_bytes_per_launch  avg_ns (scaled counters)")
+    for k in sorted(fetch, key=lambda k: -max(fetch[k])):
+        f = sum(fetch[k]) / len(fetch[k]) * sf
+        wv = write.get(k, [0.0])
+        wr = sum(wv) / len(wv) * sw
+        if f + wr < 1e6:
+            continue
+        print(f"kernel {k.replace(' ', '')} {f:.4g} {wr:.4g} {dur.get(k, float('nan')):.0f}")
+    for st, kn in STAGE_KERNEL.items():
+        if kn in fetch:
+            f = sum(fetch[kn]) / len(fetch[kn]) * sf
+            wv = write.get(kn, [0.0])
+            print(f"stage {st} {f:.6g} {sum(wv) / len(wv) * sw:.6g} {source_sha(st)}")
+
+
 def algorithmic_bytes(stage, N, s, n_codes, code_bytes, n_rows, nrows_all, W):
     """Bytes a launch of `stage` must move at minimum (per call of the path)."""
     if stage == "range":
@@ -48,7 +123,14 @@ def main():
     ap.add_argument("--n", type=int, default=1024, help="volume side (1024 = the benchmark workload)")
     ap.add_argument("--cpu-planes", type=int, default=256, help="z-planes of the CPU-oracle sample (0 = skip)")
     ap.add_argument("--no-stage-timing", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain device copy of 1 GiB (the counter calibration for traffic)")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL_STATS_CSV"),
+                    help="summarise rocprofv3 counter runs of this script and exit")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the reduction path has no multi-GPU "
               f"form in this build", file=sys.stderr)
@@ -127,14 +209,24 @@ def main():
         avg_ms = per[dom][0]
         byts = algorithmic_bytes(dom, N, s, e.n_codes, code_bytes, e.n_rows, nrows_all, W)
         ach = byts / (avg_ms * 1e-3) / 1e9
+        tr = measured_traffic(dom)
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "alg_bytes_per_launch": int(byts),
-                "avg_launch_ms": round(avg_ms, 4)}
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": (round(tr[0] + tr[1]) if tr else None),
+                "traffic_fetch_write": ([round(tr[0]), round(tr[1])] if tr else None),
+                "alg_bytes_per_launch": int(byts), "avg_launch_ms": round(avg_ms, 4)}
     # whole-path byte model: two input reads, 1-byte proxy written and read,
     # span voxels re-read, codes written, row table written
     b_alg = N * (2 * s + 2) + e.n_codes * (s + code_bytes) + 32 * e.n_rows
     path = {"alg_bytes": int(b_alg), "achieved": round(b_alg / (ms * 1e-3) / 1e9, 1),
             "frac": round(b_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    if args.calibrate_copy:
+        a = torch.empty(CALIB_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        bcp = torch.empty_like(a)
+        for _ in range(3):
+            bcp.copy_(a)
+        torch.cuda.synchronize()
+        del a, bcp
 
     cpu = None
     if args.cpu_planes > 0:

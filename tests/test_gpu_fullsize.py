@@ -1,0 +1,68 @@
+"""Full-size parity: the benchmark workload (1024^3 float32) and the 8 GB
+uint16 stack (2048 x 2048 x 1024) through the fused C-ABI call, in the launch
+configuration the benchmark times, compared bit-exactly with the CPU oracle
+through SHA-256 digests of every output section.  The digests are written by
+tests/golden/make_digests.py, which runs only the oracle."""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from roixtest import criterion, log
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "digests.json")
+
+
+def sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+@pytest.mark.parametrize("name", ["config1", "config2"])
+def test_fullsize_digests(name):
+    import torch
+
+    from paper_2602_15917_amd import roix
+    gold = json.load(open(GOLDEN)).get(name)
+    if gold is None:
+        pytest.skip(f"no oracle digest for {name}")
+    log(f"[case] full-size {name}: generating")
+    w = getattr(synth, name)()
+    assert w.sha256() == gold["input_sha256"], "generator output differs from the digested input"
+    crit = criterion(roix, w.criterion)
+    x = torch.from_numpy(w.volume).to("cuda:0")
+    del w.volume
+    dims = roix.dims_of(x)
+    dt = roix.F32 if x.dtype == torch.float32 else roix.U16
+    ctx = roix.Context(0, roix.scratch_bytes(dims, dt, crit))
+    b = roix.bounds(dims, dt, crit)
+    out = roix.Outputs("cuda:0", b["rows"], b["stream_bytes"], int(gold["extract"]["n_outliers"]) + 1024, 1 << 20)
+    log(f"[case] full-size {name}: fused")
+    ctx.fused(x, w.eb_mode, w.eb_value, crit, out)
+    torch.cuda.synchronize()
+    g = out.collect()
+    ctx.close()
+    q, s, e = g["qinfo"], g["sinfo"], g["einfo"]
+    assert (q.status, s.status, e.status) == (0, 0, 0)
+    gq = gold["quant"]
+    for f in ("qmin", "qmax", "K", "width_bits", "esc"):
+        assert getattr(q, f) == gq[f], f
+    for f in ("xmin", "xmax", "eb32", "w", "r"):
+        assert np.float32(getattr(q, f)) == np.float32(gq[f]), f
+    gs = gold["seg"]
+    for f in ("otsu_bin", "q_thr", "flags", "n_mask", "n_components", "n_kept", "n_kept_voxels"):
+        assert getattr(s, f) == gs[f], f
+    assert list(s.bbox) == gs["bbox"]
+    assert sha(np.frombuffer(bytes(s.hist), np.uint64)) == gs["hist_sha256"]
+    ge = gold["extract"]
+    for f in ("n_rows", "n_codes", "n_outliers", "stream_bytes"):
+        assert getattr(e, f) == ge[f], f
+    hs = gold["sha256"]
+    assert sha(g["rows"]) == hs["rows"]
+    assert sha(g["stream"]) == hs["stream"]
+    assert sha(g["outliers"]) == hs["outliers"]
+    assert sha(g["comps"]) == hs["comps"]
