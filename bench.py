@@ -115,6 +115,79 @@ def algorithmic_bytes(stage, N, s, n_codes, code_bytes, n_rows, nrows_all, W):
     return None
 
 
+def bench_batched(args):
+    """64 float32 volumes, sides U{64..512} per axis, 1-8 ellipsoids, eb from
+    {1e-3, 1e-4, 1e-5}: one batched graph launch against the same volumes
+    run one plain call after another."""
+    import torch
+
+    import synth
+    from paper_2602_15917_amd import roix
+
+    dev = "cuda:0"
+    t0 = time.time()
+    vols = [synth.batch_volume(j) for j in range(args.batch_volumes)]
+    total = sum(w.volume.nbytes for w in vols)
+    log(f"generated {len(vols)} volumes, {total / 1e9:.2f} GB, in {time.time() - t0:.1f}s")
+    items = []
+    need = 0
+    for w in vols:
+        crit = roix.Criterion(w.criterion.thr, 0.0, w.criterion.connectivity, w.criterion.keep,
+                              w.criterion.min_size)
+        t = torch.from_numpy(w.volume).to(dev)
+        dims = roix.dims_of(t)
+        b = roix.bounds(dims, roix.F32, crit)
+        out = roix.Outputs(dev, b["rows"], b["stream_bytes"], min(b["outliers"], 1 << 24),
+                           min(b["components"], 1 << 20))
+        items.append((t, w.eb_mode, w.eb_value, crit, out))
+        need = max(need, roix.scratch_bytes(dims, roix.F32, crit))
+        w.volume = None
+    streams = 4
+    ctx = roix.Context(0, need * streams)
+    ctx.set_param("batch_streams", streams)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def plain_pass():
+        for (t, ebm, ebv, crit, out) in items:
+            ctx.fused(t, ebm, ebv, crit, out, stream)
+
+    def batch_pass():
+        ctx.fused_batch(items, stream)
+
+    res = {}
+    for name, fn in (("plain", plain_pass), ("batched", batch_pass)):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        bad = [i for i, it in enumerate(items) if it[4].collect()["einfo"].status != 0]
+        if bad:
+            log(f"{name}: volumes {bad[:5]} report a non-zero status")
+            sys.exit(1)
+        ev0.record(stream)
+        for _ in range(args.steps):
+            fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        res[name] = ms
+        log(f"{name}: {ms:.3f} ms per batch, {total / (ms * 1e-3) / 1e9:.1f} GB/s input")
+    gbs = total / (res["batched"] * 1e-3) / 1e9
+    line = {
+        "metric": METRIC, "value": round(gbs, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(res["batched"], 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched: {len(items)} f32 volumes, sides U{{64..512}}, 1-8 ellipsoids, "
+                               f"eb in {{1e-3,1e-4,1e-5}}, Otsu, 6-connectivity, components >= 64",
+                   "input_bytes": total, "batch_streams": streams, "graph": True},
+        "plain_sequential_ms": round(res["plain"], 4),
+        "plain_sequential_gbs": round(total / (res["plain"] * 1e-3) / 1e9, 2),
+        "batched_over_plain": round(res["plain"] / res["batched"], 3),
+    }
+    print(json.dumps(line))
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,10 +200,15 @@ def main():
                     help="also run a plain device copy of 1 GiB (the counter calibration for traffic)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL_STATS_CSV"),
                     help="summarise rocprofv3 counter runs of this script and exit")
+    ap.add_argument("--workload", choices=["plain", "batched"], default="plain",
+                    help="plain: the 1024^3 volume (default); batched: 64 uneven volumes in one graph launch")
+    ap.add_argument("--batch-volumes", type=int, default=64)
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary)
         return
+    if args.workload == "batched":
+        return bench_batched(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the reduction path has no multi-GPU "
               f"form in this build", file=sys.stderr)

@@ -242,6 +242,40 @@ roix_status roix_extract(roix_ctx* ctx, const void* d_in, roix_dtype dtype, cons
 roix_status roix_fused(roix_ctx* ctx, const void* d_in, roix_dtype dtype, roix_dims dims, roix_eb eb,
                        const roix_criterion* crit, const roix_fused_out* out, void* stream);
 
+/* One volume of a batch: input, shape, bound, criterion and the caller's
+ * output buffers (as for roix_fused). */
+typedef struct {
+    const void* d_in;
+    int32_t dtype; /* roix_dtype */
+    int32_t pad;
+    roix_dims dims;
+    roix_eb eb;
+    roix_criterion crit;
+    roix_fused_out out;
+} roix_volume_desc;
+
+/* Batched form: every volume of `vols` through the fused path, with output
+ * identical to n separate roix_fused calls.  The volumes run concurrently on
+ * batch_streams internal streams (largest first, each to the least-loaded
+ * stream), each stream with its own equal share of the scratch arena; the
+ * whole fork/join launch sequence is captured into a HIP graph, which is
+ * replayed while the descriptors and launch parameters stay the same.
+ * Asynchronous on `stream`.  Errors: ROIX_EINVAL (NULL ctx/vols, any invalid
+ * descriptor), ROIX_ENOMEM (a volume does not fit one stream's share of the
+ * arena even with one stream), ROIX_EDEVICE. */
+roix_status roix_fused_batch(roix_ctx* ctx, int32_t n, const roix_volume_desc* vols, void* stream);
+
+/* Launch parameters of a context (the autotuner's knobs):
+ *   "grid_stream"    workgroups of the grid-stride streaming kernels
+ *   "grid_read"      workgroups of the read-only range kernel
+ *   "batch_streams"  concurrent streams of roix_fused_batch (1..64)
+ *   "batch_graph"    1 = capture/replay batches as a HIP graph, 0 = launch eagerly
+ *   "compute_units"  (get only) the device's compute units
+ * None of them changes any output.  Errors: ROIX_EINVAL (unknown name or
+ * value out of range). */
+roix_status roix_ctx_set_param(roix_ctx* ctx, const char* name, int64_t value);
+roix_status roix_ctx_get_param(roix_ctx* ctx, const char* name, int64_t* value);
+
 /* Per-stage GPU timing.  When enabled, every kernel of the fused, staged
  * and batched paths is bracketed by HIP events on its stream;
  * roix_ctx_read_timing synchronises those events and returns, per stage,
@@ -256,7 +290,8 @@ const char* roix_status_string(roix_status st);
 
 /* sizeof of a public struct by name ("roix_quant_info", "roix_seg_info",
  * "roix_extract_info", "roix_component", "roix_row", "roix_fused_out",
- * "roix_criterion", "roix_eb", "roix_dims"), 0 if unknown: lets bindings
+ * "roix_criterion", "roix_eb", "roix_dims", "roix_volume_desc"), 0 if
+ * unknown: lets bindings
  * check their mirrors of this header. */
 size_t roix_sizeof(const char* type_name);
 

@@ -4,6 +4,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -59,6 +60,17 @@ static const char* kStageNames[ST_COUNT] = {
 
 using namespace roix;
 
+struct BatchState {
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> joins;
+    hipEvent_t fork = nullptr;
+    hipStream_t origin = nullptr;  // the graph is captured and launched here
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::vector<uint8_t> key;  // descriptors + launch parameters of the cached graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 struct roix_ctx {
     int device = 0;
     int cus = 0;
@@ -67,6 +79,9 @@ struct roix_ctx {
     Timer timer;
     int grid_stream = 2048;
     int grid_read = 512;
+    int batch_streams = 4;
+    int batch_graph = 1;
+    BatchState batch;
 };
 
 // ----------------------------------------------------------------- layout
@@ -114,10 +129,10 @@ static size_t fixed_bytes(const Geom& g) {
     return b;
 }
 
-static bool carve(roix_ctx* c, const Geom& g, Layout* L) {
+static bool carve_at(void* base, size_t bytes, const Geom& g, Layout* L) {
     const size_t fb = fixed_bytes(g);
-    if (c->arena_bytes < fb + kRunBytes) return false;
-    uint8_t* p = (uint8_t*)c->arena;
+    if (bytes < fb + kRunBytes) return false;
+    uint8_t* p = (uint8_t*)base;
     auto take = [&](size_t n) {
         uint8_t* q = p;
         p += align256(n);
@@ -136,8 +151,8 @@ static bool carve(roix_ctx* c, const Geom& g, Layout* L) {
     L->out_list = (uint32_t*)take((size_t)g.nrows * 4);
     L->chunk_row = (uint32_t*)take((size_t)(g.N / kEmitChunk + 2) * 4);
     L->scan_tmp = (uint64_t*)take((size_t)(kScanBlocks + 1) * 8);
-    const size_t used = (size_t)(p - (uint8_t*)c->arena) + 5 * 256;
-    uint64_t cap = (c->arena_bytes - used) / kRunBytes;
+    const size_t used = (size_t)(p - (uint8_t*)base) + 5 * 256;
+    uint64_t cap = (bytes - used) / kRunBytes;
     const uint64_t w = worst_runs(g);
     if (cap > w) cap = w;
     if (cap < 1) return false;
@@ -147,8 +162,10 @@ static bool carve(roix_ctx* c, const Geom& g, Layout* L) {
     L->parent = (uint32_t*)take(cap * 4);
     L->comp_id = (uint32_t*)take(cap * 4);
     L->kept_flag = (uint8_t*)take(cap);
-    return (size_t)(p - (uint8_t*)c->arena) <= c->arena_bytes;
+    return (size_t)(p - (uint8_t*)base) <= bytes;
 }
+
+static bool carve(roix_ctx* c, const Geom& g, Layout* L) { return carve_at(c->arena, c->arena_bytes, g, L); }
 
 static LaunchCtx lctx(roix_ctx* c, void* stream) {
     LaunchCtx lc;
@@ -226,6 +243,31 @@ static hipError_t spans_and_emit(const LaunchCtx& lc, const Geom& g, const Layou
     return launch_emit(lc, g, L, in, dt, out);
 }
 
+static void batch_release(BatchState& b) {
+    if (b.exec) hipGraphExecDestroy(b.exec);
+    if (b.graph) hipGraphDestroy(b.graph);
+    b.exec = nullptr;
+    b.graph = nullptr;
+    b.key.clear();
+}
+
+// the launch sequence of the fused path on an already carved layout
+static roix_status enqueue_fused(const LaunchCtx& lc, const Geom& g, Layout L, const void* d_in, roix_dtype dtype,
+                                 roix_eb eb, const roix_criterion* crit, const roix_fused_out* out) {
+    const bool fixed = crit->thr == ROIX_THR_FIXED;
+    const int kind = dtype == ROIX_F32 ? 0 : 1;
+    ROIX_TRY(launch_init(lc, L.S));
+    ROIX_TRY(launch_range(lc, d_in, dtype, g.N, L.S));
+    ROIX_TRY(launch_resolve_dt(lc, L.S, dtype, eb, crit));
+    ROIX_TRY(launch_quant_hist(lc, d_in, kind, g, L.S, L.proxy, fixed));
+    ROIX_TRY(launch_otsu(lc, L.S, fixed));
+    ROIX_TRY(label_and_keep(lc, g, L, crit, out->d_comps, out->comps_cap));
+    ROIX_TRY(launch_spans_from_runs(lc, g, L));
+    ROIX_TRY(spans_and_emit(lc, g, L, d_in, dtype, out));
+    ROIX_TRY(launch_finalize(lc, L.S, out->d_qinfo, out->d_sinfo, out->d_einfo, true));
+    return ROIX_OK;
+}
+
 // ------------------------------------------------------------------- ABI
 
 extern "C" {
@@ -253,7 +295,7 @@ size_t roix_sizeof(const char* t) {
                      {"roix_extract_info", sizeof(roix_extract_info)}, {"roix_component", sizeof(roix_component)},
                      {"roix_row", sizeof(roix_row)},                   {"roix_fused_out", sizeof(roix_fused_out)},
                      {"roix_criterion", sizeof(roix_criterion)},       {"roix_eb", sizeof(roix_eb)},
-                     {"roix_dims", sizeof(roix_dims)}};
+                     {"roix_dims", sizeof(roix_dims)},                 {"roix_volume_desc", sizeof(roix_volume_desc)}};
     for (const auto& e : tab)
         if (strcmp(e.n, t) == 0) return e.s;
     return 0;
@@ -330,6 +372,13 @@ roix_status roix_ctx_destroy(roix_ctx* ctx) {
         hipEventDestroy(p.b);
     }
     for (auto e : ctx->timer.pool) hipEventDestroy(e);
+    batch_release(ctx->batch);
+    for (auto st : ctx->batch.streams) hipStreamDestroy(st);
+    for (auto ev : ctx->batch.joins) hipEventDestroy(ev);
+    if (ctx->batch.fork) hipEventDestroy(ctx->batch.fork);
+    if (ctx->batch.ev_in) hipEventDestroy(ctx->batch.ev_in);
+    if (ctx->batch.ev_out) hipEventDestroy(ctx->batch.ev_out);
+    if (ctx->batch.origin) hipStreamDestroy(ctx->batch.origin);
     hipFree(ctx->arena);
     hipSetDevice(prev);
     delete ctx;
@@ -433,18 +482,143 @@ roix_status roix_fused(roix_ctx* ctx, const void* d_in, roix_dtype dtype, roix_d
     if (!aligned(d_in, dtype == ROIX_F32 ? 4 : 2)) return ROIX_EINVAL;
     Layout L;
     if (!carve(ctx, g, &L)) return ROIX_ENOMEM;
-    LaunchCtx lc = lctx(ctx, stream);
-    const bool fixed = crit->thr == ROIX_THR_FIXED;
-    const int kind = dtype == ROIX_F32 ? 0 : 1;
-    ROIX_TRY(launch_init(lc, L.S));
-    ROIX_TRY(launch_range(lc, d_in, dtype, g.N, L.S));
-    ROIX_TRY(launch_resolve_dt(lc, L.S, dtype, eb, crit));
-    ROIX_TRY(launch_quant_hist(lc, d_in, kind, g, L.S, L.proxy, fixed));
-    ROIX_TRY(launch_otsu(lc, L.S, fixed));
-    ROIX_TRY(label_and_keep(lc, g, L, crit, out->d_comps, out->comps_cap));
-    ROIX_TRY(launch_spans_from_runs(lc, g, L));
-    ROIX_TRY(spans_and_emit(lc, g, L, d_in, dtype, out));
-    ROIX_TRY(launch_finalize(lc, L.S, out->d_qinfo, out->d_sinfo, out->d_einfo, true));
+    return enqueue_fused(lctx(ctx, stream), g, L, d_in, dtype, eb, crit, out);
+}
+
+roix_status roix_ctx_set_param(roix_ctx* ctx, const char* name, int64_t value) {
+    if (!ctx || !name) return ROIX_EINVAL;
+    const bool pos = value >= 1 && value <= (1 << 22);
+    if (strcmp(name, "grid_stream") == 0 && pos) ctx->grid_stream = (int)value;
+    else if (strcmp(name, "grid_read") == 0 && pos) ctx->grid_read = (int)value;
+    else if (strcmp(name, "batch_streams") == 0 && value >= 1 && value <= 64) ctx->batch_streams = (int)value;
+    else if (strcmp(name, "batch_graph") == 0 && (value == 0 || value == 1)) ctx->batch_graph = (int)value;
+    else return ROIX_EINVAL;
+    return ROIX_OK;
+}
+
+roix_status roix_ctx_get_param(roix_ctx* ctx, const char* name, int64_t* value) {
+    if (!ctx || !name || !value) return ROIX_EINVAL;
+    if (strcmp(name, "grid_stream") == 0) *value = ctx->grid_stream;
+    else if (strcmp(name, "grid_read") == 0) *value = ctx->grid_read;
+    else if (strcmp(name, "batch_streams") == 0) *value = ctx->batch_streams;
+    else if (strcmp(name, "batch_graph") == 0) *value = ctx->batch_graph;
+    else if (strcmp(name, "compute_units") == 0) *value = ctx->cus;
+    else return ROIX_EINVAL;
+    return ROIX_OK;
+}
+
+static roix_status batch_streams_ready(roix_ctx* c, int S) {
+    BatchState& b = c->batch;
+    if (!b.fork && hipEventCreateWithFlags(&b.fork, hipEventDisableTiming) != hipSuccess) return ROIX_EDEVICE;
+    if (!b.ev_in && hipEventCreateWithFlags(&b.ev_in, hipEventDisableTiming) != hipSuccess) return ROIX_EDEVICE;
+    if (!b.ev_out && hipEventCreateWithFlags(&b.ev_out, hipEventDisableTiming) != hipSuccess) return ROIX_EDEVICE;
+    if (!b.origin && hipStreamCreateWithFlags(&b.origin, hipStreamNonBlocking) != hipSuccess) return ROIX_EDEVICE;
+    while ((int)b.streams.size() < S) {
+        hipStream_t st;
+        hipEvent_t ev;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return ROIX_EDEVICE;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return ROIX_EDEVICE;
+        b.streams.push_back(st);
+        b.joins.push_back(ev);
+    }
+    return ROIX_OK;
+}
+
+// Enqueue the whole batch: volumes spread over S slots (largest first, each
+// to the least-loaded slot), each slot a stream of its own with a private
+// part of the arena, forked from and joined back into the caller's stream.
+static roix_status batch_enqueue(roix_ctx* c, int32_t n, const roix_volume_desc* v, const std::vector<Geom>& gs,
+                                 int S, size_t slot_bytes, hipStream_t stream) {
+    BatchState& b = c->batch;
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int a, int d) { return gs[a].N > gs[d].N; });
+    std::vector<uint64_t> load(S, 0);
+    std::vector<std::vector<int>> slot(S);
+    for (int i : order) {
+        int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        slot[k].push_back(i);
+        load[k] += gs[i].N;
+    }
+    ROIX_TRY(hipEventRecord(b.fork, stream));
+    for (int k = 0; k < S; ++k) {
+        ROIX_TRY(hipStreamWaitEvent(b.streams[k], b.fork, 0));
+        void* base = (uint8_t*)c->arena + (size_t)k * slot_bytes;
+        LaunchCtx lc;
+        lc.stream = b.streams[k];
+        lc.timer = nullptr;
+        lc.grid_stream = c->grid_stream;
+        lc.grid_read = c->grid_read;
+        for (int i : slot[k]) {
+            Layout L;
+            if (!carve_at(base, slot_bytes, gs[i], &L)) return ROIX_ENOMEM;
+            roix_status st = enqueue_fused(lc, gs[i], L, v[i].d_in, (roix_dtype)v[i].dtype, v[i].eb, &v[i].crit, &v[i].out);
+            if (st != ROIX_OK) return st;
+        }
+        ROIX_TRY(hipEventRecord(b.joins[k], b.streams[k]));
+        ROIX_TRY(hipStreamWaitEvent(stream, b.joins[k], 0));
+    }
+    return ROIX_OK;
+}
+
+roix_status roix_fused_batch(roix_ctx* ctx, int32_t n, const roix_volume_desc* vols, void* stream_) {
+    if (!ctx || n < 0 || (n > 0 && !vols)) return ROIX_EINVAL;
+    if (n == 0) return ROIX_OK;
+    std::vector<Geom> gs(n);
+    size_t need = 0;
+    for (int i = 0; i < n; ++i) {
+        const roix_volume_desc& d = vols[i];
+        if (!d.d_in || !geom_of(d.dims, &gs[i]) || !eb_ok(d.eb) || !crit_ok(&d.crit) || !out_ok(&d.out, true))
+            return ROIX_EINVAL;
+        if (d.dtype != ROIX_F32 && d.dtype != ROIX_U16) return ROIX_EINVAL;
+        if (!aligned(d.d_in, d.dtype == ROIX_F32 ? 4 : 2)) return ROIX_EINVAL;
+        need = std::max(need, fixed_bytes(gs[i]) + kRunBytes);
+    }
+    int S = std::min<int>(ctx->batch_streams, n);
+    size_t slot_bytes = (ctx->arena_bytes / (size_t)S) & ~(size_t)255;
+    while (S > 1 && slot_bytes < need) {
+        --S;
+        slot_bytes = (ctx->arena_bytes / (size_t)S) & ~(size_t)255;
+    }
+    if (slot_bytes < need) return ROIX_ENOMEM;
+    if (batch_streams_ready(ctx, S) != ROIX_OK) return ROIX_EDEVICE;
+    hipStream_t stream = (hipStream_t)stream_;
+    if (!ctx->batch_graph) return batch_enqueue(ctx, n, vols, gs, S, slot_bytes, stream);
+    // the graph is specific to the descriptors (buffer addresses are baked
+    // into its kernel arguments): reuse it while they are the same
+    std::vector<uint8_t> key(sizeof(roix_volume_desc) * (size_t)n + 4 * sizeof(int));
+    memcpy(key.data(), vols, sizeof(roix_volume_desc) * (size_t)n);
+    const int params[4] = {S, ctx->grid_stream, ctx->grid_read, (int)(slot_bytes >> 20)};
+    memcpy(key.data() + sizeof(roix_volume_desc) * (size_t)n, params, sizeof params);
+    BatchState& b = ctx->batch;
+    if (!b.exec || b.key != key) {
+        // capture on the context's own stream (the caller's may be the legacy
+        // default stream, which cannot be captured)
+        batch_release(b);
+        ROIX_TRY(hipStreamBeginCapture(b.origin, hipStreamCaptureModeThreadLocal));
+        roix_status st = batch_enqueue(ctx, n, vols, gs, S, slot_bytes, b.origin);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(b.origin, &graph);
+        (void)hipGetLastError();
+        if (st != ROIX_OK) {
+            if (graph) hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess || !graph) return ROIX_EDEVICE;
+        hipGraphExec_t exec = nullptr;
+        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            hipGraphDestroy(graph);
+            return ROIX_EDEVICE;
+        }
+        b.graph = graph;
+        b.exec = exec;
+        b.key = key;
+    }
+    ROIX_TRY(hipEventRecord(b.ev_in, stream));
+    ROIX_TRY(hipStreamWaitEvent(b.origin, b.ev_in, 0));
+    ROIX_TRY(hipGraphLaunch(b.exec, b.origin));
+    ROIX_TRY(hipEventRecord(b.ev_out, b.origin));
+    ROIX_TRY(hipStreamWaitEvent(stream, b.ev_out, 0));
     return ROIX_OK;
 }
 

@@ -69,6 +69,11 @@ class FusedOut(ctypes.Structure):
                 ("d_qinfo", ctypes.c_void_p), ("d_sinfo", ctypes.c_void_p), ("d_einfo", ctypes.c_void_p)]
 
 
+class VolumeDesc(ctypes.Structure):
+    _fields_ = [("d_in", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("pad", ctypes.c_int32), ("dims", Dims),
+                ("eb", Eb), ("crit", CCriterion), ("out", FusedOut)]
+
+
 COMP_BYTES, ROW_BYTES = 48, 32
 STAGE_MAX = 64
 
@@ -99,10 +104,14 @@ def load():
     lib.roix_stage_name.restype = ctypes.c_char_p
     lib.roix_ctx_set_timing.argtypes = [vp, ci]
     lib.roix_ctx_read_timing.argtypes = [vp, P(ctypes.c_double), P(i64)]
+    lib.roix_fused_batch.argtypes = [vp, ctypes.c_int32, vp, vp]
+    lib.roix_ctx_set_param.argtypes = [vp, ctypes.c_char_p, i64]
+    lib.roix_ctx_get_param.argtypes = [vp, ctypes.c_char_p, P(i64)]
     lib.roix_status_string.argtypes = [ci]
     lib.roix_status_string.restype = ctypes.c_char_p
     for f in ("roix_ctx_create", "roix_ctx_destroy", "roix_bounds", "roix_quantize", "roix_segment",
-              "roix_extract", "roix_fused", "roix_ctx_set_timing", "roix_ctx_read_timing"):
+              "roix_extract", "roix_fused", "roix_ctx_set_timing", "roix_ctx_read_timing", "roix_fused_batch",
+              "roix_ctx_set_param", "roix_ctx_get_param"):
         getattr(lib, f).restype = ci
     _lib = lib
     return lib
@@ -244,6 +253,15 @@ class Context:
         names = stage_names()
         return {names[i]: (ms[i], cnt[i]) for i in range(n)}
 
+    # ------------------------------------------------------- parameters
+    def set_param(self, name: str, value: int):
+        _check(load().roix_ctx_set_param(self.h, name.encode(), int(value)), f"roix_ctx_set_param({name})")
+
+    def get_param(self, name: str) -> int:
+        v = ctypes.c_int64()
+        _check(load().roix_ctx_get_param(self.h, name.encode(), ctypes.byref(v)), f"roix_ctx_get_param({name})")
+        return v.value
+
     # ----------------------------------------------------------- calls
     def fused(self, vol: torch.Tensor, eb_mode: str, eb_value: float, crit: Criterion, out: Outputs,
               stream=None):
@@ -252,6 +270,15 @@ class Context:
         st = load().roix_fused(self.h, _ptr(vol), dtype_of(vol), dims_of(vol), eb_of(eb_mode, eb_value),
                                ctypes.byref(c), ctypes.byref(out.c), _stream(stream))
         _check(st, "roix_fused")
+
+    def fused_batch(self, items, stream=None):
+        """items: list of (volume tensor, eb_mode, eb_value, Criterion, Outputs).
+        Enqueues the batched path (one graph launch when capture is on)."""
+        arr = (VolumeDesc * len(items))()
+        for i, (vol, ebm, ebv, crit, out) in enumerate(items):
+            arr[i] = VolumeDesc(vol.data_ptr(), dtype_of(vol), 0, dims_of(vol), eb_of(ebm, ebv), crit.c(), out.c)
+        st = load().roix_fused_batch(self.h, len(items), ctypes.cast(arr, ctypes.c_void_p), _stream(stream))
+        _check(st, "roix_fused_batch")
 
     def quantize(self, vol: torch.Tensor, eb_mode: str, eb_value: float, with_bits: bool = True, stream=None):
         n = vol.numel()

@@ -43,7 +43,8 @@ def test_struct_sizes_match_binding(lib):
     L.roix_sizeof.restype = ctypes.c_size_t
     for name, cls in (("roix_quant_info", roix.QuantInfo), ("roix_seg_info", roix.SegInfo),
                       ("roix_extract_info", roix.ExtractInfo), ("roix_fused_out", roix.FusedOut),
-                      ("roix_criterion", roix.CCriterion), ("roix_eb", roix.Eb), ("roix_dims", roix.Dims)):
+                      ("roix_criterion", roix.CCriterion), ("roix_eb", roix.Eb), ("roix_dims", roix.Dims),
+                      ("roix_volume_desc", roix.VolumeDesc)):
         assert L.roix_sizeof(name.encode()) == ctypes.sizeof(cls), name
     assert L.roix_sizeof(b"roix_component") == roix.COMP_BYTES == 48
     assert L.roix_sizeof(b"roix_row") == roix.ROW_BYTES == 32
