@@ -268,6 +268,10 @@ roix_status roix_fused_batch(roix_ctx* ctx, int32_t n, const roix_volume_desc* v
 /* Launch parameters of a context (the autotuner's knobs):
  *   "grid_stream"    workgroups of the grid-stride streaming kernels
  *   "grid_read"      workgroups of the read-only range kernel
+ *   "seg_grid"       workgroups of the component-labelling kernels
+ *   "seg_runs"       runs labelled together in one workgroup's local memory
+ *                    (a multiple of 256 up to 16384; 0 = spread the runs over
+ *                    seg_grid workgroups, at least 2048 each)
  *   "batch_streams"  concurrent streams of roix_fused_batch (1..64)
  *   "batch_graph"    1 = capture/replay batches as a HIP graph, 0 = launch eagerly
  *   "compute_units"  (get only) the device's compute units

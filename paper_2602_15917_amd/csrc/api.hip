@@ -79,6 +79,8 @@ struct roix_ctx {
     Timer timer;
     int grid_stream = 2048;
     int grid_read = 512;
+    int seg_grid = 512;
+    int seg_runs = 0;
     int batch_streams = 4;
     int batch_graph = 1;
     BatchState batch;
@@ -103,7 +105,7 @@ static bool geom_of(roix_dims d, Geom* g) {
     return true;
 }
 
-static constexpr uint64_t kRunBytes = 17;  // xs, xe, parent, comp id (4 B each) + kept flag (1 B)
+static constexpr uint64_t kRunBytes = 21;  // xs, xe, parent, comp id, row (4 B each) + kept flag (1 B)
 
 static uint64_t worst_runs(const Geom& g) {
     uint64_t w = (uint64_t)g.nrows * (uint64_t)((g.nx + 1) / 2);
@@ -125,7 +127,7 @@ static size_t fixed_bytes(const Geom& g) {
     b += 2 * align256((size_t)g.nrows * 4);               // nz_rows, out_list
     b += align256((size_t)(g.N / kEmitChunk + 2) * 4);    // chunk_row
     b += align256((size_t)(kScanBlocks + 1) * 8);         // scan tmp
-    b += 5 * 256;                                         // run-array alignment slack
+    b += 6 * 256;                                         // run-array alignment slack
     return b;
 }
 
@@ -151,7 +153,7 @@ static bool carve_at(void* base, size_t bytes, const Geom& g, Layout* L) {
     L->out_list = (uint32_t*)take((size_t)g.nrows * 4);
     L->chunk_row = (uint32_t*)take((size_t)(g.N / kEmitChunk + 2) * 4);
     L->scan_tmp = (uint64_t*)take((size_t)(kScanBlocks + 1) * 8);
-    const size_t used = (size_t)(p - (uint8_t*)base) + 5 * 256;
+    const size_t used = (size_t)(p - (uint8_t*)base) + 6 * 256;
     uint64_t cap = (bytes - used) / kRunBytes;
     const uint64_t w = worst_runs(g);
     if (cap > w) cap = w;
@@ -161,6 +163,7 @@ static bool carve_at(void* base, size_t bytes, const Geom& g, Layout* L) {
     L->run_xe = (uint32_t*)take(cap * 4);
     L->parent = (uint32_t*)take(cap * 4);
     L->comp_id = (uint32_t*)take(cap * 4);
+    L->run_row = (uint32_t*)take(cap * 4);
     L->kept_flag = (uint8_t*)take(cap);
     return (size_t)(p - (uint8_t*)base) <= bytes;
 }
@@ -173,6 +176,8 @@ static LaunchCtx lctx(roix_ctx* c, void* stream) {
     lc.timer = c->timer.on ? &c->timer : nullptr;
     lc.grid_stream = c->grid_stream;
     lc.grid_read = c->grid_read;
+    lc.seg_grid = c->seg_grid;
+    lc.seg_runs = c->seg_runs;
     return lc;
 }
 
@@ -342,6 +347,7 @@ roix_status roix_ctx_create(int device, size_t scratch_bytes, roix_ctx** out) {
     if (c->cus <= 0) c->cus = 256;
     c->grid_stream = c->cus * 8;
     c->grid_read = c->cus * 2;
+    c->seg_grid = c->cus * 2;
     if (const char* s = getenv("ROIX_GRID_STREAM")) {
         int v = atoi(s);
         if (v > 0 && v <= 1 << 20) c->grid_stream = v;
@@ -490,6 +496,9 @@ roix_status roix_ctx_set_param(roix_ctx* ctx, const char* name, int64_t value) {
     const bool pos = value >= 1 && value <= (1 << 22);
     if (strcmp(name, "grid_stream") == 0 && pos) ctx->grid_stream = (int)value;
     else if (strcmp(name, "grid_read") == 0 && pos) ctx->grid_read = (int)value;
+    else if (strcmp(name, "seg_grid") == 0 && pos) ctx->seg_grid = (int)value;
+    else if (strcmp(name, "seg_runs") == 0 && value >= 0 && value <= 16384 && value % 256 == 0)
+        ctx->seg_runs = (int)value;
     else if (strcmp(name, "batch_streams") == 0 && value >= 1 && value <= 64) ctx->batch_streams = (int)value;
     else if (strcmp(name, "batch_graph") == 0 && (value == 0 || value == 1)) ctx->batch_graph = (int)value;
     else return ROIX_EINVAL;
@@ -500,6 +509,8 @@ roix_status roix_ctx_get_param(roix_ctx* ctx, const char* name, int64_t* value) 
     if (!ctx || !name || !value) return ROIX_EINVAL;
     if (strcmp(name, "grid_stream") == 0) *value = ctx->grid_stream;
     else if (strcmp(name, "grid_read") == 0) *value = ctx->grid_read;
+    else if (strcmp(name, "seg_grid") == 0) *value = ctx->seg_grid;
+    else if (strcmp(name, "seg_runs") == 0) *value = ctx->seg_runs;
     else if (strcmp(name, "batch_streams") == 0) *value = ctx->batch_streams;
     else if (strcmp(name, "batch_graph") == 0) *value = ctx->batch_graph;
     else if (strcmp(name, "compute_units") == 0) *value = ctx->cus;
@@ -544,11 +555,8 @@ static roix_status batch_enqueue(roix_ctx* c, int32_t n, const roix_volume_desc*
     for (int k = 0; k < S; ++k) {
         ROIX_TRY(hipStreamWaitEvent(b.streams[k], b.fork, 0));
         void* base = (uint8_t*)c->arena + (size_t)k * slot_bytes;
-        LaunchCtx lc;
-        lc.stream = b.streams[k];
+        LaunchCtx lc = lctx(c, b.streams[k]);
         lc.timer = nullptr;
-        lc.grid_stream = c->grid_stream;
-        lc.grid_read = c->grid_read;
         for (int i : slot[k]) {
             Layout L;
             if (!carve_at(base, slot_bytes, gs[i], &L)) return ROIX_ENOMEM;
@@ -586,9 +594,9 @@ roix_status roix_fused_batch(roix_ctx* ctx, int32_t n, const roix_volume_desc* v
     if (!ctx->batch_graph) return batch_enqueue(ctx, n, vols, gs, S, slot_bytes, stream);
     // the graph is specific to the descriptors (buffer addresses are baked
     // into its kernel arguments): reuse it while they are the same
-    std::vector<uint8_t> key(sizeof(roix_volume_desc) * (size_t)n + 4 * sizeof(int));
+    const int params[6] = {S, ctx->grid_stream, ctx->grid_read, ctx->seg_grid, ctx->seg_runs, (int)(slot_bytes >> 20)};
+    std::vector<uint8_t> key(sizeof(roix_volume_desc) * (size_t)n + sizeof params);
     memcpy(key.data(), vols, sizeof(roix_volume_desc) * (size_t)n);
-    const int params[4] = {S, ctx->grid_stream, ctx->grid_read, (int)(slot_bytes >> 20)};
     memcpy(key.data() + sizeof(roix_volume_desc) * (size_t)n, params, sizeof params);
     BatchState& b = ctx->batch;
     if (!b.exec || b.key != key) {

@@ -64,6 +64,7 @@ struct Layout {
     uint32_t* run_xe;       // run_cap
     uint32_t* parent;       // run_cap
     uint32_t* comp_id;      // run_cap (root flags, then component ids)
+    uint32_t* run_row;      // run_cap (row z * ny + y of each run)
     uint8_t* kept_flag;     // run_cap (per component)
     uint32_t* row_xs;       // nrows
     uint32_t* row_xe;       // nrows
@@ -204,6 +205,8 @@ struct LaunchCtx {
     Timer* timer;  // may be null
     int grid_stream;  // workgroups of the grid-stride streaming kernels
     int grid_read;    // workgroups of the read-only streaming kernel (range)
+    int seg_grid;     // workgroups of the segment labelling kernels
+    int seg_runs;     // runs per segment (0: spread the runs over seg_grid)
 };
 
 // ------------------------------------------------------------ launchers

@@ -2,14 +2,15 @@
 // runs, per-component statistics and the keep rule.
 //
 // The mask (object = proxy byte above the threshold byte) is turned into a
-// row bitmask with one wave ballot per 64 voxels, and every row (z, y) into
-// its maximal runs of object voxels.  Runs are numbered in raster order, so
-// the run with the smallest number of a component holds the component's
-// smallest linear voxel index.  Runs of neighbouring rows that touch are
-// united with a lock-free union-find that always links the larger root under
-// the smaller one; after flattening, the root of a component is its first run
-// and the canonical label is that run's first voxel.  Work is O(runs), not
-// O(voxels): per-voxel traffic is one read of the 1-byte proxy and one
+// row bitmask with SWAR byte compares, and every row (z, y) into its maximal
+// runs of object voxels.  Runs are numbered in raster order, so the run with
+// the smallest number of a component holds the component's smallest linear
+// voxel index.  Touching runs of neighbouring rows are united with a union-
+// find that always links the larger root under the smaller one: first in
+// LDS within segments of consecutive run numbers, then across segments in
+// the global forest.  After flattening, the root of a component is its first
+// run and the canonical label is that run's first voxel.  Work is O(runs),
+// not O(voxels): per-voxel traffic is one read of the 1-byte proxy and one
 // write + read of the 1-bit mask.
 #include "common.h"
 
@@ -178,7 +179,8 @@ __global__ __launch_bounds__(kBlock) void k_runs_write_lanes(const uint64_t* __r
                                                              const uint32_t* __restrict__ run_off,
                                                              uint32_t* __restrict__ xs_out,
                                                              uint32_t* __restrict__ xe_out,
-                                                             uint32_t* __restrict__ parent, const DevState* S) {
+                                                             uint32_t* __restrict__ parent,
+                                                             uint32_t* __restrict__ run_row, const DevState* S) {
     if (thread_exit(S)) return;  // no barrier below; the status is the same for every lane of a wave
     const int lane = threadIdx.x % kWave;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
@@ -219,6 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_runs_write_lanes(const uint64_t* __r
             xs_out[k] = xs;
             xe_out[k] = xe;
             parent[k] = k;
+            run_row[k] = (uint32_t)wl.row;
             ++k;
         }
     }
@@ -229,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_runs_write_lanes(const uint64_t* __r
 __global__ __launch_bounds__(kBlock) void k_runs_write(const uint64_t* __restrict__ maskbits, int64_t nrows, int64_t W,
                                                        const uint32_t* __restrict__ run_off, uint32_t* __restrict__ xs_out,
                                                        uint32_t* __restrict__ xe_out, uint32_t* __restrict__ parent,
-                                                       const DevState* S) {
+                                                       uint32_t* __restrict__ run_row, const DevState* S) {
     if (thread_exit(S)) return;
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
     for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < nrows; row += nthreads) {
@@ -252,6 +255,7 @@ __global__ __launch_bounds__(kBlock) void k_runs_write(const uint64_t* __restric
                     xs_out[k] = xs;
                     xe_out[k] = pos;
                     parent[k] = k;
+                    run_row[k] = (uint32_t)row;
                     ++k;
                 }
             }
@@ -261,6 +265,7 @@ __global__ __launch_bounds__(kBlock) void k_runs_write(const uint64_t* __restric
             xs_out[k] = xs;
             xe_out[k] = (uint32_t)(W * 64);
             parent[k] = k;
+            run_row[k] = (uint32_t)row;
         }
     }
 }
@@ -271,11 +276,12 @@ hipError_t launch_runs_write(const LaunchCtx& lc, const Geom& g, const Layout& L
         const int64_t R = kWave / g.W;
         hipLaunchKernelGGL(k_runs_write_lanes, dim3(grid_for((g.nrows + R - 1) / R, kBlock / kWave, lc.grid_stream)),
                            dim3(kBlock), 0, lc.stream, (const uint64_t*)L.maskbits, g.nx, g.nrows, g.W,
-                           (const uint32_t*)L.run_off, L.run_xs, L.run_xe, L.parent, (const DevState*)L.S);
+                           (const uint32_t*)L.run_off, L.run_xs, L.run_xe, L.parent, L.run_row,
+                           (const DevState*)L.S);
     } else {
         hipLaunchKernelGGL(k_runs_write, dim3(grid_for(g.nrows, kBlock, 16384)), dim3(kBlock), 0, lc.stream,
                            (const uint64_t*)L.maskbits, g.nrows, g.W, (const uint32_t*)L.run_off, L.run_xs, L.run_xe,
-                           L.parent, (const DevState*)L.S);
+                           L.parent, L.run_row, (const DevState*)L.S);
     }
     timer_end(lc.timer, ST_RUNS, lc.stream);
     return hipGetLastError();
@@ -320,29 +326,7 @@ __device__ __forceinline__ void unite(uint32_t* parent, uint32_t a, uint32_t b) 
     }
 }
 
-// Visit every pair of touching runs of two neighbouring rows [a, a1) and
-// [b, b1): x intervals overlap (6-connectivity) or touch within one voxel
-// (26-connectivity; the rows differ in y and/or z, so a diagonal step is a
-// neighbour).  Both run lists are sorted by x, so one merge walk suffices.
-template <bool C26, typename F>
-__device__ __forceinline__ void for_touching(const uint32_t* xs, const uint32_t* xe, uint32_t a, uint32_t a1,
-                                             uint32_t b, uint32_t b1, F&& f) {
-    while (a < a1 && b < b1) {
-        const uint32_t as = xs[a], ae = xe[a], bs = xs[b], be = xe[b];
-        const bool hit = C26 ? (as <= be && bs <= ae) : (as < be && bs < ae);
-        if (hit) f(a, b);
-        if (ae < be)
-            ++a;
-        else if (be < ae)
-            ++b;
-        else {
-            ++a;
-            ++b;
-        }
-    }
-}
-
-// Union-find in LDS for the runs of one z-plane (same linking rule).
+// Union-find in LDS for the runs of one segment (same linking rule).
 __device__ __forceinline__ uint32_t lfind(uint32_t* p, uint32_t x) {
     while (true) {
         const uint32_t q = p[x];
@@ -370,115 +354,213 @@ __device__ __forceinline__ void lunite(uint32_t* p, uint32_t a, uint32_t b) {
     }
 }
 
-constexpr int kPlaneCap = 8192;  // runs of a z-plane labelled in LDS (32 KB)
-constexpr int kPairCap = 2048;   // distinct plane-root pairs per z-plane boundary (16 KB)
+// --------------------------------------------------- run-range segments
+//
+// The runs are cut into segments of T consecutive run numbers, whatever the
+// geometry: a segment may hold several z-planes of a sparse volume or a few
+// rows of a dense one, and every workgroup gets the same amount of work.
+// Level 1 labels each segment in LDS (all links whose two runs lie in the
+// segment, in-plane and across z), level 2 unites the roots of links that
+// reach back into an earlier segment in the global forest.
 
-// Level 1, one workgroup per z-plane: components of the plane's runs (links
-// inside the plane, between rows y-1 and y) in LDS, then parent[run] = the
-// run number of its plane-local root.  A plane with more runs than fit in
-// LDS is united directly in the global forest.
+constexpr int kSegCap = 16384;   // runs of a segment labelled in LDS (64 KB)
+constexpr int kSegMin = 2048;
+constexpr int kSegBlock = 1024;
+constexpr int kCrossCap = 4096;  // distinct root pairs per segment head (32 KB)
+
+// T: the launch parameter when set (a multiple of 256 in [256, kSegCap]),
+// else n spread over G workgroups, clamped.  Both levels use the same G.
+__device__ __forceinline__ uint32_t seg_runs(uint32_t n, uint32_t G, uint32_t param) {
+    if (param) return param;
+    uint32_t t = (uint32_t)(((uint64_t)n + G - 1) / G);
+    t = (t + 255u) & ~255u;
+    return t < (uint32_t)kSegMin ? (uint32_t)kSegMin : (t > (uint32_t)kSegCap ? (uint32_t)kSegCap : t);
+}
+
+// (z, y) of row r = z * ny + y: a double estimate, then an exact correction.
+__device__ __forceinline__ void row_zy(uint32_t r, uint32_t ny, double inv_ny, uint32_t& z, uint32_t& y) {
+    uint32_t q = (uint32_t)((double)r * inv_ny);
+    if ((uint64_t)q * ny > r) --q;
+    if ((uint64_t)(q + 1) * ny <= r) ++q;
+    z = q;
+    y = r - q * ny;
+}
+
+// First run b in [b0, b1) of a row that can touch [as, ae): its end reaches
+// the start (xe > as for 6-, xe >= as for 26-connectivity).  Runs of a row
+// are sorted and disjoint, so the ends increase.
 template <bool C26>
-__global__ __launch_bounds__(kBlock) void k_plane_label(const uint32_t* __restrict__ run_off,
-                                                        const uint32_t* __restrict__ xs,
-                                                        const uint32_t* __restrict__ xe, uint32_t* parent, int64_t ny,
-                                                        int64_t nz, const DevState* S) {
-    __shared__ uint32_t lp[kPlaneCap];
-    if (block_exit_l(S)) return;
-    for (int64_t z = blockIdx.x; z < nz; z += gridDim.x) {
-        const uint32_t a0 = run_off[z * ny], a1 = run_off[(z + 1) * ny];
-        const uint32_t n = a1 - a0;
-        if (n == 0) continue;
-        if (n <= (uint32_t)kPlaneCap) {
-            for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) lp[i] = i;
-            __syncthreads();
-            for (int64_t y = 1 + threadIdx.x; y < ny; y += blockDim.x) {
-                const int64_t r = z * ny + y;
-                for_touching<C26>(xs, xe, run_off[r], run_off[r + 1], run_off[r - 1], run_off[r],
-                                  [&](uint32_t a, uint32_t b) { lunite(lp, a - a0, b - a0); });
-            }
-            __syncthreads();
-            for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-                uint32_t r = i;
-                while (lp[r] != r) r = lp[r];
-                parent[a0 + i] = a0 + r;
-            }
-            __syncthreads();  // lp is reused by the next plane
-        } else {
-            for (int64_t y = 1 + threadIdx.x; y < ny; y += blockDim.x) {
-                const int64_t r = z * ny + y;
-                for_touching<C26>(xs, xe, run_off[r], run_off[r + 1], run_off[r - 1], run_off[r],
-                                  [&](uint32_t a, uint32_t b) { unite(parent, a, b); });
-            }
+__device__ __forceinline__ uint32_t first_touch(const uint32_t* xe, uint32_t b0, uint32_t b1, uint32_t as) {
+    while (b0 < b1) {
+        const uint32_t mid = b0 + ((b1 - b0) >> 1);
+        const uint32_t e = xe[mid];
+        if (C26 ? e >= as : e > as)
+            b1 = mid;
+        else
+            b0 = mid + 1;
+    }
+    return b0;
+}
+
+// The rows a run of row r = (z, y) can touch among earlier rows: (z, y-1)
+// and (z-1, y), plus (z-1, y-1) and (z-1, y+1) with 26-connectivity (the
+// diagonal x steps are in the touch rule).
+template <bool C26, typename F>
+__device__ __forceinline__ void for_back_rows(uint32_t r, uint32_t z, uint32_t y, uint32_t ny, F&& f) {
+    if (y > 0) f(r - 1);
+    if (z > 0) {
+        const uint32_t rz = r - ny;
+        f(rz);
+        if (C26) {
+            if (y > 0) f(rz - 1);
+            if (y + 1 < ny) f(rz + 1);
         }
     }
 }
 
-// Level 2, one workgroup per boundary between planes z-1 and z: every
-// touching run pair across the boundary names a pair of plane roots; the
-// distinct pairs are collected in an LDS hash set and only those are united
-// in the global forest (a giant component contributes a handful of pairs per
-// plane instead of one union per run).  A full set falls back to direct
-// global unions.
+// Level 1: one workgroup per segment [s0, s1).  Thread per run: the touching
+// runs of each earlier neighbour row are found by a binary search on their
+// ends; pairs inside the segment are united in LDS.  Then parent[run] = the
+// run number of its segment-local root.
 template <bool C26>
-__global__ __launch_bounds__(kBlock) void k_zlink(const uint32_t* __restrict__ run_off, const uint32_t* __restrict__ xs,
-                                                  const uint32_t* __restrict__ xe, uint32_t* parent, int64_t ny,
-                                                  int64_t nz, const DevState* S) {
-    __shared__ unsigned long long tab[kPairCap];
-    constexpr unsigned long long kEmpty = ~0ull;
+__global__ __launch_bounds__(kSegBlock) void k_seg_label(const uint32_t* __restrict__ run_off,
+                                                         const uint32_t* __restrict__ xs,
+                                                         const uint32_t* __restrict__ xe,
+                                                         const uint32_t* __restrict__ run_row, uint32_t* parent,
+                                                         uint32_t ny, double inv_ny, uint32_t G, uint32_t tparam,
+                                                         const DevState* S) {
+    __shared__ uint32_t lp[kSegCap];
     if (block_exit_l(S)) return;
-    for (int64_t z = 1 + blockIdx.x; z < nz; z += gridDim.x) {
-        for (int i = threadIdx.x; i < kPairCap; i += blockDim.x) tab[i] = kEmpty;
+    const uint32_t n = S->n_runs;
+    if (n == 0) return;
+    const uint32_t T = seg_runs(n, G, tparam);
+    const uint32_t nseg = (n + T - 1) / T;
+    for (uint32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
+        const uint32_t s0 = sg * T, s1 = (n - s0 < T) ? n : s0 + T, m = s1 - s0;
+        for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) lp[i] = i;
         __syncthreads();
-        auto link = [&](uint32_t a, uint32_t b) {
-            const uint32_t ra = parent[a], rb = parent[b];
-            if (ra == rb) return;
-            const unsigned long long key = ((unsigned long long)ra << 32) | rb;
-            uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 53) & (kPairCap - 1);
-            for (int pr = 0; pr < 16; ++pr) {
-                const unsigned long long old = atomicCAS(&tab[h], kEmpty, key);
-                if (old == kEmpty || old == key) return;
-                h = (h + 1) & (kPairCap - 1);
-            }
-            unite(parent, ra, rb);
-        };
-        for (int64_t y = threadIdx.x; y < ny; y += blockDim.x) {
-            const int64_t r = z * ny + y, rz = r - ny;
-            const uint32_t a0 = run_off[r], a1 = run_off[r + 1];
-            if (a0 == a1) continue;
-            for_touching<C26>(xs, xe, a0, a1, run_off[rz], run_off[rz + 1], link);
-            if (C26) {
-                if (y > 0) for_touching<C26>(xs, xe, a0, a1, run_off[rz - 1], run_off[rz], link);
-                if (y < ny - 1) for_touching<C26>(xs, xe, a0, a1, run_off[rz + 1], run_off[rz + 2], link);
-            }
+        for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+            const uint32_t a = s0 + i;
+            const uint32_t r = run_row[a];
+            uint32_t z, y;
+            row_zy(r, ny, inv_ny, z, y);
+            const uint32_t as = xs[a], ae = xe[a];
+            for_back_rows<C26>(r, z, y, ny, [&](uint32_t rb) {
+                uint32_t b0 = run_off[rb];
+                const uint32_t b1 = run_off[rb + 1];
+                if (b1 <= s0) return;  // the whole row lies in an earlier segment
+                if (b0 < s0) b0 = s0;
+                for (uint32_t b = first_touch<C26>(xe, b0, b1, as); b < b1; ++b) {
+                    const uint32_t bs = xs[b];
+                    if (C26 ? bs > ae : bs >= ae) break;
+                    lunite(lp, i, b - s0);
+                }
+            });
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < kPairCap; i += blockDim.x) {
+        for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+            uint32_t q = i;
+            while (lp[q] != q) q = lp[q];
+            parent[s0 + i] = s0 + q;
+        }
+        __syncthreads();  // lp is reused by the next segment
+    }
+}
+
+// Level 2: one workgroup per segment (the first has nothing before it).
+// Only runs whose rows lie within ny + 1 rows of the segment's first row can
+// touch an earlier segment.  Each touching pair (a, b), b < s0, names the
+// pair of their roots; the distinct pairs are collected in an LDS hash set
+// (a giant component contributes a handful instead of one per run) and
+// united in the global forest.  A full set falls back to direct unions.
+template <bool C26>
+__global__ __launch_bounds__(kBlock) void k_seg_cross(const uint32_t* __restrict__ run_off,
+                                                      const uint32_t* __restrict__ xs,
+                                                      const uint32_t* __restrict__ xe,
+                                                      const uint32_t* __restrict__ run_row, uint32_t* parent,
+                                                      uint32_t ny, double inv_ny, int64_t nrows, uint32_t G,
+                                                      uint32_t tparam, const DevState* S) {
+    __shared__ unsigned long long tab[kCrossCap];
+    constexpr unsigned long long kEmpty = ~0ull;
+    if (block_exit_l(S)) return;
+    const uint32_t n = S->n_runs;
+    if (n == 0) return;
+    const uint32_t T = seg_runs(n, G, tparam);
+    const uint32_t nseg = (n + T - 1) / T;
+    for (uint32_t sg = 1 + blockIdx.x; sg < nseg; sg += gridDim.x) {
+        const uint32_t s0 = sg * T, s1 = (n - s0 < T) ? n : s0 + T;
+        for (int i = threadIdx.x; i < kCrossCap; i += blockDim.x) tab[i] = kEmpty;
+        const uint32_t r0 = run_row[s0];  // rows after r0 hold only runs > s0
+        const int64_t rl = (int64_t)r0 + ny + 2;
+        uint32_t hend = s1;
+        if (rl < nrows && run_off[rl] < hend) hend = run_off[rl];
+        __syncthreads();
+        uint32_t last_a = kNone, last_b = kNone;
+        for (uint32_t a = s0 + threadIdx.x; a < hend; a += blockDim.x) {
+            const uint32_t r = run_row[a];
+            uint32_t z, y;
+            row_zy(r, ny, inv_ny, z, y);
+            const uint32_t as = xs[a], ae = xe[a];
+            uint32_t ra = kNone;
+            for_back_rows<C26>(r, z, y, ny, [&](uint32_t rb) {
+                if (rb > r0) return;
+                const uint32_t b0 = run_off[rb];
+                uint32_t b1 = run_off[rb + 1];
+                if (b1 > s0) b1 = s0;
+                if (b0 >= b1) return;
+                for (uint32_t b = first_touch<C26>(xe, b0, b1, as); b < b1; ++b) {
+                    const uint32_t bs = xs[b];
+                    if (C26 ? bs > ae : bs >= ae) break;
+                    if (ra == kNone) ra = parent[a];
+                    const uint32_t rbb = parent[b];
+                    if (ra == last_a && rbb == last_b) continue;
+                    last_a = ra;
+                    last_b = rbb;
+                    const unsigned long long key = ((unsigned long long)ra << 32) | rbb;
+                    uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 52) & (kCrossCap - 1);
+                    bool done = false;
+                    for (int pr = 0; pr < 8; ++pr) {
+                        const unsigned long long old = atomicCAS(&tab[h], kEmpty, key);
+                        if (old == kEmpty || old == key) {
+                            done = true;
+                            break;
+                        }
+                        h = (h + 1) & (kCrossCap - 1);
+                    }
+                    if (!done) unite(parent, ra, rbb);
+                }
+            });
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < kCrossCap; i += blockDim.x) {
             const unsigned long long key = tab[i];
             if (key != kEmpty) unite(parent, (uint32_t)(key >> 32), (uint32_t)key);
         }
-        __syncthreads();  // tab is reused by the next boundary
+        __syncthreads();  // tab is reused by the next segment
     }
 }
 
 hipError_t launch_union(const LaunchCtx& lc, const Geom& g, const Layout& L, int conn) {
     timer_begin(lc.timer, ST_UNION, lc.stream);
-    const dim3 gp(grid_for(g.nz, 1, lc.grid_stream)), gz(grid_for(g.nz - 1, 1, lc.grid_stream)), blk(kBlock);
+    const uint32_t G = (uint32_t)lc.seg_grid;
+    const uint32_t ny = (uint32_t)g.ny;
+    const double inv_ny = 1.0 / (double)g.ny;
+    const uint32_t tp = (uint32_t)lc.seg_runs;
+    const dim3 grid(G);
     if (conn == 26) {
-        hipLaunchKernelGGL(k_plane_label<true>, gp, blk, 0, lc.stream, (const uint32_t*)L.run_off,
-                           (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, L.parent, g.ny, g.nz,
-                           (const DevState*)L.S);
-        if (g.nz > 1)
-            hipLaunchKernelGGL(k_zlink<true>, gz, blk, 0, lc.stream, (const uint32_t*)L.run_off,
-                               (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, L.parent, g.ny, g.nz,
-                               (const DevState*)L.S);
+        hipLaunchKernelGGL(k_seg_label<true>, grid, dim3(kSegBlock), 0, lc.stream, (const uint32_t*)L.run_off,
+                           (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, (const uint32_t*)L.run_row,
+                           L.parent, ny, inv_ny, G, tp, (const DevState*)L.S);
+        hipLaunchKernelGGL(k_seg_cross<true>, grid, dim3(kBlock), 0, lc.stream, (const uint32_t*)L.run_off,
+                           (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, (const uint32_t*)L.run_row,
+                           L.parent, ny, inv_ny, g.nrows, G, tp, (const DevState*)L.S);
     } else {
-        hipLaunchKernelGGL(k_plane_label<false>, gp, blk, 0, lc.stream, (const uint32_t*)L.run_off,
-                           (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, L.parent, g.ny, g.nz,
-                           (const DevState*)L.S);
-        if (g.nz > 1)
-            hipLaunchKernelGGL(k_zlink<false>, gz, blk, 0, lc.stream, (const uint32_t*)L.run_off,
-                               (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, L.parent, g.ny, g.nz,
-                               (const DevState*)L.S);
+        hipLaunchKernelGGL(k_seg_label<false>, grid, dim3(kSegBlock), 0, lc.stream, (const uint32_t*)L.run_off,
+                           (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, (const uint32_t*)L.run_row,
+                           L.parent, ny, inv_ny, G, tp, (const DevState*)L.S);
+        hipLaunchKernelGGL(k_seg_cross<false>, grid, dim3(kBlock), 0, lc.stream, (const uint32_t*)L.run_off,
+                           (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, (const uint32_t*)L.run_row,
+                           L.parent, ny, inv_ny, g.nrows, G, tp, (const DevState*)L.S);
     }
     timer_end(lc.timer, ST_UNION, lc.stream);
     return hipGetLastError();
@@ -514,8 +596,8 @@ hipError_t launch_flatten(const LaunchCtx& lc, const Layout& L) {
 
 // ------------------------------------------------------- component stats
 
-constexpr int kRowsPerThread = 4;
-constexpr int kSlots = 8;
+constexpr int kStatRuns = 4;     // consecutive runs per thread and round
+constexpr int kStatTab = 1024;   // LDS table of component accumulators per workgroup (36 KB)
 
 struct Acc {
     unsigned long long size;
@@ -539,119 +621,179 @@ __device__ __forceinline__ void acc_flush_global(roix_component* comps, uint32_t
     atomicMax(&c->z1, a.z1);
 }
 
-// One thread per row: the entry of every component whose root run lies in
-// the row (label = first voxel of the root run).
-__global__ __launch_bounds__(kBlock) void k_comp_init(const uint32_t* __restrict__ run_off,
-                                                      const uint32_t* __restrict__ xs, const uint32_t* parent,
-                                                      const uint32_t* __restrict__ comp_id, int64_t nx, int64_t nrows,
+struct StatTab {
+    uint32_t key[kStatTab];
+    unsigned long long size[kStatTab];
+    uint32_t bb[6][kStatTab];
+};
+
+// Add an accumulator to the workgroup table (open addressing, a few probes),
+// or straight to the component when the table has no room for the root.
+__device__ __forceinline__ void tab_add(StatTab& t, uint32_t root, const Acc& a, roix_component* comps,
+                                        const uint32_t* comp_id) {
+    uint32_t h = (root * 2654435761u) >> 22;  // 10 bits
+    for (int pr = 0; pr < 8; ++pr) {
+        const uint32_t old = atomicCAS(&t.key[h], kNone, root);
+        if (old == kNone || old == root) {
+            atomicAdd(&t.size[h], a.size);
+            atomicMin(&t.bb[0][h], a.x0);
+            atomicMax(&t.bb[1][h], a.x1);
+            atomicMin(&t.bb[2][h], a.y0);
+            atomicMax(&t.bb[3][h], a.y1);
+            atomicMin(&t.bb[4][h], a.z0);
+            atomicMax(&t.bb[5][h], a.z1);
+            return;
+        }
+        h = (h + 1) & (kStatTab - 1);
+    }
+    acc_flush_global(comps, comp_id[root], a);
+}
+
+// Called by every lane of the wave: the lanes with `pred` hand in their
+// accumulator.  Those that share the first such lane's root (a giant
+// component, typically) are reduced across the wave into one table update;
+// the others (usually distinct small components) go in one by one.
+__device__ __forceinline__ void wave_flush(bool pred, uint32_t root, const Acc& a, StatTab& t, roix_component* comps,
+                                           const uint32_t* comp_id) {
+    const uint64_t m = __ballot(pred);
+    if (!m) return;
+    const int lane = threadIdx.x % kWave;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    const uint32_t lr = __builtin_amdgcn_readlane(root, leader);
+    const bool match = pred && root == lr;
+    Acc r;
+    r.size = wave_sum(match ? a.size : 0ull);
+    r.x0 = wave_min(match ? a.x0 : 0xFFFFFFFFu);
+    r.x1 = wave_max(match ? a.x1 : 0u);
+    r.y0 = wave_min(match ? a.y0 : 0xFFFFFFFFu);
+    r.y1 = wave_max(match ? a.y1 : 0u);
+    r.z0 = wave_min(match ? a.z0 : 0xFFFFFFFFu);
+    r.z1 = wave_max(match ? a.z1 : 0u);
+    if (lane == leader) tab_add(t, lr, r, comps, comp_id);
+    if (pred && !match) tab_add(t, root, a, comps, comp_id);
+}
+
+// One thread per root run: the entry of its component (label = first voxel
+// of the root run, i.e. of the component).
+__global__ __launch_bounds__(kBlock) void k_comp_init(const uint32_t* __restrict__ xs,
+                                                      const uint32_t* __restrict__ run_row,
+                                                      const uint32_t* __restrict__ parent,
+                                                      const uint32_t* __restrict__ comp_id, int64_t nx,
                                                       roix_component* comps, const DevState* S) {
     if (thread_exit(S)) return;
-    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += nthreads) {
-        for (uint32_t i = run_off[r]; i < run_off[r + 1]; ++i) {
-            if (parent[i] != i) continue;
-            roix_component* c = comps + comp_id[i];
-            c->label = (uint64_t)r * (uint64_t)nx + xs[i];
-            c->size = 0;
-            c->x0 = c->y0 = c->z0 = 0xFFFFFFFFu;
-            c->x1 = c->y1 = c->z1 = 0u;
-            c->kept = 0u;
-            c->pad = 0u;
-        }
+    const uint32_t n = S->n_runs;
+    const uint32_t nthreads = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += nthreads) {
+        if (parent[i] != i) continue;
+        roix_component* c = comps + comp_id[i];
+        c->label = (uint64_t)run_row[i] * (uint64_t)nx + xs[i];
+        c->size = 0;
+        c->x0 = c->y0 = c->z0 = 0xFFFFFFFFu;
+        c->x1 = c->y1 = c->z1 = 0u;
+        c->kept = 0u;
+        c->pad = 0u;
     }
 }
 
-// Per-thread accumulation over kRowsPerThread rows, then a small LDS table of
-// kSlots roots per workgroup so that a giant component costs one set of
-// global atomics per workgroup instead of one per run.
-__global__ __launch_bounds__(kBlock) void k_comp_stats(const uint32_t* __restrict__ run_off,
-                                                       const uint32_t* __restrict__ xs, const uint32_t* __restrict__ xe,
+// Size and box of every component.  Each workgroup takes a contiguous range
+// of runs; a thread accumulates kStatRuns consecutive runs while their root
+// stays the same, and hands the accumulator to the workgroup table through
+// wave_flush at uniform points.  The table goes to the components once at
+// the end, so a giant component costs one set of global atomics per
+// workgroup.
+__global__ __launch_bounds__(kBlock) void k_comp_stats(const uint32_t* __restrict__ xs,
+                                                       const uint32_t* __restrict__ xe,
+                                                       const uint32_t* __restrict__ run_row,
                                                        const uint32_t* __restrict__ parent,
-                                                       const uint32_t* __restrict__ comp_id, int64_t ny, int64_t nrows,
-                                                       roix_component* comps, const DevState* S) {
-    __shared__ uint32_t s_root[kSlots];
-    __shared__ unsigned long long s_size[kSlots];
-    __shared__ uint32_t s_bb[kSlots][6];
-    if (threadIdx.x < kSlots) {
-        s_root[threadIdx.x] = kNone;
-        s_size[threadIdx.x] = 0;
-        s_bb[threadIdx.x][0] = s_bb[threadIdx.x][2] = s_bb[threadIdx.x][4] = 0xFFFFFFFFu;
-        s_bb[threadIdx.x][1] = s_bb[threadIdx.x][3] = s_bb[threadIdx.x][5] = 0u;
+                                                       const uint32_t* __restrict__ comp_id, uint32_t ny,
+                                                       double inv_ny, roix_component* comps, const DevState* S) {
+    __shared__ StatTab t;
+    for (int i = threadIdx.x; i < kStatTab; i += blockDim.x) {
+        t.key[i] = kNone;
+        t.size[i] = 0;
+        t.bb[0][i] = t.bb[2][i] = t.bb[4][i] = 0xFFFFFFFFu;
+        t.bb[1][i] = t.bb[3][i] = t.bb[5][i] = 0u;
     }
     if (block_exit_l(S)) return;
-    uint32_t cur = kNone;
-    Acc a;
-    acc_reset(a);
-    const int64_t r0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRowsPerThread;
-    for (int rr = 0; rr < kRowsPerThread; ++rr) {
-        const int64_t r = r0 + rr;
-        if (r >= nrows) break;
-        const uint32_t z = (uint32_t)(r / ny), y = (uint32_t)(r - (int64_t)z * ny);
-        for (uint32_t i = run_off[r]; i < run_off[r + 1]; ++i) {
-            const uint32_t root = parent[i];
-            if (root != cur) {
-                if (cur != kNone) acc_flush_global(comps, comp_id[cur], a);
-                cur = root;
+    const uint32_t n = S->n_runs;
+    constexpr uint32_t kRound = (uint32_t)kBlock * kStatRuns;
+    uint64_t per = ((uint64_t)n + gridDim.x - 1) / gridDim.x;
+    per = (per + kRound - 1) / kRound * kRound;
+    const uint64_t b0 = (uint64_t)blockIdx.x * per;
+    const uint64_t b1 = b0 + per < (uint64_t)n ? b0 + per : (uint64_t)n;
+    for (uint64_t base = b0; base < b1; base += kRound) {
+        const uint64_t i0 = base + (uint64_t)threadIdx.x * kStatRuns;
+        uint32_t pr[kStatRuns], sx[kStatRuns], ex[kStatRuns], rw[kStatRuns];
+        if (i0 + kStatRuns <= b1) {  // i0 is a multiple of 4: one 16-byte load per array
+            const uint4 p4 = *reinterpret_cast<const uint4*>(parent + i0);
+            const uint4 s4 = *reinterpret_cast<const uint4*>(xs + i0);
+            const uint4 e4 = *reinterpret_cast<const uint4*>(xe + i0);
+            const uint4 r4 = *reinterpret_cast<const uint4*>(run_row + i0);
+            pr[0] = p4.x, pr[1] = p4.y, pr[2] = p4.z, pr[3] = p4.w;
+            sx[0] = s4.x, sx[1] = s4.y, sx[2] = s4.z, sx[3] = s4.w;
+            ex[0] = e4.x, ex[1] = e4.y, ex[2] = e4.z, ex[3] = e4.w;
+            rw[0] = r4.x, rw[1] = r4.y, rw[2] = r4.z, rw[3] = r4.w;
+        } else {
+#pragma unroll
+            for (int k = 0; k < kStatRuns; ++k) {
+                const bool in = i0 + k < b1;
+                pr[k] = in ? parent[i0 + k] : kNone;
+                sx[k] = in ? xs[i0 + k] : 0u;
+                ex[k] = in ? xe[i0 + k] : 0u;
+                rw[k] = in ? run_row[i0 + k] : 0u;
+            }
+        }
+        uint32_t cur = kNone;
+        Acc a;
+        acc_reset(a);
+#pragma unroll
+        for (int k = 0; k <= kStatRuns; ++k) {
+            const uint32_t root = k < kStatRuns ? pr[k] : kNone;
+            const bool fl = cur != kNone && root != cur;
+            wave_flush(fl, cur, a, t, comps, comp_id);
+            if (fl) {
+                cur = kNone;
                 acc_reset(a);
             }
-            const uint32_t s = xs[i], e = xe[i];
-            a.size += e - s;
-            a.x0 = s < a.x0 ? s : a.x0;
-            a.x1 = e > a.x1 ? e : a.x1;
-            a.y0 = y < a.y0 ? y : a.y0;
-            a.y1 = y + 1 > a.y1 ? y + 1 : a.y1;
-            a.z0 = z < a.z0 ? z : a.z0;
-            a.z1 = z + 1 > a.z1 ? z + 1 : a.z1;
-        }
-    }
-    if (cur != kNone) {
-        int slot = -1;
-        const uint32_t h = cur % kSlots;
-        for (int pr = 0; pr < kSlots; ++pr) {
-            const uint32_t sl = (h + pr) % kSlots;
-            const uint32_t old = atomicCAS(&s_root[sl], kNone, cur);
-            if (old == kNone || old == cur) {
-                slot = (int)sl;
-                break;
+            if (root != kNone) {
+                cur = root;
+                uint32_t z, y;
+                row_zy(rw[k], ny, inv_ny, z, y);
+                a.size += ex[k] - sx[k];
+                a.x0 = sx[k] < a.x0 ? sx[k] : a.x0;
+                a.x1 = ex[k] > a.x1 ? ex[k] : a.x1;
+                a.y0 = y < a.y0 ? y : a.y0;
+                a.y1 = y + 1 > a.y1 ? y + 1 : a.y1;
+                a.z0 = z < a.z0 ? z : a.z0;
+                a.z1 = z + 1 > a.z1 ? z + 1 : a.z1;
             }
-        }
-        if (slot >= 0) {
-            atomicAdd(&s_size[slot], a.size);
-            atomicMin(&s_bb[slot][0], a.x0);
-            atomicMax(&s_bb[slot][1], a.x1);
-            atomicMin(&s_bb[slot][2], a.y0);
-            atomicMax(&s_bb[slot][3], a.y1);
-            atomicMin(&s_bb[slot][4], a.z0);
-            atomicMax(&s_bb[slot][5], a.z1);
-        } else {
-            acc_flush_global(comps, comp_id[cur], a);
         }
     }
     __syncthreads();
-    if (threadIdx.x < kSlots && s_root[threadIdx.x] != kNone) {
-        Acc t;
-        t.size = s_size[threadIdx.x];
-        t.x0 = s_bb[threadIdx.x][0];
-        t.x1 = s_bb[threadIdx.x][1];
-        t.y0 = s_bb[threadIdx.x][2];
-        t.y1 = s_bb[threadIdx.x][3];
-        t.z0 = s_bb[threadIdx.x][4];
-        t.z1 = s_bb[threadIdx.x][5];
-        acc_flush_global(comps, comp_id[s_root[threadIdx.x]], t);
+    for (int i = threadIdx.x; i < kStatTab; i += blockDim.x) {
+        const uint32_t key = t.key[i];
+        if (key == kNone) continue;
+        Acc e;
+        e.size = t.size[i];
+        e.x0 = t.bb[0][i];
+        e.x1 = t.bb[1][i];
+        e.y0 = t.bb[2][i];
+        e.y1 = t.bb[3][i];
+        e.z0 = t.bb[4][i];
+        e.z1 = t.bb[5][i];
+        acc_flush_global(comps, comp_id[key], e);
     }
 }
 
 hipError_t launch_comp_stats(const LaunchCtx& lc, const Geom& g, const Layout& L, roix_component* comps) {
     timer_begin(lc.timer, ST_COMPS, lc.stream);
-    hipLaunchKernelGGL(k_comp_init, dim3(grid_for(g.nrows, kBlock, 16384)), dim3(kBlock), 0, lc.stream,
-                       (const uint32_t*)L.run_off, (const uint32_t*)L.run_xs, (const uint32_t*)L.parent,
-                       (const uint32_t*)L.comp_id, g.nx, g.nrows, comps, (const DevState*)L.S);
-    int64_t per_block = (int64_t)kBlock * kRowsPerThread;
-    int64_t grid = (g.nrows + per_block - 1) / per_block;
-    hipLaunchKernelGGL(k_comp_stats, dim3((unsigned)(grid < 1 ? 1 : grid)), dim3(kBlock), 0, lc.stream,
-                       (const uint32_t*)L.run_off, (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe,
-                       (const uint32_t*)L.parent, (const uint32_t*)L.comp_id, g.ny, g.nrows, comps,
-                       (const DevState*)L.S);
+    hipLaunchKernelGGL(k_comp_init, dim3(grid_for((int64_t)L.run_cap, kBlock, lc.grid_stream)), dim3(kBlock), 0,
+                       lc.stream, (const uint32_t*)L.run_xs, (const uint32_t*)L.run_row, (const uint32_t*)L.parent,
+                       (const uint32_t*)L.comp_id, g.nx, comps, (const DevState*)L.S);
+    hipLaunchKernelGGL(k_comp_stats, dim3(grid_for((int64_t)L.run_cap, kBlock * kStatRuns, lc.grid_stream / 2)),
+                       dim3(kBlock), 0, lc.stream, (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe,
+                       (const uint32_t*)L.run_row, (const uint32_t*)L.parent, (const uint32_t*)L.comp_id,
+                       (uint32_t)g.ny, 1.0 / (double)g.ny, comps, (const DevState*)L.S);
     timer_end(lc.timer, ST_COMPS, lc.stream);
     return hipGetLastError();
 }
