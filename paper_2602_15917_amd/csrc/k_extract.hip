@@ -104,6 +104,7 @@ struct EmitOut {
     uint64_t stream_cap;  // bytes
     float* outl;
     uint64_t outl_cap;
+    uint64_t nvox;  // voxels of the input (bound of the whole-quad loads)
 };
 
 template <int B>
@@ -145,11 +146,6 @@ __global__ __launch_bounds__(kBlock) void k_emit_index(Layout L, int64_t nrows) 
     }
 }
 
-// Codes of one chunk [c0, c1) whose spans are rows j0 .. j0 + nr - 1 of the
-// span list, nr <= 64: lane l holds span j0 + l (first code, voxel offset).
-// Each 64-code slice is consecutive codes; the uniform cursor jr walks the
-// span starts falling inside the slice, so every lane knows its voxel with
-// a few scalar reads, and all loads of a step are issued before any use.
 // Four consecutive input values starting at voxel v.  float: one 16-byte
 // load (the ISA needs only 4-byte alignment for multi-dword loads).  uint16:
 // one 12-byte load from the 4-byte-aligned voxel at or before v.
@@ -161,6 +157,12 @@ __device__ __forceinline__ void load_quad(const float* in, uint64_t v, float (&x
     x[3] = __uint_as_float(q.w);
 }
 typedef unsigned int v3u32_t __attribute__((ext_vector_type(3)));
+// Elements a whole-quad load at voxel v reads, counted from v: a quad is
+// loaded whole only when v + quad_reach <= the voxel count.
+template <typename T>
+__device__ __forceinline__ constexpr uint64_t quad_reach() {
+    return sizeof(T) == 4 ? 4 : 6;
+}
 __device__ __forceinline__ void load_quad(const uint16_t* in, uint64_t v, float (&x)[4]) {
     const uint64_t v0 = v & ~1ull;
     const v3u32_t q = __builtin_nontemporal_load(reinterpret_cast<const v3u32_t*>(in + v0));
@@ -243,7 +245,7 @@ __device__ __forceinline__ void emit_chunk_fast(const T* __restrict__ in, int64_
 #pragma unroll
         for (int k = 0; k < kEmitSlices; ++k) {
             const uint64_t t = t0 + (uint64_t)k * kEmitSlice;
-            if (!((split >> k) & 1u) && t + 3 < c1) {
+            if (!((split >> k) & 1u) && t + 3 < c1 && t + ok[k] + quad_reach<T>() <= o.nvox) {
                 load_quad(in, t + ok[k], xv[k]);
             } else {
                 // a span starts inside this quad (or the chunk ends in it):
@@ -313,41 +315,135 @@ __device__ __forceinline__ void emit_chunk_fast(const T* __restrict__ in, int64_
     }
 }
 
-// Chunks touching more than 64 spans (short spans): one span at a time.
+__device__ __forceinline__ uint32_t shfl32(uint32_t v, int src) { return (uint32_t)__shfl((int)v, src); }
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
+    const uint32_t lo = shfl32((uint32_t)v, src), hi = shfl32((uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// The last lane whose span starts at or before window-relative code `rel`
+// (starts increase over the lanes; lanes past the window hold kNone).  Six
+// cross-lane reads; every lane of the wave must execute it.
+__device__ __forceinline__ int span_lane(uint32_t rs, uint32_t rel) {
+    int pos = 0;
+#pragma unroll
+    for (int st = 32; st > 0; st >>= 1)
+        if (shfl32(rs, pos + st) <= rel) pos += st;
+    return pos;
+}
+
+constexpr int kFastSpans = 16;  // chunks touching more spans take emit_chunk_many
+constexpr int kManyQuads = 4;   // quads per lane and round in emit_chunk_many
+
+// Chunks of short spans.  The spans are taken 64 at a time (a window, lane l
+// holding span jw + l); the window covers the codes from its first span's
+// start to its last span's end.  Each lane takes quads of 4 consecutive
+// codes; a binary search over the lanes' span starts gives a quad's span,
+// and a quad inside one span is one 16-byte load.  Quads that a span start
+// splits, or that the window's ends cut, go code by code.
 template <typename T, int B>
-__device__ __forceinline__ void emit_chunk_slow(const T* __restrict__ in, int64_t nx, const Layout& L,
+__device__ __forceinline__ void emit_chunk_many(const T* __restrict__ in, int64_t nx, const Layout& L,
                                                 const EmitOut& o, uint64_t c0, uint64_t c1, uint32_t j0, uint32_t j1,
                                                 bool& trunc) {
     using C = typename CodeT<B>::type;
+    constexpr int U = kManyQuads;
     const DevState* S = L.S;
     const int lane = threadIdx.x % kWave;
     const float r = S->r, w = S->w, eb32 = S->eb32;
     const int32_t qmin = S->qmin;
     const uint32_t esc = S->esc;
     C* codes = reinterpret_cast<C*>(o.stream);
-    for (uint32_t j = j0; j <= j1; ++j) {
-        const uint32_t rid = L.nz_rows[j];
-        const uint64_t code0 = L.row_packed[rid] & kLenMask;
-        const uint64_t code1 = code0 + (L.row_xe[rid] - L.row_xs[rid]);
-        const uint64_t off = (uint64_t)rid * (uint64_t)nx + L.row_xs[rid] - code0;
-        const uint64_t lo = code0 > c0 ? code0 : c0, hi = code1 < c1 ? code1 : c1;
-        uint32_t cnt = 0;
-        for (uint64_t cb = lo; cb < hi; cb += kWave) {
-            const uint64_t c = cb + lane;
-            bool isout = false;
-            if (c < hi) {
-                const float x = (float)ld_stream(in + (c + off));
-                const int32_t q = qcode(x, r);
-                isout = outlier(x, q, w, eb32);
-                const uint32_t u = isout ? esc : (uint32_t)(q - qmin);
-                if ((c + 1) * (uint64_t)B <= o.stream_cap)
-                    codes[c] = (C)u;
-                else
-                    trunc = true;
-            }
-            cnt += (uint32_t)__popcll(__ballot(isout));
+    const bool fits = c1 * (uint64_t)B <= o.stream_cap;
+    for (uint32_t jw = j0; jw <= j1; jw += kWave) {
+        const uint32_t nw = j1 - jw + 1 < (uint32_t)kWave ? j1 - jw + 1 : (uint32_t)kWave;
+        uint32_t rid = 0;
+        uint64_t cs = ~0ull, ce = 0, off = 0;
+        if ((uint32_t)lane < nw) {
+            rid = L.nz_rows[jw + lane];
+            const uint32_t xs = L.row_xs[rid], xe = L.row_xe[rid];
+            cs = L.row_packed[rid] & kLenMask;
+            ce = cs + (xe - xs);
+            off = (uint64_t)rid * (uint64_t)nx + xs - cs;  // voxel = code + off
         }
-        if (cnt && lane == 0) atomicAdd((unsigned long long*)&L.row_outl[rid], (unsigned long long)cnt);
+        const uint64_t cs0 = readlane64(cs, 0);
+        const uint64_t wlo = cs0 > c0 ? cs0 : c0;
+        const uint64_t cel = readlane64(ce, nw - 1);
+        const uint64_t whi = cel < c1 ? cel : c1;
+        if (whi <= wlo) continue;
+        const uint32_t rs = (uint32_t)lane >= nw ? kNone : (cs <= wlo ? 0u : (uint32_t)(cs - wlo));
+        for (uint64_t tq = wlo & ~3ull; tq < whi; tq += 4ull * kWave * U) {
+            float x[U][4];
+            int pos[U];
+            bool full[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint64_t t = tq + 4ull * (uint64_t)(u * kWave + lane);
+                const uint32_t rel = t > wlo ? (uint32_t)(t - wlo) : 0u;
+                pos[u] = span_lane(rs, rel);
+                const uint32_t nxt = shfl32(rs, pos[u] < kWave - 1 ? pos[u] + 1 : kWave - 1);
+                const uint64_t ot = shfl64(off, pos[u]);
+                full[u] = t >= wlo && t + 4 <= whi && (pos[u] == kWave - 1 || nxt > rel + 3) &&
+                          t + ot + quad_reach<T>() <= o.nvox;
+                if (full[u]) load_quad(in, t + ot, x[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (!__ballot(!full[u])) continue;  // uniform
+                const uint64_t t = tq + 4ull * (uint64_t)(u * kWave + lane);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint64_t c = t + j;
+                    const uint32_t rel = c > wlo ? (uint32_t)(c - wlo) : 0u;
+                    const uint64_t oc = shfl64(off, span_lane(rs, rel));
+                    if (!full[u]) x[u][j] = (c >= wlo && c < whi) ? (float)ld_stream(in + (c + oc)) : 0.0f;
+                }
+            }
+            uint32_t outm[U];
+            uint32_t anyout = 0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint64_t t = tq + 4ull * (uint64_t)(u * kWave + lane);
+                uint32_t cu[4];
+                uint32_t om = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float xv = x[u][j];
+                    const int32_t q = qcode(xv, r);
+                    const bool valid = full[u] || (t + j >= wlo && t + j < whi);
+                    const bool ob = valid && outlier(xv, q, w, eb32);
+                    om |= ob ? (1u << j) : 0u;
+                    cu[j] = ob ? esc : (uint32_t)(q - qmin);
+                }
+                outm[u] = om;
+                anyout |= om;
+                if (full[u] && (fits || (t + 4) * (uint64_t)B <= o.stream_cap)) {
+                    store_quad<B>(o.stream, t, cu);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const uint64_t c = t + j;
+                        if (c < wlo || c >= whi) continue;
+                        if ((c + 1) * (uint64_t)B <= o.stream_cap)
+                            codes[c] = (C)cu[j];
+                        else
+                            trunc = true;
+                    }
+                }
+            }
+            if (__ballot(anyout != 0)) {  // rare: per-span outlier counts
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint64_t t = tq + 4ull * (uint64_t)(u * kWave + lane);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const uint64_t c = t + j;
+                        const uint32_t rel = c > wlo ? (uint32_t)(c - wlo) : 0u;
+                        const uint32_t rc = shfl32(rid, span_lane(rs, rel));
+                        if ((outm[u] >> j) & 1u) atomicAdd((unsigned long long*)&L.row_outl[rc], 1ull);
+                    }
+                }
+            }
+        }
     }
 }
 
@@ -365,10 +461,10 @@ __device__ __forceinline__ void emit_chunks(const T* __restrict__ in, int64_t nx
         const uint64_t c1 = c0 + kEmitChunk < n_codes ? c0 + kEmitChunk : n_codes;
         const uint32_t j0 = L.chunk_row[q];
         const uint32_t j1 = q + 1 < nchunks ? L.chunk_row[q + 1] : n_rows - 1;
-        if (j1 - j0 < (uint32_t)kWave)
+        if (j1 - j0 < (uint32_t)kFastSpans)
             emit_chunk_fast<T, B>(in, nx, L, o, c0, c1, j0, j1 - j0 + 1, trunc);
         else
-            emit_chunk_slow<T, B>(in, nx, L, o, c0, c1, j0, j1, trunc);
+            emit_chunk_many<T, B>(in, nx, L, o, c0, c1, j0, j1, trunc);
     }
 }
 
@@ -486,6 +582,7 @@ hipError_t launch_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, cons
     o.stream_cap = out->d_stream ? (uint64_t)out->stream_cap_bytes : 0;
     o.outl = out->d_outliers;
     o.outl_cap = out->d_outliers ? (uint64_t)out->outliers_cap : 0;
+    o.nvox = g.N;
     const dim3 block(kBlock);
     const dim3 grid_rows_t(grid_rows(g.nrows, kBlock, lc.grid_stream));
     const dim3 grid_waves(lc.grid_stream);

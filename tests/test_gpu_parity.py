@@ -70,11 +70,64 @@ def test_noise_many_components(env, seed, conn):
 
 @pytest.mark.parametrize("conn", [6, 26])
 def test_dense_planes_fallback(env, conn):
-    # z-planes with more runs than the per-plane LDS labelling holds, and more distinct
-    # plane-root pairs per boundary than the pair table holds: the global fallbacks
+    # z-planes of ~45k runs: many segments per plane, and more distinct root pairs
+    # across segment boundaries than the pair table holds (direct global unions)
     vol = synth.normal((4, 300, 301), 6000 + conn, 0.5, 0.1)
     for keep, ms in (("min_size", 1), ("largest", 1)):
         run_case(env, f"dense planes conn={conn}", vol, "abs", 1e-3, synth.Criterion("fixed", 0.5, conn, keep, ms))
+
+
+@pytest.mark.parametrize("seg_runs,seg_grid", [(256, 3), (2048, 1), (16384, 512), (0, 7), (768, 64)])
+def test_segment_parameters(env, seg_runs, seg_grid):
+    # segments of any size cut rows and planes anywhere; the labels must not change
+    ctx, roix, torch = env
+    ctx.set_param("seg_runs", seg_runs)
+    ctx.set_param("seg_grid", seg_grid)
+    try:
+        vol = synth.normal((9, 41, 133), 6100, 0.5, 0.1)
+        for conn in (6, 26):
+            run_case(env, f"segments T={seg_runs} G={seg_grid} noise", vol, "abs", 1e-3,
+                     synth.Criterion("fixed", 0.55, conn, "min_size", 2))
+        w = synth.config1(n=96)
+        run_case(env, f"segments T={seg_runs} G={seg_grid} cylinder", w.volume, w.eb_mode, w.eb_value, w.criterion)
+    finally:
+        ctx.set_param("seg_runs", 0)
+        ctx.set_param("seg_grid", ctx.get_param("compute_units") * 2)
+
+
+def short_span_volume(shape, seed, max_len, dtype):
+    """One object run per row at a random place, 1..max_len voxels long (row
+    spans of a few codes, many span starts inside one 4-code quad), and a
+    kept voxel at the volume's very last position."""
+    nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    lo, hi = (0.0, 1.0) if dtype == np.float32 else (100, 40000)
+    vol = np.full(shape, lo, dtype=np.float64)
+    vol += rng.random(shape) * (hi - lo) * 0.2
+    ln = rng.integers(1, max_len + 1, size=(nz, ny))
+    x0 = rng.integers(0, nx, size=(nz, ny))
+    for z in range(nz):
+        for y in range(ny):
+            if rng.random() < 0.9:
+                a = min(x0[z, y], nx - ln[z, y])
+                vol[z, y, a:a + ln[z, y]] = hi * (0.8 + 0.2 * rng.random())
+    vol[-1, -1, -1] = hi
+    return vol.astype(dtype)
+
+
+@pytest.mark.parametrize("max_len", [1, 3, 9, 40])
+@pytest.mark.parametrize("dt", ["f32", "u16"])
+def test_short_spans(env, max_len, dt):
+    dtype = np.float32 if dt == "f32" else np.uint16
+    thr = 0.5 if dt == "f32" else 20000.0
+    # f32: 16-bit codes, 16-bit codes with escapes, 32-bit codes with escapes;
+    # u16: 16- and 8-bit codes
+    ebs = (1e-3, 1e-5, 1e-6) if dt == "f32" else (2.0, 200.0)
+    for shape in ((20, 300, 257), (3, 101, 64)):
+        vol = short_span_volume(shape, 6200 + max_len, max_len, dtype)
+        for eb in ebs:
+            run_case(env, f"short spans {dt} len<={max_len} {shape} eb={eb}", vol, "abs", eb,
+                     synth.Criterion("fixed", thr, 6, "min_size", 1))
 
 
 def test_uint16_rings_small(env):
