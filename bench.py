@@ -142,9 +142,10 @@ def bench_batched(args):
         items.append((t, w.eb_mode, w.eb_value, crit, out))
         need = max(need, roix.scratch_bytes(dims, roix.F32, crit))
         w.volume = None
-    streams = 4
+    streams = args.batch_streams
     ctx = roix.Context(0, need * streams)
     ctx.set_param("batch_streams", streams)
+    ctx.set_param("batch_graph", args.batch_graph)
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
@@ -179,7 +180,7 @@ def bench_batched(args):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"batched: {len(items)} f32 volumes, sides U{{64..512}}, 1-8 ellipsoids, "
                                f"eb in {{1e-3,1e-4,1e-5}}, Otsu, 6-connectivity, components >= 64",
-                   "input_bytes": total, "batch_streams": streams, "graph": True},
+                   "input_bytes": total, "batch_streams": streams, "graph": bool(args.batch_graph)},
         "plain_sequential_ms": round(res["plain"], 4),
         "plain_sequential_gbs": round(total / (res["plain"] * 1e-3) / 1e9, 2),
         "batched_over_plain": round(res["plain"] / res["batched"], 3),
@@ -203,6 +204,9 @@ def main():
     ap.add_argument("--workload", choices=["plain", "batched"], default="plain",
                     help="plain: the 1024^3 volume (default); batched: 64 uneven volumes in one graph launch")
     ap.add_argument("--batch-volumes", type=int, default=64)
+    ap.add_argument("--batch-streams", type=int, default=4, help="concurrent streams of the batched path")
+    ap.add_argument("--batch-graph", type=int, default=1, choices=[0, 1],
+                    help="1: capture the batch into a HIP graph and replay it; 0: launch eagerly")
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary)

@@ -373,29 +373,36 @@ __device__ __forceinline__ void emit_chunk_many(const T* __restrict__ in, int64_
         const uint32_t rs = (uint32_t)lane >= nw ? kNone : (cs <= wlo ? 0u : (uint32_t)(cs - wlo));
         for (uint64_t tq = wlo & ~3ull; tq < whi; tq += 4ull * kWave * U) {
             float x[U][4];
-            int pos[U];
             bool full[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const uint64_t t = tq + 4ull * (uint64_t)(u * kWave + lane);
                 const uint32_t rel = t > wlo ? (uint32_t)(t - wlo) : 0u;
-                pos[u] = span_lane(rs, rel);
-                const uint32_t nxt = shfl32(rs, pos[u] < kWave - 1 ? pos[u] + 1 : kWave - 1);
-                const uint64_t ot = shfl64(off, pos[u]);
-                full[u] = t >= wlo && t + 4 <= whi && (pos[u] == kWave - 1 || nxt > rel + 3) &&
-                          t + ot + quad_reach<T>() <= o.nvox;
-                if (full[u]) load_quad(in, t + ot, x[u]);
-            }
+                // span of the quad's first code, and the next three span starts
+                // (a span holds at least one code, so a quad meets at most four)
+                const int p0 = span_lane(rs, rel);
+                uint32_t sn[3];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (!__ballot(!full[u])) continue;  // uniform
-                const uint64_t t = tq + 4ull * (uint64_t)(u * kWave + lane);
+                for (int k = 0; k < 3; ++k) {
+                    const uint32_t v = shfl32(rs, p0 + 1 + k < kWave ? p0 + 1 + k : kWave - 1);
+                    sn[k] = p0 + 1 + k < kWave ? v : kNone;
+                }
+                uint64_t oc[4];
+                bool vc[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const uint64_t c = t + j;
-                    const uint32_t rel = c > wlo ? (uint32_t)(c - wlo) : 0u;
-                    const uint64_t oc = shfl64(off, span_lane(rs, rel));
-                    if (!full[u]) x[u][j] = (c >= wlo && c < whi) ? (float)ld_stream(in + (c + oc)) : 0.0f;
+                    const uint32_t rj = c > wlo ? (uint32_t)(c - wlo) : 0u;
+                    const int pj = p0 + (sn[0] <= rj) + (sn[1] <= rj) + (sn[2] <= rj);
+                    oc[j] = shfl64(off, pj);
+                    vc[j] = c >= wlo && c < whi;
+                }
+                full[u] = vc[0] && vc[3] && sn[0] > rel + 3 && t + oc[0] + quad_reach<T>() <= o.nvox;
+                if (full[u]) {
+                    load_quad(in, t + oc[0], x[u]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) x[u][j] = vc[j] ? (float)ld_stream(in + (t + j + oc[j])) : 0.0f;
                 }
             }
             uint32_t outm[U];
