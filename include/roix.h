@@ -290,12 +290,121 @@ const char* roix_stage_name(int stage);
 roix_status roix_ctx_set_timing(roix_ctx* ctx, int enable);
 roix_status roix_ctx_read_timing(roix_ctx* ctx, double* ms, int64_t* launches);
 
+/* ------------------------------------------------------------------ served
+ *
+ * Served form: volumes arrive as consecutive z-slabs (a detector streaming
+ * projections, or a reconstruction written slab by slab) and are reduced
+ * while they arrive.  A server owns an HBM pool of `hbm_budget_bytes`
+ * (allocated once at roix_server_create), a copy stream and a compute
+ * stream of its own.
+ *
+ * A volume is admitted at roix_volume_open when its resident footprint
+ * (roix_server_volume_bytes) fits the free part of the pool; otherwise the
+ * call returns ROIX_EBUSY and nothing is kept (the caller retries after a
+ * volume has closed).  Every slab is copied (host or device memory) into
+ * the volume's resident buffer on the copy stream.
+ *
+ * With an absolute bound and a FIXED threshold the mask of a voxel is known
+ * when its slab arrives (the readings of Sec. 4.1.3-4.1.4 for a fixed
+ * threshold: object = q(x) > q(T)), so each slab is reduced at once: value
+ * range, mask, runs, and the connected components of the slab's runs,
+ * united with the runs of the earlier slabs that stay resident on the
+ * device.  The keep rule, the spans and the code stream depend on the whole
+ * volume (LARGEST, qmin), so they run at roix_volume_close.  Volumes with an
+ * OTSU threshold or a REL bound only collect slabs and run the whole path at
+ * close.  Either way the outputs equal roix_fused on the assembled volume
+ * with the same arguments.
+ *
+ * Requests complete asynchronously; roix_wait returns their host-clock
+ * times.  Slab latency = completion - submission (copy and compute,
+ * including the wait behind earlier requests).  All calls on one server
+ * must come from one host thread. */
+typedef struct roix_server roix_server;
+
+typedef enum { ROIX_REQ_SLAB = 0, ROIX_REQ_CLOSE = 1 } roix_req_kind;
+
+typedef struct {
+    int32_t status;    /* ROIX_OK, or the device error of the request */
+    int32_t kind;      /* roix_req_kind */
+    int64_t vol_id;
+    double submit_ms;  /* host steady clock, ms since roix_server_create */
+    double done_ms;    /* completion on the device, same clock */
+    double latency_ms; /* done_ms - submit_ms */
+} roix_req_result;
+
+typedef struct {
+    int64_t volumes_admitted, volumes_refused, volumes_open;
+    int64_t slabs_done, closes_done;
+    int64_t bytes_in;            /* slab bytes accepted */
+    uint64_t budget_bytes, bytes_in_use;
+    double slab_p50_ms, slab_p99_ms, slab_max_ms; /* over completed slabs */
+    double close_p50_ms, close_p99_ms;
+} roix_server_stats_t;
+
+/* Server on ctx's device with an HBM pool of hbm_budget_bytes.  The server
+ * does not use ctx's arena; ctx must outlive the server.  Errors:
+ * ROIX_EINVAL (NULL ctx/out, zero budget), ROIX_ENOMEM (the pool cannot be
+ * allocated), ROIX_EDEVICE. */
+roix_status roix_server_create(roix_ctx* ctx, size_t hbm_budget_bytes, roix_server** out);
+/* Waits for all work, then frees the pool, streams and events. */
+roix_status roix_server_destroy(roix_server* srv);
+
+/* Pool bytes a volume holds while open on this server: its input
+ * (N * voxel bytes) plus the labelling state (no proxy for incremental
+ * volumes) with run arrays for runs_per_row runs per row on average (a
+ * volume with more foreground runs fails with ROIX_ENOMEM in its infos at
+ * close).  0 for invalid arguments. */
+size_t roix_server_volume_bytes(const roix_server* srv, roix_dims dims, roix_dtype dtype, roix_eb eb,
+                                const roix_criterion* crit);
+
+/* Server parameters:
+ *   "runs_per_row"  run-array capacity of volumes opened from now on, as an
+ *                   average number of foreground runs per row (default 32,
+ *                   capped at the worst case of ceil(nx/2))
+ * Errors: ROIX_EINVAL (unknown name or value out of range). */
+roix_status roix_server_set_param(roix_server* srv, const char* name, int64_t value);
+
+/* Admit a volume.  `final_out` (copied; its buffers must stay valid until the
+ * close request completes) receives the outputs at close.  Errors:
+ * ROIX_EINVAL (arguments, as roix_fused), ROIX_EBUSY (the pool has no room
+ * now). */
+roix_status roix_volume_open(roix_server* srv, roix_dims dims, roix_dtype dtype, roix_eb eb,
+                             const roix_criterion* crit, const roix_fused_out* final_out, int64_t* vol_id);
+
+/* Submit planes [z0, z0 + nz_slab) of volume vol_id from `ptr` (host memory
+ * when ptr_is_device == 0 -- pinned memory gives an asynchronous copy --
+ * else device memory), C-contiguous [nz_slab][ny][nx].  The memory must stay
+ * untouched until the request completes.  Slabs must come in order: z0 must
+ * equal the end of the previous slab.  Errors: ROIX_EINVAL (unknown volume,
+ * NULL ptr, nz_slab < 1, z0 + nz_slab > nz), ROIX_ESEQ (z0 out of order or
+ * repeated, volume already closed). */
+roix_status roix_slab_submit(roix_server* srv, int64_t vol_id, int64_t z0, int64_t nz_slab, const void* ptr,
+                             int ptr_is_device, int64_t* req_id);
+
+/* Enqueue the end of volume vol_id: the remaining stages and the outputs.
+ * The volume's pool memory is released when the request completes.
+ * Errors: ROIX_EINVAL (unknown volume), ROIX_ESEQ (slabs missing, or already
+ * closed). */
+roix_status roix_volume_close(roix_server* srv, int64_t vol_id, int64_t* req_id);
+
+/* Drop a volume: no outputs; its memory is released once its enqueued work
+ * has finished.  Errors: ROIX_EINVAL (unknown volume), ROIX_ESEQ (already
+ * closed or aborted). */
+roix_status roix_volume_abort(roix_server* srv, int64_t vol_id);
+
+/* Wait up to timeout_ms (< 0: forever) for a request.  ROIX_OK with *res
+ * filled (the request is then forgotten), ROIX_EBUSY if it has not
+ * completed in time, ROIX_EINVAL for an unknown id. */
+roix_status roix_wait(roix_server* srv, int64_t req_id, int64_t timeout_ms, roix_req_result* res);
+
+roix_status roix_server_stats(roix_server* srv, roix_server_stats_t* out);
+
 const char* roix_status_string(roix_status st);
 
 /* sizeof of a public struct by name ("roix_quant_info", "roix_seg_info",
  * "roix_extract_info", "roix_component", "roix_row", "roix_fused_out",
- * "roix_criterion", "roix_eb", "roix_dims", "roix_volume_desc"), 0 if
- * unknown: lets bindings
+ * "roix_criterion", "roix_eb", "roix_dims", "roix_volume_desc",
+ * "roix_req_result", "roix_server_stats_t"), 0 if unknown: lets bindings
  * check their mirrors of this header. */
 size_t roix_sizeof(const char* type_name);
 

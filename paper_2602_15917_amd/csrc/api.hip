@@ -8,32 +8,9 @@
 #include <new>
 #include <vector>
 
-#include "common.h"
+#include "host.h"
 
 namespace roix {
-
-struct Timer {
-    bool on = false;
-    struct Open {
-        hipEvent_t a = nullptr;
-    } open[ST_COUNT];
-    struct Pending {
-        int stage;
-        hipEvent_t a, b;
-    };
-    std::vector<Pending> pending;
-    std::vector<hipEvent_t> pool;
-    hipEvent_t get() {
-        if (!pool.empty()) {
-            hipEvent_t e = pool.back();
-            pool.pop_back();
-            return e;
-        }
-        hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        return e;
-    }
-};
 
 void timer_begin(Timer* t, int stage, hipStream_t s) {
     if (!t || !t->on) return;
@@ -60,37 +37,11 @@ static const char* kStageNames[ST_COUNT] = {
 
 using namespace roix;
 
-struct BatchState {
-    std::vector<hipStream_t> streams;
-    std::vector<hipEvent_t> joins;
-    hipEvent_t fork = nullptr;
-    hipStream_t origin = nullptr;  // the graph is captured and launched here
-    hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    std::vector<uint8_t> key;  // descriptors + launch parameters of the cached graph
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-};
-
-struct roix_ctx {
-    int device = 0;
-    int cus = 0;
-    void* arena = nullptr;
-    size_t arena_bytes = 0;
-    Timer timer;
-    int grid_stream = 2048;
-    int grid_read = 512;
-    int seg_grid = 512;
-    int seg_runs = 0;
-    int batch_streams = 4;
-    int batch_graph = 1;
-    BatchState batch;
-};
-
 // ----------------------------------------------------------------- layout
 
-static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+size_t roix::align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static bool geom_of(roix_dims d, Geom* g) {
+bool roix::geom_of(roix_dims d, Geom* g) {
     if (d.nx < 1 || d.ny < 1 || d.nz < 1) return false;
     if (d.nx > (1ll << 31) - 64 || d.ny > (1ll << 31) || d.nz > (1ll << 31)) return false;
     const unsigned __int128 n = (unsigned __int128)d.nx * d.ny * d.nz;
@@ -105,19 +56,18 @@ static bool geom_of(roix_dims d, Geom* g) {
     return true;
 }
 
-static constexpr uint64_t kRunBytes = 21;  // xs, xe, parent, comp id, row (4 B each) + kept flag (1 B)
 
-static uint64_t worst_runs(const Geom& g) {
+uint64_t roix::worst_runs(const Geom& g) {
     uint64_t w = (uint64_t)g.nrows * (uint64_t)((g.nx + 1) / 2);
     const uint64_t cap = (1ull << 31) - 1;
     return w < cap ? w : cap;
 }
 
 // bytes of the per-voxel and per-row part of the arena
-static size_t fixed_bytes(const Geom& g) {
+size_t roix::fixed_bytes(const Geom& g, bool with_proxy) {
     size_t b = 0;
     b += align256(sizeof(DevState));
-    b += align256((size_t)g.nrows * g.W * 64);             // proxy
+    if (with_proxy) b += align256((size_t)g.nrows * g.W * 64);  // proxy
     b += align256((size_t)g.nrows * g.W * 8);             // mask bits
     b += align256((size_t)g.nrows * 4);                   // row_nruns
     b += align256((size_t)(g.nrows + 1) * 4);             // run_off
@@ -131,8 +81,8 @@ static size_t fixed_bytes(const Geom& g) {
     return b;
 }
 
-static bool carve_at(void* base, size_t bytes, const Geom& g, Layout* L) {
-    const size_t fb = fixed_bytes(g);
+bool roix::carve_at(void* base, size_t bytes, const Geom& g, Layout* L, bool with_proxy) {
+    const size_t fb = fixed_bytes(g, with_proxy);
     if (bytes < fb + kRunBytes) return false;
     uint8_t* p = (uint8_t*)base;
     auto take = [&](size_t n) {
@@ -141,7 +91,7 @@ static bool carve_at(void* base, size_t bytes, const Geom& g, Layout* L) {
         return q;
     };
     L->S = (DevState*)take(sizeof(DevState));
-    L->proxy = take((size_t)g.nrows * g.W * 64);
+    L->proxy = with_proxy ? take((size_t)g.nrows * g.W * 64) : nullptr;
     L->maskbits = (uint64_t*)take((size_t)g.nrows * g.W * 8);
     L->row_nruns = (uint32_t*)take((size_t)g.nrows * 4);
     L->run_off = (uint32_t*)take((size_t)(g.nrows + 1) * 4);
@@ -170,7 +120,7 @@ static bool carve_at(void* base, size_t bytes, const Geom& g, Layout* L) {
 
 static bool carve(roix_ctx* c, const Geom& g, Layout* L) { return carve_at(c->arena, c->arena_bytes, g, L); }
 
-static LaunchCtx lctx(roix_ctx* c, void* stream) {
+LaunchCtx roix::lctx(roix_ctx* c, void* stream) {
     LaunchCtx lc;
     lc.stream = (hipStream_t)stream;
     lc.timer = c->timer.on ? &c->timer : nullptr;
@@ -181,13 +131,13 @@ static LaunchCtx lctx(roix_ctx* c, void* stream) {
     return lc;
 }
 
-static bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+bool roix::aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
-static bool eb_ok(roix_eb eb) {
+bool roix::eb_ok(roix_eb eb) {
     return (eb.mode == ROIX_EB_ABS || eb.mode == ROIX_EB_REL) && eb.value > 0.0 && eb.value <= 1.7976931348623157e308;
 }
 
-static bool crit_ok(const roix_criterion* c) {
+bool roix::crit_ok(const roix_criterion* c) {
     if (!c) return false;
     if (c->thr != ROIX_THR_OTSU && c->thr != ROIX_THR_FIXED) return false;
     if (c->thr == ROIX_THR_FIXED && !(c->fixed_value >= -1.7976931348623157e308 && c->fixed_value <= 1.7976931348623157e308))
@@ -198,7 +148,7 @@ static bool crit_ok(const roix_criterion* c) {
     return true;
 }
 
-static bool out_ok(const roix_fused_out* o, bool need_comps) {
+bool roix::out_ok(const roix_fused_out* o, bool need_comps) {
     if (!o) return false;
     if (o->rows_cap < 0 || o->stream_cap_bytes < 0 || o->outliers_cap < 0 || o->comps_cap < 0) return false;
     if (o->rows_cap > 0 && (!o->d_rows || !aligned(o->d_rows, 8))) return false;
@@ -210,25 +160,26 @@ static bool out_ok(const roix_fused_out* o, bool need_comps) {
 
 static roix_status dev_err(hipError_t e) { return e == hipSuccess ? ROIX_OK : ROIX_EDEVICE; }
 
-#define ROIX_TRY(x)                                   \
-    do {                                              \
-        hipError_t _e = (x);                          \
-        if (_e != hipSuccess) return ROIX_EDEVICE;    \
-    } while (0)
 
 // --------------------------------------------------------- shared stages
 
-// mask -> runs -> components -> stats -> keep (everything after the proxy)
-static hipError_t label_and_keep(const LaunchCtx& lc, const Geom& g, const Layout& L, const roix_criterion* crit,
-                                 roix_component* comps, int64_t comps_cap) {
+// mask -> runs -> union of a whole volume (everything between the proxy and
+// the flattening)
+static hipError_t label_runs(const LaunchCtx& lc, const Geom& g, const Layout& L, int connectivity) {
     hipError_t e;
     if ((e = launch_mask_runs(lc, g, L)) != hipSuccess) return e;
     if ((e = launch_scan_u32(lc, L.row_nruns, L.run_off, g.nrows, nullptr, &L.S->n_runs, L.run_off + g.nrows,
                              L.scan_tmp)) != hipSuccess)
         return e;
     if ((e = launch_check_cap(lc, L.S, L.scan_tmp + kScanBlocks, L.run_cap, ROIX_ENOMEM)) != hipSuccess) return e;
-    if ((e = launch_runs_write(lc, g, L)) != hipSuccess) return e;
-    if ((e = launch_union(lc, g, L, crit->connectivity)) != hipSuccess) return e;
+    if ((e = launch_runs_write(lc, g, L, 0, g.nrows)) != hipSuccess) return e;
+    return launch_union(lc, g, L, connectivity);
+}
+
+// flatten -> component ids -> stats -> keep
+hipError_t roix::components_and_keep(const LaunchCtx& lc, const Geom& g, const Layout& L, const roix_criterion* crit,
+                                     roix_component* comps, int64_t comps_cap) {
+    hipError_t e;
     if ((e = launch_flatten(lc, L)) != hipSuccess) return e;
     if ((e = launch_scan_u32(lc, L.comp_id, L.comp_id, (int64_t)L.run_cap, &L.S->n_runs, &L.S->n_comps, nullptr,
                              L.scan_tmp)) != hipSuccess)
@@ -240,7 +191,14 @@ static hipError_t label_and_keep(const LaunchCtx& lc, const Geom& g, const Layou
     return launch_keep(lc, L, comps, crit);
 }
 
-static hipError_t spans_and_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, const void* in, roix_dtype dt,
+static hipError_t label_and_keep(const LaunchCtx& lc, const Geom& g, const Layout& L, const roix_criterion* crit,
+                                 roix_component* comps, int64_t comps_cap) {
+    hipError_t e;
+    if ((e = label_runs(lc, g, L, crit->connectivity)) != hipSuccess) return e;
+    return components_and_keep(lc, g, L, crit, comps, comps_cap);
+}
+
+hipError_t roix::spans_and_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, const void* in, roix_dtype dt,
                                  const roix_fused_out* out) {
     hipError_t e;
     if ((e = launch_scan_u64(lc, L.row_packed, L.row_packed, g.nrows, &L.S->span_total, L.scan_tmp)) != hipSuccess)
@@ -257,7 +215,7 @@ static void batch_release(BatchState& b) {
 }
 
 // the launch sequence of the fused path on an already carved layout
-static roix_status enqueue_fused(const LaunchCtx& lc, const Geom& g, Layout L, const void* d_in, roix_dtype dtype,
+roix_status roix::enqueue_fused(const LaunchCtx& lc, const Geom& g, Layout L, const void* d_in, roix_dtype dtype,
                                  roix_eb eb, const roix_criterion* crit, const roix_fused_out* out) {
     const bool fixed = crit->thr == ROIX_THR_FIXED;
     const int kind = dtype == ROIX_F32 ? 0 : 1;
@@ -300,7 +258,8 @@ size_t roix_sizeof(const char* t) {
                      {"roix_extract_info", sizeof(roix_extract_info)}, {"roix_component", sizeof(roix_component)},
                      {"roix_row", sizeof(roix_row)},                   {"roix_fused_out", sizeof(roix_fused_out)},
                      {"roix_criterion", sizeof(roix_criterion)},       {"roix_eb", sizeof(roix_eb)},
-                     {"roix_dims", sizeof(roix_dims)},                 {"roix_volume_desc", sizeof(roix_volume_desc)}};
+                     {"roix_dims", sizeof(roix_dims)},                 {"roix_volume_desc", sizeof(roix_volume_desc)},
+                     {"roix_req_result", sizeof(roix_req_result)},     {"roix_server_stats_t", sizeof(roix_server_stats_t)}};
     for (const auto& e : tab)
         if (strcmp(e.n, t) == 0) return e.s;
     return 0;

@@ -51,6 +51,14 @@ struct DevState {
     unsigned long long span_total;  // (rows with a span) << 40 | (codes)
     unsigned long long n_outliers, q_outliers;
     uint32_t n_outl_rows, pad2;
+    // run number where the current labelling pass starts (0 for a whole
+    // volume; the first run of the slab for a streamed slab)
+    uint32_t seg_lo;
+    // streamed volumes: the mask parameters fixed at open (r, and rint(T r)
+    // of the fixed threshold), and the status held back over the close
+    // sequence's quantiser stages
+    int32_t saved_status;
+    float serve_r, serve_rt;
 };
 
 // Per-call view of the scratch arena.
@@ -226,6 +234,16 @@ hipError_t launch_quant_hist(const LaunchCtx& lc, const void* in, int src_kind, 
 hipError_t launch_otsu(const LaunchCtx& lc, DevState* S, bool fixed);
 
 hipError_t launch_mask_runs(const LaunchCtx& lc, const Geom& g, const Layout& L);
+// streamed volumes (FIXED threshold, ABS bound): mask parameters at open,
+// then per slab of rows [r0, r1) the range, mask words and run counts
+hipError_t launch_serve_open(const LaunchCtx& lc, DevState* S, double eb_value, double fixed_value);
+hipError_t launch_slab_mask(const LaunchCtx& lc, const void* in, roix_dtype dt, const Geom& g, int64_t r0,
+                            int64_t r1, const Layout& L);
+// the histogram of the whole volume without the proxy (streamed volumes)
+hipError_t launch_hist_only(const LaunchCtx& lc, const void* in, roix_dtype dt, const Geom& g, DevState* S);
+// save = 1: hold back and clear the status; save = 0: restore it unless a
+// newer error is set
+hipError_t launch_serve_status(const LaunchCtx& lc, DevState* S, int save);
 // Exclusive scans (in place allowed).  n from the host, or from *n_dev when
 // n_dev is not null (then n_host is only an upper bound).  total_out and
 // out_end (nullable) receive the sum of all elements.
@@ -235,7 +253,13 @@ hipError_t launch_scan_u64(const LaunchCtx& lc, const uint64_t* in, uint64_t* ou
                            unsigned long long* total_out, uint64_t* tmp);
 // fail with `err` when *val > cap (val: the 64-bit total of the last scan)
 hipError_t launch_check_cap(const LaunchCtx& lc, DevState* S, const uint64_t* val, uint64_t cap, int err);
-hipError_t launch_runs_write(const LaunchCtx& lc, const Geom& g, const Layout& L);
+// runs of rows [r0, r1); their numbers continue from run_off[r0]
+hipError_t launch_runs_write(const LaunchCtx& lc, const Geom& g, const Layout& L, int64_t r0, int64_t r1);
+// exclusive scan of n_host u32 counts starting from *base (device); *base
+// becomes base + total, *lo_out the old base, *out_end the new total;
+// tmp[kScanBlocks] receives the new 64-bit total
+hipError_t launch_scan_u32_base(const LaunchCtx& lc, const uint32_t* in, uint32_t* out, int64_t n_host,
+                                uint32_t* base, uint32_t* lo_out, uint32_t* out_end, uint64_t* tmp);
 hipError_t launch_union(const LaunchCtx& lc, const Geom& g, const Layout& L, int conn);
 hipError_t launch_flatten(const LaunchCtx& lc, const Layout& L);
 hipError_t launch_comp_stats(const LaunchCtx& lc, const Geom& g, const Layout& L, roix_component* comps);

@@ -1,0 +1,100 @@
+// host.h - host-side pieces shared by the library's translation units: the
+// context, the scratch-arena layout, argument checks and the launch
+// sequences that the plain, batched and streamed forms have in common.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace roix {
+
+struct Timer {
+    bool on = false;
+    struct Open {
+        hipEvent_t a = nullptr;
+    } open[ST_COUNT];
+    struct Pending {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+};
+
+}  // namespace roix
+
+struct BatchState {
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> joins;
+    hipEvent_t fork = nullptr;
+    hipStream_t origin = nullptr;  // the graph is captured and launched here
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::vector<uint8_t> key;  // descriptors + launch parameters of the cached graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+struct roix_ctx {
+    int device = 0;
+    int cus = 0;
+    void* arena = nullptr;
+    size_t arena_bytes = 0;
+    roix::Timer timer;
+    int grid_stream = 2048;
+    int grid_read = 512;
+    int seg_grid = 512;
+    int seg_runs = 0;
+    int batch_streams = 4;
+    int batch_graph = 1;
+    BatchState batch;
+};
+
+namespace roix {
+
+constexpr uint64_t kRunBytes = 21;  // xs, xe, parent, comp id, row (4 B each) + kept flag (1 B)
+
+size_t align256(size_t x);
+// dims -> geometry; false when a dim is < 1 or a bound of the path is exceeded
+// (N <= 2^33 voxels, ny * nz < 2^31 rows, nx < 2^31 - 64)
+bool geom_of(roix_dims d, Geom* g);
+// largest possible number of runs: half the voxels of every row, capped
+uint64_t worst_runs(const Geom& g);
+// bytes of the per-voxel and per-row part of a layout (the proxy only when asked)
+size_t fixed_bytes(const Geom& g, bool with_proxy = true);
+// carve a layout from [base, base + bytes); the run arrays take what is left
+// (at most worst_runs); false when not even one run fits
+bool carve_at(void* base, size_t bytes, const Geom& g, Layout* L, bool with_proxy = true);
+LaunchCtx lctx(roix_ctx* c, void* stream);
+bool aligned(const void* p, size_t a);
+bool eb_ok(roix_eb eb);
+bool crit_ok(const roix_criterion* c);
+bool out_ok(const roix_fused_out* o, bool need_comps);
+
+// flatten -> component ids -> stats -> keep
+hipError_t components_and_keep(const LaunchCtx& lc, const Geom& g, const Layout& L, const roix_criterion* crit,
+                               roix_component* comps, int64_t comps_cap);
+// span scan -> codes -> row table -> outliers
+hipError_t spans_and_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, const void* in, roix_dtype dt,
+                          const roix_fused_out* out);
+// the whole fused path on a carved layout
+roix_status enqueue_fused(const LaunchCtx& lc, const Geom& g, Layout L, const void* d_in, roix_dtype dtype,
+                          roix_eb eb, const roix_criterion* crit, const roix_fused_out* out);
+
+}  // namespace roix
+
+#define ROIX_TRY(x)                                   \
+    do {                                              \
+        hipError_t _e = (x);                          \
+        if (_e != hipSuccess) return ROIX_EDEVICE;    \
+    } while (0)

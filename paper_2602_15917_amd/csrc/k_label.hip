@@ -180,7 +180,8 @@ __global__ __launch_bounds__(kBlock) void k_runs_write_lanes(const uint64_t* __r
                                                              uint32_t* __restrict__ xs_out,
                                                              uint32_t* __restrict__ xe_out,
                                                              uint32_t* __restrict__ parent,
-                                                             uint32_t* __restrict__ run_row, const DevState* S) {
+                                                             uint32_t* __restrict__ run_row, int64_t row_base,
+                                                             const DevState* S) {
     if (thread_exit(S)) return;  // no barrier below; the status is the same for every lane of a wave
     const int lane = threadIdx.x % kWave;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
@@ -221,7 +222,7 @@ __global__ __launch_bounds__(kBlock) void k_runs_write_lanes(const uint64_t* __r
             xs_out[k] = xs;
             xe_out[k] = xe;
             parent[k] = k;
-            run_row[k] = (uint32_t)wl.row;
+            run_row[k] = (uint32_t)(row_base + wl.row);
             ++k;
         }
     }
@@ -232,7 +233,8 @@ __global__ __launch_bounds__(kBlock) void k_runs_write_lanes(const uint64_t* __r
 __global__ __launch_bounds__(kBlock) void k_runs_write(const uint64_t* __restrict__ maskbits, int64_t nrows, int64_t W,
                                                        const uint32_t* __restrict__ run_off, uint32_t* __restrict__ xs_out,
                                                        uint32_t* __restrict__ xe_out, uint32_t* __restrict__ parent,
-                                                       uint32_t* __restrict__ run_row, const DevState* S) {
+                                                       uint32_t* __restrict__ run_row, int64_t row_base,
+                                                       const DevState* S) {
     if (thread_exit(S)) return;
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
     for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < nrows; row += nthreads) {
@@ -255,7 +257,7 @@ __global__ __launch_bounds__(kBlock) void k_runs_write(const uint64_t* __restric
                     xs_out[k] = xs;
                     xe_out[k] = pos;
                     parent[k] = k;
-                    run_row[k] = (uint32_t)row;
+                    run_row[k] = (uint32_t)(row_base + row);
                     ++k;
                 }
             }
@@ -265,23 +267,24 @@ __global__ __launch_bounds__(kBlock) void k_runs_write(const uint64_t* __restric
             xs_out[k] = xs;
             xe_out[k] = (uint32_t)(W * 64);
             parent[k] = k;
-            run_row[k] = (uint32_t)row;
+            run_row[k] = (uint32_t)(row_base + row);
         }
     }
 }
 
-hipError_t launch_runs_write(const LaunchCtx& lc, const Geom& g, const Layout& L) {
+hipError_t launch_runs_write(const LaunchCtx& lc, const Geom& g, const Layout& L, int64_t r0, int64_t r1) {
     timer_begin(lc.timer, ST_RUNS, lc.stream);
+    const int64_t nr = r1 - r0;
+    const uint64_t* mb = L.maskbits + r0 * g.W;
+    const uint32_t* off = L.run_off + r0;
     if (g.W <= kWave) {
         const int64_t R = kWave / g.W;
-        hipLaunchKernelGGL(k_runs_write_lanes, dim3(grid_for((g.nrows + R - 1) / R, kBlock / kWave, lc.grid_stream)),
-                           dim3(kBlock), 0, lc.stream, (const uint64_t*)L.maskbits, g.nx, g.nrows, g.W,
-                           (const uint32_t*)L.run_off, L.run_xs, L.run_xe, L.parent, L.run_row,
-                           (const DevState*)L.S);
+        hipLaunchKernelGGL(k_runs_write_lanes, dim3(grid_for((nr + R - 1) / R, kBlock / kWave, lc.grid_stream)),
+                           dim3(kBlock), 0, lc.stream, mb, g.nx, nr, g.W, off, L.run_xs, L.run_xe, L.parent,
+                           L.run_row, r0, (const DevState*)L.S);
     } else {
-        hipLaunchKernelGGL(k_runs_write, dim3(grid_for(g.nrows, kBlock, 16384)), dim3(kBlock), 0, lc.stream,
-                           (const uint64_t*)L.maskbits, g.nrows, g.W, (const uint32_t*)L.run_off, L.run_xs, L.run_xe,
-                           L.parent, L.run_row, (const DevState*)L.S);
+        hipLaunchKernelGGL(k_runs_write, dim3(grid_for(nr, kBlock, 16384)), dim3(kBlock), 0, lc.stream, mb, nr, g.W,
+                           off, L.run_xs, L.run_xe, L.parent, L.run_row, r0, (const DevState*)L.S);
     }
     timer_end(lc.timer, ST_RUNS, lc.stream);
     return hipGetLastError();
@@ -431,12 +434,12 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_label(const uint32_t* __restr
                                                          const DevState* S) {
     __shared__ uint32_t lp[kSegCap];
     if (block_exit_l(S)) return;
-    const uint32_t n = S->n_runs;
-    if (n == 0) return;
-    const uint32_t T = seg_runs(n, G, tparam);
-    const uint32_t nseg = (n + T - 1) / T;
+    const uint32_t n = S->n_runs, lo = S->seg_lo;
+    if (n <= lo) return;
+    const uint32_t T = seg_runs(n - lo, G, tparam);
+    const uint32_t nseg = (n - lo + T - 1) / T;
     for (uint32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
-        const uint32_t s0 = sg * T, s1 = (n - s0 < T) ? n : s0 + T, m = s1 - s0;
+        const uint32_t s0 = lo + sg * T, s1 = (n - s0 < T) ? n : s0 + T, m = s1 - s0;
         for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) lp[i] = i;
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
@@ -467,7 +470,7 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_label(const uint32_t* __restr
     }
 }
 
-// Level 2: one workgroup per segment (the first has nothing before it).
+// Level 2: one workgroup per segment.
 // Only runs whose rows lie within ny + 1 rows of the segment's first row can
 // touch an earlier segment.  Each touching pair (a, b), b < s0, names the
 // pair of their roots; the distinct pairs are collected in an LDS hash set
@@ -483,21 +486,24 @@ __global__ __launch_bounds__(kBlock) void k_seg_cross(const uint32_t* __restrict
     __shared__ unsigned long long tab[kCrossCap];
     constexpr unsigned long long kEmpty = ~0ull;
     if (block_exit_l(S)) return;
-    const uint32_t n = S->n_runs;
-    if (n == 0) return;
-    const uint32_t T = seg_runs(n, G, tparam);
-    const uint32_t nseg = (n + T - 1) / T;
-    for (uint32_t sg = 1 + blockIdx.x; sg < nseg; sg += gridDim.x) {
-        const uint32_t s0 = sg * T, s1 = (n - s0 < T) ? n : s0 + T;
+    const uint32_t n = S->n_runs, lo = S->seg_lo;
+    if (n <= lo) return;
+    const uint32_t T = seg_runs(n - lo, G, tparam);
+    const uint32_t nseg = (n - lo + T - 1) / T;
+    // the very first segment of a volume has nothing before it
+    for (uint32_t sg = (lo == 0 ? 1u : 0u) + blockIdx.x; sg < nseg; sg += gridDim.x) {
+        const uint32_t s0 = lo + sg * T, s1 = (n - s0 < T) ? n : s0 + T;
         for (int i = threadIdx.x; i < kCrossCap; i += blockDim.x) tab[i] = kEmpty;
         const uint32_t r0 = run_row[s0];  // rows after r0 hold only runs > s0
-        const int64_t rl = (int64_t)r0 + ny + 2;
-        uint32_t hend = s1;
-        if (rl < nrows && run_off[rl] < hend) hend = run_off[rl];
+        // the head: runs of rows up to r0 + ny + 1 (run rows never decrease
+        // with the run number, so a thread stops at its first run past it;
+        // offsets of later rows may not exist yet when a volume arrives in slabs)
+        const uint64_t rlast = (uint64_t)r0 + ny + 1;
         __syncthreads();
         uint32_t last_a = kNone, last_b = kNone;
-        for (uint32_t a = s0 + threadIdx.x; a < hend; a += blockDim.x) {
+        for (uint32_t a = s0 + threadIdx.x; a < s1; a += blockDim.x) {
             const uint32_t r = run_row[a];
+            if (r > rlast) break;
             uint32_t z, y;
             row_zy(r, ny, inv_ny, z, y);
             const uint32_t as = xs[a], ae = xe[a];

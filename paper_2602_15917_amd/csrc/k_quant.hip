@@ -101,6 +101,9 @@ __global__ __launch_bounds__(kBlock) void k_init(DevState* S) {
             S->span_total = S->n_outliers = S->q_outliers = 0ull;
             S->n_outl_rows = 0u;
             S->qstatus = 0;
+            S->seg_lo = 0u;
+            S->saved_status = 0;
+            S->serve_r = S->serve_rt = 0.0f;
         }
         S->hist[threadIdx.x] = 0ull;
     }
@@ -250,6 +253,21 @@ __device__ __forceinline__ void qfail(DevState* S, int32_t st) {
     fail(S, st);
 }
 
+// The fp32 bound eb32 (eb rounded toward zero, so that the fp32 guarantee
+// implies the binary64 one), the step w = 2 eb32 and r = 1/w correctly
+// rounded (the binary64 quotient rounded to binary32: double rounding is
+// harmless for division since 53 >= 2*24 + 2).  False when eb is not a
+// positive finite number or any of the three is not a normal float.
+__device__ bool resolve_bound(double eb, float& eb32, float& w, float& r) {
+    if (!(eb > 0.0) || !(eb <= 1.7976931348623157e308)) return false;
+    eb32 = (float)eb;
+    if ((double)eb32 > eb) eb32 = __uint_as_float(__float_as_uint(eb32) - 1u);  // next float toward zero
+    if (!is_normal_f32(eb32)) return false;
+    w = eb32 + eb32;
+    r = (float)(1.0 / (double)w);
+    return is_normal_f32(w) && is_normal_f32(r);
+}
+
 __global__ void k_resolve(DevState* S, int is_f32, int eb_mode, double eb_value, int fixed, double fixed_value) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     if (S->nonfinite) {
@@ -261,21 +279,8 @@ __global__ void k_resolve(DevState* S, int is_f32, int eb_mode, double eb_value,
     S->xmin = xmin;
     S->xmax = xmax;
     double eb = eb_mode == ROIX_EB_ABS ? eb_value : eb_value * ((double)xmax - (double)xmin);
-    if (!(eb > 0.0) || !(eb <= 1.7976931348623157e308)) {
-        qfail(S, ROIX_EINVAL);
-        return;
-    }
-    float eb32 = (float)eb;
-    if ((double)eb32 > eb) eb32 = __uint_as_float(__float_as_uint(eb32) - 1u);  // next float toward zero
-    if (!is_normal_f32(eb32)) {
-        qfail(S, ROIX_EINVAL);
-        return;
-    }
-    float w = eb32 + eb32;
-    // 1/w correctly rounded: the binary64 quotient rounded to binary32 (double
-    // rounding is harmless for division since 53 >= 2*24 + 2)
-    float r = (float)(1.0 / (double)w);
-    if (!is_normal_f32(w) || !is_normal_f32(r)) {
+    float eb32, w, r;
+    if (!resolve_bound(eb, eb32, w, r)) {
         qfail(S, ROIX_EINVAL);
         return;
     }
@@ -422,7 +427,7 @@ constexpr int kQhBatch = 4;  // 16-byte loads in flight per lane
 // vectors l, l + 64, ... of the row (one coalesced 1 KB load per step) and
 // stores their VN proxy bytes as one word at the same voxel offset of the
 // row's proxy.  Scalar path: lane l takes voxels l, l + 64, ...
-template <typename T, bool CODES, bool FIXED, bool FASTDIV, bool VEC>
+template <typename T, bool CODES, bool FIXED, bool FASTDIV, bool VEC, bool STORE>
 __device__ __forceinline__ void qh_rows(const T* __restrict__ in, int64_t nx, int64_t nrows, int64_t P,
                                         const QH& p, uint32_t* mine, uint8_t* __restrict__ proxy, bool& bad) {
     constexpr int VN = VecN<T>::n;
@@ -452,13 +457,13 @@ __device__ __forceinline__ void qh_rows(const T* __restrict__ in, int64_t nx, in
                         uint32_t pk = 0;
 #pragma unroll
                         for (int j = 0; j < 4; ++j) pk |= qh_one<T, CODES, FIXED, FASTDIV>(v[j], p, mine, bad) << (8 * j);
-                        reinterpret_cast<uint32_t*>(dst)[vi] = pk;
+                        if constexpr (STORE) reinterpret_cast<uint32_t*>(dst)[vi] = pk;
                     } else {
                         uint64_t pk = 0;
 #pragma unroll
                         for (int j = 0; j < 8; ++j)
                             pk |= (uint64_t)qh_one<T, CODES, FIXED, FASTDIV>(v[j], p, mine, bad) << (8 * j);
-                        reinterpret_cast<uint64_t*>(dst)[vi] = pk;
+                        if constexpr (STORE) reinterpret_cast<uint64_t*>(dst)[vi] = pk;
                     }
                 }
             }
@@ -473,7 +478,9 @@ __device__ __forceinline__ void qh_rows(const T* __restrict__ in, int64_t nx, in
 #pragma unroll
                 for (int k = 0; k < kQhBatch; ++k) {
                     const int64_t x = x0 + k * kWave + lane;
-                    if (x < nx) dst[x] = (uint8_t)qh_one<T, CODES, FIXED, FASTDIV>(v[k], p, mine, bad);
+                    if (x >= nx) continue;
+                    const uint32_t pb = qh_one<T, CODES, FIXED, FASTDIV>(v[k], p, mine, bad);
+                    if constexpr (STORE) dst[x] = (uint8_t)pb;
                 }
             }
         }
@@ -482,7 +489,7 @@ __device__ __forceinline__ void qh_rows(const T* __restrict__ in, int64_t nx, in
 
 constexpr int kQhBlock = 512;  // 8 waves share one set of LDS histogram copies
 
-template <typename T, bool CODES, bool FIXED, bool VEC>
+template <typename T, bool CODES, bool FIXED, bool VEC, bool STORE = true>
 __global__ __launch_bounds__(kQhBlock) void k_quant_hist(const T* __restrict__ in, int64_t nx, int64_t nrows,
                                                        int64_t P, DevState* S, uint8_t* __restrict__ proxy) {
     __shared__ uint32_t lh[kHistCopies * kHistStride];
@@ -499,9 +506,9 @@ __global__ __launch_bounds__(kQhBlock) void k_quant_hist(const T* __restrict__ i
     uint32_t* mine = lh + (threadIdx.x % kHistCopies) * kHistStride;
     bool bad = false;
     if (p.K <= 65536u)
-        qh_rows<T, CODES, FIXED, true, VEC>(in, nx, nrows, P, p, mine, proxy, bad);
+        qh_rows<T, CODES, FIXED, true, VEC, STORE>(in, nx, nrows, P, p, mine, proxy, bad);
     else
-        qh_rows<T, CODES, FIXED, false, VEC>(in, nx, nrows, P, p, mine, proxy, bad);
+        qh_rows<T, CODES, FIXED, false, VEC, STORE>(in, nx, nrows, P, p, mine, proxy, bad);
     if constexpr (CODES) {
         if (bad) fail(S, ROIX_EINVAL);
     }
@@ -515,14 +522,18 @@ __global__ __launch_bounds__(kQhBlock) void k_quant_hist(const T* __restrict__ i
     }
 }
 
-template <typename T, bool CODES>
-static void qh_dispatch(const LaunchCtx& lc, const void* in, const Geom& g, DevState* S, uint8_t* proxy,
-                        bool fixed) {
+static dim3 qh_grid(const LaunchCtx& lc, const Geom& g) {
     int64_t blocks = (g.nrows + kQhBlock / kWave - 1) / (kQhBlock / kWave);
     const int64_t cap = (int64_t)lc.grid_stream / 2;  // 4 workgroups of 512 threads per CU
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
-    dim3 grid((unsigned)blocks), block(kQhBlock);
+    return dim3((unsigned)blocks);
+}
+
+template <typename T, bool CODES>
+static void qh_dispatch(const LaunchCtx& lc, const void* in, const Geom& g, DevState* S, uint8_t* proxy,
+                        bool fixed) {
+    dim3 grid = qh_grid(lc, g), block(kQhBlock);
     const bool vec = ((uintptr_t)in % 16 == 0) && ((g.nx * (int64_t)sizeof(T)) % 16 == 0);
     const int64_t P = g.W * 64;
 #define QH_LAUNCH(F, V)                                                                                        \
@@ -546,6 +557,163 @@ hipError_t launch_quant_hist(const LaunchCtx& lc, const void* in, int src_kind, 
     else
         qh_dispatch<int32_t, true>(lc, in, g, S, proxy, fixed);
     timer_end(lc.timer, ST_HIST, lc.stream);
+    return hipGetLastError();
+}
+
+template <typename T>
+static void hist_only_launch(const LaunchCtx& lc, const void* in, const Geom& g, DevState* S) {
+    const bool vec = ((uintptr_t)in % 16 == 0) && ((g.nx * (int64_t)sizeof(T)) % 16 == 0);
+    const int64_t P = g.W * 64;
+    if (vec)
+        hipLaunchKernelGGL((k_quant_hist<T, false, false, true, false>), qh_grid(lc, g), dim3(kQhBlock), 0,
+                           lc.stream, (const T*)in, g.nx, g.nrows, P, S, (uint8_t*)nullptr);
+    else
+        hipLaunchKernelGGL((k_quant_hist<T, false, false, false, false>), qh_grid(lc, g), dim3(kQhBlock), 0,
+                           lc.stream, (const T*)in, g.nx, g.nrows, P, S, (uint8_t*)nullptr);
+}
+
+hipError_t launch_hist_only(const LaunchCtx& lc, const void* in, roix_dtype dt, const Geom& g, DevState* S) {
+    timer_begin(lc.timer, ST_HIST, lc.stream);
+    if (dt == ROIX_F32)
+        hist_only_launch<float>(lc, in, g, S);
+    else
+        hist_only_launch<uint16_t>(lc, in, g, S);
+    timer_end(lc.timer, ST_HIST, lc.stream);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- streamed volumes
+
+// At open: the mask of a streamed volume is decidable voxel by voxel, since
+// the bound is absolute and the threshold fixed.  r as the quantiser's, and
+// rint(T r) as a float: for every finite voxel with |x r| <= 2^24 (anything
+// else fails the volume at close), rint(x r) > rint(T r) is q > q(T), the
+// fixed-threshold mask whatever the clamp of q(T) to [qmin - 1, qmax].  An
+// unusable bound leaves r = 0 (empty masks); the close reports the error.
+__global__ void k_serve_open(DevState* S, double eb_value, double fixed_value) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    float eb32, w, r;
+    if (!resolve_bound(eb_value, eb32, w, r)) return;
+    S->serve_r = r;
+    S->serve_rt = __builtin_rintf((float)fixed_value * r);
+}
+
+hipError_t launch_serve_open(const LaunchCtx& lc, DevState* S, double eb_value, double fixed_value) {
+    hipLaunchKernelGGL(k_serve_open, dim3(1), dim3(64), 0, lc.stream, S, eb_value, fixed_value);
+    return hipGetLastError();
+}
+
+// Rows [r0, r1) of a slab: one wave per row, 64 consecutive voxels per
+// ballot, so each ballot is one mask word; run starts and counts from the
+// word and the previous word's top bit.  Also the value range (as the range
+// kernel's keys) and the mask count.  Runs regardless of the status, so that
+// the counts are complete whatever fails later (as in the whole-volume path).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_slab_mask(const T* __restrict__ in, int64_t nx, int64_t r0, int64_t r1,
+                                                      int64_t W, DevState* S, uint64_t* __restrict__ maskbits,
+                                                      uint32_t* __restrict__ row_nruns) {
+    constexpr int U = 8;  // words per step (loads in flight per lane)
+    const float r = S->serve_r, rt = S->serve_rt;
+    const int lane = threadIdx.x % kWave;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u, nf = 0u;
+    unsigned long long nmask = 0;
+    for (int64_t row = r0 + wave; row < r1; row += nwaves) {
+        const T* src = in + row * nx;
+        uint64_t carry = 0;
+        uint32_t nr = 0;
+        for (int64_t w0 = 0; w0 < W; w0 += U) {
+            T v[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int64_t x = (w0 + k) * 64 + lane;
+                v[k] = x < nx ? ld_stream(src + x) : (T)0;
+            }
+            uint64_t mine = 0;
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                if (w0 + k >= W) break;  // uniform
+                const bool valid = (w0 + k) * 64 + lane < nx;
+                const float xf = (float)v[k];
+                if (valid) {
+                    const uint32_t key = range_key<T>(v[k], nf);
+                    lo = key < lo ? key : lo;
+                    hi = key > hi ? key : hi;
+                }
+                const uint64_t m = __ballot(valid && __builtin_rintf(xf * r) > rt);
+                const uint64_t starts = m & ~((m << 1) | carry);
+                carry = m >> 63;
+                nr += (uint32_t)__popcll(starts);
+                nmask += (unsigned long long)__popcll(m);
+                if (lane == k) mine = m;
+            }
+            if (lane < U && w0 + lane < W) maskbits[row * W + w0 + lane] = mine;
+        }
+        if (lane == 0) row_nruns[row] = nr;
+    }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    nf = wave_max(nf);
+    __shared__ uint32_t s_lo[kBlock / kWave], s_hi[kBlock / kWave], s_nf[kBlock / kWave];
+    __shared__ unsigned long long s_nm[kBlock / kWave];
+    const int wv = threadIdx.x / kWave;
+    if (lane == 0) {
+        s_lo[wv] = lo;
+        s_hi[wv] = hi;
+        s_nf[wv] = nf;
+        s_nm[wv] = nmask;  // the same value in every lane: counted once per wave
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long nm = 0;
+        for (int k = 0; k < kBlock / kWave; ++k) {
+            lo = s_lo[k] < lo ? s_lo[k] : lo;
+            hi = s_hi[k] > hi ? s_hi[k] : hi;
+            nf |= s_nf[k];
+            nm += s_nm[k];
+        }
+        if (lo <= hi) {
+            atomicMin(&S->kmin, lo);
+            atomicMax(&S->kmax, hi);
+        }
+        if (nf) atomicOr(&S->nonfinite, 1u);
+        if (nm) atomicAdd(&S->n_mask, nm);
+    }
+}
+
+hipError_t launch_slab_mask(const LaunchCtx& lc, const void* in, roix_dtype dt, const Geom& g, int64_t r0,
+                            int64_t r1, const Layout& L) {
+    timer_begin(lc.timer, ST_MASK_RUNS, lc.stream);
+    int64_t blocks = (r1 - r0 + kBlock / kWave - 1) / (kBlock / kWave);
+    if (blocks > lc.grid_stream) blocks = lc.grid_stream;
+    if (blocks < 1) blocks = 1;
+    if (dt == ROIX_F32)
+        hipLaunchKernelGGL(k_slab_mask<float>, dim3((unsigned)blocks), dim3(kBlock), 0, lc.stream, (const float*)in,
+                           g.nx, r0, r1, g.W, L.S, L.maskbits, L.row_nruns);
+    else
+        hipLaunchKernelGGL(k_slab_mask<uint16_t>, dim3((unsigned)blocks), dim3(kBlock), 0, lc.stream,
+                           (const uint16_t*)in, g.nx, r0, r1, g.W, L.S, L.maskbits, L.row_nruns);
+    timer_end(lc.timer, ST_MASK_RUNS, lc.stream);
+    return hipGetLastError();
+}
+
+// The close of a streamed volume runs resolve, histogram and threshold over
+// the whole volume after the slabs have been labelled: an error the slabs
+// hit (run capacity) is held back over those stages and restored after them,
+// so that the first reported error is the one the whole-volume path reports.
+__global__ void k_serve_status(DevState* S, int save) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (save) {
+        S->saved_status = S->status;
+        S->status = 0;
+    } else if (S->status == 0) {
+        S->status = S->saved_status;
+    }
+}
+
+hipError_t launch_serve_status(const LaunchCtx& lc, DevState* S, int save) {
+    hipLaunchKernelGGL(k_serve_status, dim3(1), dim3(64), 0, lc.stream, S, save);
     return hipGetLastError();
 }
 

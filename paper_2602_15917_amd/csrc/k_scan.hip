@@ -82,6 +82,33 @@ __global__ __launch_bounds__(kScanBlocks) void k_scan_top(uint64_t* tmp, TT* tot
     }
 }
 
+// As k_scan_top, continuing from a device base: every offset is shifted by
+// *base, then *lo_out = the old base and *base = *out_end = base + total.
+__global__ __launch_bounds__(kScanBlocks) void k_scan_top_base(uint64_t* tmp, uint32_t* base, uint32_t* lo_out,
+                                                              uint32_t* out_end) {
+    __shared__ uint64_t s[kScanBlocks];
+    const int t = threadIdx.x;
+    const uint64_t b0 = *base;
+    s[t] = tmp[t];
+    __syncthreads();
+    for (int o = 1; o < kScanBlocks; o <<= 1) {
+        uint64_t a = t >= o ? s[t - o] : 0ull;
+        __syncthreads();
+        s[t] += a;
+        __syncthreads();
+    }
+    const uint64_t incl = s[t];
+    tmp[t] = b0 + incl - tmp[t];
+    __syncthreads();  // every thread has read *base before it changes
+    if (t == kScanBlocks - 1) {
+        const uint64_t tot = b0 + incl;
+        tmp[kScanBlocks] = tot;
+        *lo_out = (uint32_t)b0;
+        *base = (uint32_t)tot;
+        if (out_end) *out_end = (uint32_t)tot;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_scan_down(const T* in, T* out, int64_t n_host, const uint32_t* n_dev,
                                                       const uint64_t* tmp) {
@@ -109,6 +136,18 @@ hipError_t launch_scan_u32(const LaunchCtx& lc, const uint32_t* in, uint32_t* ou
     hipLaunchKernelGGL(k_scan_top<uint32_t>, dim3(1), dim3(kScanBlocks), 0, lc.stream, tmp, total_out, out_end);
     hipLaunchKernelGGL(k_scan_down<uint32_t>, dim3(kScanBlocks), dim3(kBlock), 0, lc.stream, in, out, n_host,
                        n_dev, (const uint64_t*)tmp);
+    timer_end(lc.timer, ST_SCAN, lc.stream);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_u32_base(const LaunchCtx& lc, const uint32_t* in, uint32_t* out, int64_t n_host,
+                                uint32_t* base, uint32_t* lo_out, uint32_t* out_end, uint64_t* tmp) {
+    timer_begin(lc.timer, ST_SCAN, lc.stream);
+    hipLaunchKernelGGL(k_scan_reduce<uint32_t>, dim3(kScanBlocks), dim3(kBlock), 0, lc.stream, in, n_host,
+                       (const uint32_t*)nullptr, tmp);
+    hipLaunchKernelGGL(k_scan_top_base, dim3(1), dim3(kScanBlocks), 0, lc.stream, tmp, base, lo_out, out_end);
+    hipLaunchKernelGGL(k_scan_down<uint32_t>, dim3(kScanBlocks), dim3(kBlock), 0, lc.stream, in, out, n_host,
+                       (const uint32_t*)nullptr, (const uint64_t*)tmp);
     timer_end(lc.timer, ST_SCAN, lc.stream);
     return hipGetLastError();
 }

@@ -74,6 +74,20 @@ class VolumeDesc(ctypes.Structure):
                 ("eb", Eb), ("crit", CCriterion), ("out", FusedOut)]
 
 
+class ReqResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("kind", ctypes.c_int32), ("vol_id", ctypes.c_int64),
+                ("submit_ms", ctypes.c_double), ("done_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("volumes_admitted", ctypes.c_int64), ("volumes_refused", ctypes.c_int64),
+                ("volumes_open", ctypes.c_int64), ("slabs_done", ctypes.c_int64), ("closes_done", ctypes.c_int64),
+                ("bytes_in", ctypes.c_int64), ("budget_bytes", ctypes.c_uint64), ("bytes_in_use", ctypes.c_uint64),
+                ("slab_p50_ms", ctypes.c_double), ("slab_p99_ms", ctypes.c_double), ("slab_max_ms", ctypes.c_double),
+                ("close_p50_ms", ctypes.c_double), ("close_p99_ms", ctypes.c_double)]
+
+
+REQ_SLAB, REQ_CLOSE = 0, 1
 COMP_BYTES, ROW_BYTES = 48, 32
 STAGE_MAX = 64
 
@@ -109,9 +123,23 @@ def load():
     lib.roix_ctx_get_param.argtypes = [vp, ctypes.c_char_p, P(i64)]
     lib.roix_status_string.argtypes = [ci]
     lib.roix_status_string.restype = ctypes.c_char_p
+    lib.roix_server_create.argtypes = [vp, sz, P(vp)]
+    lib.roix_server_destroy.argtypes = [vp]
+    lib.roix_server_volume_bytes.argtypes = [vp, Dims, ci, Eb, P(CCriterion)]
+    lib.roix_server_set_param.argtypes = [vp, ctypes.c_char_p, i64]
+    lib.roix_server_set_param.restype = ci
+    lib.roix_server_volume_bytes.restype = sz
+    lib.roix_volume_open.argtypes = [vp, Dims, ci, Eb, P(CCriterion), P(FusedOut), P(i64)]
+    lib.roix_slab_submit.argtypes = [vp, i64, i64, i64, vp, ci, P(i64)]
+    lib.roix_volume_close.argtypes = [vp, i64, P(i64)]
+    lib.roix_volume_abort.argtypes = [vp, i64]
+    lib.roix_wait.argtypes = [vp, i64, i64, P(ReqResult)]
+    lib.roix_server_stats.argtypes = [vp, P(ServerStats)]
     for f in ("roix_ctx_create", "roix_ctx_destroy", "roix_bounds", "roix_quantize", "roix_segment",
               "roix_extract", "roix_fused", "roix_ctx_set_timing", "roix_ctx_read_timing", "roix_fused_batch",
-              "roix_ctx_set_param", "roix_ctx_get_param"):
+              "roix_ctx_set_param", "roix_ctx_get_param", "roix_server_create", "roix_server_destroy",
+              "roix_volume_open", "roix_slab_submit", "roix_volume_close", "roix_volume_abort", "roix_wait",
+              "roix_server_stats"):
         getattr(lib, f).restype = ci
     _lib = lib
     return lib
@@ -310,3 +338,82 @@ class Context:
 
 def parse_info(buf: torch.Tensor, cls):
     return _info(buf, cls)
+
+
+class Server:
+    """Served form: volumes streamed slab by slab into an HBM pool of
+    `budget_bytes` on the context's device (see roix_server_create)."""
+
+    def __init__(self, ctx: Context, budget_bytes: int):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.roix_server_create(ctx.h, int(budget_bytes), ctypes.byref(h)), "roix_server_create")
+        self.h = h
+        self.ctx = ctx  # the context must outlive the server
+        self._outs = {}
+
+    def close_server(self):
+        if self.h:
+            load().roix_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close_server()
+        except Exception:
+            pass
+
+    def volume_bytes(self, shape, dtype: int, eb_mode: str, eb_value: float, crit: Criterion) -> int:
+        nz, ny, nx = shape
+        c = crit.c()
+        return int(load().roix_server_volume_bytes(self.h, Dims(nx, ny, nz), dtype, eb_of(eb_mode, eb_value),
+                                                   ctypes.byref(c)))
+
+    def set_param(self, name: str, value: int):
+        _check(load().roix_server_set_param(self.h, name.encode(), int(value)), f"roix_server_set_param({name})")
+
+    def open(self, shape, dtype: int, eb_mode: str, eb_value: float, crit: Criterion, out: Outputs) -> int:
+        """Admit a volume of shape (nz, ny, nx); returns its id.  Raises
+        RoixError with status EBUSY when the pool has no room now."""
+        nz, ny, nx = shape
+        c = crit.c()
+        vid = ctypes.c_int64()
+        _check(load().roix_volume_open(self.h, Dims(nx, ny, nz), dtype, eb_of(eb_mode, eb_value), ctypes.byref(c),
+                                       ctypes.byref(out.c), ctypes.byref(vid)), "roix_volume_open")
+        self._outs[vid.value] = out  # keep the output buffers alive until close
+        return vid.value
+
+    def submit(self, vol_id: int, z0: int, slab: torch.Tensor) -> int:
+        """Planes [z0, z0 + slab.shape[0]) from a host (ideally pinned) or
+        device tensor; the tensor must stay alive and unchanged until the
+        request completes."""
+        assert slab.is_contiguous()
+        rid = ctypes.c_int64()
+        _check(load().roix_slab_submit(self.h, vol_id, z0, slab.shape[0], ctypes.c_void_p(slab.data_ptr()),
+                                       1 if slab.is_cuda else 0, ctypes.byref(rid)), "roix_slab_submit")
+        return rid.value
+
+    def close(self, vol_id: int) -> int:
+        rid = ctypes.c_int64()
+        _check(load().roix_volume_close(self.h, vol_id, ctypes.byref(rid)), "roix_volume_close")
+        return rid.value
+
+    def abort(self, vol_id: int):
+        _check(load().roix_volume_abort(self.h, vol_id), "roix_volume_abort")
+        self._outs.pop(vol_id, None)
+
+    def wait(self, req_id: int, timeout_ms: int = -1):
+        """ReqResult once the request has completed; None on timeout."""
+        res = ReqResult()
+        st = load().roix_wait(self.h, req_id, int(timeout_ms), ctypes.byref(res))
+        if st == EBUSY:
+            return None
+        _check(st, "roix_wait")
+        if res.kind == REQ_CLOSE:
+            self._outs.pop(res.vol_id, None)
+        return res
+
+    def stats(self) -> ServerStats:
+        s = ServerStats()
+        _check(load().roix_server_stats(self.h, ctypes.byref(s)), "roix_server_stats")
+        return s

@@ -44,7 +44,8 @@ def test_struct_sizes_match_binding(lib):
     for name, cls in (("roix_quant_info", roix.QuantInfo), ("roix_seg_info", roix.SegInfo),
                       ("roix_extract_info", roix.ExtractInfo), ("roix_fused_out", roix.FusedOut),
                       ("roix_criterion", roix.CCriterion), ("roix_eb", roix.Eb), ("roix_dims", roix.Dims),
-                      ("roix_volume_desc", roix.VolumeDesc)):
+                      ("roix_volume_desc", roix.VolumeDesc), ("roix_req_result", roix.ReqResult),
+                      ("roix_server_stats_t", roix.ServerStats)):
         assert L.roix_sizeof(name.encode()) == ctypes.sizeof(cls), name
     assert L.roix_sizeof(b"roix_component") == roix.COMP_BYTES == 48
     assert L.roix_sizeof(b"roix_row") == roix.ROW_BYTES == 32
@@ -74,6 +75,26 @@ def test_sync_argument_errors(lib):
     assert L.roix_extract(null, null, roix.F32, null, d, null, ctypes.byref(out), null) == roix.EINVAL
     assert L.roix_ctx_destroy(null) == roix.EINVAL
     assert L.roix_ctx_set_timing(null, 1) == roix.EINVAL
+    # served form
+    h = ctypes.c_void_p()
+    i = ctypes.c_int64()
+    assert L.roix_server_create(null, 1 << 20, ctypes.byref(h)) == roix.EINVAL
+    assert L.roix_server_destroy(null) == roix.EINVAL
+    assert L.roix_volume_open(null, d, roix.F32, eb, ctypes.byref(c), ctypes.byref(out), ctypes.byref(i)) == roix.EINVAL
+    assert L.roix_slab_submit(null, 1, 0, 1, null, 0, ctypes.byref(i)) == roix.EINVAL
+    assert L.roix_volume_close(null, 1, ctypes.byref(i)) == roix.EINVAL
+    assert L.roix_volume_abort(null, 1) == roix.EINVAL
+    assert L.roix_wait(null, 1, 0, ctypes.byref(roix.ReqResult())) == roix.EINVAL
+    assert L.roix_server_stats(null, ctypes.byref(roix.ServerStats())) == roix.EINVAL
+
+
+def test_served_calls_without_server(lib):
+    roix, L = lib
+    null = ctypes.c_void_p(0)
+    c = roix.Criterion(thr="fixed", fixed_value=0.5).c()
+    eb = roix.Eb(roix.EB_ABS, 0, 1e-3)
+    assert L.roix_server_volume_bytes(null, roix.Dims(8, 8, 8), roix.F32, eb, ctypes.byref(c)) == 0
+    assert L.roix_server_set_param(null, b"runs_per_row", 8) == roix.EINVAL
 
 
 def test_sizes_and_bounds(lib):
