@@ -189,6 +189,170 @@ def bench_batched(args):
     ctx.close()
 
 
+def bench_served(args):
+    """Open-loop replay of a served trace: uint16 2048x2048 streams arriving
+    in 32-plane slabs (ABS bound = 1e-4 x the range of a calibration volume,
+    FIXED threshold 6400, 26-connectivity, largest component) interleaved
+    with float32 cubes sent whole (Otsu, reduced at close), Poisson arrivals,
+    an HBM budget.  Latency = completion on the device - scheduled arrival
+    (queueing, admission waits, pinned H2D and compute included).  Then the
+    closed-loop capacity (everything submitted at once) and the host-resident
+    plain comparator (pinned H2D + fused call, one volume after another)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2602_15917_amd import roix
+
+    dev = "cuda:0"
+    SLAB = 32
+    t0 = time.time()
+    calib = synth.served_calibration(nz=8)
+    eb_s = 1e-4 * (float(calib.max()) - float(calib.min()))
+    crit_s = roix.Criterion("fixed", 6400.0, 26, "largest", 1)
+    streams = [torch.from_numpy(synth.served_stream(k, nz=args.served_nz)).pin_memory()
+               for k in range(args.served_streams)]
+    cubes = []
+    for k in range(args.served_cubes):
+        w = synth.served_cube(k)
+        c = w.criterion
+        cubes.append((torch.from_numpy(w.volume).pin_memory(), w.eb_mode, w.eb_value,
+                      roix.Criterion(c.thr, c.fixed_value, c.connectivity, c.keep, c.min_size)))
+    total = sum(t.numel() * t.element_size() for t in streams) + sum(c[0].numel() * 4 for c in cubes)
+    log(f"served trace: {len(streams)} u16 streams of {tuple(streams[0].shape) if streams else ()}, "
+        f"{len(cubes)} f32 cubes, {total / 1e9:.2f} GB, eb {eb_s:.4g}; generated in {time.time() - t0:.1f}s")
+    ctx = roix.Context(0, 1 << 20)
+
+    def outputs(t, crit):
+        dims = roix.dims_of(t)
+        dt = roix.dtype_of(t)
+        b = roix.bounds(dims, dt, crit)
+        return roix.Outputs(dev, b["rows"], t.numel() * 4 + 64, min(b["outliers"], 1 << 24),
+                            min(b["components"], 1 << 22))
+
+    outs_s = [outputs(t, crit_s) for t in streams]
+    outs_c = [outputs(c[0], c[3]) for c in cubes]
+    # the trace: every slab of every stream (in order) and every cube, interleaved at random
+    rng = np.random.default_rng(3000)
+    kinds = [("s", k, z) for k in range(len(streams)) for z in range(0, streams[k].shape[0], SLAB)]
+    kinds += [("c", k, 0) for k in range(len(cubes))]
+    order = rng.permutation(len(kinds))
+    events, nexts = [], [0] * len(streams)
+    for i in order:  # keep each stream's slabs in order: take its next slab instead
+        kind, k, _ = kinds[i]
+        if kind == "s":
+            events.append(("s", k, nexts[k] * SLAB))
+            nexts[k] += 1
+        else:
+            events.append(kinds[i])
+
+    def replay(rate):
+        srv = roix.Server(ctx, int(args.served_budget_gib * (1 << 30)))
+        # cubes whose Otsu threshold falls in the noise have ~nx/4 runs per row
+        srv.set_param("runs_per_row", 256)
+        t_base = time.perf_counter()
+        gaps = rng.exponential(1.0 / rate, size=len(events)) if rate > 0 else np.zeros(len(events))
+        arrivals = np.cumsum(gaps) * 1e3 + 5.0  # ms on the server clock
+        vid = {}
+        recs = []  # (req, arrival_ms, kind)
+        busy_ms = 0.0
+
+        def admit(shape, dt, ebm, ebv, crit, out):
+            nonlocal busy_ms
+            t = time.perf_counter()
+            while True:
+                try:
+                    return srv.open(shape, dt, ebm, ebv, crit, out)
+                except roix.RoixError as e:
+                    if e.status != roix.EBUSY:
+                        raise
+                    time.sleep(0.0005)
+                    busy_ms += 0.5
+                    if time.perf_counter() - t > 60:
+                        raise
+        for (kind, k, z0), arr in zip(events, arrivals):
+            now = (time.perf_counter() - t_base) * 1e3
+            if arr > now:
+                time.sleep((arr - now) * 1e-3)
+            if kind == "s":
+                t = streams[k]
+                if z0 == 0:
+                    vid[k] = admit(tuple(t.shape), roix.U16, "abs", eb_s, crit_s, outs_s[k])
+                recs.append((srv.submit(vid[k], z0, t[z0:z0 + SLAB]), arr, "slab"))
+                if z0 + SLAB >= t.shape[0]:
+                    recs.append((srv.close(vid[k]), arr, "stream_close"))
+            else:
+                t, ebm, ebv, crit = cubes[k]
+                v = admit(tuple(t.shape), roix.F32, ebm, ebv, crit, outs_c[k])
+                srv.submit(v, 0, t)
+                recs.append((srv.close(v), arr, "cube"))
+        lat = {"slab": [], "stream_close": [], "cube": []}
+        last = 0.0
+        for rid, arr, kind in recs:
+            res = srv.wait(rid)
+            if res is None or res.status != 0:
+                log(f"request {rid} failed")
+                sys.exit(1)
+            # server clock starts at its creation, t_base right after: offset < 1 ms
+            lat[kind].append(res.done_ms - arr)
+            last = max(last, res.done_ms)
+        st = srv.stats()
+        srv.close_server()
+        torch.cuda.synchronize()
+        bad = [(i, o.collect()["einfo"].status) for i, o in enumerate(outs_s + outs_c)]
+        bad = [b for b in bad if b[1] != 0]
+        if bad:
+            log(f"volumes (index, status) with a non-zero status: {bad}")
+            sys.exit(1)
+        q = lambda v, p: round(float(np.percentile(v, p)), 3) if v else None
+        return {"rate_per_s": rate, "requests": len(recs), "slab_p50_ms": q(lat["slab"], 50),
+                "slab_p99_ms": q(lat["slab"], 99), "stream_close_p50_ms": q(lat["stream_close"], 50),
+                "cube_p50_ms": q(lat["cube"], 50), "cube_p99_ms": q(lat["cube"], 99),
+                "makespan_ms": round(last - float(arrivals[0]), 1),
+                "gbs": round(total / ((last - float(arrivals[0])) * 1e-3) / 1e9, 2),
+                "refused_opens": int(st.volumes_refused), "admission_wait_ms": round(busy_ms, 1)}
+
+    rates = [float(r) for r in args.served_rates.split(",") if r]
+    res = {}
+    for rate in rates:
+        r = replay(rate)
+        log(f"rate {rate}/s: slab p50 {r['slab_p50_ms']} ms p99 {r['slab_p99_ms']} ms, cube p50 "
+            f"{r['cube_p50_ms']} ms, {r['gbs']} GB/s over {r['makespan_ms']} ms")
+        res[str(rate)] = r
+    cap = replay(0.0)  # closed loop: all requests at once
+    log(f"closed loop: {cap['gbs']} GB/s, slab p99 {cap['slab_p99_ms']} ms")
+    # host-resident plain comparator: pinned H2D + fused call per volume, sequentially
+    vols = [(t, "abs", eb_s, crit_s, o) for t, o in zip(streams, outs_s)] + \
+           [(c[0], c[1], c[2], c[3], o) for c, o in zip(cubes, outs_c)]
+    need = max(roix.scratch_bytes(roix.dims_of(v[0]), roix.dtype_of(v[0]), v[3]) for v in vols)
+    pctx = roix.Context(0, need)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for (h, ebm, ebv, crit, out) in vols:
+        d = h.to(dev, non_blocking=True)
+        pctx.fused(d, ebm, ebv, crit, out, stream)
+        del d
+    torch.cuda.synchronize()
+    host_plain = total / (time.perf_counter() - t) / 1e9
+    log(f"host-resident plain: {host_plain:.2f} GB/s")
+    main_rate = res[str(rates[0])] if rates else cap
+    line = {
+        "metric": METRIC, "value": cap["gbs"], "unit": "GB/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": cap["makespan_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u16+f32", "data": "synthetic",
+        "config": {"workload": f"served: {len(streams)} u16 streams 2048x2048x{args.served_nz} in {SLAB}-plane "
+                               f"slabs (ABS eb, FIXED 6400, 26-conn, largest) + {len(cubes)} f32 cubes "
+                               f"U{{128..512}} (Otsu), HBM budget {args.served_budget_gib:g} GiB",
+                   "input_bytes": total},
+        "served": {"rates": res, "closed_loop": cap, "host_resident_plain_gbs": round(host_plain, 2),
+                   "p99_slab_ms_at_first_rate": main_rate["slab_p99_ms"]},
+    }
+    print(json.dumps(line))
+    pctx.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,8 +365,14 @@ def main():
                     help="also run a plain device copy of 1 GiB (the counter calibration for traffic)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL_STATS_CSV"),
                     help="summarise rocprofv3 counter runs of this script and exit")
-    ap.add_argument("--workload", choices=["plain", "batched"], default="plain",
-                    help="plain: the 1024^3 volume (default); batched: 64 uneven volumes in one graph launch")
+    ap.add_argument("--workload", choices=["plain", "batched", "served"], default="plain",
+                    help="plain: the 1024^3 volume (default); batched: 64 uneven volumes in one graph launch; "
+                         "served: open-loop slab-stream trace with p50/p99 latency")
+    ap.add_argument("--served-streams", type=int, default=4, help="uint16 2048x2048 streams of the served trace")
+    ap.add_argument("--served-nz", type=int, default=256, help="planes per served stream (slabs of 32)")
+    ap.add_argument("--served-cubes", type=int, default=16, help="float32 cubes interleaved in the served trace")
+    ap.add_argument("--served-rates", default="20,10", help="Poisson arrival rates (requests/s) to replay")
+    ap.add_argument("--served-budget-gib", type=float, default=64.0)
     ap.add_argument("--batch-volumes", type=int, default=64)
     ap.add_argument("--batch-streams", type=int, default=4, help="concurrent streams of the batched path")
     ap.add_argument("--batch-graph", type=int, default=1, choices=[0, 1],
@@ -213,6 +383,8 @@ def main():
         return
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "served":
+        return bench_served(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the reduction path has no multi-GPU "
               f"form in this build", file=sys.stderr)

@@ -216,3 +216,31 @@ def batch_volume(j, seed_base=2000, with_cls=False, threads=None, side=(64, 512)
     vol, cls = ellipsoids(nx, ny, nz, seed, n_ell=n_ell, with_cls=with_cls, threads=threads)
     return Workload(f"batch[{j}]: {nx}x{ny}x{nz} f32, {n_ell} ellipsoids", vol, "abs", eb,
                     Criterion("otsu", 0.0, 6, "min_size", 64), cls, {"n_ell": n_ell})
+
+
+def served_calibration(seed=3999, nxy=2048, nz=8, threads=None) -> np.ndarray:
+    """The calibration volume of the served streams (rings recipe): its value
+    range sets the streams' absolute bound."""
+    vol, _ = rings(nxy, nxy, nz, seed, threads=threads)
+    return vol
+
+
+def served_stream(k, nz=256, nxy=2048, seed_base=3001, threads=None) -> np.ndarray:
+    """Stream k of the served trace: a uint16 rings volume (cylinder, Poisson
+    noise, ring artefacts) of nxy x nxy x nz, sent in 32-plane slabs."""
+    s = nxy / 2048.0
+    vol, _ = rings(nxy, nxy, nz, seed_base + k, R=633.0 * s, ring_rmax=1448.0 * s, threads=threads)
+    return vol
+
+
+def served_cube(k, seed_base=3100, side=(128, 512), threads=None) -> Workload:
+    """Cube k of the served trace: a float32 ellipsoid volume with sides drawn
+    from U{side} (the small-volume recipe), sent whole."""
+    seed = seed_base + k
+    r = philox4x32_10([k, 2, 0, 0], [seed & 0xFFFFFFFF, 0x5EED])
+    lo, hi = side
+    n = lo + r[0] % (hi - lo + 1)
+    n_ell = 1 + r[1] % 8
+    vol, _ = ellipsoids(n, n, n, seed, n_ell=n_ell, threads=threads)
+    return Workload(f"served cube {k}: {n}^3 f32, {n_ell} ellipsoids", vol, "abs", 1e-3,
+                    Criterion("otsu", 0.0, 6, "min_size", 64), None)
