@@ -133,6 +133,7 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t lane) {
 // Also clears the per-row outlier counters.
 __global__ __launch_bounds__(kBlock) void k_emit_index(Layout L, int64_t nrows) {
     if (thread_exit_e(L.S)) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) L.S->n_slow = 0u;
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += nthreads) {
         L.row_outl[r] = 0ull;
@@ -454,39 +455,212 @@ __device__ __forceinline__ void emit_chunk_many(const T* __restrict__ in, int64_
     }
 }
 
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+    return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
+}
+
+// Chunks of few spans (the common case of long rows) whose voxels lie within
+// 2^30 of the voxel V0 of the chunk's first code: every index is a 32-bit
+// byte offset from a uniform base (voxel = V0 + t + d of the code's span, t
+// the code's offset in the chunk), so loads and stores take the scalar-base +
+// 32-bit offset form.  Lane l < nr holds span l's start rs (0 for a span
+// begun before the chunk) and offset d.  Per slice of 256 codes the spans
+// are found by a uniform walk over the span starts: a slice without a start
+// is one span for every lane, and each start inside a slice costs every
+// lane one compare and select per code.  All loads of a step are issued
+// before any use.
 template <typename T, int B>
-__device__ __forceinline__ void emit_chunks(const T* __restrict__ in, int64_t nx, const Layout& L, const EmitOut& o,
-                                            bool& trunc) {
+__device__ __forceinline__ void emit_chunk_near(const T* __restrict__ in, const Layout& L, const EmitOut& o,
+                                                uint64_t c0, uint32_t n, uint32_t nr, uint32_t rs, uint32_t d,
+                                                uint32_t rid, uint64_t V0, bool& trunc) {
+    using C = typename CodeT<B>::type;
     const DevState* S = L.S;
-    const uint64_t n_codes = S->span_total & kLenMask;
-    const uint32_t n_rows = (uint32_t)(S->span_total >> 40);
-    const uint64_t nchunks = (n_codes + kEmitChunk - 1) / kEmitChunk;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
-    for (uint64_t q = (uint64_t)wave; q < nchunks; q += (uint64_t)nwaves) {
-        const uint64_t c0 = q * kEmitChunk;
-        const uint64_t c1 = c0 + kEmitChunk < n_codes ? c0 + kEmitChunk : n_codes;
-        const uint32_t j0 = L.chunk_row[q];
-        const uint32_t j1 = q + 1 < nchunks ? L.chunk_row[q + 1] : n_rows - 1;
-        if (j1 - j0 < (uint32_t)kFastSpans)
-            emit_chunk_fast<T, B>(in, nx, L, o, c0, c1, j0, j1 - j0 + 1, trunc);
-        else
-            emit_chunk_many<T, B>(in, nx, L, o, c0, c1, j0, j1, trunc);
+    const int lane = threadIdx.x % kWave;
+    const float r = S->r, w = S->w, eb32 = S->eb32;
+    const int32_t qmin = S->qmin;
+    const uint32_t esc = S->esc;
+    const uint8_t* base = reinterpret_cast<const uint8_t*>(in + V0);
+    const uint64_t vlim64 = o.nvox - V0;  // voxels from V0 to the end of the input
+    const uint32_t vlim = uni(vlim64 > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)vlim64);
+    uint8_t* cbase = o.stream + c0 * B;
+    const uint64_t cap = o.stream_cap / B;  // codes the stream holds
+    const uint32_t nfit = uni(cap <= c0 ? 0u : (cap - c0 >= n ? n : (uint32_t)(cap - c0)));
+    constexpr uint32_t kStep = (uint32_t)kEmitSlice * kEmitSlices;
+    constexpr uint32_t S_ = (uint32_t)sizeof(T);
+    uint32_t jcur = 0;  // the span of the current slice's first code
+    for (uint32_t s0 = 0; s0 < n; s0 += kStep) {
+        float xv[kEmitSlices][4];
+#pragma unroll
+        for (int k = 0; k < kEmitSlices; ++k) {
+            const uint32_t tk0 = s0 + (uint32_t)k * kEmitSlice;
+            const uint32_t t = tk0 + 4u * (uint32_t)lane;
+            while (jcur + 1 < nr && uni(__builtin_amdgcn_readlane(rs, jcur + 1)) <= tk0) jcur = uni(jcur + 1);
+            const uint32_t dc = uni(__builtin_amdgcn_readlane(d, jcur));
+            uint32_t di[4] = {dc, dc, dc, dc};
+            for (uint32_t j = jcur + 1; j < nr; j = uni(j + 1)) {  // starts inside this slice
+                const uint32_t sj = uni(__builtin_amdgcn_readlane(rs, j));
+                if (sj >= tk0 + (uint32_t)kEmitSlice) break;
+                const uint32_t dj = uni(__builtin_amdgcn_readlane(d, j));
+#pragma unroll
+                for (int i = 0; i < 4; ++i) di[i] = t + (uint32_t)i >= sj ? dj : di[i];
+            }
+            if (t + 4 <= n && di[0] == di[3] && t + di[0] + (uint32_t)quad_reach<T>() <= vlim) {
+                if constexpr (sizeof(T) == 4) {
+                    const v4u32_t q = __builtin_nontemporal_load(
+                        reinterpret_cast<const v4u32_t*>(base + (uint32_t)((t + di[0]) * S_)));
+                    xv[k][0] = __uint_as_float(q.x);
+                    xv[k][1] = __uint_as_float(q.y);
+                    xv[k][2] = __uint_as_float(q.z);
+                    xv[k][3] = __uint_as_float(q.w);
+                } else {
+                    load_quad(in, V0 + (uint64_t)(t + di[0]), xv[k]);
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    xv[k][i] = t + (uint32_t)i < n
+                                   ? (float)ld_stream(reinterpret_cast<const T*>(base + (uint32_t)((t + (uint32_t)i + di[i]) * S_)))
+                                   : 0.0f;
+            }
+        }
+        uint32_t outm[kEmitSlices];
+        uint32_t anyout = 0;
+#pragma unroll
+        for (int k = 0; k < kEmitSlices; ++k) {
+            const uint32_t t = s0 + (uint32_t)k * kEmitSlice + 4u * (uint32_t)lane;
+            uint32_t u[4];
+            uint32_t om = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float x = xv[k][i];
+                const int32_t q = qcode(x, r);
+                const bool ob = t + (uint32_t)i < n && outlier(x, q, w, eb32);
+                om |= ob ? (1u << i) : 0u;
+                u[i] = ob ? esc : (uint32_t)(q - qmin);
+            }
+            outm[k] = om;
+            anyout |= om;
+            uint8_t* dst = cbase + (uint32_t)(t * B);
+            if (t + 4 <= nfit) {
+                if constexpr (B == 1) {
+                    *reinterpret_cast<uint32_t*>(dst) = u[0] | (u[1] << 8) | (u[2] << 16) | (u[3] << 24);
+                } else if constexpr (B == 2) {
+                    *reinterpret_cast<uint2*>(dst) = make_uint2(u[0] | (u[1] << 16), u[2] | (u[3] << 16));
+                } else {
+                    *reinterpret_cast<uint4*>(dst) = make_uint4(u[0], u[1], u[2], u[3]);
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (t + (uint32_t)i >= n) continue;
+                    if (t + (uint32_t)i < nfit)
+                        reinterpret_cast<C*>(dst)[i] = (C)u[i];
+                    else
+                        trunc = true;
+                }
+            }
+        }
+        if (__ballot(anyout != 0)) {  // rare: per-span outlier counts
+#pragma unroll
+            for (int k = 0; k < kEmitSlices; ++k) {
+                const uint32_t t = s0 + (uint32_t)k * kEmitSlice + 4u * (uint32_t)lane;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    int jj = 0;
+                    for (uint32_t j = 1; j < nr; j = uni(j + 1))
+                        jj = t + (uint32_t)i >= uni(__builtin_amdgcn_readlane(rs, j)) ? (int)j : jj;
+                    const uint32_t rc = shfl32(rid, jj);  // every lane executes it
+                    if ((outm[k] >> i) & 1u) atomicAdd((unsigned long long*)&L.row_outl[rc], 1ull);
+                }
+            }
+        }
     }
+}
+
+// Chunk q's bounds and span range (uniform).
+__device__ __forceinline__ void chunk_of(const Layout& L, uint64_t q, uint64_t nchunks, uint64_t n_codes,
+                                         uint32_t n_rows, uint64_t& c0, uint64_t& c1, uint32_t& j0, uint32_t& j1) {
+    c0 = q * kEmitChunk;
+    c1 = c0 + kEmitChunk < n_codes ? c0 + kEmitChunk : n_codes;
+    j0 = uni(L.chunk_row[q]);
+    j1 = uni(q + 1 < nchunks ? L.chunk_row[q + 1] : n_rows - 1);
 }
 
 // The codes of every span voxel, in row order, as one flat stream: each wave
 // takes whole kEmitChunk-code chunks, so loads and stores are contiguous and
-// no lane idles on a short row.  B = bytes per code (uniform branch).
-// The code width is device data, so one kernel per width is launched and
-// the two that do not match return at once (keeps each kernel's registers
-// to its own width).
+// no lane idles on a short row.  This kernel runs the lean path for chunks
+// of at most kFastSpans spans within 2^30 voxels, and queues every other
+// chunk for k_emit_codes_general, so that its register budget stays that of
+// the lean path.  B = bytes per code: the code width is device data, so one
+// kernel per width is launched and the two that do not match return at once.
 template <typename T, int B>
 __global__ __launch_bounds__(kBlock) void k_emit_codes(const T* __restrict__ in, int64_t nx, Layout L, EmitOut o) {
     DevState* S = L.S;
     if (thread_exit_e(S) || S->width_bits != 8 * B) return;  // no barrier below
     bool trunc = false;
-    emit_chunks<T, B>(in, nx, L, o, trunc);
+    const uint64_t n_codes = uni64(S->span_total & kLenMask);
+    const uint32_t n_rows = uni((uint32_t)(S->span_total >> 40));
+    const uint64_t nchunks = (n_codes + kEmitChunk - 1) / kEmitChunk;
+    const int lane = threadIdx.x % kWave;
+    const uint64_t wave = uni((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+    const uint64_t nwaves = (uint64_t)gridDim.x * blockDim.x / kWave;
+    for (uint64_t q = wave; q < nchunks; q += nwaves) {
+        uint64_t c0, c1;
+        uint32_t j0, j1;
+        chunk_of(L, q, nchunks, n_codes, n_rows, c0, c1, j0, j1);
+        const uint32_t nr = j1 - j0 + 1;
+        bool near = false;
+        uint32_t rid = 0, rs = kNone, d = 0;
+        uint64_t off0 = 0;
+        if (nr <= (uint32_t)kFastSpans) {
+            uint64_t cs = ~0ull, off = 0;
+            if ((uint32_t)lane < nr) {
+                rid = L.nz_rows[j0 + lane];
+                cs = L.row_packed[rid] & kLenMask;
+                off = (uint64_t)rid * (uint64_t)nx + L.row_xs[rid] - cs;  // voxel = code + off
+            }
+            // the chunk's voxels are [V0, V0 + (c1 - 1 - c0) + d_last]: offsets
+            // never decrease from one span to the next
+            off0 = uni64(readlane64(off, 0));
+            const uint64_t dl = uni64(readlane64(off, nr - 1)) - off0;
+            near = (c1 - 1 - c0) + dl < (1ull << 30);
+            rs = (uint32_t)lane >= nr ? kNone : (cs <= c0 ? 0u : (uint32_t)(cs - c0));
+            d = (uint32_t)lane >= nr ? 0u : (uint32_t)(off - off0);
+        }
+        if (near) {
+            emit_chunk_near<T, B>(in, L, o, c0, (uint32_t)(c1 - c0), nr, rs, d, rid, c0 + off0, trunc);
+        } else if (lane == 0) {
+            L.slow_chunks[atomicAdd(&S->n_slow, 1u)] = (uint32_t)q;
+        }
+    }
+    if (trunc) atomicOr(&S->trunc, 1);
+}
+
+// The queued chunks: many short spans (lane windows with a cross-lane
+// search), or few spans whose voxels lie far apart (64-bit offsets).
+template <typename T, int B>
+__global__ __launch_bounds__(kBlock) void k_emit_codes_general(const T* __restrict__ in, int64_t nx, Layout L,
+                                                               EmitOut o) {
+    DevState* S = L.S;
+    if (thread_exit_e(S) || S->width_bits != 8 * B) return;  // no barrier below
+    bool trunc = false;
+    const uint64_t n_codes = uni64(S->span_total & kLenMask);
+    const uint32_t n_rows = uni((uint32_t)(S->span_total >> 40));
+    const uint64_t nchunks = (n_codes + kEmitChunk - 1) / kEmitChunk;
+    const uint32_t nq = uni(S->n_slow);
+    const uint32_t wave = uni((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+    const uint32_t nwaves = gridDim.x * blockDim.x / kWave;
+    for (uint32_t i = wave; i < nq; i += nwaves) {
+        const uint64_t q = uni(L.slow_chunks[i]);
+        uint64_t c0, c1;
+        uint32_t j0, j1;
+        chunk_of(L, q, nchunks, n_codes, n_rows, c0, c1, j0, j1);
+        if (j1 - j0 < (uint32_t)kFastSpans)
+            emit_chunk_fast<T, B>(in, nx, L, o, c0, c1, j0, j1 - j0 + 1, trunc);
+        else
+            emit_chunk_many<T, B>(in, nx, L, o, c0, c1, j0, j1, trunc);
+    }
     if (trunc) atomicOr(&S->trunc, 1);
 }
 
@@ -595,18 +769,19 @@ hipError_t launch_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, cons
     const dim3 grid_waves(lc.grid_stream);
     timer_begin(lc.timer, ST_EMIT, lc.stream);
     hipLaunchKernelGGL(k_emit_index, grid_rows_t, block, 0, lc.stream, L, g.nrows);
+    // every width's lean kernel before any general one (the queue must be complete)
+#define EMIT_LAUNCH(K, T_)                                                                                      \
+    hipLaunchKernelGGL((K<T_, 2>), grid_waves, block, 0, lc.stream, (const T_*)in, g.nx, L, o);                \
+    hipLaunchKernelGGL((K<T_, 1>), grid_waves, block, 0, lc.stream, (const T_*)in, g.nx, L, o);                \
+    hipLaunchKernelGGL((K<T_, 4>), grid_waves, block, 0, lc.stream, (const T_*)in, g.nx, L, o)
     if (dt == ROIX_F32) {
-        hipLaunchKernelGGL((k_emit_codes<float, 2>), grid_waves, block, 0, lc.stream, (const float*)in, g.nx, L, o);
-        hipLaunchKernelGGL((k_emit_codes<float, 1>), grid_waves, block, 0, lc.stream, (const float*)in, g.nx, L, o);
-        hipLaunchKernelGGL((k_emit_codes<float, 4>), grid_waves, block, 0, lc.stream, (const float*)in, g.nx, L, o);
+        EMIT_LAUNCH(k_emit_codes, float);
+        EMIT_LAUNCH(k_emit_codes_general, float);
     } else {
-        hipLaunchKernelGGL((k_emit_codes<uint16_t, 2>), grid_waves, block, 0, lc.stream, (const uint16_t*)in, g.nx, L,
-                           o);
-        hipLaunchKernelGGL((k_emit_codes<uint16_t, 1>), grid_waves, block, 0, lc.stream, (const uint16_t*)in, g.nx, L,
-                           o);
-        hipLaunchKernelGGL((k_emit_codes<uint16_t, 4>), grid_waves, block, 0, lc.stream, (const uint16_t*)in, g.nx, L,
-                           o);
+        EMIT_LAUNCH(k_emit_codes, uint16_t);
+        EMIT_LAUNCH(k_emit_codes_general, uint16_t);
     }
+#undef EMIT_LAUNCH
     timer_end(lc.timer, ST_EMIT, lc.stream);
     hipError_t e = launch_scan_u64(lc, L.row_outl, L.row_outl, g.nrows, &L.S->n_outliers, L.scan_tmp);
     if (e != hipSuccess) return e;
