@@ -50,8 +50,7 @@ struct DevState {
     // extraction
     unsigned long long span_total;  // (rows with a span) << 40 | (codes)
     unsigned long long n_outliers, q_outliers;
-    uint32_t n_outl_rows;
-    uint32_t n_slow;  // emit chunks queued for the general chunk kernel
+    uint32_t n_slow, pad2;  // emit chunks queued for the general chunk kernel
     // run number where the current labelling pass starts (0 for a whole
     // volume; the first run of the slab for a streamed slab)
     uint32_t seg_lo;
@@ -82,7 +81,6 @@ struct Layout {
     uint32_t* nz_rows;      // nrows: row of the i-th span
     uint32_t* chunk_row;    // N / kEmitChunk + 2: span holding the first code of each emit chunk
     uint32_t* slow_chunks;  // N / kEmitChunk + 2: chunks left to the general chunk kernel
-    uint32_t* out_list;     // nrows: rows whose span has outliers
     uint64_t* scan_tmp;     // kScanBlocks + 1
     uint64_t run_cap;
 };

@@ -664,90 +664,79 @@ __global__ __launch_bounds__(kBlock) void k_emit_codes_general(const T* __restri
     if (trunc) atomicOr(&S->trunc, 1);
 }
 
-// After the scan of the per-row outlier counts, one thread per span: its row
-// table entry (coalesced), and the span is queued when it has outliers.
-__global__ __launch_bounds__(kBlock) void k_emit_rows(Layout L, int64_t ny, int64_t nrows, EmitOut o) {
-    DevState* S = L.S;
-    if (thread_exit_e(S)) return;
-    const uint32_t n_rows = (uint32_t)(S->span_total >> 40);
-    const unsigned long long total = S->n_outliers;
-    bool trunc = false;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t jb = blockIdx.x * blockDim.x; jb < n_rows; jb += stride) {
-        const uint32_t j = jb + threadIdx.x;
-        if (jb + (threadIdx.x & ~(uint32_t)(kWave - 1)) >= n_rows) break;  // whole wave past the end
-        const bool valid = j < n_rows;
-        const uint32_t rid = valid ? L.nz_rows[j] : 0u;
-        const uint64_t ooff = L.row_outl[rid];
-        const uint64_t oend = (int64_t)rid + 1 < nrows ? L.row_outl[rid + 1] : total;
-        if (!valid) {
-        } else if (j < o.rows_cap) {
-            roix_row e;
-            e.z = (uint32_t)(rid / ny);
-            e.y = (uint32_t)(rid - (int64_t)e.z * ny);
-            e.xs = L.row_xs[rid];
-            e.xe = L.row_xe[rid];
-            e.code_off = L.row_packed[rid] & kLenMask;
-            e.outlier_off = ooff;
-            o.rows[j] = e;
-        } else {
-            trunc = true;
-        }
-        // queue spans with outliers: one atomic per wave (a single counter
-        // hit once per span would serialise)
-        const bool has = valid && oend != ooff;
-        const uint64_t m = __ballot(has);
-        if (m) {
-            const int lane = threadIdx.x % kWave;
-            const int leader = __ffsll((unsigned long long)m) - 1;
-            uint32_t basei = 0;
-            if (lane == leader) basei = atomicAdd(&S->n_outl_rows, (uint32_t)__popcll(m));
-            basei = (uint32_t)__shfl((int)basei, leader);
-            if (has) L.out_list[basei + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = rid;
-        }
-    }
-    if (trunc) atomicOr(&S->trunc, 1);
-}
-
-// One wave per queued span: read it once more and store its outlier values
-// in order at the span's outlier offset.
+// After the scan of the per-row outlier counts.  Each wave takes 64 spans,
+// one per lane: the lane writes its span's row table entry (coalesced), then
+// the wave takes the spans that have outliers (a ballot, no global queue)
+// one at a time, reads each once more and stores its outlier values in order
+// at the span's outlier offset.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_emit_outliers(const T* __restrict__ in, int64_t nx, Layout L, EmitOut o) {
+__global__ __launch_bounds__(kBlock) void k_emit_rows(const T* __restrict__ in, int64_t nx, Layout L, int64_t ny,
+                                                      int64_t nrows, EmitOut o) {
     DevState* S = L.S;
     if (thread_exit_e(S)) return;
-    const int lane = threadIdx.x % kWave;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+    const uint32_t n_rows = uni((uint32_t)(S->span_total >> 40));
+    const unsigned long long total = S->n_outliers;
     const float r = S->r, w = S->w, eb32 = S->eb32;
-    const uint32_t nl = S->n_outl_rows;
+    const int lane = threadIdx.x % kWave;
+    const uint32_t wave = uni((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+    const uint32_t nwaves = gridDim.x * blockDim.x / kWave;
     bool trunc = false;
-    for (int64_t i = wave; i < (int64_t)nl; i += nwaves) {
-        const uint32_t rid = L.out_list[i];
-        const uint32_t xs = L.row_xs[rid], len = L.row_xe[rid] - xs;
-        const T* src = in + (uint64_t)rid * (uint64_t)nx + xs;
-        unsigned long long k = L.row_outl[rid];
-        constexpr int U = 8;
-        for (uint32_t j0 = 0; j0 < len; j0 += kWave * U) {
-            float xv[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t j = j0 + u * kWave + lane;
-                xv[u] = j < len ? (float)src[j] : 0.0f;
+    for (uint64_t jb = (uint64_t)wave * kWave; jb < n_rows; jb += (uint64_t)nwaves * kWave) {
+        const uint32_t j = (uint32_t)jb + (uint32_t)lane;
+        const bool valid = j < n_rows;
+        uint32_t rid = 0, xs = 0, xe = 0;
+        uint64_t ooff = 0, oend = 0;
+        if (valid) {
+            rid = L.nz_rows[j];
+            ooff = L.row_outl[rid];
+            oend = (int64_t)rid + 1 < nrows ? L.row_outl[rid + 1] : total;
+            xs = L.row_xs[rid];
+            xe = L.row_xe[rid];
+            if (j < o.rows_cap) {
+                roix_row e;
+                e.z = rid / (uint32_t)ny;
+                e.y = rid - e.z * (uint32_t)ny;
+                e.xs = xs;
+                e.xe = xe;
+                e.code_off = L.row_packed[rid] & kLenMask;
+                e.outlier_off = ooff;
+                o.rows[j] = e;
+            } else {
+                trunc = true;
             }
+        }
+        uint64_t m = __ballot(valid && oend != ooff);
+        while (m) {  // uniform: the spans of this group that have outliers
+            const int l = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            const uint32_t srid = uni(__builtin_amdgcn_readlane(rid, l));
+            const uint32_t sxs = uni(__builtin_amdgcn_readlane(xs, l));
+            const uint32_t len = uni(__builtin_amdgcn_readlane(xe, l)) - sxs;
+            unsigned long long k = readlane64(ooff, l);
+            const T* src = in + (uint64_t)srid * (uint64_t)nx + sxs;
+            constexpr int U = 8;
+            for (uint32_t j0 = 0; j0 < len; j0 += kWave * U) {
+                float xv[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t j = j0 + u * kWave + lane;
-                const float x = xv[u];
-                const bool isout = j < len && outlier(x, qcode(x, r), w, eb32);
-                const uint64_t m = __ballot(isout);
-                if (isout) {
-                    const unsigned long long at = k + (unsigned long long)__popcll(m & ((1ull << lane) - 1ull));
-                    if (at < o.outl_cap)
-                        o.outl[at] = x;
-                    else
-                        trunc = true;
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t jj = j0 + u * kWave + lane;
+                    xv[u] = jj < len ? (float)src[jj] : 0.0f;
                 }
-                k += (unsigned long long)__popcll(m);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t jj = j0 + u * kWave + lane;
+                    const float x = xv[u];
+                    const bool isout = jj < len && outlier(x, qcode(x, r), w, eb32);
+                    const uint64_t mo = __ballot(isout);
+                    if (isout) {
+                        const unsigned long long at = k + (unsigned long long)__popcll(mo & ((1ull << lane) - 1ull));
+                        if (at < o.outl_cap)
+                            o.outl[at] = x;
+                        else
+                            trunc = true;
+                    }
+                    k += (unsigned long long)__popcll(mo);
+                }
             }
         }
     }
@@ -786,11 +775,12 @@ hipError_t launch_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, cons
     hipError_t e = launch_scan_u64(lc, L.row_outl, L.row_outl, g.nrows, &L.S->n_outliers, L.scan_tmp);
     if (e != hipSuccess) return e;
     timer_begin(lc.timer, ST_EMIT_ROWS, lc.stream);
-    hipLaunchKernelGGL(k_emit_rows, grid_rows_t, block, 0, lc.stream, L, g.ny, g.nrows, o);
     if (dt == ROIX_F32)
-        hipLaunchKernelGGL(k_emit_outliers<float>, grid_waves, block, 0, lc.stream, (const float*)in, g.nx, L, o);
+        hipLaunchKernelGGL(k_emit_rows<float>, grid_rows_t, block, 0, lc.stream, (const float*)in, g.nx, L, g.ny,
+                           g.nrows, o);
     else
-        hipLaunchKernelGGL(k_emit_outliers<uint16_t>, grid_waves, block, 0, lc.stream, (const uint16_t*)in, g.nx, L, o);
+        hipLaunchKernelGGL(k_emit_rows<uint16_t>, grid_rows_t, block, 0, lc.stream, (const uint16_t*)in, g.nx, L, g.ny,
+                           g.nrows, o);
     timer_end(lc.timer, ST_EMIT_ROWS, lc.stream);
     return hipGetLastError();
 }

@@ -371,13 +371,14 @@ constexpr int kSegMin = 2048;
 constexpr int kSegBlock = 1024;
 constexpr int kCrossCap = 4096;  // distinct root pairs per segment head (32 KB)
 
-// T: the launch parameter when set (a multiple of 256 in [256, kSegCap]),
-// else n spread over G workgroups, clamped.  Both levels use the same G.
-__device__ __forceinline__ uint32_t seg_runs(uint32_t n, uint32_t G, uint32_t param) {
+// T: the launch parameter when set (a multiple of 256 in [256, cap]), else n
+// spread over G workgroups, clamped to [kSegMin, cap].  Both levels use the
+// same G and cap, so they see the same segments.
+__device__ __forceinline__ uint32_t seg_runs(uint32_t n, uint32_t G, uint32_t param, uint32_t cap) {
     if (param) return param;
     uint32_t t = (uint32_t)(((uint64_t)n + G - 1) / G);
     t = (t + 255u) & ~255u;
-    return t < (uint32_t)kSegMin ? (uint32_t)kSegMin : (t > (uint32_t)kSegCap ? (uint32_t)kSegCap : t);
+    return t < (uint32_t)kSegMin ? (uint32_t)kSegMin : (t > cap ? cap : t);
 }
 
 // (z, y) of row r = z * ny + y: a double estimate, then an exact correction.
@@ -436,7 +437,7 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_label(const uint32_t* __restr
     if (block_exit_l(S)) return;
     const uint32_t n = S->n_runs, lo = S->seg_lo;
     if (n <= lo) return;
-    const uint32_t T = seg_runs(n - lo, G, tparam);
+    const uint32_t T = seg_runs(n - lo, G, tparam, (uint32_t)kSegCap);
     const uint32_t nseg = (n - lo + T - 1) / T;
     for (uint32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
         const uint32_t s0 = lo + sg * T, s1 = (n - s0 < T) ? n : s0 + T, m = s1 - s0;
@@ -488,7 +489,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_cross(const uint32_t* __restrict
     if (block_exit_l(S)) return;
     const uint32_t n = S->n_runs, lo = S->seg_lo;
     if (n <= lo) return;
-    const uint32_t T = seg_runs(n - lo, G, tparam);
+    const uint32_t T = seg_runs(n - lo, G, tparam, (uint32_t)kSegCap);
     const uint32_t nseg = (n - lo + T - 1) / T;
     // the very first segment of a volume has nothing before it
     for (uint32_t sg = (lo == 0 ? 1u : 0u) + blockIdx.x; sg < nseg; sg += gridDim.x) {
@@ -546,6 +547,173 @@ __global__ __launch_bounds__(kBlock) void k_seg_cross(const uint32_t* __restrict
     }
 }
 
+// ---------------------------------------------- staged (LDS) segment kernels
+//
+// The same two levels with the data a segment touches copied to LDS first
+// (one coalesced pass), so that the binary searches, merges and unions run
+// on LDS instead of chains of dependent global loads.  Run extents are
+// packed as xs | xe << 16 (rows of at most 65535 voxels).  A segment whose
+// rows (or a head whose earlier rows) do not fit the staging arrays reads
+// those from global memory instead.
+
+constexpr int kLSeg = 8192;    // runs of a staged segment
+constexpr int kLRows = 3072;   // row offsets staged per segment (rows + 1)
+constexpr int kHalo = 6144;    // runs of the earlier rows staged for level 2
+constexpr int kHaloRows = 3072;
+
+__device__ __forceinline__ uint32_t px(uint32_t v) { return v & 0xFFFFu; }
+__device__ __forceinline__ uint32_t pe(uint32_t v) { return v >> 16; }
+
+// first entry of lx[b0, b1) whose end reaches as (the packed form of first_touch)
+template <bool C26>
+__device__ __forceinline__ uint32_t first_touch_p(const uint32_t* lx, uint32_t b0, uint32_t b1, uint32_t as) {
+    while (b0 < b1) {
+        const uint32_t mid = b0 + ((b1 - b0) >> 1);
+        const uint32_t e = pe(lx[mid]);
+        if (C26 ? e >= as : e > as)
+            b1 = mid;
+        else
+            b0 = mid + 1;
+    }
+    return b0;
+}
+
+template <bool C26>
+__global__ __launch_bounds__(kSegBlock) void k_seg_label_lds(const uint32_t* __restrict__ run_off,
+                                                             const uint32_t* __restrict__ xs,
+                                                             const uint32_t* __restrict__ xe,
+                                                             const uint32_t* __restrict__ run_row, uint32_t* parent,
+                                                             uint32_t ny, double inv_ny, uint32_t G,
+                                                             uint32_t tparam, const DevState* S) {
+    __shared__ uint32_t lp[kLSeg];
+    __shared__ uint32_t lx[kLSeg];
+    __shared__ uint32_t loff[kLRows];
+    if (block_exit_l(S)) return;
+    const uint32_t n = S->n_runs, lo = S->seg_lo;
+    if (n <= lo) return;
+    const uint32_t T = seg_runs(n - lo, G, tparam, (uint32_t)kLSeg);
+    const uint32_t nseg = (n - lo + T - 1) / T;
+    for (uint32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
+        const uint32_t s0 = lo + sg * T, s1 = (n - s0 < T) ? n : s0 + T, m = s1 - s0;
+        const uint32_t rf = run_row[s0], rl = run_row[s1 - 1];
+        const bool rows_in = rl - rf + 2 <= (uint32_t)kLRows;  // offsets of rows rf .. rl + 1
+        for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+            lp[i] = i;
+            lx[i] = xs[s0 + i] | (xe[s0 + i] << 16);
+        }
+        if (rows_in)
+            for (uint32_t i = threadIdx.x; i < rl - rf + 2; i += blockDim.x) loff[i] = run_off[rf + i];
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+            const uint32_t r = run_row[s0 + i];
+            uint32_t z, y;
+            row_zy(r, ny, inv_ny, z, y);
+            const uint32_t as = px(lx[i]), ae = pe(lx[i]);
+            for_back_rows<C26>(r, z, y, ny, [&](uint32_t rb) {
+                if (rb < rf) return;  // rows before the segment's first row hold only earlier runs
+                uint32_t b0 = rows_in ? loff[rb - rf] : run_off[rb];
+                const uint32_t b1 = rows_in ? loff[rb - rf + 1] : run_off[rb + 1];
+                if (b1 <= s0) return;
+                if (b0 < s0) b0 = s0;
+                for (uint32_t b = first_touch_p<C26>(lx, b0 - s0, b1 - s0, as); b < b1 - s0; ++b) {
+                    const uint32_t bs = px(lx[b]);
+                    if (C26 ? bs > ae : bs >= ae) break;
+                    lunite(lp, i, b);
+                }
+            });
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+            uint32_t q = i;
+            while (lp[q] != q) q = lp[q];
+            parent[s0 + i] = s0 + q;
+        }
+        __syncthreads();  // the arrays are reused by the next segment
+    }
+}
+
+template <bool C26>
+__global__ __launch_bounds__(kSegBlock) void k_seg_cross_lds(const uint32_t* __restrict__ run_off,
+                                                             const uint32_t* __restrict__ xs,
+                                                             const uint32_t* __restrict__ xe,
+                                                             const uint32_t* __restrict__ run_row, uint32_t* parent,
+                                                             uint32_t ny, double inv_ny, uint32_t G,
+                                                             uint32_t tparam, const DevState* S) {
+    __shared__ unsigned long long tab[kCrossCap];
+    __shared__ uint32_t hx[kHalo];
+    __shared__ uint32_t hp[kHalo];
+    __shared__ uint32_t hoff[kHaloRows];
+    constexpr unsigned long long kEmpty = ~0ull;
+    if (block_exit_l(S)) return;
+    const uint32_t n = S->n_runs, lo = S->seg_lo;
+    if (n <= lo) return;
+    const uint32_t T = seg_runs(n - lo, G, tparam, (uint32_t)kLSeg);
+    const uint32_t nseg = (n - lo + T - 1) / T;
+    for (uint32_t sg = (lo == 0 ? 1u : 0u) + blockIdx.x; sg < nseg; sg += gridDim.x) {
+        const uint32_t s0 = lo + sg * T, s1 = (n - s0 < T) ? n : s0 + T;
+        for (int i = threadIdx.x; i < kCrossCap; i += blockDim.x) tab[i] = kEmpty;
+        const uint32_t r0 = run_row[s0];  // rows after r0 hold only runs > s0
+        const uint64_t rlast = (uint64_t)r0 + ny + 1;
+        // the halo: earlier runs of rows hr0 .. r0, the only rows a head run can reach back to
+        const uint32_t hr0 = r0 > ny ? r0 - ny - 1 : 0u;
+        const uint32_t h0 = run_off[hr0];
+        const bool staged = s0 - h0 <= (uint32_t)kHalo && r0 - hr0 + 2 <= (uint32_t)kHaloRows;
+        if (staged) {
+            for (uint32_t i = threadIdx.x; i < s0 - h0; i += blockDim.x) {
+                hx[i] = xs[h0 + i] | (xe[h0 + i] << 16);
+                hp[i] = parent[h0 + i];
+            }
+            for (uint32_t i = threadIdx.x; i < r0 - hr0 + 2; i += blockDim.x) hoff[i] = run_off[hr0 + i];
+        }
+        __syncthreads();
+        uint32_t last_a = kNone, last_b = kNone;
+        for (uint32_t a = s0 + threadIdx.x; a < s1; a += blockDim.x) {
+            const uint32_t r = run_row[a];
+            if (r > rlast) break;
+            uint32_t z, y;
+            row_zy(r, ny, inv_ny, z, y);
+            const uint32_t as = xs[a], ae = xe[a];
+            uint32_t ra = kNone;
+            for_back_rows<C26>(r, z, y, ny, [&](uint32_t rb) {
+                if (rb > r0) return;
+                const uint32_t b0 = staged ? hoff[rb - hr0] : run_off[rb];
+                uint32_t b1 = staged ? hoff[rb - hr0 + 1] : run_off[rb + 1];
+                if (b1 > s0) b1 = s0;
+                if (b0 >= b1) return;
+                const uint32_t bb = staged ? first_touch_p<C26>(hx, b0 - h0, b1 - h0, as) + h0
+                                           : first_touch<C26>(xe, b0, b1, as);
+                for (uint32_t b = bb; b < b1; ++b) {
+                    const uint32_t bs = staged ? px(hx[b - h0]) : xs[b];
+                    if (C26 ? bs > ae : bs >= ae) break;
+                    if (ra == kNone) ra = parent[a];
+                    const uint32_t rbb = staged ? hp[b - h0] : parent[b];
+                    if (ra == last_a && rbb == last_b) continue;
+                    last_a = ra;
+                    last_b = rbb;
+                    const unsigned long long key = ((unsigned long long)ra << 32) | rbb;
+                    uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 52) & (kCrossCap - 1);
+                    bool done = false;
+                    for (int pr = 0; pr < 8; ++pr) {
+                        const unsigned long long old = atomicCAS(&tab[h], kEmpty, key);
+                        if (old == kEmpty || old == key) {
+                            done = true;
+                            break;
+                        }
+                        h = (h + 1) & (kCrossCap - 1);
+                    }
+                    if (!done) unite(parent, ra, rbb);
+                }
+            });
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < kCrossCap; i += blockDim.x) {
+            const unsigned long long key = tab[i];
+            if (key != kEmpty) unite(parent, (uint32_t)(key >> 32), (uint32_t)key);
+        }
+        __syncthreads();  // the arrays are reused by the next segment
+    }
+}
+
 hipError_t launch_union(const LaunchCtx& lc, const Geom& g, const Layout& L, int conn) {
     timer_begin(lc.timer, ST_UNION, lc.stream);
     const uint32_t G = (uint32_t)lc.seg_grid;
@@ -553,21 +721,31 @@ hipError_t launch_union(const LaunchCtx& lc, const Geom& g, const Layout& L, int
     const double inv_ny = 1.0 / (double)g.ny;
     const uint32_t tp = (uint32_t)lc.seg_runs;
     const dim3 grid(G);
-    if (conn == 26) {
-        hipLaunchKernelGGL(k_seg_label<true>, grid, dim3(kSegBlock), 0, lc.stream, (const uint32_t*)L.run_off,
-                           (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, (const uint32_t*)L.run_row,
-                           L.parent, ny, inv_ny, G, tp, (const DevState*)L.S);
-        hipLaunchKernelGGL(k_seg_cross<true>, grid, dim3(kBlock), 0, lc.stream, (const uint32_t*)L.run_off,
-                           (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, (const uint32_t*)L.run_row,
-                           L.parent, ny, inv_ny, g.nrows, G, tp, (const DevState*)L.S);
-    } else {
-        hipLaunchKernelGGL(k_seg_label<false>, grid, dim3(kSegBlock), 0, lc.stream, (const uint32_t*)L.run_off,
-                           (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, (const uint32_t*)L.run_row,
-                           L.parent, ny, inv_ny, G, tp, (const DevState*)L.S);
-        hipLaunchKernelGGL(k_seg_cross<false>, grid, dim3(kBlock), 0, lc.stream, (const uint32_t*)L.run_off,
-                           (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, (const uint32_t*)L.run_row,
-                           L.parent, ny, inv_ny, g.nrows, G, tp, (const DevState*)L.S);
+    // staged kernels: rows of at most 65535 voxels (packed extents) and
+    // segments of at most kLSeg runs
+    const bool staged = g.nx <= 65535 && tp <= (uint32_t)kLSeg;
+#define SEG_LAUNCH(C)                                                                                           \
+    if (staged) {                                                                                               \
+        hipLaunchKernelGGL(k_seg_label_lds<C>, grid, dim3(kSegBlock), 0, lc.stream, (const uint32_t*)L.run_off,  \
+                           (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, (const uint32_t*)L.run_row,    \
+                           L.parent, ny, inv_ny, G, tp, (const DevState*)L.S);                                  \
+        hipLaunchKernelGGL(k_seg_cross_lds<C>, grid, dim3(kSegBlock), 0, lc.stream, (const uint32_t*)L.run_off,  \
+                           (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, (const uint32_t*)L.run_row,    \
+                           L.parent, ny, inv_ny, G, tp, (const DevState*)L.S);                                  \
+    } else {                                                                                                    \
+        hipLaunchKernelGGL(k_seg_label<C>, grid, dim3(kSegBlock), 0, lc.stream, (const uint32_t*)L.run_off,      \
+                           (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, (const uint32_t*)L.run_row,    \
+                           L.parent, ny, inv_ny, G, tp, (const DevState*)L.S);                                  \
+        hipLaunchKernelGGL(k_seg_cross<C>, grid, dim3(kBlock), 0, lc.stream, (const uint32_t*)L.run_off,         \
+                           (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, (const uint32_t*)L.run_row,    \
+                           L.parent, ny, inv_ny, g.nrows, G, tp, (const DevState*)L.S);                         \
     }
+    if (conn == 26) {
+        SEG_LAUNCH(true)
+    } else {
+        SEG_LAUNCH(false)
+    }
+#undef SEG_LAUNCH
     timer_end(lc.timer, ST_UNION, lc.stream);
     return hipGetLastError();
 }

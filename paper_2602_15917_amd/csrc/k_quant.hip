@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kBlock) void k_init(DevState* S) {
             S->bbox[1] = S->bbox[3] = S->bbox[5] = 0u;
             S->n_kept = S->n_kept_voxels = 0ull;
             S->span_total = S->n_outliers = S->q_outliers = 0ull;
-            S->n_outl_rows = 0u;
+            S->n_slow = 0u;
             S->qstatus = 0;
             S->seg_lo = 0u;
             S->saved_status = 0;
