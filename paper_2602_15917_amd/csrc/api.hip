@@ -75,6 +75,7 @@ size_t roix::fixed_bytes(const Geom& g, bool with_proxy) {
     b += align256((size_t)g.nrows * 8);                   // row_packed
     b += align256((size_t)g.nrows * 8);                   // row_outl
     b += align256((size_t)g.nrows * 4);                   // nz_rows
+    b += align256((size_t)g.nrows * 16);                  // span_desc
     b += 2 * align256((size_t)(g.N / kEmitChunk + 2) * 4);  // chunk_row, slow_chunks
     b += align256((size_t)(kScanBlocks + 1) * 8);         // scan tmp
     b += 6 * 256;                                         // run-array alignment slack
@@ -100,6 +101,7 @@ bool roix::carve_at(void* base, size_t bytes, const Geom& g, Layout* L, bool wit
     L->row_packed = (uint64_t*)take((size_t)g.nrows * 8);
     L->row_outl = (uint64_t*)take((size_t)g.nrows * 8);
     L->nz_rows = (uint32_t*)take((size_t)g.nrows * 4);
+    L->span_desc = (uint64_t*)take((size_t)g.nrows * 16);
     L->chunk_row = (uint32_t*)take((size_t)(g.N / kEmitChunk + 2) * 4);
     L->slow_chunks = (uint32_t*)take((size_t)(g.N / kEmitChunk + 2) * 4);
     L->scan_tmp = (uint64_t*)take((size_t)(kScanBlocks + 1) * 8);

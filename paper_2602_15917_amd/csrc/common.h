@@ -79,6 +79,7 @@ struct Layout {
     uint64_t* row_packed;   // nrows (has_span << 40 | span length), scanned in place
     uint64_t* row_outl;     // nrows: outliers per row, then their exclusive scan
     uint32_t* nz_rows;      // nrows: row of the i-th span
+    uint64_t* span_desc;    // 2 * nrows: per span, its first code and voxel - code offset
     uint32_t* chunk_row;    // N / kEmitChunk + 2: span holding the first code of each emit chunk
     uint32_t* slow_chunks;  // N / kEmitChunk + 2: chunks left to the general chunk kernel
     uint64_t* scan_tmp;     // kScanBlocks + 1

@@ -129,9 +129,10 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t lane) {
 }
 
 // Index of the flat code space, one thread per row: nz_rows[ridx] = row of
-// the ridx-th span, chunk_row[q] = ridx of the span holding code q * chunk.
-// Also clears the per-row outlier counters.
-__global__ __launch_bounds__(kBlock) void k_emit_index(Layout L, int64_t nrows) {
+// the ridx-th span, span_desc[ridx] = its first code and voxel offset,
+// chunk_row[q] = ridx of the span holding code q * chunk.  Also clears the
+// per-row outlier counters.
+__global__ __launch_bounds__(kBlock) void k_emit_index(Layout L, int64_t nx, int64_t nrows) {
     if (thread_exit_e(L.S)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) L.S->n_slow = 0u;
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
@@ -143,6 +144,10 @@ __global__ __launch_bounds__(kBlock) void k_emit_index(Layout L, int64_t nrows) 
         const uint32_t ridx = (uint32_t)(packed >> 40);
         const uint64_t code0 = packed & kLenMask, code1 = code0 + (xe - xs);
         L.nz_rows[ridx] = (uint32_t)r;
+        // descriptor for the emit: first code, and voxel = code + offset
+        const uint64_t off = (uint64_t)r * (uint64_t)nx + xs - code0;
+        *reinterpret_cast<uint4*>(L.span_desc + 2 * (uint64_t)ridx) =
+            make_uint4((uint32_t)code0, (uint32_t)(code0 >> 32), (uint32_t)off, (uint32_t)(off >> 32));
         for (uint64_t q = (code0 + kEmitChunk - 1) / kEmitChunk; q * kEmitChunk < code1; ++q) L.chunk_row[q] = ridx;
     }
 }
@@ -488,39 +493,81 @@ __device__ __forceinline__ void emit_chunk_near(const T* __restrict__ in, const 
     const uint32_t nfit = uni(cap <= c0 ? 0u : (cap - c0 >= n ? n : (uint32_t)(cap - c0)));
     constexpr uint32_t kStep = (uint32_t)kEmitSlice * kEmitSlices;
     constexpr uint32_t S_ = (uint32_t)sizeof(T);
-    uint32_t jcur = 0;  // the span of the current slice's first code
+    // a whole-quad load reads quad_reach voxels; a volume too short for one
+    // at V0 takes the code-by-code loads only
+    const bool quads = vlim >= (uint32_t)quad_reach<T>();
+    // slice table, lane k for slice k of the chunk: the span of the slice's
+    // first code, and whether another span starts inside the slice
+    uint32_t jkv = 0, hkv = 0;
+    {
+        const uint32_t tk = (uint32_t)lane * (uint32_t)kEmitSlice;
+        for (uint32_t j = 1; j < nr; j = uni(j + 1)) {
+            const uint32_t sj = uni(__builtin_amdgcn_readlane(rs, j));
+            jkv += sj <= tk ? 1u : 0u;
+            hkv |= (sj > tk && sj < tk + (uint32_t)kEmitSlice) ? 1u : 0u;
+        }
+    }
     for (uint32_t s0 = 0; s0 < n; s0 += kStep) {
         float xv[kEmitSlices][4];
+        uint32_t split = 0;  // slices whose quad is not one contiguous load for some lane
+        // phase 1: one quad load per lane and slice, no branches (a split quad
+        // loads from voxel V0 and is redone in phase 2), so that every load of
+        // the step is in flight before any wait
 #pragma unroll
         for (int k = 0; k < kEmitSlices; ++k) {
             const uint32_t tk0 = s0 + (uint32_t)k * kEmitSlice;
             const uint32_t t = tk0 + 4u * (uint32_t)lane;
-            while (jcur + 1 < nr && uni(__builtin_amdgcn_readlane(rs, jcur + 1)) <= tk0) jcur = uni(jcur + 1);
-            const uint32_t dc = uni(__builtin_amdgcn_readlane(d, jcur));
+            const uint32_t kk = tk0 / (uint32_t)kEmitSlice;
+            const uint32_t jc = uni(__builtin_amdgcn_readlane(jkv, kk));
+            const uint32_t dc = uni(__builtin_amdgcn_readlane(d, jc));
+            uint32_t d0 = dc, d3 = dc;
+            if (uni(__builtin_amdgcn_readlane(hkv, kk))) {
+                for (uint32_t j = jc + 1; j < nr; j = uni(j + 1)) {  // starts inside this slice
+                    const uint32_t sj = uni(__builtin_amdgcn_readlane(rs, j));
+                    if (sj >= tk0 + (uint32_t)kEmitSlice) break;
+                    const uint32_t dj = uni(__builtin_amdgcn_readlane(d, j));
+                    d0 = t >= sj ? dj : d0;
+                    d3 = t + 3 >= sj ? dj : d3;
+                }
+            }
+            const bool full = quads && t + 4 <= n && d0 == d3 && t + d0 + (uint32_t)quad_reach<T>() <= vlim;
+            if (__ballot(!full)) split |= 1u << k;
+            const uint32_t vi = full ? t + d0 : 0u;  // voxels V0 .. V0 + quad_reach - 1 exist when quads holds
+            if (!quads) {  // uniform
+#pragma unroll
+                for (int i = 0; i < 4; ++i) xv[k][i] = 0.0f;
+            } else if constexpr (sizeof(T) == 4) {
+                const v4u32_t q = __builtin_nontemporal_load(reinterpret_cast<const v4u32_t*>(base + vi * S_));
+                xv[k][0] = __uint_as_float(q.x);
+                xv[k][1] = __uint_as_float(q.y);
+                xv[k][2] = __uint_as_float(q.z);
+                xv[k][3] = __uint_as_float(q.w);
+            } else {
+                load_quad(in, V0 + (uint64_t)vi, xv[k]);
+            }
+        }
+        // phase 2: the split quads, code by code (rare outside slices with span starts)
+#pragma unroll
+        for (int k = 0; k < kEmitSlices; ++k) {
+            if (!((split >> k) & 1u)) continue;  // uniform
+            const uint32_t tk0 = s0 + (uint32_t)k * kEmitSlice;
+            const uint32_t t = tk0 + 4u * (uint32_t)lane;
+            const uint32_t j0k = uni(__builtin_amdgcn_readlane(jkv, tk0 / (uint32_t)kEmitSlice));
+            const uint32_t dc = uni(__builtin_amdgcn_readlane(d, j0k));
             uint32_t di[4] = {dc, dc, dc, dc};
-            for (uint32_t j = jcur + 1; j < nr; j = uni(j + 1)) {  // starts inside this slice
+            for (uint32_t j = j0k + 1; j < nr; j = uni(j + 1)) {
                 const uint32_t sj = uni(__builtin_amdgcn_readlane(rs, j));
                 if (sj >= tk0 + (uint32_t)kEmitSlice) break;
                 const uint32_t dj = uni(__builtin_amdgcn_readlane(d, j));
 #pragma unroll
                 for (int i = 0; i < 4; ++i) di[i] = t + (uint32_t)i >= sj ? dj : di[i];
             }
-            if (t + 4 <= n && di[0] == di[3] && t + di[0] + (uint32_t)quad_reach<T>() <= vlim) {
-                if constexpr (sizeof(T) == 4) {
-                    const v4u32_t q = __builtin_nontemporal_load(
-                        reinterpret_cast<const v4u32_t*>(base + (uint32_t)((t + di[0]) * S_)));
-                    xv[k][0] = __uint_as_float(q.x);
-                    xv[k][1] = __uint_as_float(q.y);
-                    xv[k][2] = __uint_as_float(q.z);
-                    xv[k][3] = __uint_as_float(q.w);
-                } else {
-                    load_quad(in, V0 + (uint64_t)(t + di[0]), xv[k]);
-                }
-            } else {
+            const bool full = quads && t + 4 <= n && di[0] == di[3] && t + di[0] + (uint32_t)quad_reach<T>() <= vlim;
+            if (!full) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
                     xv[k][i] = t + (uint32_t)i < n
-                                   ? (float)ld_stream(reinterpret_cast<const T*>(base + (uint32_t)((t + (uint32_t)i + di[i]) * S_)))
+                                   ? (float)ld_stream(reinterpret_cast<const T*>(base + (t + (uint32_t)i + di[i]) * S_))
                                    : 0.0f;
             }
         }
@@ -590,7 +637,7 @@ __device__ __forceinline__ void chunk_of(const Layout& L, uint64_t q, uint64_t n
 // The codes of every span voxel, in row order, as one flat stream: each wave
 // takes whole kEmitChunk-code chunks, so loads and stores are contiguous and
 // no lane idles on a short row.  This kernel runs the lean path for chunks
-// of at most kFastSpans spans within 2^30 voxels, and queues every other
+// of at most 64 spans (one per lane) within 2^30 voxels, and queues every other
 // chunk for k_emit_codes_general, so that its register budget stays that of
 // the lean path.  B = bytes per code: the code width is device data, so one
 // kernel per width is launched and the two that do not match return at once.
@@ -613,12 +660,13 @@ __global__ __launch_bounds__(kBlock) void k_emit_codes(const T* __restrict__ in,
         bool near = false;
         uint32_t rid = 0, rs = kNone, d = 0;
         uint64_t off0 = 0;
-        if (nr <= (uint32_t)kFastSpans) {
+        if (nr <= (uint32_t)kWave) {
             uint64_t cs = ~0ull, off = 0;
             if ((uint32_t)lane < nr) {
+                const uint4 sd = *reinterpret_cast<const uint4*>(L.span_desc + 2 * (uint64_t)(j0 + lane));
+                cs = ((uint64_t)sd.y << 32) | sd.x;
+                off = ((uint64_t)sd.w << 32) | sd.z;  // voxel = code + off
                 rid = L.nz_rows[j0 + lane];
-                cs = L.row_packed[rid] & kLenMask;
-                off = (uint64_t)rid * (uint64_t)nx + L.row_xs[rid] - cs;  // voxel = code + off
             }
             // the chunk's voxels are [V0, V0 + (c1 - 1 - c0) + d_last]: offsets
             // never decrease from one span to the next
@@ -757,7 +805,7 @@ hipError_t launch_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, cons
     const dim3 grid_rows_t(grid_rows(g.nrows, kBlock, lc.grid_stream));
     const dim3 grid_waves(lc.grid_stream);
     timer_begin(lc.timer, ST_EMIT, lc.stream);
-    hipLaunchKernelGGL(k_emit_index, grid_rows_t, block, 0, lc.stream, L, g.nrows);
+    hipLaunchKernelGGL(k_emit_index, grid_rows_t, block, 0, lc.stream, L, g.nx, g.nrows);
     // every width's lean kernel before any general one (the queue must be complete)
 #define EMIT_LAUNCH(K, T_)                                                                                      \
     hipLaunchKernelGGL((K<T_, 2>), grid_waves, block, 0, lc.stream, (const T_*)in, g.nx, L, o);                \
