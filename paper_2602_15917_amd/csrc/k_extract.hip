@@ -636,15 +636,14 @@ __device__ __forceinline__ void chunk_of(const Layout& L, uint64_t q, uint64_t n
 
 // The codes of every span voxel, in row order, as one flat stream: each wave
 // takes whole kEmitChunk-code chunks, so loads and stores are contiguous and
-// no lane idles on a short row.  This kernel runs the lean path for chunks
-// of at most 64 spans (one per lane) within 2^30 voxels, and queues every other
-// chunk for k_emit_codes_general, so that its register budget stays that of
-// the lean path.  B = bytes per code: the code width is device data, so one
-// kernel per width is launched and the two that do not match return at once.
+// no lane idles on a short row.  The lean path takes chunks of at most 64
+// spans (one per lane) within 2^30 voxels and queues every other chunk for
+// the general kernel, so that its register budget stays that of the lean
+// path.  B = bytes per code.
 template <typename T, int B>
-__global__ __launch_bounds__(kBlock) void k_emit_codes(const T* __restrict__ in, int64_t nx, Layout L, EmitOut o) {
+__device__ __forceinline__ void emit_codes_lean(const T* __restrict__ in, int64_t nx, const Layout& L,
+                                                const EmitOut& o) {
     DevState* S = L.S;
-    if (thread_exit_e(S) || S->width_bits != 8 * B) return;  // no barrier below
     bool trunc = false;
     const uint64_t n_codes = uni64(S->span_total & kLenMask);
     const uint32_t n_rows = uni((uint32_t)(S->span_total >> 40));
@@ -688,10 +687,9 @@ __global__ __launch_bounds__(kBlock) void k_emit_codes(const T* __restrict__ in,
 // The queued chunks: many short spans (lane windows with a cross-lane
 // search), or few spans whose voxels lie far apart (64-bit offsets).
 template <typename T, int B>
-__global__ __launch_bounds__(kBlock) void k_emit_codes_general(const T* __restrict__ in, int64_t nx, Layout L,
-                                                               EmitOut o) {
+__device__ __forceinline__ void emit_codes_general(const T* __restrict__ in, int64_t nx, const Layout& L,
+                                                   const EmitOut& o) {
     DevState* S = L.S;
-    if (thread_exit_e(S) || S->width_bits != 8 * B) return;  // no barrier below
     bool trunc = false;
     const uint64_t n_codes = uni64(S->span_total & kLenMask);
     const uint32_t n_rows = uni((uint32_t)(S->span_total >> 40));
@@ -710,6 +708,33 @@ __global__ __launch_bounds__(kBlock) void k_emit_codes_general(const T* __restri
             emit_chunk_many<T, B>(in, nx, L, o, c0, c1, j0, j1, trunc);
     }
     if (trunc) atomicOr(&S->trunc, 1);
+}
+
+// The code width is device data (resolved from the value range); the branch
+// on it is uniform.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_emit_codes(const T* __restrict__ in, int64_t nx, Layout L, EmitOut o) {
+    if (thread_exit_e(L.S)) return;  // no barrier below
+    const int wb = L.S->width_bits;
+    if (wb == 16)
+        emit_codes_lean<T, 2>(in, nx, L, o);
+    else if (wb == 8)
+        emit_codes_lean<T, 1>(in, nx, L, o);
+    else
+        emit_codes_lean<T, 4>(in, nx, L, o);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_emit_codes_general(const T* __restrict__ in, int64_t nx, Layout L,
+                                                               EmitOut o) {
+    if (thread_exit_e(L.S)) return;  // no barrier below
+    const int wb = L.S->width_bits;
+    if (wb == 16)
+        emit_codes_general<T, 2>(in, nx, L, o);
+    else if (wb == 8)
+        emit_codes_general<T, 1>(in, nx, L, o);
+    else
+        emit_codes_general<T, 4>(in, nx, L, o);
 }
 
 // After the scan of the per-row outlier counts.  Each wave takes 64 spans,
@@ -806,19 +831,15 @@ hipError_t launch_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, cons
     const dim3 grid_waves(lc.grid_stream);
     timer_begin(lc.timer, ST_EMIT, lc.stream);
     hipLaunchKernelGGL(k_emit_index, grid_rows_t, block, 0, lc.stream, L, g.nx, g.nrows);
-    // every width's lean kernel before any general one (the queue must be complete)
-#define EMIT_LAUNCH(K, T_)                                                                                      \
-    hipLaunchKernelGGL((K<T_, 2>), grid_waves, block, 0, lc.stream, (const T_*)in, g.nx, L, o);                \
-    hipLaunchKernelGGL((K<T_, 1>), grid_waves, block, 0, lc.stream, (const T_*)in, g.nx, L, o);                \
-    hipLaunchKernelGGL((K<T_, 4>), grid_waves, block, 0, lc.stream, (const T_*)in, g.nx, L, o)
+    // the lean kernel queues the chunks it leaves to the general kernel
     if (dt == ROIX_F32) {
-        EMIT_LAUNCH(k_emit_codes, float);
-        EMIT_LAUNCH(k_emit_codes_general, float);
+        hipLaunchKernelGGL(k_emit_codes<float>, grid_waves, block, 0, lc.stream, (const float*)in, g.nx, L, o);
+        hipLaunchKernelGGL(k_emit_codes_general<float>, grid_waves, block, 0, lc.stream, (const float*)in, g.nx, L, o);
     } else {
-        EMIT_LAUNCH(k_emit_codes, uint16_t);
-        EMIT_LAUNCH(k_emit_codes_general, uint16_t);
+        hipLaunchKernelGGL(k_emit_codes<uint16_t>, grid_waves, block, 0, lc.stream, (const uint16_t*)in, g.nx, L, o);
+        hipLaunchKernelGGL(k_emit_codes_general<uint16_t>, grid_waves, block, 0, lc.stream, (const uint16_t*)in, g.nx,
+                           L, o);
     }
-#undef EMIT_LAUNCH
     timer_end(lc.timer, ST_EMIT, lc.stream);
     hipError_t e = launch_scan_u64(lc, L.row_outl, L.row_outl, g.nrows, &L.S->n_outliers, L.scan_tmp);
     if (e != hipSuccess) return e;
