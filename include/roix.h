@@ -269,6 +269,7 @@ roix_status roix_fused_batch(roix_ctx* ctx, int32_t n, const roix_volume_desc* v
  *   "grid_stream"    workgroups of the grid-stride streaming kernels
  *   "grid_read"      workgroups of the read-only range kernel
  *   "seg_grid"       workgroups of the component-labelling kernels
+ *   "stats_grid"     workgroups of the component-statistics kernel
  *   "seg_runs"       runs labelled together in one workgroup's local memory
  *                    (a multiple of 256 up to 16384; 0 = spread the runs over
  *                    seg_grid workgroups, at least 2048 each)

@@ -130,6 +130,7 @@ LaunchCtx roix::lctx(roix_ctx* c, void* stream) {
     lc.grid_read = c->grid_read;
     lc.seg_grid = c->seg_grid;
     lc.seg_runs = c->seg_runs;
+    lc.stats_grid = c->stats_grid;
     return lc;
 }
 
@@ -307,8 +308,9 @@ roix_status roix_ctx_create(int device, size_t scratch_bytes, roix_ctx** out) {
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->cus = prop.multiProcessorCount;
     if (c->cus <= 0) c->cus = 256;
     c->grid_stream = c->cus * 8;
-    c->grid_read = c->cus * 2;
+    c->grid_read = c->cus * 4;
     c->seg_grid = c->cus * 2;
+    c->stats_grid = c->cus;
     if (const char* s = getenv("ROIX_GRID_STREAM")) {
         int v = atoi(s);
         if (v > 0 && v <= 1 << 20) c->grid_stream = v;
@@ -458,6 +460,7 @@ roix_status roix_ctx_set_param(roix_ctx* ctx, const char* name, int64_t value) {
     if (strcmp(name, "grid_stream") == 0 && pos) ctx->grid_stream = (int)value;
     else if (strcmp(name, "grid_read") == 0 && pos) ctx->grid_read = (int)value;
     else if (strcmp(name, "seg_grid") == 0 && pos) ctx->seg_grid = (int)value;
+    else if (strcmp(name, "stats_grid") == 0 && pos) ctx->stats_grid = (int)value;
     else if (strcmp(name, "seg_runs") == 0 && value >= 0 && value <= 16384 && value % 256 == 0)
         ctx->seg_runs = (int)value;
     else if (strcmp(name, "batch_streams") == 0 && value >= 1 && value <= 64) ctx->batch_streams = (int)value;
@@ -471,6 +474,7 @@ roix_status roix_ctx_get_param(roix_ctx* ctx, const char* name, int64_t* value) 
     if (strcmp(name, "grid_stream") == 0) *value = ctx->grid_stream;
     else if (strcmp(name, "grid_read") == 0) *value = ctx->grid_read;
     else if (strcmp(name, "seg_grid") == 0) *value = ctx->seg_grid;
+    else if (strcmp(name, "stats_grid") == 0) *value = ctx->stats_grid;
     else if (strcmp(name, "seg_runs") == 0) *value = ctx->seg_runs;
     else if (strcmp(name, "batch_streams") == 0) *value = ctx->batch_streams;
     else if (strcmp(name, "batch_graph") == 0) *value = ctx->batch_graph;
@@ -555,7 +559,8 @@ roix_status roix_fused_batch(roix_ctx* ctx, int32_t n, const roix_volume_desc* v
     if (!ctx->batch_graph) return batch_enqueue(ctx, n, vols, gs, S, slot_bytes, stream);
     // the graph is specific to the descriptors (buffer addresses are baked
     // into its kernel arguments): reuse it while they are the same
-    const int params[6] = {S, ctx->grid_stream, ctx->grid_read, ctx->seg_grid, ctx->seg_runs, (int)(slot_bytes >> 20)};
+    const int params[7] = {S,           ctx->grid_stream, ctx->grid_read, ctx->seg_grid, ctx->seg_runs, ctx->stats_grid,
+                           (int)(slot_bytes >> 20)};
     std::vector<uint8_t> key(sizeof(roix_volume_desc) * (size_t)n + sizeof params);
     memcpy(key.data(), vols, sizeof(roix_volume_desc) * (size_t)n);
     memcpy(key.data() + sizeof(roix_volume_desc) * (size_t)n, params, sizeof params);

@@ -216,6 +216,7 @@ struct LaunchCtx {
     int grid_read;    // workgroups of the read-only streaming kernel (range)
     int seg_grid;     // workgroups of the segment labelling kernels
     int seg_runs;     // runs per segment (0: spread the runs over seg_grid)
+    int stats_grid;   // workgroups of the component statistics kernel
 };
 
 // ------------------------------------------------------------ launchers

@@ -55,6 +55,7 @@ struct roix_ctx {
     int grid_read = 512;
     int seg_grid = 512;
     int seg_runs = 0;
+    int stats_grid = 512;
     int batch_streams = 4;
     int batch_graph = 1;
     BatchState batch;

@@ -59,6 +59,39 @@ __device__ __forceinline__ uint64_t mask_word(const uint8_t* p, uint32_t TL, uin
     return ((uint64_t)hi << 32) | lo;
 }
 
+// The 64 mask words of proxy words [wbase, wbase + 64) (valid: the first
+// nvalid of them), lane l returning word l.  The bytes are loaded coalesced --
+// lane l takes bytes 16 l .. 16 l + 15 of each 1 KB -- and turned into 16 mask
+// bits each; word w then gathers its four quarters from lanes 4 (w % 16) + q
+// of load w / 16.  Every lane of the wave must call it.
+__device__ __forceinline__ void mask_load64(const uint8_t* proxy, int64_t wbase, int64_t nvalid, uint4 (&v)[4]) {
+    const int lane = threadIdx.x % kWave;
+    const uint4* src = reinterpret_cast<const uint4*>(proxy + wbase * 64) + lane;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = k * 16 + lane / 4 < nvalid ? ld_stream(src + k * 64) : make_uint4(0, 0, 0, 0);
+}
+
+// zero bytes are never above the threshold, so the loads' zero fill is empty mask
+__device__ __forceinline__ uint64_t mask_words64(const uint4 (&v)[4], uint32_t TL, uint32_t TR) {
+    const int lane = threadIdx.x % kWave;
+    uint32_t h[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        h[k] = gt_bytes4(v[k].x, TL, TR) | (gt_bytes4(v[k].y, TL, TR) << 4) | (gt_bytes4(v[k].z, TL, TR) << 8) |
+               (gt_bytes4(v[k].w, TL, TR) << 12);
+    const uint32_t h01 = h[0] | (h[1] << 16), h23 = h[2] | (h[3] << 16);
+    const int k = lane >> 4, m4 = (lane & 15) * 4;
+    uint64_t word = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t a = (uint32_t)__shfl((int)h01, m4 + q), b = (uint32_t)__shfl((int)h23, m4 + q);
+        const uint32_t srcv = k < 2 ? a : b;
+        const uint32_t bits = (k & 1) ? (srcv >> 16) : (srcv & 0xFFFFu);
+        word |= (uint64_t)bits << (16 * q);
+    }
+    return word;
+}
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     const int lane = threadIdx.x % kWave;
 #pragma unroll
@@ -105,23 +138,36 @@ __global__ __launch_bounds__(kBlock) void k_mask_runs(const uint8_t* __restrict_
     unsigned long long nmask = 0;
     if (W <= kWave) {
         const int64_t R = kWave / W;
-        for (int64_t row0 = wave * R; row0 < nrows; row0 += nwaves * R) {
-            const WordLane wl = word_lane(row0, W, nrows);
-            uint64_t m = 0;
-            if (wl.row >= 0) {
-                m = mask_word(proxy + wl.row * P + 64 * wl.w, TL, TR);
-                if (wl.w == W - 1) m &= lastmask;
+        // two steps of R rows per iteration, all loads of both issued first
+        for (int64_t rowA = wave * 2 * R; rowA < nrows; rowA += nwaves * 2 * R) {
+            uint4 v[2][4];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                // the step's rows are consecutive words of the proxy: lane l's word is word l
+                const int64_t row0 = rowA + u * R;
+                const int64_t rows_here = row0 >= nrows ? 0 : (nrows - row0 < R ? nrows - row0 : R);
+                mask_load64(proxy, row0 * W, rows_here * W, v[u]);
             }
-            const uint32_t prev_hi = __shfl_up((uint32_t)(m >> 32), 1);
-            const uint64_t cin = (wl.w > 0) ? (uint64_t)(prev_hi >> 31) : 0ull;
-            const uint64_t starts = m & ~((m << 1) | cin);
-            const uint32_t cnt = (uint32_t)__popcll(starts);
-            nmask += (unsigned long long)__popcll(m);
-            const uint32_t incl = wave_incl_scan(cnt);
-            const uint32_t before = __shfl(incl, wl.seg_first > 0 ? wl.seg_first - 1 : 0);
-            if (wl.row >= 0) {
-                maskbits[wl.row * W + wl.w] = m;
-                if (wl.w == W - 1) row_nruns[wl.row] = incl - (wl.seg_first > 0 ? before : 0u);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int64_t row0 = rowA + u * R;
+                const WordLane wl = word_lane(row0, W, nrows);
+                uint64_t m = mask_words64(v[u], TL, TR);
+                if (wl.row < 0)
+                    m = 0;
+                else if (wl.w == W - 1)
+                    m &= lastmask;
+                const uint32_t prev_hi = __shfl_up((uint32_t)(m >> 32), 1);
+                const uint64_t cin = (wl.w > 0) ? (uint64_t)(prev_hi >> 31) : 0ull;
+                const uint64_t starts = m & ~((m << 1) | cin);
+                const uint32_t cnt = (uint32_t)__popcll(starts);
+                nmask += (unsigned long long)__popcll(m);
+                const uint32_t incl = wave_incl_scan(cnt);
+                const uint32_t before = __shfl(incl, wl.seg_first > 0 ? wl.seg_first - 1 : 0);
+                if (wl.row >= 0) {
+                    maskbits[wl.row * W + wl.w] = m;
+                    if (wl.w == W - 1) row_nruns[wl.row] = incl - (wl.seg_first > 0 ? before : 0u);
+                }
             }
         }
     } else {
@@ -974,7 +1020,7 @@ hipError_t launch_comp_stats(const LaunchCtx& lc, const Geom& g, const Layout& L
     hipLaunchKernelGGL(k_comp_init, dim3(grid_for((int64_t)L.run_cap, kBlock, lc.grid_stream)), dim3(kBlock), 0,
                        lc.stream, (const uint32_t*)L.run_xs, (const uint32_t*)L.run_row, (const uint32_t*)L.parent,
                        (const uint32_t*)L.comp_id, g.nx, comps, (const DevState*)L.S);
-    hipLaunchKernelGGL(k_comp_stats, dim3(grid_for((int64_t)L.run_cap, kBlock * kStatRuns, lc.grid_stream / 2)),
+    hipLaunchKernelGGL(k_comp_stats, dim3(grid_for((int64_t)L.run_cap, kBlock * kStatRuns, lc.stats_grid)),
                        dim3(kBlock), 0, lc.stream, (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe,
                        (const uint32_t*)L.run_row, (const uint32_t*)L.parent, (const uint32_t*)L.comp_id,
                        (uint32_t)g.ny, 1.0 / (double)g.ny, comps, (const DevState*)L.S);
