@@ -421,54 +421,88 @@ __device__ __forceinline__ uint32_t qh_one(T x, const QH& p, uint32_t* lh_copy, 
         return b;
 }
 
-constexpr int kQhBatch = 4;  // 16-byte loads in flight per lane
+constexpr int kQhBatch = 8;  // 16-byte loads in flight per lane
 
-// One wave per row.  Vector path (row starts 16-byte aligned): lane l takes
-// vectors l, l + 64, ... of the row (one coalesced 1 KB load per step) and
-// stores their VN proxy bytes as one word at the same voxel offset of the
-// row's proxy.  Scalar path: lane l takes voxels l, l + 64, ...
+template <typename T, bool CODES, bool FIXED, bool FASTDIV>
+__device__ __forceinline__ void qh_vec(const uint4& raw, uint8_t* __restrict__ dst, int64_t vi, const QH& p,
+                                       uint32_t* mine, bool& bad) {
+    constexpr int VN = VecN<T>::n;
+    T v[VN];
+    unpack16<T>(raw, v);
+    if constexpr (VN == 4) {
+        uint32_t pk = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) pk |= qh_one<T, CODES, FIXED, FASTDIV>(v[j], p, mine, bad) << (8 * j);
+        if (dst) reinterpret_cast<uint32_t*>(dst)[vi] = pk;
+    } else {
+        uint64_t pk = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) pk |= (uint64_t)qh_one<T, CODES, FIXED, FASTDIV>(v[j], p, mine, bad) << (8 * j);
+        if (dst) reinterpret_cast<uint64_t*>(dst)[vi] = pk;
+    }
+}
+
+// Vector path (row starts 16-byte aligned): 16-byte vectors, stored as one
+// word of proxy bytes at the same voxel offset of the row's proxy.  A wave
+// fills kQhSlots vector slots per step: rows of at most kQhSlots / 2
+// vectors (padded to a power of two) are taken several at a time, longer rows
+// one at a time, so that every lane has kQhBatch loads in flight.
+// Scalar path: lane l takes voxels l, l + 64, ... of one row at a time.
 template <typename T, bool CODES, bool FIXED, bool FASTDIV, bool VEC, bool STORE>
 __device__ __forceinline__ void qh_rows(const T* __restrict__ in, int64_t nx, int64_t nrows, int64_t P,
                                         const QH& p, uint32_t* mine, uint8_t* __restrict__ proxy, bool& bad) {
     constexpr int VN = VecN<T>::n;
+    constexpr int64_t kQhSlots = (int64_t)kWave * kQhBatch;
     const int lane = threadIdx.x % kWave;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
-    for (int64_t row = wave; row < nrows; row += nwaves) {
-        const T* src = in + row * nx;
-        uint8_t* dst = proxy + row * P;
-        if constexpr (VEC) {
-            const int64_t nv = nx / VN;
-            const uint4* vs = reinterpret_cast<const uint4*>(src);
-            for (int64_t v0 = 0; v0 < nv; v0 += (int64_t)kWave * kQhBatch) {
+    if constexpr (VEC) {
+        const int64_t nv = nx / VN;
+        int lg = 0;
+        while ((1ll << lg) < nv) ++lg;
+        if ((1ll << lg) < kQhSlots) {
+            const int64_t rpi = kQhSlots >> lg;  // rows per step
+            for (int64_t row0 = wave * rpi; row0 < nrows; row0 += nwaves * rpi) {
                 uint4 raw[kQhBatch];
 #pragma unroll
                 for (int k = 0; k < kQhBatch; ++k) {
-                    const int64_t vi = v0 + k * kWave + lane;
-                    raw[k] = vi < nv ? ld_stream(vs + vi) : make_uint4(0, 0, 0, 0);
+                    const int64_t e = (int64_t)k * kWave + lane;
+                    const int64_t row = row0 + (e >> lg), vi = e & ((1ll << lg) - 1);
+                    raw[k] = (vi < nv && row < nrows) ? ld_stream(reinterpret_cast<const uint4*>(in + row * nx) + vi)
+                                                      : make_uint4(0, 0, 0, 0);
                 }
 #pragma unroll
                 for (int k = 0; k < kQhBatch; ++k) {
-                    const int64_t vi = v0 + k * kWave + lane;
-                    if (vi >= nv) continue;
-                    T v[VN];
-                    unpack16<T>(raw[k], v);
-                    if constexpr (VN == 4) {
-                        uint32_t pk = 0;
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) pk |= qh_one<T, CODES, FIXED, FASTDIV>(v[j], p, mine, bad) << (8 * j);
-                        if constexpr (STORE) reinterpret_cast<uint32_t*>(dst)[vi] = pk;
-                    } else {
-                        uint64_t pk = 0;
-#pragma unroll
-                        for (int j = 0; j < 8; ++j)
-                            pk |= (uint64_t)qh_one<T, CODES, FIXED, FASTDIV>(v[j], p, mine, bad) << (8 * j);
-                        if constexpr (STORE) reinterpret_cast<uint64_t*>(dst)[vi] = pk;
-                    }
+                    const int64_t e = (int64_t)k * kWave + lane;
+                    const int64_t row = row0 + (e >> lg), vi = e & ((1ll << lg) - 1);
+                    if (vi >= nv || row >= nrows) continue;
+                    qh_vec<T, CODES, FIXED, FASTDIV>(raw[k], STORE ? proxy + row * P : nullptr, vi, p, mine, bad);
                 }
             }
         } else {
-            for (int64_t x0 = 0; x0 < nx; x0 += (int64_t)kWave * kQhBatch) {
+            for (int64_t row = wave; row < nrows; row += nwaves) {
+                const uint4* vs = reinterpret_cast<const uint4*>(in + row * nx);
+                uint8_t* dst = STORE ? proxy + row * P : nullptr;
+                for (int64_t v0 = 0; v0 < nv; v0 += kQhSlots) {
+                    uint4 raw[kQhBatch];
+#pragma unroll
+                    for (int k = 0; k < kQhBatch; ++k) {
+                        const int64_t vi = v0 + k * kWave + lane;
+                        raw[k] = vi < nv ? ld_stream(vs + vi) : make_uint4(0, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int k = 0; k < kQhBatch; ++k) {
+                        const int64_t vi = v0 + k * kWave + lane;
+                        if (vi < nv) qh_vec<T, CODES, FIXED, FASTDIV>(raw[k], dst, vi, p, mine, bad);
+                    }
+                }
+            }
+        }
+    } else {
+        for (int64_t row = wave; row < nrows; row += nwaves) {
+            const T* src = in + row * nx;
+            uint8_t* dst = proxy + row * P;
+            for (int64_t x0 = 0; x0 < nx; x0 += kQhSlots) {
                 T v[kQhBatch];
 #pragma unroll
                 for (int k = 0; k < kQhBatch; ++k) {
