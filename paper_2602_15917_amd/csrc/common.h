@@ -16,8 +16,8 @@ constexpr int kHistStride = 257;     // copy stride: lane c + bin b lands in ban
 constexpr int kScanBlocks = 1024;    // fixed block count of the device-sized scans
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kEmitSlice = 256;  // codes per emit slice: 4 consecutive codes per lane
-constexpr int kEmitSlices = 8;   // slices per emit step (16-byte loads in flight per lane)
-constexpr int kEmitSteps = 2;
+constexpr int kEmitSlices = 4;   // slices per emit step (16-byte loads in flight per lane)
+constexpr int kEmitSteps = 4;
 constexpr uint64_t kEmitChunk = (uint64_t)kEmitSlice * kEmitSlices * kEmitSteps;  // codes per emit work item
 
 // Everything the kernels of one call share, reset by k_init at the start of

@@ -476,6 +476,17 @@ __device__ __forceinline__ uint64_t uni64(uint64_t v) {
 // lane one compare and select per code.  All loads of a step are issued
 // before any use.
 template <typename T, int B>
+__device__ __forceinline__ void store_codes4(uint8_t* dst, const uint32_t (&u)[4]) {
+    if constexpr (B == 1) {
+        *reinterpret_cast<uint32_t*>(dst) = u[0] | (u[1] << 8) | (u[2] << 16) | (u[3] << 24);
+    } else if constexpr (B == 2) {
+        *reinterpret_cast<uint2*>(dst) = make_uint2(u[0] | (u[1] << 16), u[2] | (u[3] << 16));
+    } else {
+        *reinterpret_cast<uint4*>(dst) = make_uint4(u[0], u[1], u[2], u[3]);
+    }
+}
+
+template <typename T, int B>
 __device__ __forceinline__ void emit_chunk_near(const T* __restrict__ in, const Layout& L, const EmitOut& o,
                                                 uint64_t c0, uint32_t n, uint32_t nr, uint32_t rs, uint32_t d,
                                                 uint32_t rid, uint64_t V0, bool& trunc) {
@@ -496,17 +507,21 @@ __device__ __forceinline__ void emit_chunk_near(const T* __restrict__ in, const 
     // a whole-quad load reads quad_reach voxels; a volume too short for one
     // at V0 takes the code-by-code loads only
     const bool quads = vlim >= (uint32_t)quad_reach<T>();
-    // slice table, lane k for slice k of the chunk: the span of the slice's
-    // first code, and whether another span starts inside the slice
-    uint32_t jkv = 0, hkv = 0;
+    // slice table (lane k: slice k of the chunk): the span of the slice's
+    // first code and its offset, and the mask of slices inside which another
+    // span starts
+    uint32_t jkv = 0;
+    bool hk = false;
     {
         const uint32_t tk = (uint32_t)lane * (uint32_t)kEmitSlice;
         for (uint32_t j = 1; j < nr; j = uni(j + 1)) {
             const uint32_t sj = uni(__builtin_amdgcn_readlane(rs, j));
             jkv += sj <= tk ? 1u : 0u;
-            hkv |= (sj > tk && sj < tk + (uint32_t)kEmitSlice) ? 1u : 0u;
+            hk = hk || (sj > tk && sj < tk + (uint32_t)kEmitSlice);
         }
     }
+    const uint32_t dkv = shfl32(d, (int)jkv);  // every lane executes it (jkv < nr <= 64)
+    const uint32_t hmask = (uint32_t)__ballot(hk);
     for (uint32_t s0 = 0; s0 < n; s0 += kStep) {
         float xv[kEmitSlices][4];
         uint32_t split = 0;  // slices whose quad is not one contiguous load for some lane
@@ -518,11 +533,10 @@ __device__ __forceinline__ void emit_chunk_near(const T* __restrict__ in, const 
             const uint32_t tk0 = s0 + (uint32_t)k * kEmitSlice;
             const uint32_t t = tk0 + 4u * (uint32_t)lane;
             const uint32_t kk = tk0 / (uint32_t)kEmitSlice;
-            const uint32_t jc = uni(__builtin_amdgcn_readlane(jkv, kk));
-            const uint32_t dc = uni(__builtin_amdgcn_readlane(d, jc));
+            const uint32_t dc = uni(__builtin_amdgcn_readlane(dkv, kk));
             uint32_t d0 = dc, d3 = dc;
-            if (uni(__builtin_amdgcn_readlane(hkv, kk))) {
-                for (uint32_t j = jc + 1; j < nr; j = uni(j + 1)) {  // starts inside this slice
+            if ((hmask >> kk) & 1u) {  // uniform: starts inside this slice
+                for (uint32_t j = uni(__builtin_amdgcn_readlane(jkv, kk)) + 1; j < nr; j = uni(j + 1)) {
                     const uint32_t sj = uni(__builtin_amdgcn_readlane(rs, j));
                     if (sj >= tk0 + (uint32_t)kEmitSlice) break;
                     const uint32_t dj = uni(__builtin_amdgcn_readlane(d, j));
@@ -546,67 +560,80 @@ __device__ __forceinline__ void emit_chunk_near(const T* __restrict__ in, const 
                 load_quad(in, V0 + (uint64_t)vi, xv[k]);
             }
         }
-        // phase 2: the split quads, code by code (rare outside slices with span starts)
+        // phase 2: the split quads, code by code (slices with span starts, the chunk's end)
+        if (split) {
 #pragma unroll
-        for (int k = 0; k < kEmitSlices; ++k) {
-            if (!((split >> k) & 1u)) continue;  // uniform
-            const uint32_t tk0 = s0 + (uint32_t)k * kEmitSlice;
-            const uint32_t t = tk0 + 4u * (uint32_t)lane;
-            const uint32_t j0k = uni(__builtin_amdgcn_readlane(jkv, tk0 / (uint32_t)kEmitSlice));
-            const uint32_t dc = uni(__builtin_amdgcn_readlane(d, j0k));
-            uint32_t di[4] = {dc, dc, dc, dc};
-            for (uint32_t j = j0k + 1; j < nr; j = uni(j + 1)) {
-                const uint32_t sj = uni(__builtin_amdgcn_readlane(rs, j));
-                if (sj >= tk0 + (uint32_t)kEmitSlice) break;
-                const uint32_t dj = uni(__builtin_amdgcn_readlane(d, j));
+            for (int k = 0; k < kEmitSlices; ++k) {
+                if (!((split >> k) & 1u)) continue;  // uniform
+                const uint32_t tk0 = s0 + (uint32_t)k * kEmitSlice;
+                const uint32_t t = tk0 + 4u * (uint32_t)lane;
+                const uint32_t kk = tk0 / (uint32_t)kEmitSlice;
+                const uint32_t dc = uni(__builtin_amdgcn_readlane(dkv, kk));
+                uint32_t di[4] = {dc, dc, dc, dc};
+                if ((hmask >> kk) & 1u) {
+                    for (uint32_t j = uni(__builtin_amdgcn_readlane(jkv, kk)) + 1; j < nr; j = uni(j + 1)) {
+                        const uint32_t sj = uni(__builtin_amdgcn_readlane(rs, j));
+                        if (sj >= tk0 + (uint32_t)kEmitSlice) break;
+                        const uint32_t dj = uni(__builtin_amdgcn_readlane(d, j));
 #pragma unroll
-                for (int i = 0; i < 4; ++i) di[i] = t + (uint32_t)i >= sj ? dj : di[i];
-            }
-            const bool full = quads && t + 4 <= n && di[0] == di[3] && t + di[0] + (uint32_t)quad_reach<T>() <= vlim;
-            if (!full) {
+                        for (int i = 0; i < 4; ++i) di[i] = t + (uint32_t)i >= sj ? dj : di[i];
+                    }
+                }
+                const bool full =
+                    quads && t + 4 <= n && di[0] == di[3] && t + di[0] + (uint32_t)quad_reach<T>() <= vlim;
+                if (!full) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    xv[k][i] = t + (uint32_t)i < n
-                                   ? (float)ld_stream(reinterpret_cast<const T*>(base + (t + (uint32_t)i + di[i]) * S_))
-                                   : 0.0f;
+                    for (int i = 0; i < 4; ++i)
+                        xv[k][i] = t + (uint32_t)i < n ? (float)ld_stream(reinterpret_cast<const T*>(
+                                                             base + (t + (uint32_t)i + di[i]) * S_))
+                                                       : 0.0f;
+                }
             }
         }
+        // phase 3: codes.  A slice wholly inside the chunk and the stream needs
+        // no per-code checks.
         uint32_t outm[kEmitSlices];
         uint32_t anyout = 0;
 #pragma unroll
         for (int k = 0; k < kEmitSlices; ++k) {
-            const uint32_t t = s0 + (uint32_t)k * kEmitSlice + 4u * (uint32_t)lane;
+            const uint32_t tk0 = s0 + (uint32_t)k * kEmitSlice;
+            const uint32_t t = tk0 + 4u * (uint32_t)lane;
             uint32_t u[4];
             uint32_t om = 0;
+            if (tk0 + (uint32_t)kEmitSlice <= nfit) {  // uniform
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float x = xv[k][i];
-                const int32_t q = qcode(x, r);
-                const bool ob = t + (uint32_t)i < n && outlier(x, q, w, eb32);
-                om |= ob ? (1u << i) : 0u;
-                u[i] = ob ? esc : (uint32_t)(q - qmin);
-            }
-            outm[k] = om;
-            anyout |= om;
-            uint8_t* dst = cbase + (uint32_t)(t * B);
-            if (t + 4 <= nfit) {
-                if constexpr (B == 1) {
-                    *reinterpret_cast<uint32_t*>(dst) = u[0] | (u[1] << 8) | (u[2] << 16) | (u[3] << 24);
-                } else if constexpr (B == 2) {
-                    *reinterpret_cast<uint2*>(dst) = make_uint2(u[0] | (u[1] << 16), u[2] | (u[3] << 16));
-                } else {
-                    *reinterpret_cast<uint4*>(dst) = make_uint4(u[0], u[1], u[2], u[3]);
+                for (int i = 0; i < 4; ++i) {
+                    const float x = xv[k][i];
+                    const int32_t q = qcode(x, r);
+                    const bool ob = outlier(x, q, w, eb32);
+                    om |= ob ? (1u << i) : 0u;
+                    u[i] = ob ? esc : (uint32_t)(q - qmin);
                 }
+                store_codes4<T, B>(cbase + t * B, u);
             } else {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    if (t + (uint32_t)i >= n) continue;
-                    if (t + (uint32_t)i < nfit)
-                        reinterpret_cast<C*>(dst)[i] = (C)u[i];
-                    else
-                        trunc = true;
+                    const float x = xv[k][i];
+                    const int32_t q = qcode(x, r);
+                    const bool ob = t + (uint32_t)i < n && outlier(x, q, w, eb32);
+                    om |= ob ? (1u << i) : 0u;
+                    u[i] = ob ? esc : (uint32_t)(q - qmin);
+                }
+                if (t + 4 <= nfit) {
+                    store_codes4<T, B>(cbase + t * B, u);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        if (t + (uint32_t)i >= n) continue;
+                        if (t + (uint32_t)i < nfit)
+                            reinterpret_cast<C*>(cbase + t * B)[i] = (C)u[i];
+                        else
+                            trunc = true;
+                    }
                 }
             }
+            outm[k] = om;
+            anyout |= om;
         }
         if (__ballot(anyout != 0)) {  // rare: per-span outlier counts
 #pragma unroll
