@@ -172,9 +172,8 @@ static hipError_t label_runs(const LaunchCtx& lc, const Geom& g, const Layout& L
     hipError_t e;
     if ((e = launch_mask_runs(lc, g, L)) != hipSuccess) return e;
     if ((e = launch_scan_u32(lc, L.row_nruns, L.run_off, g.nrows, nullptr, &L.S->n_runs, L.run_off + g.nrows,
-                             L.scan_tmp)) != hipSuccess)
+                             L.scan_tmp, L.S, L.run_cap, ROIX_ENOMEM)) != hipSuccess)
         return e;
-    if ((e = launch_check_cap(lc, L.S, L.scan_tmp + kScanBlocks, L.run_cap, ROIX_ENOMEM)) != hipSuccess) return e;
     if ((e = launch_runs_write(lc, g, L, 0, g.nrows)) != hipSuccess) return e;
     return launch_union(lc, g, L, connectivity);
 }
@@ -185,10 +184,7 @@ hipError_t roix::components_and_keep(const LaunchCtx& lc, const Geom& g, const L
     hipError_t e;
     if ((e = launch_flatten(lc, L)) != hipSuccess) return e;
     if ((e = launch_scan_u32(lc, L.comp_id, L.comp_id, (int64_t)L.run_cap, &L.S->n_runs, &L.S->n_comps, nullptr,
-                             L.scan_tmp)) != hipSuccess)
-        return e;
-    if ((e = launch_check_cap(lc, L.S, L.scan_tmp + kScanBlocks, (uint64_t)(comps ? comps_cap : 0), ROIX_ETRUNC)) !=
-        hipSuccess)
+                             L.scan_tmp, L.S, (uint64_t)(comps ? comps_cap : 0), ROIX_ETRUNC)) != hipSuccess)
         return e;
     if ((e = launch_comp_stats(lc, g, L, comps)) != hipSuccess) return e;
     return launch_keep(lc, L, comps, crit);

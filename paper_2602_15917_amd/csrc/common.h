@@ -248,20 +248,21 @@ hipError_t launch_hist_only(const LaunchCtx& lc, const void* in, roix_dtype dt, 
 hipError_t launch_serve_status(const LaunchCtx& lc, DevState* S, int save);
 // Exclusive scans (in place allowed).  n from the host, or from *n_dev when
 // n_dev is not null (then n_host is only an upper bound).  total_out and
-// out_end (nullable) receive the sum of all elements.
+// out_end (nullable) receive the sum of all elements.  With cap_S, a total
+// above cap fails cap_S with cap_err.
 hipError_t launch_scan_u32(const LaunchCtx& lc, const uint32_t* in, uint32_t* out, int64_t n_host,
-                           const uint32_t* n_dev, uint32_t* total_out, uint32_t* out_end, uint64_t* tmp);
+                           const uint32_t* n_dev, uint32_t* total_out, uint32_t* out_end, uint64_t* tmp,
+                           DevState* cap_S = nullptr, uint64_t cap = 0, int cap_err = 0);
 hipError_t launch_scan_u64(const LaunchCtx& lc, const uint64_t* in, uint64_t* out, int64_t n_host,
                            unsigned long long* total_out, uint64_t* tmp);
-// fail with `err` when *val > cap (val: the 64-bit total of the last scan)
-hipError_t launch_check_cap(const LaunchCtx& lc, DevState* S, const uint64_t* val, uint64_t cap, int err);
 // runs of rows [r0, r1); their numbers continue from run_off[r0]
 hipError_t launch_runs_write(const LaunchCtx& lc, const Geom& g, const Layout& L, int64_t r0, int64_t r1);
 // exclusive scan of n_host u32 counts starting from *base (device); *base
 // becomes base + total, *lo_out the old base, *out_end the new total;
 // tmp[kScanBlocks] receives the new 64-bit total
 hipError_t launch_scan_u32_base(const LaunchCtx& lc, const uint32_t* in, uint32_t* out, int64_t n_host,
-                                uint32_t* base, uint32_t* lo_out, uint32_t* out_end, uint64_t* tmp);
+                                uint32_t* base, uint32_t* lo_out, uint32_t* out_end, uint64_t* tmp,
+                                DevState* cap_S = nullptr, uint64_t cap = 0, int cap_err = 0);
 hipError_t launch_union(const LaunchCtx& lc, const Geom& g, const Layout& L, int conn);
 hipError_t launch_flatten(const LaunchCtx& lc, const Layout& L);
 hipError_t launch_comp_stats(const LaunchCtx& lc, const Geom& g, const Layout& L, roix_component* comps);

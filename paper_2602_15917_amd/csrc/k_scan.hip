@@ -62,7 +62,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const T* __restrict__ in
 
 // one workgroup of kScanBlocks threads
 template <typename TT>
-__global__ __launch_bounds__(kScanBlocks) void k_scan_top(uint64_t* tmp, TT* total_out, TT* out_end) {
+__global__ __launch_bounds__(kScanBlocks) void k_scan_top(uint64_t* tmp, TT* total_out, TT* out_end, DevState* cS,
+                                                          uint64_t cap, int cerr) {
     __shared__ uint64_t s[kScanBlocks];
     const int t = threadIdx.x;
     s[t] = tmp[t];
@@ -79,13 +80,15 @@ __global__ __launch_bounds__(kScanBlocks) void k_scan_top(uint64_t* tmp, TT* tot
         tmp[kScanBlocks] = incl;
         if (total_out) *total_out = (TT)incl;
         if (out_end) *out_end = (TT)incl;
+        if (cS && incl > cap) fail(cS, cerr);
     }
 }
 
 // As k_scan_top, continuing from a device base: every offset is shifted by
 // *base, then *lo_out = the old base and *base = *out_end = base + total.
 __global__ __launch_bounds__(kScanBlocks) void k_scan_top_base(uint64_t* tmp, uint32_t* base, uint32_t* lo_out,
-                                                              uint32_t* out_end) {
+                                                              uint32_t* out_end, DevState* cS, uint64_t cap,
+                                                              int cerr) {
     __shared__ uint64_t s[kScanBlocks];
     const int t = threadIdx.x;
     const uint64_t b0 = *base;
@@ -106,6 +109,7 @@ __global__ __launch_bounds__(kScanBlocks) void k_scan_top_base(uint64_t* tmp, ui
         *lo_out = (uint32_t)b0;
         *base = (uint32_t)tot;
         if (out_end) *out_end = (uint32_t)tot;
+        if (cS && tot > cap) fail(cS, cerr);
     }
 }
 
@@ -129,11 +133,13 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const T* in, T* out, int64
 }
 
 hipError_t launch_scan_u32(const LaunchCtx& lc, const uint32_t* in, uint32_t* out, int64_t n_host,
-                           const uint32_t* n_dev, uint32_t* total_out, uint32_t* out_end, uint64_t* tmp) {
+                           const uint32_t* n_dev, uint32_t* total_out, uint32_t* out_end, uint64_t* tmp,
+                           DevState* cap_S, uint64_t cap, int cap_err) {
     timer_begin(lc.timer, ST_SCAN, lc.stream);
     hipLaunchKernelGGL(k_scan_reduce<uint32_t>, dim3(kScanBlocks), dim3(kBlock), 0, lc.stream, in, n_host, n_dev,
                        tmp);
-    hipLaunchKernelGGL(k_scan_top<uint32_t>, dim3(1), dim3(kScanBlocks), 0, lc.stream, tmp, total_out, out_end);
+    hipLaunchKernelGGL(k_scan_top<uint32_t>, dim3(1), dim3(kScanBlocks), 0, lc.stream, tmp, total_out, out_end, cap_S,
+                       cap, cap_err);
     hipLaunchKernelGGL(k_scan_down<uint32_t>, dim3(kScanBlocks), dim3(kBlock), 0, lc.stream, in, out, n_host,
                        n_dev, (const uint64_t*)tmp);
     timer_end(lc.timer, ST_SCAN, lc.stream);
@@ -141,11 +147,13 @@ hipError_t launch_scan_u32(const LaunchCtx& lc, const uint32_t* in, uint32_t* ou
 }
 
 hipError_t launch_scan_u32_base(const LaunchCtx& lc, const uint32_t* in, uint32_t* out, int64_t n_host,
-                                uint32_t* base, uint32_t* lo_out, uint32_t* out_end, uint64_t* tmp) {
+                                uint32_t* base, uint32_t* lo_out, uint32_t* out_end, uint64_t* tmp,
+                                DevState* cap_S, uint64_t cap, int cap_err) {
     timer_begin(lc.timer, ST_SCAN, lc.stream);
     hipLaunchKernelGGL(k_scan_reduce<uint32_t>, dim3(kScanBlocks), dim3(kBlock), 0, lc.stream, in, n_host,
                        (const uint32_t*)nullptr, tmp);
-    hipLaunchKernelGGL(k_scan_top_base, dim3(1), dim3(kScanBlocks), 0, lc.stream, tmp, base, lo_out, out_end);
+    hipLaunchKernelGGL(k_scan_top_base, dim3(1), dim3(kScanBlocks), 0, lc.stream, tmp, base, lo_out, out_end, cap_S,
+                       cap, cap_err);
     hipLaunchKernelGGL(k_scan_down<uint32_t>, dim3(kScanBlocks), dim3(kBlock), 0, lc.stream, in, out, n_host,
                        (const uint32_t*)nullptr, (const uint64_t*)tmp);
     timer_end(lc.timer, ST_SCAN, lc.stream);
@@ -158,20 +166,10 @@ hipError_t launch_scan_u64(const LaunchCtx& lc, const uint64_t* in, uint64_t* ou
     hipLaunchKernelGGL(k_scan_reduce<uint64_t>, dim3(kScanBlocks), dim3(kBlock), 0, lc.stream, in, n_host,
                        (const uint32_t*)nullptr, tmp);
     hipLaunchKernelGGL(k_scan_top<unsigned long long>, dim3(1), dim3(kScanBlocks), 0, lc.stream, tmp, total_out,
-                       (unsigned long long*)nullptr);
+                       (unsigned long long*)nullptr, (DevState*)nullptr, 0ull, 0);
     hipLaunchKernelGGL(k_scan_down<uint64_t>, dim3(kScanBlocks), dim3(kBlock), 0, lc.stream, in, out, n_host,
                        (const uint32_t*)nullptr, (const uint64_t*)tmp);
     timer_end(lc.timer, ST_SCAN, lc.stream);
-    return hipGetLastError();
-}
-
-// the full 64-bit total of the last scan is tmp[kScanBlocks]
-__global__ void k_check_cap(DevState* S, const uint64_t* val, uint64_t cap, int err) {
-    if (threadIdx.x == 0 && blockIdx.x == 0 && *val > cap) fail(S, err);
-}
-
-hipError_t launch_check_cap(const LaunchCtx& lc, DevState* S, const uint64_t* val, uint64_t cap, int err) {
-    hipLaunchKernelGGL(k_check_cap, dim3(1), dim3(64), 0, lc.stream, S, val, cap, err);
     return hipGetLastError();
 }
 

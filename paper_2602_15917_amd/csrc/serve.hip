@@ -207,9 +207,8 @@ static hipError_t enqueue_slab(const LaunchCtx& lc, Vol& v, int64_t z0, int64_t 
     hipError_t e;
     if ((e = launch_slab_mask(lc, v.d_vol, v.dt, g, r0, r1, L)) != hipSuccess) return e;
     if ((e = launch_scan_u32_base(lc, L.row_nruns + r0, L.run_off + r0, r1 - r0, &L.S->n_runs, &L.S->seg_lo,
-                                  L.run_off + r1, L.scan_tmp)) != hipSuccess)
+                                  L.run_off + r1, L.scan_tmp, L.S, L.run_cap, ROIX_ENOMEM)) != hipSuccess)
         return e;
-    if ((e = launch_check_cap(lc, L.S, L.scan_tmp + kScanBlocks, L.run_cap, ROIX_ENOMEM)) != hipSuccess) return e;
     if ((e = launch_runs_write(lc, g, L, r0, r1)) != hipSuccess) return e;
     return launch_union(lc, g, L, v.crit.connectivity);
 }
