@@ -275,6 +275,11 @@ roix_status roix_fused_batch(roix_ctx* ctx, int32_t n, const roix_volume_desc* v
  *                    seg_grid workgroups, at least 2048 each)
  *   "batch_streams"  concurrent streams of roix_fused_batch (1..64)
  *   "batch_graph"    1 = capture/replay batches as a HIP graph, 0 = launch eagerly
+ *   "fused16_min_voxels"  smallest float32 volume (voxels) that the fused path
+ *                    quantises in one pass with the range, writing a 16-bit
+ *                    code proxy, when the bound is absolute, rows hold a
+ *                    multiple of 4 voxels and start 16-byte aligned, and the
+ *                    arena has room (default 2^22; 0..2^40)
  *   "compute_units"  (get only) the device's compute units
  * None of them changes any output.  Errors: ROIX_EINVAL (unknown name or
  * value out of range). */

@@ -63,11 +63,21 @@ uint64_t roix::worst_runs(const Geom& g) {
     return w < cap ? w : cap;
 }
 
+int roix::proxy_kind(const Geom& g, roix_dtype dt, uint64_t min_voxels) {
+    return (dt == ROIX_F32 && g.N >= min_voxels && g.nx % 4 == 0) ? 2 : 1;
+}
+
+int roix::proxy_kind_for(const Geom& g, roix_dtype dt, size_t bytes, uint64_t min_voxels) {
+    const int k = proxy_kind(g, dt, min_voxels);
+    return (k == 2 && bytes < fixed_bytes(g, 2) + (size_t)worst_runs(g) * kRunBytes) ? 1 : k;
+}
+
 // bytes of the per-voxel and per-row part of the arena
-size_t roix::fixed_bytes(const Geom& g, bool with_proxy) {
+size_t roix::fixed_bytes(const Geom& g, int proxy) {
     size_t b = 0;
     b += align256(sizeof(DevState));
-    if (with_proxy) b += align256((size_t)g.nrows * g.W * 64);  // proxy
+    if (proxy) b += align256((size_t)g.nrows * g.W * 64 * (proxy == 2 ? 2 : 1));  // proxy
+    if (proxy == 2) b += align256((size_t)kQrBlocks * kQrFine * 4) + align256((size_t)kQrFine * 8);
     b += align256((size_t)g.nrows * g.W * 8);             // mask bits
     b += align256((size_t)g.nrows * 4);                   // row_nruns
     b += align256((size_t)(g.nrows + 1) * 4);             // run_off
@@ -82,8 +92,8 @@ size_t roix::fixed_bytes(const Geom& g, bool with_proxy) {
     return b;
 }
 
-bool roix::carve_at(void* base, size_t bytes, const Geom& g, Layout* L, bool with_proxy) {
-    const size_t fb = fixed_bytes(g, with_proxy);
+bool roix::carve_at(void* base, size_t bytes, const Geom& g, Layout* L, int proxy) {
+    const size_t fb = fixed_bytes(g, proxy);
     if (bytes < fb + kRunBytes) return false;
     uint8_t* p = (uint8_t*)base;
     auto take = [&](size_t n) {
@@ -92,7 +102,9 @@ bool roix::carve_at(void* base, size_t bytes, const Geom& g, Layout* L, bool wit
         return q;
     };
     L->S = (DevState*)take(sizeof(DevState));
-    L->proxy = with_proxy ? take((size_t)g.nrows * g.W * 64) : nullptr;
+    L->proxy = proxy ? take((size_t)g.nrows * g.W * 64 * (proxy == 2 ? 2 : 1)) : nullptr;
+    L->fine_slots = proxy == 2 ? (uint32_t*)take((size_t)kQrBlocks * kQrFine * 4) : nullptr;
+    L->fine_total = proxy == 2 ? (unsigned long long*)take((size_t)kQrFine * 8) : nullptr;
     L->maskbits = (uint64_t*)take((size_t)g.nrows * g.W * 8);
     L->row_nruns = (uint32_t*)take((size_t)g.nrows * 4);
     L->run_off = (uint32_t*)take((size_t)(g.nrows + 1) * 4);
@@ -120,7 +132,9 @@ bool roix::carve_at(void* base, size_t bytes, const Geom& g, Layout* L, bool wit
     return (size_t)(p - (uint8_t*)base) <= bytes;
 }
 
-static bool carve(roix_ctx* c, const Geom& g, Layout* L) { return carve_at(c->arena, c->arena_bytes, g, L); }
+static bool carve(roix_ctx* c, const Geom& g, Layout* L, roix_dtype dt = ROIX_U16) {
+    return carve_at(c->arena, c->arena_bytes, g, L, proxy_kind_for(g, dt, c->arena_bytes, c->p16_min));
+}
 
 LaunchCtx roix::lctx(roix_ctx* c, void* stream) {
     LaunchCtx lc;
@@ -218,10 +232,20 @@ roix_status roix::enqueue_fused(const LaunchCtx& lc, const Geom& g, Layout L, co
                                  roix_eb eb, const roix_criterion* crit, const roix_fused_out* out) {
     const bool fixed = crit->thr == ROIX_THR_FIXED;
     const int kind = dtype == ROIX_F32 ? 0 : 1;
-    ROIX_TRY(launch_init(lc, L.S));
-    ROIX_TRY(launch_range(lc, d_in, dtype, g.N, L.S));
-    ROIX_TRY(launch_resolve_dt(lc, L.S, dtype, eb, crit));
-    ROIX_TRY(launch_quant_hist(lc, d_in, kind, g, L.S, L.proxy, fixed));
+    // the fused range + 16-bit proxy pass needs the bound before the range
+    // (absolute) and whole 16-byte vectors per row
+    const bool p16 = L.fine_slots && dtype == ROIX_F32 && eb.mode == ROIX_EB_ABS && aligned(d_in, 16);
+    if (p16) {
+        ROIX_TRY(launch_init(lc, L.S, eb.value));
+        ROIX_TRY(launch_quant_range16(lc, (const float*)d_in, g, L));
+        ROIX_TRY(launch_resolve16(lc, L, eb, crit));
+        ROIX_TRY(launch_quant_hist(lc, d_in, kind, g, L.S, L.proxy, fixed, true));  // only when K > 2^15
+    } else {
+        ROIX_TRY(launch_init(lc, L.S));
+        ROIX_TRY(launch_range(lc, d_in, dtype, g.N, L.S));
+        ROIX_TRY(launch_resolve_dt(lc, L.S, dtype, eb, crit));
+        ROIX_TRY(launch_quant_hist(lc, d_in, kind, g, L.S, L.proxy, fixed));
+    }
     ROIX_TRY(launch_otsu(lc, L.S, fixed));
     ROIX_TRY(label_and_keep(lc, g, L, crit, out->d_comps, out->comps_cap));
     ROIX_TRY(launch_spans_from_runs(lc, g, L));
@@ -272,7 +296,7 @@ size_t roix_scratch_bytes(roix_dims dims, roix_dtype dtype, const roix_criterion
     (void)crit;
     Geom g;
     if ((dtype != ROIX_F32 && dtype != ROIX_U16) || !geom_of(dims, &g)) return 0;
-    return fixed_bytes(g) + (size_t)worst_runs(g) * kRunBytes;
+    return fixed_bytes(g, proxy_kind(g, dtype)) + (size_t)worst_runs(g) * kRunBytes;
 }
 
 roix_status roix_bounds(roix_dims dims, roix_dtype dtype, const roix_criterion* crit, int64_t* max_rows,
@@ -446,7 +470,7 @@ roix_status roix_fused(roix_ctx* ctx, const void* d_in, roix_dtype dtype, roix_d
     if (dtype != ROIX_F32 && dtype != ROIX_U16) return ROIX_EINVAL;
     if (!aligned(d_in, dtype == ROIX_F32 ? 4 : 2)) return ROIX_EINVAL;
     Layout L;
-    if (!carve(ctx, g, &L)) return ROIX_ENOMEM;
+    if (!carve(ctx, g, &L, dtype)) return ROIX_ENOMEM;
     return enqueue_fused(lctx(ctx, stream), g, L, d_in, dtype, eb, crit, out);
 }
 
@@ -461,6 +485,8 @@ roix_status roix_ctx_set_param(roix_ctx* ctx, const char* name, int64_t value) {
         ctx->seg_runs = (int)value;
     else if (strcmp(name, "batch_streams") == 0 && value >= 1 && value <= 64) ctx->batch_streams = (int)value;
     else if (strcmp(name, "batch_graph") == 0 && (value == 0 || value == 1)) ctx->batch_graph = (int)value;
+    else if (strcmp(name, "fused16_min_voxels") == 0 && value >= 0 && value <= (1ll << 40))
+        ctx->p16_min = (uint64_t)value;
     else return ROIX_EINVAL;
     return ROIX_OK;
 }
@@ -475,6 +501,7 @@ roix_status roix_ctx_get_param(roix_ctx* ctx, const char* name, int64_t* value) 
     else if (strcmp(name, "batch_streams") == 0) *value = ctx->batch_streams;
     else if (strcmp(name, "batch_graph") == 0) *value = ctx->batch_graph;
     else if (strcmp(name, "compute_units") == 0) *value = ctx->cus;
+    else if (strcmp(name, "fused16_min_voxels") == 0) *value = (int64_t)ctx->p16_min;
     else return ROIX_EINVAL;
     return ROIX_OK;
 }
@@ -520,7 +547,9 @@ static roix_status batch_enqueue(roix_ctx* c, int32_t n, const roix_volume_desc*
         lc.timer = nullptr;
         for (int i : slot[k]) {
             Layout L;
-            if (!carve_at(base, slot_bytes, gs[i], &L)) return ROIX_ENOMEM;
+            const roix_dtype dt = (roix_dtype)v[i].dtype;
+            if (!carve_at(base, slot_bytes, gs[i], &L, proxy_kind_for(gs[i], dt, slot_bytes, c->p16_min)))
+                return ROIX_ENOMEM;
             roix_status st = enqueue_fused(lc, gs[i], L, v[i].d_in, (roix_dtype)v[i].dtype, v[i].eb, &v[i].crit, &v[i].out);
             if (st != ROIX_OK) return st;
         }
@@ -555,8 +584,8 @@ roix_status roix_fused_batch(roix_ctx* ctx, int32_t n, const roix_volume_desc* v
     if (!ctx->batch_graph) return batch_enqueue(ctx, n, vols, gs, S, slot_bytes, stream);
     // the graph is specific to the descriptors (buffer addresses are baked
     // into its kernel arguments): reuse it while they are the same
-    const int params[7] = {S,           ctx->grid_stream, ctx->grid_read, ctx->seg_grid, ctx->seg_runs, ctx->stats_grid,
-                           (int)(slot_bytes >> 20)};
+    const int64_t params[8] = {S,           ctx->grid_stream, ctx->grid_read,      ctx->seg_grid,
+                               ctx->seg_runs, ctx->stats_grid,  (int64_t)slot_bytes, (int64_t)ctx->p16_min};
     std::vector<uint8_t> key(sizeof(roix_volume_desc) * (size_t)n + sizeof params);
     memcpy(key.data(), vols, sizeof(roix_volume_desc) * (size_t)n);
     memcpy(key.data() + sizeof(roix_volume_desc) * (size_t)n, params, sizeof params);

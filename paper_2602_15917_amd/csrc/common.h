@@ -15,6 +15,8 @@ constexpr int kHistCopies = 32;      // LDS-privatised histogram copies (one per
 constexpr int kHistStride = 257;     // copy stride: lane c + bin b lands in bank (c + b) mod 32
 constexpr int kScanBlocks = 1024;    // fixed block count of the device-sized scans
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr int kQrFine = 1 << 15;  // code classes (q mod 2^15) of the fused 16-bit proxy pass
+constexpr int kQrBlocks = 256;    // workgroups of that pass (one LDS class table each)
 constexpr int kEmitSlice = 256;  // codes per emit slice: 4 consecutive codes per lane
 constexpr int kEmitSlices = 4;   // slices per emit step (16-byte loads in flight per lane)
 constexpr int kEmitSteps = 4;
@@ -50,7 +52,8 @@ struct DevState {
     // extraction
     unsigned long long span_total;  // (rows with a span) << 40 | (codes)
     unsigned long long n_outliers, q_outliers;
-    uint32_t n_slow, pad2;  // emit chunks queued for the general chunk kernel
+    uint32_t n_slow;  // emit chunks queued for the general chunk kernel
+    uint32_t p16;     // the proxy is the 16-bit code proxy (fused pass, K <= 2^15)
     // run number where the current labelling pass starts (0 for a whole
     // volume; the first run of the slab for a streamed slab)
     uint32_t seg_lo;
@@ -64,7 +67,7 @@ struct DevState {
 // Per-call view of the scratch arena.
 struct Layout {
     DevState* S;
-    uint8_t* proxy;         // nrows * W * 64 bytes (see Geom)
+    uint8_t* proxy;         // nrows * W * 64 bytes, or twice that for the 16-bit proxy (see Geom)
     uint64_t* maskbits;     // nrows * W words
     uint32_t* row_nruns;    // nrows
     uint32_t* run_off;      // nrows + 1
@@ -83,13 +86,15 @@ struct Layout {
     uint32_t* chunk_row;    // N / kEmitChunk + 2: span holding the first code of each emit chunk
     uint32_t* slow_chunks;  // N / kEmitChunk + 2: chunks left to the general chunk kernel
     uint64_t* scan_tmp;     // kScanBlocks + 1
+    uint32_t* fine_slots;   // kQrBlocks * kQrFine, or null (no 16-bit proxy)
+    unsigned long long* fine_total;  // kQrFine
     uint64_t run_cap;
 };
 
-// The 1-byte proxy of row r, voxel x is byte r * 64 W + x: rows are padded
-// to whole 64-voxel words, so one lane can turn 64 proxy bytes (four 16-byte
-// loads) into one mask word.  Padding bytes are never read as object: the
-// mask of a row's last word is cut at nx.
+// The proxy of row r, voxel x is element r * 64 W + x (a byte, or a 16-bit
+// word for the 16-bit proxy): rows are padded to whole 64-voxel words, so one
+// lane can turn 64 proxy elements into one mask word.  Padding elements are
+// never read as object: the mask of a row's last word is cut at nx.
 struct Geom {
     int64_t nx, ny, nz;
     uint64_t N;
@@ -148,6 +153,13 @@ __device__ __forceinline__ uint4 ld_stream(const uint4* p) {
 __device__ __forceinline__ float ld_stream(const float* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ uint16_t ld_stream(const uint16_t* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ int32_t ld_stream(const int32_t* p) { return __builtin_nontemporal_load(p); }
+typedef unsigned int v2u32_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void st_stream(uint2* p, uint2 v) {
+    v2u32_t t;
+    t.x = v.x;
+    t.y = v.y;
+    __builtin_nontemporal_store(t, reinterpret_cast<v2u32_t*>(p));
+}
 
 __device__ __forceinline__ uint32_t ld_relaxed(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -222,7 +234,8 @@ struct LaunchCtx {
 // ------------------------------------------------------------ launchers
 // Each returns hipSuccess or the launch error.
 
-hipError_t launch_init(const LaunchCtx& lc, DevState* S);
+// eb_abs > 0: the quantiser of this absolute bound is set up too (fused pass)
+hipError_t launch_init(const LaunchCtx& lc, DevState* S, double eb_abs = 0.0);
 hipError_t launch_range(const LaunchCtx& lc, const void* in, roix_dtype dt, uint64_t N, DevState* S);
 hipError_t launch_resolve_dt(const LaunchCtx& lc, DevState* S, roix_dtype dt, roix_eb eb,
                              const roix_criterion* crit);
@@ -232,7 +245,12 @@ hipError_t launch_quantize(const LaunchCtx& lc, const void* in, roix_dtype dt, u
                            int32_t* codes, uint32_t* outlier_bits);
 // src_kind: 0 = f32 values, 1 = u16 values, 2 = int32 codes
 hipError_t launch_quant_hist(const LaunchCtx& lc, const void* in, int src_kind, const Geom& g, DevState* S,
-                             uint8_t* proxy, bool fixed);
+                             uint8_t* proxy, bool fixed, bool unless_p16 = false);
+// float32, absolute bound, rows 16-byte aligned and a multiple of 4 voxels:
+// range keys, 16-bit proxy and code-class counts in one pass; then the
+// quantiser and (K <= 2^15) the histogram, setting S->p16
+hipError_t launch_quant_range16(const LaunchCtx& lc, const float* in, const Geom& g, const Layout& L);
+hipError_t launch_resolve16(const LaunchCtx& lc, const Layout& L, roix_eb eb, const roix_criterion* crit);
 hipError_t launch_otsu(const LaunchCtx& lc, DevState* S, bool fixed);
 
 hipError_t launch_mask_runs(const LaunchCtx& lc, const Geom& g, const Layout& L);

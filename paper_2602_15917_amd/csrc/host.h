@@ -56,6 +56,7 @@ struct roix_ctx {
     int seg_grid = 512;
     int seg_runs = 0;
     int stats_grid = 512;
+    uint64_t p16_min = 1ull << 22;  // fused16_min_voxels
     int batch_streams = 4;
     int batch_graph = 1;
     BatchState batch;
@@ -71,11 +72,21 @@ size_t align256(size_t x);
 bool geom_of(roix_dims d, Geom* g);
 // largest possible number of runs: half the voxels of every row, capped
 uint64_t worst_runs(const Geom& g);
-// bytes of the per-voxel and per-row part of a layout (the proxy only when asked)
-size_t fixed_bytes(const Geom& g, bool with_proxy = true);
+// Proxy kinds of a layout: 0 none, 1 the 1-byte proxy, 2 room for the 16-bit
+// proxy and the code-class tables of the fused pass (which falls back to the
+// 1-byte proxy in the same buffer when the codes span more than 2^15 values).
+// Kind 2 serves float32 volumes of at least kP16MinVoxels voxels whose rows
+// hold a multiple of 4 voxels.
+constexpr uint64_t kP16MinVoxels = 1ull << 22;
+int proxy_kind(const Geom& g, roix_dtype dt, uint64_t min_voxels = kP16MinVoxels);
+// bytes of the per-voxel and per-row part of a layout
+size_t fixed_bytes(const Geom& g, int proxy = 1);
+// the kind a region of `bytes` takes: kind 2 only when it still leaves room
+// for the worst-case run arrays
+int proxy_kind_for(const Geom& g, roix_dtype dt, size_t bytes, uint64_t min_voxels = kP16MinVoxels);
 // carve a layout from [base, base + bytes); the run arrays take what is left
 // (at most worst_runs); false when not even one run fits
-bool carve_at(void* base, size_t bytes, const Geom& g, Layout* L, bool with_proxy = true);
+bool carve_at(void* base, size_t bytes, const Geom& g, Layout* L, int proxy = 1);
 LaunchCtx lctx(roix_ctx* c, void* stream);
 bool aligned(const void* p, size_t a);
 bool eb_ok(roix_eb eb);

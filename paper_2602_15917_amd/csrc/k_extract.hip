@@ -652,6 +652,238 @@ __device__ __forceinline__ void emit_chunk_near(const T* __restrict__ in, const 
     }
 }
 
+// Near chunks read from the 16-bit proxy of the fused pass (float32 volumes
+// whose rows are whole 64-voxel words, so that proxy element = voxel): the
+// proxy holds q mod 2^15 and the outlier flag, so a code is
+// q - qmin = (p - qmin) mod 2^15, or the escape for a flagged voxel, and
+// emitting needs no quantiser arithmetic and half the input bytes.  Lane l
+// takes codes 8 l .. 8 l + 7 of each 512-code slice.  Codes of one span are
+// one 16-byte load from the 4-byte-aligned element at or before the first
+// (plus the next dword, funnel-shifted in, when that element is odd); in a
+// slice where spans start, a second such load at the offset of the lane's
+// last code covers a lane whose codes cross one span start, and phase 3
+// picks each code from the load of its span.  Lanes with codes of three or
+// more spans, at the chunk's end or at the end of the proxy store whatever
+// phase 3 makes of their stand-in loads and then redo their codes one by one
+// (phase 4).  Slice table and span walk as in emit_chunk_near, with 512-code
+// slices.
+constexpr uint32_t kP16Slice = 512;
+constexpr int kP16Slices = 4;  // slices per step
+
+__device__ __forceinline__ uint32_t half16(const uint32_t (&w)[4], int i) { return (w[i >> 1] >> (16 * (i & 1))) & 0xFFFFu; }
+
+// 8 elements from a whole load (4 dwords + the next) shifted by sh bits
+__device__ __forceinline__ void funnel8(const uint32_t (&a)[5], uint32_t sh, uint32_t (&w)[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = __builtin_amdgcn_alignbit(a[i + 1], a[i], sh);
+}
+
+template <int B>
+__device__ __forceinline__ void emit_chunk_p16(const uint16_t* __restrict__ px, const Layout& L, const EmitOut& o,
+                                               uint64_t c0, uint32_t n, uint32_t nr, uint32_t rs, uint32_t d,
+                                               uint32_t rid, uint64_t V0, bool& trunc) {
+    using C = typename CodeT<B>::type;
+    const DevState* S = L.S;
+    const int lane = threadIdx.x % kWave;
+    const uint32_t Q2 = ((uint32_t)S->qmin & 0x7FFFu) * 0x00010001u;
+    const uint32_t esc = S->esc;
+    const uint16_t* base = px + V0;
+    const uint64_t vlim64 = o.nvox - V0;  // elements from V0 to the end of the proxy
+    const uint32_t vlim = uni(vlim64 > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)vlim64);
+    uint8_t* cbase = o.stream + c0 * B;
+    const uint64_t cap = o.stream_cap / B;
+    const uint32_t nfit = uni(cap <= c0 ? 0u : (cap - c0 >= n ? n : (uint32_t)(cap - c0)));
+    constexpr uint32_t kStep = kP16Slice * kP16Slices;
+    // a whole load at offset v reads elements v - 1 .. v + 9 at most, so it
+    // needs v + 10 <= vlim; a proxy too short for one at V0 goes code by code
+    const bool whole = vlim >= 10u;
+    const uint32_t odd0 = (uint32_t)(V0 & 1ull);
+    uint32_t jkv = 0;
+    bool hk = false;
+    {
+        const uint32_t tk = (uint32_t)lane * kP16Slice;
+        for (uint32_t j = 1; j < nr; j = uni(j + 1)) {
+            const uint32_t sj = uni(__builtin_amdgcn_readlane(rs, j));
+            jkv += sj <= tk ? 1u : 0u;
+            hk = hk || (sj > tk && sj < tk + kP16Slice);
+        }
+    }
+    const uint32_t dkv = shfl32(d, (int)jkv);  // every lane executes it (jkv < nr <= 64)
+    const uint32_t hmask = (uint32_t)__ballot(hk);
+    for (uint32_t s0 = 0; s0 < n; s0 += kStep) {
+        uint32_t la[kP16Slices][5], lb[kP16Slices][5], sa[kP16Slices], sb[kP16Slices], cut[kP16Slices];
+        uint32_t split = 0, bad = 0;
+        // phase 1: every load of the step, no lane branches (a lane that
+        // cannot take whole loads loads at V0 and is redone in phase 4)
+#pragma unroll
+        for (int k = 0; k < kP16Slices; ++k) {
+            const uint32_t tk0 = s0 + (uint32_t)k * kP16Slice;
+            const uint32_t t = tk0 + 8u * (uint32_t)lane;
+            const uint32_t kk = tk0 / kP16Slice;
+            const uint32_t dc = uni(__builtin_amdgcn_readlane(dkv, kk));
+            const bool starts = (hmask >> kk) & 1u;  // uniform
+            uint32_t d0 = dc, d7 = dc, i0 = 8u;
+            bool multi = false;
+            if (starts) {
+                for (uint32_t j = uni(__builtin_amdgcn_readlane(jkv, kk)) + 1; j < nr; j = uni(j + 1)) {
+                    const uint32_t sj = uni(__builtin_amdgcn_readlane(rs, j));
+                    if (sj >= tk0 + kP16Slice) break;
+                    const uint32_t dj = uni(__builtin_amdgcn_readlane(d, j));
+                    const bool inside = sj > t && sj <= t + 7;
+                    multi = multi || (inside && i0 != 8u);
+                    i0 = (inside && i0 == 8u) ? sj - t : i0;
+                    d0 = t >= sj ? dj : d0;
+                    d7 = t + 7 >= sj ? dj : d7;
+                }
+            }
+            const uint32_t va = t + d0, vb = t + d7;  // vb >= va: offsets never decrease
+            const bool full = whole && t + 8 <= n && !multi && vb + 10 <= vlim;
+            if (__ballot(!full)) split |= 1u << k;
+            bad |= full ? 0u : (1u << k);
+            cut[k] = i0;
+            const uint32_t oa = full ? ((odd0 + va) & 1u) : odd0;
+            const int64_t aa = full ? (int64_t)va - (int64_t)oa : -(int64_t)odd0;
+            sa[k] = 16u * oa;
+            if (whole) {  // uniform; elements V0 - odd0 .. V0 - odd0 + 9 exist
+                const v4u32_t q = __builtin_nontemporal_load(reinterpret_cast<const v4u32_t*>(base + aa));
+                la[k][0] = q.x;
+                la[k][1] = q.y;
+                la[k][2] = q.z;
+                la[k][3] = q.w;
+                la[k][4] = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(base + aa + 8));
+                if (starts) {
+                    const uint32_t ob = full ? ((odd0 + vb) & 1u) : odd0;
+                    const int64_t ab = full ? (int64_t)vb - (int64_t)ob : -(int64_t)odd0;
+                    sb[k] = 16u * ob;
+                    const v4u32_t r = __builtin_nontemporal_load(reinterpret_cast<const v4u32_t*>(base + ab));
+                    lb[k][0] = r.x;
+                    lb[k][1] = r.y;
+                    lb[k][2] = r.z;
+                    lb[k][3] = r.w;
+                    lb[k][4] = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(base + ab + 8));
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 5; ++i) la[k][i] = 0u;
+            }
+        }
+        // phase 3: codes
+        uint32_t outm[kP16Slices];
+        uint32_t anyout = 0;
+#pragma unroll
+        for (int k = 0; k < kP16Slices; ++k) {
+            const uint32_t tk0 = s0 + (uint32_t)k * kP16Slice;
+            const uint32_t t = tk0 + 8u * (uint32_t)lane;
+            uint32_t w[4];
+            funnel8(la[k], sa[k], w);
+            if ((hmask >> (tk0 / kP16Slice)) & 1u) {  // uniform: codes from cut on come from the second load
+                uint32_t wb[4];
+                funnel8(lb[k], sb[k], wb);
+                const uint32_t c8 = cut[k];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const uint32_t keep = c8 >= 2u * i + 2u ? 0xFFFFFFFFu : (c8 == 2u * i + 1u ? 0x0000FFFFu : 0u);
+                    w[i] = (w[i] & keep) | (wb[i] & ~keep);
+                }
+            }
+            uint32_t c[4], fl = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                fl |= w[i] & 0x80008000u;
+                c[i] = ((w[i] | 0x80008000u) - Q2) & 0x7FFF7FFFu;
+            }
+            // flag bits of codes 0..7 (none for a lane that phase 4 redoes)
+            uint32_t om = 0;
+            if (fl && !((bad >> k) & 1u)) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) om |= ((half16(w, i) >> 15) & 1u) << i;
+            }
+            if (tk0 + kP16Slice <= nfit) {  // uniform: the slice lies inside the chunk and the stream
+                if constexpr (B == 2) {
+                    *reinterpret_cast<uint4*>(cbase + 2 * t) = make_uint4(c[0], c[1], c[2], c[3]);
+                } else {
+                    uint32_t b[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) b[i] = (c[i] & 0xFFu) | ((c[i] >> 8) & 0xFF00u);
+                    *reinterpret_cast<uint2*>(cbase + t) = make_uint2(b[0] | (b[1] << 16), b[2] | (b[3] << 16));
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    if (t + (uint32_t)i >= n) continue;
+                    if (t + (uint32_t)i < nfit)
+                        reinterpret_cast<C*>(cbase + (uint64_t)t * B)[i] = (C)half16(c, i);
+                    else
+                        trunc = true;
+                }
+            }
+            outm[k] = om;
+            anyout |= om;
+        }
+        if (__ballot(anyout != 0)) {  // rare: escapes and per-span outlier counts
+#pragma unroll
+            for (int k = 0; k < kP16Slices; ++k) {
+                const uint32_t t = s0 + (uint32_t)k * kP16Slice + 8u * (uint32_t)lane;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    int jj = 0;
+                    for (uint32_t j = 1; j < nr; j = uni(j + 1))
+                        jj = t + (uint32_t)i >= uni(__builtin_amdgcn_readlane(rs, j)) ? (int)j : jj;
+                    const uint32_t rc = shfl32(rid, jj);  // every lane executes it
+                    if ((outm[k] >> i) & 1u) {
+                        atomicAdd((unsigned long long*)&L.row_outl[rc], 1ull);
+                        if (t + (uint32_t)i < nfit) reinterpret_cast<C*>(cbase + (uint64_t)t * B)[i] = (C)esc;
+                    }
+                }
+            }
+        }
+        // phase 4 (rare): the lanes marked bad, code by code over their own
+        // stores (same lane, program order)
+        if (split) {
+#pragma unroll
+            for (int k = 0; k < kP16Slices; ++k) {
+                if (!((split >> k) & 1u)) continue;  // uniform
+                const uint32_t tk0 = s0 + (uint32_t)k * kP16Slice;
+                const uint32_t t = tk0 + 8u * (uint32_t)lane;
+                const uint32_t kk = tk0 / kP16Slice;
+                const uint32_t dc = uni(__builtin_amdgcn_readlane(dkv, kk));
+                uint32_t di[8] = {dc, dc, dc, dc, dc, dc, dc, dc};
+                int ji[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // span (lane of rid) of each code
+                const int jc = (int)uni(__builtin_amdgcn_readlane(jkv, kk));
+#pragma unroll
+                for (int i = 0; i < 8; ++i) ji[i] = jc;
+                if ((hmask >> kk) & 1u) {
+                    for (uint32_t j = (uint32_t)jc + 1; j < nr; j = uni(j + 1)) {
+                        const uint32_t sj = uni(__builtin_amdgcn_readlane(rs, j));
+                        if (sj >= tk0 + kP16Slice) break;
+                        const uint32_t dj = uni(__builtin_amdgcn_readlane(d, j));
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) {
+                            const bool in = t + (uint32_t)i >= sj;
+                            di[i] = in ? dj : di[i];
+                            ji[i] = in ? (int)j : ji[i];
+                        }
+                    }
+                }
+                const bool redo = (bad >> k) & 1u;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const uint32_t rc = shfl32(rid, ji[i]);  // every lane executes it
+                    if (!redo || t + (uint32_t)i >= n) continue;
+                    const uint32_t p = (uint32_t)ld_stream(base + (t + (uint32_t)i + di[i]));
+                    const bool ob = (p >> 15) & 1u;
+                    const uint32_t code = ob ? esc : ((p | 0x8000u) - (Q2 & 0xFFFFu)) & 0x7FFFu;
+                    if (ob) atomicAdd((unsigned long long*)&L.row_outl[rc], 1ull);
+                    if (t + (uint32_t)i < nfit)
+                        reinterpret_cast<C*>(cbase + (uint64_t)t * B)[i] = (C)code;
+                    else
+                        trunc = true;
+                }
+            }
+        }
+    }
+}
+
 // Chunk q's bounds and span range (uniform).
 __device__ __forceinline__ void chunk_of(const Layout& L, uint64_t q, uint64_t nchunks, uint64_t n_codes,
                                          uint32_t n_rows, uint64_t& c0, uint64_t& c1, uint32_t& j0, uint32_t& j1) {
@@ -667,9 +899,9 @@ __device__ __forceinline__ void chunk_of(const Layout& L, uint64_t q, uint64_t n
 // spans (one per lane) within 2^30 voxels and queues every other chunk for
 // the general kernel, so that its register budget stays that of the lean
 // path.  B = bytes per code.
-template <typename T, int B>
+template <typename T, int B, bool P16 = false>
 __device__ __forceinline__ void emit_codes_lean(const T* __restrict__ in, int64_t nx, const Layout& L,
-                                                const EmitOut& o) {
+                                                const EmitOut& o, const uint16_t* __restrict__ px = nullptr) {
     DevState* S = L.S;
     bool trunc = false;
     const uint64_t n_codes = uni64(S->span_total & kLenMask);
@@ -703,7 +935,10 @@ __device__ __forceinline__ void emit_codes_lean(const T* __restrict__ in, int64_
             d = (uint32_t)lane >= nr ? 0u : (uint32_t)(off - off0);
         }
         if (near) {
-            emit_chunk_near<T, B>(in, L, o, c0, (uint32_t)(c1 - c0), nr, rs, d, rid, c0 + off0, trunc);
+            if constexpr (P16)
+                emit_chunk_p16<B>(px, L, o, c0, (uint32_t)(c1 - c0), nr, rs, d, rid, c0 + off0, trunc);
+            else
+                emit_chunk_near<T, B>(in, L, o, c0, (uint32_t)(c1 - c0), nr, rs, d, rid, c0 + off0, trunc);
         } else if (lane == 0) {
             L.slow_chunks[atomicAdd(&S->n_slow, 1u)] = (uint32_t)q;
         }
@@ -738,10 +973,13 @@ __device__ __forceinline__ void emit_codes_general(const T* __restrict__ in, int
 }
 
 // The code width is device data (resolved from the value range); the branch
-// on it is uniform.
+// on it is uniform.  unless_p16: nothing to do when the 16-bit proxy kernel
+// below takes the lean chunks.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_emit_codes(const T* __restrict__ in, int64_t nx, Layout L, EmitOut o) {
+__global__ __launch_bounds__(kBlock) void k_emit_codes(const T* __restrict__ in, int64_t nx, Layout L, EmitOut o,
+                                                       int unless_p16) {
     if (thread_exit_e(L.S)) return;  // no barrier below
+    if (unless_p16 && L.S->p16) return;
     const int wb = L.S->width_bits;
     if (wb == 16)
         emit_codes_lean<T, 2>(in, nx, L, o);
@@ -749,6 +987,17 @@ __global__ __launch_bounds__(kBlock) void k_emit_codes(const T* __restrict__ in,
         emit_codes_lean<T, 1>(in, nx, L, o);
     else
         emit_codes_lean<T, 4>(in, nx, L, o);
+}
+
+// The lean chunks from the 16-bit proxy, when the fused pass produced it
+// (K <= 2^15, so codes are 8 or 16 bits wide).
+__global__ __launch_bounds__(kBlock) void k_emit_codes_p16(const float* __restrict__ in, int64_t nx, Layout L,
+                                                           EmitOut o, const uint16_t* __restrict__ px) {
+    if (thread_exit_e(L.S) || !L.S->p16) return;  // no barrier below
+    if (L.S->width_bits == 16)
+        emit_codes_lean<float, 2, true>(in, nx, L, o, px);
+    else
+        emit_codes_lean<float, 1, true>(in, nx, L, o, px);
 }
 
 template <typename T>
@@ -860,10 +1109,15 @@ hipError_t launch_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, cons
     hipLaunchKernelGGL(k_emit_index, grid_rows_t, block, 0, lc.stream, L, g.nx, g.nrows);
     // the lean kernel queues the chunks it leaves to the general kernel
     if (dt == ROIX_F32) {
-        hipLaunchKernelGGL(k_emit_codes<float>, grid_waves, block, 0, lc.stream, (const float*)in, g.nx, L, o);
+        // the 16-bit proxy (proxy element = voxel when rows are whole 64-voxel words)
+        const uint16_t* px = (L.fine_slots && g.W * 64 == g.nx) ? reinterpret_cast<const uint16_t*>(L.proxy) : nullptr;
+        hipLaunchKernelGGL(k_emit_codes<float>, grid_waves, block, 0, lc.stream, (const float*)in, g.nx, L, o,
+                           px ? 1 : 0);
+        if (px)
+            hipLaunchKernelGGL(k_emit_codes_p16, grid_waves, block, 0, lc.stream, (const float*)in, g.nx, L, o, px);
         hipLaunchKernelGGL(k_emit_codes_general<float>, grid_waves, block, 0, lc.stream, (const float*)in, g.nx, L, o);
     } else {
-        hipLaunchKernelGGL(k_emit_codes<uint16_t>, grid_waves, block, 0, lc.stream, (const uint16_t*)in, g.nx, L, o);
+        hipLaunchKernelGGL(k_emit_codes<uint16_t>, grid_waves, block, 0, lc.stream, (const uint16_t*)in, g.nx, L, o, 0);
         hipLaunchKernelGGL(k_emit_codes_general<uint16_t>, grid_waves, block, 0, lc.stream, (const uint16_t*)in, g.nx,
                            L, o);
     }

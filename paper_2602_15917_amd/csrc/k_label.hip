@@ -92,6 +92,62 @@ __device__ __forceinline__ uint64_t mask_words64(const uint4 (&v)[4], uint32_t T
     return word;
 }
 
+// 16-bit proxy (low 15 bits of q, outlier flag in bit 15), two voxels per
+// dword: bit 15 of ((p | 0x8000) - qmin15) & 0x7FFF, plus 0x8000 - tq, is
+// set exactly when q - qmin >= tq (no borrow or carry crosses a half, since
+// q - qmin < 2^15 and 0 <= tq <= 2^15).  Returns the 8 mask bits of 8 voxels.
+__device__ __forceinline__ uint32_t ge_halves8(const uint4& v, uint32_t Q2, uint32_t T2) {
+    const uint32_t d[4] = {v.x, v.y, v.z, v.w};
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t t = ((((d[i] | 0x80008000u) - Q2) & 0x7FFF7FFFu) + T2) & 0x80008000u;
+        m |= (((t >> 15) | (t >> 30)) & 3u) << (2 * i);
+    }
+    return m;
+}
+
+// mask word of 64 16-bit proxy elements (eight 16-byte loads)
+__device__ __forceinline__ uint64_t mask_word16(const uint16_t* p, uint32_t Q2, uint32_t T2) {
+    const uint4* q = reinterpret_cast<const uint4*>(p);
+    uint4 v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = q[k];
+    uint64_t m = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) m |= (uint64_t)ge_halves8(v[k], Q2, T2) << (8 * k);
+    return m;
+}
+
+// As mask_load64 for the 16-bit proxy: lane l takes bytes 16 l .. 16 l + 15
+// of each 1 KB, eight loads for 64 words; word w gathers its eight 8-bit
+// pieces from lanes 8 (w % 8) + j of load w / 8.  Invalid words load zeros,
+// which the caller clears.
+__device__ __forceinline__ void mask_load64_16(const uint16_t* proxy, int64_t wbase, int64_t nvalid,
+                                               uint4 (&v)[8]) {
+    const int lane = threadIdx.x % kWave;
+    const uint4* src = reinterpret_cast<const uint4*>(proxy + wbase * 64) + lane;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = k * 8 + lane / 8 < nvalid ? ld_stream(src + k * 64) : make_uint4(0, 0, 0, 0);
+}
+
+__device__ __forceinline__ uint64_t mask_words64_16(const uint4 (&v)[8], uint32_t Q2, uint32_t T2) {
+    const int lane = threadIdx.x % kWave;
+    uint32_t lo = 0, hi = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) lo |= ge_halves8(v[k], Q2, T2) << (8 * k);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) hi |= ge_halves8(v[4 + k], Q2, T2) << (8 * k);
+    const int ld = lane >> 3, src0 = (lane & 7) * 8, sh = 8 * (ld & 3);
+    uint64_t word = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const uint32_t a = (uint32_t)__shfl((int)lo, src0 + j), b = (uint32_t)__shfl((int)hi, src0 + j);
+        word |= (uint64_t)(((ld < 4 ? a : b) >> sh) & 0xFFu) << (8 * j);
+    }
+    return word;
+}
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     const int lane = threadIdx.x % kWave;
 #pragma unroll
@@ -124,12 +180,17 @@ __device__ __forceinline__ WordLane word_lane(int64_t row0, int64_t W, int64_t n
 // One 64-bit mask word per lane (SWAR byte compares on 64 proxy bytes), run
 // starts = 1-bits whose left neighbour (previous bit, or the previous lane's
 // top bit) is 0, per-row run counts by a segmented wave scan.
-__global__ __launch_bounds__(kBlock) void k_mask_runs(const uint8_t* __restrict__ proxy, int64_t nx, int64_t nrows,
-                                                      int64_t W, DevState* S, uint64_t* __restrict__ maskbits,
-                                                      uint32_t* __restrict__ row_nruns) {
-    if (block_exit_l(S)) return;
+template <bool P16>
+__device__ __forceinline__ void mask_runs_body(const uint8_t* __restrict__ proxy, int64_t nx, int64_t nrows, int64_t W,
+                                               DevState* S, uint64_t* __restrict__ maskbits,
+                                               uint32_t* __restrict__ row_nruns) {
+    // 1-byte proxy: bin > threshold bin, by SWAR byte compares
     const uint32_t T = 255u - (uint32_t)S->proxy_thr;
     const uint32_t TR = T * 0x01010101u, TL = (T & 0x7Fu) * 0x01010101u;
+    // 16-bit proxy: q - qmin >= q_thr - qmin
+    const uint32_t Q2 = ((uint32_t)S->qmin & 0x7FFFu) * 0x00010001u;
+    const uint32_t T2 = (0x8000u - (uint32_t)((int64_t)S->q_thr - (int64_t)S->qmin)) * 0x00010001u;
+    const uint16_t* proxy16 = reinterpret_cast<const uint16_t*>(proxy);
     const uint64_t lastmask = (nx % 64) ? ((1ull << (nx % 64)) - 1ull) : ~0ull;
     const int lane = threadIdx.x % kWave;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
@@ -138,36 +199,49 @@ __global__ __launch_bounds__(kBlock) void k_mask_runs(const uint8_t* __restrict_
     unsigned long long nmask = 0;
     if (W <= kWave) {
         const int64_t R = kWave / W;
-        // two steps of R rows per iteration, all loads of both issued first
-        for (int64_t rowA = wave * 2 * R; rowA < nrows; rowA += nwaves * 2 * R) {
-            uint4 v[2][4];
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                // the step's rows are consecutive words of the proxy: lane l's word is word l
-                const int64_t row0 = rowA + u * R;
-                const int64_t rows_here = row0 >= nrows ? 0 : (nrows - row0 < R ? nrows - row0 : R);
-                mask_load64(proxy, row0 * W, rows_here * W, v[u]);
+        // rows of the step at row0 (its rows are consecutive words of the
+        // proxy: lane l's word is word l)
+        auto rows_at = [&](int64_t row0) -> int64_t { return row0 >= nrows ? 0 : (nrows - row0 < R ? nrows - row0 : R); };
+        auto finish = [&](uint64_t m, int64_t row0) {
+            const WordLane wl = word_lane(row0, W, nrows);
+            if (wl.row < 0)
+                m = 0;
+            else if (wl.w == W - 1)
+                m &= lastmask;
+            const uint32_t prev_hi = __shfl_up((uint32_t)(m >> 32), 1);
+            const uint64_t cin = (wl.w > 0) ? (uint64_t)(prev_hi >> 31) : 0ull;
+            const uint64_t starts = m & ~((m << 1) | cin);
+            const uint32_t cnt = (uint32_t)__popcll(starts);
+            nmask += (unsigned long long)__popcll(m);
+            const uint32_t incl = wave_incl_scan(cnt);
+            const uint32_t before = __shfl(incl, wl.seg_first > 0 ? wl.seg_first - 1 : 0);
+            if (wl.row >= 0) {
+                maskbits[wl.row * W + wl.w] = m;
+                if (wl.w == W - 1) row_nruns[wl.row] = incl - (wl.seg_first > 0 ? before : 0u);
             }
+        };
+        if constexpr (P16) {
+            // software pipeline: the next step's eight loads per lane are in
+            // flight while this step's words are formed
+            const int64_t stride = nwaves * R;
+            int64_t row0 = wave * R;
+            uint4 cur[8];
+            mask_load64_16(proxy16, row0 * W, rows_at(row0) * W, cur);
+            for (; row0 < nrows; row0 += stride) {
+                uint4 nxt[8];
+                mask_load64_16(proxy16, (row0 + stride) * W, rows_at(row0 + stride) * W, nxt);
+                finish(mask_words64_16(cur, Q2, T2), row0);
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int64_t row0 = rowA + u * R;
-                const WordLane wl = word_lane(row0, W, nrows);
-                uint64_t m = mask_words64(v[u], TL, TR);
-                if (wl.row < 0)
-                    m = 0;
-                else if (wl.w == W - 1)
-                    m &= lastmask;
-                const uint32_t prev_hi = __shfl_up((uint32_t)(m >> 32), 1);
-                const uint64_t cin = (wl.w > 0) ? (uint64_t)(prev_hi >> 31) : 0ull;
-                const uint64_t starts = m & ~((m << 1) | cin);
-                const uint32_t cnt = (uint32_t)__popcll(starts);
-                nmask += (unsigned long long)__popcll(m);
-                const uint32_t incl = wave_incl_scan(cnt);
-                const uint32_t before = __shfl(incl, wl.seg_first > 0 ? wl.seg_first - 1 : 0);
-                if (wl.row >= 0) {
-                    maskbits[wl.row * W + wl.w] = m;
-                    if (wl.w == W - 1) row_nruns[wl.row] = incl - (wl.seg_first > 0 ? before : 0u);
-                }
+                for (int k = 0; k < 8; ++k) cur[k] = nxt[k];
+            }
+        } else {
+            // two steps per iteration, all loads of both issued first
+            for (int64_t rowA = wave * 2 * R; rowA < nrows; rowA += nwaves * 2 * R) {
+                uint4 v[2][4];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) mask_load64(proxy, (rowA + u * R) * W, rows_at(rowA + u * R) * W, v[u]);
+#pragma unroll
+                for (int u = 0; u < 2; ++u) finish(mask_words64(v[u], TL, TR), rowA + u * R);
             }
         }
     } else {
@@ -178,7 +252,10 @@ __global__ __launch_bounds__(kBlock) void k_mask_runs(const uint8_t* __restrict_
                 const int64_t w = w0 + lane;
                 uint64_t m = 0;
                 if (w < W) {
-                    m = mask_word(proxy + row * P + 64 * w, TL, TR);
+                    if constexpr (P16)
+                        m = mask_word16(proxy16 + row * P + 64 * w, Q2, T2);
+                    else
+                        m = mask_word(proxy + row * P + 64 * w, TL, TR);
                     if (w == W - 1) m &= lastmask;
                 }
                 const uint32_t hi = (uint32_t)(m >> 32);
@@ -202,6 +279,17 @@ __global__ __launch_bounds__(kBlock) void k_mask_runs(const uint8_t* __restrict_
         for (int k = 0; k < kBlock / kWave; ++k) t += s_n[k];
         if (t) atomicAdd(&S->n_mask, t);
     }
+}
+
+// The proxy's kind is device data (the fused pass decides it); the branch is uniform.
+__global__ __launch_bounds__(kBlock) void k_mask_runs(const uint8_t* __restrict__ proxy, int64_t nx, int64_t nrows,
+                                                      int64_t W, DevState* S, uint64_t* __restrict__ maskbits,
+                                                      uint32_t* __restrict__ row_nruns) {
+    if (block_exit_l(S)) return;
+    if (S->p16)
+        mask_runs_body<true>(proxy, nx, nrows, W, S, maskbits, row_nruns);
+    else
+        mask_runs_body<false>(proxy, nx, nrows, W, S, maskbits, row_nruns);
 }
 
 hipError_t launch_mask_runs(const LaunchCtx& lc, const Geom& g, const Layout& L) {

@@ -74,7 +74,11 @@ __device__ __forceinline__ bool block_exit(const DevState* S) {
 
 // ------------------------------------------------------------------ init
 
-__global__ __launch_bounds__(kBlock) void k_init(DevState* S) {
+__device__ bool resolve_bound(double eb, float& eb32, float& w, float& r);
+
+// eb_abs > 0: also the quantiser of that absolute bound (zeros when the bound
+// is unusable; the resolve after the range then reports it)
+__global__ __launch_bounds__(kBlock) void k_init(DevState* S, double eb_abs) {
     {
         if (threadIdx.x == 0) {
             S->status = 0;
@@ -100,18 +104,25 @@ __global__ __launch_bounds__(kBlock) void k_init(DevState* S) {
             S->n_kept = S->n_kept_voxels = 0ull;
             S->span_total = S->n_outliers = S->q_outliers = 0ull;
             S->n_slow = 0u;
+            S->p16 = 0u;
             S->qstatus = 0;
             S->seg_lo = 0u;
             S->saved_status = 0;
             S->serve_r = S->serve_rt = 0.0f;
+            float eb32, w, r;
+            if (eb_abs > 0.0 && resolve_bound(eb_abs, eb32, w, r)) {
+                S->eb32 = eb32;
+                S->w = w;
+                S->r = r;
+            }
         }
         S->hist[threadIdx.x] = 0ull;
     }
 }
 
-hipError_t launch_init(const LaunchCtx& lc, DevState* S) {
+hipError_t launch_init(const LaunchCtx& lc, DevState* S, double eb_abs) {
     timer_begin(lc.timer, ST_INIT, lc.stream);
-    hipLaunchKernelGGL(k_init, dim3(1), dim3(kBlock), 0, lc.stream, S);
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(kBlock), 0, lc.stream, S, eb_abs);
     timer_end(lc.timer, ST_INIT, lc.stream);
     return hipGetLastError();
 }
@@ -268,8 +279,8 @@ __device__ bool resolve_bound(double eb, float& eb32, float& w, float& r) {
     return is_normal_f32(w) && is_normal_f32(r);
 }
 
-__global__ void k_resolve(DevState* S, int is_f32, int eb_mode, double eb_value, int fixed, double fixed_value) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// the quantiser from the range (one thread)
+__device__ void resolve_core(DevState* S, int is_f32, int eb_mode, double eb_value, int fixed, double fixed_value) {
     if (S->nonfinite) {
         qfail(S, ROIX_EINVAL);
         return;
@@ -296,6 +307,11 @@ __global__ void k_resolve(DevState* S, int is_f32, int eb_mode, double eb_value,
     S->qmax = (int32_t)__builtin_rintf(qhi);
     set_width(S);
     if (fixed) resolve_fixed(S, fixed_value);
+}
+
+__global__ void k_resolve(DevState* S, int is_f32, int eb_mode, double eb_value, int fixed, double fixed_value) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    resolve_core(S, is_f32, eb_mode, eb_value, fixed, fixed_value);
 }
 
 hipError_t launch_resolve_dt(const LaunchCtx& lc, DevState* S, roix_dtype dt, roix_eb eb,
@@ -523,12 +539,16 @@ __device__ __forceinline__ void qh_rows(const T* __restrict__ in, int64_t nx, in
 
 constexpr int kQhBlock = 512;  // 8 waves share one set of LDS histogram copies
 
+// unless_p16: nothing to do when the fused pass has already produced the
+// 16-bit proxy and the histogram
 template <typename T, bool CODES, bool FIXED, bool VEC, bool STORE = true>
 __global__ __launch_bounds__(kQhBlock) void k_quant_hist(const T* __restrict__ in, int64_t nx, int64_t nrows,
-                                                       int64_t P, DevState* S, uint8_t* __restrict__ proxy) {
+                                                       int64_t P, DevState* S, uint8_t* __restrict__ proxy,
+                                                       int unless_p16) {
     __shared__ uint32_t lh[kHistCopies * kHistStride];
     for (int i = threadIdx.x; i < kHistCopies * kHistStride; i += blockDim.x) lh[i] = 0u;
     if (block_exit(S)) return;  // contains a barrier, so lh is zeroed for every thread
+    if (unless_p16 && S->p16) return;  // uniform, no barrier below before the flush
     QH p;
     p.r = S->r;
     p.qmin = S->qmin;
@@ -566,13 +586,13 @@ static dim3 qh_grid(const LaunchCtx& lc, const Geom& g) {
 
 template <typename T, bool CODES>
 static void qh_dispatch(const LaunchCtx& lc, const void* in, const Geom& g, DevState* S, uint8_t* proxy,
-                        bool fixed) {
+                        bool fixed, int unless_p16) {
     dim3 grid = qh_grid(lc, g), block(kQhBlock);
     const bool vec = ((uintptr_t)in % 16 == 0) && ((g.nx * (int64_t)sizeof(T)) % 16 == 0);
     const int64_t P = g.W * 64;
 #define QH_LAUNCH(F, V)                                                                                        \
     hipLaunchKernelGGL((k_quant_hist<T, CODES, F, V>), grid, block, 0, lc.stream, (const T*)in, g.nx, g.nrows, P, \
-                       S, proxy)
+                       S, proxy, unless_p16)
     if (fixed) {
         if (vec) QH_LAUNCH(true, true); else QH_LAUNCH(true, false);
     } else {
@@ -582,14 +602,15 @@ static void qh_dispatch(const LaunchCtx& lc, const void* in, const Geom& g, DevS
 }
 
 hipError_t launch_quant_hist(const LaunchCtx& lc, const void* in, int src_kind, const Geom& g, DevState* S,
-                             uint8_t* proxy, bool fixed) {
+                             uint8_t* proxy, bool fixed, bool unless_p16) {
     timer_begin(lc.timer, ST_HIST, lc.stream);
+    const int u = unless_p16 ? 1 : 0;
     if (src_kind == 0)
-        qh_dispatch<float, false>(lc, in, g, S, proxy, fixed);
+        qh_dispatch<float, false>(lc, in, g, S, proxy, fixed, u);
     else if (src_kind == 1)
-        qh_dispatch<uint16_t, false>(lc, in, g, S, proxy, fixed);
+        qh_dispatch<uint16_t, false>(lc, in, g, S, proxy, fixed, u);
     else
-        qh_dispatch<int32_t, true>(lc, in, g, S, proxy, fixed);
+        qh_dispatch<int32_t, true>(lc, in, g, S, proxy, fixed, u);
     timer_end(lc.timer, ST_HIST, lc.stream);
     return hipGetLastError();
 }
@@ -600,10 +621,10 @@ static void hist_only_launch(const LaunchCtx& lc, const void* in, const Geom& g,
     const int64_t P = g.W * 64;
     if (vec)
         hipLaunchKernelGGL((k_quant_hist<T, false, false, true, false>), qh_grid(lc, g), dim3(kQhBlock), 0,
-                           lc.stream, (const T*)in, g.nx, g.nrows, P, S, (uint8_t*)nullptr);
+                           lc.stream, (const T*)in, g.nx, g.nrows, P, S, (uint8_t*)nullptr, 0);
     else
         hipLaunchKernelGGL((k_quant_hist<T, false, false, false, false>), qh_grid(lc, g), dim3(kQhBlock), 0,
-                           lc.stream, (const T*)in, g.nx, g.nrows, P, S, (uint8_t*)nullptr);
+                           lc.stream, (const T*)in, g.nx, g.nrows, P, S, (uint8_t*)nullptr, 0);
 }
 
 hipError_t launch_hist_only(const LaunchCtx& lc, const void* in, roix_dtype dt, const Geom& g, DevState* S) {
@@ -613,6 +634,192 @@ hipError_t launch_hist_only(const LaunchCtx& lc, const void* in, roix_dtype dt, 
     else
         hist_only_launch<uint16_t>(lc, in, g, S);
     timer_end(lc.timer, ST_HIST, lc.stream);
+    return hipGetLastError();
+}
+
+// ------------------------------------ fused range, codes and 16-bit proxy
+
+// With an absolute bound the quantiser is known before the range, so one pass
+// can take the range keys and every voxel's code q together.  The proxy then
+// holds the low 15 bits of q and the outlier flag in bit 15, and each
+// workgroup counts its voxels by q mod 2^15 in LDS.  When the range turns out
+// to span at most 2^15 codes (K <= 2^15), q mod 2^15 identifies q, so the
+// 256-bin histogram follows exactly from these counts and the proxy decodes
+// as q - qmin = (p - qmin) mod 2^15; otherwise the 1-byte proxy pass runs as
+// usual.  Rows start 16-byte aligned and hold a multiple of 4 voxels.
+
+constexpr int kQrThreads = 1024;
+
+__device__ __forceinline__ void qr_vec(const uint4& raw, uint16_t* __restrict__ dst, int64_t vi, float r, float w,
+                                       float eb32, uint32_t* fine, uint32_t& lo, uint32_t& hi, uint32_t& nf) {
+    const float x[4] = {__uint_as_float(raw.x), __uint_as_float(raw.y), __uint_as_float(raw.z),
+                        __uint_as_float(raw.w)};
+    uint32_t p[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t k = range_key<float>(x[j], nf);
+        lo = k < lo ? k : lo;
+        hi = k > hi ? k : hi;
+        const int32_t q = qcode(x[j], r);
+        p[j] = ((uint32_t)q & (uint32_t)(kQrFine - 1)) | (outlier(x[j], q, w, eb32) ? 0x8000u : 0u);
+    }
+    st_stream(reinterpret_cast<uint2*>(dst + 4 * vi), make_uint2(p[0] | (p[1] << 16), p[2] | (p[3] << 16)));
+    // a wave step of one code (a flat region) is one LDS add instead of
+    // 256 adds to the same word
+    const uint32_t f0 = p[0] & 0x7FFFu;
+    const bool same = (((p[0] ^ p[1]) | (p[0] ^ p[2]) | (p[0] ^ p[3])) & 0x7FFFu) == 0u;
+    const uint32_t fs = __builtin_amdgcn_readfirstlane(f0);
+    const uint64_t act = __ballot(true);
+    if (__ballot(!(same && f0 == fs)) == 0ull) {
+        if ((uint32_t)(__ffsll((unsigned long long)act) - 1) == (uint32_t)(threadIdx.x % kWave))
+            atomicAdd(&fine[fs], 4u * (uint32_t)__popcll(act));
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) atomicAdd(&fine[p[j] & 0x7FFFu], 1u);
+    }
+}
+
+__global__ __launch_bounds__(kQrThreads) void k_quant_range16(const float* __restrict__ in, int64_t nx, int64_t nrows,
+                                                            int64_t P, DevState* S, uint16_t* __restrict__ proxy,
+                                                            uint32_t* __restrict__ slots,
+                                                            unsigned long long* __restrict__ fine_total) {
+    __shared__ uint32_t fine[kQrFine];
+    for (int i = threadIdx.x; i < kQrFine; i += blockDim.x) fine[i] = 0u;
+    // this workgroup's share of the totals the reduce adds into
+    for (int i = threadIdx.x; i < kQrFine / kQrBlocks; i += blockDim.x)
+        fine_total[blockIdx.x * (kQrFine / kQrBlocks) + i] = 0ull;
+    if (block_exit(S)) return;  // contains a barrier
+    const float r = S->r, w = S->w, eb32 = S->eb32;
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u, nf = 0u;
+    constexpr int64_t kSlots = (int64_t)kWave * kQhBatch;
+    const int lane = threadIdx.x % kWave;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+    const int64_t nv = nx / 4;
+    int lg = 0;
+    while ((1ll << lg) < nv) ++lg;
+    if ((1ll << lg) < kSlots) {  // several rows per step (row lengths padded to a power of two)
+        const int64_t rpi = kSlots >> lg;
+        for (int64_t row0 = wave * rpi; row0 < nrows; row0 += nwaves * rpi) {
+            uint4 raw[kQhBatch];
+#pragma unroll
+            for (int k = 0; k < kQhBatch; ++k) {
+                const int64_t e = (int64_t)k * kWave + lane;
+                const int64_t row = row0 + (e >> lg), vi = e & ((1ll << lg) - 1);
+                raw[k] = (vi < nv && row < nrows) ? ld_stream(reinterpret_cast<const uint4*>(in + row * nx) + vi)
+                                                  : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int k = 0; k < kQhBatch; ++k) {
+                const int64_t e = (int64_t)k * kWave + lane;
+                const int64_t row = row0 + (e >> lg), vi = e & ((1ll << lg) - 1);
+                if (vi >= nv || row >= nrows) continue;
+                qr_vec(raw[k], proxy + row * P, vi, r, w, eb32, fine, lo, hi, nf);
+            }
+        }
+    } else {
+        for (int64_t row = wave; row < nrows; row += nwaves) {
+            const uint4* vs = reinterpret_cast<const uint4*>(in + row * nx);
+            uint16_t* dst = proxy + row * P;
+            for (int64_t v0 = 0; v0 < nv; v0 += kSlots) {
+                uint4 raw[kQhBatch];
+#pragma unroll
+                for (int k = 0; k < kQhBatch; ++k) {
+                    const int64_t vi = v0 + k * kWave + lane;
+                    raw[k] = vi < nv ? ld_stream(vs + vi) : make_uint4(0, 0, 0, 0);
+                }
+#pragma unroll
+                for (int k = 0; k < kQhBatch; ++k) {
+                    const int64_t vi = v0 + k * kWave + lane;
+                    if (vi < nv) qr_vec(raw[k], dst, vi, r, w, eb32, fine, lo, hi, nf);
+                }
+            }
+        }
+    }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    nf = wave_max(nf);
+    if (lane == 0) {
+        atomicMin(&S->kmin, lo);
+        atomicMax(&S->kmax, hi);
+        if (nf) atomicOr(&S->nonfinite, 1u);
+    }
+    __syncthreads();
+    uint32_t* mine = slots + (int64_t)blockIdx.x * kQrFine;
+    for (int i = threadIdx.x; i < kQrFine; i += blockDim.x) mine[i] = fine[i];
+}
+
+// fine[i] += the counts of code class i of kReduceSlots workgroups (grid.y
+// picks the group of slots; fine was cleared by the pass)
+constexpr int kReduceSlots = 32;
+__global__ __launch_bounds__(256) void k_fine_reduce(const uint32_t* __restrict__ slots,
+                                                     unsigned long long* __restrict__ fine) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t* src = slots + (int64_t)blockIdx.y * kReduceSlots * kQrFine + i;
+    uint32_t c[kReduceSlots];
+#pragma unroll
+    for (int b = 0; b < kReduceSlots; ++b) c[b] = src[(int64_t)b * kQrFine];
+    unsigned long long s = 0;
+#pragma unroll
+    for (int b = 0; b < kReduceSlots; ++b) s += c[b];
+    if (s) atomicAdd(&fine[i], s);
+}
+
+// The quantiser from the range, then (K <= 2^15) the 256-bin histogram from
+// the class counts: class i is the code q = qmin + ((i - qmin) mod 2^15).
+__global__ __launch_bounds__(1024) void k_resolve16(DevState* S, double eb_value, int fixed, double fixed_value,
+                                                    const unsigned long long* __restrict__ fine) {
+    __shared__ unsigned long long sh[256];
+    __shared__ int s_ok;
+    const int t = threadIdx.x;
+    if (t < 256) sh[t] = 0ull;
+    if (t == 0) {
+        resolve_core(S, 1, ROIX_EB_ABS, eb_value, fixed, fixed_value);
+        const bool ok = S->status == 0 && S->K <= (int64_t)kQrFine;
+        S->p16 = ok ? 1u : 0u;
+        s_ok = ok ? 1 : 0;
+    }
+    __syncthreads();
+    if (!s_ok) return;  // uniform
+    const uint32_t qm = (uint32_t)S->qmin, K = (uint32_t)S->K, mlo = S->bin_mlo, mhi = S->bin_mhi;
+    constexpr int kPer = kQrFine / 1024;
+    uint32_t cur = 0;
+    unsigned long long acc = 0ull;
+    for (int j = 0; j < kPer; ++j) {
+        const uint32_t i = (uint32_t)(t * kPer + j);
+        const unsigned long long c = fine[i];
+        const uint32_t u = (i - qm) & (uint32_t)(kQrFine - 1);
+        if (c == 0ull || u >= K) continue;
+        const uint32_t b = bin_fast(u, mlo, mhi);
+        if (b != cur && acc) {
+            atomicAdd(&sh[cur], acc);
+            acc = 0ull;
+        }
+        cur = b;
+        acc += c;
+    }
+    if (acc) atomicAdd(&sh[cur], acc);
+    __syncthreads();
+    if (t < 256) S->hist[t] = sh[t];
+}
+
+hipError_t launch_quant_range16(const LaunchCtx& lc, const float* in, const Geom& g, const Layout& L) {
+    timer_begin(lc.timer, ST_HIST, lc.stream);
+    hipLaunchKernelGGL(k_quant_range16, dim3(kQrBlocks), dim3(kQrThreads), 0, lc.stream, in, g.nx, g.nrows, g.W * 64,
+                       L.S, reinterpret_cast<uint16_t*>(L.proxy), L.fine_slots, L.fine_total);
+    timer_end(lc.timer, ST_HIST, lc.stream);
+    return hipGetLastError();
+}
+
+hipError_t launch_resolve16(const LaunchCtx& lc, const Layout& L, roix_eb eb, const roix_criterion* crit) {
+    const int fixed = crit && crit->thr == ROIX_THR_FIXED;
+    timer_begin(lc.timer, ST_RESOLVE, lc.stream);
+    static_assert(kQrBlocks % kReduceSlots == 0 && kQrFine % kQrBlocks == 0, "reduce tiling");
+    hipLaunchKernelGGL(k_fine_reduce, dim3(kQrFine / 256, kQrBlocks / kReduceSlots), dim3(256), 0, lc.stream,
+                       (const uint32_t*)L.fine_slots, L.fine_total);
+    hipLaunchKernelGGL(k_resolve16, dim3(1), dim3(1024), 0, lc.stream, L.S, eb.value, fixed,
+                       fixed ? crit->fixed_value : 0.0, (const unsigned long long*)L.fine_total);
+    timer_end(lc.timer, ST_RESOLVE, lc.stream);
     return hipGetLastError();
 }
 

@@ -103,7 +103,7 @@ size_t volume_bytes(const Geom& g, roix_dtype dt, bool incremental, int64_t runs
     uint64_t runs = (uint64_t)g.nrows * (uint64_t)runs_per_row;
     const uint64_t w = worst_runs(g);
     if (runs > w) runs = w;
-    return in + fixed_bytes(g, !incremental) + (size_t)runs * kRunBytes;
+    return in + fixed_bytes(g, incremental ? 0 : proxy_kind(g, dt)) + (size_t)runs * kRunBytes;
 }
 
 double pct(std::vector<double> v, double p) {
@@ -323,7 +323,7 @@ roix_status roix_volume_open(roix_server* s, roix_dims dims, roix_dtype dtype, r
     }
     v.d_vol = (uint8_t*)s->base + v.off;
     const size_t in_bytes = align256((size_t)g.N * (dtype == ROIX_F32 ? 4 : 2));
-    if (!carve_at(v.d_vol + in_bytes, v.bytes - in_bytes, g, &v.L, !v.incremental)) {
+    if (!carve_at(v.d_vol + in_bytes, v.bytes - in_bytes, g, &v.L, v.incremental ? 0 : proxy_kind(g, dtype))) {
         s->release(v);
         return ROIX_ENOMEM;
     }

@@ -2,7 +2,10 @@
 
 Bit-exact on every output: quantiser fields, histogram, threshold, component
 table, row table, code stream and outlier values.  Inputs are the seeded
-synthetic volumes of ``synth`` plus hand-made edge cases.
+synthetic volumes of ``synth`` plus hand-made edge cases.  Every case runs
+twice: with the default launch parameters, and with the one-pass 16-bit proxy
+flow of float32 volumes forced down to the smallest volumes
+(fused16_min_voxels = 0), so that both quantiser flows meet every case.
 """
 import numpy as np
 import pytest
@@ -14,14 +17,17 @@ from roixtest import (compare_fused, criterion, default_caps, gpu_fused, log, or
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def env():
+@pytest.fixture(scope="module", params=["default", "fused16"])
+def env(request):
     import torch
 
     from paper_2602_15917_amd import roix
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     roix.load()
     ctx = roix.Context(0, 1 << 30)
+    if request.param == "fused16":
+        ctx.set_param("fused16_min_voxels", 0)
+    log(f"[env] {request.param}")
     yield ctx, roix, torch
     ctx.close()
 
@@ -43,7 +49,8 @@ def test_config0_full(env):
 
 
 SHAPES = [(1, 1, 1), (1, 1, 7), (1, 5, 3), (3, 1, 1), (2, 3, 64), (4, 9, 65), (5, 7, 130), (3, 4, 200),
-          (17, 13, 33), (9, 40, 64), (6, 6, 127), (2, 2, 1000), (40, 3, 5)]
+          (17, 13, 33), (9, 40, 64), (6, 6, 127), (2, 2, 1000), (40, 3, 5), (2, 3, 2052), (2, 2, 4160),
+          (1, 1, 4)]
 
 
 @pytest.mark.parametrize("k", range(len(SHAPES)))
@@ -130,6 +137,22 @@ def test_short_spans(env, max_len, dt):
                      synth.Criterion("fixed", thr, 6, "min_size", 1))
 
 
+@pytest.mark.parametrize("shape", [(4, 16, 256), (3, 9, 192), (2, 5, 4096)])
+def test_large_values_with_outliers(env, shape):
+    # values far above the step, so that fp32 rounding puts many voxels just
+    # outside the bound: escapes in 16-bit (K ~ 1.7e4) and 8-bit (K ~ 125)
+    # code streams, on rows of whole 64-voxel words
+    rng = np.random.default_rng(sum(shape))
+    base = rng.random(shape)
+    v16 = (1000.0 + 1000.0 * base).astype(np.float32)
+    g, o = run_case(env, f"outliers16 {shape}", v16, "abs", 0.03, synth.Criterion("otsu", 0.0, 26, "largest", 1))
+    assert o["info"].n_outliers > 0
+    v8 = (1.0e6 + 2000.0 * base).astype(np.float32)
+    v8[:, : shape[1] // 2, :] += np.float32(1000.0)
+    g, o = run_case(env, f"outliers8 {shape}", v8, "abs", 7.3, synth.Criterion("fixed", 1.0008e6, 6, "min_size", 3))
+    assert o["params"].width_bits == 8 and o["info"].n_outliers > 0
+
+
 def test_uint16_rings_small(env):
     w = synth.config2(nxy=256, nz=12)
     run_case(env, "rings u16 small", w.volume, w.eb_mode, w.eb_value, w.criterion)
@@ -152,6 +175,17 @@ def test_edge_cases(env):
     c6 = synth.Criterion("otsu", 0.0, 6, "min_size", 1)
     # constant volume: degenerate histogram, empty ROI, no rows
     run_case(env, "constant", np.full((4, 5, 66), 0.25, np.float32), "abs", 1e-3, c6)
+    run_case(env, "constant x4", np.full((3, 7, 256), -3.5, np.float32), "abs", 1e-3, c6)
+    # flat regions beside noise; K just below 2^15 with codes on both sides
+    # of zero, then of 2^15, then K above 2^15 (the 1-byte proxy flow)
+    v = synth.normal((4, 16, 128), 11, 0.0, 1.0)
+    v[:, :8, :] = np.float32(-1.0)
+    v[1:3, 4:12, 32:96] = np.float32(2.0)
+    c26 = synth.Criterion("otsu", 0.0, 26, "largest", 1)
+    run_case(env, "flat and noise", v, "abs", 1.2e-4, c26)
+    run_case(env, "flat and noise shifted", (v + np.float32(8.5)).astype(np.float32), "abs", 1.2e-4, c26)
+    run_case(env, "flat and noise fixed", v, "abs", 1.2e-4, synth.Criterion("fixed", 0.3, 6, "min_size", 2))
+    run_case(env, "flat and noise wide", v, "abs", 2e-5, c26)
     # relative bound on a constant volume: invalid bound
     run_case(env, "constant rel", np.full((2, 3, 4), 7.0, np.float32), "rel", 1e-4, c6)
     # everything is object
