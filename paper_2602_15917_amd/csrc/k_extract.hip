@@ -668,7 +668,7 @@ __device__ __forceinline__ void emit_chunk_near(const T* __restrict__ in, const 
 // (phase 4).  Slice table and span walk as in emit_chunk_near, with 512-code
 // slices.
 constexpr uint32_t kP16Slice = 512;
-constexpr int kP16Slices = 4;  // slices per step
+constexpr int kP16Slices = 2;  // slices per step
 
 __device__ __forceinline__ uint32_t half16(const uint32_t (&w)[4], int i) { return (w[i >> 1] >> (16 * (i & 1))) & 0xFFFFu; }
 

@@ -93,18 +93,22 @@ __device__ __forceinline__ uint64_t mask_words64(const uint4 (&v)[4], uint32_t T
 }
 
 // 16-bit proxy (low 15 bits of q, outlier flag in bit 15), two voxels per
-// dword: bit 15 of ((p | 0x8000) - qmin15) & 0x7FFF, plus 0x8000 - tq, is
-// set exactly when q - qmin >= tq (no borrow or carry crosses a half, since
-// q - qmin < 2^15 and 0 <= tq <= 2^15).  Returns the 8 mask bits of 8 voxels.
-__device__ __forceinline__ uint32_t ge_halves8(const uint4& v, uint32_t Q2, uint32_t T2) {
+// dword, with 16-bit lane adds (no carry between the halves): the low 15 bits
+// of p + 2^15 - qmin15 are q - qmin, and bit 15 of that plus 2^15 - tq is set
+// exactly when q - qmin >= tq (q - qmin < 2^15, 0 <= tq <= 2^15).  Returns
+// the 8 mask bits of 8 voxels (voxel i at bit i).
+typedef unsigned short u16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t add_u16x2(uint32_t a, uint32_t b) {
+    return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2_t, a) + __builtin_bit_cast(u16x2_t, b));
+}
+__device__ __forceinline__ uint32_t ge_halves8(const uint4& v, uint32_t A2, uint32_t T2) {
     const uint32_t d[4] = {v.x, v.y, v.z, v.w};
-    uint32_t m = 0;
+    uint32_t z[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint32_t t = ((((d[i] | 0x80008000u) - Q2) & 0x7FFF7FFFu) + T2) & 0x80008000u;
-        m |= (((t >> 15) | (t >> 30)) & 3u) << (2 * i);
-    }
-    return m;
+    for (int i = 0; i < 4; ++i) z[i] = add_u16x2(add_u16x2(d[i], A2) & 0x7FFF7FFFu, T2) & 0x80008000u;
+    // bit 15 of dword i to bit 2 i, bit 31 to bit 2 i + 16, then fold
+    const uint32_t y = (z[0] >> 15) | (z[1] >> 13) | (z[2] >> 11) | (z[3] >> 9);
+    return (y & 0x55u) | ((y >> 15) & 0xAAu);
 }
 
 // mask word of 64 16-bit proxy elements (eight 16-byte loads)
@@ -188,7 +192,7 @@ __device__ __forceinline__ void mask_runs_body(const uint8_t* __restrict__ proxy
     const uint32_t T = 255u - (uint32_t)S->proxy_thr;
     const uint32_t TR = T * 0x01010101u, TL = (T & 0x7Fu) * 0x01010101u;
     // 16-bit proxy: q - qmin >= q_thr - qmin
-    const uint32_t Q2 = ((uint32_t)S->qmin & 0x7FFFu) * 0x00010001u;
+    const uint32_t Q2 = (0x8000u - ((uint32_t)S->qmin & 0x7FFFu)) * 0x00010001u;
     const uint32_t T2 = (0x8000u - (uint32_t)((int64_t)S->q_thr - (int64_t)S->qmin)) * 0x00010001u;
     const uint16_t* proxy16 = reinterpret_cast<const uint16_t*>(proxy);
     const uint64_t lastmask = (nx % 64) ? ((1ull << (nx % 64)) - 1ull) : ~0ull;
