@@ -29,10 +29,10 @@ def log(msg):
 
 # source file of each stage's kernels: a traffic figure measured by the
 # counters is only reported while that file is unchanged
-STAGE_SOURCE = {"range": "k_quant.hip", "quant_hist": "k_quant.hip", "mask_runs": "k_label.hip",
-                "emit": "k_extract.hip"}
-STAGE_KERNEL = {"range": "k_range<float>", "quant_hist": "k_quant_hist<float, false, false, true>",
-                "mask_runs": "k_mask_runs", "emit": "k_emit_codes<float, 2>"}
+STAGE_SOURCE = {"range": "k_quant.hip", "quant_hist": "k_quant.hip", "quant_range16": "k_quant.hip",
+                "mask_runs": "k_label.hip", "emit": "k_extract.hip"}
+STAGE_KERNEL = {"range": "k_range<float>", "quant_hist": "k_quant_hist<float, false, false, true, true>",
+                "quant_range16": "k_quant_range16", "mask_runs": "k_mask_runs", "emit": "k_emit_codes_p16"}
 CALIB_BYTES = 1 << 30
 
 
@@ -45,7 +45,7 @@ def source_sha(stage):
 def measured_traffic(stage):
     """(fetch, write) HBM bytes per launch from the committed counter summary,
     or None when there is none or the kernel source has changed since."""
-    f = os.path.join(ROOT, "profiles", "traffic_config1_1024cubed_f32.txt")
+    f = os.path.join(ROOT, "profiles", "traffic_cylinder_1024cubed_f32.txt")
     if not os.path.exists(f):
         return None
     vals = {}
@@ -102,16 +102,20 @@ def pmc_summary(fetch_csv, write_csv, kt_csv):
             print(f"stage {st} {f:.6g} {sum(wv) / len(wv) * sw:.6g} {source_sha(st)}")
 
 
-def algorithmic_bytes(stage, N, s, n_codes, code_bytes, n_rows, nrows_all, W):
-    """Bytes a launch of `stage` must move at minimum (per call of the path)."""
+def algorithmic_bytes(stage, N, s, n_codes, code_bytes, n_rows, nrows_all, W, p16):
+    """Bytes a launch of `stage` must move at minimum (per call of the path).
+    p16: the call took the one-pass flow with the 16-bit code proxy."""
+    pb = 2 if p16 else 1                      # proxy bytes per voxel
     if stage == "range":
         return N * s
     if stage == "quant_hist":
         return N * s + N                      # read the volume, write the 1-byte bin proxy
+    if stage == "quant_range16":
+        return N * s + 2 * N                  # read the volume, write the 16-bit code proxy
     if stage == "mask_runs":
-        return N + nrows_all * W * 8          # read the proxy, write the row bitmask
-    if stage == "emit":
-        return n_codes * (s + code_bytes) + n_rows * 32
+        return N * pb + nrows_all * W * 8     # read the proxy, write the row bitmask
+    if stage == "emit":                       # read span voxels (proxy or values), write codes, row descriptors
+        return n_codes * ((2 if p16 else s) + code_bytes) + n_rows * 32
     return None
 
 
@@ -399,7 +403,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
     t0 = time.time()
-    w = synth.config1(n=args.n)
+    w = synth.cylinder1024(n=args.n)
     vol = w.volume
     nz, ny, nx = vol.shape
     N, s = vol.size, vol.itemsize
@@ -458,21 +462,29 @@ def main():
         for k, (avg, cnt) in sorted(per.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
             if cnt:
                 log(f"  stage {k:12s} {avg * 1e3:9.1f} us x {cnt // args.steps}")
-        dom = max((k for k in per if algorithmic_bytes(k, N, s, e.n_codes, code_bytes, e.n_rows, nrows_all, W)),
+        p16 = per.get("quant_range16", (0.0, 0))[1] > 0
+        dom = max((k for k in per if per[k][1] and algorithmic_bytes(k, N, s, e.n_codes, code_bytes, e.n_rows,
+                                                                      nrows_all, W, p16)),
                   key=lambda k: per[k][0])
         avg_ms = per[dom][0]
-        byts = algorithmic_bytes(dom, N, s, e.n_codes, code_bytes, e.n_rows, nrows_all, W)
+        byts = algorithmic_bytes(dom, N, s, e.n_codes, code_bytes, e.n_rows, nrows_all, W, p16)
         ach = byts / (avg_ms * 1e-3) / 1e9
         tr = measured_traffic(dom)
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": (round(tr[0] + tr[1]) if tr else None),
                 "traffic_fetch_write": ([round(tr[0]), round(tr[1])] if tr else None),
                 "alg_bytes_per_launch": int(byts), "avg_launch_ms": round(avg_ms, 4)}
-    # whole-path byte model: two input reads, 1-byte proxy written and read,
-    # span voxels re-read, codes written, row table written
+    # whole-path byte model of the method's stages: two input reads (range,
+    # quantise + histogram), 1-byte proxy written and read, span voxels
+    # re-read, codes written, row table written.  design_bytes: what the flow
+    # this call took moves at minimum (one input read, the 16-bit proxy written
+    # and read twice for the mask and the span codes, codes and rows written).
     b_alg = N * (2 * s + 2) + e.n_codes * (s + code_bytes) + 32 * e.n_rows
     path = {"alg_bytes": int(b_alg), "achieved": round(b_alg / (ms * 1e-3) / 1e9, 1),
             "frac": round(b_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if stages and per.get("quant_range16", (0.0, 0))[1] > 0:
+        b_des = N * (s + 2) + (2 * N + nrows_all * W * 8) + e.n_codes * (2 + code_bytes) + 32 * e.n_rows
+        path.update({"design_bytes": int(b_des), "design_frac": round(b_des / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
 
     if args.calibrate_copy:
         a = torch.empty(CALIB_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)

@@ -30,7 +30,7 @@ void timer_end(Timer* t, int stage, hipStream_t s) {
 }
 
 static const char* kStageNames[ST_COUNT] = {
-    "init", "range", "resolve", "quantize", "quant_hist", "otsu", "mask_runs", "scan", "runs_write",
+    "init", "range", "resolve", "quantize", "quant_hist", "quant_range16", "otsu", "mask_runs", "scan", "runs_write",
     "union", "flatten", "comp_stats", "keep", "spans", "emit", "emit_rows", "voxel_out", "finalize"};
 
 }  // namespace roix

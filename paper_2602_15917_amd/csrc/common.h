@@ -201,6 +201,7 @@ enum Stage {
     ST_RESOLVE,
     ST_QUANTIZE,
     ST_HIST,
+    ST_QR16,
     ST_OTSU,
     ST_MASK_RUNS,
     ST_SCAN,

@@ -781,15 +781,17 @@ __global__ __launch_bounds__(1024) void k_resolve16(DevState* S, double eb_value
     }
     __syncthreads();
     if (!s_ok) return;  // uniform
+    // only the K classes of codes qmin .. qmax can hold voxels; thread t
+    // takes a run of consecutive codes u = q - qmin
     const uint32_t qm = (uint32_t)S->qmin, K = (uint32_t)S->K, mlo = S->bin_mlo, mhi = S->bin_mhi;
-    constexpr int kPer = kQrFine / 1024;
+    const uint32_t per = (K + 1023u) / 1024u;
     uint32_t cur = 0;
     unsigned long long acc = 0ull;
-    for (int j = 0; j < kPer; ++j) {
-        const uint32_t i = (uint32_t)(t * kPer + j);
-        const unsigned long long c = fine[i];
-        const uint32_t u = (i - qm) & (uint32_t)(kQrFine - 1);
-        if (c == 0ull || u >= K) continue;
+    for (uint32_t j = 0; j < per; ++j) {
+        const uint32_t u = (uint32_t)t * per + j;
+        if (u >= K) break;
+        const unsigned long long c = fine[(qm + u) & (uint32_t)(kQrFine - 1)];
+        if (c == 0ull) continue;
         const uint32_t b = bin_fast(u, mlo, mhi);
         if (b != cur && acc) {
             atomicAdd(&sh[cur], acc);
@@ -804,10 +806,10 @@ __global__ __launch_bounds__(1024) void k_resolve16(DevState* S, double eb_value
 }
 
 hipError_t launch_quant_range16(const LaunchCtx& lc, const float* in, const Geom& g, const Layout& L) {
-    timer_begin(lc.timer, ST_HIST, lc.stream);
+    timer_begin(lc.timer, ST_QR16, lc.stream);
     hipLaunchKernelGGL(k_quant_range16, dim3(kQrBlocks), dim3(kQrThreads), 0, lc.stream, in, g.nx, g.nrows, g.W * 64,
                        L.S, reinterpret_cast<uint16_t*>(L.proxy), L.fine_slots, L.fine_total);
-    timer_end(lc.timer, ST_HIST, lc.stream);
+    timer_end(lc.timer, ST_QR16, lc.stream);
     return hipGetLastError();
 }
 

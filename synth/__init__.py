@@ -9,18 +9,18 @@ The workloads stand in for the paper's X-CT datasets (Table 1: cylindrical
 samples in air, 16-bit slice stacks of up to 42 GB), which are not available
 here.  Recipes:
 
-* ``config0``: 128^3 float32, N(0.10, 0.02) background, 3 axis-aligned solid
+* ``ellipsoids128``: 128^3 float32, N(0.10, 0.02) background, 3 axis-aligned solid
   ellipsoids (semi-axes U[10, 30], level U(0.6, 0.9) + N(0, 0.02)); criterion
   eb = 1e-3 absolute, Otsu, 6-connectivity, keep components of >= 64 voxels.
-* ``config1``: 1024^3 float32 z-axis cylinder, R = 400, air N(0.02, 0.01),
+* ``cylinder1024``: 1024^3 float32 z-axis cylinder, R = 400, air N(0.02, 0.01),
   matrix N(0.5, 0.03), 20 000 pores (r U[2, 12], N(0.05, 0.01)) then 500
   inclusions (r U[3, 8], N(0.95, 0.03)); eb = 1e-4 absolute, Otsu,
   26-connectivity, largest component.
-* ``config2``: 2048 x 2048 x 1024 uint16 cylinder, R = 633 (30 % of the field
+* ``rings2048``: 2048 x 2048 x 1024 uint16 cylinder, R = 633 (30 % of the field
   of view), Gaussian-approximated Poisson counts (mean 12000 inside, 800
   outside) plus 40 ring artefacts of amplitude 200; eb = 1e-4 of the value
   range, Otsu, 26-connectivity, largest component.
-* ``batch_volume(j)``: the config-0 recipe with 1..8 ellipsoids and side
+* ``batch_volume(j)``: the ellipsoids128 recipe with 1..8 ellipsoids and side
   lengths U{64..512} per axis, eb drawn from {1e-3, 1e-4, 1e-5}.
 """
 from __future__ import annotations
@@ -177,26 +177,26 @@ def normal(shape, seed, mu=0.0, sd=1.0, threads=None):
 
 # ------------------------------------------------------------------ workloads
 
-def config0(seed=1000, with_cls=False, threads=None) -> Workload:
+def ellipsoids128(seed=1000, with_cls=False, threads=None) -> Workload:
     vol, cls = ellipsoids(128, 128, 128, seed, n_ell=3, with_cls=with_cls, threads=threads)
-    return Workload("config0: 128^3 f32 ellipsoids", vol, "abs", 1e-3,
+    return Workload("128^3 f32 ellipsoids", vol, "abs", 1e-3,
                     Criterion("otsu", 0.0, 6, "min_size", 64), cls)
 
 
-def config1(seed=1001, with_cls=False, threads=None, n=1024) -> Workload:
+def cylinder1024(seed=1001, with_cls=False, threads=None, n=1024) -> Workload:
     """The 1024^3 cylinder; ``n`` < 1024 gives the same recipe scaled down
     (radius, pore and inclusion counts scale with the volume)."""
     s = n / 1024.0
     vol, cls = cylinder(n, n, n, seed, R=400.0 * s, n_pores=int(round(20000 * s ** 3)),
                         n_incl=int(round(500 * s ** 3)), with_cls=with_cls, threads=threads)
-    return Workload(f"config1: {n}^3 f32 cylinder, pores, inclusions", vol, "abs", 1e-4,
+    return Workload(f"{n}^3 f32 cylinder, pores, inclusions", vol, "abs", 1e-4,
                     Criterion("otsu", 0.0, 26, "largest", 1), cls)
 
 
-def config2(seed=1002, with_cls=False, threads=None, nxy=2048, nz=1024) -> Workload:
+def rings2048(seed=1002, with_cls=False, threads=None, nxy=2048, nz=1024) -> Workload:
     s = nxy / 2048.0
     vol, cls = rings(nxy, nxy, nz, seed, R=633.0 * s, ring_rmax=1448.0 * s, with_cls=with_cls, threads=threads)
-    return Workload(f"config2: {nxy}x{nxy}x{nz} u16 cylinder, rings", vol, "rel", 1e-4,
+    return Workload(f"{nxy}x{nxy}x{nz} u16 cylinder, rings", vol, "rel", 1e-4,
                     Criterion("otsu", 0.0, 26, "largest", 1), cls)
 
 

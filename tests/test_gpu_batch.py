@@ -24,8 +24,8 @@ def batch_env():
     from paper_2602_15917_amd import roix
     vols = [synth.batch_volume(j, side=(24, 96)) for j in range(12)]
     # a uint16 and a cylinder volume make the batch mixed in dtype and criterion
-    vols.append(synth.config2(nxy=96, nz=9))
-    vols.append(synth.config1(n=80))
+    vols.append(synth.rings2048(nxy=96, nz=9))
+    vols.append(synth.cylinder1024(n=80))
     ctx = roix.Context(0, 1 << 30)
     items, plain = [], []
     for w in vols:

@@ -42,9 +42,9 @@ def run_case(env, name, vol, eb_mode, eb_value, crit_o, caps=None):
     return g, o
 
 
-def test_config0_full(env):
-    w = synth.config0()
-    g, o = run_case(env, "config0", w.volume, w.eb_mode, w.eb_value, w.criterion)
+def test_ellipsoids128_full(env):
+    w = synth.ellipsoids128()
+    g, o = run_case(env, "ellipsoids128", w.volume, w.eb_mode, w.eb_value, w.criterion)
     assert o["info"].n_components == 3 and g["einfo"].n_codes > 0
 
 
@@ -95,7 +95,7 @@ def test_segment_parameters(env, seg_runs, seg_grid):
         for conn in (6, 26):
             run_case(env, f"segments T={seg_runs} G={seg_grid} noise", vol, "abs", 1e-3,
                      synth.Criterion("fixed", 0.55, conn, "min_size", 2))
-        w = synth.config1(n=96)
+        w = synth.cylinder1024(n=96)
         run_case(env, f"segments T={seg_runs} G={seg_grid} cylinder", w.volume, w.eb_mode, w.eb_value, w.criterion)
     finally:
         ctx.set_param("seg_runs", 0)
@@ -154,12 +154,12 @@ def test_large_values_with_outliers(env, shape):
 
 
 def test_uint16_rings_small(env):
-    w = synth.config2(nxy=256, nz=12)
+    w = synth.rings2048(nxy=256, nz=12)
     run_case(env, "rings u16 small", w.volume, w.eb_mode, w.eb_value, w.criterion)
 
 
 def test_cylinder_medium(env):
-    w = synth.config1(n=192)
+    w = synth.cylinder1024(n=192)
     run_case(env, "cylinder 192^3", w.volume, w.eb_mode, w.eb_value, w.criterion)
 
 
@@ -219,7 +219,7 @@ def test_edge_cases(env):
 def test_misaligned_input(env):
     # volumes that do not start on a 16-byte boundary: element-wise head/tail paths
     ctx, roix, torch = env
-    for w, offs in ((synth.config0(), (1, 2, 3)), (synth.config2(nxy=64, nz=5), (1, 3, 5, 7))):
+    for w, offs in ((synth.ellipsoids128(), (1, 2, 3)), (synth.rings2048(nxy=64, nz=5), (1, 3, 5, 7))):
         n = w.volume.size
         flat = torch.from_numpy(np.ascontiguousarray(w.volume).ravel()).to("cuda:0")
         base = torch.zeros(n + 8, dtype=flat.dtype, device="cuda:0")
@@ -236,7 +236,7 @@ def test_misaligned_input(env):
 
 
 def test_truncation_reports_full_counts(env):
-    w = synth.config0()
+    w = synth.ellipsoids128()
     c = w.criterion
     caps = (10, 100, 0, 3)
     run_case(env, "etrunc rows/stream", w.volume, w.eb_mode, w.eb_value, c, caps)
@@ -265,8 +265,8 @@ def test_scratch_too_small_for_runs(env):
 
 def test_staged_equals_fused_and_oracle(env):
     ctx, roix, torch = env
-    for name, w in (("config0", synth.config0()), ("rings", synth.config2(nxy=128, nz=6)),
-                    ("cyl", synth.config1(n=96))):
+    for name, w in (("ellipsoids128", synth.ellipsoids128()), ("rings", synth.rings2048(nxy=128, nz=6)),
+                    ("cyl", synth.cylinder1024(n=96))):
         for conn in (6, 26):
             c = synth.Criterion(w.criterion.thr, 0.0, conn, w.criterion.keep, w.criterion.min_size)
             crit = criterion(roix, c)
@@ -307,7 +307,7 @@ def test_staged_equals_fused_and_oracle(env):
 
 def test_repeat_determinism(env):
     ctx, roix, torch = env
-    w = synth.config1(n=128)
+    w = synth.cylinder1024(n=128)
     crit = criterion(roix, w.criterion)
     ref = None
     for i in range(5):

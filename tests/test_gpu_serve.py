@@ -81,9 +81,9 @@ def stream_volume(env, srv, vol, eb_mode, eb_value, crit, sizes, source="device"
 
 CASES = [
     # (name, volume factory, eb, criterion)
-    ("cylinder f32 fixed 26", lambda: synth.config1(n=96).volume, ("abs", 1e-4),
+    ("cylinder f32 fixed 26", lambda: synth.cylinder1024(n=96).volume, ("abs", 1e-4),
      synth.Criterion("fixed", 0.3, 26, "largest", 1)),
-    ("rings u16 fixed 6", lambda: synth.config2(nxy=160, nz=23).volume, ("abs", 3.0),
+    ("rings u16 fixed 6", lambda: synth.rings2048(nxy=160, nz=23).volume, ("abs", 3.0),
      synth.Criterion("fixed", 6400.0, 6, "min_size", 5)),
     ("noise f32 fixed 26", lambda: synth.normal((17, 41, 70), 7100, 0.5, 0.1), ("abs", 1e-3),
      synth.Criterion("fixed", 0.55, 26, "min_size", 1)),
@@ -143,7 +143,7 @@ def test_host_pinned_source(env):
 def test_deferred_volumes_equal_plain(env, thr, ebm):
     # an Otsu threshold or a relative bound needs the whole volume: reduced at close
     ctx, roix, torch = env
-    w = synth.config0()
+    w = synth.ellipsoids128()
     c = synth.Criterion(thr, 0.5, 6, "min_size", 64)
     ebv = w.eb_value if ebm == "abs" else 1e-3
     crit = criterion(roix, c)

@@ -32,15 +32,15 @@ def test_philox_known_answers():
 
 
 def test_generator_thread_invariance():
-    a = synth.config1(n=96, threads=1).volume
-    b = synth.config1(n=96, threads=4).volume
+    a = synth.cylinder1024(n=96, threads=1).volume
+    b = synth.cylinder1024(n=96, threads=4).volume
     assert a.tobytes() == b.tobytes()
 
 
 # ------------------------------------------------------------------- range
 
 def test_range_matches_numpy_and_signed_zero():
-    w = synth.config0()
+    w = synth.ellipsoids128()
     st, lo, hi = oracle.value_range(w.volume)
     assert st == oracle.OK and lo == w.volume.min() and hi == w.volume.max()
     v = np.array([0.0, -0.0, 0.0], np.float32)
@@ -111,7 +111,7 @@ def test_codes_closed_form_on_grid_points():
 
 
 def test_codes_bound_and_exact_rounding_cross_check():
-    w = synth.config0()
+    w = synth.ellipsoids128()
     x = w.volume.ravel()
     _, lo, hi = oracle.value_range(x)
     p = oracle.resolve(lo, hi, "abs", 1e-3)
@@ -365,7 +365,7 @@ def test_hand_worked_example():
 
 
 def test_decode_round_trip_and_span_invariants():
-    w = synth.config0(with_cls=True)
+    w = synth.ellipsoids128(with_cls=True)
     c = w.criterion
     r = oracle.fused(w.volume, w.eb_mode, w.eb_value, c.thr, 0.0, c.connectivity, c.keep, c.min_size)
     p, info = r["params"], r["info"]
@@ -386,7 +386,7 @@ def test_decode_round_trip_and_span_invariants():
 
 
 def test_etrunc_reports_full_counts():
-    w = synth.config0()
+    w = synth.ellipsoids128()
     c = w.criterion
     full = oracle.fused(w.volume, w.eb_mode, w.eb_value, c.thr, 0.0, c.connectivity, c.keep, c.min_size)
     small = oracle.fused(w.volume, w.eb_mode, w.eb_value, c.thr, 0.0, c.connectivity, c.keep, c.min_size,
@@ -406,8 +406,8 @@ def _dsc(a, b):
     return 2.0 * (a & b).sum() / (a.sum() + b.sum())
 
 
-def test_ground_truth_config0():
-    w = synth.config0(with_cls=True)
+def test_ground_truth_ellipsoids128():
+    w = synth.ellipsoids128(with_cls=True)
     c = w.criterion
     r = oracle.fused(w.volume, w.eb_mode, w.eb_value, c.thr, 0.0, c.connectivity, c.keep, c.min_size)
     info = r["info"]
@@ -420,7 +420,7 @@ def test_ground_truth_config0():
 
 
 def test_ground_truth_cylinder_spans():
-    w = synth.config1(n=160, with_cls=True)
+    w = synth.cylinder1024(n=160, with_cls=True)
     c = w.criterion
     r = oracle.fused(w.volume, w.eb_mode, w.eb_value, c.thr, 0.0, c.connectivity, c.keep, c.min_size)
     info = r["info"]
@@ -441,7 +441,7 @@ def test_ground_truth_cylinder_spans():
 
 
 def test_ground_truth_rings_u16():
-    w = synth.config2(nxy=256, nz=8, with_cls=True)
+    w = synth.rings2048(nxy=256, nz=8, with_cls=True)
     c = w.criterion
     r = oracle.fused(w.volume, w.eb_mode, w.eb_value, c.thr, 0.0, c.connectivity, c.keep, c.min_size)
     info = r["info"]
