@@ -119,6 +119,67 @@ def algorithmic_bytes(stage, N, s, n_codes, code_bytes, n_rows, nrows_all, W, p1
     return None
 
 
+def bench_decode(args):
+    """The reverse process of the benchmark volume's extraction: decoded
+    GB/s (float32 output bytes per second) and the roofline of the row
+    kernel, which writes every voxel once and reads the span codes."""
+    import torch
+
+    import synth
+    from paper_2602_15917_amd import roix
+    dev = "cuda:0"
+    w = synth.cylinder1024(n=args.n)
+    x = torch.from_numpy(w.volume).to(dev)
+    del w.volume
+    crit = roix.Criterion(w.criterion.thr, 0.0, w.criterion.connectivity, w.criterion.keep, w.criterion.min_size)
+    dims = roix.dims_of(x)
+    ctx = roix.Context(0, roix.scratch_bytes(dims, roix.F32, crit))
+    b = roix.bounds(dims, roix.F32, crit)
+    out = roix.Outputs(dev, b["rows"], b["stream_bytes"], 1 << 22, 1 << 22)
+    ctx.fused(x, w.eb_mode, w.eb_value, crit, out)
+    torch.cuda.synchronize()
+    e = out.collect()["einfo"]
+    qi = out.collect()["qinfo"]
+    dst = torch.empty_like(x)
+    dinfo = torch.zeros(32, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        ctx.decode(out, dims, 0.0, dst, dinfo, stream)
+    torch.cuda.synchronize()
+    assert roix.decode_info(dinfo).status == 0
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        ctx.decode(out, dims, 0.0, dst, dinfo, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    N = x.numel()
+    ctx.set_timing(True)
+    for _ in range(args.steps):
+        ctx.decode(out, dims, 0.0, dst, dinfo, stream)
+    st = ctx.read_timing()
+    ctx.set_timing(False)
+    k_ms = st["decode"][0] / max(st["decode"][1], 1)
+    c = int(qi.width_bits) // 8
+    byts = N * 4 + int(e.n_codes) * c + 32 * int(e.n_rows) + 4 * int(e.n_outliers)
+    ach = byts / (k_ms * 1e-3) / 1e9
+    line = {
+        "metric": "decoded GB/s (reverse process of the extraction, float32 output bytes)",
+        "value": round(N * 4 / (ms * 1e-3) / 1e9, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"decode of the {w.name} extraction", "n_rows": int(e.n_rows),
+                   "n_codes": int(e.n_codes), "n_outliers": int(e.n_outliers), "code_bits": int(qi.width_bits)},
+        "roofline": {"bound": "hbm", "kernel": "decode_rows", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "alg_bytes_per_launch": int(byts), "avg_launch_ms": round(k_ms, 4)},
+        "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in st.items() if v[1]},
+    }
+    print(json.dumps(line))
+    ctx.close()
+
+
 def bench_batched(args):
     """64 float32 volumes, sides U{64..512} per axis, 1-8 ellipsoids, eb from
     {1e-3, 1e-4, 1e-5}: one batched graph launch against the same volumes
@@ -369,9 +430,10 @@ def main():
                     help="also run a plain device copy of 1 GiB (the counter calibration for traffic)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL_STATS_CSV"),
                     help="summarise rocprofv3 counter runs of this script and exit")
-    ap.add_argument("--workload", choices=["plain", "batched", "served"], default="plain",
+    ap.add_argument("--workload", choices=["plain", "batched", "served", "decode"], default="plain",
                     help="plain: the 1024^3 volume (default); batched: 64 uneven volumes in one graph launch; "
-                         "served: open-loop slab-stream trace with p50/p99 latency")
+                         "served: open-loop slab-stream trace with p50/p99 latency; decode: the reverse "
+                         "process of the 1024^3 volume's extraction")
     ap.add_argument("--served-streams", type=int, default=4, help="uint16 2048x2048 streams of the served trace")
     ap.add_argument("--served-nz", type=int, default=256, help="planes per served stream (slabs of 32)")
     ap.add_argument("--served-cubes", type=int, default=16, help="float32 cubes interleaved in the served trace")
@@ -389,6 +451,8 @@ def main():
         return bench_batched(args)
     if args.workload == "served":
         return bench_served(args)
+    if args.workload == "decode":
+        return bench_decode(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the reduction path has no multi-GPU "
               f"form in this build", file=sys.stderr)

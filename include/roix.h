@@ -242,6 +242,47 @@ roix_status roix_extract(roix_ctx* ctx, const void* d_in, roix_dtype dtype, cons
 roix_status roix_fused(roix_ctx* ctx, const void* d_in, roix_dtype dtype, roix_dims dims, roix_eb eb,
                        const roix_criterion* crit, const roix_fused_out* out, void* stream);
 
+/* Decode: the reverse process of Sec. 4.3, which rebuilds the volume from
+ * the geometry section (Eq. 3, the row table), the pixel section (Eq. 4,
+ * the code stream) and the outlier values, as written by roix_extract or
+ * roix_fused.  Voxel (z, y, x) inside the span [xs, xe) of a row takes
+ * (float)(u + qmin) * w for its code u (float32 multiply), or, for the
+ * escape code, the next outlier value of its row in order of x (starting at
+ * the row's outlier_off); every other voxel takes `background`.
+ *   d_rows, rows_cap          the row table and its capacity (entries)
+ *   d_stream, stream_cap_bytes the code stream and its capacity (bytes)
+ *   d_outliers, outliers_cap  outlier values and their capacity
+ *   d_qinfo                   the quantiser (qmin, w, width_bits, esc)
+ *   d_einfo                   the counts n_rows, n_codes, n_outliers
+ *   d_out                     N float32, C order [nz][ny][nx]; every voxel
+ *                             is written
+ *   d_dinfo                   device: status and the counts used
+ * All device pointers, caller-owned; the call reads the counts on the
+ * device, so it can follow roix_fused on the same stream without a host
+ * synchronisation.  The context's arena holds a row descriptor of 32 bytes
+ * per row (ny * nz) while the call runs.
+ * d_dinfo->status is ROIX_EINVAL (and d_out unspecified) when the inputs are
+ * not one consistent extraction: the quant or extract status is not OK, a
+ * count exceeds its capacity, the width is not 8/16/32 or esc not 2^b - 1,
+ * a row lies outside the volume or has xs >= xe or codes beyond n_codes,
+ * rows are not in strictly increasing raster order, the first row's
+ * outlier_off is not 0, or a row's outlier_off plus its escapes is not the
+ * next row's (n_outliers for the last row).
+ * Errors: ROIX_EINVAL (NULL ctx/d_qinfo/d_einfo/d_out/d_dinfo, bad dims,
+ * negative or unbacked capacities, misaligned buffers), ROIX_ENOMEM (arena
+ * smaller than the row descriptors), ROIX_EDEVICE. */
+typedef struct {
+    int32_t status;
+    int32_t pad;
+    uint64_t n_rows;
+    uint64_t n_codes;
+    uint64_t n_outliers;
+} roix_decode_info; /* 32 bytes */
+roix_status roix_decode(roix_ctx* ctx, const roix_row* d_rows, int64_t rows_cap, const void* d_stream,
+                        int64_t stream_cap_bytes, const float* d_outliers, int64_t outliers_cap,
+                        const roix_quant_info* d_qinfo, const roix_extract_info* d_einfo, roix_dims dims,
+                        float background, float* d_out, roix_decode_info* d_dinfo, void* stream);
+
 /* One volume of a batch: input, shape, bound, criterion and the caller's
  * output buffers (as for roix_fused). */
 typedef struct {
@@ -410,7 +451,7 @@ const char* roix_status_string(roix_status st);
 /* sizeof of a public struct by name ("roix_quant_info", "roix_seg_info",
  * "roix_extract_info", "roix_component", "roix_row", "roix_fused_out",
  * "roix_criterion", "roix_eb", "roix_dims", "roix_volume_desc",
- * "roix_req_result", "roix_server_stats_t"), 0 if unknown: lets bindings
+ * "roix_req_result", "roix_server_stats_t", "roix_decode_info"), 0 if unknown: lets bindings
  * check their mirrors of this header. */
 size_t roix_sizeof(const char* type_name);
 

@@ -31,7 +31,7 @@ void timer_end(Timer* t, int stage, hipStream_t s) {
 
 static const char* kStageNames[ST_COUNT] = {
     "init", "range", "resolve", "quantize", "quant_hist", "quant_range16", "otsu", "mask_runs", "scan", "runs_write",
-    "union", "flatten", "comp_stats", "keep", "spans", "emit", "emit_rows", "voxel_out", "finalize"};
+    "union", "flatten", "comp_stats", "keep", "spans", "emit", "emit_rows", "voxel_out", "finalize", "decode_index", "decode"};
 
 }  // namespace roix
 
@@ -282,7 +282,8 @@ size_t roix_sizeof(const char* t) {
                      {"roix_row", sizeof(roix_row)},                   {"roix_fused_out", sizeof(roix_fused_out)},
                      {"roix_criterion", sizeof(roix_criterion)},       {"roix_eb", sizeof(roix_eb)},
                      {"roix_dims", sizeof(roix_dims)},                 {"roix_volume_desc", sizeof(roix_volume_desc)},
-                     {"roix_req_result", sizeof(roix_req_result)},     {"roix_server_stats_t", sizeof(roix_server_stats_t)}};
+                     {"roix_req_result", sizeof(roix_req_result)},     {"roix_server_stats_t", sizeof(roix_server_stats_t)},
+                     {"roix_decode_info", sizeof(roix_decode_info)}};
     for (const auto& e : tab)
         if (strcmp(e.n, t) == 0) return e.s;
     return 0;
@@ -472,6 +473,27 @@ roix_status roix_fused(roix_ctx* ctx, const void* d_in, roix_dtype dtype, roix_d
     Layout L;
     if (!carve(ctx, g, &L, dtype)) return ROIX_ENOMEM;
     return enqueue_fused(lctx(ctx, stream), g, L, d_in, dtype, eb, crit, out);
+}
+
+roix_status roix_decode(roix_ctx* ctx, const roix_row* d_rows, int64_t rows_cap, const void* d_stream,
+                        int64_t stream_cap_bytes, const float* d_outliers, int64_t outliers_cap,
+                        const roix_quant_info* d_qinfo, const roix_extract_info* d_einfo, roix_dims dims,
+                        float background, float* d_out, roix_decode_info* d_dinfo, void* stream) {
+    Geom g;
+    if (!ctx || !d_qinfo || !d_einfo || !d_out || !d_dinfo || !geom_of(dims, &g)) return ROIX_EINVAL;
+    if (rows_cap < 0 || stream_cap_bytes < 0 || outliers_cap < 0) return ROIX_EINVAL;
+    if ((rows_cap > 0 && (!d_rows || !aligned(d_rows, 8))) || (stream_cap_bytes > 0 && !d_stream) ||
+        (outliers_cap > 0 && (!d_outliers || !aligned(d_outliers, 4))) || !aligned(d_out, 4) ||
+        (d_stream && !aligned(d_stream, 4)) || !aligned(d_dinfo, 8))
+        return ROIX_EINVAL;
+    const size_t need = align256(sizeof(DevState)) + align256((size_t)g.nrows * 32);
+    if (ctx->arena_bytes < need) return ROIX_ENOMEM;
+    DevState* S = (DevState*)ctx->arena;
+    uint4* desc = (uint4*)((uint8_t*)ctx->arena + align256(sizeof(DevState)));
+    ROIX_TRY(launch_decode(lctx(ctx, stream), d_rows, (uint64_t)rows_cap, d_stream, (uint64_t)stream_cap_bytes,
+                           d_outliers, (uint64_t)outliers_cap, d_qinfo, d_einfo, g, background, d_out, S, desc,
+                           d_dinfo));
+    return ROIX_OK;
 }
 
 roix_status roix_ctx_set_param(roix_ctx* ctx, const char* name, int64_t value) {

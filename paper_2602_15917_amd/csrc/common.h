@@ -154,6 +154,7 @@ __device__ __forceinline__ float ld_stream(const float* p) { return __builtin_no
 __device__ __forceinline__ uint16_t ld_stream(const uint16_t* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ int32_t ld_stream(const int32_t* p) { return __builtin_nontemporal_load(p); }
 typedef unsigned int v2u32_t __attribute__((ext_vector_type(2)));
+typedef unsigned int v3u32_t __attribute__((ext_vector_type(3)));
 __device__ __forceinline__ void st_stream(uint2* p, uint2 v) {
     v2u32_t t;
     t.x = v.x;
@@ -215,6 +216,8 @@ enum Stage {
     ST_EMIT_ROWS,
     ST_VOXEL_OUT,
     ST_FINALIZE,
+    ST_DECODE_INDEX,
+    ST_DECODE,
     ST_COUNT
 };
 
@@ -283,6 +286,11 @@ hipError_t launch_scan_u32_base(const LaunchCtx& lc, const uint32_t* in, uint32_
                                 uint32_t* base, uint32_t* lo_out, uint32_t* out_end, uint64_t* tmp,
                                 DevState* cap_S = nullptr, uint64_t cap = 0, int cap_err = 0);
 hipError_t launch_union(const LaunchCtx& lc, const Geom& g, const Layout& L, int conn);
+// the reverse process into out (N float32); desc: 2 * ny * nz uint4 of scratch
+hipError_t launch_decode(const LaunchCtx& lc, const roix_row* rows, uint64_t rows_cap, const void* stream,
+                         uint64_t stream_cap, const float* outl, uint64_t outl_cap, const roix_quant_info* qi,
+                         const roix_extract_info* ei, const Geom& g, float background, float* out, DevState* S,
+                         uint4* desc, roix_decode_info* dinfo);
 hipError_t launch_flatten(const LaunchCtx& lc, const Layout& L);
 hipError_t launch_comp_stats(const LaunchCtx& lc, const Geom& g, const Layout& L, roix_component* comps);
 hipError_t launch_keep(const LaunchCtx& lc, const Layout& L, roix_component* comps, const roix_criterion* crit);

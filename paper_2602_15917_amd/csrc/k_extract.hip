@@ -162,7 +162,6 @@ __device__ __forceinline__ void load_quad(const float* in, uint64_t v, float (&x
     x[2] = __uint_as_float(q.z);
     x[3] = __uint_as_float(q.w);
 }
-typedef unsigned int v3u32_t __attribute__((ext_vector_type(3)));
 // Elements a whole-quad load at voxel v reads, counted from v: a quad is
 // loaded whole only when v + quad_reach <= the voxel count.
 template <typename T>

@@ -135,11 +135,12 @@ def load():
     lib.roix_volume_abort.argtypes = [vp, i64]
     lib.roix_wait.argtypes = [vp, i64, i64, P(ReqResult)]
     lib.roix_server_stats.argtypes = [vp, P(ServerStats)]
+    lib.roix_decode.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp, vp, Dims, ctypes.c_float, vp, vp, vp]
     for f in ("roix_ctx_create", "roix_ctx_destroy", "roix_bounds", "roix_quantize", "roix_segment",
               "roix_extract", "roix_fused", "roix_ctx_set_timing", "roix_ctx_read_timing", "roix_fused_batch",
               "roix_ctx_set_param", "roix_ctx_get_param", "roix_server_create", "roix_server_destroy",
               "roix_volume_open", "roix_slab_submit", "roix_volume_close", "roix_volume_abort", "roix_wait",
-              "roix_server_stats"):
+              "roix_server_stats", "roix_decode"):
         getattr(lib, f).restype = ci
     _lib = lib
     return lib
@@ -204,6 +205,10 @@ def bounds(dims: Dims, dtype: int, crit: Criterion | None = None):
     return {"rows": r.value, "stream_bytes": s.value, "outliers": o.value, "components": k.value}
 
 
+def decode_info(dinfo: torch.Tensor) -> "DecodeInfo":
+    return _info(dinfo, DecodeInfo)
+
+
 def stage_names():
     lib = load()
     return [lib.roix_stage_name(i).decode() for i in range(lib.roix_stage_count())]
@@ -245,6 +250,11 @@ class Outputs:
             "outliers": self.outliers[:no].cpu().numpy(),
             "comps": self.comps[: nc * COMP_BYTES].cpu().numpy(),
         }
+
+
+class DecodeInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("pad", ctypes.c_int32), ("n_rows", ctypes.c_uint64),
+                ("n_codes", ctypes.c_uint64), ("n_outliers", ctypes.c_uint64)]
 
 
 class Context:
@@ -291,6 +301,23 @@ class Context:
         return v.value
 
     # ----------------------------------------------------------- calls
+    def decode(self, out: Outputs, dims: Dims, background: float = 0.0, dst: torch.Tensor | None = None,
+               dinfo: torch.Tensor | None = None, stream=None):
+        """Enqueue the reverse process of the extraction held in `out` (its
+        device row table, stream, outliers and infos).  Returns (volume, dinfo)
+        device tensors; read dinfo with decode_info() after a sync."""
+        dev = out.rows.device
+        if dst is None:
+            dst = torch.empty((dims.nz, dims.ny, dims.nx), dtype=torch.float32, device=dev)
+        if dinfo is None:
+            dinfo = torch.zeros(ctypes.sizeof(DecodeInfo), dtype=torch.uint8, device=dev)
+        rows_cap, stream_cap, outl_cap, _ = out.caps
+        st = load().roix_decode(self.h, out.rows.data_ptr(), rows_cap, out.stream.data_ptr(), stream_cap,
+                                out.outliers.data_ptr(), outl_cap, out.qinfo.data_ptr(), out.einfo.data_ptr(),
+                                dims, float(background), dst.data_ptr(), dinfo.data_ptr(), _stream(stream))
+        _check(st, "roix_decode")
+        return dst, dinfo
+
     def fused(self, vol: torch.Tensor, eb_mode: str, eb_value: float, crit: Criterion, out: Outputs,
               stream=None):
         """Enqueue the fused path; returns after launching (sync, then out.collect())."""
