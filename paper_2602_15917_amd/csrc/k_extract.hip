@@ -1012,11 +1012,46 @@ __global__ __launch_bounds__(kBlock) void k_emit_codes_general(const T* __restri
         emit_codes_general<T, 4>(in, nx, L, o);
 }
 
+// Outlier values: a span of up to 1024 voxels is one round of 16 loads per
+// lane; the test recomputes the quantiser and the values are stored in order
+// of x from the span's outlier offset.
+constexpr int kOutlU = 16;  // loads per lane and round
+constexpr uint32_t kOutlRound = (uint32_t)kWave * kOutlU;
+
+template <typename T>
+__device__ __forceinline__ void outl_load(const T* __restrict__ src, uint32_t len, uint32_t j0, float (&xv)[kOutlU]) {
+    const int lane = threadIdx.x % kWave;
+#pragma unroll
+    for (int u = 0; u < kOutlU; ++u) {
+        const uint32_t jj = j0 + u * kWave + lane;
+        xv[u] = (float)src[jj < len ? jj : 0u];
+    }
+}
+
+__device__ __forceinline__ void outl_store(const float (&xv)[kOutlU], uint32_t len, uint32_t j0, float r, float w,
+                                           float eb32, unsigned long long& k, const EmitOut& o, bool& trunc) {
+    const int lane = threadIdx.x % kWave;
+#pragma unroll
+    for (int u = 0; u < kOutlU; ++u) {
+        const uint32_t jj = j0 + u * kWave + lane;
+        const float x = xv[u];
+        const bool isout = jj < len && outlier(x, qcode(x, r), w, eb32);
+        const uint64_t mo = __ballot(isout);
+        if (isout) {
+            const unsigned long long at = k + (unsigned long long)__popcll(mo & ((1ull << lane) - 1ull));
+            if (at < o.outl_cap)
+                o.outl[at] = x;
+            else
+                trunc = true;
+        }
+        k += (unsigned long long)__popcll(mo);
+    }
+}
+
 // After the scan of the per-row outlier counts.  Each wave takes 64 spans,
 // one per lane: the lane writes its span's row table entry (coalesced), then
-// the wave takes the spans that have outliers (a ballot, no global queue)
-// one at a time, reads each once more and stores its outlier values in order
-// at the span's outlier offset.
+// the wave walks the spans that have outliers (a ballot), the first round of
+// the next one in flight while the current one is tested.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_emit_rows(const T* __restrict__ in, int64_t nx, Layout L, int64_t ny,
                                                       int64_t nrows, EmitOut o) {
@@ -1032,14 +1067,15 @@ __global__ __launch_bounds__(kBlock) void k_emit_rows(const T* __restrict__ in, 
     for (uint64_t jb = (uint64_t)wave * kWave; jb < n_rows; jb += (uint64_t)nwaves * kWave) {
         const uint32_t j = (uint32_t)jb + (uint32_t)lane;
         const bool valid = j < n_rows;
-        uint32_t rid = 0, xs = 0, xe = 0;
+        uint32_t rid = 0, xs = 0, len = 0;
         uint64_t ooff = 0, oend = 0;
         if (valid) {
             rid = L.nz_rows[j];
             ooff = L.row_outl[rid];
             oend = (int64_t)rid + 1 < nrows ? L.row_outl[rid + 1] : total;
             xs = L.row_xs[rid];
-            xe = L.row_xe[rid];
+            const uint32_t xe = L.row_xe[rid];
+            len = xe - xs;
             if (j < o.rows_cap) {
                 roix_row e;
                 e.z = rid / (uint32_t)ny;
@@ -1054,38 +1090,45 @@ __global__ __launch_bounds__(kBlock) void k_emit_rows(const T* __restrict__ in, 
             }
         }
         uint64_t m = __ballot(valid && oend != ooff);
-        while (m) {  // uniform: the spans of this group that have outliers
+        if (!m) continue;  // uniform
+        auto src_of = [&](int l) {
+            return in + (uint64_t)uni(__builtin_amdgcn_readlane(rid, l)) * (uint64_t)nx +
+                   uni(__builtin_amdgcn_readlane(xs, l));
+        };
+        auto len_of = [&](int l) { return uni(__builtin_amdgcn_readlane(len, l)); };
+        // one span: its first round is in xv; longer spans loop (rare)
+        auto test = [&](int l, const float (&xv)[kOutlU]) {
+            const uint32_t lt = len_of(l);
+            unsigned long long k = readlane64(ooff, l);
+            outl_store(xv, lt, 0, r, w, eb32, k, o, trunc);
+            for (uint32_t j0 = kOutlRound; j0 < lt; j0 += kOutlRound) {
+                float xc[kOutlU];
+                outl_load<T>(src_of(l), lt, j0, xc);
+                outl_store(xc, lt, j0, r, w, eb32, k, o, trunc);
+            }
+        };
+        // ping-pong over the spans with outliers; past the last one the
+        // loads repeat it (harmless), so every load is unconditional
+        auto pop = [&](int prev) {
+            if (!m) return prev;
             const int l = __ffsll((unsigned long long)m) - 1;
             m &= m - 1;
-            const uint32_t srid = uni(__builtin_amdgcn_readlane(rid, l));
-            const uint32_t sxs = uni(__builtin_amdgcn_readlane(xs, l));
-            const uint32_t len = uni(__builtin_amdgcn_readlane(xe, l)) - sxs;
-            unsigned long long k = readlane64(ooff, l);
-            const T* src = in + (uint64_t)srid * (uint64_t)nx + sxs;
-            constexpr int U = 8;
-            for (uint32_t j0 = 0; j0 < len; j0 += kWave * U) {
-                float xv[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const uint32_t jj = j0 + u * kWave + lane;
-                    xv[u] = jj < len ? (float)src[jj] : 0.0f;
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const uint32_t jj = j0 + u * kWave + lane;
-                    const float x = xv[u];
-                    const bool isout = jj < len && outlier(x, qcode(x, r), w, eb32);
-                    const uint64_t mo = __ballot(isout);
-                    if (isout) {
-                        const unsigned long long at = k + (unsigned long long)__popcll(mo & ((1ull << lane) - 1ull));
-                        if (at < o.outl_cap)
-                            o.outl[at] = x;
-                        else
-                            trunc = true;
-                    }
-                    k += (unsigned long long)__popcll(mo);
-                }
-            }
+            return l;
+        };
+        float xa[kOutlU], xb[kOutlU];
+        int la = pop(0);
+        outl_load<T>(src_of(la), len_of(la), 0, xa);
+        while (true) {
+            const bool more_b = m != 0;
+            const int lb = pop(la);
+            outl_load<T>(src_of(lb), len_of(lb), 0, xb);
+            test(la, xa);
+            if (!more_b) break;
+            const bool more_a = m != 0;
+            la = pop(lb);
+            outl_load<T>(src_of(la), len_of(la), 0, xa);
+            test(lb, xb);
+            if (!more_a) break;
         }
     }
     if (trunc) atomicOr(&S->trunc, 1);
@@ -1124,12 +1167,13 @@ hipError_t launch_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, cons
     hipError_t e = launch_scan_u64(lc, L.row_outl, L.row_outl, g.nrows, &L.S->n_outliers, L.scan_tmp);
     if (e != hipSuccess) return e;
     timer_begin(lc.timer, ST_EMIT_ROWS, lc.stream);
-    if (dt == ROIX_F32)
+    if (dt == ROIX_F32) {
         hipLaunchKernelGGL(k_emit_rows<float>, grid_rows_t, block, 0, lc.stream, (const float*)in, g.nx, L, g.ny,
                            g.nrows, o);
-    else
+    } else {
         hipLaunchKernelGGL(k_emit_rows<uint16_t>, grid_rows_t, block, 0, lc.stream, (const uint16_t*)in, g.nx, L, g.ny,
                            g.nrows, o);
+    }
     timer_end(lc.timer, ST_EMIT_ROWS, lc.stream);
     return hipGetLastError();
 }
