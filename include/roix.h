@@ -309,6 +309,8 @@ roix_status roix_fused_batch(roix_ctx* ctx, int32_t n, const roix_volume_desc* v
 /* Launch parameters of a context (the autotuner's knobs):
  *   "grid_stream"    workgroups of the grid-stride streaming kernels
  *   "grid_read"      workgroups of the read-only range kernel
+ *   "grid_emit"      workgroups of the code-emit kernels
+ *   "grid_mask"      workgroups of the mask-word and run kernels
  *   "seg_grid"       workgroups of the component-labelling kernels
  *   "stats_grid"     workgroups of the component-statistics kernel
  *   "seg_runs"       runs labelled together in one workgroup's local memory

@@ -142,6 +142,8 @@ LaunchCtx roix::lctx(roix_ctx* c, void* stream) {
     lc.timer = c->timer.on ? &c->timer : nullptr;
     lc.grid_stream = c->grid_stream;
     lc.grid_read = c->grid_read;
+    lc.grid_emit = c->grid_emit;
+    lc.grid_mask = c->grid_mask;
     lc.seg_grid = c->seg_grid;
     lc.seg_runs = c->seg_runs;
     lc.stats_grid = c->stats_grid;
@@ -330,6 +332,10 @@ roix_status roix_ctx_create(int device, size_t scratch_bytes, roix_ctx** out) {
     if (c->cus <= 0) c->cus = 256;
     c->grid_stream = c->cus * 8;
     c->grid_read = c->cus * 4;
+    // the emit kernels run best with every wave resident at once (no
+    // second, ragged round); the mask-word kernels with many more
+    c->grid_emit = c->cus * 4;
+    c->grid_mask = c->cus * 32;
     c->seg_grid = c->cus * 2;
     c->stats_grid = c->cus;
     if (const char* s = getenv("ROIX_GRID_STREAM")) {
@@ -501,6 +507,8 @@ roix_status roix_ctx_set_param(roix_ctx* ctx, const char* name, int64_t value) {
     const bool pos = value >= 1 && value <= (1 << 22);
     if (strcmp(name, "grid_stream") == 0 && pos) ctx->grid_stream = (int)value;
     else if (strcmp(name, "grid_read") == 0 && pos) ctx->grid_read = (int)value;
+    else if (strcmp(name, "grid_emit") == 0 && pos) ctx->grid_emit = (int)value;
+    else if (strcmp(name, "grid_mask") == 0 && pos) ctx->grid_mask = (int)value;
     else if (strcmp(name, "seg_grid") == 0 && pos) ctx->seg_grid = (int)value;
     else if (strcmp(name, "stats_grid") == 0 && pos) ctx->stats_grid = (int)value;
     else if (strcmp(name, "seg_runs") == 0 && value >= 0 && value <= 16384 && value % 256 == 0)
@@ -517,6 +525,8 @@ roix_status roix_ctx_get_param(roix_ctx* ctx, const char* name, int64_t* value) 
     if (!ctx || !name || !value) return ROIX_EINVAL;
     if (strcmp(name, "grid_stream") == 0) *value = ctx->grid_stream;
     else if (strcmp(name, "grid_read") == 0) *value = ctx->grid_read;
+    else if (strcmp(name, "grid_emit") == 0) *value = ctx->grid_emit;
+    else if (strcmp(name, "grid_mask") == 0) *value = ctx->grid_mask;
     else if (strcmp(name, "seg_grid") == 0) *value = ctx->seg_grid;
     else if (strcmp(name, "stats_grid") == 0) *value = ctx->stats_grid;
     else if (strcmp(name, "seg_runs") == 0) *value = ctx->seg_runs;
@@ -606,8 +616,16 @@ roix_status roix_fused_batch(roix_ctx* ctx, int32_t n, const roix_volume_desc* v
     if (!ctx->batch_graph) return batch_enqueue(ctx, n, vols, gs, S, slot_bytes, stream);
     // the graph is specific to the descriptors (buffer addresses are baked
     // into its kernel arguments): reuse it while they are the same
-    const int64_t params[8] = {S,           ctx->grid_stream, ctx->grid_read,      ctx->seg_grid,
-                               ctx->seg_runs, ctx->stats_grid,  (int64_t)slot_bytes, (int64_t)ctx->p16_min};
+    const int64_t params[10] = {S,
+                                ctx->grid_stream,
+                                ctx->grid_read,
+                                ctx->grid_emit,
+                                ctx->grid_mask,
+                                ctx->seg_grid,
+                                ctx->seg_runs,
+                                ctx->stats_grid,
+                                (int64_t)slot_bytes,
+                                (int64_t)ctx->p16_min};
     std::vector<uint8_t> key(sizeof(roix_volume_desc) * (size_t)n + sizeof params);
     memcpy(key.data(), vols, sizeof(roix_volume_desc) * (size_t)n);
     memcpy(key.data() + sizeof(roix_volume_desc) * (size_t)n, params, sizeof params);

@@ -230,6 +230,8 @@ struct LaunchCtx {
     Timer* timer;  // may be null
     int grid_stream;  // workgroups of the grid-stride streaming kernels
     int grid_read;    // workgroups of the read-only streaming kernel (range)
+    int grid_emit;    // workgroups of the code-emit kernels
+    int grid_mask;    // workgroups of the mask-word and run kernels
     int seg_grid;     // workgroups of the segment labelling kernels
     int seg_runs;     // runs per segment (0: spread the runs over seg_grid)
     int stats_grid;   // workgroups of the component statistics kernel

@@ -1146,7 +1146,7 @@ hipError_t launch_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, cons
     o.nvox = g.N;
     const dim3 block(kBlock);
     const dim3 grid_rows_t(grid_rows(g.nrows, kBlock, lc.grid_stream));
-    const dim3 grid_waves(lc.grid_stream);
+    const dim3 grid_waves(lc.grid_emit);
     timer_begin(lc.timer, ST_EMIT, lc.stream);
     hipLaunchKernelGGL(k_emit_index, grid_rows_t, block, 0, lc.stream, L, g.nx, g.nrows);
     // the lean kernel queues the chunks it leaves to the general kernel

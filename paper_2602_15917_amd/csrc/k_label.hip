@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kBlock) void k_mask_runs(const uint8_t* __restrict_
 hipError_t launch_mask_runs(const LaunchCtx& lc, const Geom& g, const Layout& L) {
     timer_begin(lc.timer, ST_MASK_RUNS, lc.stream);
     const int64_t R = g.W <= kWave ? kWave / g.W : 1;
-    int grid = grid_for((g.nrows + R - 1) / R, kBlock / kWave, lc.grid_stream);
+    int grid = grid_for((g.nrows + R - 1) / R, kBlock / kWave, lc.grid_mask);
     hipLaunchKernelGGL(k_mask_runs, dim3(grid), dim3(kBlock), 0, lc.stream, (const uint8_t*)L.proxy, g.nx, g.nrows,
                        g.W, L.S, L.maskbits, L.row_nruns);
     timer_end(lc.timer, ST_MASK_RUNS, lc.stream);
@@ -417,7 +417,7 @@ hipError_t launch_runs_write(const LaunchCtx& lc, const Geom& g, const Layout& L
     const uint32_t* off = L.run_off + r0;
     if (g.W <= kWave) {
         const int64_t R = kWave / g.W;
-        hipLaunchKernelGGL(k_runs_write_lanes, dim3(grid_for((nr + R - 1) / R, kBlock / kWave, lc.grid_stream)),
+        hipLaunchKernelGGL(k_runs_write_lanes, dim3(grid_for((nr + R - 1) / R, kBlock / kWave, lc.grid_mask)),
                            dim3(kBlock), 0, lc.stream, mb, g.nx, nr, g.W, off, L.run_xs, L.run_xe, L.parent,
                            L.run_row, r0, (const DevState*)L.S);
     } else {
