@@ -40,7 +40,8 @@ class FusedInfo(ctypes.Structure):
                 ("n_kept_voxels", ctypes.c_uint64), ("bbox", ctypes.c_uint32 * 6),
                 ("ext_status", ctypes.c_int32), ("pad", ctypes.c_int32), ("n_rows", ctypes.c_uint64),
                 ("n_codes", ctypes.c_uint64), ("n_outliers", ctypes.c_uint64), ("stream_bytes", ctypes.c_uint64),
-                ("stage_seconds", ctypes.c_double * 8)]
+                ("stage_seconds", ctypes.c_double * 8), ("thresholds", ctypes.c_int32 * 3),
+                ("n_classes", ctypes.c_int32)]
 
 
 COMP_DTYPE = np.dtype([("label", "<u8"), ("size", "<u8"), ("x0", "<u4"), ("x1", "<u4"), ("y0", "<u4"),
@@ -77,6 +78,8 @@ def _load():
         lib.oracle_histogram_codes.restype = None
         lib.oracle_otsu.argtypes = [vp, vp]
         lib.oracle_otsu.restype = ctypes.c_uint32
+        lib.oracle_multi_otsu.argtypes = [vp, ci, vp]
+        lib.oracle_multi_otsu.restype = ctypes.c_uint32
         lib.oracle_q_thr_otsu.argtypes = [ctypes.c_int32, ctypes.POINTER(Params)]
         lib.oracle_q_thr_otsu.restype = ctypes.c_int32
         lib.oracle_q_thr_fixed.argtypes = [dbl, ctypes.POINTER(Params)]
@@ -154,6 +157,18 @@ def otsu(hist):
     t = np.zeros(1, np.int32)
     flags = _load().oracle_otsu(_p(h), _p(t))
     return int(t[0]), int(flags)
+
+
+def multi_otsu(hist, classes):
+    """Multi-level Otsu thresholds (3 or 4 classes; Liao et al. 2001, the
+    method Sec. 4.1.3 names) and flags."""
+    h = np.ascontiguousarray(hist, dtype=np.uint64)
+    t = np.zeros(3, np.int32)
+    flags = _load().oracle_multi_otsu(_p(h), int(classes), _p(t))
+    return tuple(int(v) for v in t[: classes - 1]), int(flags)
+
+
+THR_MODES = {"otsu": 0, "fixed": 1, "multi3": 2, "multi4": 3}
 
 
 def q_thr_otsu(t_star, p):
@@ -236,7 +251,7 @@ def fused(vol, eb_mode, eb_value, thr="otsu", fixed_value=0.0, connectivity=26, 
     o = np.zeros(max(min(outliers_cap, N), 1), np.float32)
     info = FusedInfo()
     lib = _load()
-    args = (_p(vol), _dt(vol), nx, ny, nz, 0 if eb_mode == "abs" else 1, eb_value, 0 if thr == "otsu" else 1,
+    args = (_p(vol), _dt(vol), nx, ny, nz, 0 if eb_mode == "abs" else 1, eb_value, THR_MODES[thr],
             fixed_value, connectivity, 1 if keep == "largest" else 0, min_size)
     st = lib.oracle_fused(*args, _p(comps), min(comps_cap, len(comps)), _p(rows_a), rows_cap, _p(s),
                           stream_cap_bytes, _p(o), len(o), ctypes.byref(info))

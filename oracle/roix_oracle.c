@@ -21,8 +21,11 @@
  *                takes the place of the paper's sequential grouping)
  *   histogram    256 equal bins over the code range: the 8-bit normalisation
  *                of Sec. 4.1.2 applied to codes
- *   threshold    two-class Otsu (1979) on those bins (Sec. 4.1.3), or a
- *                fixed threshold; pixels above the threshold are object
+ *   threshold    two-class Otsu (1979) on those bins (Sec. 4.1.3), the
+ *                multi-level Otsu of Liao, Chen & Chung (2001) that Sec.
+ *                4.1.3 names (3 or 4 classes; object = above the lowest
+ *                threshold), or a fixed threshold; pixels above the
+ *                threshold are object
  *   binarise     mask M = 1 for object voxels (Sec. 4.1.4, Eq. 2)
  *   label        connected components of the mask in 3-D (6 or 26
  *                neighbours): the volumetric form of the outer-contour
@@ -52,7 +55,7 @@
 enum { OR_OK = 0, OR_EINVAL = 1, OR_ERANGE = 2, OR_ENOMEM = 3, OR_ETRUNC = 4 };
 enum { OR_F32 = 0, OR_U16 = 1 };
 enum { OR_EB_ABS = 0, OR_EB_REL = 1 };
-enum { OR_THR_OTSU = 0, OR_THR_FIXED = 1 };
+enum { OR_THR_OTSU = 0, OR_THR_FIXED = 1, OR_THR_MULTI3 = 2, OR_THR_MULTI4 = 3 };
 enum { OR_KEEP_MIN_SIZE = 0, OR_KEEP_LARGEST = 1 };
 enum { OR_FLAG_DEGENERATE = 1u, OR_FLAG_EMPTY_ROI = 2u, OR_FLAG_FIXED = 4u };
 
@@ -86,6 +89,8 @@ typedef struct {
     int32_t ext_status, pad;
     uint64_t n_rows, n_codes, n_outliers, stream_bytes;
     double stage_seconds[8]; /* range+resolve, histogram, threshold+mask, label, keep, rows, stream, total */
+    int32_t thresholds[3];   /* multi-level Otsu: t1 < t2 (< t3), -1 unused; two-class Otsu: t*; else -1 */
+    int32_t n_classes;
 } or_fused_info;
 
 static double now_s(void) {
@@ -230,6 +235,70 @@ uint32_t oracle_otsu(const uint64_t hist[256], int32_t* t_star) {
         }
     }
     *t_star = t_best;
+    return best < 0.0 ? OR_FLAG_DEGENERATE : 0u;
+}
+
+/* Multi-level Otsu (Liao, Chen & Chung 2001), K = 3 or 4 classes: the
+ * thresholds t1 < .. < t_{K-1} in 0..254 maximising the between-class
+ * variance.  For a fixed histogram that variance is (1/NT) sum_k S_k^2 / W_k
+ * minus a constant (W_k voxels and S_k the bin sum of class k), so the
+ * search maximises sum_k S_k^2 / W_k, evaluated in binary64 in class order:
+ * ((S_0^2 / W_0 + S_1^2 / W_1) + S_2^2 / W_2) (+ S_3^2 / W_3).  Class k
+ * holds bins t_k + 1 .. t_{k+1} (t_0 = -1, t_K = 255).  Tuples with an empty
+ * class are skipped and the first maximum in lexicographic order of the
+ * tuple wins.  t[] receives the thresholds (-1 for an unused slot); with no
+ * valid tuple every threshold is 255 (empty mask).  Returns flags. */
+static double class_term(uint64_t W, uint64_t S) {
+    double s = (double)S;
+    return (s * s) / (double)W;
+}
+
+uint32_t oracle_multi_otsu(const uint64_t hist[256], int classes, int32_t t[3]) {
+    uint64_t P[257], Q[257]; /* P[i], Q[i]: voxels and bin sum of bins 0 .. i-1 */
+    P[0] = Q[0] = 0;
+    for (int i = 0; i < 256; ++i) {
+        P[i + 1] = P[i] + hist[i];
+        Q[i + 1] = Q[i] + (uint64_t)i * hist[i];
+    }
+    double best = -1.0;
+    int32_t b1 = 255, b2 = 255, b3 = 255;
+    if (classes == 3) {
+        for (int t1 = 0; t1 < 254; ++t1)
+            for (int t2 = t1 + 1; t2 < 255; ++t2) {
+                uint64_t W0 = P[t1 + 1], W1 = P[t2 + 1] - P[t1 + 1], W2 = P[256] - P[t2 + 1];
+                if (!W0 || !W1 || !W2) continue;
+                uint64_t S0 = Q[t1 + 1], S1 = Q[t2 + 1] - Q[t1 + 1], S2 = Q[256] - Q[t2 + 1];
+                double v = (class_term(W0, S0) + class_term(W1, S1)) + class_term(W2, S2);
+                if (v > best) {
+                    best = v;
+                    b1 = t1;
+                    b2 = t2;
+                }
+            }
+        t[0] = b1;
+        t[1] = b2;
+        t[2] = -1;
+    } else {
+        for (int t1 = 0; t1 < 253; ++t1)
+            for (int t2 = t1 + 1; t2 < 254; ++t2)
+                for (int t3 = t2 + 1; t3 < 255; ++t3) {
+                    uint64_t W0 = P[t1 + 1], W1 = P[t2 + 1] - P[t1 + 1], W2 = P[t3 + 1] - P[t2 + 1],
+                             W3 = P[256] - P[t3 + 1];
+                    if (!W0 || !W1 || !W2 || !W3) continue;
+                    uint64_t S0 = Q[t1 + 1], S1 = Q[t2 + 1] - Q[t1 + 1], S2 = Q[t3 + 1] - Q[t2 + 1],
+                             S3 = Q[256] - Q[t3 + 1];
+                    double v = ((class_term(W0, S0) + class_term(W1, S1)) + class_term(W2, S2)) + class_term(W3, S3);
+                    if (v > best) {
+                        best = v;
+                        b1 = t1;
+                        b2 = t2;
+                        b3 = t3;
+                    }
+                }
+        t[0] = b1;
+        t[1] = b2;
+        t[2] = b3;
+    }
     return best < 0.0 ? OR_FLAG_DEGENERATE : 0u;
 }
 
@@ -524,7 +593,7 @@ int oracle_fused(const void* in, int dtype, int64_t nx, int64_t ny, int64_t nz, 
     info->otsu_bin = -1;
     double t0 = now_s(), t1;
     if (!in || nx <= 0 || ny <= 0 || nz <= 0 || (dtype != OR_F32 && dtype != OR_U16) ||
-        (conn != 6 && conn != 26) || min_size < 1)
+        (conn != 6 && conn != 26) || min_size < 1 || thr_mode < OR_THR_OTSU || thr_mode > OR_THR_MULTI4)
         return info->q.status = info->seg_status = info->ext_status = OR_EINVAL;
     uint64_t N = (uint64_t)nx * (uint64_t)ny * (uint64_t)nz;
     float xmin, xmax;
@@ -538,8 +607,17 @@ int oracle_fused(const void* in, int dtype, int64_t nx, int64_t ny, int64_t nz, 
     for (uint64_t v = 0; v < N; ++v) info->hist[bin_of(code_of(voxel(in, dtype, v), p), p)]++;
     t1 = now_s(); info->stage_seconds[1] = t1 - t0; t0 = t1;
 
+    info->thresholds[0] = info->thresholds[1] = info->thresholds[2] = -1;
     if (thr_mode == OR_THR_OTSU) {
         info->flags |= oracle_otsu(info->hist, &info->otsu_bin);
+        info->q_thr = oracle_q_thr_otsu(info->otsu_bin, p);
+        info->thresholds[0] = info->otsu_bin;
+        info->n_classes = 2;
+    } else if (thr_mode == OR_THR_MULTI3 || thr_mode == OR_THR_MULTI4) {
+        /* object = every class above the lowest threshold */
+        info->n_classes = thr_mode == OR_THR_MULTI3 ? 3 : 4;
+        info->flags |= oracle_multi_otsu(info->hist, info->n_classes, info->thresholds);
+        info->otsu_bin = info->thresholds[0];
         info->q_thr = oracle_q_thr_otsu(info->otsu_bin, p);
     } else {
         info->flags |= OR_FLAG_FIXED;

@@ -233,6 +233,84 @@ def test_otsu_closed_forms():
     assert oracle.otsu(np.zeros(256, np.uint64)) == (255, oracle.FLAG_DEGENERATE)
 
 
+def _multi_exact(h, K):
+    """Multi-level Otsu by exact rationals: every partition of the non-empty
+    bins into K contiguous non-empty classes, scored by sum_k S_k^2 / W_k
+    (the between-class variance up to a positive factor and a constant).
+    Returns the best score, the runner-up score and the lexicographically
+    smallest threshold tuple of the best partition (a cut after non-empty bin
+    p is the threshold p, the smallest bin index that realises it)."""
+    from itertools import combinations
+    pos = [i for i in range(256) if h[i]]
+    scored = []
+    for cuts in combinations(range(len(pos) - 1), K - 1):
+        bounds = [-1] + list(cuts) + [len(pos) - 1]
+        score = Fraction(0)
+        for a, b in zip(bounds[:-1], bounds[1:]):
+            W = sum(int(h[pos[j]]) for j in range(a + 1, b + 1))
+            S = sum(pos[j] * int(h[pos[j]]) for j in range(a + 1, b + 1))
+            score += Fraction(S * S, W)
+        scored.append((score, tuple(pos[c] for c in cuts)))
+    scored.sort(key=lambda e: (-e[0], e[1]))
+    runner = scored[1][0] if len(scored) > 1 else None
+    return scored[0][0], runner, scored[0][1]
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_multi_otsu_exact_partitions(seed):
+    # the oracle's binary64 search against an exact search over partitions
+    rng = np.random.default_rng(9000 + seed)
+    K = 3 if seed % 2 == 0 else 4
+    m = int(rng.integers(K, 11))
+    h = np.zeros(256, np.uint64)
+    idx = np.sort(rng.choice(256, m, replace=False))
+    h[idx] = rng.integers(1, 10 ** (3 + seed % 6), m)
+    best, runner, tup = _multi_exact(h, K)
+    if runner is not None and best != runner:
+        assert float((best - runner) / best) > 1e-12  # no near-tie the rounding could flip
+    got, flags = oracle.multi_otsu(h, K)
+    assert flags == 0 and got == tup, (K, idx.tolist(), got, tup)
+
+
+def test_multi_otsu_closed_forms():
+    # exactly K non-empty bins: the only valid tuple cuts after each but the last
+    h = np.zeros(256, np.uint64)
+    h[[3, 90, 250]] = [5, 1, 2]
+    assert oracle.multi_otsu(h, 3) == ((3, 90), 0)
+    h[7] = 4
+    assert oracle.multi_otsu(h, 4) == ((3, 7, 90), 0)
+    # fewer non-empty bins than classes: no valid tuple, empty mask
+    h = np.zeros(256, np.uint64)
+    h[[10, 20]] = 6
+    assert oracle.multi_otsu(h, 3) == ((255, 255), oracle.FLAG_DEGENERATE)
+    assert oracle.multi_otsu(np.zeros(256, np.uint64), 4) == ((255, 255, 255), oracle.FLAG_DEGENERATE)
+    # two well-separated groups of bins per threshold: the thresholds fall in the gaps
+    h = np.zeros(256, np.uint64)
+    h[20:30] = 1000
+    h[120:130] = 1000
+    h[220:230] = 1000
+    (t1, t2), _ = oracle.multi_otsu(h, 3)
+    assert 29 <= t1 < 120 and 129 <= t2 < 220
+
+
+def test_multi_otsu_three_materials():
+    # background, matrix and inclusions of distinct intensities: three-class
+    # Otsu keeps everything above the background; four classes split no material
+    rng = np.random.default_rng(77)
+    vol = np.full((12, 24, 32), 0.1, np.float64) + rng.normal(0, 0.01, (12, 24, 32))
+    vol[2:10, 4:20, 6:26] = 0.5 + rng.normal(0, 0.01, (8, 16, 20))
+    vol[4:8, 8:14, 10:16] = 0.9 + rng.normal(0, 0.01, (4, 6, 6))
+    vol = vol.astype(np.float32)
+    fg = int(((vol > 0.3)).sum())
+    r = oracle.fused(vol, "abs", 1e-3, "multi3", 0.0, 6, "min_size", 1)
+    assert r["status"] == 0 and r["info"].n_classes == 3
+    assert r["info"].n_mask == fg
+    t = list(r["info"].thresholds)
+    assert t[0] < t[1] and t[2] == -1 and r["info"].otsu_bin == t[0]
+    r4 = oracle.fused(vol, "abs", 1e-3, "multi4", 0.0, 6, "min_size", 1)
+    assert r4["status"] == 0 and r4["info"].n_classes == 4 and r4["info"].thresholds[0] < r4["info"].thresholds[1] < r4["info"].thresholds[2]
+
+
 def test_threshold_mask_equivalence():
     # q >= q_thr  <=>  bin(q) > t*  for every code of the range (Otsu); q > q(T) for FIXED
     for K in (7, 255, 256, 1000, 65537):
