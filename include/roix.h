@@ -85,18 +85,25 @@ typedef struct {
 
 /* ROI criterion.  OTSU: two-class Otsu (1979) on the 256-bin histogram of
  * the codes (Sec. 4.1.3); the object class is the bins strictly above the
- * split.  FIXED: voxels whose code is above the code of `fixed_value`
- * (input units) are object.  Connectivity 6 or 26.  LARGEST keeps the
- * component with the most voxels (ties: smallest label); MIN_SIZE keeps
- * every component of at least `min_size` voxels. */
-typedef enum { ROIX_THR_OTSU = 0, ROIX_THR_FIXED = 1 } roix_thr_mode;
+ * split.  MULTI_OTSU: the multi-level Otsu of Liao, Chen & Chung (2001)
+ * that Sec. 4.1.3 names, with `classes` = 3 or 4 classes (0 means 3): the
+ * thresholds t1 < .. < t_{K-1} (bins 0..254, class k = bins t_k + 1 ..
+ * t_{k+1}) maximise sum_k S_k^2 / W_k (W_k voxels and S_k the bin sum of
+ * class k, the between-class variance up to a factor and a constant),
+ * evaluated in binary64 in class order; tuples with an empty class are
+ * skipped and the first maximum in lexicographic order wins; the object is
+ * every class above the lowest threshold.  FIXED: voxels whose code is
+ * above the code of `fixed_value` (input units) are object.  Connectivity 6
+ * or 26.  LARGEST keeps the component with the most voxels (ties: smallest
+ * label); MIN_SIZE keeps every component of at least `min_size` voxels. */
+typedef enum { ROIX_THR_OTSU = 0, ROIX_THR_FIXED = 1, ROIX_THR_MULTI_OTSU = 2 } roix_thr_mode;
 typedef enum { ROIX_KEEP_MIN_SIZE = 0, ROIX_KEEP_LARGEST = 1 } roix_keep_mode;
 typedef struct {
     int32_t thr;          /* roix_thr_mode */
     int32_t connectivity; /* 6 | 26 */
     double fixed_value;   /* FIXED only; finite */
     int32_t keep;         /* roix_keep_mode */
-    int32_t pad;
+    int32_t classes;      /* MULTI_OTSU only: 3 or 4 (0 = 3); otherwise ignored */
     int64_t min_size;     /* MIN_SIZE only; >= 1 */
 } roix_criterion;
 
@@ -124,8 +131,12 @@ typedef struct {
 #define ROIX_FLAG_FIXED_THRESHOLD 4u
 
 /* hist[t] counts voxels with floor(256 (q - qmin) / K) == t.  otsu_bin = t*
- * (-1 for FIXED); the mask is q >= q_thr.  bbox is the half-open box
- * [x0,x1) x [y0,y1) x [z0,z1) of the kept components (all 0 when none). */
+ * (the lowest threshold for MULTI_OTSU; -1 for FIXED); the mask is
+ * q >= q_thr.  thresholds: t* for OTSU (n_classes 2), t1 < t2 (< t3) for
+ * MULTI_OTSU (n_classes 3 or 4), -1 in unused slots and for FIXED
+ * (n_classes 0); with no valid split every threshold is 255.  bbox is the
+ * half-open box [x0,x1) x [y0,y1) x [z0,z1) of the kept components (all 0
+ * when none). */
 typedef struct {
     int32_t status;
     int32_t otsu_bin;
@@ -137,6 +148,8 @@ typedef struct {
     uint64_t n_kept;        /* kept components */
     uint64_t n_kept_voxels;
     uint32_t bbox[6];       /* x0, x1, y0, y1, z0, z1 */
+    int32_t thresholds[3];
+    int32_t n_classes;
 } roix_seg_info;
 
 /* One connected component, in ascending label order.  label = smallest

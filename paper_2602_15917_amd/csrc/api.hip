@@ -158,7 +158,8 @@ bool roix::eb_ok(roix_eb eb) {
 
 bool roix::crit_ok(const roix_criterion* c) {
     if (!c) return false;
-    if (c->thr != ROIX_THR_OTSU && c->thr != ROIX_THR_FIXED) return false;
+    if (c->thr != ROIX_THR_OTSU && c->thr != ROIX_THR_FIXED && c->thr != ROIX_THR_MULTI_OTSU) return false;
+    if (c->thr == ROIX_THR_MULTI_OTSU && c->classes != 0 && c->classes != 3 && c->classes != 4) return false;
     if (c->thr == ROIX_THR_FIXED && !(c->fixed_value >= -1.7976931348623157e308 && c->fixed_value <= 1.7976931348623157e308))
         return false;
     if (c->connectivity != 6 && c->connectivity != 26) return false;
@@ -248,7 +249,7 @@ roix_status roix::enqueue_fused(const LaunchCtx& lc, const Geom& g, Layout L, co
         ROIX_TRY(launch_resolve_dt(lc, L.S, dtype, eb, crit));
         ROIX_TRY(launch_quant_hist(lc, d_in, kind, g, L.S, L.proxy, fixed));
     }
-    ROIX_TRY(launch_otsu(lc, L.S, fixed));
+    ROIX_TRY(launch_threshold(lc, L.S, crit));
     ROIX_TRY(label_and_keep(lc, g, L, crit, out->d_comps, out->comps_cap));
     ROIX_TRY(launch_spans_from_runs(lc, g, L));
     ROIX_TRY(spans_and_emit(lc, g, L, d_in, dtype, out));
@@ -442,7 +443,7 @@ roix_status roix_segment(roix_ctx* ctx, const int32_t* d_codes, roix_dims dims, 
     ROIX_TRY(launch_init(lc, L.S));
     ROIX_TRY(launch_seg_init(lc, L.S, d_qinfo, crit));
     ROIX_TRY(launch_quant_hist(lc, d_codes, 2, g, L.S, L.proxy, fixed));
-    ROIX_TRY(launch_otsu(lc, L.S, fixed));
+    ROIX_TRY(launch_threshold(lc, L.S, crit));
     ROIX_TRY(label_and_keep(lc, g, L, crit, d_comps, comps_cap));
     ROIX_TRY(launch_voxel_out(lc, g, L, d_comps, d_keep, d_labels));
     ROIX_TRY(launch_finalize(lc, L.S, nullptr, d_sinfo, nullptr, false));

@@ -17,6 +17,10 @@ constexpr int kScanBlocks = 1024;    // fixed block count of the device-sized sc
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kQrFine = 1 << 15;  // code classes (q mod 2^15) of the fused 16-bit proxy pass
 constexpr int kQrBlocks = 256;    // workgroups of that pass (one LDS class table each)
+constexpr int kMoPairBlocks = 256; // multi-level Otsu search: workgroups over the pairs (t1, t2)
+constexpr int kMoChunks = 8;       // K = 4: t3 ranges of kMoChunk thresholds per pair
+constexpr int kMoChunk = 32;
+constexpr int kMoParts = kMoPairBlocks * kMoChunks;  // partial results of the search
 constexpr int kEmitSlice = 256;  // codes per emit slice: 4 consecutive codes per lane
 constexpr int kEmitSlices = 4;   // slices per emit step (16-byte loads in flight per lane)
 constexpr int kEmitSteps = 4;
@@ -62,6 +66,12 @@ struct DevState {
     // sequence's quantiser stages
     int32_t saved_status;
     float serve_r, serve_rt;
+    // threshold search: the thresholds and class count, and the multi-level
+    // Otsu search's best (score, tuple rank) per workgroup
+    int32_t thr_t[3];
+    int32_t n_classes;
+    double mo_val[kMoParts];
+    unsigned long long mo_rank[kMoParts];
 };
 
 // Per-call view of the scratch arena.
@@ -258,6 +268,9 @@ hipError_t launch_quant_hist(const LaunchCtx& lc, const void* in, int src_kind, 
 hipError_t launch_quant_range16(const LaunchCtx& lc, const float* in, const Geom& g, const Layout& L);
 hipError_t launch_resolve16(const LaunchCtx& lc, const Layout& L, roix_eb eb, const roix_criterion* crit);
 hipError_t launch_otsu(const LaunchCtx& lc, DevState* S, bool fixed);
+// the threshold of a criterion: Otsu, multi-level Otsu or fixed (whose q_thr
+// the resolve step has set)
+hipError_t launch_threshold(const LaunchCtx& lc, DevState* S, const roix_criterion* crit);
 
 hipError_t launch_mask_runs(const LaunchCtx& lc, const Geom& g, const Layout& L);
 // streamed volumes (FIXED threshold, ABS bound): mask parameters at open,

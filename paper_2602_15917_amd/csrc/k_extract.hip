@@ -1215,6 +1215,8 @@ __global__ void k_finalize(const DevState* S, roix_quant_info* qi, roix_seg_info
             si->n_kept_voxels = seg_ok ? S->n_kept_voxels : 0ull;
             const bool any = seg_ok && S->n_kept != 0;
             for (int k = 0; k < 6; ++k) si->bbox[k] = any ? S->bbox[k] : 0u;
+            for (int k = 0; k < 3; ++k) si->thresholds[k] = qbad ? -1 : S->thr_t[k];
+            si->n_classes = qbad ? 0 : S->n_classes;
         }
     }
     if (ei && t == 0) {

@@ -91,6 +91,8 @@ __global__ __launch_bounds__(kBlock) void k_init(DevState* S, double eb_abs) {
             S->esc = 0u;
             S->K = 0;
             S->otsu_bin = -1;
+            S->thr_t[0] = S->thr_t[1] = S->thr_t[2] = -1;
+            S->n_classes = 0;
             S->q_thr = 0;
             S->proxy_thr = 0;
             S->flags = 0u;
@@ -1018,6 +1020,8 @@ __global__ __launch_bounds__(256) void k_otsu(DevState* S, int fixed) {
             ts = sh_t[0];
         S->otsu_bin = ts;
         S->proxy_thr = ts;
+        S->thr_t[0] = ts;
+        S->n_classes = 2;
         long long c = ((long long)(ts + 1) * S->K + 255) / 256;
         S->q_thr = (int32_t)((long long)S->qmin + c);
     }
@@ -1026,6 +1030,159 @@ __global__ __launch_bounds__(256) void k_otsu(DevState* S, int fixed) {
 hipError_t launch_otsu(const LaunchCtx& lc, DevState* S, bool fixed) {
     timer_begin(lc.timer, ST_OTSU, lc.stream);
     hipLaunchKernelGGL(k_otsu, dim3(1), dim3(256), 0, lc.stream, S, fixed ? 1 : 0);
+    timer_end(lc.timer, ST_OTSU, lc.stream);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ multi-level Otsu
+
+// Multi-level Otsu (Liao, Chen & Chung 2001) with K = 3 or 4 classes over
+// the 256 bins: the thresholds t1 < .. < t_{K-1} in 0..254 (class k = bins
+// t_k + 1 .. t_{k+1}, t_0 = -1, t_K = 255) maximising the between-class
+// variance, i.e. sum_k S_k^2 / W_k for the fixed histogram (W_k voxels and
+// S_k the bin sum of class k), in binary64 in class order.  Tuples with an
+// empty class are skipped; the first maximum in lexicographic order wins:
+// every workgroup keeps its best (score, rank), rank = the tuple's
+// lexicographic position, and one workgroup picks the highest score with the
+// smallest rank.  Pairs (t1, t2) are spread over the grid as p = t1 * 255 +
+// t2; for K = 4 the workgroup's chunk c takes t3 over
+// max(t2 + 1, 32 c) .. min(254, 32 c + 31), so no thread runs more than 32
+// tuples.
+
+__device__ __forceinline__ double mo_term(unsigned long long W, unsigned long long S) {
+    const double s = (double)S;
+    return (s * s) / (double)W;
+}
+
+// (value, rank) pairs: the higher value wins, then the smaller rank
+__device__ __forceinline__ void mo_take(double& v, unsigned long long& r, double bv, unsigned long long br) {
+    if (bv > v || (bv == v && br < r)) {
+        v = bv;
+        r = br;
+    }
+}
+
+__device__ __forceinline__ void mo_reduce(double* sv, unsigned long long* sr, int t) {
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) {
+            double v = sv[t];
+            unsigned long long r = sr[t];
+            mo_take(v, r, sv[t + o], sr[t + o]);
+            sv[t] = v;
+            sr[t] = r;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_multi_search(DevState* S, int classes) {
+    __shared__ unsigned long long P[257], Q[257];
+    __shared__ double sv[256];
+    __shared__ unsigned long long sr[256];
+    const int t = threadIdx.x;
+    // prefix counts and bin sums: P[i], Q[i] over bins 0 .. i-1 (inclusive
+    // scan of the bins in LDS; integer sums, so exact in any order)
+    const unsigned long long h = S->hist[t];
+    P[t + 1] = h;
+    Q[t + 1] = (unsigned long long)t * h;
+    if (t == 0) P[0] = Q[0] = 0ull;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const unsigned long long a = t >= o ? P[t + 1 - o] : 0ull, b = t >= o ? Q[t + 1 - o] : 0ull;
+        __syncthreads();
+        P[t + 1] += a;
+        Q[t + 1] += b;
+        __syncthreads();
+    }
+    double best = -1.0;
+    unsigned long long rank = ~0ull;
+    const int p = (blockIdx.x % kMoPairBlocks) * blockDim.x + t;
+    const int t1 = p / 255, t2 = p % 255;
+    if (classes == 3) {
+        if (t1 < t2 && t2 < 255) {
+            const unsigned long long W0 = P[t1 + 1], W1 = P[t2 + 1] - P[t1 + 1], W2 = P[256] - P[t2 + 1];
+            if (W0 && W1 && W2) {
+                const unsigned long long S0 = Q[t1 + 1], S1 = Q[t2 + 1] - Q[t1 + 1], S2 = Q[256] - Q[t2 + 1];
+                best = (mo_term(W0, S0) + mo_term(W1, S1)) + mo_term(W2, S2);
+                rank = (unsigned long long)p;
+            }
+        }
+    } else if (t1 < t2 && t2 < 254) {
+        const int c = blockIdx.x / kMoPairBlocks;
+        const int lo = max(t2 + 1, c * kMoChunk), hi = min(255, (c + 1) * kMoChunk);
+        const unsigned long long W0 = P[t1 + 1], W1 = P[t2 + 1] - P[t1 + 1];
+        const unsigned long long S0 = Q[t1 + 1], S1 = Q[t2 + 1] - Q[t1 + 1];
+        if (W0 && W1 && lo < hi) {
+            const double a = mo_term(W0, S0) + mo_term(W1, S1);
+            for (int t3 = lo; t3 < hi; ++t3) {
+                const unsigned long long W2 = P[t3 + 1] - P[t2 + 1], W3 = P[256] - P[t3 + 1];
+                if (!W2 || !W3) continue;
+                const unsigned long long S2 = Q[t3 + 1] - Q[t2 + 1], S3 = Q[256] - Q[t3 + 1];
+                const double v = (a + mo_term(W2, S2)) + mo_term(W3, S3);
+                if (v > best) {  // t3 ascending: the first maximum of this pair and chunk
+                    best = v;
+                    rank = (unsigned long long)p * 255ull + (unsigned long long)t3;
+                }
+            }
+        }
+    }
+    sv[t] = best;
+    sr[t] = rank;
+    __syncthreads();
+    mo_reduce(sv, sr, t);
+    if (t == 0) {
+        S->mo_val[blockIdx.x] = sv[0];
+        S->mo_rank[blockIdx.x] = sr[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_multi_pick(DevState* S, int classes, int parts) {
+    __shared__ double sv[256];
+    __shared__ unsigned long long sr[256];
+    const int t = threadIdx.x;
+    double v = -1.0;
+    unsigned long long r = ~0ull;
+    for (int i = t; i < parts; i += 256) mo_take(v, r, S->mo_val[i], S->mo_rank[i]);
+    sv[t] = v;
+    sr[t] = r;
+    __syncthreads();
+    mo_reduce(sv, sr, t);
+    if (t == 0) {
+        if (__hip_atomic_load(&S->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+        int32_t th[3] = {255, 255, classes == 4 ? 255 : -1};
+        if (sv[0] < 0.0) {
+            S->flags |= ROIX_FLAG_DEGENERATE_HISTOGRAM;
+        } else if (classes == 3) {
+            th[0] = (int32_t)(sr[0] / 255ull);
+            th[1] = (int32_t)(sr[0] % 255ull);
+        } else {
+            const unsigned long long pr = sr[0] / 255ull;
+            th[0] = (int32_t)(pr / 255ull);
+            th[1] = (int32_t)(pr % 255ull);
+            th[2] = (int32_t)(sr[0] % 255ull);
+        }
+        S->thr_t[0] = th[0];
+        S->thr_t[1] = th[1];
+        S->thr_t[2] = th[2];
+        S->n_classes = classes;
+        // object: every class above the lowest threshold
+        const int ts = th[0];
+        S->otsu_bin = ts;
+        S->proxy_thr = ts;
+        const long long c = ((long long)(ts + 1) * S->K + 255) / 256;
+        S->q_thr = (int32_t)((long long)S->qmin + c);
+    }
+}
+
+hipError_t launch_threshold(const LaunchCtx& lc, DevState* S, const roix_criterion* crit) {
+    if (crit->thr != ROIX_THR_MULTI_OTSU) return launch_otsu(lc, S, crit->thr == ROIX_THR_FIXED);
+    const int classes = crit->classes == 4 ? 4 : 3;
+    static_assert(kMoPairBlocks * 256 >= 254 * 255 + 255, "the grid covers every pair (t1, t2)");
+    static_assert(kMoChunks * kMoChunk >= 255, "the chunks cover every t3");
+    const int parts = classes == 4 ? kMoParts : kMoPairBlocks;
+    timer_begin(lc.timer, ST_OTSU, lc.stream);
+    hipLaunchKernelGGL(k_multi_search, dim3(parts), dim3(256), 0, lc.stream, S, classes);
+    hipLaunchKernelGGL(k_multi_pick, dim3(1), dim3(256), 0, lc.stream, S, classes, parts);
     timer_end(lc.timer, ST_OTSU, lc.stream);
     return hipGetLastError();
 }

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libroix.so")
 OK, EINVAL, ERANGE, ENOMEM, ETRUNC, EDEVICE, EBUSY, ESEQ = range(8)
 F32, U16 = 0, 1
 EB_ABS, EB_REL = 0, 1
-THR_OTSU, THR_FIXED = 0, 1
+THR_OTSU, THR_FIXED, THR_MULTI_OTSU = 0, 1, 2
 KEEP_MIN_SIZE, KEEP_LARGEST = 0, 1
 FLAG_DEGENERATE_HISTOGRAM, FLAG_EMPTY_ROI, FLAG_FIXED_THRESHOLD = 1, 2, 4
 NOT_COMPUTED = (1 << 64) - 1
@@ -40,7 +40,7 @@ class Eb(ctypes.Structure):
 
 class CCriterion(ctypes.Structure):
     _fields_ = [("thr", ctypes.c_int32), ("connectivity", ctypes.c_int32), ("fixed_value", ctypes.c_double),
-                ("keep", ctypes.c_int32), ("pad", ctypes.c_int32), ("min_size", ctypes.c_int64)]
+                ("keep", ctypes.c_int32), ("classes", ctypes.c_int32), ("min_size", ctypes.c_int64)]
 
 
 class QuantInfo(ctypes.Structure):
@@ -54,7 +54,7 @@ class SegInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("otsu_bin", ctypes.c_int32), ("q_thr", ctypes.c_int32),
                 ("flags", ctypes.c_uint32), ("hist", ctypes.c_uint64 * 256), ("n_mask", ctypes.c_uint64),
                 ("n_components", ctypes.c_uint64), ("n_kept", ctypes.c_uint64), ("n_kept_voxels", ctypes.c_uint64),
-                ("bbox", ctypes.c_uint32 * 6)]
+                ("bbox", ctypes.c_uint32 * 6), ("thresholds", ctypes.c_int32 * 3), ("n_classes", ctypes.c_int32)]
 
 
 class ExtractInfo(ctypes.Structure):
@@ -149,16 +149,20 @@ def load():
 @dataclass
 class Criterion:
     """ROI criterion (mirrors roix_criterion)."""
-    thr: str = "otsu"          # "otsu" | "fixed"
+    thr: str = "otsu"          # "otsu" | "fixed" | "multi3" | "multi4" (multi-level Otsu, 3 or 4 classes)
     fixed_value: float = 0.0
     connectivity: int = 26     # 6 | 26
     keep: str = "largest"      # "largest" | "min_size"
     min_size: int = 1
 
     def c(self) -> CCriterion:
-        return CCriterion(THR_OTSU if self.thr == "otsu" else THR_FIXED, int(self.connectivity),
-                          float(self.fixed_value), KEEP_LARGEST if self.keep == "largest" else KEEP_MIN_SIZE, 0,
-                          int(self.min_size))
+        thr, classes = _THR_CODES[self.thr]
+        return CCriterion(thr, int(self.connectivity), float(self.fixed_value),
+                          KEEP_LARGEST if self.keep == "largest" else KEEP_MIN_SIZE, classes, int(self.min_size))
+
+
+_THR_CODES = {"otsu": (THR_OTSU, 0), "fixed": (THR_FIXED, 0), "multi3": (THR_MULTI_OTSU, 3),
+              "multi4": (THR_MULTI_OTSU, 4)}
 
 
 def dims_of(vol: torch.Tensor) -> Dims:

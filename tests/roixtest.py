@@ -70,6 +70,9 @@ def compare_fused(g, o, check_outputs=True):
         for f in ("n_kept", "n_kept_voxels"):
             assert getattr(s, f) == getattr(oi, f), (f, getattr(s, f), getattr(oi, f))
         assert list(s.bbox) == list(oi.bbox), ("bbox", list(s.bbox), list(oi.bbox))
+    if p.status == 0 and s.status == 0:
+        assert list(s.thresholds) == list(oi.thresholds), ("thresholds", list(s.thresholds), list(oi.thresholds))
+        assert s.n_classes == oi.n_classes, ("n_classes", s.n_classes, oi.n_classes)
     e = g["einfo"]
     assert e.status == oi.ext_status, ("einfo.status", e.status, oi.ext_status)
     for f in ("n_rows", "n_codes", "n_outliers", "stream_bytes"):

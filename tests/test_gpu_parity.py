@@ -317,3 +317,56 @@ def test_repeat_determinism(env):
         if ref is None:
             ref = cur
         assert cur == ref
+
+
+def three_materials(shape, seed):
+    """Background, a matrix block and an inclusion of distinct intensities."""
+    nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    vol = 0.1 + rng.normal(0, 0.01, shape)
+    vol[nz // 6: nz - nz // 6, ny // 6: ny - ny // 6, nx // 5: nx - nx // 5] = 0.5
+    vol[nz // 3: nz - nz // 3, ny // 3: ny - ny // 3, nx // 3: nx - nx // 3] = 0.9
+    vol += rng.normal(0, 0.01, shape)
+    return vol.astype(np.float32)
+
+
+@pytest.mark.parametrize("thr", ["multi3", "multi4"])
+@pytest.mark.parametrize("conn", [6, 26])
+def test_multi_otsu(env, thr, conn):
+    # multi-level Otsu: thresholds, class count and every output against the oracle
+    cases = [
+        ("three materials", three_materials((12, 24, 96), 31), "abs", 1e-3),
+        ("three materials ragged", three_materials((7, 19, 133), 32), "abs", 1e-4),
+        ("ellipsoids", synth.ellipsoids(130, 40, 9, 4100, n_ell=4, ax=(2.0, 20.0))[0], "abs", 1e-3),
+        ("noise", synth.normal((9, 31, 70), 4200, 0.5, 0.1), "abs", 1e-3),
+        ("rings u16", synth.rings2048(nxy=96, nz=5).volume, "rel", 1e-4),
+        ("constant", np.full((3, 8, 64), 2.5, np.float32), "abs", 1e-3),
+        ("two values", np.where(np.arange(3 * 8 * 64).reshape(3, 8, 64) % 3 == 0, 1.0, 0.0).astype(np.float32),
+         "abs", 1e-3),
+        ("single voxel", np.full((1, 1, 1), 0.25, np.float32), "abs", 1e-3),
+    ]
+    for name, vol, ebm, ebv in cases:
+        for keep, ms in (("largest", 1), ("min_size", 4)):
+            c = synth.Criterion(thr, 0.0, conn, keep, ms)
+            g, o = run_case(env, f"{thr} {name}", vol, ebm, ebv, c)
+            assert g["sinfo"].n_classes == (3 if thr == "multi3" else 4)
+
+
+@pytest.mark.parametrize("thr", ["multi3", "multi4"])
+def test_multi_otsu_staged(env, thr):
+    # the staged segmentation takes the same thresholds from the codes' histogram
+    ctx, roix, torch = env
+    vol = three_materials((10, 30, 128), 33)
+    c = synth.Criterion(thr, 0.0, 26, "min_size", 1)
+    crit = criterion(roix, c)
+    log(f"[case] staged {thr}")
+    t = torch.from_numpy(vol).to("cuda:0")
+    codes, bits, qinfo = ctx.quantize(t, "abs", 1e-3)
+    caps = default_caps(roix, vol, crit)
+    keep, labels, comps, sinfo = ctx.segment(codes, qinfo, crit, caps[3], want_labels=True)
+    torch.cuda.synchronize()
+    s = roix.parse_info(sinfo, roix.SegInfo)
+    f = oracle_fused(vol, "abs", 1e-3, c)
+    oi = f["info"]
+    assert s.status == 0 and list(s.thresholds) == list(oi.thresholds) and s.n_classes == oi.n_classes
+    assert (s.otsu_bin, s.q_thr, s.n_mask, s.n_components) == (oi.otsu_bin, oi.q_thr, oi.n_mask, oi.n_components)
