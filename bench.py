@@ -180,6 +180,95 @@ def bench_decode(args):
     ctx.close()
 
 
+def bench_background(args):
+    """Background subtraction (M = I - B) of the benchmark volume put on a
+    smooth calibration plane: GB/s of the subtraction with one plane for
+    every z and with a reference volume, and the whole path run on M after
+    the subtraction (one step = subtraction + fused path)."""
+    import torch
+
+    import synth
+    from paper_2602_15917_amd import roix
+    dev = "cuda:0"
+    w = synth.cylinder1024(n=args.n)
+    nz, ny, nx = w.volume.shape
+    x = torch.from_numpy(w.volume).to(dev)
+    del w.volume
+    yy, xx = torch.meshgrid(torch.arange(ny, device=dev, dtype=torch.float32),
+                            torch.arange(nx, device=dev, dtype=torch.float32), indexing="ij")
+    plane = (0.3 + 0.4 * xx / nx - 0.2 * ((xx - nx / 2) ** 2 + (yy - ny / 2) ** 2) / (nx * nx / 4))[None]
+    plane = plane.contiguous()
+    x.add_(plane)  # the image: object on its background
+    crit = roix.Criterion(w.criterion.thr, 0.0, w.criterion.connectivity, w.criterion.keep, w.criterion.min_size)
+    dims = roix.dims_of(x)
+    ctx = roix.Context(0, roix.scratch_bytes(dims, roix.F32, crit))
+    b = roix.bounds(dims, roix.F32, crit)
+    out = roix.Outputs(dev, b["rows"], b["stream_bytes"], 1 << 22, 1 << 22)
+    m = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    N = x.numel()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / args.steps
+
+    def kernel_ms(fn):
+        ctx.set_timing(True)
+        for _ in range(args.steps):
+            fn()
+        st = ctx.read_timing()
+        ctx.set_timing(False)
+        return st["background"][0] / max(st["background"][1], 1), st
+
+    sub_plane = lambda: ctx.background(x, plane, "subtract", m, stream)
+    ms_plane = timed(sub_plane)
+    k_plane, _ = kernel_ms(sub_plane)
+    bytes_plane = N * 8 + plane.numel() * 4
+    ref = plane.expand(nz, ny, nx).contiguous()
+    sub_vol = lambda: ctx.background(x, ref, "subtract", m, stream)
+    ms_vol = timed(sub_vol)
+    k_vol, _ = kernel_ms(sub_vol)
+    del ref
+    bytes_vol = N * 12
+
+    def step():
+        ctx.background(x, plane, "subtract", m, stream)
+        ctx.fused(m, w.eb_mode, w.eb_value, crit, out, stream)
+    ms_step = timed(step)
+    _, st = kernel_ms(step)
+    g = out.collect()
+    assert g["qinfo"].status == 0 and g["sinfo"].status == 0 and g["einfo"].status == 0
+    ach = bytes_plane / (k_plane * 1e-3) / 1e9
+    line = {
+        "metric": "background subtraction GB/s (float32 image in, float32 M = I - B out)",
+        "value": round(N * 8 / (ms_plane * 1e-3) / 1e9, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_plane, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{w.name} on a calibration plane (offset, tilt, radial falloff)",
+                   "reference": "one ny*nx plane for every z"},
+        "roofline": {"bound": "hbm", "kernel": "background", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "alg_bytes_per_launch": int(bytes_plane), "avg_launch_ms": round(k_plane, 4)},
+        "reference_volume": {"ms": round(ms_vol, 4), "kernel_ms": round(k_vol, 4),
+                             "achieved_GBps": round(bytes_vol / (k_vol * 1e-3) / 1e9, 1),
+                             "alg_bytes_per_launch": int(bytes_vol)},
+        "subtract_then_path": {"ms_per_step": round(ms_step, 4),
+                               "voxels_per_s": round(N / (ms_step * 1e-3), 1),
+                               "n_kept_voxels": int(g["sinfo"].n_kept_voxels)},
+        "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in st.items() if v[1]},
+    }
+    print(json.dumps(line))
+    ctx.close()
+
+
 def bench_batched(args):
     """64 float32 volumes, sides U{64..512} per axis, 1-8 ellipsoids, eb from
     {1e-3, 1e-4, 1e-5}: one batched graph launch against the same volumes
@@ -430,10 +519,11 @@ def main():
                     help="also run a plain device copy of 1 GiB (the counter calibration for traffic)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL_STATS_CSV"),
                     help="summarise rocprofv3 counter runs of this script and exit")
-    ap.add_argument("--workload", choices=["plain", "batched", "served", "decode"], default="plain",
+    ap.add_argument("--workload", choices=["plain", "batched", "served", "decode", "background"], default="plain",
                     help="plain: the 1024^3 volume (default); batched: 64 uneven volumes in one graph launch; "
                          "served: open-loop slab-stream trace with p50/p99 latency; decode: the reverse "
-                         "process of the 1024^3 volume's extraction")
+                         "process of the 1024^3 volume's extraction; background: subtraction of a "
+                         "calibration plane or volume, then the path on the result")
     ap.add_argument("--served-streams", type=int, default=4, help="uint16 2048x2048 streams of the served trace")
     ap.add_argument("--served-nz", type=int, default=256, help="planes per served stream (slabs of 32)")
     ap.add_argument("--served-cubes", type=int, default=16, help="float32 cubes interleaved in the served trace")
@@ -451,6 +541,8 @@ def main():
         return bench_batched(args)
     if args.workload == "served":
         return bench_served(args)
+    if args.workload == "background":
+        return bench_background(args)
     if args.workload == "decode":
         return bench_decode(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

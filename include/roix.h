@@ -296,6 +296,28 @@ roix_status roix_decode(roix_ctx* ctx, const roix_row* d_rows, int64_t rows_cap,
                         const roix_quant_info* d_qinfo, const roix_extract_info* d_einfo, roix_dims dims,
                         float background, float* d_out, roix_decode_info* d_dinfo, void* stream);
 
+/* Background subtraction (Sec. 4.1.1): the output image is the input minus
+ * a background reference, voxel by voxel, M = I - B; and its inverse for the
+ * reverse process (Sec. 4.3), which puts the reconstructed object back on
+ * the background, I' = M' + B.
+ *   d_in       N voxels, C order [nz][ny][nx]: float32, or uint16 (SUBTRACT
+ *              only; converted exactly to float32 first)
+ *   d_bg       float32 reference, bg_planes planes of ny * nx voxels: 1 (the
+ *              same calibration plane for every z) or nz (a reference volume)
+ *   op         ROIX_BG_SUBTRACT: out = in - bg;  ROIX_BG_ADD: out = in + bg
+ *   d_out      N float32; may be d_in itself when the input is float32 (in
+ *              place), must not overlap it otherwise, nor the reference
+ * One float32 operation per voxel, rounded to nearest even, so the output
+ * is exact to the bit.  Subtracting before roix_fused (on the same stream)
+ * runs the whole path on M; decoding and adding the reference back rebuilds
+ * I within the error bound plus the roundings of the two operations.  All
+ * pointers are device memory owned by the caller; asynchronous on `stream`.
+ * Errors: ROIX_EINVAL (NULL arguments, bad dims or dtype, ADD on uint16,
+ * bg_planes not 1 or nz, misaligned or overlapping buffers), ROIX_EDEVICE. */
+typedef enum { ROIX_BG_SUBTRACT = 0, ROIX_BG_ADD = 1 } roix_bg_op;
+roix_status roix_background(roix_ctx* ctx, const void* d_in, roix_dtype dtype, roix_dims dims, const float* d_bg,
+                            int64_t bg_planes, roix_bg_op op, float* d_out, void* stream);
+
 /* One volume of a batch: input, shape, bound, criterion and the caller's
  * output buffers (as for roix_fused). */
 typedef struct {

@@ -92,6 +92,8 @@ def _load():
         lib.oracle_stream.restype = ci
         lib.oracle_decode.argtypes = [vp, u64, vp, vp, u64, ctypes.POINTER(Params), i64, i64, i64, f32, vp]
         lib.oracle_decode.restype = ci
+        lib.oracle_background.argtypes = [vp, ci, vp, i64, i64, i64, i64, ci, vp]
+        lib.oracle_background.restype = ci
         lib.oracle_fused.argtypes = [vp, ci, i64, i64, i64, ci, dbl, ci, dbl, ci, ci, i64, vp, i64, vp, i64, vp,
                                      i64, vp, i64, ctypes.POINTER(FusedInfo)]
         lib.oracle_fused.restype = ci
@@ -229,6 +231,23 @@ def decode(row_table, stream_bytes, outliers, p, shape, background=0.0):
     ol = np.ascontiguousarray(outliers, dtype=np.float32)
     st = _load().oracle_decode(_p(rt), len(rt), _p(sb) if sb.size else None, _p(ol) if ol.size else None,
                                ol.size, ctypes.byref(p), nx, ny, nz, background, _p(out))
+    return st, out
+
+
+def background(vol, bg, op="subtract"):
+    """Background subtraction of Sec. 4.1.1, M = I - B voxel by voxel
+    (op "subtract"), or I + B (op "add": the decoded object back on its
+    background, Sec. 4.3).  bg: float32 of shape (1, ny, nx) -- one
+    calibration plane for every z -- or (nz, ny, nx).  Returns (status,
+    float32 volume)."""
+    vol = np.ascontiguousarray(vol)
+    bg = np.ascontiguousarray(bg, dtype=np.float32)
+    nz, ny, nx = vol.shape
+    if bg.ndim != 3 or bg.shape[1:] != (ny, nx):
+        return EINVAL, None
+    out = np.empty(vol.shape, np.float32)
+    st = _load().oracle_background(_p(vol), _dt(vol), _p(bg), bg.shape[0], nx, ny, nz,
+                                   {"subtract": 0, "add": 1}[op], _p(out))
     return st, out
 
 

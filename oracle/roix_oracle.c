@@ -38,6 +38,9 @@
  *                b bits, with the raw value of every outlier kept aside
  *   decode       the reverse process of Sec. 4.3 (rows restored from the
  *                geometry section)
+ *   background   background subtraction M = I - B of Sec. 4.1.1 (B a
+ *                calibration plane or volume), and M + B to put a decoded
+ *                volume back on its background
  *
  * Where the paper is silent or ambiguous this file takes these readings:
  * half-open spans [x_start, x_end) so that n_i = x_end - x_start; a span
@@ -543,6 +546,27 @@ int oracle_stream(const void* in, int dtype, int64_t nx, int64_t ny, const or_pa
     *n_codes = nc;
     *n_outliers = no;
     if (nc * (uint64_t)bytes > stream_cap_bytes || no > outliers_cap) return OR_ETRUNC;
+    return OR_OK;
+}
+
+/* Background subtraction (Sec. 4.1.1): out = I - B voxel by voxel (op 0),
+ * or out = I + B (op 1, the reverse process putting a decoded object back on
+ * its background).  B holds bg_planes planes of ny * nx float32 values: one
+ * plane for every z (bg_planes == 1) or one per z.  uint16 input (dtype 1)
+ * is converted to float32 first (exactly).  One binary32 operation per
+ * voxel.  Returns OR_EINVAL for a bad dtype, op or plane count. */
+int oracle_background(const void* in, int dtype, const float* bg, int64_t bg_planes, int64_t nx, int64_t ny,
+                      int64_t nz, int op, float* out) {
+    if ((dtype != 0 && dtype != 1) || (op != 0 && op != 1) || (bg_planes != 1 && bg_planes != nz))
+        return OR_EINVAL;
+    for (int64_t z = 0; z < nz; ++z)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t x = 0; x < nx; ++x) {
+                int64_t v = (z * ny + y) * nx + x;
+                int64_t b = ((bg_planes == 1 ? 0 : z) * ny + y) * nx + x;
+                float i = dtype == 0 ? ((const float*)in)[v] : (float)((const uint16_t*)in)[v];
+                out[v] = op == 0 ? i - bg[b] : i + bg[b];
+            }
     return OR_OK;
 }
 

@@ -31,7 +31,7 @@ void timer_end(Timer* t, int stage, hipStream_t s) {
 
 static const char* kStageNames[ST_COUNT] = {
     "init", "range", "resolve", "quantize", "quant_hist", "quant_range16", "otsu", "mask_runs", "scan", "runs_write",
-    "union", "flatten", "comp_stats", "keep", "spans", "emit", "emit_rows", "voxel_out", "finalize", "decode_index", "decode"};
+    "union", "flatten", "comp_stats", "keep", "spans", "emit", "emit_rows", "voxel_out", "finalize", "decode_index", "decode", "background"};
 
 }  // namespace roix
 
@@ -500,6 +500,24 @@ roix_status roix_decode(roix_ctx* ctx, const roix_row* d_rows, int64_t rows_cap,
     ROIX_TRY(launch_decode(lctx(ctx, stream), d_rows, (uint64_t)rows_cap, d_stream, (uint64_t)stream_cap_bytes,
                            d_outliers, (uint64_t)outliers_cap, d_qinfo, d_einfo, g, background, d_out, S, desc,
                            d_dinfo));
+    return ROIX_OK;
+}
+
+roix_status roix_background(roix_ctx* ctx, const void* d_in, roix_dtype dtype, roix_dims dims, const float* d_bg,
+                            int64_t bg_planes, roix_bg_op op, float* d_out, void* stream) {
+    Geom g;
+    if (!ctx || !d_in || !d_bg || !d_out || !geom_of(dims, &g)) return ROIX_EINVAL;
+    if (dtype != ROIX_F32 && dtype != ROIX_U16) return ROIX_EINVAL;
+    if (op != ROIX_BG_SUBTRACT && (op != ROIX_BG_ADD || dtype != ROIX_F32)) return ROIX_EINVAL;
+    if (bg_planes != 1 && bg_planes != g.nz) return ROIX_EINVAL;
+    const size_t es = dtype == ROIX_F32 ? 4 : 2;
+    if (!aligned(d_in, es) || !aligned(d_bg, 4) || !aligned(d_out, 4)) return ROIX_EINVAL;
+    // the output may be the float32 input itself, and must not overlap it otherwise
+    const uintptr_t i0 = (uintptr_t)d_in, i1 = i0 + g.N * es, o0 = (uintptr_t)d_out, o1 = o0 + g.N * 4;
+    if (!(dtype == ROIX_F32 && i0 == o0) && i0 < o1 && o0 < i1) return ROIX_EINVAL;
+    const uintptr_t b0 = (uintptr_t)d_bg, b1 = b0 + (size_t)bg_planes * (size_t)(g.nx * g.ny) * 4;
+    if (b0 < o1 && o0 < b1) return ROIX_EINVAL;
+    ROIX_TRY(launch_background(lctx(ctx, stream), d_in, dtype, d_bg, bg_planes > 1, g, (int)op, d_out));
     return ROIX_OK;
 }
 

@@ -228,6 +228,7 @@ enum Stage {
     ST_FINALIZE,
     ST_DECODE_INDEX,
     ST_DECODE,
+    ST_BACKGROUND,
     ST_COUNT
 };
 
@@ -306,6 +307,8 @@ hipError_t launch_decode(const LaunchCtx& lc, const roix_row* rows, uint64_t row
                          uint64_t stream_cap, const float* outl, uint64_t outl_cap, const roix_quant_info* qi,
                          const roix_extract_info* ei, const Geom& g, float background, float* out, DevState* S,
                          uint4* desc, roix_decode_info* dinfo);
+hipError_t launch_background(const LaunchCtx& lc, const void* in, roix_dtype dt, const float* bg, bool full,
+                             const Geom& g, int op, float* out);
 hipError_t launch_flatten(const LaunchCtx& lc, const Layout& L);
 hipError_t launch_comp_stats(const LaunchCtx& lc, const Geom& g, const Layout& L, roix_component* comps);
 hipError_t launch_keep(const LaunchCtx& lc, const Layout& L, roix_component* comps, const roix_criterion* crit);

@@ -19,6 +19,7 @@ OK, EINVAL, ERANGE, ENOMEM, ETRUNC, EDEVICE, EBUSY, ESEQ = range(8)
 F32, U16 = 0, 1
 EB_ABS, EB_REL = 0, 1
 THR_OTSU, THR_FIXED, THR_MULTI_OTSU = 0, 1, 2
+BG_OPS = {"subtract": 0, "add": 1}
 KEEP_MIN_SIZE, KEEP_LARGEST = 0, 1
 FLAG_DEGENERATE_HISTOGRAM, FLAG_EMPTY_ROI, FLAG_FIXED_THRESHOLD = 1, 2, 4
 NOT_COMPUTED = (1 << 64) - 1
@@ -136,11 +137,12 @@ def load():
     lib.roix_wait.argtypes = [vp, i64, i64, P(ReqResult)]
     lib.roix_server_stats.argtypes = [vp, P(ServerStats)]
     lib.roix_decode.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp, vp, Dims, ctypes.c_float, vp, vp, vp]
+    lib.roix_background.argtypes = [vp, vp, ci, Dims, vp, i64, ci, vp, vp]
     for f in ("roix_ctx_create", "roix_ctx_destroy", "roix_bounds", "roix_quantize", "roix_segment",
               "roix_extract", "roix_fused", "roix_ctx_set_timing", "roix_ctx_read_timing", "roix_fused_batch",
               "roix_ctx_set_param", "roix_ctx_get_param", "roix_server_create", "roix_server_destroy",
               "roix_volume_open", "roix_slab_submit", "roix_volume_close", "roix_volume_abort", "roix_wait",
-              "roix_server_stats", "roix_decode"):
+              "roix_server_stats", "roix_decode", "roix_background"):
         getattr(lib, f).restype = ci
     _lib = lib
     return lib
@@ -321,6 +323,22 @@ class Context:
                                 dims, float(background), dst.data_ptr(), dinfo.data_ptr(), _stream(stream))
         _check(st, "roix_decode")
         return dst, dinfo
+
+    def background(self, vol: torch.Tensor, bg: torch.Tensor, op: str = "subtract",
+                   dst: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Enqueue M = vol - bg (op "subtract") or vol + bg (op "add") on the
+        device; bg is float32 of shape (1, ny, nx) or (nz, ny, nx).  dst
+        (float32, the volume's shape) may be vol itself for a float32 volume.
+        Returns dst."""
+        if not (vol.is_contiguous() and bg.is_contiguous()):
+            raise ValueError("background: volume and reference must be contiguous")
+        if dst is None:
+            dst = torch.empty(vol.shape, dtype=torch.float32, device=vol.device)
+        planes = bg.shape[0] if bg.dim() == 3 else -1
+        st = load().roix_background(self.h, _ptr(vol), dtype_of(vol), dims_of(vol), _ptr(bg), planes,
+                                    BG_OPS[op], _ptr(dst), _stream(stream))
+        _check(st, "roix_background")
+        return dst
 
     def fused(self, vol: torch.Tensor, eb_mode: str, eb_value: float, crit: Criterion, out: Outputs,
               stream=None):

@@ -27,7 +27,7 @@ def declared_functions():
 def test_header_declares_the_path_calls():
     names = declared_functions()
     for n in ("roix_quantize", "roix_segment", "roix_extract", "roix_fused", "roix_ctx_create",
-              "roix_ctx_destroy", "roix_scratch_bytes", "roix_bounds", "roix_decode"):
+              "roix_ctx_destroy", "roix_scratch_bytes", "roix_bounds", "roix_decode", "roix_background"):
         assert n in names
 
 
@@ -87,6 +87,7 @@ def test_sync_argument_errors(lib):
     assert L.roix_wait(null, 1, 0, ctypes.byref(roix.ReqResult())) == roix.EINVAL
     assert L.roix_server_stats(null, ctypes.byref(roix.ServerStats())) == roix.EINVAL
     assert L.roix_decode(null, null, 0, null, 0, null, 0, null, null, d, 0.0, null, null, null) == roix.EINVAL
+    assert L.roix_background(null, null, roix.F32, d, null, 1, 0, null, null) == roix.EINVAL
 
 
 def test_served_calls_without_server(lib):

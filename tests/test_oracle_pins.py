@@ -527,3 +527,56 @@ def test_ground_truth_rings_u16():
     st, out = oracle.decode(r["rows"], r["stream"], r["outliers"], r["params"], w.volume.shape, np.nan)
     span = ~np.isnan(out)
     assert np.abs(out[span] - w.volume[span].astype(np.float32)).max() <= np.float32(r["params"].eb32)
+
+
+def _dyadic_object_and_background(shape, seed, planes):
+    # object values on a 2^-12 grid in [0, 1), background on a 2^-8 grid in
+    # [0, 2): every sum is exact in float32 (at most 14 significant bits)
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    obj = (rng.integers(0, 4096, shape) / 4096.0).astype(np.float32)
+    bg = (rng.integers(0, 512, (planes, ny, nx)) / 256.0).astype(np.float32)
+    return obj, bg, (obj + bg).astype(np.float32)
+
+
+def test_background_subtraction_recovers_the_object():
+    # Sec. 4.1.1: M = I - B; with I = O + B exact, M is O to the bit, and
+    # adding B back (the reverse process) gives I to the bit
+    for planes in (1, 5):
+        obj, bg, img = _dyadic_object_and_background((5, 7, 9), 90 + planes, planes)
+        st, m = oracle.background(img, bg)
+        assert st == oracle.OK and m.view(np.uint32).tobytes() == obj.view(np.uint32).tobytes()
+        st, back = oracle.background(m, bg, "add")
+        assert st == oracle.OK and back.view(np.uint32).tobytes() == img.view(np.uint32).tobytes()
+    # one plane for every z == the same plane repeated as a volume
+    obj, bg, img = _dyadic_object_and_background((4, 6, 10), 95, 1)
+    assert np.array_equal(oracle.background(img, bg)[1], oracle.background(img, np.repeat(bg, 4, axis=0))[1])
+    # uint16 input converts exactly: subtracting its own float values gives zeros
+    u = np.random.default_rng(96).integers(0, 65536, (3, 4, 5)).astype(np.uint16)
+    st, m = oracle.background(u, u.astype(np.float32))
+    assert st == oracle.OK and not m.any()
+    st, m = oracle.background(u, np.zeros((1, 4, 5), np.float32))
+    assert np.array_equal(m, u.astype(np.float32))
+    # the reference must be one plane or one per z
+    assert oracle.background(u, np.zeros((2, 4, 5), np.float32))[0] == oracle.EINVAL
+
+
+def test_background_subtraction_isolates_the_object():
+    # a strong background field hides the object from the threshold; after
+    # subtraction the path sees exactly the object volume
+    nz, ny, nx = 8, 32, 48
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    obj = np.where((x - 24) ** 2 + (y - 16) ** 2 + 4 * (z - 4) ** 2 < 81, 0.5, 0.0)
+    obj = (np.round(obj * 4096) / 4096).astype(np.float32)
+    ramp = np.round(2.0 * np.arange(nx) / nx * 256) / 256          # 0 .. 2 across x, on a 2^-8 grid
+    bg = np.broadcast_to(ramp, (1, ny, nx)).astype(np.float32)
+    img = (obj + bg).astype(np.float32)
+    st, m = oracle.background(img, bg)
+    assert st == oracle.OK and np.array_equal(m, obj)
+    ref = oracle.fused(obj, "abs", 1e-3, "otsu", 0.0, 26, "largest", 1)
+    sub = oracle.fused(m, "abs", 1e-3, "otsu", 0.0, 26, "largest", 1)
+    raw = oracle.fused(img, "abs", 1e-3, "otsu", 0.0, 26, "largest", 1)
+    n_obj = int((obj > 0).sum())
+    assert ref["info"].n_kept_voxels == n_obj and sub["info"].n_kept_voxels == n_obj
+    assert sub["rows"].tobytes() == ref["rows"].tobytes() and sub["stream"].tobytes() == ref["stream"].tobytes()
+    assert raw["info"].n_kept_voxels != n_obj  # without the subtraction the ramp decides the mask
