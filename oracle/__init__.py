@@ -94,6 +94,8 @@ def _load():
         lib.oracle_decode.restype = ci
         lib.oracle_background.argtypes = [vp, ci, vp, i64, i64, i64, i64, ci, vp]
         lib.oracle_background.restype = ci
+        lib.oracle_abs_quantize.argtypes = [vp, u64, dbl, vp, vp]
+        lib.oracle_abs_quantize.restype = ci
         lib.oracle_fused.argtypes = [vp, ci, i64, i64, i64, ci, dbl, ci, dbl, ci, ci, i64, vp, i64, vp, i64, vp,
                                      i64, vp, i64, ctypes.POINTER(FusedInfo)]
         lib.oracle_fused.restype = ci
@@ -249,6 +251,17 @@ def background(vol, bg, op="subtract"):
     st = _load().oracle_background(_p(vol), _dt(vol), _p(bg), bg.shape[0], nx, ny, nz,
                                    {"subtract": 0, "add": 1}[op], _p(out))
     return st, out
+
+
+def abs_quantize(pixels, e_abs):
+    """The paper's absolute error-bounded quantisation of an 8-bit pixel
+    sequence (Sec. 4.2.3, Steps 1-5; tolerance floor(e_abs) on integer
+    pixels).  Returns (status, Q uint8, number of groups)."""
+    d = np.ascontiguousarray(pixels, dtype=np.uint8).reshape(-1)
+    q = np.empty(max(d.size, 1), np.uint8)
+    n = np.zeros(1, np.uint64)
+    st = _load().oracle_abs_quantize(_p(d) if d.size else None, d.size, float(e_abs), _p(q), _p(n))
+    return st, q[: d.size].copy(), int(n[0])
 
 
 def fused(vol, eb_mode, eb_value, thr="otsu", fixed_value=0.0, connectivity=26, keep="largest", min_size=1,

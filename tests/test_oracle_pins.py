@@ -580,3 +580,76 @@ def test_background_subtraction_isolates_the_object():
     assert ref["info"].n_kept_voxels == n_obj and sub["info"].n_kept_voxels == n_obj
     assert sub["rows"].tobytes() == ref["rows"].tobytes() and sub["stream"].tobytes() == ref["stream"].tobytes()
     assert raw["info"].n_kept_voxels != n_obj  # without the subtraction the ramp decides the mask
+
+
+def _min_groups(d, K):
+    # fewest contiguous groups with max - min <= K, by dynamic programming
+    # over every split (independent of the greedy scan)
+    n = len(d)
+    best = [0] + [n + 1] * n
+    for j in range(1, n + 1):
+        lo = hi = int(d[j - 1])
+        for i in range(j - 1, -1, -1):
+            lo, hi = min(lo, int(d[i])), max(hi, int(d[i]))
+            if hi - lo > K:
+                break
+            best[j] = min(best[j], best[i] + 1)
+    return best[n]
+
+
+def test_abs_quantize_hand_examples():
+    g = json.load(open(os.path.join(GOLDEN, "hand_abs_quantize.json")))
+    for c in g["cases"]:
+        st, q, n = oracle.abs_quantize(np.array(c["D"], np.uint8), c["E"])
+        assert st == oracle.OK and q.tolist() == c["Q"] and n == c["groups"], c
+
+
+def test_abs_quantize_bound_and_optimal_group_count():
+    # Sec. 4.2.3: |Q - D| <= E for every pixel; the greedy growth gives the
+    # fewest groups (checked against an exhaustive dynamic programme); Q
+    # changes value only between groups
+    rng = np.random.default_rng(97)
+    for trial in range(300):
+        n = int(rng.integers(1, 60))
+        kind = trial % 3
+        if kind == 0:
+            d = rng.integers(0, 256, n)
+        elif kind == 1:
+            d = np.clip(np.round(128 + np.cumsum(rng.normal(0, 2, n))), 0, 255)
+        else:
+            d = np.clip(np.round(rng.normal(120, 6, n)), 0, 255)
+        d = d.astype(np.uint8)
+        e = float(rng.choice([0.0, 0.3, 1.0, 1.7, 2.0, 3.0, 5.5, 20.0]))
+        st, q, groups = oracle.abs_quantize(d, e)
+        ei = int(np.floor(e))
+        assert st == oracle.OK
+        assert np.all(np.abs(q.astype(int) - d.astype(int)) <= ei)
+        assert groups == _min_groups(d, 2 * ei)
+        assert int((np.diff(q.astype(int)) != 0).sum()) <= groups - 1
+
+
+def test_abs_quantize_closed_forms():
+    # constant pixels: one group, Q = D
+    st, q, n = oracle.abs_quantize(np.full(50, 77, np.uint8), 3)
+    assert n == 1 and np.all(q == 77)
+    # E < 1: groups are the runs of equal pixels and Q = D
+    d = np.array([5, 5, 6, 6, 6, 5, 200, 200, 0], np.uint8)
+    st, q, n = oracle.abs_quantize(d, 0.9)
+    assert np.array_equal(q, d) and n == 5
+    # ramp 0, 1, 2, ...: groups of 2E + 1 pixels written at their centre
+    for e in (1, 2, 4):
+        d = np.arange(200, dtype=np.uint8)
+        st, q, n = oracle.abs_quantize(d, e)
+        L = 2 * e + 1
+        assert n == -(-200 // L)
+        full = (200 // L) * L
+        assert np.array_equal(q[:full], (np.arange(full) // L) * L + e)
+        if full < 200:  # the last, shorter group: floor of its midpoint
+            assert np.all(q[full:] == (full + 199) // 2)
+    # a tolerance covering the whole 8-bit range: one group at (min + max) / 2
+    d = np.array([0, 255, 17, 3], np.uint8)
+    st, q, n = oracle.abs_quantize(d, 128)
+    assert n == 1 and np.all(q == 127)
+    # empty input and a negative tolerance
+    assert oracle.abs_quantize(np.zeros(0, np.uint8), 1)[2] == 0
+    assert oracle.abs_quantize(d, -1.0)[0] == oracle.EINVAL
