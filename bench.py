@@ -269,6 +269,70 @@ def bench_background(args):
     ctx.close()
 
 
+def bench_absq(args):
+    """The paper's absolute error-bounded quantisation (Sec. 4.2.3) of an
+    8-bit pixel section with the make-up of the benchmark volume's region of
+    interest, at its full size (514 688 000 pixels): pixels per second, with
+    the oracle's sequential scan timed on the same sequence."""
+    import torch
+
+    import synth
+    from paper_2602_15917_amd import roix
+    dev = "cuda:0"
+    m = synth.PIXEL_SECTION_FULL
+    t0 = time.time()
+    d = synth.pixel_section_u8(m)
+    log(f"generated the pixel section ({m} pixels) in {time.time() - t0:.1f}s")
+    x = torch.from_numpy(d).to(dev)
+    ctx = roix.Context(0, roix.abs_quantize_scratch_bytes(m))
+    q = torch.empty_like(x)
+    info = torch.zeros(32, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    per_e = {}
+    for e in (args.absq_e, 1.0, 5.0):
+        if e in per_e:
+            continue
+        for _ in range(args.warmup):
+            ctx.abs_quantize(x, e, q, info, stream)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            ctx.abs_quantize(x, e, q, info, stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        i = roix.absq_info(info)
+        per_e[e] = {"ms": round(ms, 4), "n_groups": int(i.n_groups), "rounds": int(i.rounds),
+                    "finisher_chunks": int(i.finisher_chunks), "pixels_per_group": round(m / max(int(i.n_groups), 1), 3)}
+    main = per_e[args.absq_e]
+    ms = main["ms"]
+    cpu = None
+    if args.cpu_planes != 0:
+        import oracle
+        t0 = time.time()
+        oracle.abs_quantize(d, args.absq_e)
+        dt = time.time() - t0
+        cpu = {"value": round(m / dt / 1e9, 4), "unit": "Gpixel/s", "cores": 1, "kind": "oracle",
+               "sample": f"the whole {m}-pixel section, single-threaded C oracle, {dt:.1f} s"}
+    byts = 2 * m
+    line = {
+        "metric": "pixels quantised per second (absolute error-bounded, 8-bit pixel section)",
+        "value": round(m / (ms * 1e-3) / 1e9, 3), "unit": "Gpixel/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "8-bit pixel section of the 1024^3 cylinder's region of interest (synthetic)",
+                   "pixels": m, "E": args.absq_e},
+        "roofline": {"bound": "hbm", "kernel": "abs_quantize (all passes)", "achieved": round(byts / (ms * 1e-3) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None, "alg_bytes_per_launch": byts},
+        "by_tolerance": {str(k): v for k, v in per_e.items()},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+    ctx.close()
+
+
 def bench_batched(args):
     """64 float32 volumes, sides U{64..512} per axis, 1-8 ellipsoids, eb from
     {1e-3, 1e-4, 1e-5}: one batched graph launch against the same volumes
@@ -519,11 +583,13 @@ def main():
                     help="also run a plain device copy of 1 GiB (the counter calibration for traffic)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL_STATS_CSV"),
                     help="summarise rocprofv3 counter runs of this script and exit")
-    ap.add_argument("--workload", choices=["plain", "batched", "served", "decode", "background"], default="plain",
+    ap.add_argument("--workload", choices=["plain", "batched", "served", "decode", "background", "absq"], default="plain",
                     help="plain: the 1024^3 volume (default); batched: 64 uneven volumes in one graph launch; "
                          "served: open-loop slab-stream trace with p50/p99 latency; decode: the reverse "
                          "process of the 1024^3 volume's extraction; background: subtraction of a "
-                         "calibration plane or volume, then the path on the result")
+                         "calibration plane or volume, then the path on the result; absq: the paper's "
+                         "absolute error-bounded quantisation of an 8-bit pixel section")
+    ap.add_argument("--absq-e", type=float, default=2.0, help="tolerance of the absq workload")
     ap.add_argument("--served-streams", type=int, default=4, help="uint16 2048x2048 streams of the served trace")
     ap.add_argument("--served-nz", type=int, default=256, help="planes per served stream (slabs of 32)")
     ap.add_argument("--served-cubes", type=int, default=16, help="float32 cubes interleaved in the served trace")
@@ -543,6 +609,8 @@ def main():
         return bench_served(args)
     if args.workload == "background":
         return bench_background(args)
+    if args.workload == "absq":
+        return bench_absq(args)
     if args.workload == "decode":
         return bench_decode(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

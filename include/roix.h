@@ -318,6 +318,43 @@ typedef enum { ROIX_BG_SUBTRACT = 0, ROIX_BG_ADD = 1 } roix_bg_op;
 roix_status roix_background(roix_ctx* ctx, const void* d_in, roix_dtype dtype, roix_dims dims, const float* d_bg,
                             int64_t bg_planes, roix_bg_op op, float* d_out, void* stream);
 
+/* Absolute error-bounded quantisation of an 8-bit pixel sequence, the
+ * paper's own algorithm (Sec. 4.2.3, Steps 1-5): a group grows pixel by
+ * pixel while the intervals [D - E, D + E] of its pixels intersect, and
+ * every pixel of the group is written as the floor of the midpoint of that
+ * intersection, floor((min + max) / 2), clipped to 0..255.  The pixels are
+ * integers, so the tolerance taken is floor(e_abs), which keeps
+ * |Q - D| <= e_abs for every pixel (with a fractional tolerance the floored
+ * midpoint could miss the bound).  The result is the sequential scan's,
+ * bit for bit.
+ *   d_pixels  m uint8 pixels (e.g. the 8-bit normalised pixel section of
+ *             Sec. 4.1.2), 16-byte aligned
+ *   d_q       m uint8 outputs, 16-byte aligned; may be d_pixels (in place)
+ *             but must not overlap it otherwise
+ *   d_info    device: status, n_groups (the number of groups), rounds (the
+ *             fix-up rounds that ran) and finisher_chunks (chunks settled
+ *             by the sequential pass; see below)
+ * The context's arena holds roix_abs_quantize_scratch_bytes(m) bytes of
+ * per-chunk state (about 49 bytes per 256 pixels) while the call runs.
+ * Sequences are cut into chunks of 256 pixels scanned in parallel from a
+ * guessed start and corrected in up to 4 rounds; chunks whose groups still
+ * depend on an earlier chunk after that (group chains that never meet, as
+ * on long exact ramps) are settled by a single-wave sequential pass, which
+ * is correct but slow.  Asynchronous on `stream`.
+ * Errors: ROIX_EINVAL (NULL ctx/d_info, NULL or misaligned buffers for
+ * m > 0, m < 0, e_abs negative or NaN, partial overlap), ROIX_ENOMEM (arena
+ * too small), ROIX_EDEVICE. */
+typedef struct {
+    int32_t status;
+    int32_t rounds;
+    uint64_t n_groups;
+    uint64_t finisher_chunks;
+    uint64_t pad;
+} roix_absq_info; /* 32 bytes */
+size_t roix_abs_quantize_scratch_bytes(int64_t m);
+roix_status roix_abs_quantize(roix_ctx* ctx, const uint8_t* d_pixels, int64_t m, double e_abs, uint8_t* d_q,
+                              roix_absq_info* d_info, void* stream);
+
 /* One volume of a batch: input, shape, bound, criterion and the caller's
  * output buffers (as for roix_fused). */
 typedef struct {

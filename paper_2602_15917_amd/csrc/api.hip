@@ -31,7 +31,7 @@ void timer_end(Timer* t, int stage, hipStream_t s) {
 
 static const char* kStageNames[ST_COUNT] = {
     "init", "range", "resolve", "quantize", "quant_hist", "quant_range16", "otsu", "mask_runs", "scan", "runs_write",
-    "union", "flatten", "comp_stats", "keep", "spans", "emit", "emit_rows", "voxel_out", "finalize", "decode_index", "decode", "background"};
+    "union", "flatten", "comp_stats", "keep", "spans", "emit", "emit_rows", "voxel_out", "finalize", "decode_index", "decode", "background", "abs_quantize"};
 
 }  // namespace roix
 
@@ -286,7 +286,7 @@ size_t roix_sizeof(const char* t) {
                      {"roix_criterion", sizeof(roix_criterion)},       {"roix_eb", sizeof(roix_eb)},
                      {"roix_dims", sizeof(roix_dims)},                 {"roix_volume_desc", sizeof(roix_volume_desc)},
                      {"roix_req_result", sizeof(roix_req_result)},     {"roix_server_stats_t", sizeof(roix_server_stats_t)},
-                     {"roix_decode_info", sizeof(roix_decode_info)}};
+                     {"roix_decode_info", sizeof(roix_decode_info)},   {"roix_absq_info", sizeof(roix_absq_info)}};
     for (const auto& e : tab)
         if (strcmp(e.n, t) == 0) return e.s;
     return 0;
@@ -518,6 +518,26 @@ roix_status roix_background(roix_ctx* ctx, const void* d_in, roix_dtype dtype, r
     const uintptr_t b0 = (uintptr_t)d_bg, b1 = b0 + (size_t)bg_planes * (size_t)(g.nx * g.ny) * 4;
     if (b0 < o1 && o0 < b1) return ROIX_EINVAL;
     ROIX_TRY(launch_background(lctx(ctx, stream), d_in, dtype, d_bg, bg_planes > 1, g, (int)op, d_out));
+    return ROIX_OK;
+}
+
+size_t roix_abs_quantize_scratch_bytes(int64_t m) { return m < 0 ? 0 : absq_scratch_bytes(m); }
+
+roix_status roix_abs_quantize(roix_ctx* ctx, const uint8_t* d_pixels, int64_t m, double e_abs, uint8_t* d_q,
+                              roix_absq_info* d_info, void* stream) {
+    if (!ctx || !d_info || m < 0 || !(e_abs >= 0.0) || !aligned(d_info, 8)) return ROIX_EINVAL;
+    if (m > ((int64_t)1 << 40)) return ROIX_EINVAL;
+    if (m > 0) {
+        if (!d_pixels || !d_q || !aligned(d_pixels, 16) || !aligned(d_q, 16)) return ROIX_EINVAL;
+        // in place, or apart: a partial overlap would overwrite pixels not yet read
+        const uintptr_t a0 = (uintptr_t)d_pixels, b0 = (uintptr_t)d_q;
+        if (a0 != b0 && a0 < b0 + (uint64_t)m && b0 < a0 + (uint64_t)m) return ROIX_EINVAL;
+    }
+    if (ctx->arena_bytes < absq_scratch_bytes(m)) return ROIX_ENOMEM;
+    // integer pixels: |Q - D| <= E exactly when |Q - D| <= floor(E); groups span at most 2 floor(E)
+    const double ef = e_abs >= 1024.0 ? 1024.0 : floor(e_abs);
+    const uint32_t K = 2.0 * ef >= 255.0 ? 255u : (uint32_t)(2.0 * ef);
+    ROIX_TRY(launch_absq(lctx(ctx, stream), d_pixels, m, K, d_q, ctx->arena, d_info));
     return ROIX_OK;
 }
 

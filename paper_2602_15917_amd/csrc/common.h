@@ -229,6 +229,7 @@ enum Stage {
     ST_DECODE_INDEX,
     ST_DECODE,
     ST_BACKGROUND,
+    ST_ABSQ,
     ST_COUNT
 };
 
@@ -309,6 +310,9 @@ hipError_t launch_decode(const LaunchCtx& lc, const roix_row* rows, uint64_t row
                          uint4* desc, roix_decode_info* dinfo);
 hipError_t launch_background(const LaunchCtx& lc, const void* in, roix_dtype dt, const float* bg, bool full,
                              const Geom& g, int op, float* out);
+size_t absq_scratch_bytes(int64_t m);
+hipError_t launch_absq(const LaunchCtx& lc, const uint8_t* D, int64_t m, uint32_t K, uint8_t* Q, void* scratch,
+                       roix_absq_info* info);
 hipError_t launch_flatten(const LaunchCtx& lc, const Layout& L);
 hipError_t launch_comp_stats(const LaunchCtx& lc, const Geom& g, const Layout& L, roix_component* comps);
 hipError_t launch_keep(const LaunchCtx& lc, const Layout& L, roix_component* comps, const roix_criterion* crit);

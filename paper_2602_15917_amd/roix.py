@@ -138,11 +138,14 @@ def load():
     lib.roix_server_stats.argtypes = [vp, P(ServerStats)]
     lib.roix_decode.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp, vp, Dims, ctypes.c_float, vp, vp, vp]
     lib.roix_background.argtypes = [vp, vp, ci, Dims, vp, i64, ci, vp, vp]
+    lib.roix_abs_quantize.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp, vp]
+    lib.roix_abs_quantize_scratch_bytes.argtypes = [i64]
+    lib.roix_abs_quantize_scratch_bytes.restype = sz
     for f in ("roix_ctx_create", "roix_ctx_destroy", "roix_bounds", "roix_quantize", "roix_segment",
               "roix_extract", "roix_fused", "roix_ctx_set_timing", "roix_ctx_read_timing", "roix_fused_batch",
               "roix_ctx_set_param", "roix_ctx_get_param", "roix_server_create", "roix_server_destroy",
               "roix_volume_open", "roix_slab_submit", "roix_volume_close", "roix_volume_abort", "roix_wait",
-              "roix_server_stats", "roix_decode", "roix_background"):
+              "roix_server_stats", "roix_decode", "roix_background", "roix_abs_quantize"):
         getattr(lib, f).restype = ci
     _lib = lib
     return lib
@@ -215,6 +218,14 @@ def decode_info(dinfo: torch.Tensor) -> "DecodeInfo":
     return _info(dinfo, DecodeInfo)
 
 
+def absq_info(info: torch.Tensor) -> "AbsqInfo":
+    return _info(info, AbsqInfo)
+
+
+def abs_quantize_scratch_bytes(m: int) -> int:
+    return int(load().roix_abs_quantize_scratch_bytes(int(m)))
+
+
 def stage_names():
     lib = load()
     return [lib.roix_stage_name(i).decode() for i in range(lib.roix_stage_count())]
@@ -261,6 +272,11 @@ class Outputs:
 class DecodeInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("pad", ctypes.c_int32), ("n_rows", ctypes.c_uint64),
                 ("n_codes", ctypes.c_uint64), ("n_outliers", ctypes.c_uint64)]
+
+
+class AbsqInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("rounds", ctypes.c_int32), ("n_groups", ctypes.c_uint64),
+                ("finisher_chunks", ctypes.c_uint64), ("pad", ctypes.c_uint64)]
 
 
 class Context:
@@ -339,6 +355,21 @@ class Context:
                                     BG_OPS[op], _ptr(dst), _stream(stream))
         _check(st, "roix_background")
         return dst
+
+    def abs_quantize(self, pixels: torch.Tensor, e_abs: float, dst: torch.Tensor | None = None,
+                     info: torch.Tensor | None = None, stream=None):
+        """Enqueue the absolute error-bounded quantisation of a uint8 pixel
+        sequence (any contiguous shape, taken flat).  Returns (Q, info)."""
+        if pixels.dtype != torch.uint8 or not pixels.is_contiguous():
+            raise ValueError("abs_quantize: a contiguous uint8 tensor")
+        if dst is None:
+            dst = torch.empty_like(pixels)
+        if info is None:
+            info = torch.zeros(ctypes.sizeof(AbsqInfo), dtype=torch.uint8, device=pixels.device)
+        st = load().roix_abs_quantize(self.h, _ptr(pixels), pixels.numel(), float(e_abs), _ptr(dst), _ptr(info),
+                                      _stream(stream))
+        _check(st, "roix_abs_quantize")
+        return dst, info
 
     def fused(self, vol: torch.Tensor, eb_mode: str, eb_value: float, crit: Criterion, out: Outputs,
               stream=None):

@@ -22,6 +22,13 @@ here.  Recipes:
   range, Otsu, 26-connectivity, largest component.
 * ``batch_volume(j)``: the ellipsoids128 recipe with 1..8 ellipsoids and side
   lengths U{64..512} per axis, eb drawn from {1e-3, 1e-4, 1e-5}.
+* ``pixel_section_u8(m)``: an 8-bit pixel section with the make-up of the
+  cylinder's region of interest scaled to 0..255 (the normalisation of Sec.
+  4.1.2, I_max = 1): matrix N(127.5, 7.65); runs of pore pixels
+  N(12.75, 2.55), lengths U{2..20}, over 5.6 % of the section; runs of
+  inclusion pixels N(242, 7.65), lengths U{4..14}, over 0.1 %.  The full
+  size, 514 688 000 pixels, is the number of span voxels of the 1024^3
+  cylinder's extraction.
 """
 from __future__ import annotations
 
@@ -173,6 +180,25 @@ def normal(shape, seed, mu=0.0, sd=1.0, threads=None):
     out = np.empty(shape, dtype=np.float32)
     lib.synth_normal_f32(_ptr(out), out.size, seed, mu, sd, _threads(threads))
     return out
+
+
+def pixel_section_u8(m, seed=4001, threads=None):
+    """Seeded 8-bit pixel section of m pixels (recipe in the module notes)."""
+    v = normal((m,), seed, 127.5, 7.65, threads)
+    rng = np.random.default_rng(seed)
+    for frac, lo, hi, mu, sd, s2 in ((0.056, 2, 20, 12.75, 2.55, seed + 1), (0.001, 4, 14, 242.0, 7.65, seed + 2)):
+        n_runs = int(frac * m / ((lo + hi) / 2))
+        if n_runs == 0 or m <= hi:
+            continue
+        starts = rng.integers(0, m - hi, n_runs)
+        lens = rng.integers(lo, hi + 1, n_runs)
+        offs = np.arange(int(lens.sum())) - np.repeat(np.cumsum(lens) - lens, lens)
+        idx = np.repeat(starts, lens) + offs
+        v[idx] = normal((idx.size,), s2, mu, sd, threads)
+    return np.clip(np.rint(v), 0, 255).astype(np.uint8)
+
+
+PIXEL_SECTION_FULL = 514_688_000
 
 
 # ------------------------------------------------------------------ workloads
