@@ -96,6 +96,12 @@ def _load():
         lib.oracle_background.restype = ci
         lib.oracle_abs_quantize.argtypes = [vp, u64, dbl, vp, vp]
         lib.oracle_abs_quantize.restype = ci
+        lib.oracle_huff_lengths.argtypes = [vp, vp]
+        lib.oracle_huff_lengths.restype = ci
+        lib.oracle_huff_encode.argtypes = [vp, u64, vp, vp, vp, u64, vp]
+        lib.oracle_huff_encode.restype = ci
+        lib.oracle_huff_decode.argtypes = [vp, vp, vp, u64, u64, vp]
+        lib.oracle_huff_decode.restype = ci
         lib.oracle_fused.argtypes = [vp, ci, i64, i64, i64, ci, dbl, ci, dbl, ci, ci, i64, vp, i64, vp, i64, vp,
                                      i64, vp, i64, ctypes.POINTER(FusedInfo)]
         lib.oracle_fused.restype = ci
@@ -262,6 +268,42 @@ def abs_quantize(pixels, e_abs):
     n = np.zeros(1, np.uint64)
     st = _load().oracle_abs_quantize(_p(d) if d.size else None, d.size, float(e_abs), _p(q), _p(n))
     return st, q[: d.size].copy(), int(n[0])
+
+
+HUFF_BLOCK = 4096
+
+
+def huff_lengths(hist):
+    """Huffman code lengths (bits) for 256 byte counts; (status, uint8[256])."""
+    h = np.ascontiguousarray(hist, dtype=np.uint64)
+    ln = np.zeros(256, np.uint8)
+    st = _load().oracle_huff_lengths(_p(h), _p(ln))
+    return st, ln
+
+
+def huff_encode(data, cap_words=None):
+    """Canonical Huffman coding of a byte sequence in blocks of 4096 bytes.
+    Returns (status, lengths uint8[256], block offsets uint64[nblocks + 1]
+    in 32-bit words, payload uint32[words])."""
+    d = np.ascontiguousarray(data, dtype=np.uint8).reshape(-1)
+    nb = (d.size + HUFF_BLOCK - 1) // HUFF_BLOCK
+    cap = nb * HUFF_BLOCK if cap_words is None else cap_words  # 32 bits per byte at most
+    ln = np.zeros(256, np.uint8)
+    off = np.zeros(nb + 1, np.uint64)
+    pay = np.zeros(max(cap, 1), np.uint32)
+    tot = np.zeros(1, np.uint64)
+    st = _load().oracle_huff_encode(_p(d) if d.size else None, d.size, _p(ln), _p(off), _p(pay), cap, _p(tot))
+    return st, ln, off, pay[: min(int(tot[0]), cap)].copy()
+
+
+def huff_decode(lengths, block_off, payload, n):
+    """Inverse of huff_encode; (status, bytes)."""
+    ln = np.ascontiguousarray(lengths, dtype=np.uint8)
+    off = np.ascontiguousarray(block_off, dtype=np.uint64)
+    pay = np.ascontiguousarray(payload, dtype=np.uint32)
+    out = np.zeros(max(n, 1), np.uint8)
+    st = _load().oracle_huff_decode(_p(ln), _p(off), _p(pay) if pay.size else None, pay.size, n, _p(out))
+    return st, out[:n].copy()
 
 
 def fused(vol, eb_mode, eb_value, thr="otsu", fixed_value=0.0, connectivity=26, keep="largest", min_size=1,

@@ -45,6 +45,10 @@
  *                8-bit pixel sequence (Sec. 4.2.3, Steps 1-5): groups grown
  *                while the error intervals intersect, each written as the
  *                floor of its midpoint, clipped to 0..255
+ *   huffman      a lossless entropy stage for the packed stream (the Huffman
+ *                coding the paper lists among lossless coders, Sec. 1):
+ *                byte counts, Huffman code lengths, canonical codes, the
+ *                bytes coded in blocks of 4096, and the decoder
  *
  * Where the paper is silent or ambiguous this file takes these readings:
  * half-open spans [x_start, x_end) so that n_i = x_end - x_start; a span
@@ -785,6 +789,153 @@ int oracle_abs_quantize(const uint8_t* D, uint64_t m, double e_abs, uint8_t* Q, 
         ++groups;
     }
     *n_groups = groups;
+    return OR_OK;
+}
+
+/* ---- Huffman coding of a byte sequence ----
+ * Code lengths by Huffman's construction (1952) over the byte counts, with a
+ * fixed order for equal weights: the leaves sorted by (count, byte value)
+ * and the merged nodes, created in order of non-decreasing weight, form two
+ * queues; each step takes the two lightest heads, a leaf before a merged
+ * node of the same weight.  A single used byte gets length 1.  Lengths above
+ * 32 bits are refused (OR_ERANGE).  Canonical codes: within a length, codes
+ * increase with the byte value, and the first code of length L follows the
+ * last of length L - 1 shifted left (the assignment of RFC 1951, 3.2.2).
+ * Format: the input is cut into blocks of 4096 bytes; block b is written
+ * from 32-bit word block_off[b] of the payload, its codes one after another
+ * from the most significant bit of each word down, zero bits up to the next
+ * word; block_off[nblocks] is the payload length in words. */
+#define OR_HUFF_BLOCK 4096
+
+int oracle_huff_lengths(const uint64_t hist[256], uint8_t len[256]) {
+    int sym[256], ns = 0;
+    for (int i = 0; i < 256; ++i) {
+        len[i] = 0;
+        if (hist[i]) sym[ns++] = i;
+    }
+    if (ns == 0) return OR_OK;
+    if (ns == 1) {
+        len[sym[0]] = 1;
+        return OR_OK;
+    }
+    for (int i = 1; i < ns; ++i) /* insertion sort by (count, byte) */
+        for (int j = i; j > 0 && hist[sym[j]] < hist[sym[j - 1]]; --j) {
+            int t = sym[j];
+            sym[j] = sym[j - 1];
+            sym[j - 1] = t;
+        }
+    /* nodes 0..ns-1: the leaves in queue order; ns..2ns-2: merged nodes */
+    uint64_t w[511];
+    int parent[511];
+    for (int i = 0; i < ns; ++i) w[i] = hist[sym[i]];
+    int lq = 0, mq = ns, next = ns;
+    while (next < 2 * ns - 1) {
+        int pick[2];
+        for (int k = 0; k < 2; ++k) {
+            if (lq < ns && (mq >= next || w[lq] <= w[mq])) pick[k] = lq++;
+            else pick[k] = mq++;
+        }
+        w[next] = w[pick[0]] + w[pick[1]];
+        parent[pick[0]] = parent[pick[1]] = next;
+        ++next;
+    }
+    int depth[511];
+    depth[2 * ns - 2] = 0;
+    for (int i = 2 * ns - 3; i >= 0; --i) depth[i] = depth[parent[i]] + 1;
+    for (int i = 0; i < ns; ++i) {
+        if (depth[i] > 32) return OR_ERANGE;
+        len[sym[i]] = (uint8_t)depth[i];
+    }
+    return OR_OK;
+}
+
+static void huff_codes(const uint8_t len[256], uint32_t code[256]) {
+    uint32_t bl_count[34] = {0}, next_code[34] = {0};
+    for (int i = 0; i < 256; ++i) bl_count[len[i]]++;
+    bl_count[0] = 0;
+    uint64_t c = 0;
+    for (int bits = 1; bits <= 32; ++bits) {
+        c = (c + bl_count[bits - 1]) << 1;
+        next_code[bits] = (uint32_t)c;
+    }
+    for (int i = 0; i < 256; ++i) code[i] = len[i] ? next_code[len[i]]++ : 0u;
+}
+
+/* Encode: lengths from the counts of `in`, then the blocks.  block_off has
+ * nblocks + 1 entries.  OR_ETRUNC (and *total_words) when the payload does
+ * not fit cap_words. */
+int oracle_huff_encode(const uint8_t* in, uint64_t n, uint8_t len[256], uint64_t* block_off, uint32_t* payload,
+                       uint64_t cap_words, uint64_t* total_words) {
+    uint64_t hist[256] = {0};
+    for (uint64_t i = 0; i < n; ++i) hist[in[i]]++;
+    int st = oracle_huff_lengths(hist, len);
+    if (st != OR_OK) return st;
+    uint32_t code[256];
+    huff_codes(len, code);
+    const uint64_t nb = (n + OR_HUFF_BLOCK - 1) / OR_HUFF_BLOCK;
+    uint64_t word = 0;
+    for (uint64_t b = 0; b < nb; ++b) {
+        block_off[b] = word;
+        uint64_t bits = 0;
+        const uint64_t e = (b + 1) * OR_HUFF_BLOCK < n ? (b + 1) * OR_HUFF_BLOCK : n;
+        for (uint64_t i = b * OR_HUFF_BLOCK; i < e; ++i) bits += len[in[i]];
+        const uint64_t words = (bits + 31) / 32;
+        if (word + words <= cap_words) {
+            for (uint64_t k = 0; k < words; ++k) payload[word + k] = 0u;
+            uint64_t p = 0; /* bit position from the block's first bit, most significant first */
+            for (uint64_t i = b * OR_HUFF_BLOCK; i < e; ++i) {
+                const int L = len[in[i]];
+                for (int k = L - 1; k >= 0; --k, ++p)
+                    if ((code[in[i]] >> k) & 1u) payload[word + p / 32] |= 0x80000000u >> (p % 32);
+            }
+        }
+        word += words;
+    }
+    block_off[nb] = word;
+    *total_words = word;
+    return word > cap_words ? OR_ETRUNC : OR_OK;
+}
+
+/* Decode n bytes; OR_EINVAL on lengths that are no prefix code, offsets that
+ * decrease or pass the payload, or bits that match no code. */
+int oracle_huff_decode(const uint8_t len[256], const uint64_t* block_off, const uint32_t* payload,
+                       uint64_t payload_words, uint64_t n, uint8_t* out) {
+    uint32_t code[256];
+    double kraft = 0.0;
+    int used = 0;
+    for (int i = 0; i < 256; ++i)
+        if (len[i]) {
+            if (len[i] > 32) return OR_EINVAL;
+            kraft += ldexp(1.0, -len[i]);
+            ++used;
+        }
+    if (n > 0 && used == 0) return OR_EINVAL;
+    if (kraft > 1.0) return OR_EINVAL;
+    huff_codes(len, code);
+    const uint64_t nb = (n + OR_HUFF_BLOCK - 1) / OR_HUFF_BLOCK;
+    if (nb > 0 && block_off[0] != 0) return OR_EINVAL;
+    for (uint64_t b = 0; b < nb; ++b) {
+        if (block_off[b + 1] < block_off[b] || block_off[b + 1] > payload_words) return OR_EINVAL;
+        const uint64_t w0 = block_off[b], nbits = (block_off[b + 1] - w0) * 32;
+        uint64_t p = 0;
+        const uint64_t e = (b + 1) * OR_HUFF_BLOCK < n ? (b + 1) * OR_HUFF_BLOCK : n;
+        for (uint64_t i = b * OR_HUFF_BLOCK; i < e; ++i) {
+            uint32_t c = 0;
+            int L = 0, found = -1;
+            while (found < 0) {
+                if (L == 32 || p >= nbits) return OR_EINVAL;
+                c = (c << 1) | ((payload[w0 + p / 32] >> (31 - p % 32)) & 1u);
+                ++p;
+                ++L;
+                for (int s = 0; s < 256; ++s)
+                    if (len[s] == L && code[s] == c) {
+                        found = s;
+                        break;
+                    }
+            }
+            out[i] = (uint8_t)found;
+        }
+    }
     return OR_OK;
 }
 

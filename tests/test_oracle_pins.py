@@ -653,3 +653,125 @@ def test_abs_quantize_closed_forms():
     # empty input and a negative tolerance
     assert oracle.abs_quantize(np.zeros(0, np.uint8), 1)[2] == 0
     assert oracle.abs_quantize(d, -1.0)[0] == oracle.EINVAL
+
+
+def _huffman_cost(counts):
+    # optimal total code length of a prefix code: the sum of the merged
+    # weights of any Huffman construction (heap order is irrelevant to it)
+    import heapq
+    h = [int(c) for c in counts if c > 0]
+    if len(h) <= 1:
+        return sum(h)
+    heapq.heapify(h)
+    cost = 0
+    while len(h) > 1:
+        a, b = heapq.heappop(h), heapq.heappop(h)
+        cost += a + b
+        heapq.heappush(h, a + b)
+    return cost
+
+
+def _canonical_decode(lengths, block_off, payload, n):
+    # decoder written from the format definition: canonical codes by
+    # (length, byte), most significant bit first, blocks of 4096 bytes on
+    # fresh 32-bit words
+    items = sorted((int(l), s) for s, l in enumerate(lengths) if l)
+    table, code, prev = {}, 0, items[0][0] if items else 0
+    for i, (l, s) in enumerate(items):
+        if i:
+            code = (code + 1) << (l - prev)
+        prev = l
+        table[(l, code)] = s
+    out = []
+    for b in range(len(block_off) - 1):
+        bits = "".join(f"{int(w):032b}" for w in payload[int(block_off[b]): int(block_off[b + 1])])
+        p = 0
+        for _ in range(min(4096, n - 4096 * b)):
+            c, l = 0, 0
+            while (l, c) not in table:
+                c, l, p = (c << 1) | int(bits[p]), l + 1, p + 1
+            out.append(table[(l, c)])
+    return np.array(out, np.uint8)
+
+
+def test_huffman_hand_examples():
+    g = json.load(open(os.path.join(GOLDEN, "hand_huffman.json")))
+    for c in g["cases"]:
+        st, ln, off, pay = oracle.huff_encode(np.array(c["data"], np.uint8))
+        assert st == oracle.OK
+        assert {str(i): int(ln[i]) for i in range(256) if ln[i]} == c["lengths"], c
+        assert off.tolist() == c["block_off"] and pay.tolist() == c["payload"], c
+
+
+def test_huffman_lengths_optimal_and_complete():
+    rng = np.random.default_rng(98)
+    for trial in range(200):
+        k = int(rng.integers(2, 257))
+        counts = np.zeros(256, np.uint64)
+        syms = rng.choice(256, k, replace=False)
+        kind = trial % 3
+        if kind == 0:
+            counts[syms] = rng.integers(1, 1000, k)
+        elif kind == 1:
+            counts[syms] = (rng.pareto(1.2, k) * 100).astype(np.uint64) + 1
+        else:
+            counts[syms] = rng.integers(1, 4, k)  # many ties
+        st, ln = oracle.huff_lengths(counts)
+        assert st == oracle.OK
+        used = counts > 0
+        assert np.all((ln > 0) == used)
+        kraft = sum(2.0 ** -int(l) for l in ln[used])
+        assert kraft == 1.0  # a complete prefix code
+        assert int((counts.astype(object) * ln.astype(object)).sum()) == _huffman_cost(counts)
+
+
+def test_huffman_closed_forms():
+    st, ln = oracle.huff_lengths(np.full(256, 5, np.uint64))
+    assert np.all(ln == 8)                       # uniform over 256 bytes: 8 bits
+    c = np.zeros(256, np.uint64)
+    c[[10, 20, 30, 40, 50]] = [16, 8, 4, 2, 2]   # dyadic: lengths -log2(p)
+    st, ln = oracle.huff_lengths(c)
+    assert [int(ln[i]) for i in (10, 20, 30, 40, 50)] == [1, 2, 3, 4, 4]
+    c = np.zeros(256, np.uint64)
+    c[200] = 9
+    assert oracle.huff_lengths(c)[1][200] == 1    # one used byte: one bit
+    # Fibonacci counts force a depth beyond 32 bits: refused
+    fib = [1, 1]
+    while len(fib) < 40:
+        fib.append(fib[-1] + fib[-2])
+    c = np.zeros(256, np.uint64)
+    c[:40] = fib
+    assert oracle.huff_lengths(c)[0] == oracle.ERANGE
+
+
+def test_huffman_round_trip_and_format():
+    rng = np.random.default_rng(99)
+    for n in (0, 1, 5, 4095, 4096, 4097, 20000):
+        for kind in range(3):
+            if kind == 0:
+                d = rng.integers(0, 256, n).astype(np.uint8)
+            elif kind == 1:
+                d = np.clip(np.round(rng.normal(100, 3, n)), 0, 255).astype(np.uint8)
+            else:
+                d = np.full(n, 42, np.uint8)
+            st, ln, off, pay = oracle.huff_encode(d)
+            assert st == oracle.OK and len(off) == (n + 4095) // 4096 + 1
+            st, back = oracle.huff_decode(ln, off, pay, n)
+            assert st == oracle.OK and np.array_equal(back, d)
+            if 0 < n <= 4097:
+                assert np.array_equal(_canonical_decode(ln, off, pay, n), d)
+            h = np.bincount(d, minlength=256)
+            bits = int((h.astype(np.int64) * ln.astype(np.int64)).sum())
+            assert int(off[-1]) * 32 - bits < 32 * max(len(off) - 1, 1)  # padding below a word per block
+    # a payload too small: the full size is still reported
+    d = rng.integers(0, 256, 10000).astype(np.uint8)
+    st, ln, off, pay = oracle.huff_encode(d, cap_words=10)
+    assert st == oracle.ETRUNC and int(off[-1]) > 10
+    # decoder rejects tables that are no prefix code and offsets past the payload
+    st, ln, off, pay = oracle.huff_encode(d)
+    bad = ln.copy()
+    bad[bad > 0] = 1
+    assert oracle.huff_decode(bad, off, pay, d.size)[0] == oracle.EINVAL
+    off2 = off.copy()
+    off2[-1] += 5
+    assert oracle.huff_decode(ln, off2, pay, d.size)[0] == oracle.EINVAL
