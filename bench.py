@@ -333,6 +333,103 @@ def bench_absq(args):
     ctx.close()
 
 
+def bench_huffman(args):
+    """The lossless Huffman stage on the benchmark volume's code stream:
+    encode and decode GB/s and the compression ratios it gives the ROI
+    representation (volume bytes over row table + coded stream + outliers),
+    and on the paper quantiser's output for the synthetic pixel section."""
+    import torch
+
+    import synth
+    from paper_2602_15917_amd import roix
+    dev = "cuda:0"
+    w = synth.cylinder1024(n=args.n)
+    x = torch.from_numpy(w.volume).to(dev)
+    del w.volume
+    crit = roix.Criterion(w.criterion.thr, 0.0, w.criterion.connectivity, w.criterion.keep, w.criterion.min_size)
+    dims = roix.dims_of(x)
+    ctx = roix.Context(0, roix.scratch_bytes(dims, roix.F32, crit))
+    b = roix.bounds(dims, roix.F32, crit)
+    out = roix.Outputs(dev, b["rows"], b["stream_bytes"], 1 << 22, 1 << 22)
+    ctx.fused(x, w.eb_mode, w.eb_value, crit, out)
+    torch.cuda.synchronize()
+    vol_bytes = x.numel() * 4
+    del x
+    e = out.collect()["einfo"]
+    q = out.collect()["qinfo"]
+    n = int(e.n_codes) * (int(q.width_bits) // 8)
+    s = out.stream[:n]
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            r = fn()
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            r = fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / args.steps, r
+
+    ms_enc, (ln, off, pay, info) = timed(lambda: ctx.huff_encode(s, stream=stream))
+    i = roix.huff_info(info)
+    assert i.status == 0
+    dst = torch.empty(n, dtype=torch.uint8, device=dev)
+    ms_dec, (back, dinfo) = timed(lambda: ctx.huff_decode(ln, off, pay, i.payload_words, n, dst, stream))
+    assert roix.huff_info(dinfo).status == 0 and torch.equal(back, s)
+    roi_plain = 32 * int(e.n_rows) + n + 4 * int(e.n_outliers)
+    roi_huff = 32 * int(e.n_rows) + int(i.compressed_bytes) + 4 * int(e.n_outliers)
+    # the paper quantiser's output on the synthetic pixel section, E = 2
+    m = synth.PIXEL_SECTION_FULL if args.n == 1024 else int(e.n_codes)
+    px = torch.from_numpy(synth.pixel_section_u8(m)).to(dev)
+    qx, _ = ctx_absq(roix, px, 2.0)
+    _, _, _, qinfo = ctx.huff_encode(qx)
+    torch.cuda.synchronize()
+    qi = roix.huff_info(qinfo)
+    cpu = None
+    if args.cpu_planes != 0:
+        import oracle
+        k = min(n, 64 << 20)
+        sample = s[:k].cpu().numpy()
+        t0 = time.time()
+        oracle.huff_encode(sample)
+        dt = time.time() - t0
+        cpu = {"value": round(k / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"the first {k} bytes of the same stream, single-threaded C oracle, {dt:.1f} s"}
+    line = {
+        "metric": "Huffman encode GB/s of the packed code stream (input bytes)",
+        "value": round(n / (ms_enc * 1e-3) / 1e9, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_enc, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"code stream of the {w.name} extraction", "stream_bytes": n,
+                   "code_bits": int(q.width_bits)},
+        "roofline": {"bound": "hbm", "kernel": "huff_encode (all passes)",
+                     "achieved": round((n + 4 * int(i.payload_words)) / (ms_enc * 1e-3) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round((n + 4 * int(i.payload_words)) / (ms_enc * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None, "alg_bytes_per_launch": n + 4 * int(i.payload_words)},
+        "decode": {"ms": round(ms_dec, 4), "GBps_out": round(n / (ms_dec * 1e-3) / 1e9, 2)},
+        "compression": {"stream_ratio": round(n / int(i.compressed_bytes), 4), "max_code_bits": int(i.max_len),
+                        "roi_ratio_plain": round(vol_bytes / roi_plain, 3),
+                        "roi_ratio_huffman": round(vol_bytes / roi_huff, 3),
+                        "pixel_section_e2_ratio": round(m / int(qi.compressed_bytes), 3)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+    ctx.close()
+
+
+def ctx_absq(roix, px, e):
+    c = roix.Context(0, roix.abs_quantize_scratch_bytes(px.numel()))
+    qx, info = c.abs_quantize(px, e)
+    import torch
+    torch.cuda.synchronize()
+    c.close()
+    return qx, info
+
+
 def bench_batched(args):
     """64 float32 volumes, sides U{64..512} per axis, 1-8 ellipsoids, eb from
     {1e-3, 1e-4, 1e-5}: one batched graph launch against the same volumes
@@ -583,12 +680,13 @@ def main():
                     help="also run a plain device copy of 1 GiB (the counter calibration for traffic)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL_STATS_CSV"),
                     help="summarise rocprofv3 counter runs of this script and exit")
-    ap.add_argument("--workload", choices=["plain", "batched", "served", "decode", "background", "absq"], default="plain",
+    ap.add_argument("--workload", choices=["plain", "batched", "served", "decode", "background", "absq", "huffman"], default="plain",
                     help="plain: the 1024^3 volume (default); batched: 64 uneven volumes in one graph launch; "
                          "served: open-loop slab-stream trace with p50/p99 latency; decode: the reverse "
                          "process of the 1024^3 volume's extraction; background: subtraction of a "
                          "calibration plane or volume, then the path on the result; absq: the paper's "
-                         "absolute error-bounded quantisation of an 8-bit pixel section")
+                         "absolute error-bounded quantisation of an 8-bit pixel section; huffman: the "
+                         "lossless stage on the code stream, with compression ratios")
     ap.add_argument("--absq-e", type=float, default=2.0, help="tolerance of the absq workload")
     ap.add_argument("--served-streams", type=int, default=4, help="uint16 2048x2048 streams of the served trace")
     ap.add_argument("--served-nz", type=int, default=256, help="planes per served stream (slabs of 32)")
@@ -611,6 +709,8 @@ def main():
         return bench_background(args)
     if args.workload == "absq":
         return bench_absq(args)
+    if args.workload == "huffman":
+        return bench_huffman(args)
     if args.workload == "decode":
         return bench_decode(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

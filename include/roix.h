@@ -355,6 +355,57 @@ size_t roix_abs_quantize_scratch_bytes(int64_t m);
 roix_status roix_abs_quantize(roix_ctx* ctx, const uint8_t* d_pixels, int64_t m, double e_abs, uint8_t* d_q,
                               roix_absq_info* d_info, void* stream);
 
+/* Lossless Huffman stage for a byte sequence (the packed code stream, or the
+ * output of roix_abs_quantize): Huffman coding, which Sec. 1 lists among the
+ * lossless coders a ROI representation can be handed to.
+ * Code lengths follow Huffman's construction over the 256 byte counts, with
+ * equal weights ordered by (count, byte value) for leaves and by creation
+ * for merged nodes, a leaf first on a tie; a single used byte gets length 1.
+ * Codes are canonical (within a length increasing with the byte value; the
+ * first code of a length follows the last of the length before, shifted
+ * left).  Format: blocks of 4096 input bytes; block b starts at 32-bit word
+ * block_off[b] of the payload, its codes written one after another from the
+ * most significant bit of each word down, zero bits to the end of its last
+ * word; block_off[nblocks] is the payload length in words.
+ * The compressed form is lengths (256 bytes) + block_off (8 bytes per
+ * block + 8) + payload (4 bytes per word): info.compressed_bytes.
+ *   d_in          n bytes, 16-byte aligned
+ *   d_lengths     out: 256 code lengths (0 = byte unused)
+ *   d_block_off   out: nblocks + 1 offsets, nblocks = ceil(n / 4096)
+ *   d_payload     out: payload_cap_words words; at most 32 bits per input
+ *                 byte, so 4096 words per block always suffice
+ *   d_info        device: status, max_len, n, n_blocks, payload_words,
+ *                 compressed_bytes
+ * info.status: ROIX_ERANGE when a code length would exceed 32 bits (counts
+ * growing like the Fibonacci numbers over more than 33 bytes; the payload is
+ * then unspecified), ROIX_ETRUNC when the payload exceeds payload_cap_words
+ * (the offsets and sizes are still complete; blocks that do not fit are not
+ * written).  The context's arena holds 4 KB of state while the call runs.
+ * Errors: ROIX_EINVAL (NULL or misaligned buffers, n outside 0..2^40,
+ * negative capacity), ROIX_ENOMEM (arena too small), ROIX_EDEVICE. */
+typedef struct {
+    int32_t status;
+    int32_t max_len;
+    uint64_t n;
+    uint64_t n_blocks;
+    uint64_t payload_words;
+    uint64_t compressed_bytes;
+    uint64_t pad[3];
+} roix_huff_info; /* 64 bytes */
+roix_status roix_huff_encode(roix_ctx* ctx, const uint8_t* d_in, int64_t n, uint8_t* d_lengths,
+                             uint64_t* d_block_off, uint32_t* d_payload, int64_t payload_cap_words,
+                             roix_huff_info* d_info, void* stream);
+
+/* Decode n bytes from the format of roix_huff_encode into d_out (16-byte
+ * aligned).  info.status is ROIX_EINVAL when the lengths are no prefix code
+ * (a length above 32, Kraft sum above 1, none used for n > 0), the offsets
+ * do not start at 0, decrease or pass payload_words, or a block's bits end
+ * or match no code before its bytes are complete; d_out is then
+ * unspecified.  One lane decodes a block.  Errors as roix_huff_encode. */
+roix_status roix_huff_decode(roix_ctx* ctx, const uint8_t* d_lengths, const uint64_t* d_block_off,
+                             const uint32_t* d_payload, int64_t payload_words, int64_t n, uint8_t* d_out,
+                             roix_huff_info* d_info, void* stream);
+
 /* One volume of a batch: input, shape, bound, criterion and the caller's
  * output buffers (as for roix_fused). */
 typedef struct {

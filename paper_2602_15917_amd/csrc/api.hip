@@ -31,7 +31,7 @@ void timer_end(Timer* t, int stage, hipStream_t s) {
 
 static const char* kStageNames[ST_COUNT] = {
     "init", "range", "resolve", "quantize", "quant_hist", "quant_range16", "otsu", "mask_runs", "scan", "runs_write",
-    "union", "flatten", "comp_stats", "keep", "spans", "emit", "emit_rows", "voxel_out", "finalize", "decode_index", "decode", "background", "abs_quantize"};
+    "union", "flatten", "comp_stats", "keep", "spans", "emit", "emit_rows", "voxel_out", "finalize", "decode_index", "decode", "background", "abs_quantize", "huffman"};
 
 }  // namespace roix
 
@@ -286,7 +286,8 @@ size_t roix_sizeof(const char* t) {
                      {"roix_criterion", sizeof(roix_criterion)},       {"roix_eb", sizeof(roix_eb)},
                      {"roix_dims", sizeof(roix_dims)},                 {"roix_volume_desc", sizeof(roix_volume_desc)},
                      {"roix_req_result", sizeof(roix_req_result)},     {"roix_server_stats_t", sizeof(roix_server_stats_t)},
-                     {"roix_decode_info", sizeof(roix_decode_info)},   {"roix_absq_info", sizeof(roix_absq_info)}};
+                     {"roix_decode_info", sizeof(roix_decode_info)},   {"roix_absq_info", sizeof(roix_absq_info)},
+                     {"roix_huff_info", sizeof(roix_huff_info)}};
     for (const auto& e : tab)
         if (strcmp(e.n, t) == 0) return e.s;
     return 0;
@@ -538,6 +539,34 @@ roix_status roix_abs_quantize(roix_ctx* ctx, const uint8_t* d_pixels, int64_t m,
     const double ef = e_abs >= 1024.0 ? 1024.0 : floor(e_abs);
     const uint32_t K = 2.0 * ef >= 255.0 ? 255u : (uint32_t)(2.0 * ef);
     ROIX_TRY(launch_absq(lctx(ctx, stream), d_pixels, m, K, d_q, ctx->arena, d_info));
+    return ROIX_OK;
+}
+
+static bool huff_n_ok(int64_t n) { return n >= 0 && n <= ((int64_t)1 << 40); }
+
+roix_status roix_huff_encode(roix_ctx* ctx, const uint8_t* d_in, int64_t n, uint8_t* d_lengths,
+                             uint64_t* d_block_off, uint32_t* d_payload, int64_t payload_cap_words,
+                             roix_huff_info* d_info, void* stream) {
+    if (!ctx || !d_lengths || !d_block_off || !d_info || !huff_n_ok(n) || payload_cap_words < 0) return ROIX_EINVAL;
+    if (!aligned(d_block_off, 8) || !aligned(d_info, 8)) return ROIX_EINVAL;
+    if (n > 0 && (!d_in || !aligned(d_in, 16))) return ROIX_EINVAL;
+    if (payload_cap_words > 0 && (!d_payload || !aligned(d_payload, 4))) return ROIX_EINVAL;
+    if (ctx->arena_bytes < huff_scratch_bytes()) return ROIX_ENOMEM;
+    ROIX_TRY(launch_huff_encode(lctx(ctx, stream), d_in, n, d_lengths, (unsigned long long*)d_block_off, d_payload,
+                                payload_cap_words, ctx->arena, d_info));
+    return ROIX_OK;
+}
+
+roix_status roix_huff_decode(roix_ctx* ctx, const uint8_t* d_lengths, const uint64_t* d_block_off,
+                             const uint32_t* d_payload, int64_t payload_words, int64_t n, uint8_t* d_out,
+                             roix_huff_info* d_info, void* stream) {
+    if (!ctx || !d_lengths || !d_block_off || !d_info || !huff_n_ok(n) || payload_words < 0) return ROIX_EINVAL;
+    if (!aligned(d_block_off, 8) || !aligned(d_info, 8)) return ROIX_EINVAL;
+    if (n > 0 && (!d_out || !aligned(d_out, 16))) return ROIX_EINVAL;
+    if (payload_words > 0 && (!d_payload || !aligned(d_payload, 4))) return ROIX_EINVAL;
+    if (ctx->arena_bytes < huff_scratch_bytes()) return ROIX_ENOMEM;
+    ROIX_TRY(launch_huff_decode(lctx(ctx, stream), d_lengths, (const unsigned long long*)d_block_off, d_payload,
+                                payload_words, n, d_out, ctx->arena, d_info));
     return ROIX_OK;
 }
 

@@ -230,6 +230,7 @@ enum Stage {
     ST_DECODE,
     ST_BACKGROUND,
     ST_ABSQ,
+    ST_HUFF,
     ST_COUNT
 };
 
@@ -311,6 +312,13 @@ hipError_t launch_decode(const LaunchCtx& lc, const roix_row* rows, uint64_t row
 hipError_t launch_background(const LaunchCtx& lc, const void* in, roix_dtype dt, const float* bg, bool full,
                              const Geom& g, int op, float* out);
 size_t absq_scratch_bytes(int64_t m);
+size_t huff_scratch_bytes();
+hipError_t launch_huff_encode(const LaunchCtx& lc, const uint8_t* in, int64_t n, uint8_t* lengths,
+                              unsigned long long* block_off, uint32_t* payload, int64_t cap_words, void* scratch,
+                              roix_huff_info* info);
+hipError_t launch_huff_decode(const LaunchCtx& lc, const uint8_t* lengths, const unsigned long long* block_off,
+                              const uint32_t* payload, int64_t payload_words, int64_t n, uint8_t* out,
+                              void* scratch, roix_huff_info* info);
 hipError_t launch_absq(const LaunchCtx& lc, const uint8_t* D, int64_t m, uint32_t K, uint8_t* Q, void* scratch,
                        roix_absq_info* info);
 hipError_t launch_flatten(const LaunchCtx& lc, const Layout& L);

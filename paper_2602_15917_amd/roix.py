@@ -139,13 +139,16 @@ def load():
     lib.roix_decode.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp, vp, Dims, ctypes.c_float, vp, vp, vp]
     lib.roix_background.argtypes = [vp, vp, ci, Dims, vp, i64, ci, vp, vp]
     lib.roix_abs_quantize.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp, vp]
+    lib.roix_huff_encode.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, vp]
+    lib.roix_huff_decode.argtypes = [vp, vp, vp, vp, i64, i64, vp, vp, vp]
     lib.roix_abs_quantize_scratch_bytes.argtypes = [i64]
     lib.roix_abs_quantize_scratch_bytes.restype = sz
     for f in ("roix_ctx_create", "roix_ctx_destroy", "roix_bounds", "roix_quantize", "roix_segment",
               "roix_extract", "roix_fused", "roix_ctx_set_timing", "roix_ctx_read_timing", "roix_fused_batch",
               "roix_ctx_set_param", "roix_ctx_get_param", "roix_server_create", "roix_server_destroy",
               "roix_volume_open", "roix_slab_submit", "roix_volume_close", "roix_volume_abort", "roix_wait",
-              "roix_server_stats", "roix_decode", "roix_background", "roix_abs_quantize"):
+              "roix_server_stats", "roix_decode", "roix_background", "roix_abs_quantize",
+              "roix_huff_encode", "roix_huff_decode"):
         getattr(lib, f).restype = ci
     _lib = lib
     return lib
@@ -222,6 +225,10 @@ def absq_info(info: torch.Tensor) -> "AbsqInfo":
     return _info(info, AbsqInfo)
 
 
+def huff_info(info: torch.Tensor) -> "HuffInfo":
+    return _info(info, HuffInfo)
+
+
 def abs_quantize_scratch_bytes(m: int) -> int:
     return int(load().roix_abs_quantize_scratch_bytes(int(m)))
 
@@ -272,6 +279,15 @@ class Outputs:
 class DecodeInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("pad", ctypes.c_int32), ("n_rows", ctypes.c_uint64),
                 ("n_codes", ctypes.c_uint64), ("n_outliers", ctypes.c_uint64)]
+
+
+class HuffInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("max_len", ctypes.c_int32), ("n", ctypes.c_uint64),
+                ("n_blocks", ctypes.c_uint64), ("payload_words", ctypes.c_uint64),
+                ("compressed_bytes", ctypes.c_uint64), ("pad", ctypes.c_uint64 * 3)]
+
+
+HUFF_BLOCK = 4096
 
 
 class AbsqInfo(ctypes.Structure):
@@ -370,6 +386,36 @@ class Context:
                                       _stream(stream))
         _check(st, "roix_abs_quantize")
         return dst, info
+
+    def huff_encode(self, data: torch.Tensor, payload_cap_words: int | None = None, stream=None):
+        """Enqueue the Huffman stage over a contiguous uint8 tensor (taken
+        flat).  Returns (lengths, block_off, payload, info); the payload holds
+        payload_cap_words words (default: enough for any input)."""
+        if data.dtype != torch.uint8 or not data.is_contiguous():
+            raise ValueError("huff_encode: a contiguous uint8 tensor")
+        n = data.numel()
+        nb = (n + HUFF_BLOCK - 1) // HUFF_BLOCK
+        cap = nb * HUFF_BLOCK if payload_cap_words is None else int(payload_cap_words)
+        dev = data.device
+        lengths = torch.zeros(256, dtype=torch.uint8, device=dev)
+        off = torch.zeros(nb + 1, dtype=torch.int64, device=dev)
+        payload = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        info = torch.zeros(ctypes.sizeof(HuffInfo), dtype=torch.uint8, device=dev)
+        st = load().roix_huff_encode(self.h, _ptr(data), n, _ptr(lengths), _ptr(off), _ptr(payload), cap,
+                                     _ptr(info), _stream(stream))
+        _check(st, "roix_huff_encode")
+        return lengths, off, payload, info
+
+    def huff_decode(self, lengths: torch.Tensor, off: torch.Tensor, payload: torch.Tensor, payload_words: int,
+                    n: int, dst: torch.Tensor | None = None, stream=None):
+        """Enqueue the decoder; returns (bytes, info)."""
+        if dst is None:
+            dst = torch.empty(max(n, 1), dtype=torch.uint8, device=lengths.device)
+        info = torch.zeros(ctypes.sizeof(HuffInfo), dtype=torch.uint8, device=lengths.device)
+        st = load().roix_huff_decode(self.h, _ptr(lengths), _ptr(off), _ptr(payload), int(payload_words), int(n),
+                                     _ptr(dst), _ptr(info), _stream(stream))
+        _check(st, "roix_huff_decode")
+        return dst[:n], info
 
     def fused(self, vol: torch.Tensor, eb_mode: str, eb_value: float, crit: Criterion, out: Outputs,
               stream=None):
