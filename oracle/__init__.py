@@ -103,7 +103,7 @@ def _load():
         lib.oracle_huff_decode.argtypes = [vp, vp, vp, u64, u64, vp]
         lib.oracle_huff_decode.restype = ci
         lib.oracle_fused.argtypes = [vp, ci, i64, i64, i64, ci, dbl, ci, dbl, ci, ci, i64, vp, i64, vp, i64, vp,
-                                     i64, vp, i64, ctypes.POINTER(FusedInfo)]
+                                     i64, vp, i64, ctypes.POINTER(FusedInfo), vp]
         lib.oracle_fused.restype = ci
         lib.oracle_sizes.argtypes = [vp]
         lib.oracle_sizes.restype = None
@@ -178,7 +178,8 @@ def multi_otsu(hist, classes):
     return tuple(int(v) for v in t[: classes - 1]), int(flags)
 
 
-THR_MODES = {"otsu": 0, "fixed": 1, "multi3": 2, "multi4": 3}
+THR_MODES = {"otsu": 0, "fixed": 1, "multi3": 2, "multi4": 3, "otsu_slice": 4}
+FLAG_SLICE = 8
 
 
 def q_thr_otsu(t_star, p):
@@ -325,15 +326,16 @@ def fused(vol, eb_mode, eb_value, thr="otsu", fixed_value=0.0, connectivity=26, 
     o = np.zeros(max(min(outliers_cap, N), 1), np.float32)
     info = FusedInfo()
     lib = _load()
+    sthr = np.full(nz, -1, np.int32)
     args = (_p(vol), _dt(vol), nx, ny, nz, 0 if eb_mode == "abs" else 1, eb_value, THR_MODES[thr],
             fixed_value, connectivity, 1 if keep == "largest" else 0, min_size)
     st = lib.oracle_fused(*args, _p(comps), min(comps_cap, len(comps)), _p(rows_a), rows_cap, _p(s),
-                          stream_cap_bytes, _p(o), len(o), ctypes.byref(info))
+                          stream_cap_bytes, _p(o), len(o), ctypes.byref(info), _p(sthr))
     if info.n_components > len(comps) and comps_cap >= info.n_components:
         comps = np.zeros(int(info.n_components), COMP_DTYPE)
         info = FusedInfo()
         st = lib.oracle_fused(*args, _p(comps), len(comps), _p(rows_a), rows_cap, _p(s), stream_cap_bytes,
-                              _p(o), len(o), ctypes.byref(info))
+                              _p(o), len(o), ctypes.byref(info), _p(sthr))
     nb = min(int(info.stream_bytes), stream_cap_bytes)
     return {
         "status": st,
@@ -344,4 +346,5 @@ def fused(vol, eb_mode, eb_value, thr="otsu", fixed_value=0.0, connectivity=26, 
         "stream": s[:nb].copy(),
         "outliers": o[:min(int(info.n_outliers), len(o))].copy(),
         "hist": np.frombuffer(bytes(info.hist), dtype=np.uint64).copy(),
+        "slice_thr": sthr,
     }

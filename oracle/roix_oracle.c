@@ -66,9 +66,9 @@
 enum { OR_OK = 0, OR_EINVAL = 1, OR_ERANGE = 2, OR_ENOMEM = 3, OR_ETRUNC = 4 };
 enum { OR_F32 = 0, OR_U16 = 1 };
 enum { OR_EB_ABS = 0, OR_EB_REL = 1 };
-enum { OR_THR_OTSU = 0, OR_THR_FIXED = 1, OR_THR_MULTI3 = 2, OR_THR_MULTI4 = 3 };
+enum { OR_THR_OTSU = 0, OR_THR_FIXED = 1, OR_THR_MULTI3 = 2, OR_THR_MULTI4 = 3, OR_THR_SLICE = 4 };
 enum { OR_KEEP_MIN_SIZE = 0, OR_KEEP_LARGEST = 1 };
-enum { OR_FLAG_DEGENERATE = 1u, OR_FLAG_EMPTY_ROI = 2u, OR_FLAG_FIXED = 4u };
+enum { OR_FLAG_DEGENERATE = 1u, OR_FLAG_EMPTY_ROI = 2u, OR_FLAG_FIXED = 4u, OR_FLAG_SLICE = 8u };
 
 typedef struct {
     int32_t status;
@@ -616,16 +616,21 @@ int oracle_decode(const or_row* rows, uint64_t n_rows, const uint8_t* stream, co
 /* The whole path on one volume, in the paper's order of dependence:
  * range -> error bound -> codes -> histogram -> threshold -> mask ->
  * components -> keep -> rows -> stream.  Buffers are caller-owned; a
- * buffer too small gives OR_ETRUNC with the full counts reported. */
+ * buffer too small gives OR_ETRUNC with the full counts reported.
+ * thr_mode OR_THR_SLICE thresholds each z-slice on its own, as the paper
+ * thresholds each 2-D image (Sec. 4.1.3): two-class Otsu on the slice's
+ * histogram over the volume's 256 bins, object = bins above the slice's
+ * split; slice_thr (nz entries, may be NULL) receives the splits. */
 int oracle_fused(const void* in, int dtype, int64_t nx, int64_t ny, int64_t nz, int eb_mode, double eb_value,
                  int thr_mode, double fixed_value, int conn, int keep_mode, int64_t min_size,
                  or_comp* comps, int64_t comps_cap, or_row* rows, int64_t rows_cap, uint8_t* stream,
-                 int64_t stream_cap_bytes, float* outliers, int64_t outliers_cap, or_fused_info* info) {
+                 int64_t stream_cap_bytes, float* outliers, int64_t outliers_cap, or_fused_info* info,
+                 int32_t* slice_thr) {
     memset(info, 0, sizeof *info);
     info->otsu_bin = -1;
     double t0 = now_s(), t1;
     if (!in || nx <= 0 || ny <= 0 || nz <= 0 || (dtype != OR_F32 && dtype != OR_U16) ||
-        (conn != 6 && conn != 26) || min_size < 1 || thr_mode < OR_THR_OTSU || thr_mode > OR_THR_MULTI4)
+        (conn != 6 && conn != 26) || min_size < 1 || thr_mode < OR_THR_OTSU || thr_mode > OR_THR_SLICE)
         return info->q.status = info->seg_status = info->ext_status = OR_EINVAL;
     uint64_t N = (uint64_t)nx * (uint64_t)ny * (uint64_t)nz;
     float xmin, xmax;
@@ -651,17 +656,41 @@ int oracle_fused(const void* in, int dtype, int64_t nx, int64_t ny, int64_t nz, 
         info->flags |= oracle_multi_otsu(info->hist, info->n_classes, info->thresholds);
         info->otsu_bin = info->thresholds[0];
         info->q_thr = oracle_q_thr_otsu(info->otsu_bin, p);
+    } else if (thr_mode == OR_THR_SLICE) {
+        info->flags |= OR_FLAG_SLICE;
+        info->n_classes = 2;
     } else {
         info->flags |= OR_FLAG_FIXED;
         info->q_thr = oracle_q_thr_fixed(fixed_value, p);
     }
+    int32_t* sthr = NULL;
+    if (thr_mode == OR_THR_SLICE) {
+        sthr = (int32_t*)malloc((size_t)nz * sizeof(int32_t));
+        if (!sthr) return info->seg_status = info->ext_status = OR_ENOMEM;
+        const uint64_t plane = (uint64_t)nx * (uint64_t)ny;
+        for (int64_t z = 0; z < nz; ++z) {
+            uint64_t h[256] = {0};
+            for (uint64_t v = (uint64_t)z * plane; v < (uint64_t)(z + 1) * plane; ++v)
+                h[bin_of(code_of(voxel(in, dtype, v), p), p)]++;
+            info->flags |= oracle_otsu(h, &sthr[z]);
+            if (slice_thr) slice_thr[z] = sthr[z];
+        }
+    }
     uint64_t* bits = (uint64_t*)calloc((size_t)((N + 63) / 64), sizeof(uint64_t));
-    if (!bits) return info->seg_status = info->ext_status = OR_ENOMEM;
-    for (uint64_t v = 0; v < N; ++v)
-        if (code_of(voxel(in, dtype, v), p) >= info->q_thr) {
+    if (!bits) {
+        free(sthr);
+        return info->seg_status = info->ext_status = OR_ENOMEM;
+    }
+    const uint64_t plane_n = (uint64_t)nx * (uint64_t)ny;
+    for (uint64_t v = 0; v < N; ++v) {
+        const int32_t q = code_of(voxel(in, dtype, v), p);
+        const int object = sthr ? (int32_t)bin_of(q, p) > sthr[v / plane_n] : q >= info->q_thr;
+        if (object) {
             bits[v >> 6] |= 1ull << (v & 63);
             info->n_mask++;
         }
+    }
+    free(sthr);
     t1 = now_s(); info->stage_seconds[2] = t1 - t0; t0 = t1;
 
     uint32_t* comp = (uint32_t*)calloc((size_t)N, sizeof(uint32_t));

@@ -775,3 +775,37 @@ def test_huffman_round_trip_and_format():
     off2 = off.copy()
     off2[-1] += 5
     assert oracle.huff_decode(ln, off2, pay, d.size)[0] == oracle.EINVAL
+
+
+def test_per_slice_threshold():
+    # per-slice Otsu (each z-slice thresholded on its own, as the paper does
+    # per 2-D image): identical slices give the global split on every slice
+    rng = np.random.default_rng(100)
+    img = np.where(rng.random((24, 40)) < 0.3, 0.8, 0.2) + rng.normal(0, 0.02, (24, 40))
+    vol = np.repeat(img[None], 5, axis=0).astype(np.float32)
+    g = oracle.fused(vol, "abs", 1e-3, "otsu", 0.0, 6, "min_size", 1)
+    s = oracle.fused(vol, "abs", 1e-3, "otsu_slice", 0.0, 6, "min_size", 1)
+    assert s["status"] == 0 and s["info"].flags & oracle.FLAG_SLICE
+    assert np.all(s["slice_thr"] == g["info"].otsu_bin)
+    assert s["info"].n_mask == g["info"].n_mask
+    # a brightness drift across z: one global split misses the dim slices,
+    # per-slice splits find the object in every slice
+    nz = 6
+    obj = np.zeros((nz, 24, 40), bool)
+    obj[:, 6:18, 10:30] = True
+    drift = np.linspace(0.0, 0.6, nz)[:, None, None]
+    vol = (np.where(obj, 0.35, 0.05) + drift + rng.normal(0, 0.01, obj.shape)).astype(np.float32)
+    s = oracle.fused(vol, "abs", 1e-3, "otsu_slice", 0.0, 6, "min_size", 1)
+    g = oracle.fused(vol, "abs", 1e-3, "otsu", 0.0, 6, "min_size", 1)
+    assert s["info"].n_mask == obj.sum() and g["info"].n_mask != obj.sum()
+    # each split is Otsu's on that slice's bins (bins from the oracle's codes)
+    p = s["params"]
+    _, codes, _, _ = oracle.quantize(vol, p)
+    bins = ((codes.astype(np.int64) - p.qmin) * 256) // p.K
+    for z in range(nz):
+        h = np.bincount(bins[z].ravel(), minlength=256).astype(np.uint64)
+        assert oracle.otsu(h)[0] == s["slice_thr"][z]
+    # a constant slice has no split: empty there, flagged
+    vol[2] = 0.5
+    s = oracle.fused(vol, "abs", 1e-3, "otsu_slice", 0.0, 6, "min_size", 1)
+    assert s["slice_thr"][2] == 255 and s["info"].flags & oracle.FLAG_DEGENERATE
