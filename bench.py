@@ -688,6 +688,8 @@ def main():
                          "absolute error-bounded quantisation of an 8-bit pixel section; huffman: the "
                          "lossless stage on the code stream, with compression ratios")
     ap.add_argument("--absq-e", type=float, default=2.0, help="tolerance of the absq workload")
+    ap.add_argument("--thr", choices=["otsu", "multi3", "multi4", "otsu_slice"], default=None,
+                    help="plain workload: threshold mode instead of the workload's two-class Otsu")
     ap.add_argument("--served-streams", type=int, default=4, help="uint16 2048x2048 streams of the served trace")
     ap.add_argument("--served-nz", type=int, default=256, help="planes per served stream (slabs of 32)")
     ap.add_argument("--served-cubes", type=int, default=16, help="float32 cubes interleaved in the served trace")
@@ -733,11 +735,14 @@ def main():
     N, s = vol.size, vol.itemsize
     log(f"generated {w.name} in {time.time() - t0:.1f}s")
     x = torch.from_numpy(vol).to(dev)
+    if args.thr:  # another threshold mode on the same workload
+        w.criterion.thr = args.thr
     crit = roix.Criterion(w.criterion.thr, 0.0, w.criterion.connectivity, w.criterion.keep, w.criterion.min_size)
     dims = roix.dims_of(x)
     ctx = roix.Context(0, roix.scratch_bytes(dims, roix.F32, crit))
     b = roix.bounds(dims, roix.F32, crit)
-    out = roix.Outputs(dev, b["rows"], b["stream_bytes"], b["outliers"], 1 << 22)
+    out = roix.Outputs(dev, b["rows"], b["stream_bytes"], b["outliers"], 1 << 22,
+                       nz_slices=nz if crit.thr == "otsu_slice" else 0)
     stream = torch.cuda.current_stream()
 
     def step():

@@ -92,11 +92,15 @@ typedef struct {
  * class k, the between-class variance up to a factor and a constant),
  * evaluated in binary64 in class order; tuples with an empty class are
  * skipped and the first maximum in lexicographic order wins; the object is
- * every class above the lowest threshold.  FIXED: voxels whose code is
+ * every class above the lowest threshold.  OTSU_SLICE: each z-slice is
+ * thresholded on its own, as the paper thresholds each 2-D image: two-class
+ * Otsu on the slice's histogram over the volume's 256 bins, object = bins
+ * above the slice's split (roix_fused and roix_fused_batch only; the splits
+ * go to roix_fused_out.d_slice_thr).  FIXED: voxels whose code is
  * above the code of `fixed_value` (input units) are object.  Connectivity 6
  * or 26.  LARGEST keeps the component with the most voxels (ties: smallest
  * label); MIN_SIZE keeps every component of at least `min_size` voxels. */
-typedef enum { ROIX_THR_OTSU = 0, ROIX_THR_FIXED = 1, ROIX_THR_MULTI_OTSU = 2 } roix_thr_mode;
+typedef enum { ROIX_THR_OTSU = 0, ROIX_THR_FIXED = 1, ROIX_THR_MULTI_OTSU = 2, ROIX_THR_OTSU_SLICE = 3 } roix_thr_mode;
 typedef enum { ROIX_KEEP_MIN_SIZE = 0, ROIX_KEEP_LARGEST = 1 } roix_keep_mode;
 typedef struct {
     int32_t thr;          /* roix_thr_mode */
@@ -129,6 +133,7 @@ typedef struct {
 #define ROIX_FLAG_DEGENERATE_HISTOGRAM 1u /* no Otsu split has two non-empty classes */
 #define ROIX_FLAG_EMPTY_ROI 2u            /* no component kept */
 #define ROIX_FLAG_FIXED_THRESHOLD 4u
+#define ROIX_FLAG_PER_SLICE 8u            /* OTSU_SLICE: per-slice splits (otsu_bin -1, q_thr 0) */
 
 /* hist[t] counts voxels with floor(256 (q - qmin) / K) == t.  otsu_bin = t*
  * (the lowest threshold for MULTI_OTSU; -1 for FIXED); the mask is
@@ -195,6 +200,7 @@ typedef struct {
     roix_quant_info* d_qinfo;
     roix_seg_info* d_sinfo;
     roix_extract_info* d_einfo;
+    int32_t* d_slice_thr; /* nz: each slice's Otsu split (255: none) for OTSU_SLICE; may be NULL */
 } roix_fused_out;
 
 typedef struct roix_ctx roix_ctx;

@@ -158,7 +158,9 @@ bool roix::eb_ok(roix_eb eb) {
 
 bool roix::crit_ok(const roix_criterion* c) {
     if (!c) return false;
-    if (c->thr != ROIX_THR_OTSU && c->thr != ROIX_THR_FIXED && c->thr != ROIX_THR_MULTI_OTSU) return false;
+    if (c->thr != ROIX_THR_OTSU && c->thr != ROIX_THR_FIXED && c->thr != ROIX_THR_MULTI_OTSU &&
+        c->thr != ROIX_THR_OTSU_SLICE)
+        return false;
     if (c->thr == ROIX_THR_MULTI_OTSU && c->classes != 0 && c->classes != 3 && c->classes != 4) return false;
     if (c->thr == ROIX_THR_FIXED && !(c->fixed_value >= -1.7976931348623157e308 && c->fixed_value <= 1.7976931348623157e308))
         return false;
@@ -237,7 +239,9 @@ roix_status roix::enqueue_fused(const LaunchCtx& lc, const Geom& g, Layout L, co
     const int kind = dtype == ROIX_F32 ? 0 : 1;
     // the fused range + 16-bit proxy pass needs the bound before the range
     // (absolute) and whole 16-byte vectors per row
-    const bool p16 = L.fine_slots && dtype == ROIX_F32 && eb.mode == ROIX_EB_ABS && aligned(d_in, 16);
+    // per-slice thresholds rewrite the 1-byte proxy: the two-pass flow
+    const bool per_slice = crit->thr == ROIX_THR_OTSU_SLICE;
+    const bool p16 = !per_slice && L.fine_slots && dtype == ROIX_F32 && eb.mode == ROIX_EB_ABS && aligned(d_in, 16);
     if (p16) {
         ROIX_TRY(launch_init(lc, L.S, eb.value));
         ROIX_TRY(launch_quant_range16(lc, (const float*)d_in, g, L));
@@ -249,7 +253,10 @@ roix_status roix::enqueue_fused(const LaunchCtx& lc, const Geom& g, Layout L, co
         ROIX_TRY(launch_resolve_dt(lc, L.S, dtype, eb, crit));
         ROIX_TRY(launch_quant_hist(lc, d_in, kind, g, L.S, L.proxy, fixed));
     }
-    ROIX_TRY(launch_threshold(lc, L.S, crit));
+    if (per_slice)
+        ROIX_TRY(launch_slice_otsu(lc, g, L.proxy, L.S, out->d_slice_thr));
+    else
+        ROIX_TRY(launch_threshold(lc, L.S, crit));
     ROIX_TRY(label_and_keep(lc, g, L, crit, out->d_comps, out->comps_cap));
     ROIX_TRY(launch_spans_from_runs(lc, g, L));
     ROIX_TRY(spans_and_emit(lc, g, L, d_in, dtype, out));
@@ -432,7 +439,8 @@ roix_status roix_segment(roix_ctx* ctx, const int32_t* d_codes, roix_dims dims, 
                          const roix_criterion* crit, uint8_t* d_keep, int64_t* d_labels, roix_component* d_comps,
                          int64_t comps_cap, roix_seg_info* d_sinfo, void* stream) {
     Geom g;
-    if (!ctx || !d_codes || !d_qinfo || !d_keep || !d_sinfo || !geom_of(dims, &g) || !crit_ok(crit))
+    if (!ctx || !d_codes || !d_qinfo || !d_keep || !d_sinfo || !geom_of(dims, &g) || !crit_ok(crit) ||
+        crit->thr == ROIX_THR_OTSU_SLICE)
         return ROIX_EINVAL;
     if (comps_cap < 0 || (comps_cap > 0 && (!d_comps || !aligned(d_comps, 8))) || !aligned(d_codes, 4) ||
         (d_labels && !aligned(d_labels, 8)))

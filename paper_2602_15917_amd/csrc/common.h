@@ -311,6 +311,7 @@ hipError_t launch_decode(const LaunchCtx& lc, const roix_row* rows, uint64_t row
                          uint4* desc, roix_decode_info* dinfo);
 hipError_t launch_background(const LaunchCtx& lc, const void* in, roix_dtype dt, const float* bg, bool full,
                              const Geom& g, int op, float* out);
+hipError_t launch_slice_otsu(const LaunchCtx& lc, const Geom& g, uint8_t* proxy, DevState* S, int32_t* slice_thr);
 size_t absq_scratch_bytes(int64_t m);
 size_t huff_scratch_bytes();
 hipError_t launch_huff_encode(const LaunchCtx& lc, const uint8_t* in, int64_t n, uint8_t* lengths,

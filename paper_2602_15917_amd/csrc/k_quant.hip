@@ -1034,6 +1034,153 @@ hipError_t launch_otsu(const LaunchCtx& lc, DevState* S, bool fixed) {
     return hipGetLastError();
 }
 
+// ------------------------------------------------------ per-slice Otsu
+
+// One workgroup per z-slice (grid-stride over slices): the histogram of the
+// slice's 1-byte proxy (bins over the volume's code range), two-class Otsu
+// on it with the same binary64 expression and first-maximum rule as k_otsu,
+// then the slice's proxy bytes rewritten as clamp(bin - t + 127, 0, 255): the
+// mask's single test "byte > 127" is then "bin > t" of each slice, and the
+// mask kernel runs unchanged.  16 copies of the LDS counters keep lanes that
+// hold the same bin from colliding.
+constexpr int kSliceCopies = 16;
+
+__device__ __forceinline__ uint32_t slice_remap(uint32_t w, int32_t ts) {
+    uint32_t o = 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int32_t b = (int32_t)((w >> (8 * k)) & 0xFFu) - ts + 127;
+        b = b < 0 ? 0 : (b > 255 ? 255 : b);
+        o |= (uint32_t)b << (8 * k);
+    }
+    return o;
+}
+
+__global__ __launch_bounds__(256) void k_slice_otsu(uint8_t* __restrict__ proxy, int64_t nx, int64_t ny, int64_t nz,
+                                                    int64_t P, DevState* S, int32_t* slice_thr) {
+    __shared__ uint32_t h[256 * kSliceCopies];
+    __shared__ unsigned long long sh_w[256], sh_s[256];
+    __shared__ double sh_v[256];
+    __shared__ int sh_t[256];
+    if (block_exit(S)) return;  // contains a barrier
+    const int t = threadIdx.x;
+    const uint32_t copy = (uint32_t)t % kSliceCopies;
+    // whole 16-byte vectors per row, then single bytes; a slice holds fewer
+    // than 2^32 vectors (ny * nx < 2^33 voxels)
+    const uint32_t vpr = (uint32_t)(nx / 16), nvec = (uint32_t)((nx / 16) * ny);
+    const int64_t tail = nx % 16;
+    const int ln = t % kWave;
+    const int64_t wv = t / kWave, nw = 256 / kWave;
+    if (blockIdx.x == 0 && t == 0) {
+        S->proxy_thr = 127;
+        S->q_thr = 0;
+        S->otsu_bin = -1;
+        S->n_classes = 2;
+        atomicOr(&S->flags, ROIX_FLAG_PER_SLICE);
+    }
+    for (int64_t z = blockIdx.x; z < nz; z += gridDim.x) {
+        uint8_t* base = proxy + z * ny * P;
+        for (int i = t; i < 256 * kSliceCopies; i += 256) h[i] = 0u;
+        __syncthreads();
+        // the slice's 16-byte vectors, flat (row = i / vpr), 8 loads in flight per lane
+        for (uint32_t i0 = (uint32_t)t; i0 < nvec; i0 += 8u * 256u) {
+            uint4 q[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t i = i0 + 256u * k;
+                const uint32_t r = i < nvec ? i / vpr : 0u, v = i < nvec ? i - r * vpr : 0u;
+                q[k] = *reinterpret_cast<const uint4*>(base + (int64_t)r * P + 16 * (int64_t)v);
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (i0 + 256u * k >= nvec) continue;
+                const uint32_t w[4] = {q[k].x, q[k].y, q[k].z, q[k].w};
+#pragma unroll
+                for (int b = 0; b < 16; ++b)
+                    atomicAdd(&h[((w[b >> 2] >> (8 * (b & 3))) & 0xFFu) * kSliceCopies + copy], 1u);
+            }
+        }
+        for (int64_t r = wv; r < ny && ln < tail; r += nw)
+            atomicAdd(&h[(uint32_t)base[r * P + 16 * vpr + ln] * kSliceCopies + copy], 1u);
+        __syncthreads();
+        unsigned long long hv = 0ull;
+#pragma unroll
+        for (int c = 0; c < kSliceCopies; ++c) hv += h[t * kSliceCopies + c];
+        sh_w[t] = hv;
+        sh_s[t] = (unsigned long long)t * hv;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {
+            const unsigned long long aw = t >= o ? sh_w[t - o] : 0ull, as = t >= o ? sh_s[t - o] : 0ull;
+            __syncthreads();
+            sh_w[t] += aw;
+            sh_s[t] += as;
+            __syncthreads();
+        }
+        const unsigned long long NT = sh_w[255], ST = sh_s[255];
+        const unsigned long long W0 = sh_w[t], S0 = sh_s[t], W1 = NT - W0;
+        double sv = -1.0;
+        if (t < 255 && W0 != 0ull && W1 != 0ull) {
+            double m0 = (double)S0 / (double)W0;
+            double m1 = (double)(ST - S0) / (double)W1;
+            double d = m0 - m1;
+            sv = (((double)W0 * (double)W1) * d) * d;
+        }
+        sh_v[t] = sv;
+        sh_t[t] = t;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (t < o) {
+                const double a = sh_v[t], b = sh_v[t + o];
+                const int ta = sh_t[t], tb = sh_t[t + o];
+                if (b > a || (b == a && tb < ta)) {
+                    sh_v[t] = b;
+                    sh_t[t] = tb;
+                }
+            }
+            __syncthreads();
+        }
+        const bool degenerate = sh_v[0] < 0.0;
+        const int32_t ts = degenerate ? 255 : sh_t[0];
+        if (t == 0) {
+            if (degenerate) atomicOr(&S->flags, ROIX_FLAG_DEGENERATE_HISTOGRAM);
+            if (slice_thr) slice_thr[z] = ts;
+        }
+        // the slice's bytes, shifted so that "> 127" is "> ts"
+        for (uint32_t i0 = (uint32_t)t; i0 < nvec; i0 += 8u * 256u) {
+            uint4 q[8];
+            uint4* pv[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t i = i0 + 256u * k;
+                const uint32_t r = i < nvec ? i / vpr : 0u, v = i < nvec ? i - r * vpr : 0u;
+                pv[k] = reinterpret_cast<uint4*>(base + (int64_t)r * P + 16 * (int64_t)v);
+                q[k] = *pv[k];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (i0 + 256u * k >= nvec) continue;
+                *pv[k] = make_uint4(slice_remap(q[k].x, ts), slice_remap(q[k].y, ts), slice_remap(q[k].z, ts),
+                                    slice_remap(q[k].w, ts));
+            }
+        }
+        for (int64_t r = wv; r < ny && ln < tail; r += nw) {
+            uint8_t* pb = base + r * P + 16 * vpr + ln;
+            const int32_t b = (int32_t)*pb - ts + 127;
+            *pb = (uint8_t)(b < 0 ? 0 : (b > 255 ? 255 : b));
+        }
+        __syncthreads();  // sh_* are reused by the next slice
+    }
+}
+
+hipError_t launch_slice_otsu(const LaunchCtx& lc, const Geom& g, uint8_t* proxy, DevState* S, int32_t* slice_thr) {
+    timer_begin(lc.timer, ST_OTSU, lc.stream);
+    const int64_t grid = g.nz < 8192 ? g.nz : 8192;
+    hipLaunchKernelGGL(k_slice_otsu, dim3((unsigned)grid), dim3(256), 0, lc.stream, proxy, g.nx, g.ny, g.nz, g.W * 64,
+                       S, slice_thr);
+    timer_end(lc.timer, ST_OTSU, lc.stream);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------ multi-level Otsu
 
 // Multi-level Otsu (Liao, Chen & Chung 2001) with K = 3 or 4 classes over

@@ -243,7 +243,8 @@ extern "C" {
 size_t roix_server_volume_bytes(const roix_server* s, roix_dims dims, roix_dtype dtype, roix_eb eb,
                                 const roix_criterion* crit) {
     Geom g;
-    if (!s || (dtype != ROIX_F32 && dtype != ROIX_U16) || !geom_of(dims, &g) || !eb_ok(eb) || !crit_ok(crit))
+    if (!s || (dtype != ROIX_F32 && dtype != ROIX_U16) || !geom_of(dims, &g) || !eb_ok(eb) || !crit_ok(crit) ||
+        crit->thr == ROIX_THR_OTSU_SLICE)
         return 0;
     return volume_bytes(g, dtype, incremental_of(eb, crit), s->runs_per_row);
 }
@@ -304,6 +305,7 @@ roix_status roix_server_destroy(roix_server* s) {
 roix_status roix_volume_open(roix_server* s, roix_dims dims, roix_dtype dtype, roix_eb eb,
                              const roix_criterion* crit, const roix_fused_out* final_out, int64_t* vol_id) {
     if (!s || !vol_id || !eb_ok(eb) || !crit_ok(crit) || !out_ok(final_out, true)) return ROIX_EINVAL;
+    if (crit->thr == ROIX_THR_OTSU_SLICE) return ROIX_EINVAL;  // slabs are thresholded as they arrive
     if (dtype != ROIX_F32 && dtype != ROIX_U16) return ROIX_EINVAL;
     Geom g;
     if (!geom_of(dims, &g)) return ROIX_EINVAL;

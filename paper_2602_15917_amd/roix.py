@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libroix.so")
 OK, EINVAL, ERANGE, ENOMEM, ETRUNC, EDEVICE, EBUSY, ESEQ = range(8)
 F32, U16 = 0, 1
 EB_ABS, EB_REL = 0, 1
-THR_OTSU, THR_FIXED, THR_MULTI_OTSU = 0, 1, 2
+THR_OTSU, THR_FIXED, THR_MULTI_OTSU, THR_OTSU_SLICE = 0, 1, 2, 3
+FLAG_PER_SLICE = 8
 BG_OPS = {"subtract": 0, "add": 1}
 KEEP_MIN_SIZE, KEEP_LARGEST = 0, 1
 FLAG_DEGENERATE_HISTOGRAM, FLAG_EMPTY_ROI, FLAG_FIXED_THRESHOLD = 1, 2, 4
@@ -67,7 +68,8 @@ class FusedOut(ctypes.Structure):
     _fields_ = [("d_rows", ctypes.c_void_p), ("rows_cap", ctypes.c_int64), ("d_stream", ctypes.c_void_p),
                 ("stream_cap_bytes", ctypes.c_int64), ("d_outliers", ctypes.c_void_p),
                 ("outliers_cap", ctypes.c_int64), ("d_comps", ctypes.c_void_p), ("comps_cap", ctypes.c_int64),
-                ("d_qinfo", ctypes.c_void_p), ("d_sinfo", ctypes.c_void_p), ("d_einfo", ctypes.c_void_p)]
+                ("d_qinfo", ctypes.c_void_p), ("d_sinfo", ctypes.c_void_p), ("d_einfo", ctypes.c_void_p),
+                ("d_slice_thr", ctypes.c_void_p)]
 
 
 class VolumeDesc(ctypes.Structure):
@@ -157,7 +159,7 @@ def load():
 @dataclass
 class Criterion:
     """ROI criterion (mirrors roix_criterion)."""
-    thr: str = "otsu"          # "otsu" | "fixed" | "multi3" | "multi4" (multi-level Otsu, 3 or 4 classes)
+    thr: str = "otsu"          # "otsu" | "fixed" | "multi3" | "multi4" (multi-level Otsu) | "otsu_slice"
     fixed_value: float = 0.0
     connectivity: int = 26     # 6 | 26
     keep: str = "largest"      # "largest" | "min_size"
@@ -170,7 +172,7 @@ class Criterion:
 
 
 _THR_CODES = {"otsu": (THR_OTSU, 0), "fixed": (THR_FIXED, 0), "multi3": (THR_MULTI_OTSU, 3),
-              "multi4": (THR_MULTI_OTSU, 4)}
+              "multi4": (THR_MULTI_OTSU, 4), "otsu_slice": (THR_OTSU_SLICE, 0)}
 
 
 def dims_of(vol: torch.Tensor) -> Dims:
@@ -245,7 +247,7 @@ def _info(buf: torch.Tensor, cls):
 class Outputs:
     """Caller-owned output buffers of extract/fused (device tensors)."""
 
-    def __init__(self, device, rows_cap, stream_cap_bytes, outliers_cap, comps_cap):
+    def __init__(self, device, rows_cap, stream_cap_bytes, outliers_cap, comps_cap, nz_slices=0):
         self.rows = torch.empty(max(rows_cap, 1) * ROW_BYTES, dtype=torch.uint8, device=device)
         self.stream = torch.empty(max(stream_cap_bytes, 4), dtype=torch.uint8, device=device)
         self.outliers = torch.empty(max(outliers_cap, 1), dtype=torch.float32, device=device)
@@ -253,10 +255,13 @@ class Outputs:
         self.qinfo = torch.zeros(ctypes.sizeof(QuantInfo), dtype=torch.uint8, device=device)
         self.sinfo = torch.zeros(ctypes.sizeof(SegInfo), dtype=torch.uint8, device=device)
         self.einfo = torch.zeros(ctypes.sizeof(ExtractInfo), dtype=torch.uint8, device=device)
+        # per-slice thresholds (criterion "otsu_slice"): one int32 per z-slice
+        self.slice_thr = torch.full((nz_slices,), -1, dtype=torch.int32, device=device) if nz_slices else None
         self.caps = (rows_cap, stream_cap_bytes, outliers_cap, comps_cap)
         self.c = FusedOut(self.rows.data_ptr(), rows_cap, self.stream.data_ptr(), stream_cap_bytes,
                           self.outliers.data_ptr(), outliers_cap, self.comps.data_ptr(), comps_cap,
-                          self.qinfo.data_ptr(), self.sinfo.data_ptr(), self.einfo.data_ptr())
+                          self.qinfo.data_ptr(), self.sinfo.data_ptr(), self.einfo.data_ptr(),
+                          self.slice_thr.data_ptr() if nz_slices else None)
 
     def collect(self):
         """Host copies of the infos and the outputs trimmed to the counts
@@ -273,6 +278,7 @@ class Outputs:
             "stream": self.stream[:nb].cpu().numpy(),
             "outliers": self.outliers[:no].cpu().numpy(),
             "comps": self.comps[: nc * COMP_BYTES].cpu().numpy(),
+            "slice_thr": self.slice_thr.cpu().numpy() if self.slice_thr is not None else None,
         }
 
 

@@ -30,7 +30,7 @@ def default_caps(roix, vol, crit, comps_cap=None):
 def gpu_fused(ctx, roix, torch, vol, eb_mode, eb_value, crit, caps=None, device="cuda:0"):
     t = torch.from_numpy(np.ascontiguousarray(vol)).to(device)
     caps = caps or default_caps(roix, vol, crit)
-    out = roix.Outputs(device, *caps)
+    out = roix.Outputs(device, *caps, nz_slices=vol.shape[0] if crit.thr == "otsu_slice" else 0)
     ctx.fused(t, eb_mode, eb_value, crit, out)
     torch.cuda.synchronize()
     return out.collect()
@@ -73,6 +73,8 @@ def compare_fused(g, o, check_outputs=True):
     if p.status == 0 and s.status == 0:
         assert list(s.thresholds) == list(oi.thresholds), ("thresholds", list(s.thresholds), list(oi.thresholds))
         assert s.n_classes == oi.n_classes, ("n_classes", s.n_classes, oi.n_classes)
+        if g.get("slice_thr") is not None:
+            assert np.array_equal(g["slice_thr"], o["slice_thr"]), "per-slice splits"
     e = g["einfo"]
     assert e.status == oi.ext_status, ("einfo.status", e.status, oi.ext_status)
     for f in ("n_rows", "n_codes", "n_outliers", "stream_bytes"):

@@ -370,3 +370,60 @@ def test_multi_otsu_staged(env, thr):
     oi = f["info"]
     assert s.status == 0 and list(s.thresholds) == list(oi.thresholds) and s.n_classes == oi.n_classes
     assert (s.otsu_bin, s.q_thr, s.n_mask, s.n_components) == (oi.otsu_bin, oi.q_thr, oi.n_mask, oi.n_components)
+
+
+def drifting(shape, seed, span=0.6):
+    """A block object whose brightness, and the background's, rises along z."""
+    nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    obj = np.zeros(shape, bool)
+    obj[:, ny // 4: ny - ny // 4, nx // 4: nx - nx // 4] = True
+    drift = np.linspace(0.0, span, nz)[:, None, None]
+    return (np.where(obj, 0.35, 0.05) + drift + rng.normal(0, 0.01, shape)).astype(np.float32)
+
+
+@pytest.mark.parametrize("conn", [6, 26])
+def test_per_slice_otsu(env, conn):
+    # each z-slice thresholded on its own: the splits and every output
+    cases = [
+        ("drift", drifting((8, 24, 96), 41), "abs", 1e-3),
+        ("drift ragged rows", drifting((5, 19, 133), 42), "abs", 1e-4),
+        ("drift narrow rows", drifting((6, 9, 13), 43), "abs", 1e-3),
+        ("one slice", drifting((1, 40, 64), 44), "abs", 1e-3),
+        ("ellipsoids", synth.ellipsoids(130, 40, 9, 4300, n_ell=4, ax=(2.0, 20.0))[0], "abs", 1e-3),
+        ("rings u16", synth.rings2048(nxy=96, nz=5).volume, "rel", 1e-4),
+        ("cylinder", synth.cylinder1024(n=96).volume, "abs", 1e-4),
+    ]
+    vol = drifting((6, 20, 64), 45)
+    vol[3] = 0.5  # a constant slice: no split there
+    cases.append(("constant slice", vol, "abs", 1e-3))
+    for name, vol, ebm, ebv in cases:
+        for keep, ms in (("largest", 1), ("min_size", 4)):
+            c = synth.Criterion("otsu_slice", 0.0, conn, keep, ms)
+            g, o = run_case(env, f"per-slice {name}", vol, ebm, ebv, c)
+            assert g["sinfo"].flags & 8 and g["slice_thr"] is not None
+            assert np.array_equal(g["slice_thr"], o["slice_thr"])
+
+
+def test_per_slice_batched_and_rejected_forms(env):
+    ctx, roix, torch = env
+    # the batched form takes the per-slice criterion like the plain call
+    vols = [drifting((4 + k, 16, 48 + 16 * k), 50 + k) for k in range(3)]
+    crit = roix.Criterion("otsu_slice", 0.0, 26, "largest", 1)
+    items, outs = [], []
+    for v in vols:
+        out = roix.Outputs("cuda:0", *default_caps(roix, v, crit), nz_slices=v.shape[0])
+        items.append((torch.from_numpy(v).to("cuda:0"), "abs", 1e-3, crit, out))
+        outs.append(out)
+    log("[case] per-slice batched")
+    ctx.fused_batch(items)
+    torch.cuda.synchronize()
+    for v, out in zip(vols, outs):
+        o = oracle_fused(v, "abs", 1e-3, synth.Criterion("otsu_slice", 0.0, 26, "largest", 1))
+        compare_fused(out.collect(), o)
+    # the staged segmentation and the served form refuse it
+    t = torch.from_numpy(vols[0]).to("cuda:0")
+    codes, bits, qinfo = ctx.quantize(t, "abs", 1e-3)
+    with pytest.raises(roix.RoixError) as ei:
+        ctx.segment(codes, qinfo, crit, 1024)
+    assert ei.value.status == roix.EINVAL
