@@ -183,8 +183,9 @@ def bench_decode(args):
 def bench_background(args):
     """Background subtraction (M = I - B) of the benchmark volume put on a
     smooth calibration plane: GB/s of the subtraction with one plane for
-    every z and with a reference volume, and the whole path run on M after
-    the subtraction (one step = subtraction + fused path)."""
+    every z and with a reference volume; the whole path run on M after the
+    subtraction (one step = subtraction + fused path); and the fused path
+    with the subtraction folded in (roix_fused_background, same outputs)."""
     import torch
 
     import synth
@@ -243,9 +244,17 @@ def bench_background(args):
         ctx.background(x, plane, "subtract", m, stream)
         ctx.fused(m, w.eb_mode, w.eb_value, crit, out, stream)
     ms_step = timed(step)
-    _, st = kernel_ms(step)
     g = out.collect()
     assert g["qinfo"].status == 0 and g["sinfo"].status == 0 and g["einfo"].status == 0
+    sep = (g["rows"].tobytes(), g["stream"].tobytes(), g["outliers"].tobytes())
+
+    def step_fused():  # the subtraction folded into the path (M is not written)
+        ctx.fused_background(x, plane, w.eb_mode, w.eb_value, crit, out, m, stream)
+    ms_fused = timed(step_fused)
+    _, st = kernel_ms(step_fused)
+    g = out.collect()
+    assert g["einfo"].status == 0
+    assert (g["rows"].tobytes(), g["stream"].tobytes(), g["outliers"].tobytes()) == sep
     ach = bytes_plane / (k_plane * 1e-3) / 1e9
     line = {
         "metric": "background subtraction GB/s (float32 image in, float32 M = I - B out)",
@@ -263,6 +272,9 @@ def bench_background(args):
         "subtract_then_path": {"ms_per_step": round(ms_step, 4),
                                "voxels_per_s": round(N / (ms_step * 1e-3), 1),
                                "n_kept_voxels": int(g["sinfo"].n_kept_voxels)},
+        "fused_background_path": {"ms_per_step": round(ms_fused, 4),
+                                  "voxels_per_s": round(N / (ms_fused * 1e-3), 1),
+                                  "outputs_equal_subtract_then_path": True},
         "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in st.items() if v[1]},
     }
     print(json.dumps(line))

@@ -324,6 +324,29 @@ typedef enum { ROIX_BG_SUBTRACT = 0, ROIX_BG_ADD = 1 } roix_bg_op;
 roix_status roix_background(roix_ctx* ctx, const void* d_in, roix_dtype dtype, roix_dims dims, const float* d_bg,
                             int64_t bg_planes, roix_bg_op op, float* d_out, void* stream);
 
+/* The fused path of roix_fused on M = I - B (background subtraction,
+ * Sec. 4.1.1, then the whole path): the outputs are those of
+ * roix_background followed by roix_fused on its output, bit for bit.  With
+ * an absolute bound, rows of whole 64-voxel words and 16-byte aligned image
+ * and reference, the subtraction is folded into the passes that read the
+ * image (the range/code pass reads I and B; outlier values are gathered as
+ * I - B), so M is not written.  M goes to d_work only where a stage must read
+ * it: when the code range exceeds 2^15 codes (the 1-byte proxy flow) or when
+ * the code emit meets chunks of many short spans.  Any other case
+ * (a relative bound, other row lengths, OTSU_SLICE) subtracts into d_work
+ * first and runs roix_fused on it.
+ *   d_in      N float32 image
+ *   d_bg      float32 reference of bg_planes planes (1 or nz), as
+ *             roix_background
+ *   d_work    N float32, caller-owned workspace overlapping neither d_in
+ *             nor d_bg; its contents afterwards are unspecified
+ * Other arguments, outputs, arena use and errors as roix_fused; also
+ * ROIX_EINVAL for bg_planes not 1 or nz, a NULL reference or workspace, or
+ * overlapping buffers. */
+roix_status roix_fused_background(roix_ctx* ctx, const float* d_in, roix_dims dims, const float* d_bg,
+                                  int64_t bg_planes, roix_eb eb, const roix_criterion* crit,
+                                  const roix_fused_out* out, float* d_work, void* stream);
+
 /* Absolute error-bounded quantisation of an 8-bit pixel sequence, the
  * paper's own algorithm (Sec. 4.2.3, Steps 1-5): a group grows pixel by
  * pixel while the intervals [D - E, D + E] of its pixels intersect, and

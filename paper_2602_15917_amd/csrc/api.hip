@@ -217,11 +217,11 @@ static hipError_t label_and_keep(const LaunchCtx& lc, const Geom& g, const Layou
 }
 
 hipError_t roix::spans_and_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, const void* in, roix_dtype dt,
-                                 const roix_fused_out* out) {
+                                 const roix_fused_out* out, const BgRef* bg) {
     hipError_t e;
     if ((e = launch_scan_u64(lc, L.row_packed, L.row_packed, g.nrows, &L.S->span_total, L.scan_tmp)) != hipSuccess)
         return e;
-    return launch_emit(lc, g, L, in, dt, out);
+    return launch_emit(lc, g, L, in, dt, out, bg);
 }
 
 static void batch_release(BatchState& b) {
@@ -260,6 +260,35 @@ roix_status roix::enqueue_fused(const LaunchCtx& lc, const Geom& g, Layout L, co
     ROIX_TRY(label_and_keep(lc, g, L, crit, out->d_comps, out->comps_cap));
     ROIX_TRY(launch_spans_from_runs(lc, g, L));
     ROIX_TRY(spans_and_emit(lc, g, L, d_in, dtype, out));
+    ROIX_TRY(launch_finalize(lc, L.S, out->d_qinfo, out->d_sinfo, out->d_einfo, true));
+    return ROIX_OK;
+}
+
+// The fused path on M = I - B.  With the one-pass flow and the 16-bit proxy
+// (rows of whole 64-voxel words) the range/code pass reads I and B and the
+// row-table kernel gathers outlier values as I - B: M is never written.  M
+// goes to bg.work only where a stage must read it: when the range pass falls
+// back to the 1-byte proxy (K > 2^15), or when the proxy emit queued chunks
+// for the general kernel.  Any other case subtracts first and runs the path
+// on bg.work.
+roix_status roix::enqueue_fused_bg(const LaunchCtx& lc, const Geom& g, Layout L, const float* d_in, const BgRef& bg,
+                                    roix_eb eb, const roix_criterion* crit, const roix_fused_out* out) {
+    const bool fused = crit->thr != ROIX_THR_OTSU_SLICE && L.fine_slots && eb.mode == ROIX_EB_ABS &&
+                       aligned(d_in, 16) && aligned(bg.bg, 16) && g.W * 64 == g.nx;
+    if (!fused) {
+        ROIX_TRY(launch_background(lc, d_in, ROIX_F32, bg.bg, !bg.plane, g, ROIX_BG_SUBTRACT, bg.work));
+        return enqueue_fused(lc, g, L, bg.work, ROIX_F32, eb, crit, out);
+    }
+    const bool fixed = crit->thr == ROIX_THR_FIXED;
+    ROIX_TRY(launch_init(lc, L.S, eb.value));
+    ROIX_TRY(launch_quant_range16(lc, d_in, g, L, &bg));
+    ROIX_TRY(launch_resolve16(lc, L, eb, crit));
+    ROIX_TRY(launch_background_if(lc, d_in, bg, g, L.S, 1));
+    ROIX_TRY(launch_quant_hist(lc, bg.work, 0, g, L.S, L.proxy, fixed, true));  // only when K > 2^15
+    ROIX_TRY(launch_threshold(lc, L.S, crit));
+    ROIX_TRY(label_and_keep(lc, g, L, crit, out->d_comps, out->comps_cap));
+    ROIX_TRY(launch_spans_from_runs(lc, g, L));
+    ROIX_TRY(spans_and_emit(lc, g, L, d_in, ROIX_F32, out, &bg));
     ROIX_TRY(launch_finalize(lc, L.S, out->d_qinfo, out->d_sinfo, out->d_einfo, true));
     return ROIX_OK;
 }
@@ -489,6 +518,24 @@ roix_status roix_fused(roix_ctx* ctx, const void* d_in, roix_dtype dtype, roix_d
     Layout L;
     if (!carve(ctx, g, &L, dtype)) return ROIX_ENOMEM;
     return enqueue_fused(lctx(ctx, stream), g, L, d_in, dtype, eb, crit, out);
+}
+
+roix_status roix_fused_background(roix_ctx* ctx, const float* d_in, roix_dims dims, const float* d_bg,
+                                  int64_t bg_planes, roix_eb eb, const roix_criterion* crit,
+                                  const roix_fused_out* out, float* d_work, void* stream) {
+    Geom g;
+    if (!ctx || !d_in || !d_bg || !d_work || !geom_of(dims, &g) || !eb_ok(eb) || !crit_ok(crit) || !out_ok(out, true))
+        return ROIX_EINVAL;
+    if (bg_planes != 1 && bg_planes != g.nz) return ROIX_EINVAL;
+    if (!aligned(d_in, 4) || !aligned(d_bg, 4) || !aligned(d_work, 4)) return ROIX_EINVAL;
+    // the workspace overlaps neither the image nor the reference
+    const uintptr_t w0 = (uintptr_t)d_work, w1 = w0 + g.N * 4, i0 = (uintptr_t)d_in, i1 = i0 + g.N * 4;
+    const uintptr_t b0 = (uintptr_t)d_bg, b1 = b0 + (size_t)bg_planes * (size_t)(g.nx * g.ny) * 4;
+    if ((w0 < i1 && i0 < w1) || (w0 < b1 && b0 < w1)) return ROIX_EINVAL;
+    Layout L;
+    if (!carve(ctx, g, &L, ROIX_F32)) return ROIX_ENOMEM;
+    const BgRef b = {d_bg, bg_planes == 1, d_work};
+    return enqueue_fused_bg(lctx(ctx, stream), g, L, d_in, b, eb, crit, out);
 }
 
 roix_status roix_decode(roix_ctx* ctx, const roix_row* d_rows, int64_t rows_cap, const void* d_stream,

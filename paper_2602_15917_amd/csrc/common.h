@@ -268,7 +268,16 @@ hipError_t launch_quant_hist(const LaunchCtx& lc, const void* in, int src_kind, 
 // float32, absolute bound, rows 16-byte aligned and a multiple of 4 voxels:
 // range keys, 16-bit proxy and code-class counts in one pass; then the
 // quantiser and (K <= 2^15) the histogram, setting S->p16
-hipError_t launch_quant_range16(const LaunchCtx& lc, const float* in, const Geom& g, const Layout& L);
+// A background reference subtracted on the fly (M = I - B): bg holds one
+// ny x nx plane (plane = true: row r reads plane row r % ny) or a plane per
+// z; work (N floats) receives M where a stage must read M itself.
+struct BgRef {
+    const float* bg;
+    bool plane;
+    float* work;
+};
+hipError_t launch_quant_range16(const LaunchCtx& lc, const float* in, const Geom& g, const Layout& L,
+                                const BgRef* bg = nullptr);
 hipError_t launch_resolve16(const LaunchCtx& lc, const Layout& L, roix_eb eb, const roix_criterion* crit);
 hipError_t launch_otsu(const LaunchCtx& lc, DevState* S, bool fixed);
 // the threshold of a criterion: Otsu, multi-level Otsu or fixed (whose q_thr
@@ -311,6 +320,12 @@ hipError_t launch_decode(const LaunchCtx& lc, const roix_row* rows, uint64_t row
                          uint4* desc, roix_decode_info* dinfo);
 hipError_t launch_background(const LaunchCtx& lc, const void* in, roix_dtype dt, const float* bg, bool full,
                              const Geom& g, int op, float* out);
+// M = in - bg into bg.work, only when the device state asks for it:
+// when = 1 after the fused range pass when it fell back to the 1-byte proxy
+// (p16 == 0); when = 2 before the general emit kernel when the proxy path
+// queued chunks for it (p16 == 1 and n_slow > 0)
+hipError_t launch_background_if(const LaunchCtx& lc, const float* in, const BgRef& bg, const Geom& g, DevState* S,
+                                int when);
 hipError_t launch_slice_otsu(const LaunchCtx& lc, const Geom& g, uint8_t* proxy, DevState* S, int32_t* slice_thr);
 size_t absq_scratch_bytes(int64_t m);
 size_t huff_scratch_bytes();
@@ -330,8 +345,10 @@ hipError_t launch_voxel_out(const LaunchCtx& lc, const Geom& g, const Layout& L,
 
 hipError_t launch_spans_from_runs(const LaunchCtx& lc, const Geom& g, const Layout& L);
 hipError_t launch_spans_from_keep(const LaunchCtx& lc, const Geom& g, const Layout& L, const uint8_t* keep);
+// with bg: `in` is the image I; the codes come from the 16-bit proxy, the
+// queued chunks read M from bg->work, the outlier values are I - B
 hipError_t launch_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, const void* in, roix_dtype dt,
-                       const roix_fused_out* out);
+                       const roix_fused_out* out, const BgRef* bg = nullptr);
 // mode bits: 1 = quant info, 2 = seg info, 4 = extract info; fused marks n_outliers not computed
 hipError_t launch_finalize(const LaunchCtx& lc, DevState* S, roix_quant_info* qi, roix_seg_info* si,
                            roix_extract_info* ei, bool fused_q);

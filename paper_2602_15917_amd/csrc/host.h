@@ -100,10 +100,13 @@ hipError_t components_and_keep(const LaunchCtx& lc, const Geom& g, const Layout&
                                roix_component* comps, int64_t comps_cap);
 // span scan -> codes -> row table -> outliers
 hipError_t spans_and_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, const void* in, roix_dtype dt,
-                          const roix_fused_out* out);
+                          const roix_fused_out* out, const BgRef* bg = nullptr);
 // the whole fused path on a carved layout
 roix_status enqueue_fused(const LaunchCtx& lc, const Geom& g, Layout L, const void* d_in, roix_dtype dtype,
                           roix_eb eb, const roix_criterion* crit, const roix_fused_out* out);
+// the same on M = I - B, the subtraction folded into the passes that read I
+roix_status enqueue_fused_bg(const LaunchCtx& lc, const Geom& g, Layout L, const float* d_in, const BgRef& bg,
+                             roix_eb eb, const roix_criterion* crit, const roix_fused_out* out);
 
 }  // namespace roix
 

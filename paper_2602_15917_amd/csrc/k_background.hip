@@ -48,9 +48,18 @@ __device__ __forceinline__ v4f32_t bg_load4<uint16_t>(const uint16_t* in, int64_
 // otherwise single voxels.  plane_e: elements per plane; full: the reference
 // has a plane per z.  out may be in (float32 in place): every element is
 // read and then written by the same lane.
-template <typename T, int OP, bool VEC>
+// WHEN (the fused path's on-demand M, read from the device state S): 0
+// always; 1 only when the range pass fell back to the 1-byte proxy; 2 only
+// when the 16-bit proxy path queued chunks for the general emit kernel.
+template <typename T, int OP, bool VEC, int WHEN = 0>
 __global__ __launch_bounds__(kBlock) void k_background(const T* in, const float* __restrict__ bg, float* out,
-                                                       int64_t plane_e, int64_t nz, int full) {
+                                                       int64_t plane_e, int64_t nz, int full,
+                                                       const DevState* S) {
+    if constexpr (WHEN == 1) {
+        if (S->p16) return;
+    } else if constexpr (WHEN == 2) {
+        if (!S->p16 || S->n_slow == 0u) return;
+    }
     const int64_t upp = (plane_e + kBgUnit - 1) / kBgUnit;  // units per plane
     const int64_t units = upp * nz;
     for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
@@ -106,10 +115,10 @@ static void bg_launch(const LaunchCtx& lc, const T* in, const float* bg, float* 
     const int grid = (int)(units < (int64_t)lc.grid_stream ? units : (int64_t)lc.grid_stream);
     if (vec)
         hipLaunchKernelGGL((k_background<T, OP, true>), dim3(grid), dim3(kBlock), 0, lc.stream, in, bg, out,
-                           plane_e, g.nz, full ? 1 : 0);
+                           plane_e, g.nz, full ? 1 : 0, (const DevState*)nullptr);
     else
         hipLaunchKernelGGL((k_background<T, OP, false>), dim3(grid), dim3(kBlock), 0, lc.stream, in, bg, out,
-                           plane_e, g.nz, full ? 1 : 0);
+                           plane_e, g.nz, full ? 1 : 0, (const DevState*)nullptr);
 }
 
 hipError_t launch_background(const LaunchCtx& lc, const void* in, roix_dtype dt, const float* bg, bool full,
@@ -126,6 +135,24 @@ hipError_t launch_background(const LaunchCtx& lc, const void* in, roix_dtype dt,
     } else {
         bg_launch<uint16_t, ROIX_BG_SUBTRACT>(lc, (const uint16_t*)in, bg, out, g, full, vec);
     }
+    timer_end(lc.timer, ST_BACKGROUND, lc.stream);
+    return hipGetLastError();
+}
+
+hipError_t launch_background_if(const LaunchCtx& lc, const float* in, const BgRef& bg, const Geom& g, DevState* S,
+                                int when) {
+    // the fused path with a background runs on 16-byte aligned rows of whole 64-voxel words
+    const int64_t plane_e = g.nx * g.ny / 4;
+    const int64_t units = (plane_e + kBgUnit - 1) / kBgUnit * g.nz;
+    const int grid = (int)(units < (int64_t)lc.grid_stream ? units : (int64_t)lc.grid_stream);
+    const int full = bg.plane ? 0 : 1;
+    timer_begin(lc.timer, ST_BACKGROUND, lc.stream);
+    if (when == 1)
+        hipLaunchKernelGGL((k_background<float, ROIX_BG_SUBTRACT, true, 1>), dim3(grid), dim3(kBlock), 0, lc.stream,
+                           in, bg.bg, bg.work, plane_e, g.nz, full, (const DevState*)S);
+    else
+        hipLaunchKernelGGL((k_background<float, ROIX_BG_SUBTRACT, true, 2>), dim3(grid), dim3(kBlock), 0, lc.stream,
+                           in, bg.bg, bg.work, plane_e, g.nz, full, (const DevState*)S);
     timer_end(lc.timer, ST_BACKGROUND, lc.stream);
     return hipGetLastError();
 }

@@ -1018,13 +1018,18 @@ __global__ __launch_bounds__(kBlock) void k_emit_codes_general(const T* __restri
 constexpr int kOutlU = 16;  // loads per lane and round
 constexpr uint32_t kOutlRound = (uint32_t)kWave * kOutlU;
 
-template <typename T>
-__device__ __forceinline__ void outl_load(const T* __restrict__ src, uint32_t len, uint32_t j0, float (&xv)[kOutlU]) {
+template <typename T, bool BG = false>
+__device__ __forceinline__ void outl_load(const T* __restrict__ src, const float* __restrict__ bsrc, uint32_t len,
+                                          uint32_t j0, float (&xv)[kOutlU]) {
     const int lane = threadIdx.x % kWave;
 #pragma unroll
     for (int u = 0; u < kOutlU; ++u) {
         const uint32_t jj = j0 + u * kWave + lane;
-        xv[u] = (float)src[jj < len ? jj : 0u];
+        const uint32_t js = jj < len ? jj : 0u;
+        if constexpr (BG)
+            xv[u] = (float)src[js] - bsrc[js];  // M = I - B, the value the codes were taken of
+        else
+            xv[u] = (float)src[js];
     }
 }
 
@@ -1052,9 +1057,10 @@ __device__ __forceinline__ void outl_store(const float (&xv)[kOutlU], uint32_t l
 // one per lane: the lane writes its span's row table entry (coalesced), then
 // the wave walks the spans that have outliers (a ballot), the first round of
 // the next one in flight while the current one is tested.
-template <typename T>
+template <typename T, bool BG = false>
 __global__ __launch_bounds__(kBlock) void k_emit_rows(const T* __restrict__ in, int64_t nx, Layout L, int64_t ny,
-                                                      int64_t nrows, EmitOut o) {
+                                                      int64_t nrows, EmitOut o, const float* __restrict__ bg,
+                                                      int bg_plane) {
     DevState* S = L.S;
     if (thread_exit_e(S)) return;
     const uint32_t n_rows = uni((uint32_t)(S->span_total >> 40));
@@ -1095,6 +1101,12 @@ __global__ __launch_bounds__(kBlock) void k_emit_rows(const T* __restrict__ in, 
             return in + (uint64_t)uni(__builtin_amdgcn_readlane(rid, l)) * (uint64_t)nx +
                    uni(__builtin_amdgcn_readlane(xs, l));
         };
+        // the reference row under span l: plane row (row mod ny) or the row itself
+        auto bsrc_of = [&](int l) -> const float* {
+            if constexpr (!BG) return nullptr;
+            const uint64_t rr = (uint64_t)uni(__builtin_amdgcn_readlane(rid, l));
+            return bg + (bg_plane ? rr % (uint64_t)ny : rr) * (uint64_t)nx + uni(__builtin_amdgcn_readlane(xs, l));
+        };
         auto len_of = [&](int l) { return uni(__builtin_amdgcn_readlane(len, l)); };
         // one span: its first round is in xv; longer spans loop (rare)
         auto test = [&](int l, const float (&xv)[kOutlU]) {
@@ -1103,7 +1115,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_rows(const T* __restrict__ in, 
             outl_store(xv, lt, 0, r, w, eb32, k, o, trunc);
             for (uint32_t j0 = kOutlRound; j0 < lt; j0 += kOutlRound) {
                 float xc[kOutlU];
-                outl_load<T>(src_of(l), lt, j0, xc);
+                outl_load<T, BG>(src_of(l), bsrc_of(l), lt, j0, xc);
                 outl_store(xc, lt, j0, r, w, eb32, k, o, trunc);
             }
         };
@@ -1117,16 +1129,16 @@ __global__ __launch_bounds__(kBlock) void k_emit_rows(const T* __restrict__ in, 
         };
         float xa[kOutlU], xb[kOutlU];
         int la = pop(0);
-        outl_load<T>(src_of(la), len_of(la), 0, xa);
+        outl_load<T, BG>(src_of(la), bsrc_of(la), len_of(la), 0, xa);
         while (true) {
             const bool more_b = m != 0;
             const int lb = pop(la);
-            outl_load<T>(src_of(lb), len_of(lb), 0, xb);
+            outl_load<T, BG>(src_of(lb), bsrc_of(lb), len_of(lb), 0, xb);
             test(la, xa);
             if (!more_b) break;
             const bool more_a = m != 0;
             la = pop(lb);
-            outl_load<T>(src_of(la), len_of(la), 0, xa);
+            outl_load<T, BG>(src_of(la), bsrc_of(la), len_of(la), 0, xa);
             test(lb, xb);
             if (!more_a) break;
         }
@@ -1135,7 +1147,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_rows(const T* __restrict__ in, 
 }
 
 hipError_t launch_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, const void* in, roix_dtype dt,
-                       const roix_fused_out* out) {
+                       const roix_fused_out* out, const BgRef* bg) {
     EmitOut o;
     o.rows = out->d_rows;
     o.rows_cap = out->d_rows ? (uint64_t)out->rows_cap : 0;
@@ -1153,11 +1165,16 @@ hipError_t launch_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, cons
     if (dt == ROIX_F32) {
         // the 16-bit proxy (proxy element = voxel when rows are whole 64-voxel words)
         const uint16_t* px = (L.fine_slots && g.W * 64 == g.nx) ? reinterpret_cast<const uint16_t*>(L.proxy) : nullptr;
-        hipLaunchKernelGGL(k_emit_codes<float>, grid_waves, block, 0, lc.stream, (const float*)in, g.nx, L, o,
-                           px ? 1 : 0);
+        // with a background the kernels that read voxel values read M
+        const float* vals = bg ? bg->work : (const float*)in;
+        hipLaunchKernelGGL(k_emit_codes<float>, grid_waves, block, 0, lc.stream, vals, g.nx, L, o, px ? 1 : 0);
         if (px)
             hipLaunchKernelGGL(k_emit_codes_p16, grid_waves, block, 0, lc.stream, (const float*)in, g.nx, L, o, px);
-        hipLaunchKernelGGL(k_emit_codes_general<float>, grid_waves, block, 0, lc.stream, (const float*)in, g.nx, L, o);
+        if (bg) {
+            hipError_t e = launch_background_if(lc, (const float*)in, *bg, g, L.S, 2);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k_emit_codes_general<float>, grid_waves, block, 0, lc.stream, vals, g.nx, L, o);
     } else {
         hipLaunchKernelGGL(k_emit_codes<uint16_t>, grid_waves, block, 0, lc.stream, (const uint16_t*)in, g.nx, L, o, 0);
         hipLaunchKernelGGL(k_emit_codes_general<uint16_t>, grid_waves, block, 0, lc.stream, (const uint16_t*)in, g.nx,
@@ -1167,12 +1184,15 @@ hipError_t launch_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, cons
     hipError_t e = launch_scan_u64(lc, L.row_outl, L.row_outl, g.nrows, &L.S->n_outliers, L.scan_tmp);
     if (e != hipSuccess) return e;
     timer_begin(lc.timer, ST_EMIT_ROWS, lc.stream);
-    if (dt == ROIX_F32) {
-        hipLaunchKernelGGL(k_emit_rows<float>, grid_rows_t, block, 0, lc.stream, (const float*)in, g.nx, L, g.ny,
-                           g.nrows, o);
+    if (dt == ROIX_F32 && bg) {
+        hipLaunchKernelGGL((k_emit_rows<float, true>), grid_rows_t, block, 0, lc.stream, (const float*)in, g.nx, L,
+                           g.ny, g.nrows, o, bg->bg, bg->plane ? 1 : 0);
+    } else if (dt == ROIX_F32) {
+        hipLaunchKernelGGL((k_emit_rows<float, false>), grid_rows_t, block, 0, lc.stream, (const float*)in, g.nx, L,
+                           g.ny, g.nrows, o, (const float*)nullptr, 0);
     } else {
-        hipLaunchKernelGGL(k_emit_rows<uint16_t>, grid_rows_t, block, 0, lc.stream, (const uint16_t*)in, g.nx, L, g.ny,
-                           g.nrows, o);
+        hipLaunchKernelGGL((k_emit_rows<uint16_t, false>), grid_rows_t, block, 0, lc.stream, (const uint16_t*)in, g.nx,
+                           L, g.ny, g.nrows, o, (const float*)nullptr, 0);
     }
     timer_end(lc.timer, ST_EMIT_ROWS, lc.stream);
     return hipGetLastError();

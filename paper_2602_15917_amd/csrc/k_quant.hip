@@ -681,10 +681,22 @@ __device__ __forceinline__ void qr_vec(const uint4& raw, uint16_t* __restrict__ 
     }
 }
 
+// M = I - B lane by lane: the raw bits of 4 image voxels minus 4 reference voxels
+__device__ __forceinline__ uint4 qr_sub(const uint4& a, const uint4& b) {
+    return make_uint4(__float_as_uint(__uint_as_float(a.x) - __uint_as_float(b.x)),
+                      __float_as_uint(__uint_as_float(a.y) - __uint_as_float(b.y)),
+                      __float_as_uint(__uint_as_float(a.z) - __uint_as_float(b.z)),
+                      __float_as_uint(__uint_as_float(a.w) - __uint_as_float(b.w)));
+}
+
+// BG: the pass quantises M = I - B, B read from bg (row r of the image takes
+// row r % ny of a plane reference, or row r of a volume reference)
+template <bool BG>
 __global__ __launch_bounds__(kQrThreads) void k_quant_range16(const float* __restrict__ in, int64_t nx, int64_t nrows,
                                                             int64_t P, DevState* S, uint16_t* __restrict__ proxy,
                                                             uint32_t* __restrict__ slots,
-                                                            unsigned long long* __restrict__ fine_total) {
+                                                            unsigned long long* __restrict__ fine_total,
+                                                            const float* __restrict__ bg, int64_t bg_ny) {
     __shared__ uint32_t fine[kQrFine];
     for (int i = threadIdx.x; i < kQrFine; i += blockDim.x) fine[i] = 0u;
     // this workgroup's share of the totals the reduce adds into
@@ -693,7 +705,10 @@ __global__ __launch_bounds__(kQrThreads) void k_quant_range16(const float* __res
     if (block_exit(S)) return;  // contains a barrier
     const float r = S->r, w = S->w, eb32 = S->eb32;
     uint32_t lo = 0xFFFFFFFFu, hi = 0u, nf = 0u;
-    constexpr int64_t kSlots = (int64_t)kWave * kQhBatch;
+    // with a reference each load has a partner: half the batch keeps the
+    // registers within the 1024-thread budget
+    constexpr int NB = BG ? kQhBatch / 2 : kQhBatch;
+    constexpr int64_t kSlots = (int64_t)kWave * NB;
     const int lane = threadIdx.x % kWave;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
@@ -703,37 +718,50 @@ __global__ __launch_bounds__(kQrThreads) void k_quant_range16(const float* __res
     if ((1ll << lg) < kSlots) {  // several rows per step (row lengths padded to a power of two)
         const int64_t rpi = kSlots >> lg;
         for (int64_t row0 = wave * rpi; row0 < nrows; row0 += nwaves * rpi) {
-            uint4 raw[kQhBatch];
+            uint4 raw[NB], braw[BG ? NB : 1];
 #pragma unroll
-            for (int k = 0; k < kQhBatch; ++k) {
+            for (int k = 0; k < NB; ++k) {
                 const int64_t e = (int64_t)k * kWave + lane;
                 const int64_t row = row0 + (e >> lg), vi = e & ((1ll << lg) - 1);
-                raw[k] = (vi < nv && row < nrows) ? ld_stream(reinterpret_cast<const uint4*>(in + row * nx) + vi)
-                                                  : make_uint4(0, 0, 0, 0);
+                const bool ok = vi < nv && row < nrows;
+                raw[k] = ok ? ld_stream(reinterpret_cast<const uint4*>(in + row * nx) + vi) : make_uint4(0, 0, 0, 0);
+                if constexpr (BG) {
+                    const int64_t brow = bg_ny ? row % bg_ny : row;
+                    braw[k] = ok ? *(reinterpret_cast<const uint4*>(bg + brow * nx) + vi) : make_uint4(0, 0, 0, 0);
+                }
             }
 #pragma unroll
-            for (int k = 0; k < kQhBatch; ++k) {
+            for (int k = 0; k < NB; ++k) {
                 const int64_t e = (int64_t)k * kWave + lane;
                 const int64_t row = row0 + (e >> lg), vi = e & ((1ll << lg) - 1);
                 if (vi >= nv || row >= nrows) continue;
-                qr_vec(raw[k], proxy + row * P, vi, r, w, eb32, fine, lo, hi, nf);
+                if constexpr (BG)
+                    qr_vec(qr_sub(raw[k], braw[k]), proxy + row * P, vi, r, w, eb32, fine, lo, hi, nf);
+                else
+                    qr_vec(raw[k], proxy + row * P, vi, r, w, eb32, fine, lo, hi, nf);
             }
         }
     } else {
         for (int64_t row = wave; row < nrows; row += nwaves) {
             const uint4* vs = reinterpret_cast<const uint4*>(in + row * nx);
+            const uint4* bs = BG ? reinterpret_cast<const uint4*>(bg + (bg_ny ? row % bg_ny : row) * nx) : nullptr;
             uint16_t* dst = proxy + row * P;
             for (int64_t v0 = 0; v0 < nv; v0 += kSlots) {
-                uint4 raw[kQhBatch];
+                uint4 raw[NB], braw[BG ? NB : 1];
 #pragma unroll
-                for (int k = 0; k < kQhBatch; ++k) {
+                for (int k = 0; k < NB; ++k) {
                     const int64_t vi = v0 + k * kWave + lane;
                     raw[k] = vi < nv ? ld_stream(vs + vi) : make_uint4(0, 0, 0, 0);
+                    if constexpr (BG) braw[k] = vi < nv ? bs[vi] : make_uint4(0, 0, 0, 0);
                 }
 #pragma unroll
-                for (int k = 0; k < kQhBatch; ++k) {
+                for (int k = 0; k < NB; ++k) {
                     const int64_t vi = v0 + k * kWave + lane;
-                    if (vi < nv) qr_vec(raw[k], dst, vi, r, w, eb32, fine, lo, hi, nf);
+                    if (vi >= nv) continue;
+                    if constexpr (BG)
+                        qr_vec(qr_sub(raw[k], braw[k]), dst, vi, r, w, eb32, fine, lo, hi, nf);
+                    else
+                        qr_vec(raw[k], dst, vi, r, w, eb32, fine, lo, hi, nf);
                 }
             }
         }
@@ -807,10 +835,16 @@ __global__ __launch_bounds__(1024) void k_resolve16(DevState* S, double eb_value
     if (t < 256) S->hist[t] = sh[t];
 }
 
-hipError_t launch_quant_range16(const LaunchCtx& lc, const float* in, const Geom& g, const Layout& L) {
+hipError_t launch_quant_range16(const LaunchCtx& lc, const float* in, const Geom& g, const Layout& L, const BgRef* bg) {
     timer_begin(lc.timer, ST_QR16, lc.stream);
-    hipLaunchKernelGGL(k_quant_range16, dim3(kQrBlocks), dim3(kQrThreads), 0, lc.stream, in, g.nx, g.nrows, g.W * 64,
-                       L.S, reinterpret_cast<uint16_t*>(L.proxy), L.fine_slots, L.fine_total);
+    if (bg)
+        hipLaunchKernelGGL(k_quant_range16<true>, dim3(kQrBlocks), dim3(kQrThreads), 0, lc.stream, in, g.nx, g.nrows,
+                           g.W * 64, L.S, reinterpret_cast<uint16_t*>(L.proxy), L.fine_slots, L.fine_total, bg->bg,
+                           bg->plane ? g.ny : (int64_t)0);
+    else
+        hipLaunchKernelGGL(k_quant_range16<false>, dim3(kQrBlocks), dim3(kQrThreads), 0, lc.stream, in, g.nx, g.nrows,
+                           g.W * 64, L.S, reinterpret_cast<uint16_t*>(L.proxy), L.fine_slots, L.fine_total,
+                           (const float*)nullptr, (int64_t)0);
     timer_end(lc.timer, ST_QR16, lc.stream);
     return hipGetLastError();
 }

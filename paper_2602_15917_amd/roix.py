@@ -140,6 +140,7 @@ def load():
     lib.roix_server_stats.argtypes = [vp, P(ServerStats)]
     lib.roix_decode.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp, vp, Dims, ctypes.c_float, vp, vp, vp]
     lib.roix_background.argtypes = [vp, vp, ci, Dims, vp, i64, ci, vp, vp]
+    lib.roix_fused_background.argtypes = [vp, vp, Dims, vp, i64, Eb, P(CCriterion), P(FusedOut), vp, vp]
     lib.roix_abs_quantize.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp, vp]
     lib.roix_huff_encode.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, vp]
     lib.roix_huff_decode.argtypes = [vp, vp, vp, vp, i64, i64, vp, vp, vp]
@@ -149,7 +150,7 @@ def load():
               "roix_extract", "roix_fused", "roix_ctx_set_timing", "roix_ctx_read_timing", "roix_fused_batch",
               "roix_ctx_set_param", "roix_ctx_get_param", "roix_server_create", "roix_server_destroy",
               "roix_volume_open", "roix_slab_submit", "roix_volume_close", "roix_volume_abort", "roix_wait",
-              "roix_server_stats", "roix_decode", "roix_background", "roix_abs_quantize",
+              "roix_server_stats", "roix_decode", "roix_background", "roix_fused_background", "roix_abs_quantize",
               "roix_huff_encode", "roix_huff_decode"):
         getattr(lib, f).restype = ci
     _lib = lib
@@ -377,6 +378,22 @@ class Context:
                                     BG_OPS[op], _ptr(dst), _stream(stream))
         _check(st, "roix_background")
         return dst
+
+    def fused_background(self, vol: torch.Tensor, bg: torch.Tensor, eb_mode: str, eb_value: float, crit: Criterion,
+                         out: Outputs, work: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Enqueue the fused path on M = vol - bg (float32 volume; bg of shape
+        (1, ny, nx) or (nz, ny, nx)).  work: float32 workspace of the volume's
+        size (allocated when None).  Returns the workspace."""
+        if vol.dtype != torch.float32 or not (vol.is_contiguous() and bg.is_contiguous()):
+            raise ValueError("fused_background: contiguous float32 volume and reference")
+        if work is None:
+            work = torch.empty_like(vol)
+        c = crit.c()
+        planes = bg.shape[0] if bg.dim() == 3 else -1
+        st = load().roix_fused_background(self.h, _ptr(vol), dims_of(vol), _ptr(bg), planes, eb_of(eb_mode, eb_value),
+                                          ctypes.byref(c), ctypes.byref(out.c), _ptr(work), _stream(stream))
+        _check(st, "roix_fused_background")
+        return work
 
     def abs_quantize(self, pixels: torch.Tensor, e_abs: float, dst: torch.Tensor | None = None,
                      info: torch.Tensor | None = None, stream=None):

@@ -27,7 +27,7 @@ def declared_functions():
 def test_header_declares_the_path_calls():
     names = declared_functions()
     for n in ("roix_quantize", "roix_segment", "roix_extract", "roix_fused", "roix_ctx_create",
-              "roix_ctx_destroy", "roix_scratch_bytes", "roix_bounds", "roix_decode", "roix_background",
+              "roix_ctx_destroy", "roix_scratch_bytes", "roix_bounds", "roix_decode", "roix_background", "roix_fused_background",
               "roix_abs_quantize", "roix_huff_encode", "roix_huff_decode"):
         assert n in names
 

@@ -181,3 +181,80 @@ def test_background_argument_errors(env):
     assert call(v.data_ptr(), roix.F32, b.data_ptr(), 1, 0, v.data_ptr() + 4) == roix.EINVAL  # partial overlap
     assert call(v.data_ptr(), roix.F32, o.data_ptr(), 1, 0, o.data_ptr()) == roix.EINVAL  # output over reference
     assert call(u.data_ptr(), roix.U16, b.data_ptr(), 1, 0, u.data_ptr()) == roix.EINVAL  # uint16 in place
+
+
+def fused_bg_case(ctx, roix, torch, img, bg, ebm, ebv, c, name):
+    log(f"[case] fused background {name} shape={img.shape} planes={bg.shape[0]} eb={ebm}:{ebv} crit={c}")
+    crit = criterion(roix, c)
+    t = torch.from_numpy(img).to("cuda:0")
+    b = torch.from_numpy(bg).to("cuda:0")
+    out = roix.Outputs("cuda:0", *default_caps(roix, img, crit),
+                       nz_slices=img.shape[0] if c.thr == "otsu_slice" else 0)
+    ctx.fused_background(t, b, ebm, ebv, crit, out)
+    torch.cuda.synchronize()
+    st, m = oracle.background(img, bg)
+    o = oracle_fused(m, ebm, ebv, c)
+    g = out.collect()
+    compare_fused(g, o)
+    assert g["rows"].tobytes() == o["rows"].tobytes()
+    assert g["stream"].tobytes() == o["stream"].tobytes()
+    assert g["outliers"].view(np.uint32).tobytes() == o["outliers"].view(np.uint32).tobytes()
+    return g, o
+
+
+@pytest.mark.parametrize("small_fused", [False, True])
+def test_fused_background_equals_subtract_then_path(env, small_fused):
+    # the subtraction folded into the path gives the outputs of subtracting
+    # first; small_fused lets volumes below the default size take the
+    # one-pass flow, where the folding happens
+    ctx, roix, torch = env
+    c2 = roix.Context(0, 1 << 30)
+    if small_fused:
+        c2.set_param("fused16_min_voxels", 0)
+    w = synth.ellipsoids128()
+    plane = background_field(w.volume.shape, 910)
+    img = (w.volume + plane).astype(np.float32)
+    crit = synth.Criterion("otsu", 0.0, 26, "min_size", 64)
+    fused_bg_case(c2, roix, torch, img, plane, "abs", 1e-3, crit, "plane")
+    vref = np.concatenate([plane * (1.0 + 0.01 * z) for z in range(img.shape[0])]).astype(np.float32)
+    img_v = (w.volume + vref).astype(np.float32)
+    fused_bg_case(c2, roix, torch, img_v, vref, "abs", 1e-3, crit, "volume reference")
+    # escapes: a bound so small that fp32 rounding misses it on many voxels
+    g, o = fused_bg_case(c2, roix, torch, img, plane, "abs", 3.3e-6, crit, "escapes")
+    assert o["info"].n_outliers > 0
+    # more than 2^15 codes: the range pass falls back to the 1-byte proxy and M is written on the device
+    big = (1000.0 + 1000.0 * np.random.default_rng(9).random((4, 16, 256))).astype(np.float32)
+    bplane = background_field(big.shape, 911) * 100.0
+    g, o = fused_bg_case(c2, roix, torch, (big + bplane).astype(np.float32), bplane, "abs", 0.01,
+                         synth.Criterion("otsu", 0.0, 26, "largest", 1), "wide code range")
+    assert o["params"].K > (1 << 15)
+    # many short spans: the proxy emit queues chunks for the general kernel, which reads M
+    noise = synth.normal((11, 200, 64), 912, 0.5, 0.1)
+    nplane = background_field(noise.shape, 913)
+    g, o = fused_bg_case(c2, roix, torch, (noise + nplane).astype(np.float32), nplane, "abs", 1e-3,
+                         synth.Criterion("fixed", 0.75, 6, "min_size", 1), "short spans")
+    assert o["info"].n_rows > 500 and o["info"].n_codes < 64 * o["info"].n_rows
+    # rows that are no whole 64-voxel words, a relative bound, per-slice thresholds: subtract first
+    odd = (w.volume[:, :, :100] + plane[:, :, :100]).astype(np.float32)
+    fused_bg_case(c2, roix, torch, np.ascontiguousarray(odd), np.ascontiguousarray(plane[:, :, :100]), "abs", 1e-3,
+                  crit, "ragged rows")
+    fused_bg_case(c2, roix, torch, img, plane, "rel", 1e-4, crit, "relative bound")
+    fused_bg_case(c2, roix, torch, img, plane, "abs", 1e-3, synth.Criterion("otsu_slice", 0.0, 26, "largest", 1),
+                  "per-slice")
+    c2.close()
+
+
+def test_fused_background_argument_errors(env):
+    ctx, roix, torch = env
+    img = np.zeros((2, 4, 64), np.float32)
+    crit = roix.Criterion("otsu", 0.0, 26, "largest", 1)
+    t = torch.from_numpy(img).to("cuda:0")
+    b = torch.zeros((1, 4, 64), dtype=torch.float32, device="cuda:0")
+    out = roix.Outputs("cuda:0", *default_caps(roix, img, crit))
+    with pytest.raises(roix.RoixError) as ei:  # workspace over the image
+        ctx.fused_background(t, b, "abs", 1e-3, crit, out, work=t)
+    assert ei.value.status == roix.EINVAL
+    with pytest.raises(roix.RoixError) as ei:  # a reference of neither 1 nor nz planes
+        ctx.fused_background(t, torch.zeros((3, 4, 64), dtype=torch.float32, device="cuda:0"), "abs", 1e-3, crit,
+                             out)
+    assert ei.value.status == roix.EINVAL
