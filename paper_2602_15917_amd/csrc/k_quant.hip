@@ -651,6 +651,7 @@ hipError_t launch_hist_only(const LaunchCtx& lc, const void* in, roix_dtype dt, 
 // usual.  Rows start 16-byte aligned and hold a multiple of 4 voxels.
 
 constexpr int kQrThreads = 1024;
+constexpr int64_t kQrZb = 8;  // slices sharing one load of a reference plane row
 
 __device__ __forceinline__ void qr_vec(const uint4& raw, uint16_t* __restrict__ dst, int64_t vi, float r, float w,
                                        float eb32, uint32_t* fine, uint32_t& lo, uint32_t& hi, uint32_t& nf) {
@@ -715,7 +716,46 @@ __global__ __launch_bounds__(kQrThreads) void k_quant_range16(const float* __res
     const int64_t nv = nx / 4;
     int lg = 0;
     while ((1ll << lg) < nv) ++lg;
-    if ((1ll << lg) < kSlots) {  // several rows per step (row lengths padded to a power of two)
+    if (BG && bg_ny && (1ll << lg) >= kSlots) {
+        // a plane reference on long rows: a wave takes one plane row y and
+        // the image rows y of kQrZb consecutive slices, so that each plane
+        // row is loaded once per kQrZb slices; the next slice's loads are in
+        // flight while one is quantised
+        const int64_t ny = bg_ny, nzb = (nrows / ny + kQrZb - 1) / kQrZb;
+        for (int64_t u = wave; u < ny * nzb; u += nwaves) {
+            const int64_t y = u % ny, z0 = (u / ny) * kQrZb;
+            const int64_t z1 = z0 + kQrZb < nrows / ny ? z0 + kQrZb : nrows / ny;
+            const uint4* bs = reinterpret_cast<const uint4*>(bg + y * nx);
+            for (int64_t v0 = 0; v0 < nv; v0 += kSlots) {
+                uint4 braw[NB], cur[NB], nxt[NB];
+#pragma unroll
+                for (int k = 0; k < NB; ++k) {
+                    const int64_t vi = v0 + k * kWave + lane;
+                    braw[k] = vi < nv ? bs[vi] : make_uint4(0, 0, 0, 0);
+                    cur[k] = vi < nv ? ld_stream(reinterpret_cast<const uint4*>(in + (z0 * ny + y) * nx) + vi)
+                                     : make_uint4(0, 0, 0, 0);
+                }
+                for (int64_t z = z0; z < z1; ++z) {
+                    // the next slice's row (the last one repeats, unused)
+                    const int64_t zn = z + 1 < z1 ? z + 1 : z;
+#pragma unroll
+                    for (int k = 0; k < NB; ++k) {
+                        const int64_t vi = v0 + k * kWave + lane;
+                        nxt[k] = vi < nv ? ld_stream(reinterpret_cast<const uint4*>(in + (zn * ny + y) * nx) + vi)
+                                         : make_uint4(0, 0, 0, 0);
+                    }
+                    uint16_t* dst = proxy + (z * ny + y) * P;
+#pragma unroll
+                    for (int k = 0; k < NB; ++k) {
+                        const int64_t vi = v0 + k * kWave + lane;
+                        if (vi < nv) qr_vec(qr_sub(cur[k], braw[k]), dst, vi, r, w, eb32, fine, lo, hi, nf);
+                    }
+#pragma unroll
+                    for (int k = 0; k < NB; ++k) cur[k] = nxt[k];
+                }
+            }
+        }
+    } else if ((1ll << lg) < kSlots) {  // several rows per step (row lengths padded to a power of two)
         const int64_t rpi = kSlots >> lg;
         for (int64_t row0 = wave * rpi; row0 < nrows; row0 += nwaves * rpi) {
             uint4 raw[NB], braw[BG ? NB : 1];

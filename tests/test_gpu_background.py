@@ -234,6 +234,14 @@ def test_fused_background_equals_subtract_then_path(env, small_fused):
     g, o = fused_bg_case(c2, roix, torch, (noise + nplane).astype(np.float32), nplane, "abs", 1e-3,
                          synth.Criterion("fixed", 0.75, 6, "min_size", 1), "short spans")
     assert o["info"].n_rows > 500 and o["info"].n_codes < 64 * o["info"].n_rows
+    # long rows (the range pass loads each plane row once for 8 slices; 19
+    # slices leave a partial block) and 768-voxel rows
+    for shape in ((19, 12, 1024), (10, 7, 768)):
+        nz, ny, nx = shape
+        vol, _ = synth.ellipsoids(nx, ny, nz, 914, n_ell=3, ax=(3.0, 40.0))
+        lp = background_field(shape, 915)
+        fused_bg_case(c2, roix, torch, (vol + lp).astype(np.float32), lp, "abs", 1e-3,
+                      synth.Criterion("otsu", 0.0, 26, "min_size", 8), f"long rows {shape}")
     # rows that are no whole 64-voxel words, a relative bound, per-slice thresholds: subtract first
     odd = (w.volume[:, :, :100] + plane[:, :, :100]).astype(np.float32)
     fused_bg_case(c2, roix, torch, np.ascontiguousarray(odd), np.ascontiguousarray(plane[:, :, :100]), "abs", 1e-3,
