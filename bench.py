@@ -475,6 +475,13 @@ def bench_batched(args):
     ctx.set_param("batch_graph", args.batch_graph)
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tuning = None
+    if args.autotune:  # the launch parameters, tuned on the largest volume of the batch
+        big = max(items, key=lambda it: it[0].numel())
+        tr = ctx.autotune(big[0], big[1], big[2], big[3], big[4], reps=3, stream=stream)
+        tuning = {"on_voxels": int(big[0].numel()), "default_ms": round(tr.default_ms, 4),
+                  "best_ms": round(tr.best_ms, 4), "params": dict(zip(roix.TUNE_PARAMS, [int(v) for v in tr.params]))}
+        log(f"autotune: {tuning}")
 
     def plain_pass():
         for (t, ebm, ebv, crit, out) in items:
@@ -512,6 +519,8 @@ def bench_batched(args):
         "plain_sequential_gbs": round(total / (res["plain"] * 1e-3) / 1e9, 2),
         "batched_over_plain": round(res["plain"] / res["batched"], 3),
     }
+    if tuning:
+        line["autotune"] = tuning
     print(json.dumps(line))
     ctx.close()
 
@@ -700,6 +709,8 @@ def main():
                          "absolute error-bounded quantisation of an 8-bit pixel section; huffman: the "
                          "lossless stage on the code stream, with compression ratios")
     ap.add_argument("--absq-e", type=float, default=2.0, help="tolerance of the absq workload")
+    ap.add_argument("--autotune", action="store_true",
+                    help="plain and batched workloads: tune the launch parameters on the volume(s) before timing")
     ap.add_argument("--thr", choices=["otsu", "multi3", "multi4", "otsu_slice"], default=None,
                     help="plain workload: threshold mode instead of the workload's two-class Otsu")
     ap.add_argument("--served-streams", type=int, default=4, help="uint16 2048x2048 streams of the served trace")
@@ -760,6 +771,12 @@ def main():
     def step():
         ctx.fused(x, w.eb_mode, w.eb_value, crit, out, stream)
 
+    tuning = None
+    if args.autotune:  # pick the launch parameters on this volume first
+        tr = ctx.autotune(x, w.eb_mode, w.eb_value, crit, out, reps=3, stream=stream)
+        tuning = {"default_ms": round(tr.default_ms, 4), "best_ms": round(tr.best_ms, 4), "runs": int(tr.n_timed),
+                  "params": dict(zip(roix.TUNE_PARAMS, [int(v) for v in tr.params]))}
+        log(f"autotune: {tuning}")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -867,6 +884,8 @@ def main():
         "roofline": roof, "path_roofline": path, "cpu_baseline": cpu,
         "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in stages.items() if v[1]},
     }
+    if tuning:
+        line["autotune"] = tuning
     print(json.dumps(line))
     ctx.close()
 

@@ -481,6 +481,41 @@ roix_status roix_fused_batch(roix_ctx* ctx, int32_t n, const roix_volume_desc* v
 roix_status roix_ctx_set_param(roix_ctx* ctx, const char* name, int64_t value);
 roix_status roix_ctx_get_param(roix_ctx* ctx, const char* name, int64_t* value);
 
+/* Autotuner of the launch parameters above, on the caller's own volume.
+ * Runs roix_fused with the given arguments and tunes grid_stream,
+ * grid_read, grid_mask, grid_emit, seg_grid, stats_grid and then seg_runs by
+ * coordinate descent: for each knob in that order, each candidate (4, 8, 16
+ * x CUs; 1, 2, 4; 16, 32, 64; 2, 4, 8; 1, 2, 4; 1, 2, 4 x CUs; seg_runs 0,
+ * 1024, 2048, 4096) is timed as the median of `reps` runs (HIP events on
+ * `stream`) with the other knobs held, and the fastest is kept on the
+ * context.  Every candidate's outputs must equal the first run's (the info
+ * structs byte for byte, position-weighted checksums of the row table, code
+ * stream, outliers and component table): a difference is a defect and
+ * returns ROIX_EDEVICE with the knob restored.
+ * cache_path (may be NULL): a text file of tuned values keyed by the
+ * device's architecture, dtype, bound mode, connectivity, threshold mode and
+ * the power-of-two buckets of nx, ny, nz.  On a hit the values are applied
+ * without timing (from_cache = 1); after tuning the line is appended.
+ * Synchronous: it waits for its runs.  The outputs hold the last run's
+ * results (those of every candidate).  res->status is the outputs'
+ * extraction status when it is not OK (nothing is tuned then), or
+ * ROIX_EDEVICE on a difference.  It allocates 32 bytes of device memory for
+ * the checksums while it runs.
+ * Errors: those of roix_fused; ROIX_EINVAL (NULL res, reps outside 1..100,
+ * NULL info pointers in out), ROIX_EDEVICE. */
+typedef struct {
+    int32_t status;
+    int32_t n_timed;      /* fused runs timed */
+    int32_t from_cache;
+    int32_t pad;
+    double default_ms;    /* median with the context's parameters before tuning (-1 from the cache) */
+    double best_ms;       /* median with the chosen parameters (-1 from the cache) */
+    int64_t params[7];    /* grid_stream, grid_read, grid_mask, grid_emit, seg_grid, stats_grid, seg_runs */
+} roix_tune_result;       /* 88 bytes */
+roix_status roix_autotune(roix_ctx* ctx, const void* d_in, roix_dtype dtype, roix_dims dims, roix_eb eb,
+                          const roix_criterion* crit, const roix_fused_out* out, int32_t reps,
+                          const char* cache_path, roix_tune_result* res, void* stream);
+
 /* Per-stage GPU timing.  When enabled, every kernel of the fused, staged
  * and batched paths is bracketed by HIP events on its stream;
  * roix_ctx_read_timing synchronises those events and returns, per stage,

@@ -323,7 +323,7 @@ size_t roix_sizeof(const char* t) {
                      {"roix_dims", sizeof(roix_dims)},                 {"roix_volume_desc", sizeof(roix_volume_desc)},
                      {"roix_req_result", sizeof(roix_req_result)},     {"roix_server_stats_t", sizeof(roix_server_stats_t)},
                      {"roix_decode_info", sizeof(roix_decode_info)},   {"roix_absq_info", sizeof(roix_absq_info)},
-                     {"roix_huff_info", sizeof(roix_huff_info)}};
+                     {"roix_huff_info", sizeof(roix_huff_info)},       {"roix_tune_result", sizeof(roix_tune_result)}};
     for (const auto& e : tab)
         if (strcmp(e.n, t) == 0) return e.s;
     return 0;

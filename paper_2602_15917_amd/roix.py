@@ -143,6 +143,8 @@ def load():
     lib.roix_fused_background.argtypes = [vp, vp, Dims, vp, i64, Eb, P(CCriterion), P(FusedOut), vp, vp]
     lib.roix_abs_quantize.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp, vp]
     lib.roix_huff_encode.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, vp]
+    lib.roix_autotune.argtypes = [vp, vp, ci, Dims, Eb, P(CCriterion), P(FusedOut), ctypes.c_int32, ctypes.c_char_p,
+                                  P(TuneResult), vp]
     lib.roix_huff_decode.argtypes = [vp, vp, vp, vp, i64, i64, vp, vp, vp]
     lib.roix_abs_quantize_scratch_bytes.argtypes = [i64]
     lib.roix_abs_quantize_scratch_bytes.restype = sz
@@ -151,7 +153,7 @@ def load():
               "roix_ctx_set_param", "roix_ctx_get_param", "roix_server_create", "roix_server_destroy",
               "roix_volume_open", "roix_slab_submit", "roix_volume_close", "roix_volume_abort", "roix_wait",
               "roix_server_stats", "roix_decode", "roix_background", "roix_fused_background", "roix_abs_quantize",
-              "roix_huff_encode", "roix_huff_decode"):
+              "roix_huff_encode", "roix_huff_decode", "roix_autotune"):
         getattr(lib, f).restype = ci
     _lib = lib
     return lib
@@ -297,6 +299,15 @@ class HuffInfo(ctypes.Structure):
 HUFF_BLOCK = 4096
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_timed", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("default_ms", ctypes.c_double), ("best_ms", ctypes.c_double),
+                ("params", ctypes.c_int64 * 7)]
+
+
+TUNE_PARAMS = ("grid_stream", "grid_read", "grid_mask", "grid_emit", "seg_grid", "stats_grid", "seg_runs")
+
+
 class AbsqInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("rounds", ctypes.c_int32), ("n_groups", ctypes.c_uint64),
                 ("finisher_chunks", ctypes.c_uint64), ("pad", ctypes.c_uint64)]
@@ -409,6 +420,18 @@ class Context:
                                       _stream(stream))
         _check(st, "roix_abs_quantize")
         return dst, info
+
+    def autotune(self, vol: torch.Tensor, eb_mode: str, eb_value: float, crit: Criterion, out: Outputs, reps: int = 3,
+                 cache: str | None = None, stream=None) -> "TuneResult":
+        """Tune the context's launch parameters on this volume (synchronous;
+        see roix_autotune).  Returns the TuneResult."""
+        c = crit.c()
+        res = TuneResult()
+        st = load().roix_autotune(self.h, _ptr(vol), dtype_of(vol), dims_of(vol), eb_of(eb_mode, eb_value),
+                                  ctypes.byref(c), ctypes.byref(out.c), int(reps),
+                                  cache.encode() if cache else None, ctypes.byref(res), _stream(stream))
+        _check(st, "roix_autotune")
+        return res
 
     def huff_encode(self, data: torch.Tensor, payload_cap_words: int | None = None, stream=None):
         """Enqueue the Huffman stage over a contiguous uint8 tensor (taken

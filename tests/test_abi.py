@@ -28,7 +28,8 @@ def test_header_declares_the_path_calls():
     names = declared_functions()
     for n in ("roix_quantize", "roix_segment", "roix_extract", "roix_fused", "roix_ctx_create",
               "roix_ctx_destroy", "roix_scratch_bytes", "roix_bounds", "roix_decode", "roix_background", "roix_fused_background",
-              "roix_abs_quantize", "roix_huff_encode", "roix_huff_decode"):
+              "roix_abs_quantize", "roix_huff_encode", "roix_huff_decode",
+              "roix_autotune"):
         assert n in names
 
 
@@ -47,7 +48,8 @@ def test_struct_sizes_match_binding(lib):
                       ("roix_criterion", roix.CCriterion), ("roix_eb", roix.Eb), ("roix_dims", roix.Dims),
                       ("roix_volume_desc", roix.VolumeDesc), ("roix_req_result", roix.ReqResult),
                       ("roix_server_stats_t", roix.ServerStats), ("roix_decode_info", roix.DecodeInfo),
-                      ("roix_absq_info", roix.AbsqInfo), ("roix_huff_info", roix.HuffInfo)):
+                      ("roix_absq_info", roix.AbsqInfo), ("roix_huff_info", roix.HuffInfo),
+                      ("roix_tune_result", roix.TuneResult)):
         assert L.roix_sizeof(name.encode()) == ctypes.sizeof(cls), name
     assert L.roix_sizeof(b"roix_component") == roix.COMP_BYTES == 48
     assert L.roix_sizeof(b"roix_row") == roix.ROW_BYTES == 32
@@ -93,6 +95,8 @@ def test_sync_argument_errors(lib):
     assert L.roix_abs_quantize(null, null, 0, 1.0, null, null, null) == roix.EINVAL
     assert L.roix_huff_encode(null, null, 0, null, null, null, 0, null, null) == roix.EINVAL
     assert L.roix_huff_decode(null, null, null, null, 0, 0, null, null, null) == roix.EINVAL
+    assert L.roix_autotune(null, null, roix.F32, d, eb, ctypes.byref(c), ctypes.byref(out), 1, None,
+                           ctypes.byref(roix.TuneResult()), null) == roix.EINVAL
 
 
 def test_served_calls_without_server(lib):
