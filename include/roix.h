@@ -358,8 +358,8 @@ roix_status roix_fused_background(roix_ctx* ctx, const float* d_in, roix_dims di
  * bit for bit.
  *   d_pixels  m uint8 pixels (e.g. the 8-bit normalised pixel section of
  *             Sec. 4.1.2), 16-byte aligned
- *   d_q       m uint8 outputs, 16-byte aligned; may be d_pixels (in place)
- *             but must not overlap it otherwise
+ *   d_q       m uint8 outputs, 16-byte aligned, not overlapping d_pixels
+ *             (the output is written while later passes still read pixels)
  *   d_info    device: status, n_groups (the number of groups), rounds (the
  *             fix-up rounds that ran) and finisher_chunks (chunks settled
  *             by the sequential pass; see below)
@@ -371,7 +371,7 @@ roix_status roix_fused_background(roix_ctx* ctx, const float* d_in, roix_dims di
  * on long exact ramps) are settled by a single-wave sequential pass, which
  * is correct but slow.  Asynchronous on `stream`.
  * Errors: ROIX_EINVAL (NULL ctx/d_info, NULL or misaligned buffers for
- * m > 0, m < 0, e_abs negative or NaN, partial overlap), ROIX_ENOMEM (arena
+ * m > 0, m < 0, e_abs negative or NaN, overlapping buffers), ROIX_ENOMEM (arena
  * too small), ROIX_EDEVICE. */
 typedef struct {
     int32_t status;

@@ -585,9 +585,9 @@ roix_status roix_abs_quantize(roix_ctx* ctx, const uint8_t* d_pixels, int64_t m,
     if (m > ((int64_t)1 << 40)) return ROIX_EINVAL;
     if (m > 0) {
         if (!d_pixels || !d_q || !aligned(d_pixels, 16) || !aligned(d_q, 16)) return ROIX_EINVAL;
-        // in place, or apart: a partial overlap would overwrite pixels not yet read
+        // apart: the output is written while later passes still read the pixels
         const uintptr_t a0 = (uintptr_t)d_pixels, b0 = (uintptr_t)d_q;
-        if (a0 != b0 && a0 < b0 + (uint64_t)m && b0 < a0 + (uint64_t)m) return ROIX_EINVAL;
+        if (a0 < b0 + (uint64_t)m && b0 < a0 + (uint64_t)m) return ROIX_EINVAL;
     }
     if (ctx->arena_bytes < absq_scratch_bytes(m)) return ROIX_ENOMEM;
     // integer pixels: |Q - D| <= E exactly when |Q - D| <= floor(E); groups span at most 2 floor(E)

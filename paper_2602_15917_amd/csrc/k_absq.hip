@@ -24,9 +24,12 @@
 //     long exact ramps);
 //  3. the value of every group that crosses a chunk end goes, from the chunk
 //     where the group ends, into a slot of the chunk where it starts;
-//  4. every chunk is scanned a last time from its settled entry: the running
-//     value of the open group is kept at its first pixel in LDS, a second
-//     sweep spreads the final values over the groups, and the tile is stored.
+//  4. the speculation already wrote its own groups' values (the running
+//     value of the open group kept at its first pixel in LDS, spread by a
+//     second sweep, the tile stored); every chunk is rescanned from its
+//     settled entry up to where its true chain meets the speculative one,
+//     the bytes before that point rewritten with the true groups' values and
+//     the group crossing the chunk end given its slot's value.
 // Chunks of a wave are staged through LDS as a 16 KB tile, loaded and stored
 // with coalesced 16-byte accesses; each chunk's 64 words are padded to 65 so
 // that the lanes' word-by-word reads fall in distinct banks.
@@ -201,9 +204,15 @@ __global__ void k_aq_init(AqArgs a) {
     a.ctl->finisher_chunks = 0ull;
 }
 
-// Speculation: every chunk from a group starting at its first pixel.
+// Speculation: every chunk from a group starting at its first pixel.  The
+// speculative chain's values are written as the output: every group after
+// the point where the true chain meets this one is a true group already, so
+// the last pass only repairs the part before that point and the group that
+// crosses the chunk end.  The running value of the open group is kept at its
+// first byte in LDS after every pixel, and a second sweep spreads them.
 __global__ __launch_bounds__(kWave) void k_aq_spec(AqArgs a) {
     __shared__ uint32_t lds[kWave * kAqStride];
+    __shared__ uint32_t hbs[kWave * 9];  // group starts of each lane's chunk, a bit per pixel
     const int lane = threadIdx.x;
     const uint32_t K = a.K;
     const unsigned long long ntiles = (a.nchunks + kWave - 1) / kWave;
@@ -212,40 +221,64 @@ __global__ __launch_bounds__(kWave) void k_aq_spec(AqArgs a) {
         __syncthreads();
         aq_load_tile(a, t, lds, lane);
         __syncthreads();
-        if (k >= a.nchunks) continue;
-        const uint32_t* row = lds + lane * kAqStride;
-        const int len = aq_len(a, k);
-        uint32_t mn = 255u, mx = 0u;
-        uint32_t* sh = reinterpret_cast<uint32_t*>(a.sheads + 2 * k);
-        int lh = 0;
+        if (k < a.nchunks) {
+            uint32_t* row = lds + lane * kAqStride;
+            uint32_t* hb = hbs + lane * 9;
+            uint8_t* bytes = reinterpret_cast<uint8_t*>(row);
+            const int len = aq_len(a, k);
+            uint32_t mn = 255u, mx = 0u;
+            uint32_t* sh = reinterpret_cast<uint32_t*>(a.sheads + 2 * k);
+            int lh = 0;
 #pragma unroll 1
-        for (int seg = 0; seg < kAqC / 32; ++seg) {
-            uint32_t hbw = 0u;
+            for (int seg = 0; seg < kAqC / 32; ++seg) {
+                uint32_t hbw = 0u;
 #pragma unroll
-            for (int w = 0; w < 8; ++w) {
-                const uint32_t word = row[seg * 8 + w];
+                for (int w = 0; w < 8; ++w) {
+                    const uint32_t word = row[seg * 8 + w];
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int jl = 4 * w + b;
-                    const int j = seg * 32 + jl;
-                    if (j < len) {
-                        const uint32_t v = (word >> (8 * b)) & 0xFFu;
-                        AQ_STEP(v, j == 0)
-                        lh = head ? j : lh;
-                        hbw |= head ? (1u << jl) : 0u;
+                    for (int b = 0; b < 4; ++b) {
+                        const int jl = 4 * w + b;
+                        const int j = seg * 32 + jl;
+                        if (j < len) {
+                            const uint32_t v = (word >> (8 * b)) & 0xFFu;
+                            AQ_STEP(v, j == 0)
+                            lh = head ? j : lh;
+                            hbw |= head ? (1u << jl) : 0u;
+                            bytes[lh] = (uint8_t)((mn + mx) >> 1);
+                        }
                     }
                 }
+                sh[seg] = hbw;
+                hb[seg] = hbw;
             }
-            sh[seg] = hbw;
+            AqState ex;
+            ex.mm = aq_pack(mn, mx);
+            ex.pad = 0u;
+            ex.head = k * (unsigned long long)kAqC + (unsigned long long)lh;
+            a.spec[k] = ex;
+            a.exitb[k] = ex;  // round parity 0
+            a.used[k] = AqState{0u, 0u, 0ull};
+            a.closev[k] = 0;
+            // spread each group's value from its first byte
+            uint32_t cur = 0u;
+#pragma unroll 1
+            for (int seg = 0; seg < kAqC / 32; ++seg) {
+                const uint32_t hbw = hb[seg];
+#pragma unroll
+                for (int w = 0; w < 8; ++w) {
+                    const uint32_t word = row[seg * 8 + w];
+                    uint32_t o = 0u;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        if ((hbw >> (4 * w + b)) & 1u) cur = (word >> (8 * b)) & 0xFFu;
+                        o |= cur << (8 * b);
+                    }
+                    row[seg * 8 + w] = o;
+                }
+            }
         }
-        AqState ex;
-        ex.mm = aq_pack(mn, mx);
-        ex.pad = 0u;
-        ex.head = k * (unsigned long long)kAqC + (unsigned long long)lh;
-        a.spec[k] = ex;
-        a.exitb[k] = ex;  // round parity 0
-        a.used[k] = AqState{0u, 0u, 0ull};
-        a.closev[k] = 0;
+        __syncthreads();
+        aq_store_tile(a, t, lds, lane);
     }
 }
 
@@ -370,82 +403,99 @@ __global__ __launch_bounds__(256) void k_aq_close(AqArgs a) {
     }
 }
 
-// The output: every group's value over its pixels; counts the groups.  The
-// scan stores the running value of the open group at its first pixel after
-// every pixel, so each group's first byte ends with its final value; a
-// second sweep spreads it over the group.
-__global__ __launch_bounds__(kWave) void k_aq_write(AqArgs a) {
-    __shared__ uint32_t lds[kWave * kAqStride];
-    __shared__ uint32_t hbs[kWave * 9];  // group starts of each lane's chunk, a bit per pixel
-    const int lane = threadIdx.x;
+// The output's repair: each chunk is rescanned from its settled entry (its
+// predecessor's final open group) until a group starts where a speculative
+// one does; the bytes before that point are rewritten with the true groups'
+// values (the entering group's from its slot), and the group open at the
+// chunk end gets its value from its slot.  A chunk whose true chain never
+// meets the speculative one is rewritten whole.  Counts the true groups.
+// Pixels are read 16 at a time from global memory, as far as the rescan
+// goes; bytes are written one by one.
+__device__ __forceinline__ void aq_fill(uint8_t* q, int from, int to, uint32_t v) {
+    for (int j = from; j < to; ++j) q[j] = (uint8_t)v;
+}
+
+__global__ __launch_bounds__(256) void k_aq_fix(AqArgs a) {
     const uint32_t K = a.K;
     const AqState* ex = a.exitb + (size_t)(kAqRounds & 1) * a.nchunks;
-    const unsigned long long ntiles = (a.nchunks + kWave - 1) / kWave;
     unsigned long long groups = 0;
-    for (unsigned long long t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const unsigned long long k = t * kWave + (unsigned long long)lane;
-        __syncthreads();
-        aq_load_tile(a, t, lds, lane);
-        __syncthreads();
-        if (k < a.nchunks) {
-            uint32_t* row = lds + lane * kAqStride;
-            uint32_t* hb = hbs + lane * 9;
-            uint8_t* bytes = reinterpret_cast<uint8_t*>(row);
-            const int len = aq_len(a, k);
-            AqState entry = {0u, 0u, 0ull};
-            if (k >= 1) entry = ex[k - 1];
-            const uint32_t lead = k >= 1 ? (uint32_t)a.gv[entry.head / kAqC] : 0u;
-            const uint32_t trail = (uint32_t)a.gv[k];
-            const bool none = entry.mm == 0u;
-            uint32_t mn = none ? 255u : (entry.mm & 0xFFu), mx = none ? 0u : ((entry.mm >> 8) & 0xFFu);
-            int s = -1;  // first pixel of the group being scanned (-1: the entering group)
-#pragma unroll 1
-            for (int seg = 0; seg < kAqC / 32; ++seg) {
-                uint32_t hbw = 0u;
-#pragma unroll
-                for (int w = 0; w < 8; ++w) {
-                    const uint32_t word = row[seg * 8 + w];
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const int jl = 4 * w + b;
-                        const int j = seg * 32 + jl;
-                        if (j < len) {
-                            const uint32_t v = (word >> (8 * b)) & 0xFFu;
-                            AQ_STEP(v, j == 0 && none)
-                            s = head ? j : s;
-                            hbw |= head ? (1u << jl) : 0u;
-                            if (s >= 0) bytes[s] = (uint8_t)((mn + mx) >> 1);
-                        }
-                    }
+    const unsigned long long n = (unsigned long long)gridDim.x * blockDim.x;
+    for (unsigned long long k = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; k < a.nchunks; k += n) {
+        const int len = aq_len(a, k);
+        const uint32_t* sh = reinterpret_cast<const uint32_t*>(a.sheads + 2 * k);
+        const AqState spec = a.spec[k];
+        const int spec_last = (int)(spec.head - k * (unsigned long long)kAqC);
+        uint8_t* q = a.Q + k * (unsigned long long)kAqC;
+        if (k == 0) {  // the sequence starts here: the true chain is the speculative one
+            int c = 0;
+            for (int i = 0; i < kAqC / 32; ++i) c += __popc(sh[i]);
+            groups += (unsigned long long)c;
+            if (a.nchunks > 1) aq_fill(q, spec_last, len, a.gv[0]);
+            continue;
+        }
+        const AqState entry = ex[k - 1];
+        const uint32_t lead = a.gv[entry.head / kAqC];
+        uint32_t mn = entry.mm & 0xFFu, mx = (entry.mm >> 8) & 0xFFu;
+        int s = -1;  // first pixel of the true group being scanned (-1: the entering group)
+        int p = -1;  // where the chains meet
+        int own = 0;  // true group starts before p
+        const uint4* d = reinterpret_cast<const uint4*>(a.D + k * (unsigned long long)kAqC);
+        uint4 blk = make_uint4(0u, 0u, 0u, 0u);
+        for (int j = 0; j < len && p < 0; ++j) {
+            if ((j & 15) == 0) {  // the next 16 pixels (whole within the buffer, or the last chunk's tail)
+                if (k * (unsigned long long)kAqC + (unsigned long long)j + 16ull <= a.m) {
+                    blk = d[j >> 4];
+                } else {
+                    uint32_t w[4] = {0u, 0u, 0u, 0u};
+                    for (int b = 0; b < 16 && j + b < len; ++b)
+                        w[b >> 2] |= (uint32_t)a.D[k * (unsigned long long)kAqC + j + b] << (8 * (b & 3));
+                    blk = make_uint4(w[0], w[1], w[2], w[3]);
                 }
-                hb[seg] = hbw;
-                groups += (unsigned long long)__popc(hbw);
             }
-            // spread the values: the entering group takes lead, the group
-            // open at the chunk end takes trail, the others their first byte
-            uint32_t cur = lead;
-#pragma unroll 1
-            for (int seg = 0; seg < kAqC / 32; ++seg) {
-                const uint32_t hbw = hb[seg];
-#pragma unroll
-                for (int w = 0; w < 8; ++w) {
-                    const uint32_t word = row[seg * 8 + w];
-                    uint32_t out = 0u;
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const int jl = 4 * w + b;
-                        if ((hbw >> jl) & 1u) cur = seg * 32 + jl == s ? trail : (word >> (8 * b)) & 0xFFu;
-                        out |= cur << (8 * b);
-                    }
-                    row[seg * 8 + w] = out;
+            const uint32_t wd = (j & 8) ? ((j & 4) ? blk.w : blk.z) : ((j & 4) ? blk.y : blk.x);
+            const uint32_t v = (wd >> (8 * (j & 3))) & 0xFFu;
+            const uint32_t nmn = v < mn ? v : mn, nmx = v > mx ? v : mx;
+            if (nmx - nmn > K) {  // a true group starts at j
+                if (s < 0) aq_fill(q, 0, j, lead);
+                else aq_fill(q, s, j, (mn + mx) >> 1);
+                if ((sh[j >> 5] >> (j & 31)) & 1u) {
+                    p = j;
+                    break;
                 }
+                ++own;
+                s = j;
+                mn = mx = v;
+            } else {
+                mn = nmn;
+                mx = nmx;
             }
         }
-        __syncthreads();
-        aq_store_tile(a, t, lds, lane);
+        if (p >= 0) {  // from p on the speculative chain's values stand, but for the group crossing the end
+            int c = own;
+            for (int i = 0; i < kAqC / 32; ++i) {
+                const uint32_t w = sh[i];
+                const int lo = i * 32;
+                const uint32_t m = p <= lo ? ~0u : (p >= lo + 32 ? 0u : (~0u << (p - lo)));
+                c += __popc(w & m);
+            }
+            groups += (unsigned long long)c;
+            if (k + 1 < a.nchunks) aq_fill(q, spec_last, len, a.gv[k]);
+            // the last chunk's final group ends with the sequence: its value is the speculation's
+        } else {  // never met: the true groups throughout
+            groups += (unsigned long long)own;
+            const uint32_t tv = s < 0 ? lead : (k + 1 < a.nchunks ? a.gv[k] : ((mn + mx) >> 1));
+            aq_fill(q, s < 0 ? 0 : s, len, tv);
+        }
     }
     groups = wave_sum(groups);
-    if (lane == 0) a.partial[blockIdx.x] = groups;
+    __shared__ unsigned long long part[256 / kWave];
+    if (threadIdx.x % kWave == 0) part[threadIdx.x / kWave] = groups;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long sum = 0;
+        for (int i = 0; i < 256 / kWave; ++i) sum += part[i];
+        a.partial[blockIdx.x] = sum;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_aq_finalize(AqArgs a, int nparts, int32_t status) {
@@ -510,17 +560,18 @@ hipError_t launch_absq(const LaunchCtx& lc, const uint8_t* D, int64_t m, uint32_
     a.partial = (unsigned long long*)p;
     a.info = info;
     timer_begin(lc.timer, ST_ABSQ, lc.stream);
+    // chunk-per-thread kernels (close, repair): at most kAqMaxGrid partial counts
+    const int cgrid = (int)((a.nchunks + 255) / 256 < 4096 ? (a.nchunks + 255) / 256 : 4096);
     hipLaunchKernelGGL(k_aq_init, dim3(1), dim3(64), 0, lc.stream, a);
     if (m > 0) {
         hipLaunchKernelGGL(k_aq_spec, dim3(grid), dim3(kWave), 0, lc.stream, a);
         for (int r = 1; r <= kAqRounds; ++r)
             hipLaunchKernelGGL(k_aq_round, dim3(grid), dim3(kWave), 0, lc.stream, a, r);
         hipLaunchKernelGGL(k_aq_finish, dim3(1), dim3(kWave), 0, lc.stream, a);
-        const int cgrid = (int)((a.nchunks + 255) / 256 < 4096 ? (a.nchunks + 255) / 256 : 4096);
         hipLaunchKernelGGL(k_aq_close, dim3(cgrid), dim3(256), 0, lc.stream, a);
-        hipLaunchKernelGGL(k_aq_write, dim3(grid), dim3(kWave), 0, lc.stream, a);
+        hipLaunchKernelGGL(k_aq_fix, dim3(cgrid), dim3(256), 0, lc.stream, a);
     }
-    hipLaunchKernelGGL(k_aq_finalize, dim3(1), dim3(256), 0, lc.stream, a, m > 0 ? grid : 0, 0);
+    hipLaunchKernelGGL(k_aq_finalize, dim3(1), dim3(256), 0, lc.stream, a, m > 0 ? cgrid : 0, 0);
     timer_end(lc.timer, ST_ABSQ, lc.stream);
     return hipGetLastError();
 }

@@ -3,7 +3,7 @@ through the C ABI: roix_abs_quantize against the oracle's sequential scan,
 byte for byte with the same group count, on seeded sequences of every kind
 the scan meets (uniform noise, random walks, X-CT-like pixel sections,
 repeated values, exact ramps whose group chains never meet), at sizes from
-empty to several tiles with ragged tails, in place, and at the full size of
+empty to several tiles with ragged tails, and at the full size of
 the benchmark's pixel section."""
 import ctypes
 
@@ -73,17 +73,19 @@ def test_abs_quantize_equals_oracle(env, kind, n):
         assert q.tobytes() == oq.tobytes()
 
 
-def test_abs_quantize_wide_tolerance_and_in_place(env):
+def test_abs_quantize_wide_tolerance_and_overlap(env):
     d = sequence("section", 300_001, 71)
     for e in (127.0, 128.0, 500.0):  # one group over the whole sequence
         log(f"[case] abs_quantize wide E={e}")
         q, info = run(env, d, e)
         st, oq, og = oracle.abs_quantize(d, e)
         assert og == 1 and info.n_groups == 1 and q.tobytes() == oq.tobytes()
-    log("[case] abs_quantize in place")
-    st, oq, og = oracle.abs_quantize(d, 2.0)
-    q, info = run(env, d, 2.0, inplace=True)
-    assert q.tobytes() == oq.tobytes() and info.n_groups == og
+    # the output may not overlap the pixels, not even exactly
+    ctx, roix, torch = env
+    t = torch.from_numpy(d).to("cuda:0")
+    with pytest.raises(roix.RoixError) as ei:
+        ctx.abs_quantize(t, 2.0, t)
+    assert ei.value.status == roix.EINVAL
 
 
 def test_abs_quantize_long_ramp_uses_the_finisher(env):
