@@ -170,7 +170,7 @@ __device__ __forceinline__ constexpr uint64_t quad_reach() {
 }
 __device__ __forceinline__ void load_quad(const uint16_t* in, uint64_t v, float (&x)[4]) {
     const uint64_t v0 = v & ~1ull;
-    const v3u32_t q = __builtin_nontemporal_load(reinterpret_cast<const v3u32_t*>(in + v0));
+    const v3u32_t q = *(reinterpret_cast<const v3u32_t*>(in + v0));
     const uint32_t sh = (uint32_t)(v - v0) * 16u;
     const uint64_t lo = ((uint64_t)q.y << 32) | q.x, hi = ((uint64_t)q.z << 32) | q.y;
     const uint64_t a = sh ? (lo >> 16) | ((uint64_t)q.z << 48) : lo;  // values v .. v+3
@@ -550,7 +550,7 @@ __device__ __forceinline__ void emit_chunk_near(const T* __restrict__ in, const 
 #pragma unroll
                 for (int i = 0; i < 4; ++i) xv[k][i] = 0.0f;
             } else if constexpr (sizeof(T) == 4) {
-                const v4u32_t q = __builtin_nontemporal_load(reinterpret_cast<const v4u32_t*>(base + vi * S_));
+                const v4u32_t q = *(reinterpret_cast<const v4u32_t*>(base + vi * S_));
                 xv[k][0] = __uint_as_float(q.x);
                 xv[k][1] = __uint_as_float(q.y);
                 xv[k][2] = __uint_as_float(q.z);
@@ -744,22 +744,22 @@ __device__ __forceinline__ void emit_chunk_p16(const uint16_t* __restrict__ px, 
             const int64_t aa = full ? (int64_t)va - (int64_t)oa : -(int64_t)odd0;
             sa[k] = 16u * oa;
             if (whole) {  // uniform; elements V0 - odd0 .. V0 - odd0 + 9 exist
-                const v4u32_t q = __builtin_nontemporal_load(reinterpret_cast<const v4u32_t*>(base + aa));
+                const v4u32_t q = *(reinterpret_cast<const v4u32_t*>(base + aa));
                 la[k][0] = q.x;
                 la[k][1] = q.y;
                 la[k][2] = q.z;
                 la[k][3] = q.w;
-                la[k][4] = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(base + aa + 8));
+                la[k][4] = *(reinterpret_cast<const uint32_t*>(base + aa + 8));
                 if (starts) {
                     const uint32_t ob = full ? ((odd0 + vb) & 1u) : odd0;
                     const int64_t ab = full ? (int64_t)vb - (int64_t)ob : -(int64_t)odd0;
                     sb[k] = 16u * ob;
-                    const v4u32_t r = __builtin_nontemporal_load(reinterpret_cast<const v4u32_t*>(base + ab));
+                    const v4u32_t r = *(reinterpret_cast<const v4u32_t*>(base + ab));
                     lb[k][0] = r.x;
                     lb[k][1] = r.y;
                     lb[k][2] = r.z;
                     lb[k][3] = r.w;
-                    lb[k][4] = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(base + ab + 8));
+                    lb[k][4] = *(reinterpret_cast<const uint32_t*>(base + ab + 8));
                 }
             } else {
 #pragma unroll
