@@ -19,14 +19,17 @@
 // count (for an
 // exclusive scan of the block sizes), and the codes, ORed into the block's
 // words in LDS at the positions a wave prefix sum gives, then copied out.
-// Decoding: a lane per block with a 64-bit bit window, a 10-bit lookup table
-// and a canonical search for longer codes.
+// Decoding: a lane per block with a 64-bit bit window fed a 16-byte load
+// ahead, an 11-bit lookup table that yields one or two codes, and a
+// canonical search for longer codes.
 #include "common.h"
 
 namespace roix {
 
 constexpr int kHfBlock = 4096;   // input bytes per block
-constexpr int kHfPeek = 10;      // bits of the decoder's lookup table
+constexpr int kHfPeek = 11;      // bits of the decoder's lookup table
+constexpr int kHfRound = 8;      // decoder steps between refills (2 bytes each at most)
+constexpr int kHfRing = 36;      // LDS bytes of a lane's 32-byte output ring (stride against bank conflicts)
 
 struct HfState {
     unsigned long long hist[256];
@@ -81,16 +84,20 @@ __global__ __launch_bounds__(256) void k_hf_build(HfState* S, uint8_t* lengths_o
     __shared__ unsigned long long w[511];
     __shared__ int parent[511];
     __shared__ int sym[256];
-    __shared__ int ns_sh;
+    __shared__ int ns_sh, maxl_sh, bad_sh;
     __shared__ uint32_t bl_count[34], next_code[34];
     __shared__ unsigned long long hs[256];
     __shared__ uint8_t lens[256];
-    __shared__ uint32_t codes[256];
     const int t = threadIdx.x;
     const unsigned long long c = S->hist[t];
     hs[t] = c;
     // rank of this byte among the used ones by (count, byte value)
-    if (t == 0) ns_sh = 0;
+    if (t == 0) {
+        ns_sh = 0;
+        maxl_sh = 0;
+        bad_sh = 0;
+    }
+    if (t < 34) bl_count[t] = 0u;
     __syncthreads();
     if (c) atomicAdd(&ns_sh, 1);
     int rank = 0;
@@ -100,57 +107,63 @@ __global__ __launch_bounds__(256) void k_hf_build(HfState* S, uint8_t* lengths_o
     }
     __syncthreads();
     if (c) sym[rank] = t;
-    lens[t] = 0;
     __syncthreads();
     const int ns = ns_sh;
-    if (t == 0) {
-        int maxl = 0;
-        bool ok = true;
-        if (ns == 1) {
-            lens[sym[0]] = 1;
-            maxl = 1;
-        } else if (ns > 1) {
-            for (int i = 0; i < ns; ++i) w[i] = hs[sym[i]];
-            int lq = 0, mq = ns, next = ns;
-            while (next < 2 * ns - 1) {
-                int pick[2];
-                for (int k = 0; k < 2; ++k) {
-                    if (lq < ns && (mq >= next || w[lq] <= w[mq])) pick[k] = lq++;
-                    else pick[k] = mq++;
-                }
-                w[next] = w[pick[0]] + w[pick[1]];
-                parent[pick[0]] = next;
-                parent[pick[1]] = next;
-                ++next;
+    // the two-queue merge (sequential: each step depends on the last)
+    if (t == 0 && ns > 1) {
+        for (int i = 0; i < ns; ++i) w[i] = hs[sym[i]];
+        int lq = 0, mq = ns, next = ns;
+        while (next < 2 * ns - 1) {
+            int pick[2];
+            for (int k = 0; k < 2; ++k) {
+                if (lq < ns && (mq >= next || w[lq] <= w[mq])) pick[k] = lq++;
+                else pick[k] = mq++;
             }
-            // depths, the root first (stored over the weights, no longer needed)
-            int* depth = reinterpret_cast<int*>(w);
-            depth[2 * ns - 2] = 0;
-            for (int i = 2 * ns - 3; i >= 0; --i) depth[i] = depth[parent[i]] + 1;
-            for (int i = 0; i < ns; ++i) {
-                const int d = depth[i];
-                maxl = d > maxl ? d : maxl;
-                if (d > 32) ok = false;
-                lens[sym[i]] = (uint8_t)(d > 32 ? 0 : d);
-            }
+            w[next] = w[pick[0]] + w[pick[1]];
+            parent[pick[0]] = next;
+            parent[pick[1]] = next;
+            ++next;
         }
-        S->max_len = maxl;
-        if (!ok) S->status = ROIX_ERANGE;
-        // canonical codes
-        for (int i = 0; i < 34; ++i) bl_count[i] = next_code[i] = 0u;
-        for (int i = 0; i < 256; ++i) bl_count[lens[i]]++;
-        bl_count[0] = 0u;
-        unsigned long long cc = 0ull;
-        for (int b = 1; b <= 32; ++b) {
-            cc = (cc + bl_count[b - 1]) << 1;
-            next_code[b] = (uint32_t)cc;
-        }
-        for (int i = 0; i < 256; ++i) codes[i] = lens[i] ? next_code[lens[i]]++ : 0u;
     }
     __syncthreads();
-    S->len[t] = lens[t];
-    S->code[t] = codes[t];
-    if (lengths_out) lengths_out[t] = lens[t];
+    // a leaf's code length is its depth: the steps from it up to the root
+    int len = 0;
+    if (c) {
+        if (ns == 1) {
+            len = 1;
+        } else {
+            for (int v = rank; v != 2 * ns - 2; v = parent[v]) ++len;
+        }
+        atomicMax(&maxl_sh, len);
+        if (len > 32) {
+            bad_sh = 1;
+            len = 0;
+        }
+    }
+    lens[t] = (uint8_t)len;
+    if (len) atomicAdd(&bl_count[len], 1u);
+    __syncthreads();
+    if (t == 0) {  // canonical codes: the first code of each length
+        S->max_len = maxl_sh;
+        if (bad_sh) S->status = ROIX_ERANGE;
+        unsigned long long cc = 0ull;
+        next_code[0] = 0u;
+        for (int b = 1; b <= 32; ++b) {
+            cc = (cc + (b > 1 ? bl_count[b - 1] : 0u)) << 1;
+            next_code[b] = (uint32_t)cc;
+        }
+    }
+    __syncthreads();
+    // within a length, codes follow the byte values
+    uint32_t code = 0u;
+    if (len) {
+        uint32_t r = 0u;
+        for (int u = 0; u < t; ++u) r += lens[u] == len ? 1u : 0u;
+        code = next_code[len] + r;
+    }
+    S->len[t] = (uint8_t)len;
+    S->code[t] = code;
+    if (lengths_out) lengths_out[t] = (uint8_t)len;
 }
 
 // ------------------------------------------------------------ encoding
@@ -196,16 +209,80 @@ __global__ __launch_bounds__(kWave) void k_hf_count(const uint8_t* __restrict__ 
     }
 }
 
+// One window of a block's output words, [pb, pb + nw): each lane gathers
+// its bits [pos, pos + bits) in a 64-bit accumulator (acc_n bits, most
+// significant first) and writes the words that fall in the window; a lane's
+// interior words are its own (plain LDS stores), its first and last may be
+// shared with the neighbours (ORed).  P: code and length packed in one
+// entry, code << 6 | length.
+template <bool P>
+__device__ __forceinline__ void hf_emit_window(const uint4 (&v)[4], int cnt, uint32_t pos, uint32_t bits,
+                                               uint32_t pb, uint32_t nw, const uint32_t* lc, const uint8_t* len,
+                                               const uint32_t* code, uint32_t* buf) {
+    const uint32_t first_w = pos >> 5, last_w = (pos + bits - 1u) >> 5;
+    if (bits == 0u || last_w < pb || first_w >= pb + nw) return;
+    unsigned long long acc = 0ull;
+    uint32_t acc_n = pos & 31u;  // the word starts before the lane's first bit: zeros there
+    uint32_t wi = first_w;
+    uint4 q[4] = {v[0], v[1], v[2], v[3]};
+#pragma unroll 1
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t ww[4] = {q[0].x, q[0].y, q[0].z, q[0].w};
+        q[0] = q[1];  // the next 16 bytes move up (no indexing by i)
+        q[1] = q[2];
+        q[2] = q[3];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (16 * i + k < cnt) {
+                const uint32_t sy = (ww[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+                uint32_t L, c;
+                if constexpr (P) {
+                    const uint32_t ent = lc[sy];
+                    L = ent & 63u;
+                    c = ent >> 6;
+                } else {
+                    L = len[sy];
+                    c = code[sy];
+                }
+                acc |= (unsigned long long)c << (64u - acc_n - L);
+                acc_n += L;
+                if (acc_n >= 32u) {
+                    const uint32_t word = (uint32_t)(acc >> 32);
+                    const uint32_t r = wi - pb;
+                    if (r < nw) {
+                        if (wi == first_w || wi == last_w) atomicOr(&buf[r], word);
+                        else buf[r] = word;
+                    }
+                    ++wi;
+                    acc <<= 32;
+                    acc_n -= 32u;
+                }
+            }
+        }
+    }
+    if (acc_n > 0u && wi - pb < nw) atomicOr(&buf[wi - pb], (uint32_t)(acc >> 32));
+}
+
+// A wave per block: the lanes' bit counts, their exclusive prefix, then the
+// codes ORed into the block's words in LDS and copied out.  The LDS window
+// holds kHfBufWords words (8 bits a byte); a block that needs more (long
+// codes) goes through it in several windows.
+constexpr uint32_t kHfBufWords = 1024;
+
 __global__ __launch_bounds__(kWave) void k_hf_encode(const uint8_t* __restrict__ in, unsigned long long n,
                                                      const HfState* S, const unsigned long long* block_off,
                                                      uint32_t* __restrict__ payload, unsigned long long cap_words) {
     __shared__ uint8_t len[256];
     __shared__ uint32_t code[256];
-    __shared__ uint32_t buf[kHfBlock];  // a block's words: 32 bits per byte at most
+    __shared__ uint32_t lc[256];
+    __shared__ uint32_t buf[kHfBufWords];
     const int lane = threadIdx.x;
+    const bool packed = S->max_len <= 26;  // uniform
     for (int i = lane; i < 256; i += kWave) {
-        len[i] = S->len[i];
-        code[i] = S->code[i];
+        const uint32_t L = S->len[i], c = S->code[i];
+        len[i] = (uint8_t)L;
+        code[i] = c;
+        lc[i] = packed ? (c << 6) | L : 0u;
     }
     __syncthreads();
     if (S->status != 0) return;
@@ -214,8 +291,6 @@ __global__ __launch_bounds__(kWave) void k_hf_encode(const uint8_t* __restrict__
         const unsigned long long w0 = block_off[b], w1 = block_off[b + 1];
         if (w1 > cap_words) continue;  // the payload does not hold this block (reported as ETRUNC)
         const uint32_t words = (uint32_t)(w1 - w0);
-        __syncthreads();
-        for (uint32_t i = lane; i < words; i += kWave) buf[i] = 0u;
         uint4 v[4];
         const uint32_t bits = hf_lane_bits(in, n, b, lane, len, v);
         // exclusive prefix of the lanes' bit counts
@@ -226,41 +301,20 @@ __global__ __launch_bounds__(kWave) void k_hf_encode(const uint8_t* __restrict__
             if (lane >= o) pos += u;
         }
         pos -= bits;
-        __syncthreads();
         const unsigned long long p0 = b * kHfBlock + 64ull * lane;
         const int cnt = p0 >= n ? 0 : (n - p0 >= 64 ? 64 : (int)(n - p0));
-        // the lane's bits [pos, pos + bits) gather in a 64-bit accumulator
-        // (acc_n bits, most significant first); whole words go out with
-        // plain stores except the lane's first and last, which neighbours
-        // may share (ORed)
-        const uint32_t first_w = pos >> 5, last_w = (pos + bits - 1u) >> 5;
-        unsigned long long acc = 0ull;
-        uint32_t acc_n = pos & 31u;  // the word starts before the lane's first bit: zeros there
-        uint32_t wi = first_w;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const uint32_t ww[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                if (16 * i + k < cnt) {
-                    const uint32_t sy = (ww[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-                    const uint32_t L = len[sy];
-                    acc |= (unsigned long long)code[sy] << (64u - acc_n - L);
-                    acc_n += L;
-                    if (acc_n >= 32u) {
-                        const uint32_t word = (uint32_t)(acc >> 32);
-                        if (wi == first_w || wi == last_w) atomicOr(&buf[wi], word);
-                        else buf[wi] = word;
-                        ++wi;
-                        acc <<= 32;
-                        acc_n -= 32u;
-                    }
-                }
-            }
+        for (uint32_t pb = 0; pb < words; pb += kHfBufWords) {
+            const uint32_t nw = words - pb < kHfBufWords ? words - pb : kHfBufWords;
+            __syncthreads();  // the last window's copy is done
+            for (uint32_t i = lane; i < nw; i += kWave) buf[i] = 0u;
+            __syncthreads();
+            if (packed)
+                hf_emit_window<true>(v, cnt, pos, bits, pb, nw, lc, len, code, buf);
+            else
+                hf_emit_window<false>(v, cnt, pos, bits, pb, nw, lc, len, code, buf);
+            __syncthreads();
+            for (uint32_t i = lane; i < nw; i += kWave) payload[w0 + pb + i] = buf[i];
         }
-        if (bits > 0u && acc_n > 0u) atomicOr(&buf[wi], (uint32_t)(acc >> 32));
-        __syncthreads();
-        for (uint32_t i = lane; i < words; i += kWave) payload[w0 + i] = buf[i];
     }
 }
 
@@ -284,113 +338,233 @@ __global__ void k_hf_finalize(const HfState* S, const unsigned long long* block_
 
 // ------------------------------------------------------------ decoding
 
+// Decoder tables, built in LDS by each workgroup.  The lookup entry of the
+// next kHfPeek bits holds the first code's byte and length (bits 0-7,
+// 16-20) and, when a second whole code follows inside the same kHfPeek
+// bits, that one's byte and length (bits 8-15, 21-25; length 0: none).
+// A first length of 0 marks a code longer than the table.
 struct HfDecode {
     uint32_t first[34];   // first canonical code of each length
     uint32_t count[34];   // codes of each length
     uint32_t index[34];   // position of a length's first byte in sym
     uint8_t sym[256];     // bytes by (length, value)
-    uint16_t peek[1 << kHfPeek];  // top bits -> len << 8 | byte (len 0: longer code)
+    uint32_t peek[1 << kHfPeek];
+    int maxl;             // longest code length in use
 };
+
+// The code of length <= lmax at the top of the kHfPeek-bit value e
+// (canonical: a length-L code c is valid when c - first[L] < count[L]).
+__device__ __forceinline__ bool hf_short_code(const HfDecode& T, uint32_t e, int lmax, int& L, uint32_t& s) {
+    for (L = 1; L <= lmax; ++L) {
+        const uint32_t c = e >> (kHfPeek - L);
+        if (c - T.first[L] < T.count[L]) {
+            s = T.sym[T.index[L] + (c - T.first[L])];
+            return true;
+        }
+    }
+    return false;
+}
+
+// Four payload words from quad-aligned word a; words at or past w1 read as
+// zero (they are never consumed) and the quad is one 16-byte load when the
+// payload is 16-byte aligned and the quad lies inside it.
+__device__ __forceinline__ void hf_quad(const uint32_t* __restrict__ payload, unsigned long long a,
+                                        unsigned long long w1, unsigned long long pw, bool vec, uint32_t (&q)[4]) {
+    if (vec && a + 4 <= pw) {
+        const uint4 v = *reinterpret_cast<const uint4*>(payload + a);
+        q[0] = v.x;
+        q[1] = v.y;
+        q[2] = v.z;
+        q[3] = v.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) q[k] = a + k < w1 ? payload[a + k] : 0u;
+    }
+}
 
 __global__ __launch_bounds__(256) void k_hf_decode(const uint8_t* lengths, const unsigned long long* block_off,
                                                    const uint32_t* payload, unsigned long long payload_words,
-                                                   unsigned long long n, uint8_t* out, HfState* S) {
+                                                   unsigned long long n, uint8_t* out, HfState* S, int vec) {
     __shared__ HfDecode T;
     __shared__ int bad_table;
-    __shared__ uint32_t fill[34];
+    __shared__ unsigned long long kraft;  // in units of 2^-32
+    __shared__ uint8_t lens[256];
+    __shared__ __align__(16) uint8_t ring_sh[kHfRing * 256];
     const int t = threadIdx.x;
+    const int Lt = lengths[t];
+    lens[t] = (uint8_t)Lt;
+    if (t < 34) T.count[t] = 0u;
     if (t == 0) {
         bad_table = 0;
-        for (int i = 0; i < 34; ++i) T.count[i] = 0u;
-        unsigned long long kraft = 0ull;  // in units of 2^-32
-        int used = 0;
-        for (int i = 0; i < 256; ++i) {
-            const int L = lengths[i];
-            if (L > 32) bad_table = 1;
-            else if (L) {
-                T.count[L]++;
-                kraft += 1ull << (32 - L);
-                ++used;
-            }
-        }
-        if (kraft > (1ull << 32) || (n > 0 && used == 0)) bad_table = 1;
+        kraft = 0ull;
+    }
+    __syncthreads();
+    if (Lt > 32) bad_table = 1;
+    else if (Lt) {
+        atomicAdd(&T.count[Lt], 1u);
+        atomicAdd(&kraft, 1ull << (32 - Lt));
+    }
+    __syncthreads();
+    if (t == 0) {
+        if (kraft > (1ull << 32) || (n > 0 && kraft == 0ull)) bad_table = 1;
         uint32_t pos = 0u;
         unsigned long long c = 0ull;
+        T.count[0] = 0u;
         for (int L = 1; L <= 32; ++L) {
-            c = (c + (L > 1 ? T.count[L - 1] : 0u)) << 1;
+            c = (c + T.count[L - 1]) << 1;
             T.first[L] = (uint32_t)c;
             T.index[L] = pos;
             pos += T.count[L];
         }
-        fill[0] = 0u;
-        for (int L = 1; L <= 32; ++L) fill[L] = T.index[L];
-        for (int i = 0; i < 256; ++i)
-            if (lengths[i] && lengths[i] <= 32) T.sym[fill[lengths[i]]++] = (uint8_t)i;
+        T.first[0] = T.index[0] = 0u;
+        T.first[33] = T.count[33] = T.index[33] = 0u;
+        int ml = 0;
+        for (int L = 1; L <= 32; ++L) ml = T.count[L] ? L : ml;
+        T.maxl = ml;
     }
     __syncthreads();
-    for (int e = t; e < (1 << kHfPeek); e += blockDim.x) {
-        uint16_t val = 0;
-        for (int L = 1; L <= kHfPeek && val == 0; ++L) {
-            const uint32_t c = (uint32_t)e >> (kHfPeek - L);
-            if (T.count[L] && c - T.first[L] < T.count[L])
-                val = (uint16_t)((L << 8) | T.sym[T.index[L] + (c - T.first[L])]);
-        }
-        T.peek[e] = val;
+    if (Lt >= 1 && Lt <= 32) {  // byte t's place among the bytes of its length
+        uint32_t r = 0u;
+        for (int u = 0; u < t; ++u) r += lens[u] == Lt ? 1u : 0u;
+        T.sym[T.index[Lt] + r] = (uint8_t)t;
     }
     __syncthreads();
     if (bad_table) {
         if (t == 0) atomicCAS(&S->status, 0, ROIX_EINVAL);
         return;
     }
+    for (int e = t; e < (1 << kHfPeek); e += blockDim.x) {
+        uint32_t val = 0u, s1 = 0u, s2 = 0u;
+        int L1 = 0, L2 = 0;
+        if (hf_short_code(T, (uint32_t)e, kHfPeek, L1, s1)) {
+            val = s1 | ((uint32_t)L1 << 16);
+            if (L1 < kHfPeek && hf_short_code(T, ((uint32_t)e << L1) & ((1u << kHfPeek) - 1u), kHfPeek - L1, L2, s2))
+                val |= (s2 << 8) | ((uint32_t)L2 << 21);
+        }
+        T.peek[e] = val;
+    }
+    __syncthreads();
     const unsigned long long nb = (n + kHfBlock - 1) / kHfBlock;
-    for (unsigned long long b = (unsigned long long)blockIdx.x * blockDim.x + t; b < nb;
-         b += (unsigned long long)gridDim.x * blockDim.x) {
-        const unsigned long long w0 = block_off[b], w1 = block_off[b + 1];
-        if ((b == 0 && w0 != 0) || w1 < w0 || w1 > payload_words) {
+    const int maxl = T.maxl;
+    uint8_t* ring = ring_sh + kHfRing * t;  // this lane's output bytes, 16 at a time to HBM
+    // The wave goes in rounds: at the top of a round each lane takes the
+    // quad it loaded the round before, asks for the next, and stores 16
+    // output bytes; then kHfRound steps decode from registers only (a lane
+    // whose bits run short before its next quad arrives waits a round).
+    for (unsigned long long base = (unsigned long long)blockIdx.x * blockDim.x; base < nb;
+         base += (unsigned long long)gridDim.x * blockDim.x) {
+        const unsigned long long b = base + t;
+        bool live = b < nb;
+        unsigned long long w0 = 0ull, w1 = 0ull;
+        if (live) {
+            w0 = block_off[b];
+            w1 = block_off[b + 1];
+            if ((b == 0 && w0 != 0) || w1 < w0 || w1 > payload_words) {
+                atomicCAS(&S->status, 0, ROIX_EINVAL);
+                live = false;
+            }
+        }
+        const unsigned long long i0 = b * kHfBlock;
+        uint32_t left = live ? (uint32_t)(i0 + kHfBlock < n ? kHfBlock : n - i0) : 0u;  // bytes to decode
+        uint32_t rem = (uint32_t)(w1 - w0);  // payload words not yet in the window
+        // quad A holds payload words qa..qa+3 (the next one to take: ci),
+        // quad B the four after it once valid, Lq the quad in flight
+        unsigned long long qa = w0 & ~3ull;
+        uint32_t ci = (uint32_t)(w0 & 3ull);
+        uint32_t A[4] = {0u, 0u, 0u, 0u}, B[4] = {0u, 0u, 0u, 0u}, Lq[4] = {0u, 0u, 0u, 0u};
+        bool bvalid = false, pending = false;
+        if (live && rem > 0u) hf_quad(payload, qa, w1, payload_words, vec, A);
+        // A arrives here: the steps below then wait on nothing but LDS
+        __builtin_amdgcn_s_waitcnt(0);
+        unsigned long long window = 0ull;  // bits, the next one most significant
+        int have = 0;
+        bool ok = true;
+        uint32_t wr = 0u, rd = 0u;      // ring bytes written, stored
+        unsigned long long g = i0;      // output position of the next store
+        while (__any(ok && left > 0u)) {
+            if (pending) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) B[k] = Lq[k];
+                bvalid = true;
+                pending = false;
+            }
+            if (ci == 4u && bvalid) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) A[k] = B[k];
+                ci = 0u;
+                qa += 4;
+                bvalid = false;
+            }
+            if (!bvalid && rem > 4u - ci) {  // words past quad A
+                hf_quad(payload, qa + 4, w1, payload_words, vec, Lq);
+                pending = true;
+            }
+            if (wr - rd >= 16u) {
+                const uint32_t* r32 = reinterpret_cast<const uint32_t*>(ring + (rd & 31u));
+                *reinterpret_cast<uint4*>(out + g) = make_uint4(r32[0], r32[1], r32[2], r32[3]);
+                g += 16;
+                rd += 16u;
+            }
+#pragma unroll 1
+            for (int it = 0; it < kHfRound; ++it) {
+                // take a word into the window (no branch)
+                const bool take = have <= 32 && ci < 4u && rem > 0u;
+                const uint32_t word = ci == 0u ? A[0] : ci == 1u ? A[1] : ci == 2u ? A[2] : A[3];
+                const unsigned long long add = (unsigned long long)word << ((32 - have) & 63);
+                window |= take ? add : 0ull;
+                have += take ? 32 : 0;
+                ci += take ? 1u : 0u;
+                rem -= take ? 1u : 0u;
+                const bool shift = ci == 4u && bvalid;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) A[k] = shift ? B[k] : A[k];
+                ci = shift ? 0u : ci;
+                qa += shift ? 4ull : 0ull;
+                bvalid = bvalid && !shift;
+                // with words still outside the window, decode only what is sure to fit
+                if (!ok || left == 0u || (rem > 0u && have < maxl)) continue;
+                const uint32_t pk = T.peek[window >> (64 - kHfPeek)];
+                int L = (int)((pk >> 16) & 31u);
+                uint32_t v = pk;
+                if (L == 0) {  // a code longer than the table
+                    for (L = kHfPeek + 1; L <= 32; ++L) {  // L = 33 after the loop: no code
+                        const uint32_t c = (uint32_t)(window >> (64 - L));
+                        if (c - T.first[L] < T.count[L]) {
+                            v = T.sym[T.index[L] + (c - T.first[L])];
+                            break;
+                        }
+                    }
+                }
+                const int L2 = (int)(pk >> 21);
+                const bool pair = L2 != 0 && left > 1u && L + L2 <= have;
+                L += pair ? L2 : 0;
+                const uint32_t k = pair ? 2u : 1u;
+                if (L > 32 || L > have) {  // no code, or past the block's payload
+                    ok = false;
+                    continue;
+                }
+                window <<= L;
+                have -= L;
+                // both bytes always: a second byte of a single code lands
+                // past the ring's live bytes and is overwritten later
+                ring[wr & 31u] = (uint8_t)v;
+                ring[(wr + 1u) & 31u] = (uint8_t)(v >> 8);
+                wr += k;
+                left -= k;
+            }
+        }
+        if (!live) continue;
+        if (!ok) {
             atomicCAS(&S->status, 0, ROIX_EINVAL);
             continue;
         }
-        const unsigned long long e = (b + 1) * kHfBlock < n ? (b + 1) * kHfBlock : n;
-        unsigned long long wp = w0;          // next payload word to read
-        unsigned long long window = 0ull;    // bits, the next one most significant
-        int have = 0;
-        bool ok = true;
-        uint32_t acc = 0u;
-        for (unsigned long long i = b * kHfBlock; i < e; ++i) {
-            if (have <= 32 && wp < w1) {
-                window |= (unsigned long long)payload[wp++] << (32 - have);
-                have += 32;
-            }
-            const uint16_t pk = T.peek[window >> (64 - kHfPeek)];
-            int L = pk >> 8;
-            uint32_t s = pk & 0xFFu;
-            if (L == 0) {  // a code longer than the table
-                for (L = kHfPeek + 1; L <= 32; ++L) {
-                    const uint32_t c = (uint32_t)(window >> (64 - L));
-                    if (T.count[L] && c - T.first[L] < T.count[L]) {
-                        s = T.sym[T.index[L] + (c - T.first[L])];
-                        break;
-                    }
-                }
-            }
-            if (L > 32 || L > have) {
-                ok = false;
-                break;
-            }
-            window <<= L;
-            have -= L;
-            acc |= s << (8 * (i & 3));
-            if ((i & 3) == 3 || i + 1 == e) {
-                const unsigned long long a = i & ~3ull;
-                if (a + 4 <= n) {
-                    *reinterpret_cast<uint32_t*>(out + a) = acc;
-                } else {
-                    for (unsigned long long k = a; k < n; ++k) out[k] = (uint8_t)(acc >> (8 * (k - a)));
-                }
-                acc = 0u;
-            }
+        if (wr - rd >= 16u) {
+            const uint32_t* r32 = reinterpret_cast<const uint32_t*>(ring + (rd & 31u));
+            *reinterpret_cast<uint4*>(out + g) = make_uint4(r32[0], r32[1], r32[2], r32[3]);
+            g += 16;
+            rd += 16u;
         }
-        if (!ok) atomicCAS(&S->status, 0, ROIX_EINVAL);
+        for (uint32_t k = rd; k < wr; ++k) out[g + (k - rd)] = ring[k & 31u];  // the block's last bytes
     }
 }
 
@@ -453,8 +627,9 @@ hipError_t launch_huff_decode(const LaunchCtx& lc, const uint8_t* lengths, const
     if (nb > 0) {
         const int64_t g = (nb + 255) / 256;
         const int grid = (int)(g < (int64_t)lc.grid_stream ? g : (int64_t)lc.grid_stream);
+        const int vec = ((uintptr_t)payload & 15u) == 0u ? 1 : 0;
         hipLaunchKernelGGL(k_hf_decode, dim3(grid), dim3(256), 0, lc.stream, lengths, block_off, payload,
-                           (unsigned long long)payload_words, N, out, S);
+                           (unsigned long long)payload_words, N, out, S, vec);
     }
     hipLaunchKernelGGL(k_hf_decode_finalize, dim3(1), dim3(1), 0, lc.stream, (const HfState*)S, N, info);
     timer_end(lc.timer, ST_HUFF, lc.stream);

@@ -87,6 +87,42 @@ def test_huffman_equals_oracle(env, kind, n):
         assert back.cpu().numpy().tobytes() == d.tobytes()
 
 
+@pytest.mark.parametrize("kind", ["section", "uniform", "two"])
+@pytest.mark.parametrize("n", [17, 4097, 100_003, (1 << 20) + 5])
+def test_huffman_decode_unaligned_payload(env, kind, n):
+    # a payload that is 4-byte but not 16-byte aligned: the decoder reads it
+    # word by word instead of in 16-byte loads
+    ctx, roix, torch = env
+    d = data(kind, n, 7700 + n % 101)
+    st, oln, ooff, opay = oracle.huff_encode(d)
+    words = int(ooff[-1])
+    log(f"[case] huffman decode, unaligned payload kind={kind} n={n}")
+    buf = torch.zeros(words + 4, dtype=torch.int32, device="cuda:0")
+    buf[1:1 + words] = torch.from_numpy(opay.view(np.int32)).to("cuda:0")
+    p = buf[1:1 + words]
+    assert st == 0 and p.data_ptr() % 16 == 4
+    back, dinfo = ctx.huff_decode(torch.from_numpy(oln).to("cuda:0"),
+                                  torch.from_numpy(ooff.astype(np.int64)).to("cuda:0"), p, words, n)
+    torch.cuda.synchronize()
+    assert roix.huff_info(dinfo).status == 0
+    assert back.cpu().numpy().tobytes() == d.tobytes()
+
+
+def test_huffman_decode_truncated_payload(env):
+    # the last block's offset cut short: its codes run past its words
+    ctx, roix, torch = env
+    d = data("section", 50_000, 19)
+    st, oln, ooff, opay = oracle.huff_encode(d)
+    o = ooff.astype(np.int64).copy()
+    o[-1] -= 1
+    words = int(o[-1])
+    log("[case] huffman decode, last block one word short")
+    back, dinfo = ctx.huff_decode(torch.from_numpy(oln).to("cuda:0"), torch.from_numpy(o).to("cuda:0"),
+                                  torch.from_numpy(opay.view(np.int32)).to("cuda:0"), words, d.size)
+    torch.cuda.synchronize()
+    assert roix.huff_info(dinfo).status == roix.EINVAL
+
+
 def test_huffman_of_an_extraction_stream(env):
     # the packed code stream of an extraction (16-bit codes) and the paper
     # quantiser's 8-bit output
@@ -118,6 +154,33 @@ def test_huffman_lengths_beyond_32_bits(env):
     st, *_ = oracle.huff_encode(d)
     ln, off, pay, info = gpu_encode(env, d)
     assert st == oracle.ERANGE and info.status == roix_status(env, "ERANGE") and info.max_len == 33
+
+
+@pytest.mark.parametrize("nsym", [26, 29, 31])
+def test_huffman_long_codes_and_wide_blocks(env, nsym):
+    # Fibonacci counts over nsym bytes give codes of up to nsym - 1 bits
+    # (25: code and length share one table entry; 28 and 30: they do not);
+    # the rarest bytes come first, so the first block needs 1491 to 2131
+    # payload words and the encoder goes through it in several LDS windows
+    ctx, roix, torch = env
+    fib = [1, 1]
+    while len(fib) < nsym:
+        fib.append(fib[-1] + fib[-2])
+    d = np.repeat(np.arange(nsym, dtype=np.uint8), fib)
+    np.random.default_rng(nsym).shuffle(d[4096:])
+    log(f"[case] huffman long codes nsym={nsym} ({d.size} bytes)")
+    st, oln, ooff, opay = oracle.huff_encode(d)
+    ln, off, pay, info = gpu_encode(env, d)
+    assert st == 0 and info.status == 0 and info.max_len == nsym - 1
+    assert int(ooff[1]) > 1024
+    assert np.array_equal(ln, oln) and np.array_equal(off, ooff)
+    words = int(ooff[-1])
+    assert pay[:words].cpu().numpy().view(np.uint32).tobytes() == opay.tobytes()
+    back, dinfo = ctx.huff_decode(torch.as_tensor(ln).to("cuda:0"), torch.from_numpy(off.astype(np.int64)).to("cuda:0"),
+                                  pay, words, d.size)
+    torch.cuda.synchronize()
+    assert roix.huff_info(dinfo).status == 0
+    assert back.cpu().numpy().tobytes() == d.tobytes()
 
 
 def roix_status(env, name):
