@@ -209,80 +209,106 @@ __global__ __launch_bounds__(kWave) void k_hf_count(const uint8_t* __restrict__ 
     }
 }
 
-// One window of a block's output words, [pb, pb + nw): each lane gathers
-// its bits [pos, pos + bits) in a 64-bit accumulator (acc_n bits, most
-// significant first) and writes the words that fall in the window; a lane's
-// interior words are its own (plain LDS stores), its first and last may be
-// shared with the neighbours (ORed).  P: code and length packed in one
-// entry, code << 6 | length.
+// One lane's 32 bytes of a half block, emitted into the window [pb, pb + nw)
+// of the block's output words: the lane's bits [pos, pos + bits) gather in
+// a 64-bit accumulator (acc_n bits, most significant first) and the words
+// that fall in the window are written; a lane's interior words are its own
+// (plain LDS stores), its first and last may be shared with the neighbours
+// (ORed).  e[k]: the table entry of byte k, code << 6 | length when P, the
+// length alone otherwise (the code then read again by the byte in q).
 template <bool P>
-__device__ __forceinline__ void hf_emit_window(const uint4 (&v)[4], int cnt, uint32_t pos, uint32_t bits,
-                                               uint32_t pb, uint32_t nw, const uint32_t* lc, const uint8_t* len,
-                                               const uint32_t* code, uint32_t* buf) {
+__device__ __forceinline__ void hf_emit_half(const uint32_t (&e)[32], const uint4 (&q)[2], int cnt, uint32_t pos,
+                                             uint32_t bits, uint32_t pb, uint32_t nw, const uint32_t* code,
+                                             uint32_t* buf) {
     const uint32_t first_w = pos >> 5, last_w = (pos + bits - 1u) >> 5;
     if (bits == 0u || last_w < pb || first_w >= pb + nw) return;
+    const uint32_t ww[8] = {q[0].x, q[0].y, q[0].z, q[0].w, q[1].x, q[1].y, q[1].z, q[1].w};
     unsigned long long acc = 0ull;
     uint32_t acc_n = pos & 31u;  // the word starts before the lane's first bit: zeros there
     uint32_t wi = first_w;
-    uint4 q[4] = {v[0], v[1], v[2], v[3]};
-#pragma unroll 1
-    for (int i = 0; i < 4; ++i) {
-        const uint32_t ww[4] = {q[0].x, q[0].y, q[0].z, q[0].w};
-        q[0] = q[1];  // the next 16 bytes move up (no indexing by i)
-        q[1] = q[2];
-        q[2] = q[3];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            if (16 * i + k < cnt) {
-                const uint32_t sy = (ww[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-                uint32_t L, c;
-                if constexpr (P) {
-                    const uint32_t ent = lc[sy];
-                    L = ent & 63u;
-                    c = ent >> 6;
-                } else {
-                    L = len[sy];
-                    c = code[sy];
+    for (int k = 0; k < 32; ++k) {
+        if (k < cnt) {
+            const uint32_t L = P ? (e[k] & 63u) : e[k];
+            const uint32_t c = P ? (e[k] >> 6) : code[(ww[k >> 2] >> (8 * (k & 3))) & 0xFFu];
+            acc |= (unsigned long long)c << (64u - acc_n - L);
+            acc_n += L;
+            if (acc_n >= 32u) {
+                const uint32_t word = (uint32_t)(acc >> 32);
+                const uint32_t r = wi - pb;
+                if (r < nw) {
+                    if (wi == first_w || wi == last_w) atomicOr(&buf[r], word);
+                    else buf[r] = word;
                 }
-                acc |= (unsigned long long)c << (64u - acc_n - L);
-                acc_n += L;
-                if (acc_n >= 32u) {
-                    const uint32_t word = (uint32_t)(acc >> 32);
-                    const uint32_t r = wi - pb;
-                    if (r < nw) {
-                        if (wi == first_w || wi == last_w) atomicOr(&buf[r], word);
-                        else buf[r] = word;
-                    }
-                    ++wi;
-                    acc <<= 32;
-                    acc_n -= 32u;
-                }
+                ++wi;
+                acc <<= 32;
+                acc_n -= 32u;
             }
         }
     }
     if (acc_n > 0u && wi - pb < nw) atomicOr(&buf[wi - pb], (uint32_t)(acc >> 32));
 }
 
-// A wave per block: the lanes' bit counts, their exclusive prefix, then the
-// codes ORed into the block's words in LDS and copied out.  The LDS window
-// holds kHfBufWords words (8 bits a byte); a block that needs more (long
-// codes) goes through it in several windows.
+// Half h of block b in one window: lane l takes bytes 2048 h + 32 l ..
+// + 31, so a half is 2 KB read contiguously and its bits follow the lanes in
+// order.  Returns the half's bit count.
+template <bool P>
+__device__ __forceinline__ uint32_t hf_half(const uint8_t* __restrict__ in, unsigned long long n,
+                                            unsigned long long p0, uint32_t carry, uint32_t pb, uint32_t nw,
+                                            const uint32_t* tab, const uint32_t* code, uint32_t* buf) {
+    const int lane = threadIdx.x;
+    const unsigned long long p = p0 + 32ull * lane;
+    const int cnt = p >= n ? 0 : (n - p >= 32 ? 32 : (int)(n - p));
+    uint4 q[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const unsigned long long pi = p + 16ull * i;
+        if (pi + 16 <= n) {
+            q[i] = ld_stream(reinterpret_cast<const uint4*>(in + pi));
+        } else {
+            uint32_t w4[4] = {0u, 0u, 0u, 0u};
+            for (int k = 0; k < 16; ++k)
+                if (pi + k < n) w4[k >> 2] |= (uint32_t)in[pi + k] << (8 * (k & 3));
+            q[i] = make_uint4(w4[0], w4[1], w4[2], w4[3]);
+        }
+    }
+    const uint32_t ww[8] = {q[0].x, q[0].y, q[0].z, q[0].w, q[1].x, q[1].y, q[1].z, q[1].w};
+    uint32_t e[32];
+    uint32_t bits = 0u;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        e[k] = k < cnt ? tab[(ww[k >> 2] >> (8 * (k & 3))) & 0xFFu] : 0u;
+        bits += P ? (e[k] & 63u) : e[k];
+    }
+    // inclusive prefix of the lanes' bit counts
+    uint32_t inc = bits;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t u = __shfl_up(inc, o);
+        if (lane >= o) inc += u;
+    }
+    hf_emit_half<P>(e, q, cnt, carry + inc - bits, bits, pb, nw, code, buf);
+    return (uint32_t)__shfl(inc, kWave - 1);
+}
+
+// A wave per block: each half's table entries, bit counts and their prefix,
+// then the codes ORed into the block's words in LDS and copied out.  The
+// LDS window holds kHfBufWords words (8 bits a byte); a block that needs
+// more (long codes) goes through it in several windows.
 constexpr uint32_t kHfBufWords = 1024;
 
 __global__ __launch_bounds__(kWave) void k_hf_encode(const uint8_t* __restrict__ in, unsigned long long n,
                                                      const HfState* S, const unsigned long long* block_off,
                                                      uint32_t* __restrict__ payload, unsigned long long cap_words) {
-    __shared__ uint8_t len[256];
     __shared__ uint32_t code[256];
-    __shared__ uint32_t lc[256];
+    __shared__ uint32_t tab[256];  // code << 6 | length when every length is at most 26, else the length
     __shared__ uint32_t buf[kHfBufWords];
     const int lane = threadIdx.x;
     const bool packed = S->max_len <= 26;  // uniform
     for (int i = lane; i < 256; i += kWave) {
         const uint32_t L = S->len[i], c = S->code[i];
-        len[i] = (uint8_t)L;
         code[i] = c;
-        lc[i] = packed ? (c << 6) | L : 0u;
+        tab[i] = packed ? (c << 6) | L : L;
     }
     __syncthreads();
     if (S->status != 0) return;
@@ -291,27 +317,18 @@ __global__ __launch_bounds__(kWave) void k_hf_encode(const uint8_t* __restrict__
         const unsigned long long w0 = block_off[b], w1 = block_off[b + 1];
         if (w1 > cap_words) continue;  // the payload does not hold this block (reported as ETRUNC)
         const uint32_t words = (uint32_t)(w1 - w0);
-        uint4 v[4];
-        const uint32_t bits = hf_lane_bits(in, n, b, lane, len, v);
-        // exclusive prefix of the lanes' bit counts
-        uint32_t pos = bits;
-#pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-            const uint32_t u = __shfl_up(pos, o);
-            if (lane >= o) pos += u;
-        }
-        pos -= bits;
-        const unsigned long long p0 = b * kHfBlock + 64ull * lane;
-        const int cnt = p0 >= n ? 0 : (n - p0 >= 64 ? 64 : (int)(n - p0));
         for (uint32_t pb = 0; pb < words; pb += kHfBufWords) {
             const uint32_t nw = words - pb < kHfBufWords ? words - pb : kHfBufWords;
             __syncthreads();  // the last window's copy is done
             for (uint32_t i = lane; i < nw; i += kWave) buf[i] = 0u;
             __syncthreads();
-            if (packed)
-                hf_emit_window<true>(v, cnt, pos, bits, pb, nw, lc, len, code, buf);
-            else
-                hf_emit_window<false>(v, cnt, pos, bits, pb, nw, lc, len, code, buf);
+            uint32_t carry = 0u;
+#pragma unroll 1
+            for (int h = 0; h < 2; ++h) {
+                const unsigned long long p0 = b * kHfBlock + (unsigned long long)h * (kHfBlock / 2);
+                carry += packed ? hf_half<true>(in, n, p0, carry, pb, nw, tab, code, buf)
+                                : hf_half<false>(in, n, p0, carry, pb, nw, tab, code, buf);
+            }
             __syncthreads();
             for (uint32_t i = lane; i < nw; i += kWave) payload[w0 + pb + i] = buf[i];
         }
