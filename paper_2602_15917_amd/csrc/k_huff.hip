@@ -168,44 +168,41 @@ __global__ __launch_bounds__(256) void k_hf_build(HfState* S, uint8_t* lengths_o
 
 // ------------------------------------------------------------ encoding
 
-// bits of the 64 bytes lane `lane` holds of block b (len from LDS)
-__device__ __forceinline__ uint32_t hf_lane_bits(const uint8_t* in, unsigned long long n, unsigned long long b, int lane,
-                                                 const uint8_t* len, uint4* v) {
-    const unsigned long long p0 = b * kHfBlock + 64ull * lane;
-    uint32_t bits = 0u;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const unsigned long long p = p0 + 16ull * i;
-        if (p + 16 <= n) {
-            v[i] = ld_stream(reinterpret_cast<const uint4*>(in + p));
-        } else {
-            uint32_t ww[4] = {0u, 0u, 0u, 0u};
-            for (int k = 0; k < 16; ++k)
-                if (p + k < n) ww[k >> 2] |= (uint32_t)in[p + k] << (8 * (k & 3));
-            v[i] = make_uint4(ww[0], ww[1], ww[2], ww[3]);
-        }
-    }
-    const int cnt = p0 >= n ? 0 : (n - p0 >= 64 ? 64 : (int)(n - p0));
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint32_t ww[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
-#pragma unroll
-        for (int k = 0; k < 16; ++k)
-            if (16 * i + k < cnt) bits += len[(ww[k >> 2] >> (8 * (k & 3))) & 0xFFu];
-    }
-    return bits;
-}
-
+// Bit count of each block: lane l takes bytes 1024 i + 16 l .. + 15 of the
+// block (i = 0..3), so each load instruction reads 1 KB contiguously.
 __global__ __launch_bounds__(kWave) void k_hf_count(const uint8_t* __restrict__ in, unsigned long long n,
                                                     const HfState* S, unsigned long long* block_words) {
     __shared__ uint8_t len[256];
     for (int i = threadIdx.x; i < 256; i += kWave) len[i] = S->len[i];
     __syncthreads();
+    const int lane = threadIdx.x;
     const unsigned long long nb = (n + kHfBlock - 1) / kHfBlock;
     for (unsigned long long b = blockIdx.x; b < nb; b += gridDim.x) {
         uint4 v[4];
-        const uint32_t bits = wave_sum(hf_lane_bits(in, n, b, threadIdx.x, len, v));
-        if (threadIdx.x == 0) block_words[b] = (bits + 31u) / 32u;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const unsigned long long p = b * kHfBlock + 1024ull * i + 16ull * lane;
+            if (p + 16 <= n) {
+                v[i] = ld_stream(reinterpret_cast<const uint4*>(in + p));
+            } else {  // the stream's last bytes
+                uint32_t w4[4] = {0u, 0u, 0u, 0u};
+                for (int k = 0; k < 16; ++k)
+                    if (p + k < n) w4[k >> 2] |= (uint32_t)in[p + k] << (8 * (k & 3));
+                v[i] = make_uint4(w4[0], w4[1], w4[2], w4[3]);
+            }
+        }
+        uint32_t bits = 0u;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const unsigned long long p = b * kHfBlock + 1024ull * i + 16ull * lane;
+            const int cnt = p >= n ? 0 : (n - p >= 16 ? 16 : (int)(n - p));
+            const uint32_t ww[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                if (k < cnt) bits += len[(ww[k >> 2] >> (8 * (k & 3))) & 0xFFu];
+        }
+        bits = wave_sum(bits);
+        if (lane == 0) block_words[b] = (bits + 31u) / 32u;
     }
 }
 
@@ -264,7 +261,7 @@ __device__ __forceinline__ uint32_t hf_half(const uint8_t* __restrict__ in, unsi
     for (int i = 0; i < 2; ++i) {
         const unsigned long long pi = p + 16ull * i;
         if (pi + 16 <= n) {
-            q[i] = ld_stream(reinterpret_cast<const uint4*>(in + pi));
+            q[i] = *reinterpret_cast<const uint4*>(in + pi);
         } else {
             uint32_t w4[4] = {0u, 0u, 0u, 0u};
             for (int k = 0; k < 16; ++k)
