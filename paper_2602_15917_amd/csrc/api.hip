@@ -88,6 +88,7 @@ size_t roix::fixed_bytes(const Geom& g, int proxy) {
     b += align256((size_t)g.nrows * 16);                  // span_desc
     b += 2 * align256((size_t)(g.N / kEmitChunk + 2) * 4);  // chunk_row, slow_chunks
     b += align256((size_t)(kScanBlocks + 1) * 8);         // scan tmp
+    b += align256((size_t)g.nz * 4);                      // slice_thr
     b += 6 * 256;                                         // run-array alignment slack
     return b;
 }
@@ -117,6 +118,7 @@ bool roix::carve_at(void* base, size_t bytes, const Geom& g, Layout* L, int prox
     L->chunk_row = (uint32_t*)take((size_t)(g.N / kEmitChunk + 2) * 4);
     L->slow_chunks = (uint32_t*)take((size_t)(g.N / kEmitChunk + 2) * 4);
     L->scan_tmp = (uint64_t*)take((size_t)(kScanBlocks + 1) * 8);
+    L->slice_thr = (int32_t*)take((size_t)g.nz * 4);
     const size_t used = (size_t)(p - (uint8_t*)base) + 6 * 256;
     uint64_t cap = (bytes - used) / kRunBytes;
     const uint64_t w = worst_runs(g);
@@ -187,9 +189,10 @@ static roix_status dev_err(hipError_t e) { return e == hipSuccess ? ROIX_OK : RO
 
 // mask -> runs -> union of a whole volume (everything between the proxy and
 // the flattening)
-static hipError_t label_runs(const LaunchCtx& lc, const Geom& g, const Layout& L, int connectivity) {
+static hipError_t label_runs(const LaunchCtx& lc, const Geom& g, const Layout& L, int connectivity,
+                             const int32_t* slice_thr = nullptr) {
     hipError_t e;
-    if ((e = launch_mask_runs(lc, g, L)) != hipSuccess) return e;
+    if ((e = launch_mask_runs(lc, g, L, slice_thr)) != hipSuccess) return e;
     if ((e = launch_scan_u32(lc, L.row_nruns, L.run_off, g.nrows, nullptr, &L.S->n_runs, L.run_off + g.nrows,
                              L.scan_tmp, L.S, L.run_cap, ROIX_ENOMEM)) != hipSuccess)
         return e;
@@ -212,7 +215,8 @@ hipError_t roix::components_and_keep(const LaunchCtx& lc, const Geom& g, const L
 static hipError_t label_and_keep(const LaunchCtx& lc, const Geom& g, const Layout& L, const roix_criterion* crit,
                                  roix_component* comps, int64_t comps_cap) {
     hipError_t e;
-    if ((e = label_runs(lc, g, L, crit->connectivity)) != hipSuccess) return e;
+    const int32_t* st = crit->thr == ROIX_THR_OTSU_SLICE ? L.slice_thr : nullptr;
+    if ((e = label_runs(lc, g, L, crit->connectivity, st)) != hipSuccess) return e;
     return components_and_keep(lc, g, L, crit, comps, comps_cap);
 }
 
@@ -239,7 +243,7 @@ roix_status roix::enqueue_fused(const LaunchCtx& lc, const Geom& g, Layout L, co
     const int kind = dtype == ROIX_F32 ? 0 : 1;
     // the fused range + 16-bit proxy pass needs the bound before the range
     // (absolute) and whole 16-byte vectors per row
-    // per-slice thresholds rewrite the 1-byte proxy: the two-pass flow
+    // per-slice thresholds compare 1-byte bins slice by slice: the two-pass flow
     const bool per_slice = crit->thr == ROIX_THR_OTSU_SLICE;
     const bool p16 = !per_slice && L.fine_slots && dtype == ROIX_F32 && eb.mode == ROIX_EB_ABS && aligned(d_in, 16);
     if (p16) {
@@ -254,7 +258,7 @@ roix_status roix::enqueue_fused(const LaunchCtx& lc, const Geom& g, Layout L, co
         ROIX_TRY(launch_quant_hist(lc, d_in, kind, g, L.S, L.proxy, fixed));
     }
     if (per_slice)
-        ROIX_TRY(launch_slice_otsu(lc, g, L.proxy, L.S, out->d_slice_thr));
+        ROIX_TRY(launch_slice_otsu(lc, g, L.proxy, L.S, L.slice_thr, out->d_slice_thr));
     else
         ROIX_TRY(launch_threshold(lc, L.S, crit));
     ROIX_TRY(label_and_keep(lc, g, L, crit, out->d_comps, out->comps_cap));

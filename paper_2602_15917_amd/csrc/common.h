@@ -96,6 +96,7 @@ struct Layout {
     uint32_t* chunk_row;    // N / kEmitChunk + 2: span holding the first code of each emit chunk
     uint32_t* slow_chunks;  // N / kEmitChunk + 2: chunks left to the general chunk kernel
     uint64_t* scan_tmp;     // kScanBlocks + 1
+    int32_t* slice_thr;     // nz: threshold bin of each slice (per-slice Otsu)
     uint32_t* fine_slots;   // kQrBlocks * kQrFine, or null (no 16-bit proxy)
     unsigned long long* fine_total;  // kQrFine
     uint64_t run_cap;
@@ -284,7 +285,7 @@ hipError_t launch_otsu(const LaunchCtx& lc, DevState* S, bool fixed);
 // the resolve step has set)
 hipError_t launch_threshold(const LaunchCtx& lc, DevState* S, const roix_criterion* crit);
 
-hipError_t launch_mask_runs(const LaunchCtx& lc, const Geom& g, const Layout& L);
+hipError_t launch_mask_runs(const LaunchCtx& lc, const Geom& g, const Layout& L, const int32_t* slice_thr = nullptr);
 // streamed volumes (FIXED threshold, ABS bound): mask parameters at open,
 // then per slab of rows [r0, r1) the range, mask words and run counts
 hipError_t launch_serve_open(const LaunchCtx& lc, DevState* S, double eb_value, double fixed_value);
@@ -326,7 +327,8 @@ hipError_t launch_background(const LaunchCtx& lc, const void* in, roix_dtype dt,
 // queued chunks for it (p16 == 1 and n_slow > 0)
 hipError_t launch_background_if(const LaunchCtx& lc, const float* in, const BgRef& bg, const Geom& g, DevState* S,
                                 int when);
-hipError_t launch_slice_otsu(const LaunchCtx& lc, const Geom& g, uint8_t* proxy, DevState* S, int32_t* slice_thr);
+hipError_t launch_slice_otsu(const LaunchCtx& lc, const Geom& g, const uint8_t* proxy, DevState* S, int32_t* thr,
+                             int32_t* slice_thr_out);
 size_t absq_scratch_bytes(int64_t m);
 size_t huff_scratch_bytes();
 hipError_t launch_huff_encode(const LaunchCtx& lc, const uint8_t* in, int64_t n, uint8_t* lengths,

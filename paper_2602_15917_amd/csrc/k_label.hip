@@ -72,13 +72,14 @@ __device__ __forceinline__ void mask_load64(const uint8_t* proxy, int64_t wbase,
 }
 
 // zero bytes are never above the threshold, so the loads' zero fill is empty mask
-__device__ __forceinline__ uint64_t mask_words64(const uint4 (&v)[4], uint32_t TL, uint32_t TR) {
+__device__ __forceinline__ uint64_t mask_words64(const uint4 (&v)[4], const uint32_t (&TL)[4],
+                                                 const uint32_t (&TR)[4]) {
     const int lane = threadIdx.x % kWave;
     uint32_t h[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-        h[k] = gt_bytes4(v[k].x, TL, TR) | (gt_bytes4(v[k].y, TL, TR) << 4) | (gt_bytes4(v[k].z, TL, TR) << 8) |
-               (gt_bytes4(v[k].w, TL, TR) << 12);
+        h[k] = gt_bytes4(v[k].x, TL[k], TR[k]) | (gt_bytes4(v[k].y, TL[k], TR[k]) << 4) |
+               (gt_bytes4(v[k].z, TL[k], TR[k]) << 8) | (gt_bytes4(v[k].w, TL[k], TR[k]) << 12);
     const uint32_t h01 = h[0] | (h[1] << 16), h23 = h[2] | (h[3] << 16);
     const int k = lane >> 4, m4 = (lane & 15) * 4;
     uint64_t word = 0;
@@ -181,13 +182,26 @@ __device__ __forceinline__ WordLane word_lane(int64_t row0, int64_t W, int64_t n
     return wl;
 }
 
+// SWAR constants of "byte > t" for the slice of row `row` (per-slice
+// thresholds thr[z]; z0 = the slice of a row at or before `row`).
+__device__ __forceinline__ void slice_consts(const int32_t* __restrict__ thr, int64_t row, int64_t z0, int64_t ny,
+                                             uint32_t& TL, uint32_t& TR) {
+    int64_t z = z0;
+    while (row >= (z + 1) * ny) ++z;
+    const uint32_t T = 255u - (uint32_t)thr[z];
+    TR = T * 0x01010101u;
+    TL = (T & 0x7Fu) * 0x01010101u;
+}
+
 // One 64-bit mask word per lane (SWAR byte compares on 64 proxy bytes), run
 // starts = 1-bits whose left neighbour (previous bit, or the previous lane's
-// top bit) is 0, per-row run counts by a segmented wave scan.
+// top bit) is 0, per-row run counts by a segmented wave scan.  slice_thr
+// (1-byte proxy only): a threshold bin per z-slice instead of one.
 template <bool P16>
 __device__ __forceinline__ void mask_runs_body(const uint8_t* __restrict__ proxy, int64_t nx, int64_t nrows, int64_t W,
                                                DevState* S, uint64_t* __restrict__ maskbits,
-                                               uint32_t* __restrict__ row_nruns) {
+                                               uint32_t* __restrict__ row_nruns, const int32_t* __restrict__ slice_thr,
+                                               int64_t ny) {
     // 1-byte proxy: bin > threshold bin, by SWAR byte compares
     const uint32_t T = 255u - (uint32_t)S->proxy_thr;
     const uint32_t TR = T * 0x01010101u, TL = (T & 0x7Fu) * 0x01010101u;
@@ -245,13 +259,30 @@ __device__ __forceinline__ void mask_runs_body(const uint8_t* __restrict__ proxy
 #pragma unroll
                 for (int u = 0; u < 2; ++u) mask_load64(proxy, (rowA + u * R) * W, rows_at(rowA + u * R) * W, v[u]);
 #pragma unroll
-                for (int u = 0; u < 2; ++u) finish(mask_words64(v[u], TL, TR), rowA + u * R);
+                for (int u = 0; u < 2; ++u) {
+                    const int64_t row0 = rowA + u * R;
+                    uint32_t tl[4] = {TL, TL, TL, TL}, tr[4] = {TR, TR, TR, TR};
+                    if (slice_thr) {  // uniform
+                        // load k of this lane holds word 16 k + lane / 4 of the step
+                        const int64_t r0 = row0 < nrows ? row0 : nrows - 1;
+                        const int64_t z0 = r0 / ny;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const int64_t rr = (16 * k + lane / 4) / W;
+                            const int64_t rk = rr < R && row0 + rr < nrows ? row0 + rr : r0;
+                            slice_consts(slice_thr, rk, z0, ny, tl[k], tr[k]);
+                        }
+                    }
+                    finish(mask_words64(v[u], tl, tr), row0);
+                }
             }
         }
     } else {
         // long rows: one row per wave, 64 words per step, carries between steps
         for (int64_t row = wave; row < nrows; row += nwaves) {
             uint32_t carry = 0, total = 0;
+            uint32_t tl = TL, tr = TR;
+            if (!P16 && slice_thr) slice_consts(slice_thr, row, row / ny, ny, tl, tr);
             for (int64_t w0 = 0; w0 < W; w0 += kWave) {
                 const int64_t w = w0 + lane;
                 uint64_t m = 0;
@@ -259,7 +290,7 @@ __device__ __forceinline__ void mask_runs_body(const uint8_t* __restrict__ proxy
                     if constexpr (P16)
                         m = mask_word16(proxy16 + row * P + 64 * w, Q2, T2);
                     else
-                        m = mask_word(proxy + row * P + 64 * w, TL, TR);
+                        m = mask_word(proxy + row * P + 64 * w, tl, tr);
                     if (w == W - 1) m &= lastmask;
                 }
                 const uint32_t hi = (uint32_t)(m >> 32);
@@ -288,20 +319,21 @@ __device__ __forceinline__ void mask_runs_body(const uint8_t* __restrict__ proxy
 // The proxy's kind is device data (the fused pass decides it); the branch is uniform.
 __global__ __launch_bounds__(kBlock) void k_mask_runs(const uint8_t* __restrict__ proxy, int64_t nx, int64_t nrows,
                                                       int64_t W, DevState* S, uint64_t* __restrict__ maskbits,
-                                                      uint32_t* __restrict__ row_nruns) {
+                                                      uint32_t* __restrict__ row_nruns,
+                                                      const int32_t* __restrict__ slice_thr, int64_t ny) {
     if (block_exit_l(S)) return;
     if (S->p16)
-        mask_runs_body<true>(proxy, nx, nrows, W, S, maskbits, row_nruns);
+        mask_runs_body<true>(proxy, nx, nrows, W, S, maskbits, row_nruns, nullptr, ny);
     else
-        mask_runs_body<false>(proxy, nx, nrows, W, S, maskbits, row_nruns);
+        mask_runs_body<false>(proxy, nx, nrows, W, S, maskbits, row_nruns, slice_thr, ny);
 }
 
-hipError_t launch_mask_runs(const LaunchCtx& lc, const Geom& g, const Layout& L) {
+hipError_t launch_mask_runs(const LaunchCtx& lc, const Geom& g, const Layout& L, const int32_t* slice_thr) {
     timer_begin(lc.timer, ST_MASK_RUNS, lc.stream);
     const int64_t R = g.W <= kWave ? kWave / g.W : 1;
     int grid = grid_for((g.nrows + R - 1) / R, kBlock / kWave, lc.grid_mask);
     hipLaunchKernelGGL(k_mask_runs, dim3(grid), dim3(kBlock), 0, lc.stream, (const uint8_t*)L.proxy, g.nx, g.nrows,
-                       g.W, L.S, L.maskbits, L.row_nruns);
+                       g.W, L.S, L.maskbits, L.row_nruns, slice_thr, g.ny);
     timer_end(lc.timer, ST_MASK_RUNS, lc.stream);
     return hipGetLastError();
 }

@@ -1111,27 +1111,16 @@ hipError_t launch_otsu(const LaunchCtx& lc, DevState* S, bool fixed) {
 // ------------------------------------------------------ per-slice Otsu
 
 // One workgroup per z-slice (grid-stride over slices): the histogram of the
-// slice's 1-byte proxy (bins over the volume's code range), two-class Otsu
-// on it with the same binary64 expression and first-maximum rule as k_otsu,
-// then the slice's proxy bytes rewritten as clamp(bin - t + 127, 0, 255): the
-// mask's single test "byte > 127" is then "bin > t" of each slice, and the
-// mask kernel runs unchanged.  16 copies of the LDS counters keep lanes that
-// hold the same bin from colliding.
+// slice's 1-byte proxy (bins over the volume's code range) and two-class
+// Otsu on it, with the same binary64 expression and first-maximum rule as
+// k_otsu.  The slice's threshold bin goes to thr[z]; the mask kernel then
+// tests "bin > thr[z]" row by row.  16 copies of the LDS counters keep lanes
+// that hold the same bin from colliding.
 constexpr int kSliceCopies = 16;
 
-__device__ __forceinline__ uint32_t slice_remap(uint32_t w, int32_t ts) {
-    uint32_t o = 0u;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        int32_t b = (int32_t)((w >> (8 * k)) & 0xFFu) - ts + 127;
-        b = b < 0 ? 0 : (b > 255 ? 255 : b);
-        o |= (uint32_t)b << (8 * k);
-    }
-    return o;
-}
-
-__global__ __launch_bounds__(256) void k_slice_otsu(uint8_t* __restrict__ proxy, int64_t nx, int64_t ny, int64_t nz,
-                                                    int64_t P, DevState* S, int32_t* slice_thr) {
+__global__ __launch_bounds__(256) void k_slice_otsu(const uint8_t* __restrict__ proxy, int64_t nx, int64_t ny,
+                                                    int64_t nz, int64_t P, DevState* S, int32_t* __restrict__ thr,
+                                                    int32_t* __restrict__ slice_thr) {
     __shared__ uint32_t h[256 * kSliceCopies];
     __shared__ unsigned long long sh_w[256], sh_s[256];
     __shared__ double sh_v[256];
@@ -1153,7 +1142,7 @@ __global__ __launch_bounds__(256) void k_slice_otsu(uint8_t* __restrict__ proxy,
         atomicOr(&S->flags, ROIX_FLAG_PER_SLICE);
     }
     for (int64_t z = blockIdx.x; z < nz; z += gridDim.x) {
-        uint8_t* base = proxy + z * ny * P;
+        const uint8_t* base = proxy + z * ny * P;
         for (int i = t; i < 256 * kSliceCopies; i += 256) h[i] = 0u;
         __syncthreads();
         // the slice's 16-byte vectors, flat (row = i / vpr), 8 loads in flight per lane
@@ -1217,40 +1206,19 @@ __global__ __launch_bounds__(256) void k_slice_otsu(uint8_t* __restrict__ proxy,
         const int32_t ts = degenerate ? 255 : sh_t[0];
         if (t == 0) {
             if (degenerate) atomicOr(&S->flags, ROIX_FLAG_DEGENERATE_HISTOGRAM);
+            thr[z] = ts;
             if (slice_thr) slice_thr[z] = ts;
-        }
-        // the slice's bytes, shifted so that "> 127" is "> ts"
-        for (uint32_t i0 = (uint32_t)t; i0 < nvec; i0 += 8u * 256u) {
-            uint4 q[8];
-            uint4* pv[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const uint32_t i = i0 + 256u * k;
-                const uint32_t r = i < nvec ? i / vpr : 0u, v = i < nvec ? i - r * vpr : 0u;
-                pv[k] = reinterpret_cast<uint4*>(base + (int64_t)r * P + 16 * (int64_t)v);
-                q[k] = *pv[k];
-            }
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                if (i0 + 256u * k >= nvec) continue;
-                *pv[k] = make_uint4(slice_remap(q[k].x, ts), slice_remap(q[k].y, ts), slice_remap(q[k].z, ts),
-                                    slice_remap(q[k].w, ts));
-            }
-        }
-        for (int64_t r = wv; r < ny && ln < tail; r += nw) {
-            uint8_t* pb = base + r * P + 16 * vpr + ln;
-            const int32_t b = (int32_t)*pb - ts + 127;
-            *pb = (uint8_t)(b < 0 ? 0 : (b > 255 ? 255 : b));
         }
         __syncthreads();  // sh_* are reused by the next slice
     }
 }
 
-hipError_t launch_slice_otsu(const LaunchCtx& lc, const Geom& g, uint8_t* proxy, DevState* S, int32_t* slice_thr) {
+hipError_t launch_slice_otsu(const LaunchCtx& lc, const Geom& g, const uint8_t* proxy, DevState* S, int32_t* thr,
+                             int32_t* slice_thr_out) {
     timer_begin(lc.timer, ST_OTSU, lc.stream);
     const int64_t grid = g.nz < 8192 ? g.nz : 8192;
     hipLaunchKernelGGL(k_slice_otsu, dim3((unsigned)grid), dim3(256), 0, lc.stream, proxy, g.nx, g.ny, g.nz, g.W * 64,
-                       S, slice_thr);
+                       S, thr, slice_thr_out);
     timer_end(lc.timer, ST_OTSU, lc.stream);
     return hipGetLastError();
 }

@@ -390,6 +390,7 @@ def test_per_slice_otsu(env, conn):
         ("drift ragged rows", drifting((5, 19, 133), 42), "abs", 1e-4),
         ("drift narrow rows", drifting((6, 9, 13), 43), "abs", 1e-3),
         ("one slice", drifting((1, 40, 64), 44), "abs", 1e-3),
+        ("drift long rows", drifting((3, 5, 4160), 46), "abs", 1e-3),  # 65 mask words a row
         ("ellipsoids", synth.ellipsoids(130, 40, 9, 4300, n_ell=4, ax=(2.0, 20.0))[0], "abs", 1e-3),
         ("rings u16", synth.rings2048(nxy=96, nz=5).volume, "rel", 1e-4),
         ("cylinder", synth.cylinder1024(n=96).volume, "abs", 1e-4),
