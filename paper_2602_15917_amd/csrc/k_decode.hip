@@ -7,7 +7,7 @@
 // writes a 32-byte descriptor per volume row: its span, first code, first
 // outlier and the number of escapes the offsets imply (an empty span for a
 // row without an entry).  Then a wave takes 64 volume rows at a time, one
-// descriptor per lane, and walks them in units of 1024 voxels, the code
+// descriptor per lane, and walks them in units of 512 voxels, the code
 // loads of the next unit in flight while the current one is written:
 // background outside the span, (u + qmin) * w inside it, the k-th escape of
 // the row taking outlier outlier_off + k (a wave prefix count, skipped when
@@ -124,19 +124,19 @@ __device__ __forceinline__ uint64_t codes4_end(uint64_t c) {
 template <int B>
 __device__ __forceinline__ void window_load(const uint8_t* __restrict__ s, uint64_t c, uint32_t (&d)[4]) {
     if constexpr (B == 4) {
-        const v4u32_t q = __builtin_nontemporal_load(reinterpret_cast<const v4u32_t*>(s + 4 * c));
+        const v4u32_t q = *(reinterpret_cast<const v4u32_t*>(s + 4 * c));
         d[0] = q.x;
         d[1] = q.y;
         d[2] = q.z;
         d[3] = q.w;
     } else if constexpr (B == 2) {
-        const v3u32_t q = __builtin_nontemporal_load(reinterpret_cast<const v3u32_t*>(s + ((2 * c) & ~3ull)));
+        const v3u32_t q = *(reinterpret_cast<const v3u32_t*>(s + ((2 * c) & ~3ull)));
         d[0] = q.x;
         d[1] = q.y;
         d[2] = q.z;
         d[3] = 0u;
     } else {
-        const v2u32_t q = __builtin_nontemporal_load(reinterpret_cast<const v2u32_t*>(s + (c & ~3ull)));
+        const v2u32_t q = *(reinterpret_cast<const v2u32_t*>(s + (c & ~3ull)));
         d[0] = q.x;
         d[1] = q.y;
         d[2] = d[3] = 0u;
@@ -165,7 +165,7 @@ __device__ __forceinline__ void window_codes(const uint32_t (&d)[4], uint64_t c,
     }
 }
 
-constexpr int kDecSteps = 4;                             // 256-voxel steps per unit
+constexpr int kDecSteps = 2;                             // 256-voxel steps per unit
 constexpr int64_t kDecUnit = (int64_t)kDecSteps * 4 * kWave;  // voxels per unit
 
 // Descriptor of row j of the wave's group (lane j holds it), uniform.
