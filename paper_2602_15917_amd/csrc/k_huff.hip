@@ -16,9 +16,9 @@
 //
 // Encoding: a byte histogram (16 copies of LDS counters per workgroup), the
 // code built by one workgroup, then a wave per block twice: the block's bit
-// count (for an
-// exclusive scan of the block sizes), and the codes, ORed into the block's
-// words in LDS at the positions a wave prefix sum gives, then copied out.
+// count (for an exclusive scan of the block sizes), and the codes, ORed into
+// the block's words in an LDS window at the positions a wave prefix sum
+// gives, then copied out.
 // Decoding: a lane per block with a 64-bit bit window fed a 16-byte load
 // ahead, an 11-bit lookup table that yields one or two codes, and a
 // canonical search for longer codes.
