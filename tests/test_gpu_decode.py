@@ -58,6 +58,11 @@ CASES = [
      .astype(np.float32), "abs", 7.3, synth.Criterion("fixed", 1.0008e6, 6, "min_size", 1)),
     ("ragged rows", lambda: synth.normal((3, 5, 67), 9, 0.0, 1.0), "abs", 1e-3,
      synth.Criterion("otsu", 0.0, 6, "min_size", 1)),
+    # rows of several 512-voxel units and a ragged last unit
+    ("long rows, 16-bit", lambda: synth.normal((2, 6, 1100), 13, 0.5, 0.2), "abs", 1e-4,
+     synth.Criterion("fixed", 0.45, 26, "min_size", 1)),
+    ("long rows, 32-bit escapes", lambda: synth.normal((2, 5, 1300), 14, 0.5, 0.2), "abs", 3.3e-6,
+     synth.Criterion("fixed", 0.5, 6, "min_size", 1)),
 ]
 
 

@@ -54,7 +54,7 @@ def gpu_encode(env, d, cap=None):
     return ln.cpu().numpy(), off.cpu().numpy().astype(np.uint64), pay, i
 
 
-SIZES = [0, 1, 15, 16, 17, 4095, 4096, 4097, 100_003, (1 << 20) + 5]
+SIZES = [0, 1, 15, 16, 17, 2048, 4095, 4096, 4097, 7096, 100_003, (1 << 20) + 5]
 KINDS = ["uniform", "peaked", "constant", "two", "pareto", "section"]
 
 
