@@ -844,6 +844,26 @@ def main():
         b_des = N * (s + 2) + (2 * N + nrows_all * W * 8) + e.n_codes * (2 + code_bytes) + 32 * e.n_rows
         path.update({"design_bytes": int(b_des), "design_frac": round(b_des / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
 
+    # a measured read-only stream of the same size: the range kernel of the
+    # two-pass flow (one read of the N*s input bytes, one atomic per
+    # workgroup), timed by the library's stage events on a few steps with that
+    # flow forced, outside the timed region
+    if stages:
+        keep16 = ctx.get_param("fused16_min_voxels")
+        ctx.set_param("fused16_min_voxels", 1 << 40)
+        ctx.set_timing(True)
+        for _ in range(3):
+            step()
+        torch.cuda.synchronize()
+        st2 = ctx.read_timing()
+        ctx.set_timing(False)
+        ctx.set_param("fused16_min_voxels", keep16)
+        r_ms, r_n = st2.get("range", (0.0, 0))
+        if r_n:
+            ro_gbs = N * s / (r_ms / r_n * 1e-3) / 1e9
+            path.update({"read_only_kernel": "k_range (two-pass flow)", "read_only_GBps": round(ro_gbs, 1),
+                         "frac_vs_read_only": round(path["achieved"] / ro_gbs, 4)})
+
     if args.calibrate_copy:
         a = torch.empty(CALIB_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
         bcp = torch.empty_like(a)
