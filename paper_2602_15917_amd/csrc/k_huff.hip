@@ -109,19 +109,33 @@ __global__ __launch_bounds__(256) void k_hf_build(HfState* S, uint8_t* lengths_o
     if (c) sym[rank] = t;
     __syncthreads();
     const int ns = ns_sh;
-    // the two-queue merge (sequential: each step depends on the last)
+    if (t < ns) w[t] = hs[sym[t]];  // the leaves, lightest first
+    __syncthreads();
+    // the two-queue merge (sequential: each step depends on the last); the
+    // heads of both queues stay in registers, lw = w[lq] and, while the
+    // merged queue is not empty (mq < next), mw = w[mq]
     if (t == 0 && ns > 1) {
-        for (int i = 0; i < ns; ++i) w[i] = hs[sym[i]];
         int lq = 0, mq = ns, next = ns;
+        unsigned long long lw = w[0], mw = 0ull;
         while (next < 2 * ns - 1) {
-            int pick[2];
+            int p[2];
+            unsigned long long sum = 0ull;
+#pragma unroll
             for (int k = 0; k < 2; ++k) {
-                if (lq < ns && (mq >= next || w[lq] <= w[mq])) pick[k] = lq++;
-                else pick[k] = mq++;
+                if (lq < ns && (mq >= next || lw <= mw)) {  // a leaf before a merged node of the same weight
+                    p[k] = lq++;
+                    sum += lw;
+                    lw = lq < ns ? w[lq] : 0ull;
+                } else {
+                    p[k] = mq++;
+                    sum += mw;
+                    mw = mq < next ? w[mq] : 0ull;
+                }
             }
-            w[next] = w[pick[0]] + w[pick[1]];
-            parent[pick[0]] = next;
-            parent[pick[1]] = next;
+            w[next] = sum;
+            if (mq == next) mw = sum;  // the merged queue was empty: the new node heads it
+            parent[p[0]] = next;
+            parent[p[1]] = next;
             ++next;
         }
     }
