@@ -1053,14 +1053,56 @@ __device__ __forceinline__ void outl_store(const float (&xv)[kOutlU], uint32_t l
     }
 }
 
+// The 16-bit proxy's outlier flags (bit 15) of one round, and the stores of
+// the flagged voxels' values (read from the input, I - B with a background)
+// in order of x from the span's outlier offset.
+__device__ __forceinline__ void outl_flags(const uint16_t* __restrict__ ps, uint32_t len, uint32_t j0,
+                                           uint32_t (&fv)[kOutlU]) {
+    const int lane = threadIdx.x % kWave;
+#pragma unroll
+    for (int u = 0; u < kOutlU; ++u) {
+        const uint32_t jj = j0 + u * kWave + lane;
+        fv[u] = ps[jj < len ? jj : 0u];
+    }
+}
+
+template <typename T, bool BG>
+__device__ __forceinline__ void outl_store_flagged(const uint32_t (&fv)[kOutlU], const T* __restrict__ src,
+                                                   const float* __restrict__ bsrc, uint32_t len, uint32_t j0,
+                                                   unsigned long long& k, const EmitOut& o, bool& trunc) {
+    const int lane = threadIdx.x % kWave;
+#pragma unroll
+    for (int u = 0; u < kOutlU; ++u) {
+        const uint32_t jj = j0 + u * kWave + lane;
+        const bool isout = jj < len && ((fv[u] >> 15) & 1u);
+        const uint64_t mo = __ballot(isout);
+        if (isout) {
+            float x;
+            if constexpr (BG)
+                x = (float)src[jj] - bsrc[jj];
+            else
+                x = (float)src[jj];
+            const unsigned long long at = k + (unsigned long long)__popcll(mo & ((1ull << lane) - 1ull));
+            if (at < o.outl_cap)
+                o.outl[at] = x;
+            else
+                trunc = true;
+        }
+        k += (unsigned long long)__popcll(mo);
+    }
+}
+
 // After the scan of the per-row outlier counts.  Each wave takes 64 spans,
 // one per lane: the lane writes its span's row table entry (coalesced), then
 // the wave walks the spans that have outliers (a ballot), the first round of
-// the next one in flight while the current one is tested.
+// the next one in flight while the current one is tested.  px: the 16-bit
+// proxy (element = voxel), or null; when the call took the one-pass flow the
+// outliers are found by its flag bits (2 bytes a voxel) and only their
+// values are read from the input.
 template <typename T, bool BG = false>
 __global__ __launch_bounds__(kBlock) void k_emit_rows(const T* __restrict__ in, int64_t nx, Layout L, int64_t ny,
                                                       int64_t nrows, EmitOut o, const float* __restrict__ bg,
-                                                      int bg_plane) {
+                                                      int bg_plane, const uint16_t* __restrict__ px) {
     DevState* S = L.S;
     if (thread_exit_e(S)) return;
     const uint32_t n_rows = uni((uint32_t)(S->span_total >> 40));
@@ -1108,6 +1150,44 @@ __global__ __launch_bounds__(kBlock) void k_emit_rows(const T* __restrict__ in, 
             return bg + (bg_plane ? rr % (uint64_t)ny : rr) * (uint64_t)nx + uni(__builtin_amdgcn_readlane(xs, l));
         };
         auto len_of = [&](int l) { return uni(__builtin_amdgcn_readlane(len, l)); };
+        if (px && S->p16) {  // uniform: the proxy's flags, ping-pong over the spans as below
+            auto psrc_of = [&](int l) {
+                return px + (uint64_t)uni(__builtin_amdgcn_readlane(rid, l)) * (uint64_t)nx +
+                       uni(__builtin_amdgcn_readlane(xs, l));
+            };
+            auto ftest = [&](int l, const uint32_t (&fv)[kOutlU]) {
+                const uint32_t lt = len_of(l);
+                unsigned long long k = readlane64(ooff, l);
+                outl_store_flagged<T, BG>(fv, src_of(l), bsrc_of(l), lt, 0, k, o, trunc);
+                for (uint32_t j0 = kOutlRound; j0 < lt; j0 += kOutlRound) {
+                    uint32_t fc[kOutlU];
+                    outl_flags(psrc_of(l), lt, j0, fc);
+                    outl_store_flagged<T, BG>(fc, src_of(l), bsrc_of(l), lt, j0, k, o, trunc);
+                }
+            };
+            auto fpop = [&](int prev) {
+                if (!m) return prev;
+                const int l = __ffsll((unsigned long long)m) - 1;
+                m &= m - 1;
+                return l;
+            };
+            uint32_t fa[kOutlU], fb[kOutlU];
+            int la = fpop(0);
+            outl_flags(psrc_of(la), len_of(la), 0, fa);
+            while (true) {
+                const bool more_b = m != 0;
+                const int lb = fpop(la);
+                outl_flags(psrc_of(lb), len_of(lb), 0, fb);
+                ftest(la, fa);
+                if (!more_b) break;
+                const bool more_a = m != 0;
+                la = fpop(lb);
+                outl_flags(psrc_of(la), len_of(la), 0, fa);
+                ftest(lb, fb);
+                if (!more_a) break;
+            }
+            continue;
+        }
         // one span: its first round is in xv; longer spans loop (rare)
         auto test = [&](int l, const float (&xv)[kOutlU]) {
             const uint32_t lt = len_of(l);
@@ -1184,15 +1264,19 @@ hipError_t launch_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, cons
     hipError_t e = launch_scan_u64(lc, L.row_outl, L.row_outl, g.nrows, &L.S->n_outliers, L.scan_tmp);
     if (e != hipSuccess) return e;
     timer_begin(lc.timer, ST_EMIT_ROWS, lc.stream);
+    // the 16-bit proxy when the layout holds one with element = voxel (the
+    // kernel uses it only if the call took the one-pass flow)
+    const uint16_t* px16 =
+        (dt == ROIX_F32 && L.fine_slots && g.W * 64 == g.nx) ? reinterpret_cast<const uint16_t*>(L.proxy) : nullptr;
     if (dt == ROIX_F32 && bg) {
         hipLaunchKernelGGL((k_emit_rows<float, true>), grid_rows_t, block, 0, lc.stream, (const float*)in, g.nx, L,
-                           g.ny, g.nrows, o, bg->bg, bg->plane ? 1 : 0);
+                           g.ny, g.nrows, o, bg->bg, bg->plane ? 1 : 0, px16);
     } else if (dt == ROIX_F32) {
         hipLaunchKernelGGL((k_emit_rows<float, false>), grid_rows_t, block, 0, lc.stream, (const float*)in, g.nx, L,
-                           g.ny, g.nrows, o, (const float*)nullptr, 0);
+                           g.ny, g.nrows, o, (const float*)nullptr, 0, px16);
     } else {
         hipLaunchKernelGGL((k_emit_rows<uint16_t, false>), grid_rows_t, block, 0, lc.stream, (const uint16_t*)in, g.nx,
-                           L, g.ny, g.nrows, o, (const float*)nullptr, 0);
+                           L, g.ny, g.nrows, o, (const float*)nullptr, 0, (const uint16_t*)nullptr);
     }
     timer_end(lc.timer, ST_EMIT_ROWS, lc.stream);
     return hipGetLastError();
