@@ -261,6 +261,28 @@ roix_status roix_extract(roix_ctx* ctx, const void* d_in, roix_dtype dtype, cons
 roix_status roix_fused(roix_ctx* ctx, const void* d_in, roix_dtype dtype, roix_dims dims, roix_eb eb,
                        const roix_criterion* crit, const roix_fused_out* out, void* stream);
 
+/* No-allocation form of roix_fused, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  It needs no context: its scratch arena is a fixed array
+ * of ROIX_NOALLOC_SCRATCH_BYTES compiled into the library, one copy per GPU,
+ * held until the process ends.  It runs on the current device (the stream
+ * must belong to it) with the launch parameters of a new context, and
+ * enqueues exactly the kernels of roix_fused, so its outputs equal
+ * roix_fused's bit for bit.
+ *  - Limit: the volume's worst-case scratch (roix_scratch_bytes) must not
+ *    exceed ROIX_NOALLOC_SCRATCH_BYTES (64 MiB: e.g. 128^3 float32 volumes);
+ *    a larger volume returns ROIX_ENOMEM synchronously and enqueues nothing.
+ *  - Every call on one GPU shares that GPU's array, and each call resets the
+ *    state it reads at its start: calls that overlap on one GPU (two streams,
+ *    two host threads) race.  Serialise them, e.g. on one stream.
+ *  - Errors: as roix_fused (ROIX_EINVAL for bad arguments), ROIX_ENOMEM (too
+ *    large, see above), ROIX_EDEVICE (the array's address could not be
+ *    resolved on this device, or a launch failed).
+ *  - Allocates nothing: no hipMalloc, hipFree or allocating library call. */
+#define ROIX_NOALLOC_SCRATCH_BYTES (64ull << 20)
+roix_status roix_fused_noalloc(const void* d_in, roix_dtype dtype, roix_dims dims, roix_eb eb,
+                               const roix_criterion* crit, const roix_fused_out* out, void* stream);
+
 /* Decode: the reverse process of Sec. 4.3, which rebuilds the volume from
  * the geometry section (Eq. 3, the row table), the pixel section (Eq. 4,
  * the code stream) and the outlier values, as written by roix_extract or

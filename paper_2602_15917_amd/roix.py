@@ -116,6 +116,7 @@ def load():
     lib.roix_segment.argtypes = [vp, vp, Dims, vp, P(CCriterion), vp, vp, vp, i64, vp, vp]
     lib.roix_extract.argtypes = [vp, vp, ci, vp, Dims, vp, P(FusedOut), vp]
     lib.roix_fused.argtypes = [vp, vp, ci, Dims, Eb, P(CCriterion), P(FusedOut), vp]
+    lib.roix_fused_noalloc.argtypes = [vp, ci, Dims, Eb, P(CCriterion), P(FusedOut), vp]
     lib.roix_stage_count.restype = ci
     lib.roix_stage_name.argtypes = [ci]
     lib.roix_stage_name.restype = ctypes.c_char_p
@@ -149,7 +150,7 @@ def load():
     lib.roix_abs_quantize_scratch_bytes.argtypes = [i64]
     lib.roix_abs_quantize_scratch_bytes.restype = sz
     for f in ("roix_ctx_create", "roix_ctx_destroy", "roix_bounds", "roix_quantize", "roix_segment",
-              "roix_extract", "roix_fused", "roix_ctx_set_timing", "roix_ctx_read_timing", "roix_fused_batch",
+              "roix_extract", "roix_fused", "roix_fused_noalloc", "roix_ctx_set_timing", "roix_ctx_read_timing", "roix_fused_batch",
               "roix_ctx_set_param", "roix_ctx_get_param", "roix_server_create", "roix_server_destroy",
               "roix_volume_open", "roix_slab_submit", "roix_volume_close", "roix_volume_abort", "roix_wait",
               "roix_server_stats", "roix_decode", "roix_background", "roix_fused_background", "roix_abs_quantize",
@@ -207,6 +208,20 @@ def _stream(stream):
 def _check(st, what):
     if st != OK:
         raise RoixError(st, what)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # ROIX_NOALLOC_SCRATCH_BYTES
+
+
+def fused_noalloc(vol: torch.Tensor, eb_mode: str, eb_value: float, crit: Criterion, out: "Outputs",
+                  stream=None):
+    """roix_fused_noalloc: the fused path on the library's fixed scratch array
+    (no context, no device allocation; volumes whose worst-case scratch fits
+    NOALLOC_SCRATCH_BYTES).  Runs on the current device."""
+    c = crit.c()
+    st = load().roix_fused_noalloc(_ptr(vol), dtype_of(vol), dims_of(vol), eb_of(eb_mode, eb_value),
+                                   ctypes.byref(c), ctypes.byref(out.c), _stream(stream))
+    _check(st, "roix_fused_noalloc")
 
 
 def scratch_bytes(dims: Dims, dtype: int, crit: Criterion | None = None) -> int:

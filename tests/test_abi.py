@@ -74,6 +74,12 @@ def test_sync_argument_errors(lib):
     null = ctypes.c_void_p(0)
     # null context / input
     assert L.roix_fused(null, null, roix.F32, d, eb, ctypes.byref(c), ctypes.byref(out), null) == roix.EINVAL
+    assert L.roix_fused_noalloc(null, roix.F32, d, eb, ctypes.byref(c), ctypes.byref(out), null) == roix.EINVAL
+    # beyond the fixed scratch array: refused before any device call
+    big = roix.Dims(200, 200, 200)
+    assert roix.scratch_bytes(big, roix.F32) > roix.NOALLOC_SCRATCH_BYTES
+    fake = ctypes.c_void_p(1 << 20)
+    assert L.roix_fused_noalloc(fake, roix.F32, big, eb, ctypes.byref(c), ctypes.byref(out), null) == roix.ENOMEM
     assert L.roix_quantize(null, null, roix.F32, d, eb, null, null, null, null) == roix.EINVAL
     assert L.roix_segment(null, null, d, null, ctypes.byref(c), null, null, null, 0, null, null) == roix.EINVAL
     assert L.roix_extract(null, null, roix.F32, null, d, null, ctypes.byref(out), null) == roix.EINVAL
