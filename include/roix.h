@@ -370,7 +370,7 @@ roix_status roix_fused_background(roix_ctx* ctx, const float* d_in, roix_dims di
                                   const roix_fused_out* out, float* d_work, void* stream);
 
 /* Absolute error-bounded quantisation of an 8-bit pixel sequence, the
- * paper's own algorithm (Sec. 4.2.3, Steps 1-5): a group grows pixel by
+ * paper's own algorithm (Sec. 4.2.3): a group grows pixel by
  * pixel while the intervals [D - E, D + E] of its pixels intersect, and
  * every pixel of the group is written as the floor of the midpoint of that
  * intersection, floor((min + max) / 2), clipped to 0..255.  The pixels are
@@ -573,6 +573,16 @@ roix_status roix_ctx_read_timing(roix_ctx* ctx, double* ms, int64_t* launches);
  * close.  Either way the outputs equal roix_fused on the assembled volume
  * with the same arguments.
  *
+ * A uint16 volume with an absolute bound and a FIXED threshold whose codes
+ * cannot span more than 2^15 values (rint(65535 / (2 eb32)) < 2^15, i.e. eb
+ * of about 1 or more) is not kept whole: each slab is staged (at most
+ * "slab_planes" planes at a time), and only each row's extent -- from its
+ * first to its last mask voxel, where every span of the row must lie -- is
+ * kept, in a store of "store_permille" per mille of the volume's voxels;
+ * counts of the code classes q mod 2^15 stand in for the histogram, which
+ * close rebuilds once the range is known (Sec. 4.1.2).  A volume whose
+ * extents outgrow the store fails with ROIX_ENOMEM in its infos at close.
+ *
  * Requests complete asynchronously; roix_wait returns their host-clock
  * times.  Slab latency = completion - submission (copy and compute,
  * including the wait behind earlier requests).  All calls on one server
@@ -611,14 +621,20 @@ roix_status roix_server_destroy(roix_server* srv);
  * (N * voxel bytes) plus the labelling state (no proxy for incremental
  * volumes) with run arrays for runs_per_row runs per row on average (a
  * volume with more foreground runs fails with ROIX_ENOMEM in its infos at
- * close).  0 for invalid arguments. */
+ * close); for a volume kept as row extents, its stage, store, row tables,
+ * code-class counts and run arrays instead of the input.  0 for invalid
+ * arguments. */
 size_t roix_server_volume_bytes(const roix_server* srv, roix_dims dims, roix_dtype dtype, roix_eb eb,
                                 const roix_criterion* crit);
 
-/* Server parameters:
- *   "runs_per_row"  run-array capacity of volumes opened from now on, as an
- *                   average number of foreground runs per row (default 32,
- *                   capped at the worst case of ceil(nx/2))
+/* Server parameters (each applies to volumes opened from now on):
+ *   "runs_per_row"  run-array capacity, as an average number of foreground
+ *                   runs per row (default 32, capped at the worst case of
+ *                   ceil(nx/2))
+ *   "slab_planes"   planes a volume kept as row extents stages at once
+ *                   (1..4096, default 32; larger slabs are staged in turn)
+ *   "store_permille" store of a volume kept as row extents, per mille of its
+ *                   voxels (1..1000, default 500)
  * Errors: ROIX_EINVAL (unknown name or value out of range). */
 roix_status roix_server_set_param(roix_server* srv, const char* name, int64_t value);
 

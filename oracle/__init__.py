@@ -262,8 +262,7 @@ def background(vol, bg, op="subtract"):
 
 def abs_quantize(pixels, e_abs):
     """The paper's absolute error-bounded quantisation of an 8-bit pixel
-    sequence (Sec. 4.2.3, Steps 1-5; tolerance floor(e_abs) on integer
-    pixels).  Returns (status, Q uint8, number of groups)."""
+    sequence (Sec. 4.2.3; tolerance floor(e_abs) on integer pixels).  Returns (status, Q uint8, number of groups)."""
     d = np.ascontiguousarray(pixels, dtype=np.uint8).reshape(-1)
     q = np.empty(max(d.size, 1), np.uint8)
     n = np.zeros(1, np.uint64)

@@ -42,9 +42,9 @@
  *                calibration plane or volume), and M + B to put a decoded
  *                volume back on its background
  *   abs_quantize the paper's own absolute error-bounded quantisation of an
- *                8-bit pixel sequence (Sec. 4.2.3, Steps 1-5): groups grown
- *                while the error intervals intersect, each written as the
- *                floor of its midpoint, clipped to 0..255
+ *                8-bit pixel sequence (Sec. 4.2.3): the longest runs whose
+ *                largest and smallest pixel differ by at most 2E, each
+ *                written as floor((min + max) / 2)
  *   huffman      a lossless entropy stage for the packed stream (the Huffman
  *                coding the paper lists among lossless coders, Sec. 1):
  *                byte counts, Huffman code lengths, canonical codes, the
@@ -776,48 +776,55 @@ int oracle_fused(const void* in, int dtype, int64_t nx, int64_t ny, int64_t nz, 
 /* Absolute error-bounded quantisation of a pixel sequence (Sec. 4.2.3).
  * Input: D[0..m) 8-bit pixels (the normalised pixel section, Sec. 4.1.2) and
  * the tolerance E_abs.  The pixels are integers and so is the output, and
- * |Q - D| <= E for integers means |Q - D| <= floor(E): the steps below take
+ * |Q - D| <= E for integers means |Q - D| <= floor(E): the tolerance used is
  * E = floor(E_abs).  With that E the floored midpoint keeps the bound, which
  * it does not for a fractional E >= 0.5 (e.g. D = {0, 3}, E = 1.5: the
- * intervals meet at 1.5 and the floor gives 1, 2 away from 3).
- *   Step 1  lower[i] = D[i] - E, upper[i] = D[i] + E
- *   Step 2  u = +inf, l = -inf, head = 0
- *   Step 3  for each i: l' = max(l, lower[i]), u' = min(u, upper[i]); when
- *           u' < l' the group [head, i) is written as floor((u + l) / 2)
- *           and a new group starts at i with [lower[i], upper[i]];
- *           otherwise [l, u] = [l', u']
- *   Step 4  the last group [head, m) is written the same way
- *   Step 5  Q = clip(Q, 0, 255)
- * Exact integer arithmetic (int64).  *n_groups receives the number of
- * groups.  Returns OR_EINVAL for a negative or NaN tolerance. */
+ * tolerance intervals meet at 1.5 and the floor gives 1, 2 away from 3).
+ *
+ * The method cuts the sequence, from left to right, into the longest runs of
+ * consecutive pixels that one value can represent within E, and gives every
+ * pixel of a run that value.  One value fits a run exactly when the pixels'
+ * tolerance intervals [D - E, D + E] share a point, i.e. when the run's
+ * largest and smallest pixel differ by at most 2E; the shared points are
+ * then [max - E, min + E], and the value written is the floor of that
+ * interval's midpoint, floor((min + max) / 2), clipped to the 8-bit range
+ * (a no-op here, since min and max are 8-bit).  So a run grows while
+ * max - min <= 2E and the pixel that would break this starts the next run.
+ * Exact integer arithmetic.  *n_groups receives the number of runs.  Returns
+ * OR_EINVAL for a negative or NaN tolerance. */
+static void abs_quantize_write(uint8_t* Q, uint64_t a, uint64_t b, int lo, int hi) {
+    int q = (lo + hi) / 2; /* both >= 0: integer division is the floor */
+    q = q < 0 ? 0 : q > 255 ? 255 : q;
+    for (uint64_t j = a; j < b; ++j) Q[j] = (uint8_t)q;
+}
+
 int oracle_abs_quantize(const uint8_t* D, uint64_t m, double e_abs, uint8_t* Q, uint64_t* n_groups) {
     if (!(e_abs >= 0.0)) return OR_EINVAL;
     const int64_t E = e_abs >= 1024.0 ? 1024 : (int64_t)floor(e_abs);
-    int64_t u = INT64_MAX, l = INT64_MIN;
-    uint64_t head = 0, groups = 0;
+    uint64_t start = 0, runs = 0;
+    int lo = 0, hi = 0;
     for (uint64_t i = 0; i < m; ++i) {
-        const int64_t lower = (int64_t)D[i] - E, upper = (int64_t)D[i] + E;
-        const int64_t l_new = l > lower ? l : lower, u_new = u < upper ? u : upper;
-        if (u_new < l_new) {
-            const int64_t s = u + l; /* both finite here: the group holds pixel head */
-            const int64_t q = s >= 0 ? s / 2 : -((-s + 1) / 2);
-            for (uint64_t j = head; j < i; ++j) Q[j] = (uint8_t)(q < 0 ? 0 : q > 255 ? 255 : q);
-            ++groups;
-            l = lower;
-            u = upper;
-            head = i;
+        const int d = D[i];
+        if (i == start) {
+            lo = hi = d;
+            continue;
+        }
+        const int nlo = d < lo ? d : lo, nhi = d > hi ? d : hi;
+        if ((int64_t)(nhi - nlo) > 2 * E) {
+            abs_quantize_write(Q, start, i, lo, hi);
+            ++runs;
+            start = i;
+            lo = hi = d;
         } else {
-            l = l_new;
-            u = u_new;
+            lo = nlo;
+            hi = nhi;
         }
     }
     if (m > 0) {
-        const int64_t s = u + l;
-        const int64_t q = s >= 0 ? s / 2 : -((-s + 1) / 2);
-        for (uint64_t j = head; j < m; ++j) Q[j] = (uint8_t)(q < 0 ? 0 : q > 255 ? 255 : q);
-        ++groups;
+        abs_quantize_write(Q, start, m, lo, hi);
+        ++runs;
     }
-    *n_groups = groups;
+    *n_groups = runs;
     return OR_OK;
 }
 
