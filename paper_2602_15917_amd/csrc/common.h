@@ -66,6 +66,9 @@ struct DevState {
     // sequence's quantiser stages
     int32_t saved_status;
     float serve_r, serve_rt;
+    // streamed volumes kept as row extents: values of the store in use, and
+    // the extent total of the slab being stored
+    unsigned long long store_used, store_slab;
     // threshold search: the thresholds and class count, and the multi-level
     // Otsu search's best (score, tuple rank) per workgroup
     int32_t thr_t[3];
@@ -100,7 +103,18 @@ struct Layout {
     uint32_t* fine_slots;   // kQrBlocks * kQrFine, or null (no 16-bit proxy)
     unsigned long long* fine_total;  // kQrFine
     uint64_t run_cap;
+    // Where the input values of row r start: element row_org[r] of the value
+    // array is voxel (r, x = 0), so voxel (r, x) is element row_org[r] + x.
+    // Null: the volume itself, row_org = r * nx.  A streamed volume that keeps
+    // only each row's extent sets this (values outside the extent are never
+    // read).  nvals: elements of the value array (0: the N voxels).
+    const uint64_t* row_org;
+    uint64_t nvals;
 };
+
+__device__ __forceinline__ uint64_t row_origin(const Layout& L, uint32_t rid, int64_t nx) {
+    return L.row_org ? L.row_org[rid] : (uint64_t)rid * (uint64_t)nx;
+}
 
 // The proxy of row r, voxel x is element r * 64 W + x (a byte, or a 16-bit
 // word for the 16-bit proxy): rows are padded to whole 64-voxel words, so one
@@ -127,8 +141,15 @@ __device__ __forceinline__ float key2f(uint32_t k) {
 }
 
 // code of a value: fp32 multiply (no contraction: built with -ffp-contract=off),
-// round to nearest even.
-__device__ __forceinline__ int32_t qcode(float x, float r) { return (int32_t)__builtin_rintf(x * r); }
+// round to nearest even.  The rounded value is clamped into int32 range
+// before the conversion (maxNum/minNum: a NaN becomes the lower bound), so the
+// conversion is defined for every input; codes with |x r| > 2^24 or of a
+// non-finite voxel are never used (ERANGE, EINVAL), and inside that range the
+// clamp changes nothing.
+__device__ __forceinline__ int32_t qcode(float x, float r) {
+    const float t = __builtin_rintf(x * r);
+    return (int32_t)__builtin_fminf(__builtin_fmaxf(t, -2147483648.0f), 2147483520.0f);
+}
 
 __device__ __forceinline__ bool outlier(float x, int32_t q, float w, float eb32) {
     float xh = (float)q * w;
@@ -293,6 +314,19 @@ hipError_t launch_slab_mask(const LaunchCtx& lc, const void* in, roix_dtype dt, 
                             int64_t r1, const Layout& L);
 // the histogram of the whole volume without the proxy (streamed volumes)
 hipError_t launch_hist_only(const LaunchCtx& lc, const void* in, roix_dtype dt, const Geom& g, DevState* S);
+// Streamed uint16 volumes kept as row extents (codes within 2^15 classes):
+// clear the class table and the store counters; count the code classes of a
+// slab's n values; store the extent of each slab row [r0, r1) (the span of
+// the row's runs) from the slab's values at `stage` into `store` (cap values),
+// setting row_org; at close, resolve the quantiser and rebuild the histogram
+// from the class counts
+hipError_t launch_store_open(const LaunchCtx& lc, DevState* S, unsigned long long* classes);
+hipError_t launch_slab_classes(const LaunchCtx& lc, const uint16_t* stage, uint64_t n, DevState* S,
+                               unsigned long long* classes);
+hipError_t launch_store_rows(const LaunchCtx& lc, const Geom& g, const Layout& L, const uint16_t* stage, int64_t r0,
+                             int64_t r1, uint16_t* store, uint64_t cap, uint64_t* row_org, uint64_t* lens);
+hipError_t launch_serve_resolve(const LaunchCtx& lc, DevState* S, double eb_value, double fixed_value,
+                                const unsigned long long* classes);
 // save = 1: hold back and clear the status; save = 0: restore it unless a
 // newer error is set
 hipError_t launch_serve_status(const LaunchCtx& lc, DevState* S, int save);
