@@ -73,12 +73,13 @@ int roix::proxy_kind_for(const Geom& g, roix_dtype dt, size_t bytes, uint64_t mi
 }
 
 // bytes of the per-voxel and per-row part of the arena
-size_t roix::fixed_bytes(const Geom& g, int proxy) {
+size_t roix::fixed_bytes(const Geom& g, int proxy, int64_t mask_rows) {
+    const int64_t mrows = mask_rows < 0 ? g.nrows : mask_rows;
     size_t b = 0;
     b += align256(sizeof(DevState));
     if (proxy) b += align256((size_t)g.nrows * g.W * 64 * (proxy == 2 ? 2 : 1));  // proxy
     if (proxy == 2) b += align256((size_t)kQrBlocks * kQrFine * 4) + align256((size_t)kQrFine * 8);
-    b += align256((size_t)g.nrows * g.W * 8);             // mask bits
+    b += align256((size_t)mrows * g.W * 8);               // mask bits
     b += align256((size_t)g.nrows * 4);                   // row_nruns
     b += align256((size_t)(g.nrows + 1) * 4);             // run_off
     b += 2 * align256((size_t)g.nrows * 4);               // row_xs, row_xe
@@ -93,8 +94,9 @@ size_t roix::fixed_bytes(const Geom& g, int proxy) {
     return b;
 }
 
-bool roix::carve_at(void* base, size_t bytes, const Geom& g, Layout* L, int proxy) {
-    const size_t fb = fixed_bytes(g, proxy);
+bool roix::carve_at(void* base, size_t bytes, const Geom& g, Layout* L, int proxy, int64_t mask_rows) {
+    const size_t fb = fixed_bytes(g, proxy, mask_rows);
+    const int64_t mrows = mask_rows < 0 ? g.nrows : mask_rows;
     if (bytes < fb + kRunBytes) return false;
     uint8_t* p = (uint8_t*)base;
     auto take = [&](size_t n) {
@@ -106,7 +108,7 @@ bool roix::carve_at(void* base, size_t bytes, const Geom& g, Layout* L, int prox
     L->proxy = proxy ? take((size_t)g.nrows * g.W * 64 * (proxy == 2 ? 2 : 1)) : nullptr;
     L->fine_slots = proxy == 2 ? (uint32_t*)take((size_t)kQrBlocks * kQrFine * 4) : nullptr;
     L->fine_total = proxy == 2 ? (unsigned long long*)take((size_t)kQrFine * 8) : nullptr;
-    L->maskbits = (uint64_t*)take((size_t)g.nrows * g.W * 8);
+    L->maskbits = (uint64_t*)take((size_t)mrows * g.W * 8);
     L->row_nruns = (uint32_t*)take((size_t)g.nrows * 4);
     L->run_off = (uint32_t*)take((size_t)(g.nrows + 1) * 4);
     L->row_xs = (uint32_t*)take((size_t)g.nrows * 4);
@@ -125,6 +127,8 @@ bool roix::carve_at(void* base, size_t bytes, const Geom& g, Layout* L, int prox
     if (cap > w) cap = w;
     if (cap < 1) return false;
     L->run_cap = cap;
+    L->row_org = nullptr;
+    L->nvals = 0;
     L->run_xs = (uint32_t*)take(cap * 4);
     L->run_xe = (uint32_t*)take(cap * 4);
     L->parent = (uint32_t*)take(cap * 4);

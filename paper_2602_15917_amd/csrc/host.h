@@ -82,13 +82,15 @@ uint64_t worst_runs(const Geom& g);
 constexpr uint64_t kP16MinVoxels = 1ull << 22;
 int proxy_kind(const Geom& g, roix_dtype dt, uint64_t min_voxels = kP16MinVoxels);
 // bytes of the per-voxel and per-row part of a layout
-size_t fixed_bytes(const Geom& g, int proxy = 1);
+// mask_rows: rows of the bitmask (-1: every row; a streamed volume kept as
+// row extents holds only its staged slab's rows)
+size_t fixed_bytes(const Geom& g, int proxy = 1, int64_t mask_rows = -1);
 // the kind a region of `bytes` takes: kind 2 only when it still leaves room
 // for the worst-case run arrays
 int proxy_kind_for(const Geom& g, roix_dtype dt, size_t bytes, uint64_t min_voxels = kP16MinVoxels);
 // carve a layout from [base, base + bytes); the run arrays take what is left
 // (at most worst_runs); false when not even one run fits
-bool carve_at(void* base, size_t bytes, const Geom& g, Layout* L, int proxy = 1);
+bool carve_at(void* base, size_t bytes, const Geom& g, Layout* L, int proxy = 1, int64_t mask_rows = -1);
 LaunchCtx lctx(roix_ctx* c, void* stream);
 bool aligned(const void* p, size_t a);
 bool eb_ok(roix_eb eb);

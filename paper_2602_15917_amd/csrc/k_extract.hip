@@ -145,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_index(Layout L, int64_t nx, int
         const uint64_t code0 = packed & kLenMask, code1 = code0 + (xe - xs);
         L.nz_rows[ridx] = (uint32_t)r;
         // descriptor for the emit: first code, and voxel = code + offset
-        const uint64_t off = (uint64_t)r * (uint64_t)nx + xs - code0;
+        const uint64_t off = row_origin(L, (uint32_t)r, nx) + xs - code0;
         *reinterpret_cast<uint4*>(L.span_desc + 2 * (uint64_t)ridx) =
             make_uint4((uint32_t)code0, (uint32_t)(code0 >> 32), (uint32_t)off, (uint32_t)(off >> 32));
         for (uint64_t q = (code0 + kEmitChunk - 1) / kEmitChunk; q * kEmitChunk < code1; ++q) L.chunk_row[q] = ridx;
@@ -217,7 +217,7 @@ __device__ __forceinline__ void emit_chunk_fast(const T* __restrict__ in, int64_
     if ((uint32_t)lane < nr) {
         rid = L.nz_rows[j0 + lane];
         code0 = L.row_packed[rid] & kLenMask;
-        off = (uint64_t)rid * (uint64_t)nx + L.row_xs[rid] - code0;  // voxel = code + off
+        off = row_origin(L, rid, nx) + L.row_xs[rid] - code0;  // value index = code + off
     }
     constexpr uint32_t kStep = (uint32_t)kEmitSlice * kEmitSlices;
     uint32_t jr = 0;  // span holding the step's first code (uniform)
@@ -368,7 +368,7 @@ __device__ __forceinline__ void emit_chunk_many(const T* __restrict__ in, int64_
             const uint32_t xs = L.row_xs[rid], xe = L.row_xe[rid];
             cs = L.row_packed[rid] & kLenMask;
             ce = cs + (xe - xs);
-            off = (uint64_t)rid * (uint64_t)nx + xs - cs;  // voxel = code + off
+            off = row_origin(L, rid, nx) + xs - cs;  // value index = code + off
         }
         const uint64_t cs0 = readlane64(cs, 0);
         const uint64_t wlo = cs0 > c0 ? cs0 : c0;
@@ -1140,7 +1140,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_rows(const T* __restrict__ in, 
         uint64_t m = __ballot(valid && oend != ooff);
         if (!m) continue;  // uniform
         auto src_of = [&](int l) {
-            return in + (uint64_t)uni(__builtin_amdgcn_readlane(rid, l)) * (uint64_t)nx +
+            return in + uni64(row_origin(L, uni(__builtin_amdgcn_readlane(rid, l)), nx)) +
                    uni(__builtin_amdgcn_readlane(xs, l));
         };
         // the reference row under span l: plane row (row mod ny) or the row itself
@@ -1235,7 +1235,7 @@ hipError_t launch_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, cons
     o.stream_cap = out->d_stream ? (uint64_t)out->stream_cap_bytes : 0;
     o.outl = out->d_outliers;
     o.outl_cap = out->d_outliers ? (uint64_t)out->outliers_cap : 0;
-    o.nvox = g.N;
+    o.nvox = L.nvals ? L.nvals : g.N;
     const dim3 block(kBlock);
     const dim3 grid_rows_t(grid_rows(g.nrows, kBlock, lc.grid_stream));
     const dim3 grid_waves(lc.grid_emit);

@@ -111,6 +111,7 @@ __global__ __launch_bounds__(kBlock) void k_init(DevState* S, double eb_abs) {
             S->seg_lo = 0u;
             S->saved_status = 0;
             S->serve_r = S->serve_rt = 0.0f;
+            S->store_used = S->store_slab = 0ull;
             float eb32, w, r;
             if (eb_abs > 0.0 && resolve_bound(eb_abs, eb32, w, r)) {
                 S->eb32 = eb32;
@@ -835,24 +836,13 @@ __global__ __launch_bounds__(256) void k_fine_reduce(const uint32_t* __restrict_
     if (s) atomicAdd(&fine[i], s);
 }
 
-// The quantiser from the range, then (K <= 2^15) the 256-bin histogram from
-// the class counts: class i is the code q = qmin + ((i - qmin) mod 2^15).
-__global__ __launch_bounds__(1024) void k_resolve16(DevState* S, double eb_value, int fixed, double fixed_value,
-                                                    const unsigned long long* __restrict__ fine) {
-    __shared__ unsigned long long sh[256];
-    __shared__ int s_ok;
+// The 256-bin histogram from code-class counts (K <= 2^15): class i holds
+// the code q = qmin + ((i - qmin) mod 2^15).  Only the K classes of codes
+// qmin .. qmax can hold voxels; thread t of the 1024 takes a run of
+// consecutive codes u = q - qmin.  sh: 256 zeroed shared counters.
+__device__ void hist_from_classes(DevState* S, const unsigned long long* __restrict__ fine,
+                                  unsigned long long* sh) {
     const int t = threadIdx.x;
-    if (t < 256) sh[t] = 0ull;
-    if (t == 0) {
-        resolve_core(S, 1, ROIX_EB_ABS, eb_value, fixed, fixed_value);
-        const bool ok = S->status == 0 && S->K <= (int64_t)kQrFine;
-        S->p16 = ok ? 1u : 0u;
-        s_ok = ok ? 1 : 0;
-    }
-    __syncthreads();
-    if (!s_ok) return;  // uniform
-    // only the K classes of codes qmin .. qmax can hold voxels; thread t
-    // takes a run of consecutive codes u = q - qmin
     const uint32_t qm = (uint32_t)S->qmin, K = (uint32_t)S->K, mlo = S->bin_mlo, mhi = S->bin_mhi;
     const uint32_t per = (K + 1023u) / 1024u;
     uint32_t cur = 0;
@@ -873,6 +863,25 @@ __global__ __launch_bounds__(1024) void k_resolve16(DevState* S, double eb_value
     if (acc) atomicAdd(&sh[cur], acc);
     __syncthreads();
     if (t < 256) S->hist[t] = sh[t];
+}
+
+// The quantiser from the range, then (K <= 2^15) the 256-bin histogram from
+// the class counts.
+__global__ __launch_bounds__(1024) void k_resolve16(DevState* S, double eb_value, int fixed, double fixed_value,
+                                                    const unsigned long long* __restrict__ fine) {
+    __shared__ unsigned long long sh[256];
+    __shared__ int s_ok;
+    const int t = threadIdx.x;
+    if (t < 256) sh[t] = 0ull;
+    if (t == 0) {
+        resolve_core(S, 1, ROIX_EB_ABS, eb_value, fixed, fixed_value);
+        const bool ok = S->status == 0 && S->K <= (int64_t)kQrFine;
+        S->p16 = ok ? 1u : 0u;
+        s_ok = ok ? 1 : 0;
+    }
+    __syncthreads();
+    if (!s_ok) return;  // uniform
+    hist_from_classes(S, fine, sh);
 }
 
 hipError_t launch_quant_range16(const LaunchCtx& lc, const float* in, const Geom& g, const Layout& L, const BgRef* bg) {
@@ -1033,6 +1042,175 @@ __global__ void k_serve_status(DevState* S, int save) {
 
 hipError_t launch_serve_status(const LaunchCtx& lc, DevState* S, int save) {
     hipLaunchKernelGGL(k_serve_status, dim3(1), dim3(64), 0, lc.stream, S, save);
+    return hipGetLastError();
+}
+
+// ------------------------------ streamed volumes kept as row extents
+//
+// A uint16 stream with an absolute bound and a fixed threshold whose codes
+// can span at most 2^15 values (rint(65535 r) < 2^15) keeps, per row, only
+// the values between the row's first and last mask voxel: every span lies
+// there, since a span runs from the row's first to its last kept voxel and
+// kept voxels are mask voxels.  The histogram, which needs the range of the
+// whole volume, is rebuilt at close from counts of the code classes
+// q mod 2^15, one-to-one on [qmin, qmax] when K <= 2^15 (as in the one-pass
+// flow).
+
+__global__ void k_store_open(DevState* S, unsigned long long* __restrict__ classes) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kQrFine; i += gridDim.x * blockDim.x) classes[i] = 0ull;
+    if (blockIdx.x == 0 && threadIdx.x == 0) S->store_used = S->store_slab = 0ull;
+}
+
+hipError_t launch_store_open(const LaunchCtx& lc, DevState* S, unsigned long long* classes) {
+    hipLaunchKernelGGL(k_store_open, dim3(kQrFine / 256), dim3(256), 0, lc.stream, S, classes);
+    return hipGetLastError();
+}
+
+// Code classes of n slab values: per-workgroup LDS counters (128 KB, one
+// workgroup per CU), 16-byte loads of 8 values, then one atomic add per
+// non-zero class and workgroup.  r is the open-time quantiser step.
+constexpr int kClassThreads = 1024;
+__global__ __launch_bounds__(kClassThreads) void k_slab_classes(const uint16_t* __restrict__ in, uint64_t n,
+                                                                const DevState* S,
+                                                                unsigned long long* __restrict__ classes) {
+    __shared__ uint32_t cnt[kQrFine];
+    for (int i = threadIdx.x; i < kQrFine; i += blockDim.x) cnt[i] = 0u;
+    __syncthreads();
+    const float r = S->serve_r;
+    const uint64_t nvec = n / 8;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t gt = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint4* v4 = reinterpret_cast<const uint4*>(in);
+    for (uint64_t i = gt; i < nvec; i += stride) {
+        const uint4 q = ld_stream(v4 + i);
+        const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            atomicAdd(&cnt[(uint32_t)qcode((float)(wd[k] & 0xFFFFu), r) & (uint32_t)(kQrFine - 1)], 1u);
+            atomicAdd(&cnt[(uint32_t)qcode((float)(wd[k] >> 16), r) & (uint32_t)(kQrFine - 1)], 1u);
+        }
+    }
+    for (uint64_t i = nvec * 8 + gt; i < n; i += stride)
+        atomicAdd(&cnt[(uint32_t)qcode((float)in[i], r) & (uint32_t)(kQrFine - 1)], 1u);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kQrFine; i += blockDim.x)
+        if (cnt[i]) atomicAdd(&classes[i], (unsigned long long)cnt[i]);
+}
+
+hipError_t launch_slab_classes(const LaunchCtx& lc, const uint16_t* stage, uint64_t n, DevState* S,
+                               unsigned long long* classes) {
+    uint64_t blocks = (n / 8 + (uint64_t)kClassThreads * 16 - 1) / ((uint64_t)kClassThreads * 16);
+    const uint64_t cap = (uint64_t)(lc.grid_read > 0 ? lc.grid_read / 4 : 256);
+    if (blocks > cap) blocks = cap;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_slab_classes, dim3((unsigned)blocks), dim3(kClassThreads), 0, lc.stream, stage, n,
+                       (const DevState*)S, classes);
+    return hipGetLastError();
+}
+
+// Extent of each slab row from its runs (run_off after the slab's scan,
+// run_xs/run_xe written): [xs of the first run, xe of the last run), or
+// empty.  lens[r - r0] = its length, xlo[r] = its start.  Nothing when the
+// volume has failed (its runs may be unwritten).
+__global__ __launch_bounds__(kBlock) void k_store_extent(const uint32_t* __restrict__ run_off,
+                                                         const uint32_t* __restrict__ run_xs,
+                                                         const uint32_t* __restrict__ run_xe, uint64_t run_cap,
+                                                         int64_t r0, int64_t r1, uint32_t* __restrict__ xlo,
+                                                         uint64_t* __restrict__ lens, const DevState* S) {
+    const bool dead = __hip_atomic_load(&S->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    for (int64_t r = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < r1;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t a = run_off[r], b = run_off[r + 1];
+        uint32_t lo = 0, hi = 0;
+        if (!dead && b > a && b <= run_cap) {
+            lo = run_xs[a];
+            hi = run_xe[b - 1];
+        }
+        xlo[r] = lo;
+        lens[r - r0] = (uint64_t)(hi - lo);
+    }
+}
+
+// Copy each slab row's extent into the store after the values already there
+// (offs: exclusive scan of the lengths; S->store_slab their total), a wave
+// per row; row_org[r] = store index of voxel (r, 0).  A store that would
+// overflow fails the volume (ROIX_ENOMEM) and copies nothing.
+__global__ __launch_bounds__(kBlock) void k_store_copy(const uint16_t* __restrict__ stage, int64_t nx, int64_t r0,
+                                                       int64_t r1, const uint32_t* __restrict__ xlo,
+                                                       const uint64_t* __restrict__ offs, uint16_t* __restrict__ store,
+                                                       uint64_t cap, uint64_t* __restrict__ row_org, DevState* S) {
+    if (__hip_atomic_load(&S->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+    const uint64_t base = S->store_used, total = S->store_slab;
+    if (base + total > cap) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) fail(S, ROIX_ENOMEM);
+        return;
+    }
+    const int lane = threadIdx.x % kWave;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+    for (int64_t r = r0 + wave; r < r1; r += nwaves) {
+        const uint64_t o = offs[r - r0];
+        const uint64_t end = r + 1 < r1 ? offs[r + 1 - r0] : total;
+        const uint32_t lo = xlo[r];
+        const uint64_t len = end - o;
+        if (lane == 0) row_org[r] = base + o - lo;
+        const uint16_t* src = stage + (uint64_t)(r - r0) * (uint64_t)nx + lo;
+        uint16_t* dst = store + base + o;
+        for (uint64_t j = lane; j < len; j += kWave) dst[j] = src[j];
+    }
+}
+
+__global__ void k_store_advance(DevState* S, uint64_t cap) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (S->status == 0 && S->store_used + S->store_slab <= cap) S->store_used += S->store_slab;
+}
+
+hipError_t launch_store_rows(const LaunchCtx& lc, const Geom& g, const Layout& L, const uint16_t* stage, int64_t r0,
+                             int64_t r1, uint16_t* store, uint64_t cap, uint64_t* row_org, uint64_t* lens) {
+    const int64_t nr = r1 - r0;
+    int64_t blocks = (nr + kBlock - 1) / kBlock;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_store_extent, dim3((unsigned)blocks), dim3(kBlock), 0, lc.stream,
+                       (const uint32_t*)L.run_off, (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, L.run_cap,
+                       r0, r1, L.row_xs, lens, (const DevState*)L.S);
+    hipError_t e = launch_scan_u64(lc, lens, lens, nr, &L.S->store_slab, L.scan_tmp);
+    if (e != hipSuccess) return e;
+    int64_t wblocks = (nr + kBlock / kWave - 1) / (kBlock / kWave);
+    if (wblocks > lc.grid_stream) wblocks = lc.grid_stream;
+    if (wblocks < 1) wblocks = 1;
+    hipLaunchKernelGGL(k_store_copy, dim3((unsigned)wblocks), dim3(kBlock), 0, lc.stream, stage, g.nx, r0, r1,
+                       (const uint32_t*)L.row_xs, (const uint64_t*)lens, store, cap, row_org, L.S);
+    hipLaunchKernelGGL(k_store_advance, dim3(1), dim3(64), 0, lc.stream, L.S, cap);
+    return hipGetLastError();
+}
+
+// At close: the quantiser from the slabs' range (uint16 keys), the fixed
+// threshold, and the histogram from the class counts.  K <= 2^15 is certain
+// (checked at open for the whole uint16 range); a quantiser error (none is
+// possible for uint16 values with such a bound) leaves the histogram empty.
+__global__ __launch_bounds__(1024) void k_serve_resolve(DevState* S, double eb_value, double fixed_value,
+                                                        const unsigned long long* __restrict__ classes) {
+    __shared__ unsigned long long sh[256];
+    __shared__ int s_ok;
+    const int t = threadIdx.x;
+    if (t < 256) sh[t] = 0ull;
+    if (t == 0) {
+        resolve_core(S, 0, ROIX_EB_ABS, eb_value, 1, fixed_value);
+        const bool ok = S->status == 0;
+        if (ok && S->K > (int64_t)kQrFine) fail(S, ROIX_EDEVICE);
+        s_ok = ok && S->K <= (int64_t)kQrFine;
+    }
+    __syncthreads();
+    if (!s_ok) return;  // uniform
+    hist_from_classes(S, classes, sh);
+}
+
+hipError_t launch_serve_resolve(const LaunchCtx& lc, DevState* S, double eb_value, double fixed_value,
+                                const unsigned long long* classes) {
+    timer_begin(lc.timer, ST_RESOLVE, lc.stream);
+    hipLaunchKernelGGL(k_serve_resolve, dim3(1), dim3(1024), 0, lc.stream, S, eb_value, fixed_value, classes);
+    timer_end(lc.timer, ST_RESOLVE, lc.stream);
     return hipGetLastError();
 }
 

@@ -12,6 +12,7 @@
 // against a reference event recorded when the server was created.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <map>
 #include <thread>
 
@@ -24,6 +25,8 @@ using namespace roix;
 namespace {
 
 constexpr int64_t kServeRunsPerRow = 32;  // default run-array capacity of a served volume, per row
+constexpr int64_t kSlabPlanes = 32;       // default planes staged at once by a volume kept as row extents
+constexpr int64_t kStorePermille = 500;   // default store of such a volume, per mille of its voxels
 
 // First-fit allocator over [0, size) in 256-byte units.
 struct Pool {
@@ -78,11 +81,29 @@ struct Vol {
     roix_fused_out out;
     bool incremental = false;
     size_t off = 0, bytes = 0;  // pool region
-    uint8_t* d_vol = nullptr;   // resident input
+    uint8_t* d_vol = nullptr;   // resident input (whole volumes)
     Layout L;
     int64_t next_z = 0;
     VolState state = V_OPEN;
     hipEvent_t release_ev = nullptr;  // aborted: the pool region is free once this completes
+    // kept as row extents: the staged slab, the store of row extents, the
+    // code-class counts and per-row tables; stage_free marks the compute of
+    // the staged planes done (the next copy into the stage waits for it)
+    bool compact = false;
+    int64_t stage_planes = 0;
+    uint16_t* stage = nullptr;
+    uint16_t* store = nullptr;
+    uint64_t store_cap = 0;  // values
+    uint64_t* row_org = nullptr;
+    uint64_t* lens = nullptr;
+    unsigned long long* classes = nullptr;
+    hipEvent_t stage_free = nullptr;
+};
+
+// Geometry of a volume kept as row extents, in bytes from its region start.
+struct CompactPlan {
+    size_t stage, store, row_org, lens, classes, layout, total;
+    uint64_t store_cap;
 };
 
 struct Req {
@@ -98,12 +119,56 @@ bool incremental_of(roix_eb eb, const roix_criterion* crit) {
     return eb.mode == ROIX_EB_ABS && crit->thr == ROIX_THR_FIXED;
 }
 
-size_t volume_bytes(const Geom& g, roix_dtype dt, bool incremental, int64_t runs_per_row) {
-    const size_t in = align256((size_t)g.N * (dt == ROIX_F32 ? 4 : 2));
+// A uint16 volume with an absolute bound and a fixed threshold is kept as row
+// extents when every uint16 value codes within 2^15 classes: the device's
+// bound resolution (fp32 bound rounded toward zero, w = 2 eb32, r = 1 / w
+// through binary64) redone here, then rint(65535 r) <= 2^15 - 1, so that
+// K = qmax - qmin + 1 <= 2^15 whatever the data (the codes of 0 and 65535
+// bound every code).
+bool compact_of(roix_dtype dt, roix_eb eb, const roix_criterion* crit) {
+    if (dt != ROIX_U16 || !incremental_of(eb, crit)) return false;
+    if (!(eb.value > 0.0) || !(eb.value <= 3.4028234663852886e38)) return false;
+    float eb32 = (float)eb.value;
+    if ((double)eb32 > eb.value) eb32 = nextafterf(eb32, 0.0f);
+    if (!std::isnormal(eb32)) return false;
+    const float w = eb32 + eb32;
+    const float r = (float)(1.0 / (double)w);
+    if (!std::isnormal(w) || !std::isnormal(r)) return false;
+    const float q = rintf(65535.0f * r);
+    return q <= 32767.0f;
+}
+
+size_t runs_bytes(const Geom& g, int64_t runs_per_row) {
     uint64_t runs = (uint64_t)g.nrows * (uint64_t)runs_per_row;
     const uint64_t w = worst_runs(g);
     if (runs > w) runs = w;
-    return in + fixed_bytes(g, incremental ? 0 : proxy_kind(g, dt)) + (size_t)runs * kRunBytes;
+    return (size_t)runs * kRunBytes;
+}
+
+CompactPlan compact_plan(const Geom& g, int64_t slab_planes, int64_t permille, int64_t runs_per_row) {
+    CompactPlan p;
+    const int64_t sp = slab_planes < g.nz ? slab_planes : g.nz;
+    p.store_cap = (g.N * (uint64_t)permille + 999) / 1000;
+    size_t o = 0;
+    p.stage = o;
+    o += align256((size_t)sp * (size_t)g.nx * (size_t)g.ny * 2);
+    p.store = o;
+    o += align256((size_t)p.store_cap * 2 + 64);
+    p.row_org = o;
+    o += align256((size_t)g.nrows * 8);
+    p.lens = o;
+    o += align256((size_t)sp * (size_t)g.ny * 8);
+    p.classes = o;
+    o += align256((size_t)kQrFine * 8);
+    p.layout = o;
+    o += fixed_bytes(g, 0, sp * g.ny) + runs_bytes(g, runs_per_row);
+    p.total = o;
+    return p;
+}
+
+size_t volume_bytes(const Geom& g, roix_dtype dt, bool incremental, int64_t runs_per_row, uint64_t p16_min) {
+    const size_t in = align256((size_t)g.N * (dt == ROIX_F32 ? 4 : 2));
+    return in + fixed_bytes(g, incremental ? 0 : proxy_kind(g, dt, p16_min)) + runs_bytes(g, runs_per_row);
 }
 
 double pct(std::vector<double> v, double p) {
@@ -137,6 +202,11 @@ struct roix_server {
     std::vector<hipEvent_t> events;  // idle timing events
     int64_t next_vol = 1, next_req = 1;
     int64_t runs_per_row = kServeRunsPerRow;
+    int64_t slab_planes = kSlabPlanes, store_permille = kStorePermille;
+    size_t bytes_of(const Geom& g, roix_dtype dt, roix_eb eb, const roix_criterion* crit) const {
+        if (compact_of(dt, eb, crit)) return compact_plan(g, slab_planes, store_permille, runs_per_row).total;
+        return volume_bytes(g, dt, incremental_of(eb, crit), runs_per_row, ctx->p16_min);
+    }
     int64_t admitted = 0, refused = 0, slabs_done = 0, closes_done = 0, bytes_in = 0;
     std::vector<double> slab_lat, close_lat;
 
@@ -156,6 +226,10 @@ struct roix_server {
     void release(Vol& v) {
         pool.release(v.off, v.bytes);
         v.bytes = 0;
+        if (v.stage_free) {
+            hipEventDestroy(v.stage_free);
+            v.stage_free = nullptr;
+        }
     }
     // Account for every request and aborted volume whose events completed.
     void reap() {
@@ -213,6 +287,45 @@ static hipError_t enqueue_slab(const LaunchCtx& lc, Vol& v, int64_t z0, int64_t 
     return launch_union(lc, g, L, v.crit.connectivity);
 }
 
+// A staged chunk of planes [z0, z0 + nzs) of a volume kept as row extents:
+// the slab kernels on the stage (the input and bitmask pointers shifted so
+// that absolute row numbers land in the stage), then the code classes and
+// the store of the rows' extents.
+static hipError_t enqueue_slab_compact(const LaunchCtx& lc, Vol& v, int64_t z0, int64_t nzs) {
+    const Geom& g = v.g;
+    const int64_t r0 = z0 * g.ny, r1 = (z0 + nzs) * g.ny;
+    Layout L = v.L;
+    L.maskbits = (uint64_t*)((uintptr_t)v.L.maskbits - (uintptr_t)(r0 * g.W * 8));
+    const uint16_t* in = (const uint16_t*)((uintptr_t)v.stage - (uintptr_t)(r0 * g.nx * 2));
+    hipError_t e;
+    if ((e = launch_slab_mask(lc, in, ROIX_U16, g, r0, r1, L)) != hipSuccess) return e;
+    if ((e = launch_scan_u32_base(lc, L.row_nruns + r0, L.run_off + r0, r1 - r0, &L.S->n_runs, &L.S->seg_lo,
+                                  L.run_off + r1, L.scan_tmp, L.S, L.run_cap, ROIX_ENOMEM)) != hipSuccess)
+        return e;
+    if ((e = launch_runs_write(lc, g, L, r0, r1)) != hipSuccess) return e;
+    if ((e = launch_union(lc, g, L, v.crit.connectivity)) != hipSuccess) return e;
+    if ((e = launch_slab_classes(lc, v.stage, (uint64_t)nzs * (uint64_t)g.ny * (uint64_t)g.nx, L.S, v.classes)) !=
+        hipSuccess)
+        return e;
+    return launch_store_rows(lc, g, L, v.stage, r0, r1, v.store, v.store_cap, v.row_org, v.lens);
+}
+
+// The close of a volume kept as row extents: the quantiser and the histogram
+// from the slabs' range and class counts, then the rest of the path reading
+// the span values from the store.
+static roix_status enqueue_close_compact(const LaunchCtx& lc, Vol& v) {
+    DevState* S = v.L.S;
+    ROIX_TRY(launch_serve_status(lc, S, 1));
+    ROIX_TRY(launch_serve_resolve(lc, S, v.eb.value, v.crit.fixed_value, v.classes));
+    ROIX_TRY(launch_otsu(lc, S, true));
+    ROIX_TRY(launch_serve_status(lc, S, 0));
+    ROIX_TRY(components_and_keep(lc, v.g, v.L, &v.crit, v.out.d_comps, v.out.comps_cap));
+    ROIX_TRY(launch_spans_from_runs(lc, v.g, v.L));
+    ROIX_TRY(spans_and_emit(lc, v.g, v.L, v.store, ROIX_U16, &v.out));
+    ROIX_TRY(launch_finalize(lc, S, v.out.d_qinfo, v.out.d_sinfo, v.out.d_einfo, true));
+    return ROIX_OK;
+}
+
 // The stages of the fused path that need the whole volume.  The quantiser
 // stages (resolve, histogram, threshold) run with any run-capacity error of
 // the slabs held back, so that errors are reported in the fused path's order.
@@ -246,13 +359,21 @@ size_t roix_server_volume_bytes(const roix_server* s, roix_dims dims, roix_dtype
     if (!s || (dtype != ROIX_F32 && dtype != ROIX_U16) || !geom_of(dims, &g) || !eb_ok(eb) || !crit_ok(crit) ||
         crit->thr == ROIX_THR_OTSU_SLICE)
         return 0;
-    return volume_bytes(g, dtype, incremental_of(eb, crit), s->runs_per_row);
+    return s->bytes_of(g, dtype, eb, crit);
 }
 
 roix_status roix_server_set_param(roix_server* s, const char* name, int64_t value) {
     if (!s || !name) return ROIX_EINVAL;
     if (strcmp(name, "runs_per_row") == 0 && value >= 1 && value <= (1ll << 30)) {
         s->runs_per_row = value;
+        return ROIX_OK;
+    }
+    if (strcmp(name, "slab_planes") == 0 && value >= 1 && value <= 4096) {
+        s->slab_planes = value;
+        return ROIX_OK;
+    }
+    if (strcmp(name, "store_permille") == 0 && value >= 1 && value <= 1000) {
+        s->store_permille = value;
         return ROIX_OK;
     }
     return ROIX_EINVAL;
@@ -290,8 +411,10 @@ roix_status roix_server_destroy(roix_server* s) {
     if (s->compute) hipStreamSynchronize(s->compute);
     for (auto& kv : s->reqs)
         if (kv.second.done) hipEventDestroy(kv.second.done);
-    for (auto& kv : s->vols)
+    for (auto& kv : s->vols) {
         if (kv.second.release_ev) hipEventDestroy(kv.second.release_ev);
+        if (kv.second.stage_free) hipEventDestroy(kv.second.stage_free);
+    }
     for (hipEvent_t e : s->events) hipEventDestroy(e);
     if (s->ev_ref) hipEventDestroy(s->ev_ref);
     if (s->ev_copy) hipEventDestroy(s->ev_copy);
@@ -318,20 +441,46 @@ roix_status roix_volume_open(roix_server* s, roix_dims dims, roix_dtype dtype, r
     v.crit = *crit;
     v.out = *final_out;
     v.incremental = incremental_of(eb, crit);
-    v.bytes = volume_bytes(g, dtype, v.incremental, s->runs_per_row);
+    v.compact = compact_of(dtype, eb, crit);
+    v.bytes = s->bytes_of(g, dtype, eb, crit);
     if (!s->pool.alloc(v.bytes, &v.off)) {
         ++s->refused;
         return ROIX_EBUSY;
     }
-    v.d_vol = (uint8_t*)s->base + v.off;
-    const size_t in_bytes = align256((size_t)g.N * (dtype == ROIX_F32 ? 4 : 2));
-    if (!carve_at(v.d_vol + in_bytes, v.bytes - in_bytes, g, &v.L, v.incremental ? 0 : proxy_kind(g, dtype))) {
-        s->release(v);
-        return ROIX_ENOMEM;
+    uint8_t* region = (uint8_t*)s->base + v.off;
+    if (v.compact) {
+        const CompactPlan p = compact_plan(g, s->slab_planes, s->store_permille, s->runs_per_row);
+        v.stage_planes = s->slab_planes < g.nz ? s->slab_planes : g.nz;
+        v.stage = (uint16_t*)(region + p.stage);
+        v.store = (uint16_t*)(region + p.store);
+        v.store_cap = p.store_cap;
+        v.row_org = (uint64_t*)(region + p.row_org);
+        v.lens = (uint64_t*)(region + p.lens);
+        v.classes = (unsigned long long*)(region + p.classes);
+        if (!carve_at(region + p.layout, p.total - p.layout, g, &v.L, 0, v.stage_planes * g.ny)) {
+            s->release(v);
+            return ROIX_ENOMEM;
+        }
+        v.L.row_org = v.row_org;
+        v.L.nvals = v.store_cap;
+        if (hipEventCreateWithFlags(&v.stage_free, hipEventDisableTiming) != hipSuccess) {
+            v.stage_free = nullptr;
+            s->release(v);
+            return ROIX_EDEVICE;
+        }
+    } else {
+        v.d_vol = region;
+        const size_t in_bytes = align256((size_t)g.N * (dtype == ROIX_F32 ? 4 : 2));
+        if (!carve_at(v.d_vol + in_bytes, v.bytes - in_bytes, g, &v.L,
+                      v.incremental ? 0 : proxy_kind(g, dtype, s->ctx->p16_min))) {
+            s->release(v);
+            return ROIX_ENOMEM;
+        }
     }
     const LaunchCtx lc = serve_lctx(s);
     if (launch_init(lc, v.L.S) != hipSuccess ||
-        (v.incremental && launch_serve_open(lc, v.L.S, eb.value, crit->fixed_value) != hipSuccess)) {
+        (v.incremental && launch_serve_open(lc, v.L.S, eb.value, crit->fixed_value) != hipSuccess) ||
+        (v.compact && launch_store_open(lc, v.L.S, v.classes) != hipSuccess)) {
         s->release(v);
         return ROIX_EDEVICE;
     }
@@ -361,15 +510,33 @@ roix_status roix_slab_submit(roix_server* s, int64_t vol_id, int64_t z0, int64_t
     const size_t vb = v.dt == ROIX_F32 ? 4 : 2;
     const size_t plane = (size_t)v.g.nx * (size_t)v.g.ny * vb;
     const size_t bytes = plane * (size_t)nz_slab;
-    hipError_t e = hipMemcpyAsync(v.d_vol + plane * (size_t)z0, ptr, bytes,
-                                  ptr_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->copy);
-    if (v.incremental) {
-        if (e == hipSuccess) e = hipEventRecord(s->ev_copy, s->copy);
-        if (e == hipSuccess) e = hipStreamWaitEvent(s->compute, s->ev_copy, 0);
-        if (e == hipSuccess) e = enqueue_slab(serve_lctx(s), v, z0, nz_slab);
+    const hipMemcpyKind kind = ptr_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    hipError_t e = hipSuccess;
+    if (v.compact) {
+        // staged chunk by chunk: a copy into the stage waits until the
+        // compute of the chunk before it has read the stage
+        const LaunchCtx lc = serve_lctx(s);
+        for (int64_t p = 0; p < nz_slab && e == hipSuccess; p += v.stage_planes) {
+            const int64_t n = nz_slab - p < v.stage_planes ? nz_slab - p : v.stage_planes;
+            e = hipStreamWaitEvent(s->copy, v.stage_free, 0);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(v.stage, (const uint8_t*)ptr + plane * (size_t)p, plane * (size_t)n, kind, s->copy);
+            if (e == hipSuccess) e = hipEventRecord(s->ev_copy, s->copy);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s->compute, s->ev_copy, 0);
+            if (e == hipSuccess) e = enqueue_slab_compact(lc, v, z0 + p, n);
+            if (e == hipSuccess) e = hipEventRecord(v.stage_free, s->compute);
+        }
         if (e == hipSuccess) e = hipEventRecord(r.done, s->compute);
-    } else if (e == hipSuccess) {
-        e = hipEventRecord(r.done, s->copy);  // nothing to compute before the close
+    } else {
+        e = hipMemcpyAsync(v.d_vol + plane * (size_t)z0, ptr, bytes, kind, s->copy);
+        if (v.incremental) {
+            if (e == hipSuccess) e = hipEventRecord(s->ev_copy, s->copy);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s->compute, s->ev_copy, 0);
+            if (e == hipSuccess) e = enqueue_slab(serve_lctx(s), v, z0, nz_slab);
+            if (e == hipSuccess) e = hipEventRecord(r.done, s->compute);
+        } else if (e == hipSuccess) {
+            e = hipEventRecord(r.done, s->copy);  // nothing to compute before the close
+        }
     }
     if (e != hipSuccess) {
         s->events.push_back(r.done);
@@ -403,8 +570,9 @@ roix_status roix_volume_close(roix_server* s, int64_t vol_id, int64_t* req_id) {
     if (hipEventRecord(s->ev_copy, s->copy) != hipSuccess || hipStreamWaitEvent(s->compute, s->ev_copy, 0) != hipSuccess)
         st = ROIX_EDEVICE;
     if (st == ROIX_OK)
-        st = v.incremental ? enqueue_close_incremental(lc, v)
-                           : enqueue_fused(lc, v.g, v.L, v.d_vol, v.dt, v.eb, &v.crit, &v.out);
+        st = v.compact       ? enqueue_close_compact(lc, v)
+             : v.incremental ? enqueue_close_incremental(lc, v)
+                             : enqueue_fused(lc, v.g, v.L, v.d_vol, v.dt, v.eb, &v.crit, &v.out);
     if (st == ROIX_OK && hipEventRecord(r.done, s->compute) != hipSuccess) st = ROIX_EDEVICE;
     if (st != ROIX_OK) {
         s->events.push_back(r.done);

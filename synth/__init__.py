@@ -72,6 +72,8 @@ def _load():
         lib.synth_cylinder_f32.restype = ci
         lib.synth_rings_u16.argtypes = [vp, vp, i64, i64, i64, u64, dbl, dbl, dbl, ci, dbl, dbl, ci]
         lib.synth_rings_u16.restype = ci
+        lib.synth_rings_u16_planes.argtypes = [vp, vp, i64, i64, i64, i64, u64, dbl, dbl, dbl, ci, dbl, dbl, ci]
+        lib.synth_rings_u16_planes.restype = ci
         lib.synth_philox4x32_10.argtypes = [vp, vp, vp]
         lib.synth_philox4x32_10.restype = None
         lib.synth_bernoulli_u8.argtypes = [vp, i64, u64, dbl]
@@ -157,12 +159,15 @@ def cylinder(nx, ny, nz, seed, R=400.0, air=(0.02, 0.01), matrix=(0.5, 0.03), n_
 
 
 def rings(nx, ny, nz, seed, R=633.0, lam_in=12000.0, lam_out=800.0, n_rings=40, ring_rmax=1448.0,
-          ring_amp=200.0, with_cls=False, threads=None):
+          ring_amp=200.0, with_cls=False, threads=None, z0=0, out=None):
+    """The rings volume, or its planes [z0, z0 + nz) (slabs cut this way
+    assemble into the whole volume exactly); ``out`` may supply the array."""
     lib = _load()
-    vol = np.empty((nz, ny, nx), dtype=np.uint16)
+    vol = np.empty((nz, ny, nx), dtype=np.uint16) if out is None else out
+    assert vol.shape == (nz, ny, nx) and vol.dtype == np.uint16 and vol.flags.c_contiguous
     cls = np.empty((nz, ny, nx), dtype=np.uint8) if with_cls else None
-    rc = lib.synth_rings_u16(_ptr(vol), _ptr(cls), nx, ny, nz, seed, R, lam_in, lam_out, n_rings, ring_rmax,
-                             ring_amp, _threads(threads))
+    rc = lib.synth_rings_u16_planes(_ptr(vol), _ptr(cls), nx, ny, z0, nz, seed, R, lam_in, lam_out, n_rings,
+                                    ring_rmax, ring_amp, _threads(threads))
     if rc < 0:
         raise RuntimeError("synth_rings_u16 failed")
     return vol, cls
@@ -256,6 +261,14 @@ def served_stream(k, nz=256, nxy=2048, seed_base=3001, threads=None) -> np.ndarr
     noise, ring artefacts) of nxy x nxy x nz, sent in 32-plane slabs."""
     s = nxy / 2048.0
     vol, _ = rings(nxy, nxy, nz, seed_base + k, R=633.0 * s, ring_rmax=1448.0 * s, threads=threads)
+    return vol
+
+
+def served_slab(k, z0, nz=32, nxy=2048, seed_base=3001, threads=None, out=None) -> np.ndarray:
+    """Planes [z0, z0 + nz) of served stream k (generated alone, so a trace
+    need not hold whole streams in memory)."""
+    s = nxy / 2048.0
+    vol, _ = rings(nxy, nxy, nz, seed_base + k, R=633.0 * s, ring_rmax=1448.0 * s, threads=threads, z0=z0, out=out)
     return vol
 
 

@@ -279,10 +279,13 @@ int synth_cylinder_f32(float* out, uint8_t* cls, int64_t nx, int64_t ny, int64_t
  * lam_out outside, plus `offset` for every ring whose [radius, radius+width)
  * contains the voxel's radial distance.  Value = clamp(rint(lambda +
  * sqrt(lambda) * N(0,1)), 0, 65535). */
-int synth_rings_u16(uint16_t* out, uint8_t* cls, int64_t nx, int64_t ny, int64_t nz, uint64_t seed,
-                    double R, double lam_in, double lam_out, int n_rings, double ring_rmax,
-                    double ring_amp, int nthreads) {
-    if (!out || nx <= 0 || ny <= 0 || nz <= 0 || n_rings < 0) return -1;
+/* Planes [z0, z0 + nz) of that volume (the noise counter is the voxel's
+ * linear index in the whole volume, so slabs cut this way assemble into
+ * exactly the volume synth_rings_u16 writes). */
+int synth_rings_u16_planes(uint16_t* out, uint8_t* cls, int64_t nx, int64_t ny, int64_t z0, int64_t nz,
+                           uint64_t seed, double R, double lam_in, double lam_out, int n_rings, double ring_rmax,
+                           double ring_amp, int nthreads) {
+    if (!out || nx <= 0 || ny <= 0 || nz <= 0 || z0 < 0 || n_rings < 0) return -1;
     set_threads(nthreads);
     double ccx = 0.5 * (double)nx, ccy = 0.5 * (double)ny;
     double* rr = (double*)malloc(sizeof(double) * (size_t)(n_rings > 0 ? n_rings : 1));
@@ -316,7 +319,7 @@ int synth_rings_u16(uint16_t* out, uint8_t* cls, int64_t nx, int64_t ny, int64_t
         for (int64_t p = 0; p < nx * ny; ++p) {
             uint64_t v = (uint64_t)(z * nx * ny + p);
             double l = (double)lam[p];
-            double val = rint(l + sqrt(l) * normal_at(seed, ST_NOISE, v));
+            double val = rint(l + sqrt(l) * normal_at(seed, ST_NOISE, v + (uint64_t)(z0 * nx * ny)));
             if (val < 0) val = 0;
             if (val > 65535) val = 65535;
             out[v] = (uint16_t)val;
@@ -325,6 +328,13 @@ int synth_rings_u16(uint16_t* out, uint8_t* cls, int64_t nx, int64_t ny, int64_t
     }
     free(rr); free(rw); free(ra); free(lam); free(inside);
     return 0;
+}
+
+int synth_rings_u16(uint16_t* out, uint8_t* cls, int64_t nx, int64_t ny, int64_t nz, uint64_t seed,
+                    double R, double lam_in, double lam_out, int n_rings, double ring_rmax,
+                    double ring_amp, int nthreads) {
+    return synth_rings_u16_planes(out, cls, nx, ny, 0, nz, seed, R, lam_in, lam_out, n_rings, ring_rmax,
+                                  ring_amp, nthreads);
 }
 
 /* Uniform random bytes (for tiny adversarial test masks); byte v is 1 with

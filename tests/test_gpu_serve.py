@@ -1,8 +1,10 @@
 """Served form: volumes streamed slab by slab must give exactly the outputs
 of one plain fused call on the assembled volume (and so of the oracle), for
-any slab sizes, interleaved volumes and host or device sources; and the
-request state machine must refuse what it should (out-of-order, repeated or
-missing slabs, a full pool) without disturbing the other volumes."""
+any slab sizes, interleaved volumes and host or device sources, under both
+quantiser flows, and at the detector's slab shape (2048 x 2048 x 32 uint16
+planes); and the request state machine must refuse what it should
+(out-of-order, repeated or missing slabs, a full pool) without disturbing the
+other volumes."""
 import numpy as np
 import pytest
 
@@ -19,12 +21,17 @@ def _equal(a, b):
         assert bytes(a[k]) == bytes(b[k]), k
 
 
-@pytest.fixture(scope="module")
-def env():
+@pytest.fixture(scope="module", params=["default", "onepass"])
+def env(request):
+    # "onepass": every float32 volume with an absolute bound that a server
+    # reduces whole at close (and every plain reference) takes the one-pass
+    # 16-bit-proxy flow, whatever its size
     import torch
 
     from paper_2602_15917_amd import roix
-    ctx = roix.Context(0, 1 << 30)
+    ctx = roix.Context(0, 2 << 30)
+    if request.param == "onepass":
+        ctx.set_param("fused16_min_voxels", 0)
     yield ctx, roix, torch
     ctx.close()
 
@@ -89,6 +96,9 @@ CASES = [
      synth.Criterion("fixed", 0.55, 26, "min_size", 1)),
     ("noise f32 fixed 6", lambda: synth.normal((13, 33, 129), 7101, 0.5, 0.1), ("abs", 1e-3),
      synth.Criterion("fixed", 0.5, 6, "largest", 1)),
+    # a bound too fine for 2^15 code classes: kept whole, not as row extents
+    ("rings u16 fixed 26 fine", lambda: synth.rings2048(nxy=128, nz=20).volume, ("abs", 0.4),
+     synth.Criterion("fixed", 6400.0, 26, "largest", 1)),
 ]
 
 
@@ -296,5 +306,99 @@ def test_run_capacity_error_is_isolated(env):
         crit = criterion(roix, cc)
         ref, _ = plain(env, vol, ebm, ebv, crit)
         _equal(stream_volume(env, srv, vol, ebm, ebv, crit, (9,)), ref)
+    finally:
+        srv.close_server()
+
+
+def test_detector_slab_shape_equals_plain(env):
+    """uint16 2048 x 2048 planes in 32-plane slabs from pinned host memory
+    (ring-artefact cylinder; ABS bound = 1e-4 x a calibration volume's range;
+    FIXED threshold 6400; 26-connectivity; largest component), interleaved
+    with a float32 cube sent whole, each equal to its plain call."""
+    ctx, roix, torch = env
+    calib = synth.served_calibration(nz=4)
+    eb = 1e-4 * (float(calib.max()) - float(calib.min()))
+    crit = roix.Criterion("fixed", 6400.0, 26, "largest", 1)
+    vol = synth.served_stream(0, nz=96)
+    cube = synth.served_cube(1, side=(128, 160))
+    ccrit = criterion(roix, cube.criterion)
+    log(f"[case] served detector slabs {vol.shape} eb={eb:.4g} + cube {cube.volume.shape}")
+    ref, caps = plain(env, vol, "abs", eb, crit)
+    cref, ccaps = plain(env, cube.volume, cube.eb_mode, cube.eb_value, ccrit)
+    srv = roix.Server(ctx, 8 << 30)
+    try:
+        out = roix.Outputs("cuda:0", *caps)
+        cout = roix.Outputs("cuda:0", *ccaps)
+        vid = srv.open(vol.shape, roix.U16, "abs", eb, crit, out)
+        reqs, keep = [], []
+        for k, z0 in enumerate(range(0, vol.shape[0], 32)):
+            t = torch.from_numpy(np.ascontiguousarray(vol[z0:z0 + 32])).pin_memory()
+            keep.append(t)
+            reqs.append(srv.submit(vid, z0, t))
+            if k == 1:  # the cube arrives between two slabs
+                cid = srv.open(cube.volume.shape, roix.F32, cube.eb_mode, cube.eb_value, ccrit, cout)
+                ct = torch.from_numpy(cube.volume).pin_memory()
+                keep.append(ct)
+                reqs.append(srv.submit(cid, 0, ct))
+                reqs.append(srv.close(cid))
+        reqs.append(srv.close(vid))
+        for r in reqs:
+            assert srv.wait(r).status == 0
+        torch.cuda.synchronize()
+        got = out.collect()
+        assert got["einfo"].status == 0 and got["einfo"].n_codes > 0 and got["sinfo"].n_components >= 1
+        _equal(got, ref)
+        _equal(cout.collect(), cref)
+        st = srv.stats()
+        assert st.slabs_done == 3 + 1 and st.closes_done == 2
+    finally:
+        srv.close_server()
+
+
+@pytest.mark.parametrize("planes", [1, 3, 32])
+def test_row_extent_store_staged_in_chunks(env, planes):
+    """A uint16 stream kept as row extents, staged a few planes at a time
+    (slabs larger than the stage go in turn), equals plain."""
+    ctx, roix, torch = env
+    name, make, (ebm, ebv), c = CASES[1]
+    vol = make()
+    crit = criterion(roix, c)
+    log(f"[case] served row extents, {planes} planes staged")
+    ref, _ = plain(env, vol, ebm, ebv, crit)
+    srv = server(roix, ctx, 2 << 30)
+    try:
+        srv.set_param("slab_planes", planes)
+        for sizes in ((7, 1, 3), (23,)):
+            _equal(stream_volume(env, srv, vol, ebm, ebv, crit, sizes, source="host"), ref)
+    finally:
+        srv.close_server()
+
+
+def test_row_extent_store_bytes_and_overflow(env):
+    ctx, roix, torch = env
+    log("[case] served row-extent store: size and overflow")
+    srv = roix.Server(ctx, 1 << 30)
+    try:
+        crit = roix.Criterion("fixed", 6400.0, 26, "largest", 1)
+        shape = (1024, 2048, 2048)
+        srv.set_param("runs_per_row", 4)
+        compact = srv.volume_bytes(shape, roix.U16, "abs", 1.24, crit)
+        whole = srv.volume_bytes(shape, roix.U16, "abs", 0.4, crit)
+        assert 0 < compact * 1.8 < whole, (compact, whole)  # default store: half the voxels
+        # a store of 32 % of the voxels: the cylinder's share of the field of view (30 %) and a margin
+        srv.set_param("store_permille", 320)
+        assert srv.volume_bytes(shape, roix.U16, "abs", 1.24, crit) * 2.6 < whole
+        srv.set_param("runs_per_row", 32)
+        # a store too small for the extents fails that volume only
+        name, make, (ebm, ebv), c = CASES[1]
+        vol = make()
+        cr = criterion(roix, c)
+        srv.set_param("store_permille", 1)
+        got = stream_volume(env, srv, vol, ebm, ebv, cr, (5,))
+        assert got["sinfo"].status == roix.ENOMEM and got["einfo"].status == roix.ENOMEM
+        assert got["qinfo"].status == 0
+        srv.set_param("store_permille", 500)
+        ref, _ = plain(env, vol, ebm, ebv, cr)
+        _equal(stream_volume(env, srv, vol, ebm, ebv, cr, (5,)), ref)
     finally:
         srv.close_server()
