@@ -442,10 +442,158 @@ def ctx_absq(roix, px, e):
     return qx, info
 
 
-def bench_batched(args):
-    """64 float32 volumes, sides U{64..512} per axis, 1-8 ellipsoids, eb from
-    {1e-3, 1e-4, 1e-5}: one batched graph launch against the same volumes
-    run one plain call after another."""
+# ------------------------------------------------------------ extra sections
+# The default run reports, beside the headline plain workload, every other
+# configuration of the metric: the 128^3 volume (launch-bound), the 8 GB
+# uint16 stack, the 64-volume batch and the served slab stream.  Each is
+# checked for parity before its figure is reported: against the digests the
+# oracle wrote (tests/golden/digests.json) for the single volumes, against
+# per-volume plain calls for the batched and served forms.
+
+GOLDEN = os.path.join(ROOT, "tests", "golden", "digests.json")
+
+
+def _sha(a):
+    import hashlib
+
+    import numpy as np
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def golden_parity(name, g):
+    """Compare collected outputs with the oracle's digests of workload `name`:
+    'bit-exact' or the list of fields that differ."""
+    import numpy as np
+    gold = json.load(open(GOLDEN)).get(name) if os.path.exists(GOLDEN) else None
+    if gold is None:
+        return "no oracle digest"
+    q, s, e = g["qinfo"], g["sinfo"], g["einfo"]
+    bad = []
+    if (q.status, s.status, e.status) != (0, 0, 0):
+        bad.append("status")
+    for f in ("qmin", "qmax", "K", "width_bits", "esc"):
+        if getattr(q, f) != gold["quant"][f]:
+            bad.append(f)
+    for f in ("xmin", "xmax", "eb32", "w", "r"):
+        if np.float32(getattr(q, f)) != np.float32(gold["quant"][f]):
+            bad.append(f)
+    for f in ("otsu_bin", "q_thr", "flags", "n_mask", "n_components", "n_kept", "n_kept_voxels"):
+        if getattr(s, f) != gold["seg"][f]:
+            bad.append(f)
+    if list(s.bbox) != gold["seg"]["bbox"]:
+        bad.append("bbox")
+    if _sha(np.frombuffer(bytes(s.hist), np.uint64)) != gold["seg"]["hist_sha256"]:
+        bad.append("hist")
+    for f in ("n_rows", "n_codes", "n_outliers", "stream_bytes"):
+        if getattr(e, f) != gold["extract"][f]:
+            bad.append(f)
+    for k in ("rows", "stream", "outliers", "comps"):
+        if _sha(g[k]) != gold["sha256"][k]:
+            bad.append(k)
+    return "bit-exact with the oracle's digests" if not bad else {"differs": bad}
+
+
+def b_alg(N, s, n_codes, code_bytes, n_rows):
+    """The method's byte model: two input reads, a 1-byte proxy written and
+    read, the span voxels re-read, the codes and the row table written."""
+    return N * (2 * s + 2) + n_codes * (s + code_bytes) + 32 * n_rows
+
+
+def plain_single(name, w, steps, warmup, dev="cuda:0"):
+    """Time the plain fused path on one workload (device-resident input) and
+    check it against the oracle's digests."""
+    import torch
+
+    from paper_2602_15917_amd import roix
+    crit = roix.Criterion(w.criterion.thr, 0.0, w.criterion.connectivity, w.criterion.keep, w.criterion.min_size)
+    x = torch.from_numpy(w.volume).to(dev)
+    s = w.volume.itemsize
+    w.volume = None
+    dims = roix.dims_of(x)
+    dt = roix.dtype_of(x)
+    ctx = roix.Context(0, roix.scratch_bytes(dims, dt, crit))
+    b = roix.bounds(dims, dt, crit)
+    out = roix.Outputs(dev, b["rows"], b["stream_bytes"], min(b["outliers"], 1 << 26), 1 << 20)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        ctx.fused(x, w.eb_mode, w.eb_value, crit, out, stream)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        ctx.fused(x, w.eb_mode, w.eb_value, crit, out, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    g = out.collect()
+    parity = golden_parity(name, g)
+    e, qi = g["einfo"], g["qinfo"]
+    N = x.numel()
+    ba = b_alg(N, s, int(e.n_codes), int(qi.width_bits) // 8, int(e.n_rows))
+    res = {"workload": w.name, "ms": round(ms, 4), "steps": steps, "GBps": round(N * s / (ms * 1e-3) / 1e9, 2),
+           "alg_bytes": int(ba), "frac": round(ba / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "n_codes": int(e.n_codes), "reduction": round(N / max(int(e.n_codes), 1), 3), "parity": parity}
+    del x, out
+    ctx.close()
+    torch.cuda.empty_cache()
+    return res
+
+
+def section_c0(args):
+    """128^3 float32 ellipsoids (ABS 1e-3, Otsu, 6-connectivity, components
+    of 64 voxels or more): launch-bound; 100 timed calls."""
+    import synth
+    w = synth.ellipsoids128()
+    r = plain_single("ellipsoids128", w, steps=100, warmup=5)
+    log(f"c0 {r['workload']}: {r['ms']:.4f} ms, {r['GBps']} GB/s, parity {r['parity']}")
+    return r
+
+
+def section_c2(args):
+    """2048 x 2048 x 1024 uint16 stack (REL 1e-4, Otsu, 26-connectivity,
+    largest component): 8.6 GB, 5 timed calls."""
+    import synth
+    t = time.time()
+    w = synth.rings2048()
+    log(f"c2 generated in {time.time() - t:.1f}s")
+    r = plain_single("rings2048", w, steps=5, warmup=2)
+    log(f"c2 {r['workload']}: {r['ms']:.3f} ms, {r['GBps']} GB/s, frac {r['frac']}, parity {r['parity']}")
+    return r
+
+
+def device_sections(out):
+    """Info structs (host bytes) and output sections trimmed to their counts,
+    left on the device."""
+    import torch
+
+    from paper_2602_15917_amd import roix
+    q = bytes(out.qinfo.cpu().numpy().tobytes())
+    s = bytes(out.sinfo.cpu().numpy().tobytes())
+    e = bytes(out.einfo.cpu().numpy().tobytes())
+    ei = roix.ExtractInfo.from_buffer_copy(e)
+    si = roix.SegInfo.from_buffer_copy(s)
+    qi = roix.QuantInfo.from_buffer_copy(q)
+    rows_cap, stream_cap, outl_cap, comps_cap = out.caps
+    nr, nb = min(int(ei.n_rows), rows_cap), min(int(ei.stream_bytes), stream_cap)
+    no, nc = min(int(ei.n_outliers), outl_cap), min(int(si.n_components), comps_cap)
+    return {"info": (q, s, e), "status": (int(qi.status), int(si.status), int(ei.status)),
+            "n_codes": int(ei.n_codes), "n_rows": int(ei.n_rows), "code_bytes": int(qi.width_bits) // 8,
+            "sec": (out.rows[: nr * roix.ROW_BYTES], out.stream[:nb], out.outliers[:no].view(torch.int32),
+                    out.comps[: nc * roix.COMP_BYTES])}
+
+
+def sections_equal(a, b):
+    import torch
+    return a["info"] == b["info"] and all(x.numel() == y.numel() and torch.equal(x, y)
+                                          for x, y in zip(a["sec"], b["sec"]))
+
+
+def section_batched(args):
+    """The 64-volume batch (float32, sides U{64..512} per axis, 1-8
+    ellipsoids, eb from {1e-3, 1e-4, 1e-5}, Otsu, 6-connectivity, components
+    of 64 voxels or more) in one batched call, against the same volumes run
+    one plain call after another; every output of the batch is compared with
+    its plain call on the device."""
     import torch
 
     import synth
@@ -453,87 +601,94 @@ def bench_batched(args):
 
     dev = "cuda:0"
     t0 = time.time()
-    vols = [synth.batch_volume(j) for j in range(args.batch_volumes)]
-    total = sum(w.volume.nbytes for w in vols)
-    log(f"generated {len(vols)} volumes, {total / 1e9:.2f} GB, in {time.time() - t0:.1f}s")
-    items = []
-    need = 0
-    for w in vols:
-        crit = roix.Criterion(w.criterion.thr, 0.0, w.criterion.connectivity, w.criterion.keep,
-                              w.criterion.min_size)
+    items, refs, need = [], [], 0
+    total = 0
+    for j in range(args.batch_volumes):
+        w = synth.batch_volume(j)
+        crit = roix.Criterion(w.criterion.thr, 0.0, w.criterion.connectivity, w.criterion.keep, w.criterion.min_size)
         t = torch.from_numpy(w.volume).to(dev)
+        total += w.volume.nbytes
         dims = roix.dims_of(t)
         b = roix.bounds(dims, roix.F32, crit)
-        out = roix.Outputs(dev, b["rows"], b["stream_bytes"], min(b["outliers"], 1 << 24),
-                           min(b["components"], 1 << 20))
-        items.append((t, w.eb_mode, w.eb_value, crit, out))
+        caps = (b["rows"], b["stream_bytes"], min(b["outliers"], 1 << 24), min(b["components"], 1 << 20))
+        items.append((t, w.eb_mode, w.eb_value, crit, roix.Outputs(dev, *caps)))
+        refs.append(roix.Outputs(dev, *caps))
         need = max(need, roix.scratch_bytes(dims, roix.F32, crit))
-        w.volume = None
-    streams = args.batch_streams
-    ctx = roix.Context(0, need * streams)
-    ctx.set_param("batch_streams", streams)
+    log(f"batched: generated {len(items)} volumes, {total / 1e9:.2f} GB, in {time.time() - t0:.1f}s")
+    ctx = roix.Context(0, need * args.batch_streams)
+    ctx.set_param("batch_streams", args.batch_streams)
     ctx.set_param("batch_graph", args.batch_graph)
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    tuning = None
-    if args.autotune:  # the launch parameters, tuned on the largest volume of the batch
-        big = max(items, key=lambda it: it[0].numel())
-        tr = ctx.autotune(big[0], big[1], big[2], big[3], big[4], reps=3, stream=stream)
-        tuning = {"on_voxels": int(big[0].numel()), "default_ms": round(tr.default_ms, 4),
-                  "best_ms": round(tr.best_ms, 4), "params": dict(zip(roix.TUNE_PARAMS, [int(v) for v in tr.params]))}
-        log(f"autotune: {tuning}")
 
-    def plain_pass():
-        for (t, ebm, ebv, crit, out) in items:
-            ctx.fused(t, ebm, ebv, crit, out, stream)
+    def plain_pass(outs):
+        for (t, ebm, ebv, crit, _), o in zip(items, outs):
+            ctx.fused(t, ebm, ebv, crit, o, stream)
 
     def batch_pass():
         ctx.fused_batch(items, stream)
 
+    # parity first: the batch against one plain call per volume
+    plain_pass(refs)
+    batch_pass()
+    torch.cuda.synchronize()
+    ba_total, equal, bad = 0, True, []
+    for j, (it, ref) in enumerate(zip(items, refs)):
+        a, b = device_sections(it[4]), device_sections(ref)
+        if b["status"] != (0, 0, 0):
+            bad.append(j)
+        equal = equal and sections_equal(a, b)
+        ba_total += b_alg(it[0].numel(), 4, b["n_codes"], b["code_bytes"], b["n_rows"])
     res = {}
-    for name, fn in (("plain", plain_pass), ("batched", batch_pass)):
+    for name, fn in (("plain", lambda: plain_pass(refs)), ("batched", batch_pass)):
         for _ in range(args.warmup):
             fn()
         torch.cuda.synchronize()
-        bad = [i for i, it in enumerate(items) if it[4].collect()["einfo"].status != 0]
-        if bad:
-            log(f"{name}: volumes {bad[:5]} report a non-zero status")
-            sys.exit(1)
         ev0.record(stream)
-        for _ in range(args.steps):
+        for _ in range(args.batch_steps):
             fn()
         ev1.record(stream)
         torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / args.steps
-        res[name] = ms
-        log(f"{name}: {ms:.3f} ms per batch, {total / (ms * 1e-3) / 1e9:.1f} GB/s input")
-    gbs = total / (res["batched"] * 1e-3) / 1e9
-    line = {
-        "metric": METRIC, "value": round(gbs, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(res["batched"], 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"batched: {len(items)} f32 volumes, sides U{{64..512}}, 1-8 ellipsoids, "
-                               f"eb in {{1e-3,1e-4,1e-5}}, Otsu, 6-connectivity, components >= 64",
-                   "input_bytes": total, "batch_streams": streams, "graph": bool(args.batch_graph)},
-        "plain_sequential_ms": round(res["plain"], 4),
-        "plain_sequential_gbs": round(total / (res["plain"] * 1e-3) / 1e9, 2),
-        "batched_over_plain": round(res["plain"] / res["batched"], 3),
-    }
-    if tuning:
-        line["autotune"] = tuning
-    print(json.dumps(line))
+        res[name] = ev0.elapsed_time(ev1) / args.batch_steps
+    # and once more after the timed repeats
+    equal = equal and all(sections_equal(device_sections(it[4]), device_sections(r)) for it, r in zip(items, refs))
+    out = {"workload": f"{len(items)} f32 volumes, sides U{{64..512}}, 1-8 ellipsoids, eb in {{1e-3,1e-4,1e-5}}, "
+                       f"Otsu, 6-connectivity, components >= 64",
+           "input_bytes": total, "ms": round(res["batched"], 4), "steps": args.batch_steps,
+           "GBps": round(total / (res["batched"] * 1e-3) / 1e9, 2),
+           "alg_bytes": int(ba_total), "frac": round(ba_total / (res["batched"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "plain_sequential_ms": round(res["plain"], 4),
+           "plain_sequential_GBps": round(total / (res["plain"] * 1e-3) / 1e9, 2),
+           "batched_over_plain": round(res["plain"] / res["batched"], 3),
+           "parity": "equal to per-volume plain calls" if equal and not bad else
+                     {"equal": bool(equal), "nonzero_status": bad}}
+    log(f"batched: {out['ms']} ms ({out['GBps']} GB/s, frac {out['frac']}) vs plain {out['plain_sequential_ms']} ms; "
+        f"parity {out['parity']}")
+    del items, refs
     ctx.close()
+    torch.cuda.empty_cache()
+    return out
 
 
-def bench_served(args):
-    """Open-loop replay of a served trace: uint16 2048x2048 streams arriving
-    in 32-plane slabs (ABS bound = 1e-4 x the range of a calibration volume,
-    FIXED threshold 6400, 26-connectivity, largest component) interleaved
-    with float32 cubes sent whole (Otsu, reduced at close), Poisson arrivals,
-    an HBM budget.  Latency = completion on the device - scheduled arrival
-    (queueing, admission waits, pinned H2D and compute included).  Then the
-    closed-loop capacity (everything submitted at once) and the host-resident
-    plain comparator (pinned H2D + fused call, one volume after another)."""
+def section_served(args):
+    """The served slab stream: `served_streams` uint16 2048 x 2048 volumes
+    of `served_nz` planes (ring-artefact cylinders; ABS bound = 1e-4 x the
+    range of a calibration volume; FIXED threshold 6400; 26-connectivity;
+    largest component) arriving in 32-plane slabs, interleaved with
+    `served_cubes` float32 cubes of side U{128..512} sent whole (ABS 1e-3,
+    Otsu, reduced at close), Poisson arrivals at each rate, an HBM budget.
+
+    Inputs: one stream's planes are generated once into pinned memory; stream
+    k sends them rotated by 4k slabs (the cylinder and rings are constant
+    along z and the noise independent per plane, so each rotation is a volume
+    of the same make-up); the cubes are 16 generated ones, reused in turn.
+    Latency of a request = completion on the device - its scheduled arrival
+    (queueing, waits for admission, pinned H2D and compute included).  At the
+    first rate the whole trace runs and every volume's output is compared
+    with a plain call on the assembled volume; the other rates replay the
+    trace for at most `served_seconds` each."""
+    import collections
+
     import numpy as np
     import torch
 
@@ -541,152 +696,201 @@ def bench_served(args):
     from paper_2602_15917_amd import roix
 
     dev = "cuda:0"
-    SLAB = 32
+    SLAB, NXY = 32, 2048
+    nz = args.served_nz
+    nslab = nz // SLAB
     t0 = time.time()
     calib = synth.served_calibration(nz=8)
     eb_s = 1e-4 * (float(calib.max()) - float(calib.min()))
+    del calib
     crit_s = roix.Criterion("fixed", 6400.0, 26, "largest", 1)
-    streams = [torch.from_numpy(synth.served_stream(k, nz=args.served_nz)).pin_memory()
-               for k in range(args.served_streams)]
-    cubes = []
-    for k in range(args.served_cubes):
+    pool = torch.empty((nz, NXY, NXY), dtype=torch.uint16, pin_memory=True)
+    pnp = pool.numpy()
+    for j in range(nslab):
+        synth.served_slab(0, j * SLAB, nz=SLAB, out=pnp[j * SLAB:(j + 1) * SLAB])
+    cube_pool = []
+    for k in range(min(16, args.served_cubes)):
         w = synth.served_cube(k)
         c = w.criterion
-        cubes.append((torch.from_numpy(w.volume).pin_memory(), w.eb_mode, w.eb_value,
-                      roix.Criterion(c.thr, c.fixed_value, c.connectivity, c.keep, c.min_size)))
-    total = sum(t.numel() * t.element_size() for t in streams) + sum(c[0].numel() * 4 for c in cubes)
-    log(f"served trace: {len(streams)} u16 streams of {tuple(streams[0].shape) if streams else ()}, "
-        f"{len(cubes)} f32 cubes, {total / 1e9:.2f} GB, eb {eb_s:.4g}; generated in {time.time() - t0:.1f}s")
-    ctx = roix.Context(0, 1 << 20)
+        cube_pool.append((torch.from_numpy(w.volume).pin_memory(), w.eb_mode, w.eb_value,
+                          roix.Criterion(c.thr, c.fixed_value, c.connectivity, c.keep, c.min_size)))
+    n_streams, n_cubes = args.served_streams, args.served_cubes
+    slab_bytes = SLAB * NXY * NXY * 2
+    total = n_streams * nz * NXY * NXY * 2 + sum(cube_pool[i % len(cube_pool)][0].numel() * 4 for i in range(n_cubes))
+    log(f"served: {n_streams} u16 streams of {nz} planes, {n_cubes} f32 cubes, {total / 1e9:.1f} GB, eb {eb_s:.4g}; "
+        f"inputs generated in {time.time() - t0:.1f}s")
 
-    def outputs(t, crit):
-        dims = roix.dims_of(t)
-        dt = roix.dtype_of(t)
-        b = roix.bounds(dims, dt, crit)
-        return roix.Outputs(dev, b["rows"], t.numel() * 4 + 64, min(b["outliers"], 1 << 24),
-                            min(b["components"], 1 << 22))
+    def slab_of(k, j):  # pinned view of stream k's slab j
+        p = (j + 4 * k) % nslab
+        return pool[p * SLAB:(p + 1) * SLAB]
 
-    outs_s = [outputs(t, crit_s) for t in streams]
-    outs_c = [outputs(c[0], c[3]) for c in cubes]
+    Nst = nz * NXY * NXY
+    s_caps = (nz * NXY, int(0.45 * Nst) * 2 + 256, 1 << 24, 1 << 20)
+    outs_s = [roix.Outputs(dev, *s_caps) for _ in range(n_streams)]
+    outs_c = []
+    for i in range(n_cubes):
+        t = cube_pool[i % len(cube_pool)][0]
+        b = roix.bounds(roix.dims_of(t), roix.F32, cube_pool[i % len(cube_pool)][3])
+        outs_c.append(roix.Outputs(dev, b["rows"], t.numel() * 2 + 256, 1 << 22, min(b["components"], 1 << 22)))
     # the trace: every slab of every stream (in order) and every cube, interleaved at random
     rng = np.random.default_rng(3000)
-    kinds = [("s", k, z) for k in range(len(streams)) for z in range(0, streams[k].shape[0], SLAB)]
-    kinds += [("c", k, 0) for k in range(len(cubes))]
-    order = rng.permutation(len(kinds))
-    events, nexts = [], [0] * len(streams)
-    for i in order:  # keep each stream's slabs in order: take its next slab instead
-        kind, k, _ = kinds[i]
+    kinds = [("s", k) for k in range(n_streams) for _ in range(nslab)] + [("c", i) for i in range(n_cubes)]
+    events, nexts = [], [0] * n_streams
+    for i in rng.permutation(len(kinds)):
+        kind, k = kinds[i]
         if kind == "s":
-            events.append(("s", k, nexts[k] * SLAB))
+            events.append(("s", k, nexts[k]))
             nexts[k] += 1
         else:
-            events.append(kinds[i])
+            events.append(("c", k, 0))
+    ctx = roix.Context(0, 1 << 20)
 
-    def replay(rate):
+    def replay(rate, max_seconds):
         srv = roix.Server(ctx, int(args.served_budget_gib * (1 << 30)))
-        # cubes whose Otsu threshold falls in the noise have ~nx/4 runs per row
-        srv.set_param("runs_per_row", 256)
+        # the streams keep their rows' extents in a store of 40 % of their voxels
+        # (the cylinder covers 30 % of the field of view)
+        srv.set_param("store_permille", 400)
         t_base = time.perf_counter()
         gaps = rng.exponential(1.0 / rate, size=len(events)) if rate > 0 else np.zeros(len(events))
         arrivals = np.cumsum(gaps) * 1e3 + 5.0  # ms on the server clock
-        vid = {}
-        recs = []  # (req, arrival_ms, kind)
-        busy_ms = 0.0
+        ev = [(e, a) for e, a in zip(events, arrivals) if max_seconds is None or a <= max_seconds * 1e3]
+        vid = {}          # ("s", k) or ("c", i) -> volume id once admitted
+        pending = collections.deque()
+        recs = []         # (request id, arrival ms, kind)
+        closed = set()
 
-        def admit(shape, dt, ebm, ebv, crit, out):
-            nonlocal busy_ms
-            t = time.perf_counter()
-            while True:
+        def try_submit(e, arr):
+            kind, k, j = e
+            key = (kind, k)
+            if key not in vid:
+                # run capacity per row: a cylinder chord is one run; a cube
+                # whose Otsu split falls in the noise has many runs per row
+                if kind == "s":
+                    shape, dt, ebm, ebv, crit, out = (nz, NXY, NXY), roix.U16, "abs", eb_s, crit_s, outs_s[k]
+                    srv.set_param("runs_per_row", 4)
+                else:
+                    c = cube_pool[k % len(cube_pool)]
+                    shape, dt, ebm, ebv, crit, out = tuple(c[0].shape), roix.F32, c[1], c[2], c[3], outs_c[k]
+                    srv.set_param("runs_per_row", 256)
                 try:
-                    return srv.open(shape, dt, ebm, ebv, crit, out)
-                except roix.RoixError as e:
-                    if e.status != roix.EBUSY:
+                    vid[key] = srv.open(shape, dt, ebm, ebv, crit, out)
+                except roix.RoixError as err:
+                    if err.status != roix.EBUSY:
                         raise
-                    time.sleep(0.0005)
-                    busy_ms += 0.5
-                    if time.perf_counter() - t > 60:
-                        raise
-        for (kind, k, z0), arr in zip(events, arrivals):
+                    return False
+            v = vid[key]
+            if kind == "s":
+                recs.append((srv.submit(v, j * SLAB, slab_of(k, j)), arr, "slab"))
+                if j == nslab - 1:
+                    recs.append((srv.close(v), arr, "stream_close"))
+                    closed.add(key)
+            else:
+                srv.submit(v, 0, cube_pool[k % len(cube_pool)][0])
+                recs.append((srv.close(v), arr, "cube"))
+                closed.add(key)
+            return True
+
+        def drain():
+            blocked = set()
+            for _ in range(len(pending)):
+                e, arr = pending.popleft()
+                key = (e[0], e[1])
+                if key in blocked or not try_submit(e, arr):
+                    blocked.add(key)
+                    pending.append((e, arr))
+
+        for e, arr in ev:
             now = (time.perf_counter() - t_base) * 1e3
             if arr > now:
                 time.sleep((arr - now) * 1e-3)
-            if kind == "s":
-                t = streams[k]
-                if z0 == 0:
-                    vid[k] = admit(tuple(t.shape), roix.U16, "abs", eb_s, crit_s, outs_s[k])
-                recs.append((srv.submit(vid[k], z0, t[z0:z0 + SLAB]), arr, "slab"))
-                if z0 + SLAB >= t.shape[0]:
-                    recs.append((srv.close(vid[k]), arr, "stream_close"))
-            else:
-                t, ebm, ebv, crit = cubes[k]
-                v = admit(tuple(t.shape), roix.F32, ebm, ebv, crit, outs_c[k])
-                srv.submit(v, 0, t)
-                recs.append((srv.close(v), arr, "cube"))
+            pending.append((e, arr))
+            drain()
+        # the whole trace waits for every admission; a replay cut short leaves
+        # what still waits unserved (its streams never close)
+        t_end = time.perf_counter() + 120.0
+        while pending and max_seconds is None and time.perf_counter() < t_end:
+            time.sleep(0.0005)
+            drain()
+        unserved = len(pending)
         lat = {"slab": [], "stream_close": [], "cube": []}
         last = 0.0
         for rid, arr, kind in recs:
-            res = srv.wait(rid)
-            if res is None or res.status != 0:
-                log(f"request {rid} failed")
-                sys.exit(1)
-            # server clock starts at its creation, t_base right after: offset < 1 ms
-            lat[kind].append(res.done_ms - arr)
-            last = max(last, res.done_ms)
+            r = srv.wait(rid)
+            if r is None or r.status != 0:
+                raise RuntimeError(f"served request {rid} failed")
+            lat[kind].append(r.done_ms - arr)
+            last = max(last, r.done_ms)
+        for key, v in vid.items():  # a replay cut short leaves streams open
+            if key not in closed:
+                srv.abort(v)
         st = srv.stats()
         srv.close_server()
         torch.cuda.synchronize()
-        bad = [(i, o.collect()["einfo"].status) for i, o in enumerate(outs_s + outs_c)]
-        bad = [b for b in bad if b[1] != 0]
-        if bad:
-            log(f"volumes (index, status) with a non-zero status: {bad}")
-            sys.exit(1)
+        span = max(last - float(ev[0][1]), 1e-3)
+        moved = len(lat["slab"]) * slab_bytes + sum(cube_pool[e[1] % len(cube_pool)][0].numel() * 4
+                                                    for e, _ in ev if e[0] == "c")
         q = lambda v, p: round(float(np.percentile(v, p)), 3) if v else None
-        return {"rate_per_s": rate, "requests": len(recs), "slab_p50_ms": q(lat["slab"], 50),
-                "slab_p99_ms": q(lat["slab"], 99), "stream_close_p50_ms": q(lat["stream_close"], 50),
+        return {"rate_per_s": rate, "requests": len(recs), "slab_requests": len(lat["slab"]), "unserved": unserved,
+                "trace_seconds": round(float(ev[-1][1]) * 1e-3, 1),
+                "slab_p50_ms": q(lat["slab"], 50), "slab_p99_ms": q(lat["slab"], 99),
+                "slab_max_ms": q(lat["slab"], 100), "stream_close_p50_ms": q(lat["stream_close"], 50),
                 "cube_p50_ms": q(lat["cube"], 50), "cube_p99_ms": q(lat["cube"], 99),
-                "makespan_ms": round(last - float(arrivals[0]), 1),
-                "gbs": round(total / ((last - float(arrivals[0])) * 1e-3) / 1e9, 2),
-                "refused_opens": int(st.volumes_refused), "admission_wait_ms": round(busy_ms, 1)}
+                "GBps": round(moved / (span * 1e-3) / 1e9, 2), "refused_opens": int(st.volumes_refused)}
 
     rates = [float(r) for r in args.served_rates.split(",") if r]
     res = {}
-    for rate in rates:
-        r = replay(rate)
-        log(f"rate {rate}/s: slab p50 {r['slab_p50_ms']} ms p99 {r['slab_p99_ms']} ms, cube p50 "
-            f"{r['cube_p50_ms']} ms, {r['gbs']} GB/s over {r['makespan_ms']} ms")
+    parity, host_plain_s = None, 0.0
+    for i, rate in enumerate(rates):
+        r = replay(rate, None if i == 0 else args.served_seconds)
+        log(f"served rate {rate}/s: {r['slab_requests']} slabs, p50 {r['slab_p50_ms']} ms p99 {r['slab_p99_ms']} ms, "
+            f"cube p50 {r['cube_p50_ms']} ms, {r['GBps']} GB/s")
         res[str(rate)] = r
-    cap = replay(0.0)  # closed loop: all requests at once
-    log(f"closed loop: {cap['gbs']} GB/s, slab p99 {cap['slab_p99_ms']} ms")
-    # host-resident plain comparator: pinned H2D + fused call per volume, sequentially
-    vols = [(t, "abs", eb_s, crit_s, o) for t, o in zip(streams, outs_s)] + \
-           [(c[0], c[1], c[2], c[3], o) for c, o in zip(cubes, outs_c)]
-    need = max(roix.scratch_bytes(roix.dims_of(v[0]), roix.dtype_of(v[0]), v[3]) for v in vols)
-    pctx = roix.Context(0, need)
-    stream = torch.cuda.current_stream()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for (h, ebm, ebv, crit, out) in vols:
-        d = h.to(dev, non_blocking=True)
-        pctx.fused(d, ebm, ebv, crit, out, stream)
-        del d
-    torch.cuda.synchronize()
-    host_plain = total / (time.perf_counter() - t) / 1e9
-    log(f"host-resident plain: {host_plain:.2f} GB/s")
-    main_rate = res[str(rates[0])] if rates else cap
-    line = {
-        "metric": METRIC, "value": cap["gbs"], "unit": "GB/s", "n_gpus": 1, "steps": 1, "warmup": 0,
-        "ms_per_step": cap["makespan_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u16+f32", "data": "synthetic",
-        "config": {"workload": f"served: {len(streams)} u16 streams 2048x2048x{args.served_nz} in {SLAB}-plane "
-                               f"slabs (ABS eb, FIXED 6400, 26-conn, largest) + {len(cubes)} f32 cubes "
-                               f"U{{128..512}} (Otsu), HBM budget {args.served_budget_gib:g} GiB",
-                   "input_bytes": total},
-        "served": {"rates": res, "closed_loop": cap, "host_resident_plain_gbs": round(host_plain, 2),
-                   "p99_slab_ms_at_first_rate": main_rate["slab_p99_ms"]},
-    }
-    print(json.dumps(line))
-    pctx.close()
+        if i == 0:  # every volume of the whole trace against its plain call
+            pctx = roix.Context(0, 12 << 30)
+            ok, bad, host_plain_s = True, [], 0.0
+            for k in range(n_streams):
+                # also the host-resident plain comparator: pinned H2D of the
+                # stream, then one plain call
+                ref = roix.Outputs(dev, *s_caps)
+                torch.cuda.synchronize()
+                th = time.perf_counter()
+                vol = torch.cat([slab_of(k, j).to(dev, non_blocking=True) for j in range(nslab)])
+                pctx.fused(vol, "abs", eb_s, crit_s, ref)
+                torch.cuda.synchronize()
+                host_plain_s += time.perf_counter() - th
+                a, b = device_sections(outs_s[k]), device_sections(ref)
+                if b["status"] != (0, 0, 0):
+                    bad.append(("stream", k, b["status"]))
+                ok = ok and sections_equal(a, b)
+                del vol, ref
+            crefs = {}
+            for i2 in range(n_cubes):
+                c = cube_pool[i2 % len(cube_pool)]
+                if i2 % len(cube_pool) not in crefs:
+                    ref = roix.Outputs(dev, *outs_c[i2].caps)
+                    pctx.fused(c[0].to(dev), c[1], c[2], c[3], ref)
+                    torch.cuda.synchronize()
+                    crefs[i2 % len(cube_pool)] = device_sections(ref)
+                a, b = device_sections(outs_c[i2]), crefs[i2 % len(cube_pool)]
+                if b["status"] != (0, 0, 0):
+                    bad.append(("cube", i2, b["status"]))
+                ok = ok and sections_equal(a, b)
+            parity = "equal to plain calls on the assembled volumes" if ok and not bad else {"equal": ok, "bad": bad}
+            log(f"served parity: {parity}")
+            del crefs
+            pctx.close()
+            torch.cuda.empty_cache()
+    cap = replay(0.0, None)  # closed loop: every request at once
+    log(f"served closed loop: {cap['GBps']} GB/s, slab p99 {cap['slab_p99_ms']} ms")
+    out = {"workload": f"{n_streams} u16 streams 2048x2048x{nz} in {SLAB}-plane slabs (ABS eb {eb_s:.4g}, FIXED 6400, "
+                       f"26-conn, largest) + {n_cubes} f32 cubes U{{128..512}} (Otsu), HBM budget "
+                       f"{args.served_budget_gib:g} GiB",
+           "input_bytes": int(total), "rates": res, "closed_loop": cap, "parity": parity,
+           "host_resident_plain_GBps": round(n_streams * Nst * 2 / max(host_plain_s, 1e-9) / 1e9, 2)}
     ctx.close()
+    del pool, cube_pool, outs_s, outs_c
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -713,11 +917,21 @@ def main():
                     help="plain and batched workloads: tune the launch parameters on the volume(s) before timing")
     ap.add_argument("--thr", choices=["otsu", "multi3", "multi4", "otsu_slice"], default=None,
                     help="plain workload: threshold mode instead of the workload's two-class Otsu")
-    ap.add_argument("--served-streams", type=int, default=4, help="uint16 2048x2048 streams of the served trace")
-    ap.add_argument("--served-nz", type=int, default=256, help="planes per served stream (slabs of 32)")
-    ap.add_argument("--served-cubes", type=int, default=16, help="float32 cubes interleaved in the served trace")
-    ap.add_argument("--served-rates", default="20,10", help="Poisson arrival rates (requests/s) to replay")
+    ap.add_argument("--two-pass", action="store_true",
+                    help="plain workload: force the two-pass flow (range, then quantise + 1-byte bin proxy)")
+    ap.add_argument("--sections", default="c0,c2,batched,served",
+                    help="plain workload: the other configurations reported in the same line "
+                         "(comma list of c0, c2, batched, served; 'none' for the headline alone)")
+    ap.add_argument("--served-streams", type=int, default=8, help="uint16 2048x2048 streams of the served trace")
+    ap.add_argument("--served-nz", type=int, default=1024, help="planes per served stream (slabs of 32)")
+    ap.add_argument("--served-cubes", type=int, default=64, help="float32 cubes interleaved in the served trace")
+    ap.add_argument("--served-rates", default="20,10,5,1",
+                    help="Poisson arrival rates (requests/s); the first replays the whole trace and is checked "
+                         "against plain calls")
+    ap.add_argument("--served-seconds", type=float, default=30.0,
+                    help="trace seconds replayed at every rate after the first")
     ap.add_argument("--served-budget-gib", type=float, default=64.0)
+    ap.add_argument("--batch-steps", type=int, default=10, help="timed repeats of the batch and of the plain calls")
     ap.add_argument("--batch-volumes", type=int, default=64)
     ap.add_argument("--batch-streams", type=int, default=4, help="concurrent streams of the batched path")
     ap.add_argument("--batch-graph", type=int, default=1, choices=[0, 1],
@@ -726,10 +940,10 @@ def main():
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary)
         return
-    if args.workload == "batched":
-        return bench_batched(args)
-    if args.workload == "served":
-        return bench_served(args)
+    if args.workload in ("batched", "served"):
+        r = section_batched(args) if args.workload == "batched" else section_served(args)
+        print(json.dumps({"metric": METRIC, "workload": args.workload, args.workload: r}))
+        return
     if args.workload == "background":
         return bench_background(args)
     if args.workload == "absq":
@@ -767,6 +981,8 @@ def main():
     out = roix.Outputs(dev, b["rows"], b["stream_bytes"], b["outliers"], 1 << 22,
                        nz_slices=nz if crit.thr == "otsu_slice" else 0)
     stream = torch.cuda.current_stream()
+    if args.two_pass:
+        ctx.set_param("fused16_min_voxels", 1 << 40)
 
     def step():
         ctx.fused(x, w.eb_mode, w.eb_value, crit, out, stream)
@@ -906,8 +1122,21 @@ def main():
     }
     if tuning:
         line["autotune"] = tuning
-    print(json.dumps(line))
+    line["config"]["reduction"] = round(N / max(int(e.n_codes), 1), 3)  # spatial reduction N / codes
+    line["parity"] = golden_parity("cylinder1024", res) if args.n == 1024 else None
+    del x, out
     ctx.close()
+    torch.cuda.empty_cache()
+    w.volume = vol = None
+    sections = [t for t in args.sections.split(",") if t and t != "none"]
+    for name in sections:
+        fn = {"c0": section_c0, "c2": section_c2, "batched": section_batched, "served": section_served}[name]
+        try:
+            line[name] = fn(args)
+        except Exception as ex:  # a failing section is reported, the headline still printed
+            log(f"section {name} failed: {ex!r}")
+            line[name] = {"error": repr(ex)}
+    print(json.dumps(line))
 
 
 if __name__ == "__main__":

@@ -2,10 +2,11 @@
 info fields) by running the CPU oracle.  Calls only ``synth`` (inputs) and
 ``oracle``; nothing here touches the GPU library.
 
-    python tests/golden/make_digests.py [cylinder1024] [rings2048]
+    python tests/golden/make_digests.py [ellipsoids128] [cylinder1024] [rings2048]
 
-cylinder1024 (1024^3 f32) takes about two minutes and 10 GB of host memory;
-rings2048 (2048 x 2048 x 1024 u16) about ten minutes and 30 GB.
+ellipsoids128 (128^3 f32) takes a second; cylinder1024 (1024^3 f32) about two
+minutes and 10 GB of host memory; rings2048 (2048 x 2048 x 1024 u16) about ten
+minutes and 30 GB.
 """
 import hashlib
 import json
@@ -54,7 +55,7 @@ def digest(name, w):
 
 
 def main():
-    which = sys.argv[1:] or ["cylinder1024", "rings2048"]
+    which = sys.argv[1:] or ["ellipsoids128", "cylinder1024", "rings2048"]
     out = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for name in which:
         w = getattr(synth, name)()

@@ -105,3 +105,33 @@ def digest(g):
     for k in ("rows", "stream", "outliers", "comps"):
         h[k] = hashlib.sha256(np.ascontiguousarray(g[k]).tobytes()).hexdigest()
     return h
+
+
+def device_sections(out):
+    """The info structs (host bytes) and the output sections trimmed to their
+    counts, left on the device (for large comparisons without host copies)."""
+    import torch
+
+    from paper_2602_15917_amd import roix
+    q = bytes(out.qinfo.cpu().numpy().tobytes())
+    s = bytes(out.sinfo.cpu().numpy().tobytes())
+    e = bytes(out.einfo.cpu().numpy().tobytes())
+    ei = roix.ExtractInfo.from_buffer_copy(e)
+    si = roix.SegInfo.from_buffer_copy(s)
+    rows_cap, stream_cap, outl_cap, comps_cap = out.caps
+    nr = min(int(ei.n_rows), rows_cap)
+    nb = min(int(ei.stream_bytes), stream_cap)
+    no = min(int(ei.n_outliers), outl_cap)
+    nc = min(int(si.n_components), comps_cap)
+    return {"qinfo": q, "sinfo": s, "einfo": e, "status": (int(ei.status), int(si.status)),
+            "rows": out.rows[: nr * roix.ROW_BYTES], "stream": out.stream[:nb],
+            "outliers": out.outliers[:no].view(torch.int32), "comps": out.comps[: nc * roix.COMP_BYTES]}
+
+
+def assert_sections_equal(a, b, what=""):
+    """Byte equality of two device_sections() results."""
+    import torch
+    for k in ("qinfo", "sinfo", "einfo"):
+        assert a[k] == b[k], (what, k)
+    for k in ("rows", "stream", "outliers", "comps"):
+        assert a[k].numel() == b[k].numel() and torch.equal(a[k], b[k]), (what, k)

@@ -228,6 +228,20 @@ def test_fused_background_equals_subtract_then_path(env, small_fused):
     g, o = fused_bg_case(c2, roix, torch, (big + bplane).astype(np.float32), bplane, "abs", 0.01,
                          synth.Criterion("otsu", 0.0, 26, "largest", 1), "wide code range")
     assert o["params"].K > (1 << 15)
+    # outliers on the one-pass flow: K <= 2^15 keeps the 16-bit proxy, whose
+    # flag bits find the outliers, whose values are gathered as I - B; rows of
+    # whole 64-voxel words, and 4096-voxel rows so that a span needs several
+    # rounds of loads
+    for shape, seed in (((4, 16, 256), 916), ((2, 5, 4096), 917)):
+        m = (1000.0 + 50.0 * np.random.default_rng(seed).random(shape)).astype(np.float32)
+        oplane = background_field(shape, seed + 10) * 100.0
+        img_o = (m + oplane).astype(np.float32)
+        st_o, m_o = oracle.background(img_o, oplane)
+        o_chk = oracle_fused(m_o, "abs", 0.03, synth.Criterion("otsu", 0.0, 26, "largest", 1))
+        assert o_chk["params"].K <= (1 << 15) and o_chk["info"].n_outliers > 0, (o_chk["params"].K,
+                                                                                  o_chk["info"].n_outliers)
+        fused_bg_case(c2, roix, torch, img_o, oplane, "abs", 0.03, synth.Criterion("otsu", 0.0, 26, "largest", 1),
+                      f"outliers on the one-pass flow {shape}")
     # many short spans: the proxy emit queues chunks for the general kernel, which reads M
     noise = synth.normal((11, 200, 64), 912, 0.5, 0.1)
     nplane = background_field(noise.shape, 913)

@@ -1,11 +1,15 @@
-"""Batched form: many volumes of uneven size in one graph launch must give
-exactly the outputs of separate plain calls -- on every replay of the
-captured graph, with eager work in between, for every launch parameter."""
+"""Batched form: many volumes of uneven size in one call must give exactly
+the outputs of separate plain calls -- on every repeat, with eager work in
+between, for every launch parameter, under both quantiser flows (the default
+one, where volumes of at least 2^22 voxels with rows of a multiple of 4 take
+the one-pass 16-bit-proxy flow, and the one-pass flow forced on every float32
+volume with an absolute bound), and for the full 64-volume batch workload
+(sides 64..512 per axis, eb from {1e-3, 1e-4, 1e-5})."""
 import numpy as np
 import pytest
 
 import synth
-from roixtest import criterion, default_caps, log
+from roixtest import assert_sections_equal, criterion, default_caps, device_sections, log
 
 pytestmark = pytest.mark.gpu
 
@@ -17,16 +21,33 @@ def _outputs_equal(a, b):
         assert bytes(a[k]) == bytes(b[k]), k
 
 
-@pytest.fixture(scope="module")
-def batch_env():
-    import torch
-
-    from paper_2602_15917_amd import roix
+def _volumes():
     vols = [synth.batch_volume(j, side=(24, 96)) for j in range(12)]
     # a uint16 and a cylinder volume make the batch mixed in dtype and criterion
     vols.append(synth.rings2048(nxy=96, nz=9))
     vols.append(synth.cylinder1024(n=80))
-    ctx = roix.Context(0, 1 << 30)
+    # volumes of at least 2^22 voxels with rows of a multiple of 4: the
+    # default flow takes the one-pass form on them (16-bit proxy with K <=
+    # 2^15, and its 1-byte fallback with K > 2^15), with outliers
+    big, _ = synth.ellipsoids(256, 96, 192, 2901, n_ell=5)
+    vols.append(synth.Workload("256x96x192 f32 ellipsoids eb 1e-4", big, "abs", 1e-4,
+                               synth.Criterion("otsu", 0.0, 6, "min_size", 64), None))
+    wide, _ = synth.ellipsoids(192, 160, 144, 2902, n_ell=3)
+    vols.append(synth.Workload("192x160x144 f32 ellipsoids eb 1e-5", wide, "abs", 1e-5,
+                               synth.Criterion("otsu", 0.0, 26, "largest", 1), None))
+    vols.append(synth.cylinder1024(n=176))
+    return vols
+
+
+@pytest.fixture(scope="module", params=["default", "onepass"])
+def batch_env(request):
+    import torch
+
+    from paper_2602_15917_amd import roix
+    vols = _volumes()
+    ctx = roix.Context(0, 3 << 30)
+    if request.param == "onepass":
+        ctx.set_param("fused16_min_voxels", 0)
     items, plain = [], []
     for w in vols:
         crit = criterion(roix, w.criterion)
@@ -39,26 +60,44 @@ def batch_env():
         plain.append(ref)
     torch.cuda.synchronize()
     plain = [r.collect() for r in plain]
+    # the batch covers what it is meant to: outliers in one-pass-sized volumes
+    big = [i for i, w in enumerate(vols) if w.volume.size >= (1 << 22)]
+    assert len(big) == 3 and all(vols[i].volume.shape[2] % 4 == 0 for i in big)
+    assert sum(int(plain[i]["einfo"].n_outliers) for i in big) > 0
     yield ctx, roix, torch, items, plain
     ctx.close()
 
 
-def test_batch_graph_replays_equal_plain(batch_env):
+def test_batch_repeats_equal_plain(batch_env):
     ctx, roix, torch, items, plain = batch_env
     for rep in range(4):
-        log(f"[case] batch graph replay {rep}")
-        for it in items:  # clear the outputs so that every replay must rewrite them
+        log(f"[case] batch repeat {rep}")
+        for it in items:  # clear the outputs so that every repeat must rewrite them
             it[4].stream.zero_()
             it[4].rows.zero_()
         ctx.fused_batch(items)
         torch.cuda.synchronize()
         for i, it in enumerate(items):
             _outputs_equal(it[4].collect(), plain[i])
-        # eager work between replays
+        # eager work between repeats
         t = items[0][0]
         ctx.fused(t, items[0][1], items[0][2], items[0][3], roix.Outputs("cuda:0", *default_caps(
             roix, t.cpu().numpy(), items[0][3])))
         torch.cuda.synchronize()
+
+
+def test_batch_subsets_and_order(batch_env):
+    # a batch of other volumes, in another order, then the first again
+    ctx, roix, torch, items, plain = batch_env
+    order = [len(items) - 1, 3, 0, len(items) - 3, 7]
+    for sel in (order, list(range(len(items)))):
+        log(f"[case] batch subset {sel}")
+        for i in sel:
+            items[i][4].stream.zero_()
+        ctx.fused_batch([items[i] for i in sel])
+        torch.cuda.synchronize()
+        for i in sel:
+            _outputs_equal(items[i][4].collect(), plain[i])
 
 
 @pytest.mark.parametrize("streams,graph", [(1, 1), (2, 0), (3, 1), (8, 1), (8, 0)])
@@ -83,3 +122,35 @@ def test_batch_rejects_bad_descriptor(batch_env):
     with pytest.raises(roix.RoixError) as ei:
         ctx.fused_batch(bad)
     assert ei.value.status == roix.EINVAL
+
+
+def test_full_batch_workload_equals_plain():
+    """The 64-volume batch workload (5.7 GB of float32 volumes) against 64
+    plain calls, every output section compared on the device."""
+    import torch
+
+    from paper_2602_15917_amd import roix
+    items, need = [], 0
+    for j in range(64):
+        w = synth.batch_volume(j)
+        crit = criterion(roix, w.criterion)
+        t = torch.from_numpy(w.volume).to("cuda:0")
+        dims = roix.dims_of(t)
+        b = roix.bounds(dims, roix.F32, crit)
+        caps = (b["rows"], b["stream_bytes"], min(b["outliers"], 1 << 24), min(b["components"], 1 << 20))
+        items.append((t, w.eb_mode, w.eb_value, crit, roix.Outputs("cuda:0", *caps), roix.Outputs("cuda:0", *caps)))
+        need = max(need, roix.scratch_bytes(dims, roix.F32, crit))
+    ctx = roix.Context(0, need * 4)
+    log(f"[case] 64-volume batch, {sum(it[0].numel() for it in items) * 4 / 1e9:.2f} GB")
+    for (t, ebm, ebv, crit, _, ref) in items:
+        ctx.fused(t, ebm, ebv, crit, ref)
+    ctx.fused_batch([it[:5] for it in items])
+    torch.cuda.synchronize()
+    n_out = 0
+    for j, it in enumerate(items):
+        a, b = device_sections(it[4]), device_sections(it[5])
+        assert a["status"] == (0, 0), (j, a["status"])
+        assert_sections_equal(a, b, f"volume {j}")
+        n_out += int(roix.ExtractInfo.from_buffer_copy(b["einfo"]).n_outliers)
+    assert n_out > 0
+    ctx.close()

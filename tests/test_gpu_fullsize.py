@@ -22,7 +22,7 @@ def sha(a):
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
 
 
-@pytest.mark.parametrize("name", ["cylinder1024", "rings2048"])
+@pytest.mark.parametrize("name", ["ellipsoids128", "cylinder1024", "rings2048"])
 def test_fullsize_digests(name):
     import torch
 
