@@ -31,7 +31,7 @@ def log(msg):
 # counters is only reported while that file is unchanged
 STAGE_SOURCE = {"range": "k_quant.hip", "quant_hist": "k_quant.hip", "quant_range16": "k_quant.hip",
                 "mask_runs": "k_label.hip", "emit": "k_extract.hip"}
-STAGE_KERNEL = {"range": "k_range<float>", "quant_hist": "k_quant_hist<float, false, false, true, true>",
+STAGE_KERNEL = {"range": "k_range<float>", "quant_hist": "k_quant_hist<float, false, false, 1, true>",
                 "quant_range16": "k_quant_range16<false>", "mask_runs": "k_mask_runs", "emit": "k_emit_codes_p16"}
 CALIB_BYTES = 1 << 30
 
@@ -613,10 +613,10 @@ def section_batched(args):
         caps = (b["rows"], b["stream_bytes"], min(b["outliers"], 1 << 24), min(b["components"], 1 << 20))
         items.append((t, w.eb_mode, w.eb_value, crit, roix.Outputs(dev, *caps)))
         refs.append(roix.Outputs(dev, *caps))
-        need = max(need, roix.scratch_bytes(dims, roix.F32, crit))
+        need += roix.scratch_bytes(dims, roix.F32, crit)  # every volume's layout at once
     log(f"batched: generated {len(items)} volumes, {total / 1e9:.2f} GB, in {time.time() - t0:.1f}s")
-    ctx = roix.Context(0, need * args.batch_streams)
-    ctx.set_param("batch_streams", args.batch_streams)
+    ctx = roix.Context(0, need + (64 << 20))
+    ctx.set_param("batch_group", args.batch_group)
     ctx.set_param("batch_graph", args.batch_graph)
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -933,7 +933,8 @@ def main():
     ap.add_argument("--served-budget-gib", type=float, default=64.0)
     ap.add_argument("--batch-steps", type=int, default=10, help="timed repeats of the batch and of the plain calls")
     ap.add_argument("--batch-volumes", type=int, default=64)
-    ap.add_argument("--batch-streams", type=int, default=4, help="concurrent streams of the batched path")
+    ap.add_argument("--batch-group", type=int, default=0,
+                    help="volumes per launch group of the batched path (0: as many as the arena holds)")
     ap.add_argument("--batch-graph", type=int, default=1, choices=[0, 1],
                     help="1: capture the batch into a HIP graph and replay it; 0: launch eagerly")
     args = ap.parse_args()

@@ -470,14 +470,20 @@ typedef struct {
 } roix_volume_desc;
 
 /* Batched form: every volume of `vols` through the fused path, with output
- * identical to n separate roix_fused calls.  The volumes run concurrently on
- * batch_streams internal streams (largest first, each to the least-loaded
- * stream), each stream with its own equal share of the scratch arena; the
- * whole fork/join launch sequence is captured into a HIP graph, which is
- * replayed while the descriptors and launch parameters stay the same.
- * Asynchronous on `stream`.  Errors: ROIX_EINVAL (NULL ctx/vols, any invalid
- * descriptor), ROIX_ENOMEM (a volume does not fit one stream's share of the
- * arena even with one stream), ROIX_EDEVICE. */
+ * identical to n separate roix_fused calls, in one launch per stage for all
+ * the volumes.  Each volume's launch sequence is that of roix_fused on its
+ * own part of the arena (the voxel-proportional passes on its share of the
+ * grid); the sequences are merged so that each kernel runs once for every
+ * volume that needs it next, each workgroup finding its volume in a device
+ * table of arguments.  Volumes whose worst-case layouts do not all fit the
+ * arena at once run in consecutive groups.  The launch sequence is captured
+ * into a HIP graph (batch_graph) and replayed while the batch's structure --
+ * volume shapes, flows, grids -- is the same; buffer addresses may change
+ * from call to call.  Asynchronous on `stream`; the argument tables are
+ * copied from pinned host memory the context keeps (allocated, or grown, on
+ * the first batch that needs it).  Errors: ROIX_EINVAL (NULL ctx/vols, any
+ * invalid descriptor), ROIX_ENOMEM (a volume does not fit the arena even
+ * alone), ROIX_EDEVICE. */
 roix_status roix_fused_batch(roix_ctx* ctx, int32_t n, const roix_volume_desc* vols, void* stream);
 
 /* Launch parameters of a context (the autotuner's knobs):
@@ -490,8 +496,12 @@ roix_status roix_fused_batch(roix_ctx* ctx, int32_t n, const roix_volume_desc* v
  *   "seg_runs"       runs labelled together in one workgroup's local memory
  *                    (a multiple of 256 up to 16384; 0 = spread the runs over
  *                    seg_grid workgroups, at least 2048 each)
- *   "batch_streams"  concurrent streams of roix_fused_batch (1..64)
+ *   "batch_group"    volumes per launch group of roix_fused_batch (0 = as
+ *                    many as the arena holds; 1 = one volume at a time)
  *   "batch_graph"    1 = capture/replay batches as a HIP graph, 0 = launch eagerly
+ *   "batch_fused16_min_voxels"  as fused16_min_voxels, for the volumes of a
+ *                    batch (default 2^26: below it the one-pass flow's
+ *                    per-workgroup class tables outweigh its saved read)
  *   "fused16_min_voxels"  smallest float32 volume (voxels) that the fused path
  *                    quantises in one pass with the range, writing a 16-bit
  *                    code proxy, when the bound is absolute, rows hold a

@@ -232,14 +232,6 @@ hipError_t roix::spans_and_emit(const LaunchCtx& lc, const Geom& g, const Layout
     return launch_emit(lc, g, L, in, dt, out, bg);
 }
 
-static void batch_release(BatchState& b) {
-    if (b.exec) hipGraphExecDestroy(b.exec);
-    if (b.graph) hipGraphDestroy(b.graph);
-    b.exec = nullptr;
-    b.graph = nullptr;
-    b.key.clear();
-}
-
 // the launch sequence of the fused path on an already carved layout
 roix_status roix::enqueue_fused(const LaunchCtx& lc, const Geom& g, Layout L, const void* d_in, roix_dtype dtype,
                                  roix_eb eb, const roix_criterion* crit, const roix_fused_out* out) {
@@ -414,13 +406,7 @@ roix_status roix_ctx_destroy(roix_ctx* ctx) {
         hipEventDestroy(p.b);
     }
     for (auto e : ctx->timer.pool) hipEventDestroy(e);
-    batch_release(ctx->batch);
-    for (auto st : ctx->batch.streams) hipStreamDestroy(st);
-    for (auto ev : ctx->batch.joins) hipEventDestroy(ev);
-    if (ctx->batch.fork) hipEventDestroy(ctx->batch.fork);
-    if (ctx->batch.ev_in) hipEventDestroy(ctx->batch.ev_in);
-    if (ctx->batch.ev_out) hipEventDestroy(ctx->batch.ev_out);
-    if (ctx->batch.origin) hipStreamDestroy(ctx->batch.origin);
+    batch_destroy(ctx->batch);
     hipFree(ctx->arena);
     hipSetDevice(prev);
     delete ctx;
@@ -644,7 +630,9 @@ roix_status roix_ctx_set_param(roix_ctx* ctx, const char* name, int64_t value) {
     else if (strcmp(name, "stats_grid") == 0 && pos) ctx->stats_grid = (int)value;
     else if (strcmp(name, "seg_runs") == 0 && value >= 0 && value <= 16384 && value % 256 == 0)
         ctx->seg_runs = (int)value;
-    else if (strcmp(name, "batch_streams") == 0 && value >= 1 && value <= 64) ctx->batch_streams = (int)value;
+    else if (strcmp(name, "batch_group") == 0 && value >= 0 && value <= (1 << 20)) ctx->batch_group = (int)value;
+    else if (strcmp(name, "batch_fused16_min_voxels") == 0 && value >= 0 && value <= (1ll << 40))
+        ctx->batch_p16_min = (uint64_t)value;
     else if (strcmp(name, "batch_graph") == 0 && (value == 0 || value == 1)) ctx->batch_graph = (int)value;
     else if (strcmp(name, "fused16_min_voxels") == 0 && value >= 0 && value <= (1ll << 40))
         ctx->p16_min = (uint64_t)value;
@@ -661,134 +649,12 @@ roix_status roix_ctx_get_param(roix_ctx* ctx, const char* name, int64_t* value) 
     else if (strcmp(name, "seg_grid") == 0) *value = ctx->seg_grid;
     else if (strcmp(name, "stats_grid") == 0) *value = ctx->stats_grid;
     else if (strcmp(name, "seg_runs") == 0) *value = ctx->seg_runs;
-    else if (strcmp(name, "batch_streams") == 0) *value = ctx->batch_streams;
+    else if (strcmp(name, "batch_group") == 0) *value = ctx->batch_group;
+    else if (strcmp(name, "batch_fused16_min_voxels") == 0) *value = (int64_t)ctx->batch_p16_min;
     else if (strcmp(name, "batch_graph") == 0) *value = ctx->batch_graph;
     else if (strcmp(name, "compute_units") == 0) *value = ctx->cus;
     else if (strcmp(name, "fused16_min_voxels") == 0) *value = (int64_t)ctx->p16_min;
     else return ROIX_EINVAL;
-    return ROIX_OK;
-}
-
-static roix_status batch_streams_ready(roix_ctx* c, int S) {
-    BatchState& b = c->batch;
-    if (!b.fork && hipEventCreateWithFlags(&b.fork, hipEventDisableTiming) != hipSuccess) return ROIX_EDEVICE;
-    if (!b.ev_in && hipEventCreateWithFlags(&b.ev_in, hipEventDisableTiming) != hipSuccess) return ROIX_EDEVICE;
-    if (!b.ev_out && hipEventCreateWithFlags(&b.ev_out, hipEventDisableTiming) != hipSuccess) return ROIX_EDEVICE;
-    if (!b.origin && hipStreamCreateWithFlags(&b.origin, hipStreamNonBlocking) != hipSuccess) return ROIX_EDEVICE;
-    while ((int)b.streams.size() < S) {
-        hipStream_t st;
-        hipEvent_t ev;
-        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return ROIX_EDEVICE;
-        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return ROIX_EDEVICE;
-        b.streams.push_back(st);
-        b.joins.push_back(ev);
-    }
-    return ROIX_OK;
-}
-
-// Enqueue the whole batch: volumes spread over S slots (largest first, each
-// to the least-loaded slot), each slot a stream of its own with a private
-// part of the arena, forked from and joined back into the caller's stream.
-static roix_status batch_enqueue(roix_ctx* c, int32_t n, const roix_volume_desc* v, const std::vector<Geom>& gs,
-                                 int S, size_t slot_bytes, hipStream_t stream) {
-    BatchState& b = c->batch;
-    std::vector<int> order(n);
-    for (int i = 0; i < n; ++i) order[i] = i;
-    std::sort(order.begin(), order.end(), [&](int a, int d) { return gs[a].N > gs[d].N; });
-    std::vector<uint64_t> load(S, 0);
-    std::vector<std::vector<int>> slot(S);
-    for (int i : order) {
-        int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        slot[k].push_back(i);
-        load[k] += gs[i].N;
-    }
-    ROIX_TRY(hipEventRecord(b.fork, stream));
-    for (int k = 0; k < S; ++k) {
-        ROIX_TRY(hipStreamWaitEvent(b.streams[k], b.fork, 0));
-        void* base = (uint8_t*)c->arena + (size_t)k * slot_bytes;
-        LaunchCtx lc = lctx(c, b.streams[k]);
-        lc.timer = nullptr;
-        for (int i : slot[k]) {
-            Layout L;
-            const roix_dtype dt = (roix_dtype)v[i].dtype;
-            if (!carve_at(base, slot_bytes, gs[i], &L, proxy_kind_for(gs[i], dt, slot_bytes, c->p16_min)))
-                return ROIX_ENOMEM;
-            roix_status st = enqueue_fused(lc, gs[i], L, v[i].d_in, (roix_dtype)v[i].dtype, v[i].eb, &v[i].crit, &v[i].out);
-            if (st != ROIX_OK) return st;
-        }
-        ROIX_TRY(hipEventRecord(b.joins[k], b.streams[k]));
-        ROIX_TRY(hipStreamWaitEvent(stream, b.joins[k], 0));
-    }
-    return ROIX_OK;
-}
-
-roix_status roix_fused_batch(roix_ctx* ctx, int32_t n, const roix_volume_desc* vols, void* stream_) {
-    if (!ctx || n < 0 || (n > 0 && !vols)) return ROIX_EINVAL;
-    if (n == 0) return ROIX_OK;
-    std::vector<Geom> gs(n);
-    size_t need = 0;
-    for (int i = 0; i < n; ++i) {
-        const roix_volume_desc& d = vols[i];
-        if (!d.d_in || !geom_of(d.dims, &gs[i]) || !eb_ok(d.eb) || !crit_ok(&d.crit) || !out_ok(&d.out, true))
-            return ROIX_EINVAL;
-        if (d.dtype != ROIX_F32 && d.dtype != ROIX_U16) return ROIX_EINVAL;
-        if (!aligned(d.d_in, d.dtype == ROIX_F32 ? 4 : 2)) return ROIX_EINVAL;
-        need = std::max(need, fixed_bytes(gs[i]) + kRunBytes);
-    }
-    int S = std::min<int>(ctx->batch_streams, n);
-    size_t slot_bytes = (ctx->arena_bytes / (size_t)S) & ~(size_t)255;
-    while (S > 1 && slot_bytes < need) {
-        --S;
-        slot_bytes = (ctx->arena_bytes / (size_t)S) & ~(size_t)255;
-    }
-    if (slot_bytes < need) return ROIX_ENOMEM;
-    if (batch_streams_ready(ctx, S) != ROIX_OK) return ROIX_EDEVICE;
-    hipStream_t stream = (hipStream_t)stream_;
-    if (!ctx->batch_graph) return batch_enqueue(ctx, n, vols, gs, S, slot_bytes, stream);
-    // the graph is specific to the descriptors (buffer addresses are baked
-    // into its kernel arguments): reuse it while they are the same
-    const int64_t params[10] = {S,
-                                ctx->grid_stream,
-                                ctx->grid_read,
-                                ctx->grid_emit,
-                                ctx->grid_mask,
-                                ctx->seg_grid,
-                                ctx->seg_runs,
-                                ctx->stats_grid,
-                                (int64_t)slot_bytes,
-                                (int64_t)ctx->p16_min};
-    std::vector<uint8_t> key(sizeof(roix_volume_desc) * (size_t)n + sizeof params);
-    memcpy(key.data(), vols, sizeof(roix_volume_desc) * (size_t)n);
-    memcpy(key.data() + sizeof(roix_volume_desc) * (size_t)n, params, sizeof params);
-    BatchState& b = ctx->batch;
-    if (!b.exec || b.key != key) {
-        // capture on the context's own stream (the caller's may be the legacy
-        // default stream, which cannot be captured)
-        batch_release(b);
-        ROIX_TRY(hipStreamBeginCapture(b.origin, hipStreamCaptureModeThreadLocal));
-        roix_status st = batch_enqueue(ctx, n, vols, gs, S, slot_bytes, b.origin);
-        hipGraph_t graph = nullptr;
-        hipError_t e = hipStreamEndCapture(b.origin, &graph);
-        (void)hipGetLastError();
-        if (st != ROIX_OK) {
-            if (graph) hipGraphDestroy(graph);
-            return st;
-        }
-        if (e != hipSuccess || !graph) return ROIX_EDEVICE;
-        hipGraphExec_t exec = nullptr;
-        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-            hipGraphDestroy(graph);
-            return ROIX_EDEVICE;
-        }
-        b.graph = graph;
-        b.exec = exec;
-        b.key = key;
-    }
-    ROIX_TRY(hipEventRecord(b.ev_in, stream));
-    ROIX_TRY(hipStreamWaitEvent(b.origin, b.ev_in, 0));
-    ROIX_TRY(hipGraphLaunch(b.exec, b.origin));
-    ROIX_TRY(hipEventRecord(b.ev_out, b.origin));
-    ROIX_TRY(hipStreamWaitEvent(stream, b.ev_out, 0));
     return ROIX_OK;
 }
 

@@ -4,6 +4,10 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
+
+#include <utility>
+#include <vector>
 
 #include "../../include/roix.h"
 
@@ -260,6 +264,110 @@ struct Timer;  // defined in api.hip
 void timer_begin(Timer* t, int stage, hipStream_t s);
 void timer_end(Timer* t, int stage, hipStream_t s);
 
+// ------------------------------------------------- one launch, many volumes
+//
+// Every kernel of the fused path is a body run on a virtual grid: VPart.b is
+// the workgroup's index among the VPart.n workgroups that work on one
+// volume.  A plain launch gives the body the hardware grid.  A batch records
+// each volume's launches (body, grid, arguments) instead of launching them,
+// then launches each body once for all the volumes that need it next: the
+// arguments of every volume in a device table, and the workgroups split by
+// a prefix table of the volumes' grids (a workgroup finds its volume by
+// binary search).  Each volume sees exactly the grid and arguments of its
+// plain launch, and its launches keep their order.
+
+struct VPart {
+    uint32_t b, n;
+};
+
+__device__ __forceinline__ VPart hw_part() { return VPart{blockIdx.x, gridDim.x}; }
+
+template <class... A>
+struct ArgPack;
+template <>
+struct ArgPack<> {};
+template <class H, class... T>
+struct ArgPack<H, T...> {
+    H h;
+    ArgPack<T...> t;
+};
+
+inline ArgPack<> make_pack() { return ArgPack<>{}; }
+template <class H, class... T>
+inline ArgPack<H, T...> make_pack(H h, T... t) {
+    return ArgPack<H, T...>{h, make_pack(t...)};
+}
+
+template <size_t I, class H, class... T>
+__host__ __device__ __forceinline__ const auto& pack_get(const ArgPack<H, T...>& p) {
+    if constexpr (I == 0)
+        return p.h;
+    else
+        return pack_get<I - 1>(p.t);
+}
+
+template <auto Body, class... A, size_t... I>
+__device__ __forceinline__ void pack_call(VPart vp, const ArgPack<A...>& p, std::index_sequence<I...>) {
+    Body(vp, pack_get<I>(p)...);
+}
+
+// start[v] = first workgroup of volume v, start[n] = the grid, start[n + 1]
+// = kTableMark: a table that did not arrive intact runs nothing
+constexpr uint32_t kTableMark = 0x5849'4F52u;
+template <int LB, auto Body, class... A>
+__global__ __launch_bounds__(LB) void k_many(const ArgPack<A...>* __restrict__ args,
+                                             const uint32_t* __restrict__ start, uint32_t n) {
+    if (start[n + 1] != kTableMark) return;  // uniform
+    const uint32_t b = blockIdx.x;
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (start[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const uint32_t s0 = start[lo];
+    pack_call<Body>(VPart{b - s0, start[lo + 1] - s0}, args[lo], std::index_sequence_for<A...>{});
+}
+
+using ManyLaunch = void (*)(const void* args, const uint32_t* start, uint32_t n, uint32_t grid, uint32_t block,
+                            uint32_t shmem, hipStream_t s);
+
+template <int LB, auto Body, class... A>
+void many_launch(const void* args, const uint32_t* start, uint32_t n, uint32_t grid, uint32_t block, uint32_t shmem,
+                 hipStream_t s) {
+    hipLaunchKernelGGL((k_many<LB, Body, A...>), dim3(grid), dim3(block), shmem, s,
+                       reinterpret_cast<const ArgPack<A...>*>(args), start, n);
+}
+
+// One recorded launch of one volume.
+struct RecLaunch {
+    ManyLaunch launch;  // also the key: one per (body, block bound, argument types)
+    uint32_t grid, block, shmem;
+    uint32_t arg_size, arg_align;
+    std::vector<uint8_t> args;
+};
+
+struct Recorder {
+    std::vector<RecLaunch> seq;
+    bool bad = false;  // a launch that cannot be recorded (a 2-D grid)
+    template <int LB, auto Body, class... A>
+    void add(dim3 grid, dim3 block, size_t shmem, const ArgPack<A...>& p) {
+        if (grid.y != 1 || grid.z != 1 || block.y != 1 || block.z != 1) bad = true;
+        RecLaunch r;
+        r.launch = &many_launch<LB, Body, A...>;
+        r.grid = grid.x;
+        r.block = block.x;
+        r.shmem = (uint32_t)shmem;
+        r.arg_size = (uint32_t)sizeof(ArgPack<A...>);
+        r.arg_align = (uint32_t)alignof(ArgPack<A...>);
+        r.args.resize(sizeof(ArgPack<A...>));
+        memcpy(r.args.data(), &p, sizeof(ArgPack<A...>));
+        seq.push_back(std::move(r));
+    }
+};
+
 struct LaunchCtx {
     hipStream_t stream;
     Timer* timer;  // may be null
@@ -270,7 +378,19 @@ struct LaunchCtx {
     int seg_grid;     // workgroups of the segment labelling kernels
     int seg_runs;     // runs per segment (0: spread the runs over seg_grid)
     int stats_grid;   // workgroups of the component statistics kernel
+    int scan_grid = kScanBlocks;  // chunks of the device-sized scans (at most kScanBlocks)
+    int grid_vox = 0;             // quantise + histogram pass (0: grid_stream); a batch scales it
+    Recorder* rec = nullptr;      // batch: record the launches instead of making them
 };
+
+// Launch kernel `kern` (whose body is Body, block bound LB), or record it.
+template <int LB, auto Body, class K, class... A>
+inline void launch_k(const LaunchCtx& lc, K kern, dim3 grid, dim3 block, size_t shmem, A... a) {
+    if (lc.rec)
+        lc.rec->add<LB, Body>(grid, block, shmem, make_pack(a...));
+    else
+        hipLaunchKernelGGL(kern, grid, block, shmem, lc.stream, a...);
+}
 
 // ------------------------------------------------------------ launchers
 // Each returns hipSuccess or the launch error.

@@ -34,16 +34,20 @@ struct Timer {
 
 }  // namespace roix
 
+// The batched form's cached graph: the launch sequence of the last batch,
+// keyed by its structure (bodies, grids, table offsets), not by its buffers.
 struct BatchState {
-    std::vector<hipStream_t> streams;
-    std::vector<hipEvent_t> joins;
-    hipEvent_t fork = nullptr;
     hipStream_t origin = nullptr;  // the graph is captured and launched here
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    std::vector<uint8_t> key;  // descriptors + launch parameters of the cached graph
+    std::vector<uint8_t> host;       // the argument tables, built here
+    uint8_t* pinned = nullptr;       // and copied to the device from this pinned buffer
+    size_t pinned_cap = 0;
+    hipEvent_t ev_copy = nullptr;    // that copy has read `pinned`
+    std::vector<uint8_t> key;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
+void batch_destroy(BatchState& b);
 
 struct roix_ctx {
     int device = 0;
@@ -59,7 +63,10 @@ struct roix_ctx {
     int seg_runs = 0;
     int stats_grid = 512;
     uint64_t p16_min = 1ull << 22;  // fused16_min_voxels
-    int batch_streams = 4;
+    int batch_group = 0;  // volumes per launch group of a batch (0: as many as the arena holds)
+    // smallest float32 volume a batch quantises in one pass: below this the
+    // per-workgroup class tables of that pass cost more than a second read
+    uint64_t batch_p16_min = 1ull << 26;
     int batch_graph = 1;
     BatchState batch;
 };

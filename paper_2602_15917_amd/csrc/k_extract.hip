@@ -34,10 +34,10 @@ __device__ __forceinline__ void put_span(const Layout& L, int64_t r, uint32_t xs
 }
 
 // from the runs: first and last run of a kept component
-__global__ __launch_bounds__(kBlock) void k_spans_runs(Layout L, int64_t nrows) {
+__device__ __forceinline__ void k_spans_runs_body(const VPart vp, Layout L, int64_t nrows) {
     const bool dead = thread_exit_e(L.S);
-    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += nthreads) {
+    const int64_t nthreads = (int64_t)vp.n * blockDim.x;
+    for (int64_t r = (int64_t)vp.b * blockDim.x + threadIdx.x; r < nrows; r += nthreads) {
         uint32_t xs = 0, xe = 0;
         bool has = false;
         if (!dead) {
@@ -52,10 +52,13 @@ __global__ __launch_bounds__(kBlock) void k_spans_runs(Layout L, int64_t nrows) 
         put_span(L, r, xs, xe, has);
     }
 }
+__global__ __launch_bounds__(kBlock) void k_spans_runs(Layout L, int64_t nrows) {
+    k_spans_runs_body(hw_part(), L, nrows);
+}
 
 hipError_t launch_spans_from_runs(const LaunchCtx& lc, const Geom& g, const Layout& L) {
     timer_begin(lc.timer, ST_SPANS, lc.stream);
-    hipLaunchKernelGGL(k_spans_runs, dim3(grid_rows(g.nrows, kBlock, 16384)), dim3(kBlock), 0, lc.stream, L, g.nrows);
+    launch_k<kBlock, k_spans_runs_body>(lc, k_spans_runs, dim3(grid_rows(g.nrows, kBlock, 16384)), dim3(kBlock), 0, L, g.nrows);
     timer_end(lc.timer, ST_SPANS, lc.stream);
     return hipGetLastError();
 }
@@ -132,11 +135,11 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t lane) {
 // the ridx-th span, span_desc[ridx] = its first code and voxel offset,
 // chunk_row[q] = ridx of the span holding code q * chunk.  Also clears the
 // per-row outlier counters.
-__global__ __launch_bounds__(kBlock) void k_emit_index(Layout L, int64_t nx, int64_t nrows) {
+__device__ __forceinline__ void k_emit_index_body(const VPart vp, Layout L, int64_t nx, int64_t nrows) {
     if (thread_exit_e(L.S)) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) L.S->n_slow = 0u;
-    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += nthreads) {
+    if (vp.b == 0 && threadIdx.x == 0) L.S->n_slow = 0u;
+    const int64_t nthreads = (int64_t)vp.n * blockDim.x;
+    for (int64_t r = (int64_t)vp.b * blockDim.x + threadIdx.x; r < nrows; r += nthreads) {
         L.row_outl[r] = 0ull;
         const uint32_t xs = L.row_xs[r], xe = L.row_xe[r];
         if (xe <= xs) continue;
@@ -150,6 +153,9 @@ __global__ __launch_bounds__(kBlock) void k_emit_index(Layout L, int64_t nx, int
             make_uint4((uint32_t)code0, (uint32_t)(code0 >> 32), (uint32_t)off, (uint32_t)(off >> 32));
         for (uint64_t q = (code0 + kEmitChunk - 1) / kEmitChunk; q * kEmitChunk < code1; ++q) L.chunk_row[q] = ridx;
     }
+}
+__global__ __launch_bounds__(kBlock) void k_emit_index(Layout L, int64_t nx, int64_t nrows) {
+    k_emit_index_body(hw_part(), L, nx, nrows);
 }
 
 // Four consecutive input values starting at voxel v.  float: one 16-byte
@@ -899,7 +905,7 @@ __device__ __forceinline__ void chunk_of(const Layout& L, uint64_t q, uint64_t n
 // the general kernel, so that its register budget stays that of the lean
 // path.  B = bytes per code.
 template <typename T, int B, bool P16 = false>
-__device__ __forceinline__ void emit_codes_lean(const T* __restrict__ in, int64_t nx, const Layout& L,
+__device__ __forceinline__ void emit_codes_lean(const VPart vp, const T* __restrict__ in, int64_t nx, const Layout& L,
                                                 const EmitOut& o, const uint16_t* __restrict__ px = nullptr) {
     DevState* S = L.S;
     bool trunc = false;
@@ -907,8 +913,8 @@ __device__ __forceinline__ void emit_codes_lean(const T* __restrict__ in, int64_
     const uint32_t n_rows = uni((uint32_t)(S->span_total >> 40));
     const uint64_t nchunks = (n_codes + kEmitChunk - 1) / kEmitChunk;
     const int lane = threadIdx.x % kWave;
-    const uint64_t wave = uni((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
-    const uint64_t nwaves = (uint64_t)gridDim.x * blockDim.x / kWave;
+    const uint64_t wave = uni((vp.b * blockDim.x + threadIdx.x) / kWave);
+    const uint64_t nwaves = (uint64_t)vp.n * blockDim.x / kWave;
     for (uint64_t q = wave; q < nchunks; q += nwaves) {
         uint64_t c0, c1;
         uint32_t j0, j1;
@@ -948,16 +954,16 @@ __device__ __forceinline__ void emit_codes_lean(const T* __restrict__ in, int64_
 // The queued chunks: many short spans (lane windows with a cross-lane
 // search), or few spans whose voxels lie far apart (64-bit offsets).
 template <typename T, int B>
-__device__ __forceinline__ void emit_codes_general(const T* __restrict__ in, int64_t nx, const Layout& L,
-                                                   const EmitOut& o) {
+__device__ __forceinline__ void emit_codes_general(const VPart vp, const T* __restrict__ in, int64_t nx,
+                                                   const Layout& L, const EmitOut& o) {
     DevState* S = L.S;
     bool trunc = false;
     const uint64_t n_codes = uni64(S->span_total & kLenMask);
     const uint32_t n_rows = uni((uint32_t)(S->span_total >> 40));
     const uint64_t nchunks = (n_codes + kEmitChunk - 1) / kEmitChunk;
     const uint32_t nq = uni(S->n_slow);
-    const uint32_t wave = uni((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
-    const uint32_t nwaves = gridDim.x * blockDim.x / kWave;
+    const uint32_t wave = uni((vp.b * blockDim.x + threadIdx.x) / kWave);
+    const uint32_t nwaves = vp.n * blockDim.x / kWave;
     for (uint32_t i = wave; i < nq; i += nwaves) {
         const uint64_t q = uni(L.slow_chunks[i]);
         uint64_t c0, c1;
@@ -975,41 +981,55 @@ __device__ __forceinline__ void emit_codes_general(const T* __restrict__ in, int
 // on it is uniform.  unless_p16: nothing to do when the 16-bit proxy kernel
 // below takes the lean chunks.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_emit_codes(const T* __restrict__ in, int64_t nx, Layout L, EmitOut o,
+__device__ __forceinline__ void k_emit_codes_body(const VPart vp, const T* __restrict__ in, int64_t nx, Layout L, EmitOut o,
                                                        int unless_p16) {
     if (thread_exit_e(L.S)) return;  // no barrier below
     if (unless_p16 && L.S->p16) return;
     const int wb = L.S->width_bits;
     if (wb == 16)
-        emit_codes_lean<T, 2>(in, nx, L, o);
+        emit_codes_lean<T, 2>(vp, in, nx, L, o);
     else if (wb == 8)
-        emit_codes_lean<T, 1>(in, nx, L, o);
+        emit_codes_lean<T, 1>(vp, in, nx, L, o);
     else
-        emit_codes_lean<T, 4>(in, nx, L, o);
+        emit_codes_lean<T, 4>(vp, in, nx, L, o);
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_emit_codes(const T* __restrict__ in, int64_t nx, Layout L, EmitOut o,
+                                                       int unless_p16) {
+    k_emit_codes_body<T>(hw_part(), in, nx, L, o, unless_p16);
 }
 
 // The lean chunks from the 16-bit proxy, when the fused pass produced it
 // (K <= 2^15, so codes are 8 or 16 bits wide).
-__global__ __launch_bounds__(kBlock) void k_emit_codes_p16(const float* __restrict__ in, int64_t nx, Layout L,
+__device__ __forceinline__ void k_emit_codes_p16_body(const VPart vp, const float* __restrict__ in, int64_t nx, Layout L,
                                                            EmitOut o, const uint16_t* __restrict__ px) {
     if (thread_exit_e(L.S) || !L.S->p16) return;  // no barrier below
     if (L.S->width_bits == 16)
-        emit_codes_lean<float, 2, true>(in, nx, L, o, px);
+        emit_codes_lean<float, 2, true>(vp, in, nx, L, o, px);
     else
-        emit_codes_lean<float, 1, true>(in, nx, L, o, px);
+        emit_codes_lean<float, 1, true>(vp, in, nx, L, o, px);
+}
+__global__ __launch_bounds__(kBlock) void k_emit_codes_p16(const float* __restrict__ in, int64_t nx, Layout L,
+                                                           EmitOut o, const uint16_t* __restrict__ px) {
+    k_emit_codes_p16_body(hw_part(), in, nx, L, o, px);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_emit_codes_general(const T* __restrict__ in, int64_t nx, Layout L,
+__device__ __forceinline__ void k_emit_codes_general_body(const VPart vp, const T* __restrict__ in, int64_t nx, Layout L,
                                                                EmitOut o) {
     if (thread_exit_e(L.S)) return;  // no barrier below
     const int wb = L.S->width_bits;
     if (wb == 16)
-        emit_codes_general<T, 2>(in, nx, L, o);
+        emit_codes_general<T, 2>(vp, in, nx, L, o);
     else if (wb == 8)
-        emit_codes_general<T, 1>(in, nx, L, o);
+        emit_codes_general<T, 1>(vp, in, nx, L, o);
     else
-        emit_codes_general<T, 4>(in, nx, L, o);
+        emit_codes_general<T, 4>(vp, in, nx, L, o);
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_emit_codes_general(const T* __restrict__ in, int64_t nx, Layout L,
+                                                               EmitOut o) {
+    k_emit_codes_general_body<T>(hw_part(), in, nx, L, o);
 }
 
 // Outlier values: a span of up to 1024 voxels is one round of 16 loads per
@@ -1100,7 +1120,7 @@ __device__ __forceinline__ void outl_store_flagged(const uint32_t (&fv)[kOutlU],
 // outliers are found by its flag bits (2 bytes a voxel) and only their
 // values are read from the input.
 template <typename T, bool BG = false>
-__global__ __launch_bounds__(kBlock) void k_emit_rows(const T* __restrict__ in, int64_t nx, Layout L, int64_t ny,
+__device__ __forceinline__ void k_emit_rows_body(const VPart vp, const T* __restrict__ in, int64_t nx, Layout L, int64_t ny,
                                                       int64_t nrows, EmitOut o, const float* __restrict__ bg,
                                                       int bg_plane, const uint16_t* __restrict__ px) {
     DevState* S = L.S;
@@ -1109,8 +1129,8 @@ __global__ __launch_bounds__(kBlock) void k_emit_rows(const T* __restrict__ in, 
     const unsigned long long total = S->n_outliers;
     const float r = S->r, w = S->w, eb32 = S->eb32;
     const int lane = threadIdx.x % kWave;
-    const uint32_t wave = uni((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
-    const uint32_t nwaves = gridDim.x * blockDim.x / kWave;
+    const uint32_t wave = uni((vp.b * blockDim.x + threadIdx.x) / kWave);
+    const uint32_t nwaves = vp.n * blockDim.x / kWave;
     bool trunc = false;
     for (uint64_t jb = (uint64_t)wave * kWave; jb < n_rows; jb += (uint64_t)nwaves * kWave) {
         const uint32_t j = (uint32_t)jb + (uint32_t)lane;
@@ -1225,6 +1245,12 @@ __global__ __launch_bounds__(kBlock) void k_emit_rows(const T* __restrict__ in, 
     }
     if (trunc) atomicOr(&S->trunc, 1);
 }
+template <typename T, bool BG = false>
+__global__ __launch_bounds__(kBlock) void k_emit_rows(const T* __restrict__ in, int64_t nx, Layout L, int64_t ny,
+                                                      int64_t nrows, EmitOut o, const float* __restrict__ bg,
+                                                      int bg_plane, const uint16_t* __restrict__ px) {
+    k_emit_rows_body<T, BG>(hw_part(), in, nx, L, ny, nrows, o, bg, bg_plane, px);
+}
 
 hipError_t launch_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, const void* in, roix_dtype dt,
                        const roix_fused_out* out, const BgRef* bg) {
@@ -1240,24 +1266,24 @@ hipError_t launch_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, cons
     const dim3 grid_rows_t(grid_rows(g.nrows, kBlock, lc.grid_stream));
     const dim3 grid_waves(lc.grid_emit);
     timer_begin(lc.timer, ST_EMIT, lc.stream);
-    hipLaunchKernelGGL(k_emit_index, grid_rows_t, block, 0, lc.stream, L, g.nx, g.nrows);
+    launch_k<kBlock, k_emit_index_body>(lc, k_emit_index, grid_rows_t, block, 0, L, g.nx, g.nrows);
     // the lean kernel queues the chunks it leaves to the general kernel
     if (dt == ROIX_F32) {
         // the 16-bit proxy (proxy element = voxel when rows are whole 64-voxel words)
         const uint16_t* px = (L.fine_slots && g.W * 64 == g.nx) ? reinterpret_cast<const uint16_t*>(L.proxy) : nullptr;
         // with a background the kernels that read voxel values read M
         const float* vals = bg ? bg->work : (const float*)in;
-        hipLaunchKernelGGL(k_emit_codes<float>, grid_waves, block, 0, lc.stream, vals, g.nx, L, o, px ? 1 : 0);
+        launch_k<kBlock, k_emit_codes_body<float>>(lc, k_emit_codes<float>, grid_waves, block, 0, vals, g.nx, L, o, px ? 1 : 0);
         if (px)
-            hipLaunchKernelGGL(k_emit_codes_p16, grid_waves, block, 0, lc.stream, (const float*)in, g.nx, L, o, px);
+            launch_k<kBlock, k_emit_codes_p16_body>(lc, k_emit_codes_p16, grid_waves, block, 0, (const float*)in, g.nx, L, o, px);
         if (bg) {
             hipError_t e = launch_background_if(lc, (const float*)in, *bg, g, L.S, 2);
             if (e != hipSuccess) return e;
         }
-        hipLaunchKernelGGL(k_emit_codes_general<float>, grid_waves, block, 0, lc.stream, vals, g.nx, L, o);
+        launch_k<kBlock, k_emit_codes_general_body<float>>(lc, k_emit_codes_general<float>, grid_waves, block, 0, vals, g.nx, L, o);
     } else {
-        hipLaunchKernelGGL(k_emit_codes<uint16_t>, grid_waves, block, 0, lc.stream, (const uint16_t*)in, g.nx, L, o, 0);
-        hipLaunchKernelGGL(k_emit_codes_general<uint16_t>, grid_waves, block, 0, lc.stream, (const uint16_t*)in, g.nx,
+        launch_k<kBlock, k_emit_codes_body<uint16_t>>(lc, k_emit_codes<uint16_t>, grid_waves, block, 0, (const uint16_t*)in, g.nx, L, o, 0);
+        launch_k<kBlock, k_emit_codes_general_body<uint16_t>>(lc, k_emit_codes_general<uint16_t>, grid_waves, block, 0, (const uint16_t*)in, g.nx,
                            L, o);
     }
     timer_end(lc.timer, ST_EMIT, lc.stream);
@@ -1269,13 +1295,13 @@ hipError_t launch_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, cons
     const uint16_t* px16 =
         (dt == ROIX_F32 && L.fine_slots && g.W * 64 == g.nx) ? reinterpret_cast<const uint16_t*>(L.proxy) : nullptr;
     if (dt == ROIX_F32 && bg) {
-        hipLaunchKernelGGL((k_emit_rows<float, true>), grid_rows_t, block, 0, lc.stream, (const float*)in, g.nx, L,
+        launch_k<kBlock, k_emit_rows_body<float, true>>(lc, k_emit_rows<float, true>, grid_rows_t, block, 0, (const float*)in, g.nx, L,
                            g.ny, g.nrows, o, bg->bg, bg->plane ? 1 : 0, px16);
     } else if (dt == ROIX_F32) {
-        hipLaunchKernelGGL((k_emit_rows<float, false>), grid_rows_t, block, 0, lc.stream, (const float*)in, g.nx, L,
+        launch_k<kBlock, k_emit_rows_body<float, false>>(lc, k_emit_rows<float, false>, grid_rows_t, block, 0, (const float*)in, g.nx, L,
                            g.ny, g.nrows, o, (const float*)nullptr, 0, px16);
     } else {
-        hipLaunchKernelGGL((k_emit_rows<uint16_t, false>), grid_rows_t, block, 0, lc.stream, (const uint16_t*)in, g.nx,
+        launch_k<kBlock, k_emit_rows_body<uint16_t, false>>(lc, k_emit_rows<uint16_t, false>, grid_rows_t, block, 0, (const uint16_t*)in, g.nx,
                            L, g.ny, g.nrows, o, (const float*)nullptr, 0, (const uint16_t*)nullptr);
     }
     timer_end(lc.timer, ST_EMIT_ROWS, lc.stream);
@@ -1284,7 +1310,7 @@ hipError_t launch_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, cons
 
 // --------------------------------------------------------------- finalize
 
-__global__ void k_finalize(const DevState* S, roix_quant_info* qi, roix_seg_info* si, roix_extract_info* ei,
+__device__ __forceinline__ void k_finalize_body(const VPart vp, const DevState* S, roix_quant_info* qi, roix_seg_info* si, roix_extract_info* ei,
                            int fused_q) {
     const int t = threadIdx.x;
     const int32_t st = S->status;
@@ -1333,11 +1359,15 @@ __global__ void k_finalize(const DevState* S, roix_quant_info* qi, roix_seg_info
         ei->stream_bytes = ok ? (S->span_total & kLenMask) * (uint64_t)(S->width_bits / 8) : 0ull;
     }
 }
+__global__ __launch_bounds__(1024) void k_finalize(const DevState* S, roix_quant_info* qi, roix_seg_info* si, roix_extract_info* ei,
+                           int fused_q) {
+    k_finalize_body(hw_part(), S, qi, si, ei, fused_q);
+}
 
 hipError_t launch_finalize(const LaunchCtx& lc, DevState* S, roix_quant_info* qi, roix_seg_info* si,
                            roix_extract_info* ei, bool fused_q) {
     timer_begin(lc.timer, ST_FINALIZE, lc.stream);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, lc.stream, (const DevState*)S, qi, si, ei, fused_q ? 1 : 0);
+    launch_k<1024, k_finalize_body>(lc, k_finalize, dim3(1), dim3(256), 0, (const DevState*)S, qi, si, ei, fused_q ? 1 : 0);
     timer_end(lc.timer, ST_FINALIZE, lc.stream);
     return hipGetLastError();
 }

@@ -198,7 +198,8 @@ __device__ __forceinline__ void slice_consts(const int32_t* __restrict__ thr, in
 // top bit) is 0, per-row run counts by a segmented wave scan.  slice_thr
 // (1-byte proxy only): a threshold bin per z-slice instead of one.
 template <bool P16>
-__device__ __forceinline__ void mask_runs_body(const uint8_t* __restrict__ proxy, int64_t nx, int64_t nrows, int64_t W,
+__device__ __forceinline__ void mask_runs_body(const VPart vp, const uint8_t* __restrict__ proxy, int64_t nx,
+                                               int64_t nrows, int64_t W,
                                                DevState* S, uint64_t* __restrict__ maskbits,
                                                uint32_t* __restrict__ row_nruns, const int32_t* __restrict__ slice_thr,
                                                int64_t ny) {
@@ -211,8 +212,8 @@ __device__ __forceinline__ void mask_runs_body(const uint8_t* __restrict__ proxy
     const uint16_t* proxy16 = reinterpret_cast<const uint16_t*>(proxy);
     const uint64_t lastmask = (nx % 64) ? ((1ull << (nx % 64)) - 1ull) : ~0ull;
     const int lane = threadIdx.x % kWave;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+    const int64_t wave = ((int64_t)vp.b * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)vp.n * blockDim.x / kWave;
     const int64_t P = W * 64;
     unsigned long long nmask = 0;
     if (W <= kWave) {
@@ -317,22 +318,28 @@ __device__ __forceinline__ void mask_runs_body(const uint8_t* __restrict__ proxy
 }
 
 // The proxy's kind is device data (the fused pass decides it); the branch is uniform.
-__global__ __launch_bounds__(kBlock) void k_mask_runs(const uint8_t* __restrict__ proxy, int64_t nx, int64_t nrows,
+__device__ __forceinline__ void k_mask_runs_body(const VPart vp, const uint8_t* __restrict__ proxy, int64_t nx, int64_t nrows,
                                                       int64_t W, DevState* S, uint64_t* __restrict__ maskbits,
                                                       uint32_t* __restrict__ row_nruns,
                                                       const int32_t* __restrict__ slice_thr, int64_t ny) {
     if (block_exit_l(S)) return;
     if (S->p16)
-        mask_runs_body<true>(proxy, nx, nrows, W, S, maskbits, row_nruns, nullptr, ny);
+        mask_runs_body<true>(vp, proxy, nx, nrows, W, S, maskbits, row_nruns, nullptr, ny);
     else
-        mask_runs_body<false>(proxy, nx, nrows, W, S, maskbits, row_nruns, slice_thr, ny);
+        mask_runs_body<false>(vp, proxy, nx, nrows, W, S, maskbits, row_nruns, slice_thr, ny);
+}
+__global__ __launch_bounds__(kBlock) void k_mask_runs(const uint8_t* __restrict__ proxy, int64_t nx, int64_t nrows,
+                                                      int64_t W, DevState* S, uint64_t* __restrict__ maskbits,
+                                                      uint32_t* __restrict__ row_nruns,
+                                                      const int32_t* __restrict__ slice_thr, int64_t ny) {
+    k_mask_runs_body(hw_part(), proxy, nx, nrows, W, S, maskbits, row_nruns, slice_thr, ny);
 }
 
 hipError_t launch_mask_runs(const LaunchCtx& lc, const Geom& g, const Layout& L, const int32_t* slice_thr) {
     timer_begin(lc.timer, ST_MASK_RUNS, lc.stream);
     const int64_t R = g.W <= kWave ? kWave / g.W : 1;
     int grid = grid_for((g.nrows + R - 1) / R, kBlock / kWave, lc.grid_mask);
-    hipLaunchKernelGGL(k_mask_runs, dim3(grid), dim3(kBlock), 0, lc.stream, (const uint8_t*)L.proxy, g.nx, g.nrows,
+    launch_k<kBlock, k_mask_runs_body>(lc, k_mask_runs, dim3(grid), dim3(kBlock), 0, (const uint8_t*)L.proxy, g.nx, g.nrows,
                        g.W, L.S, L.maskbits, L.row_nruns, slice_thr, g.ny);
     timer_end(lc.timer, ST_MASK_RUNS, lc.stream);
     return hipGetLastError();
@@ -344,7 +351,7 @@ hipError_t launch_mask_runs(const LaunchCtx& lc, const Geom& g, const Layout& L,
 // start in its word; a run still open at the word's end closes at the first
 // 0-bit of a later word of the row (segmented suffix minimum across lanes) or
 // at nx.  Output slot = run_off[row] + runs starting earlier in the row.
-__global__ __launch_bounds__(kBlock) void k_runs_write_lanes(const uint64_t* __restrict__ maskbits, int64_t nx,
+__device__ __forceinline__ void k_runs_write_lanes_body(const VPart vp, const uint64_t* __restrict__ maskbits, int64_t nx,
                                                              int64_t nrows, int64_t W,
                                                              const uint32_t* __restrict__ run_off,
                                                              uint32_t* __restrict__ xs_out,
@@ -354,8 +361,8 @@ __global__ __launch_bounds__(kBlock) void k_runs_write_lanes(const uint64_t* __r
                                                              const DevState* S) {
     if (thread_exit(S)) return;  // no barrier below; the status is the same for every lane of a wave
     const int lane = threadIdx.x % kWave;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+    const int64_t wave = ((int64_t)vp.b * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)vp.n * blockDim.x / kWave;
     const int64_t R = kWave / W;
     const uint32_t kBig = 0xFFFFFFFFu;
     for (int64_t row0 = wave * R; row0 < nrows; row0 += nwaves * R) {
@@ -397,17 +404,27 @@ __global__ __launch_bounds__(kBlock) void k_runs_write_lanes(const uint64_t* __r
         }
     }
 }
+__global__ __launch_bounds__(kBlock) void k_runs_write_lanes(const uint64_t* __restrict__ maskbits, int64_t nx,
+                                                             int64_t nrows, int64_t W,
+                                                             const uint32_t* __restrict__ run_off,
+                                                             uint32_t* __restrict__ xs_out,
+                                                             uint32_t* __restrict__ xe_out,
+                                                             uint32_t* __restrict__ parent,
+                                                             uint32_t* __restrict__ run_row, int64_t row_base,
+                                                             const DevState* S) {
+    k_runs_write_lanes_body(hw_part(), maskbits, nx, nrows, W, run_off, xs_out, xe_out, parent, run_row, row_base, S);
+}
 
 // Rows of more than 64 words: one thread per row walks the row's words; a
 // start event opens a run, an end event (0-bit after a 1-bit) closes it.
-__global__ __launch_bounds__(kBlock) void k_runs_write(const uint64_t* __restrict__ maskbits, int64_t nrows, int64_t W,
+__device__ __forceinline__ void k_runs_write_body(const VPart vp, const uint64_t* __restrict__ maskbits, int64_t nrows, int64_t W,
                                                        const uint32_t* __restrict__ run_off, uint32_t* __restrict__ xs_out,
                                                        uint32_t* __restrict__ xe_out, uint32_t* __restrict__ parent,
                                                        uint32_t* __restrict__ run_row, int64_t row_base,
                                                        const DevState* S) {
     if (thread_exit(S)) return;
-    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < nrows; row += nthreads) {
+    const int64_t nthreads = (int64_t)vp.n * blockDim.x;
+    for (int64_t row = (int64_t)vp.b * blockDim.x + threadIdx.x; row < nrows; row += nthreads) {
         const uint64_t* mb = maskbits + row * W;
         uint32_t k = run_off[row];
         uint64_t carry = 0;
@@ -441,6 +458,13 @@ __global__ __launch_bounds__(kBlock) void k_runs_write(const uint64_t* __restric
         }
     }
 }
+__global__ __launch_bounds__(kBlock) void k_runs_write(const uint64_t* __restrict__ maskbits, int64_t nrows, int64_t W,
+                                                       const uint32_t* __restrict__ run_off, uint32_t* __restrict__ xs_out,
+                                                       uint32_t* __restrict__ xe_out, uint32_t* __restrict__ parent,
+                                                       uint32_t* __restrict__ run_row, int64_t row_base,
+                                                       const DevState* S) {
+    k_runs_write_body(hw_part(), maskbits, nrows, W, run_off, xs_out, xe_out, parent, run_row, row_base, S);
+}
 
 hipError_t launch_runs_write(const LaunchCtx& lc, const Geom& g, const Layout& L, int64_t r0, int64_t r1) {
     timer_begin(lc.timer, ST_RUNS, lc.stream);
@@ -449,11 +473,11 @@ hipError_t launch_runs_write(const LaunchCtx& lc, const Geom& g, const Layout& L
     const uint32_t* off = L.run_off + r0;
     if (g.W <= kWave) {
         const int64_t R = kWave / g.W;
-        hipLaunchKernelGGL(k_runs_write_lanes, dim3(grid_for((nr + R - 1) / R, kBlock / kWave, lc.grid_mask)),
-                           dim3(kBlock), 0, lc.stream, mb, g.nx, nr, g.W, off, L.run_xs, L.run_xe, L.parent,
+        launch_k<kBlock, k_runs_write_lanes_body>(lc, k_runs_write_lanes, dim3(grid_for((nr + R - 1) / R, kBlock / kWave, lc.grid_mask)),
+                           dim3(kBlock), 0, mb, g.nx, nr, g.W, off, L.run_xs, L.run_xe, L.parent,
                            L.run_row, r0, (const DevState*)L.S);
     } else {
-        hipLaunchKernelGGL(k_runs_write, dim3(grid_for(nr, kBlock, 16384)), dim3(kBlock), 0, lc.stream, mb, nr, g.W,
+        launch_k<kBlock, k_runs_write_body>(lc, k_runs_write, dim3(grid_for(nr, kBlock, 16384)), dim3(kBlock), 0, mb, nr, g.W,
                            off, L.run_xs, L.run_xe, L.parent, L.run_row, r0, (const DevState*)L.S);
     }
     timer_end(lc.timer, ST_RUNS, lc.stream);
@@ -597,7 +621,7 @@ __device__ __forceinline__ void for_back_rows(uint32_t r, uint32_t z, uint32_t y
 // ends; pairs inside the segment are united in LDS.  Then parent[run] = the
 // run number of its segment-local root.
 template <bool C26>
-__global__ __launch_bounds__(kSegBlock) void k_seg_label(const uint32_t* __restrict__ run_off,
+__device__ __forceinline__ void k_seg_label_body(const VPart vp, const uint32_t* __restrict__ run_off,
                                                          const uint32_t* __restrict__ xs,
                                                          const uint32_t* __restrict__ xe,
                                                          const uint32_t* __restrict__ run_row, uint32_t* parent,
@@ -609,7 +633,7 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_label(const uint32_t* __restr
     if (n <= lo) return;
     const uint32_t T = seg_runs(n - lo, G, tparam, (uint32_t)kSegCap);
     const uint32_t nseg = (n - lo + T - 1) / T;
-    for (uint32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
+    for (uint32_t sg = vp.b; sg < nseg; sg += vp.n) {
         const uint32_t s0 = lo + sg * T, s1 = (n - s0 < T) ? n : s0 + T, m = s1 - s0;
         for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) lp[i] = i;
         __syncthreads();
@@ -640,6 +664,15 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_label(const uint32_t* __restr
         __syncthreads();  // lp is reused by the next segment
     }
 }
+template <bool C26>
+__global__ __launch_bounds__(kSegBlock) void k_seg_label(const uint32_t* __restrict__ run_off,
+                                                         const uint32_t* __restrict__ xs,
+                                                         const uint32_t* __restrict__ xe,
+                                                         const uint32_t* __restrict__ run_row, uint32_t* parent,
+                                                         uint32_t ny, double inv_ny, uint32_t G, uint32_t tparam,
+                                                         const DevState* S) {
+    k_seg_label_body<C26>(hw_part(), run_off, xs, xe, run_row, parent, ny, inv_ny, G, tparam, S);
+}
 
 // Level 2: one workgroup per segment.
 // Only runs whose rows lie within ny + 1 rows of the segment's first row can
@@ -648,7 +681,7 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_label(const uint32_t* __restr
 // (a giant component contributes a handful instead of one per run) and
 // united in the global forest.  A full set falls back to direct unions.
 template <bool C26>
-__global__ __launch_bounds__(kBlock) void k_seg_cross(const uint32_t* __restrict__ run_off,
+__device__ __forceinline__ void k_seg_cross_body(const VPart vp, const uint32_t* __restrict__ run_off,
                                                       const uint32_t* __restrict__ xs,
                                                       const uint32_t* __restrict__ xe,
                                                       const uint32_t* __restrict__ run_row, uint32_t* parent,
@@ -662,7 +695,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_cross(const uint32_t* __restrict
     const uint32_t T = seg_runs(n - lo, G, tparam, (uint32_t)kSegCap);
     const uint32_t nseg = (n - lo + T - 1) / T;
     // the very first segment of a volume has nothing before it
-    for (uint32_t sg = (lo == 0 ? 1u : 0u) + blockIdx.x; sg < nseg; sg += gridDim.x) {
+    for (uint32_t sg = (lo == 0 ? 1u : 0u) + vp.b; sg < nseg; sg += vp.n) {
         const uint32_t s0 = lo + sg * T, s1 = (n - s0 < T) ? n : s0 + T;
         for (int i = threadIdx.x; i < kCrossCap; i += blockDim.x) tab[i] = kEmpty;
         const uint32_t r0 = run_row[s0];  // rows after r0 hold only runs > s0
@@ -716,6 +749,15 @@ __global__ __launch_bounds__(kBlock) void k_seg_cross(const uint32_t* __restrict
         __syncthreads();  // tab is reused by the next segment
     }
 }
+template <bool C26>
+__global__ __launch_bounds__(kBlock) void k_seg_cross(const uint32_t* __restrict__ run_off,
+                                                      const uint32_t* __restrict__ xs,
+                                                      const uint32_t* __restrict__ xe,
+                                                      const uint32_t* __restrict__ run_row, uint32_t* parent,
+                                                      uint32_t ny, double inv_ny, int64_t nrows, uint32_t G,
+                                                      uint32_t tparam, const DevState* S) {
+    k_seg_cross_body<C26>(hw_part(), run_off, xs, xe, run_row, parent, ny, inv_ny, nrows, G, tparam, S);
+}
 
 // ---------------------------------------------- staged (LDS) segment kernels
 //
@@ -749,7 +791,7 @@ __device__ __forceinline__ uint32_t first_touch_p(const uint32_t* lx, uint32_t b
 }
 
 template <bool C26>
-__global__ __launch_bounds__(kSegBlock) void k_seg_label_lds(const uint32_t* __restrict__ run_off,
+__device__ __forceinline__ void k_seg_label_lds_body(const VPart vp, const uint32_t* __restrict__ run_off,
                                                              const uint32_t* __restrict__ xs,
                                                              const uint32_t* __restrict__ xe,
                                                              const uint32_t* __restrict__ run_row, uint32_t* parent,
@@ -763,7 +805,7 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_label_lds(const uint32_t* __r
     if (n <= lo) return;
     const uint32_t T = seg_runs(n - lo, G, tparam, (uint32_t)kLSeg);
     const uint32_t nseg = (n - lo + T - 1) / T;
-    for (uint32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
+    for (uint32_t sg = vp.b; sg < nseg; sg += vp.n) {
         const uint32_t s0 = lo + sg * T, s1 = (n - s0 < T) ? n : s0 + T, m = s1 - s0;
         const uint32_t rf = run_row[s0], rl = run_row[s1 - 1];
         const bool rows_in = rl - rf + 2 <= (uint32_t)kLRows;  // offsets of rows rf .. rl + 1
@@ -801,9 +843,18 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_label_lds(const uint32_t* __r
         __syncthreads();  // the arrays are reused by the next segment
     }
 }
+template <bool C26>
+__global__ __launch_bounds__(kSegBlock) void k_seg_label_lds(const uint32_t* __restrict__ run_off,
+                                                             const uint32_t* __restrict__ xs,
+                                                             const uint32_t* __restrict__ xe,
+                                                             const uint32_t* __restrict__ run_row, uint32_t* parent,
+                                                             uint32_t ny, double inv_ny, uint32_t G,
+                                                             uint32_t tparam, const DevState* S) {
+    k_seg_label_lds_body<C26>(hw_part(), run_off, xs, xe, run_row, parent, ny, inv_ny, G, tparam, S);
+}
 
 template <bool C26>
-__global__ __launch_bounds__(kSegBlock) void k_seg_cross_lds(const uint32_t* __restrict__ run_off,
+__device__ __forceinline__ void k_seg_cross_lds_body(const VPart vp, const uint32_t* __restrict__ run_off,
                                                              const uint32_t* __restrict__ xs,
                                                              const uint32_t* __restrict__ xe,
                                                              const uint32_t* __restrict__ run_row, uint32_t* parent,
@@ -819,7 +870,7 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_cross_lds(const uint32_t* __r
     if (n <= lo) return;
     const uint32_t T = seg_runs(n - lo, G, tparam, (uint32_t)kLSeg);
     const uint32_t nseg = (n - lo + T - 1) / T;
-    for (uint32_t sg = (lo == 0 ? 1u : 0u) + blockIdx.x; sg < nseg; sg += gridDim.x) {
+    for (uint32_t sg = (lo == 0 ? 1u : 0u) + vp.b; sg < nseg; sg += vp.n) {
         const uint32_t s0 = lo + sg * T, s1 = (n - s0 < T) ? n : s0 + T;
         for (int i = threadIdx.x; i < kCrossCap; i += blockDim.x) tab[i] = kEmpty;
         const uint32_t r0 = run_row[s0];  // rows after r0 hold only runs > s0
@@ -883,6 +934,15 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_cross_lds(const uint32_t* __r
         __syncthreads();  // the arrays are reused by the next segment
     }
 }
+template <bool C26>
+__global__ __launch_bounds__(kSegBlock) void k_seg_cross_lds(const uint32_t* __restrict__ run_off,
+                                                             const uint32_t* __restrict__ xs,
+                                                             const uint32_t* __restrict__ xe,
+                                                             const uint32_t* __restrict__ run_row, uint32_t* parent,
+                                                             uint32_t ny, double inv_ny, uint32_t G,
+                                                             uint32_t tparam, const DevState* S) {
+    k_seg_cross_lds_body<C26>(hw_part(), run_off, xs, xe, run_row, parent, ny, inv_ny, G, tparam, S);
+}
 
 hipError_t launch_union(const LaunchCtx& lc, const Geom& g, const Layout& L, int conn) {
     timer_begin(lc.timer, ST_UNION, lc.stream);
@@ -896,17 +956,17 @@ hipError_t launch_union(const LaunchCtx& lc, const Geom& g, const Layout& L, int
     const bool staged = g.nx <= 65535 && tp <= (uint32_t)kLSeg;
 #define SEG_LAUNCH(C)                                                                                           \
     if (staged) {                                                                                               \
-        hipLaunchKernelGGL(k_seg_label_lds<C>, grid, dim3(kSegBlock), 0, lc.stream, (const uint32_t*)L.run_off,  \
+        launch_k<kSegBlock, k_seg_label_lds_body<C>>(lc, k_seg_label_lds<C>, grid, dim3(kSegBlock), 0, (const uint32_t*)L.run_off,  \
                            (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, (const uint32_t*)L.run_row,    \
                            L.parent, ny, inv_ny, G, tp, (const DevState*)L.S);                                  \
-        hipLaunchKernelGGL(k_seg_cross_lds<C>, grid, dim3(kSegBlock), 0, lc.stream, (const uint32_t*)L.run_off,  \
+        launch_k<kSegBlock, k_seg_cross_lds_body<C>>(lc, k_seg_cross_lds<C>, grid, dim3(kSegBlock), 0, (const uint32_t*)L.run_off,  \
                            (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, (const uint32_t*)L.run_row,    \
                            L.parent, ny, inv_ny, G, tp, (const DevState*)L.S);                                  \
     } else {                                                                                                    \
-        hipLaunchKernelGGL(k_seg_label<C>, grid, dim3(kSegBlock), 0, lc.stream, (const uint32_t*)L.run_off,      \
+        launch_k<kSegBlock, k_seg_label_body<C>>(lc, k_seg_label<C>, grid, dim3(kSegBlock), 0, (const uint32_t*)L.run_off,      \
                            (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, (const uint32_t*)L.run_row,    \
                            L.parent, ny, inv_ny, G, tp, (const DevState*)L.S);                                  \
-        hipLaunchKernelGGL(k_seg_cross<C>, grid, dim3(kBlock), 0, lc.stream, (const uint32_t*)L.run_off,         \
+        launch_k<kBlock, k_seg_cross_body<C>>(lc, k_seg_cross<C>, grid, dim3(kBlock), 0, (const uint32_t*)L.run_off,         \
                            (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe, (const uint32_t*)L.run_row,    \
                            L.parent, ny, inv_ny, g.nrows, G, tp, (const DevState*)L.S);                         \
     }
@@ -925,11 +985,11 @@ hipError_t launch_union(const LaunchCtx& lc, const Geom& g, const Layout& L, int
 // intermediate ancestor back into an entry another thread has already set to
 // its root.  Each entry is written by its own thread only, so every entry
 // ends at its root.
-__global__ __launch_bounds__(kBlock) void k_flatten(uint32_t* parent, uint32_t* root_flag, const DevState* S) {
+__device__ __forceinline__ void k_flatten_body(const VPart vp, uint32_t* parent, uint32_t* root_flag, const DevState* S) {
     if (thread_exit(S)) return;
     const uint32_t n = S->n_runs;
-    const uint32_t nthreads = gridDim.x * blockDim.x;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += nthreads) {
+    const uint32_t nthreads = vp.n * blockDim.x;
+    for (uint32_t i = vp.b * blockDim.x + threadIdx.x; i < n; i += nthreads) {
         uint32_t r = i, p = ld_relaxed(&parent[i]);
         while (p != r) {
             r = p;
@@ -939,10 +999,13 @@ __global__ __launch_bounds__(kBlock) void k_flatten(uint32_t* parent, uint32_t* 
         root_flag[i] = (r == i) ? 1u : 0u;
     }
 }
+__global__ __launch_bounds__(kBlock) void k_flatten(uint32_t* parent, uint32_t* root_flag, const DevState* S) {
+    k_flatten_body(hw_part(), parent, root_flag, S);
+}
 
 hipError_t launch_flatten(const LaunchCtx& lc, const Layout& L) {
     timer_begin(lc.timer, ST_FLATTEN, lc.stream);
-    hipLaunchKernelGGL(k_flatten, dim3(2048), dim3(kBlock), 0, lc.stream, L.parent, L.comp_id,
+    launch_k<kBlock, k_flatten_body>(lc, k_flatten, dim3(lc.grid_stream), dim3(kBlock), 0, L.parent, L.comp_id,
                        (const DevState*)L.S);
     timer_end(lc.timer, ST_FLATTEN, lc.stream);
     return hipGetLastError();
@@ -1029,15 +1092,15 @@ __device__ __forceinline__ void wave_flush(bool pred, uint32_t root, const Acc& 
 
 // One thread per root run: the entry of its component (label = first voxel
 // of the root run, i.e. of the component).
-__global__ __launch_bounds__(kBlock) void k_comp_init(const uint32_t* __restrict__ xs,
+__device__ __forceinline__ void k_comp_init_body(const VPart vp, const uint32_t* __restrict__ xs,
                                                       const uint32_t* __restrict__ run_row,
                                                       const uint32_t* __restrict__ parent,
                                                       const uint32_t* __restrict__ comp_id, int64_t nx,
                                                       roix_component* comps, const DevState* S) {
     if (thread_exit(S)) return;
     const uint32_t n = S->n_runs;
-    const uint32_t nthreads = gridDim.x * blockDim.x;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += nthreads) {
+    const uint32_t nthreads = vp.n * blockDim.x;
+    for (uint32_t i = vp.b * blockDim.x + threadIdx.x; i < n; i += nthreads) {
         if (parent[i] != i) continue;
         roix_component* c = comps + comp_id[i];
         c->label = (uint64_t)run_row[i] * (uint64_t)nx + xs[i];
@@ -1048,6 +1111,13 @@ __global__ __launch_bounds__(kBlock) void k_comp_init(const uint32_t* __restrict
         c->pad = 0u;
     }
 }
+__global__ __launch_bounds__(kBlock) void k_comp_init(const uint32_t* __restrict__ xs,
+                                                      const uint32_t* __restrict__ run_row,
+                                                      const uint32_t* __restrict__ parent,
+                                                      const uint32_t* __restrict__ comp_id, int64_t nx,
+                                                      roix_component* comps, const DevState* S) {
+    k_comp_init_body(hw_part(), xs, run_row, parent, comp_id, nx, comps, S);
+}
 
 // Size and box of every component.  Each workgroup takes a contiguous range
 // of runs; a thread accumulates kStatRuns consecutive runs while their root
@@ -1055,7 +1125,7 @@ __global__ __launch_bounds__(kBlock) void k_comp_init(const uint32_t* __restrict
 // wave_flush at uniform points.  The table goes to the components once at
 // the end, so a giant component costs one set of global atomics per
 // workgroup.
-__global__ __launch_bounds__(kBlock) void k_comp_stats(const uint32_t* __restrict__ xs,
+__device__ __forceinline__ void k_comp_stats_body(const VPart vp, const uint32_t* __restrict__ xs,
                                                        const uint32_t* __restrict__ xe,
                                                        const uint32_t* __restrict__ run_row,
                                                        const uint32_t* __restrict__ parent,
@@ -1071,9 +1141,9 @@ __global__ __launch_bounds__(kBlock) void k_comp_stats(const uint32_t* __restric
     if (block_exit_l(S)) return;
     const uint32_t n = S->n_runs;
     constexpr uint32_t kRound = (uint32_t)kBlock * kStatRuns;
-    uint64_t per = ((uint64_t)n + gridDim.x - 1) / gridDim.x;
+    uint64_t per = ((uint64_t)n + vp.n - 1) / vp.n;
     per = (per + kRound - 1) / kRound * kRound;
-    const uint64_t b0 = (uint64_t)blockIdx.x * per;
+    const uint64_t b0 = (uint64_t)vp.b * per;
     const uint64_t b1 = b0 + per < (uint64_t)n ? b0 + per : (uint64_t)n;
     for (uint64_t base = b0; base < b1; base += kRound) {
         const uint64_t i0 = base + (uint64_t)threadIdx.x * kStatRuns;
@@ -1138,14 +1208,21 @@ __global__ __launch_bounds__(kBlock) void k_comp_stats(const uint32_t* __restric
         acc_flush_global(comps, comp_id[key], e);
     }
 }
+__global__ __launch_bounds__(kBlock) void k_comp_stats(const uint32_t* __restrict__ xs,
+                                                       const uint32_t* __restrict__ xe,
+                                                       const uint32_t* __restrict__ run_row,
+                                                       const uint32_t* __restrict__ parent,
+                                                       const uint32_t* __restrict__ comp_id, uint32_t ny,
+                                                       double inv_ny, roix_component* comps, const DevState* S) {
+    k_comp_stats_body(hw_part(), xs, xe, run_row, parent, comp_id, ny, inv_ny, comps, S);
+}
 
 hipError_t launch_comp_stats(const LaunchCtx& lc, const Geom& g, const Layout& L, roix_component* comps) {
     timer_begin(lc.timer, ST_COMPS, lc.stream);
-    hipLaunchKernelGGL(k_comp_init, dim3(grid_for((int64_t)L.run_cap, kBlock, lc.grid_stream)), dim3(kBlock), 0,
-                       lc.stream, (const uint32_t*)L.run_xs, (const uint32_t*)L.run_row, (const uint32_t*)L.parent,
+    launch_k<kBlock, k_comp_init_body>(lc, k_comp_init, dim3(grid_for((int64_t)L.run_cap, kBlock, lc.grid_stream)), dim3(kBlock), 0, (const uint32_t*)L.run_xs, (const uint32_t*)L.run_row, (const uint32_t*)L.parent,
                        (const uint32_t*)L.comp_id, g.nx, comps, (const DevState*)L.S);
-    hipLaunchKernelGGL(k_comp_stats, dim3(grid_for((int64_t)L.run_cap, kBlock * kStatRuns, lc.stats_grid)),
-                       dim3(kBlock), 0, lc.stream, (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe,
+    launch_k<kBlock, k_comp_stats_body>(lc, k_comp_stats, dim3(grid_for((int64_t)L.run_cap, kBlock * kStatRuns, lc.stats_grid)),
+                       dim3(kBlock), 0, (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe,
                        (const uint32_t*)L.run_row, (const uint32_t*)L.parent, (const uint32_t*)L.comp_id,
                        (uint32_t)g.ny, 1.0 / (double)g.ny, comps, (const DevState*)L.S);
     timer_end(lc.timer, ST_COMPS, lc.stream);
@@ -1154,36 +1231,42 @@ hipError_t launch_comp_stats(const LaunchCtx& lc, const Geom& g, const Layout& L
 
 // ------------------------------------------------------------- keep rule
 
-__global__ __launch_bounds__(kBlock) void k_largest_max(const roix_component* comps, DevState* S) {
+__device__ __forceinline__ void k_largest_max_body(const VPart vp, const roix_component* comps, DevState* S) {
     if (block_exit_l(S)) return;
     const uint32_t n = S->n_comps;
     unsigned long long m = 0;
-    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
+    for (uint32_t c = vp.b * blockDim.x + threadIdx.x; c < n; c += vp.n * blockDim.x)
         m = comps[c].size > m ? comps[c].size : m;
     m = wave_max(m);
     if (threadIdx.x % kWave == 0 && m) atomicMax(&S->max_size, m);
 }
+__global__ __launch_bounds__(kBlock) void k_largest_max(const roix_component* comps, DevState* S) {
+    k_largest_max_body(hw_part(), comps, S);
+}
 
-__global__ __launch_bounds__(kBlock) void k_largest_arg(const roix_component* comps, DevState* S) {
+__device__ __forceinline__ void k_largest_arg_body(const VPart vp, const roix_component* comps, DevState* S) {
     if (block_exit_l(S)) return;
     const uint32_t n = S->n_comps;
     const unsigned long long m = S->max_size;
     uint32_t best = kNone;
-    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
+    for (uint32_t c = vp.b * blockDim.x + threadIdx.x; c < n; c += vp.n * blockDim.x)
         if (comps[c].size == m && c < best) best = c;
     best = wave_min(best);
     if (threadIdx.x % kWave == 0 && best != kNone) atomicMin(&S->largest_cid, best);
 }
+__global__ __launch_bounds__(kBlock) void k_largest_arg(const roix_component* comps, DevState* S) {
+    k_largest_arg_body(hw_part(), comps, S);
+}
 
 // kept flags, counts and the union box of kept components
-__global__ __launch_bounds__(kBlock) void k_keep_apply(roix_component* comps, uint8_t* kept_flag, int largest,
+__device__ __forceinline__ void k_keep_apply_body(const VPart vp, roix_component* comps, uint8_t* kept_flag, int largest,
                                                        unsigned long long min_size, DevState* S) {
     if (block_exit_l(S)) return;
     const uint32_t n = S->n_comps;
     const uint32_t lc = S->largest_cid;
     unsigned long long nk = 0, nv = 0;
     uint32_t bb[6] = {0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu, 0u};
-    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    for (uint32_t c = vp.b * blockDim.x + threadIdx.x; c < n; c += vp.n * blockDim.x) {
         roix_component* e = comps + c;
         const bool k = largest ? (c == lc) : (e->size >= min_size);
         e->kept = k ? 1u : 0u;
@@ -1217,16 +1300,20 @@ __global__ __launch_bounds__(kBlock) void k_keep_apply(roix_component* comps, ui
         atomicMax(&S->bbox[5], bb[5]);
     }
 }
+__global__ __launch_bounds__(kBlock) void k_keep_apply(roix_component* comps, uint8_t* kept_flag, int largest,
+                                                       unsigned long long min_size, DevState* S) {
+    k_keep_apply_body(hw_part(), comps, kept_flag, largest, min_size, S);
+}
 
 hipError_t launch_keep(const LaunchCtx& lc, const Layout& L, roix_component* comps, const roix_criterion* crit) {
     timer_begin(lc.timer, ST_KEEP, lc.stream);
     const int largest = crit->keep == ROIX_KEEP_LARGEST;
     const int grid = 512;
     if (largest) {
-        hipLaunchKernelGGL(k_largest_max, dim3(grid), dim3(kBlock), 0, lc.stream, (const roix_component*)comps, L.S);
-        hipLaunchKernelGGL(k_largest_arg, dim3(grid), dim3(kBlock), 0, lc.stream, (const roix_component*)comps, L.S);
+        launch_k<kBlock, k_largest_max_body>(lc, k_largest_max, dim3(grid), dim3(kBlock), 0, (const roix_component*)comps, L.S);
+        launch_k<kBlock, k_largest_arg_body>(lc, k_largest_arg, dim3(grid), dim3(kBlock), 0, (const roix_component*)comps, L.S);
     }
-    hipLaunchKernelGGL(k_keep_apply, dim3(grid), dim3(kBlock), 0, lc.stream, comps, L.kept_flag, largest,
+    launch_k<kBlock, k_keep_apply_body>(lc, k_keep_apply, dim3(grid), dim3(kBlock), 0, comps, L.kept_flag, largest,
                        (unsigned long long)(crit->min_size > 0 ? crit->min_size : 1), L.S);
     timer_end(lc.timer, ST_KEEP, lc.stream);
     return hipGetLastError();

@@ -78,7 +78,7 @@ __device__ bool resolve_bound(double eb, float& eb32, float& w, float& r);
 
 // eb_abs > 0: also the quantiser of that absolute bound (zeros when the bound
 // is unusable; the resolve after the range then reports it)
-__global__ __launch_bounds__(kBlock) void k_init(DevState* S, double eb_abs) {
+__device__ __forceinline__ void k_init_body(const VPart vp, DevState* S, double eb_abs) {
     {
         if (threadIdx.x == 0) {
             S->status = 0;
@@ -122,10 +122,13 @@ __global__ __launch_bounds__(kBlock) void k_init(DevState* S, double eb_abs) {
         S->hist[threadIdx.x] = 0ull;
     }
 }
+__global__ __launch_bounds__(kBlock) void k_init(DevState* S, double eb_abs) {
+    k_init_body(hw_part(), S, eb_abs);
+}
 
 hipError_t launch_init(const LaunchCtx& lc, DevState* S, double eb_abs) {
     timer_begin(lc.timer, ST_INIT, lc.stream);
-    hipLaunchKernelGGL(k_init, dim3(1), dim3(kBlock), 0, lc.stream, S, eb_abs);
+    launch_k<kBlock, k_init_body>(lc, k_init, dim3(1), dim3(kBlock), 0, S, eb_abs);
     timer_end(lc.timer, ST_INIT, lc.stream);
     return hipGetLastError();
 }
@@ -146,12 +149,12 @@ __device__ __forceinline__ uint32_t range_key<uint16_t>(uint16_t x, uint32_t& no
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_range(const T* __restrict__ in, uint64_t N, uint64_t head,
+__device__ __forceinline__ void k_range_body(const VPart vp, const T* __restrict__ in, uint64_t N, uint64_t head,
                                                   uint64_t nvec, DevState* S) {
     constexpr int VN = VecN<T>::n;
     uint32_t lo = 0xFFFFFFFFu, hi = 0u, nf = 0u;
-    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t nthreads = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t tid = (uint64_t)vp.b * blockDim.x + threadIdx.x;
+    const uint64_t nthreads = (uint64_t)vp.n * blockDim.x;
     // scalar head and tail
     const uint64_t tail0 = head + nvec * VN;
     for (uint64_t i = tid; i < head + (N - tail0); i += nthreads) {
@@ -162,7 +165,7 @@ __global__ __launch_bounds__(kBlock) void k_range(const T* __restrict__ in, uint
     }
     const uint4* vin = reinterpret_cast<const uint4*>(in + head);
     const uint64_t per_iter = nthreads * kUnroll;
-    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x * kUnroll; base < nvec; base += per_iter) {
+    for (uint64_t base = (uint64_t)vp.b * blockDim.x * kUnroll; base < nvec; base += per_iter) {
         uint4 raw[kUnroll];
 #pragma unroll
         for (int k = 0; k < kUnroll; ++k) {
@@ -205,6 +208,11 @@ __global__ __launch_bounds__(kBlock) void k_range(const T* __restrict__ in, uint
         if (nf) atomicOr(&S->nonfinite, 1u);
     }
 }
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_range(const T* __restrict__ in, uint64_t N, uint64_t head,
+                                                  uint64_t nvec, DevState* S) {
+    k_range_body<T>(hw_part(), in, N, head, nvec, S);
+}
 
 static int stream_grid(const LaunchCtx& lc, uint64_t nvec) {
     uint64_t need = (nvec + (uint64_t)kBlock * kUnroll - 1) / ((uint64_t)kBlock * kUnroll);
@@ -217,11 +225,11 @@ hipError_t launch_range(const LaunchCtx& lc, const void* in, roix_dtype dt, uint
     timer_begin(lc.timer, ST_RANGE, lc.stream);
     if (dt == ROIX_F32) {
         split_vec<float>(in, N, &head, &nvec);
-        hipLaunchKernelGGL(k_range<float>, dim3(stream_grid(lc, nvec)), dim3(kBlock), 0, lc.stream,
+        launch_k<kBlock, k_range_body<float>>(lc, k_range<float>, dim3(stream_grid(lc, nvec)), dim3(kBlock), 0,
                            (const float*)in, N, head, nvec, S);
     } else {
         split_vec<uint16_t>(in, N, &head, &nvec);
-        hipLaunchKernelGGL(k_range<uint16_t>, dim3(stream_grid(lc, nvec)), dim3(kBlock), 0, lc.stream,
+        launch_k<kBlock, k_range_body<uint16_t>>(lc, k_range<uint16_t>, dim3(stream_grid(lc, nvec)), dim3(kBlock), 0,
                            (const uint16_t*)in, N, head, nvec, S);
     }
     timer_end(lc.timer, ST_RANGE, lc.stream);
@@ -312,16 +320,19 @@ __device__ void resolve_core(DevState* S, int is_f32, int eb_mode, double eb_val
     if (fixed) resolve_fixed(S, fixed_value);
 }
 
-__global__ void k_resolve(DevState* S, int is_f32, int eb_mode, double eb_value, int fixed, double fixed_value) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ __forceinline__ void k_resolve_body(const VPart vp, DevState* S, int is_f32, int eb_mode, double eb_value, int fixed, double fixed_value) {
+    if (threadIdx.x != 0 || vp.b != 0) return;
     resolve_core(S, is_f32, eb_mode, eb_value, fixed, fixed_value);
+}
+__global__ __launch_bounds__(1024) void k_resolve(DevState* S, int is_f32, int eb_mode, double eb_value, int fixed, double fixed_value) {
+    k_resolve_body(hw_part(), S, is_f32, eb_mode, eb_value, fixed, fixed_value);
 }
 
 hipError_t launch_resolve_dt(const LaunchCtx& lc, DevState* S, roix_dtype dt, roix_eb eb,
                              const roix_criterion* crit) {
     int fixed = crit && crit->thr == ROIX_THR_FIXED;
     timer_begin(lc.timer, ST_RESOLVE, lc.stream);
-    hipLaunchKernelGGL(k_resolve, dim3(1), dim3(64), 0, lc.stream, S, dt == ROIX_F32 ? 1 : 0, (int)eb.mode,
+    launch_k<1024, k_resolve_body>(lc, k_resolve, dim3(1), dim3(64), 0, S, dt == ROIX_F32 ? 1 : 0, (int)eb.mode,
                        eb.value, fixed, fixed ? crit->fixed_value : 0.0);
     timer_end(lc.timer, ST_RESOLVE, lc.stream);
     return hipGetLastError();
@@ -461,21 +472,77 @@ __device__ __forceinline__ void qh_vec(const uint4& raw, uint8_t* __restrict__ d
     }
 }
 
-// Vector path (row starts 16-byte aligned): 16-byte vectors, stored as one
-// word of proxy bytes at the same voxel offset of the row's proxy.  A wave
-// fills kQhSlots vector slots per step: rows of at most kQhSlots / 2
-// vectors (padded to a power of two) are taken several at a time, longer rows
-// one at a time, so that every lane has kQhBatch loads in flight.
-// Scalar path: lane l takes voxels l, l + 64, ... of one row at a time.
-template <typename T, bool CODES, bool FIXED, bool FASTDIV, bool VEC, bool STORE>
-__device__ __forceinline__ void qh_rows(const T* __restrict__ in, int64_t nx, int64_t nrows, int64_t P,
+// Flat path (rows not 16-byte aligned, the volume is): the N values as one
+// array of 16-byte vectors, kQhBatch in flight per lane, a wave step being
+// kQhSlots consecutive vectors.  A value's row and column come from the
+// step's first row and column (one scalar division per step) and its offset
+// in the step: q = floor(t / nx) for t < nx + kQhSlots * VN from a float
+// estimate and one correction.  The last N mod VN values go value by value.
+template <typename T, bool CODES, bool FIXED, bool FASTDIV, bool STORE>
+__device__ __forceinline__ void qh_flat(const VPart vp, const T* __restrict__ in, int64_t nx, int64_t nrows, int64_t P,
                                         const QH& p, uint32_t* mine, uint8_t* __restrict__ proxy, bool& bad) {
     constexpr int VN = VecN<T>::n;
     constexpr int64_t kQhSlots = (int64_t)kWave * kQhBatch;
     const int lane = threadIdx.x % kWave;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
-    if constexpr (VEC) {
+    const int64_t wave = ((int64_t)vp.b * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)vp.n * blockDim.x / kWave;
+    const int64_t N = nx * nrows, nvec = N / VN;
+    const uint4* v4 = reinterpret_cast<const uint4*>(in);
+    const float inv_nx = 1.0f / (float)nx;
+    const uint32_t unx = (uint32_t)nx;
+    for (int64_t s0 = wave * kQhSlots; s0 < nvec; s0 += nwaves * kQhSlots) {
+        uint4 raw[kQhBatch];
+#pragma unroll
+        for (int k = 0; k < kQhBatch; ++k) {
+            const int64_t vi = s0 + k * kWave + lane;
+            raw[k] = vi < nvec ? ld_stream(v4 + vi) : make_uint4(0, 0, 0, 0);
+        }
+        const int64_t f0 = s0 * VN;  // first value of the step (uniform)
+        const int64_t row0 = f0 / nx, x0 = f0 - row0 * nx;
+#pragma unroll
+        for (int k = 0; k < kQhBatch; ++k) {
+            const int64_t vi = s0 + k * kWave + lane;
+            if (vi >= nvec) continue;
+            T v[VN];
+            unpack16<T>(raw[k], v);
+            const uint32_t t0 = (uint32_t)(x0 + (vi - s0) * VN);
+#pragma unroll
+            for (int j = 0; j < VN; ++j) {
+                const uint32_t t = t0 + (uint32_t)j;
+                uint32_t q = (uint32_t)((float)t * inv_nx);
+                if ((uint64_t)q * unx > t) --q;
+                if ((uint64_t)(q + 1) * unx <= t) ++q;
+                const uint32_t pb = qh_one<T, CODES, FIXED, FASTDIV>(v[j], p, mine, bad);
+                if constexpr (STORE) proxy[(row0 + q) * P + (t - q * unx)] = (uint8_t)pb;
+            }
+        }
+    }
+    if (wave == 0)
+        for (int64_t f = nvec * VN + lane; f < N; f += kWave) {
+            const int64_t row = f / nx, x = f - row * nx;
+            const uint32_t pb = qh_one<T, CODES, FIXED, FASTDIV>(ld_stream(in + f), p, mine, bad);
+            if constexpr (STORE) proxy[row * P + x] = (uint8_t)pb;
+        }
+}
+
+// Vector path (VEC 1: row starts 16-byte aligned): 16-byte vectors, stored as
+// one word of proxy bytes at the same voxel offset of the row's proxy.  A
+// wave fills kQhSlots vector slots per step: rows of at most kQhSlots / 2
+// vectors (padded to a power of two) are taken several at a time, longer rows
+// one at a time, so that every lane has kQhBatch loads in flight.
+// VEC 2: the flat path above.  VEC 0 (the volume itself not 16-byte
+// aligned): lane l takes voxels l, l + 64, ... of one row at a time.
+template <typename T, bool CODES, bool FIXED, bool FASTDIV, int VEC, bool STORE>
+__device__ __forceinline__ void qh_rows(const VPart vp, const T* __restrict__ in, int64_t nx, int64_t nrows, int64_t P,
+                                        const QH& p, uint32_t* mine, uint8_t* __restrict__ proxy, bool& bad) {
+    constexpr int VN = VecN<T>::n;
+    constexpr int64_t kQhSlots = (int64_t)kWave * kQhBatch;
+    const int lane = threadIdx.x % kWave;
+    const int64_t wave = ((int64_t)vp.b * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)vp.n * blockDim.x / kWave;
+    if constexpr (VEC == 2) {
+        qh_flat<T, CODES, FIXED, FASTDIV, STORE>(vp, in, nx, nrows, P, p, mine, proxy, bad);
+    } else if constexpr (VEC == 1) {
         const int64_t nv = nx / VN;
         int lg = 0;
         while ((1ll << lg) < nv) ++lg;
@@ -544,8 +611,8 @@ constexpr int kQhBlock = 512;  // 8 waves share one set of LDS histogram copies
 
 // unless_p16: nothing to do when the fused pass has already produced the
 // 16-bit proxy and the histogram
-template <typename T, bool CODES, bool FIXED, bool VEC, bool STORE = true>
-__global__ __launch_bounds__(kQhBlock) void k_quant_hist(const T* __restrict__ in, int64_t nx, int64_t nrows,
+template <typename T, bool CODES, bool FIXED, int VEC, bool STORE = true>
+__device__ __forceinline__ void k_quant_hist_body(const VPart vp, const T* __restrict__ in, int64_t nx, int64_t nrows,
                                                        int64_t P, DevState* S, uint8_t* __restrict__ proxy,
                                                        int unless_p16) {
     __shared__ uint32_t lh[kHistCopies * kHistStride];
@@ -563,9 +630,9 @@ __global__ __launch_bounds__(kQhBlock) void k_quant_hist(const T* __restrict__ i
     uint32_t* mine = lh + (threadIdx.x % kHistCopies) * kHistStride;
     bool bad = false;
     if (p.K <= 65536u)
-        qh_rows<T, CODES, FIXED, true, VEC, STORE>(in, nx, nrows, P, p, mine, proxy, bad);
+        qh_rows<T, CODES, FIXED, true, VEC, STORE>(vp, in, nx, nrows, P, p, mine, proxy, bad);
     else
-        qh_rows<T, CODES, FIXED, false, VEC, STORE>(in, nx, nrows, P, p, mine, proxy, bad);
+        qh_rows<T, CODES, FIXED, false, VEC, STORE>(vp, in, nx, nrows, P, p, mine, proxy, bad);
     if constexpr (CODES) {
         if (bad) fail(S, ROIX_EINVAL);
     }
@@ -578,28 +645,41 @@ __global__ __launch_bounds__(kQhBlock) void k_quant_hist(const T* __restrict__ i
         if (s) atomicAdd(&S->hist[b], (unsigned long long)s);
     }
 }
+template <typename T, bool CODES, bool FIXED, int VEC, bool STORE = true>
+__global__ __launch_bounds__(kQhBlock) void k_quant_hist(const T* __restrict__ in, int64_t nx, int64_t nrows,
+                                                       int64_t P, DevState* S, uint8_t* __restrict__ proxy,
+                                                       int unless_p16) {
+    k_quant_hist_body<T, CODES, FIXED, VEC, STORE>(hw_part(), in, nx, nrows, P, S, proxy, unless_p16);
+}
 
 static dim3 qh_grid(const LaunchCtx& lc, const Geom& g) {
     int64_t blocks = (g.nrows + kQhBlock / kWave - 1) / (kQhBlock / kWave);
-    const int64_t cap = (int64_t)lc.grid_stream / 2;  // 4 workgroups of 512 threads per CU
+    const int64_t cap = (int64_t)(lc.grid_vox > 0 ? lc.grid_vox : lc.grid_stream) / 2;  // 4 of 512 threads per CU
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
     return dim3((unsigned)blocks);
+}
+
+// 1: rows 16-byte aligned; 2: the volume aligned, its rows not; 0: neither
+template <typename T>
+static int qh_path(const void* in, const Geom& g) {
+    if ((uintptr_t)in % 16 != 0) return 0;
+    return (g.nx * (int64_t)sizeof(T)) % 16 == 0 ? 1 : 2;
 }
 
 template <typename T, bool CODES>
 static void qh_dispatch(const LaunchCtx& lc, const void* in, const Geom& g, DevState* S, uint8_t* proxy,
                         bool fixed, int unless_p16) {
     dim3 grid = qh_grid(lc, g), block(kQhBlock);
-    const bool vec = ((uintptr_t)in % 16 == 0) && ((g.nx * (int64_t)sizeof(T)) % 16 == 0);
+    const int vec = qh_path<T>(in, g);
     const int64_t P = g.W * 64;
 #define QH_LAUNCH(F, V)                                                                                        \
-    hipLaunchKernelGGL((k_quant_hist<T, CODES, F, V>), grid, block, 0, lc.stream, (const T*)in, g.nx, g.nrows, P, \
+    launch_k<kQhBlock, k_quant_hist_body<T, CODES, F, V>>(lc, k_quant_hist<T, CODES, F, V>, grid, block, 0, (const T*)in, g.nx, g.nrows, P, \
                        S, proxy, unless_p16)
     if (fixed) {
-        if (vec) QH_LAUNCH(true, true); else QH_LAUNCH(true, false);
+        if (vec == 1) QH_LAUNCH(true, 1); else if (vec == 2) QH_LAUNCH(true, 2); else QH_LAUNCH(true, 0);
     } else {
-        if (vec) QH_LAUNCH(false, true); else QH_LAUNCH(false, false);
+        if (vec == 1) QH_LAUNCH(false, 1); else if (vec == 2) QH_LAUNCH(false, 2); else QH_LAUNCH(false, 0);
     }
 #undef QH_LAUNCH
 }
@@ -620,14 +700,14 @@ hipError_t launch_quant_hist(const LaunchCtx& lc, const void* in, int src_kind, 
 
 template <typename T>
 static void hist_only_launch(const LaunchCtx& lc, const void* in, const Geom& g, DevState* S) {
-    const bool vec = ((uintptr_t)in % 16 == 0) && ((g.nx * (int64_t)sizeof(T)) % 16 == 0);
+    const int vec = qh_path<T>(in, g);
     const int64_t P = g.W * 64;
-    if (vec)
-        hipLaunchKernelGGL((k_quant_hist<T, false, false, true, false>), qh_grid(lc, g), dim3(kQhBlock), 0,
-                           lc.stream, (const T*)in, g.nx, g.nrows, P, S, (uint8_t*)nullptr, 0);
+    if (vec == 1)
+        launch_k<kQhBlock, k_quant_hist_body<T, false, false, 1, false>>(lc, k_quant_hist<T, false, false, 1, false>, qh_grid(lc, g), dim3(kQhBlock), 0, (const T*)in, g.nx, g.nrows, P, S, (uint8_t*)nullptr, 0);
+    else if (vec == 2)
+        launch_k<kQhBlock, k_quant_hist_body<T, false, false, 2, false>>(lc, k_quant_hist<T, false, false, 2, false>, qh_grid(lc, g), dim3(kQhBlock), 0, (const T*)in, g.nx, g.nrows, P, S, (uint8_t*)nullptr, 0);
     else
-        hipLaunchKernelGGL((k_quant_hist<T, false, false, false, false>), qh_grid(lc, g), dim3(kQhBlock), 0,
-                           lc.stream, (const T*)in, g.nx, g.nrows, P, S, (uint8_t*)nullptr, 0);
+        launch_k<kQhBlock, k_quant_hist_body<T, false, false, 0, false>>(lc, k_quant_hist<T, false, false, 0, false>, qh_grid(lc, g), dim3(kQhBlock), 0, (const T*)in, g.nx, g.nrows, P, S, (uint8_t*)nullptr, 0);
 }
 
 hipError_t launch_hist_only(const LaunchCtx& lc, const void* in, roix_dtype dt, const Geom& g, DevState* S) {
@@ -694,7 +774,7 @@ __device__ __forceinline__ uint4 qr_sub(const uint4& a, const uint4& b) {
 // BG: the pass quantises M = I - B, B read from bg (row r of the image takes
 // row r % ny of a plane reference, or row r of a volume reference)
 template <bool BG>
-__global__ __launch_bounds__(kQrThreads) void k_quant_range16(const float* __restrict__ in, int64_t nx, int64_t nrows,
+__device__ __forceinline__ void k_quant_range16_body(const VPart vp, const float* __restrict__ in, int64_t nx, int64_t nrows,
                                                             int64_t P, DevState* S, uint16_t* __restrict__ proxy,
                                                             uint32_t* __restrict__ slots,
                                                             unsigned long long* __restrict__ fine_total,
@@ -703,7 +783,7 @@ __global__ __launch_bounds__(kQrThreads) void k_quant_range16(const float* __res
     for (int i = threadIdx.x; i < kQrFine; i += blockDim.x) fine[i] = 0u;
     // this workgroup's share of the totals the reduce adds into
     for (int i = threadIdx.x; i < kQrFine / kQrBlocks; i += blockDim.x)
-        fine_total[blockIdx.x * (kQrFine / kQrBlocks) + i] = 0ull;
+        fine_total[vp.b * (kQrFine / kQrBlocks) + i] = 0ull;
     if (block_exit(S)) return;  // contains a barrier
     const float r = S->r, w = S->w, eb32 = S->eb32;
     uint32_t lo = 0xFFFFFFFFu, hi = 0u, nf = 0u;
@@ -712,8 +792,8 @@ __global__ __launch_bounds__(kQrThreads) void k_quant_range16(const float* __res
     constexpr int NB = BG ? kQhBatch / 2 : kQhBatch;
     constexpr int64_t kSlots = (int64_t)kWave * NB;
     const int lane = threadIdx.x % kWave;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+    const int64_t wave = ((int64_t)vp.b * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)vp.n * blockDim.x / kWave;
     const int64_t nv = nx / 4;
     int lg = 0;
     while ((1ll << lg) < nv) ++lg;
@@ -816,17 +896,28 @@ __global__ __launch_bounds__(kQrThreads) void k_quant_range16(const float* __res
         if (nf) atomicOr(&S->nonfinite, 1u);
     }
     __syncthreads();
-    uint32_t* mine = slots + (int64_t)blockIdx.x * kQrFine;
+    uint32_t* mine = slots + (int64_t)vp.b * kQrFine;
     for (int i = threadIdx.x; i < kQrFine; i += blockDim.x) mine[i] = fine[i];
+}
+template <bool BG>
+__global__ __launch_bounds__(kQrThreads) void k_quant_range16(const float* __restrict__ in, int64_t nx, int64_t nrows,
+                                                            int64_t P, DevState* S, uint16_t* __restrict__ proxy,
+                                                            uint32_t* __restrict__ slots,
+                                                            unsigned long long* __restrict__ fine_total,
+                                                            const float* __restrict__ bg, int64_t bg_ny) {
+    k_quant_range16_body<BG>(hw_part(), in, nx, nrows, P, S, proxy, slots, fine_total, bg, bg_ny);
 }
 
 // fine[i] += the counts of code class i of kReduceSlots workgroups (grid.y
 // picks the group of slots; fine was cleared by the pass)
 constexpr int kReduceSlots = 32;
-__global__ __launch_bounds__(256) void k_fine_reduce(const uint32_t* __restrict__ slots,
-                                                     unsigned long long* __restrict__ fine) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t* src = slots + (int64_t)blockIdx.y * kReduceSlots * kQrFine + i;
+// workgroup (x, y) of the kQrFine / 256 x kQrBlocks / kReduceSlots grid is
+// workgroup y * (kQrFine / 256) + x of a flat grid
+__device__ __forceinline__ void k_fine_reduce_body(const VPart vp, const uint32_t* __restrict__ slots,
+                                                   unsigned long long* __restrict__ fine) {
+    const uint32_t bx = vp.b % (uint32_t)(kQrFine / 256), by = vp.b / (uint32_t)(kQrFine / 256);
+    const int i = (int)bx * blockDim.x + threadIdx.x;
+    const uint32_t* src = slots + (int64_t)by * kReduceSlots * kQrFine + i;
     uint32_t c[kReduceSlots];
 #pragma unroll
     for (int b = 0; b < kReduceSlots; ++b) c[b] = src[(int64_t)b * kQrFine];
@@ -834,6 +925,10 @@ __global__ __launch_bounds__(256) void k_fine_reduce(const uint32_t* __restrict_
 #pragma unroll
     for (int b = 0; b < kReduceSlots; ++b) s += c[b];
     if (s) atomicAdd(&fine[i], s);
+}
+__global__ __launch_bounds__(256) void k_fine_reduce(const uint32_t* __restrict__ slots,
+                                                     unsigned long long* __restrict__ fine) {
+    k_fine_reduce_body(hw_part(), slots, fine);
 }
 
 // The 256-bin histogram from code-class counts (K <= 2^15): class i holds
@@ -867,7 +962,7 @@ __device__ void hist_from_classes(DevState* S, const unsigned long long* __restr
 
 // The quantiser from the range, then (K <= 2^15) the 256-bin histogram from
 // the class counts.
-__global__ __launch_bounds__(1024) void k_resolve16(DevState* S, double eb_value, int fixed, double fixed_value,
+__device__ __forceinline__ void k_resolve16_body(const VPart vp, DevState* S, double eb_value, int fixed, double fixed_value,
                                                     const unsigned long long* __restrict__ fine) {
     __shared__ unsigned long long sh[256];
     __shared__ int s_ok;
@@ -883,15 +978,19 @@ __global__ __launch_bounds__(1024) void k_resolve16(DevState* S, double eb_value
     if (!s_ok) return;  // uniform
     hist_from_classes(S, fine, sh);
 }
+__global__ __launch_bounds__(1024) void k_resolve16(DevState* S, double eb_value, int fixed, double fixed_value,
+                                                    const unsigned long long* __restrict__ fine) {
+    k_resolve16_body(hw_part(), S, eb_value, fixed, fixed_value, fine);
+}
 
 hipError_t launch_quant_range16(const LaunchCtx& lc, const float* in, const Geom& g, const Layout& L, const BgRef* bg) {
     timer_begin(lc.timer, ST_QR16, lc.stream);
     if (bg)
-        hipLaunchKernelGGL(k_quant_range16<true>, dim3(kQrBlocks), dim3(kQrThreads), 0, lc.stream, in, g.nx, g.nrows,
+        launch_k<kQrThreads, k_quant_range16_body<true>>(lc, k_quant_range16<true>, dim3(kQrBlocks), dim3(kQrThreads), 0, in, g.nx, g.nrows,
                            g.W * 64, L.S, reinterpret_cast<uint16_t*>(L.proxy), L.fine_slots, L.fine_total, bg->bg,
                            bg->plane ? g.ny : (int64_t)0);
     else
-        hipLaunchKernelGGL(k_quant_range16<false>, dim3(kQrBlocks), dim3(kQrThreads), 0, lc.stream, in, g.nx, g.nrows,
+        launch_k<kQrThreads, k_quant_range16_body<false>>(lc, k_quant_range16<false>, dim3(kQrBlocks), dim3(kQrThreads), 0, in, g.nx, g.nrows,
                            g.W * 64, L.S, reinterpret_cast<uint16_t*>(L.proxy), L.fine_slots, L.fine_total,
                            (const float*)nullptr, (int64_t)0);
     timer_end(lc.timer, ST_QR16, lc.stream);
@@ -902,9 +1001,9 @@ hipError_t launch_resolve16(const LaunchCtx& lc, const Layout& L, roix_eb eb, co
     const int fixed = crit && crit->thr == ROIX_THR_FIXED;
     timer_begin(lc.timer, ST_RESOLVE, lc.stream);
     static_assert(kQrBlocks % kReduceSlots == 0 && kQrFine % kQrBlocks == 0, "reduce tiling");
-    hipLaunchKernelGGL(k_fine_reduce, dim3(kQrFine / 256, kQrBlocks / kReduceSlots), dim3(256), 0, lc.stream,
-                       (const uint32_t*)L.fine_slots, L.fine_total);
-    hipLaunchKernelGGL(k_resolve16, dim3(1), dim3(1024), 0, lc.stream, L.S, eb.value, fixed,
+    launch_k<256, k_fine_reduce_body>(lc, k_fine_reduce, dim3((kQrFine / 256) * (kQrBlocks / kReduceSlots)),
+                                      dim3(256), 0, (const uint32_t*)L.fine_slots, L.fine_total);
+    launch_k<1024, k_resolve16_body>(lc, k_resolve16, dim3(1), dim3(1024), 0, L.S, eb.value, fixed,
                        fixed ? crit->fixed_value : 0.0, (const unsigned long long*)L.fine_total);
     timer_end(lc.timer, ST_RESOLVE, lc.stream);
     return hipGetLastError();
@@ -1220,7 +1319,7 @@ hipError_t launch_serve_resolve(const LaunchCtx& lc, DevState* S, double eb_valu
 // (class 0 = bins 0..t), first maximum on ties, splits with an empty class
 // skipped.  Every thread evaluates one split with the same binary64
 // expression and operation order.
-__global__ __launch_bounds__(256) void k_otsu(DevState* S, int fixed) {
+__device__ __forceinline__ void k_otsu_body(const VPart vp, DevState* S, int fixed) {
     __shared__ unsigned long long sh_w[256], sh_s[256];
     __shared__ double sh_v[256];
     __shared__ int sh_t[256];
@@ -1278,10 +1377,13 @@ __global__ __launch_bounds__(256) void k_otsu(DevState* S, int fixed) {
         S->q_thr = (int32_t)((long long)S->qmin + c);
     }
 }
+__global__ __launch_bounds__(256) void k_otsu(DevState* S, int fixed) {
+    k_otsu_body(hw_part(), S, fixed);
+}
 
 hipError_t launch_otsu(const LaunchCtx& lc, DevState* S, bool fixed) {
     timer_begin(lc.timer, ST_OTSU, lc.stream);
-    hipLaunchKernelGGL(k_otsu, dim3(1), dim3(256), 0, lc.stream, S, fixed ? 1 : 0);
+    launch_k<256, k_otsu_body>(lc, k_otsu, dim3(1), dim3(256), 0, S, fixed ? 1 : 0);
     timer_end(lc.timer, ST_OTSU, lc.stream);
     return hipGetLastError();
 }
@@ -1296,7 +1398,7 @@ hipError_t launch_otsu(const LaunchCtx& lc, DevState* S, bool fixed) {
 // that hold the same bin from colliding.
 constexpr int kSliceCopies = 16;
 
-__global__ __launch_bounds__(256) void k_slice_otsu(const uint8_t* __restrict__ proxy, int64_t nx, int64_t ny,
+__device__ __forceinline__ void k_slice_otsu_body(const VPart vp, const uint8_t* __restrict__ proxy, int64_t nx, int64_t ny,
                                                     int64_t nz, int64_t P, DevState* S, int32_t* __restrict__ thr,
                                                     int32_t* __restrict__ slice_thr) {
     __shared__ uint32_t h[256 * kSliceCopies];
@@ -1312,14 +1414,14 @@ __global__ __launch_bounds__(256) void k_slice_otsu(const uint8_t* __restrict__ 
     const int64_t tail = nx % 16;
     const int ln = t % kWave;
     const int64_t wv = t / kWave, nw = 256 / kWave;
-    if (blockIdx.x == 0 && t == 0) {
+    if (vp.b == 0 && t == 0) {
         S->proxy_thr = 127;
         S->q_thr = 0;
         S->otsu_bin = -1;
         S->n_classes = 2;
         atomicOr(&S->flags, ROIX_FLAG_PER_SLICE);
     }
-    for (int64_t z = blockIdx.x; z < nz; z += gridDim.x) {
+    for (int64_t z = vp.b; z < nz; z += vp.n) {
         const uint8_t* base = proxy + z * ny * P;
         for (int i = t; i < 256 * kSliceCopies; i += 256) h[i] = 0u;
         __syncthreads();
@@ -1390,12 +1492,17 @@ __global__ __launch_bounds__(256) void k_slice_otsu(const uint8_t* __restrict__ 
         __syncthreads();  // sh_* are reused by the next slice
     }
 }
+__global__ __launch_bounds__(256) void k_slice_otsu(const uint8_t* __restrict__ proxy, int64_t nx, int64_t ny,
+                                                    int64_t nz, int64_t P, DevState* S, int32_t* __restrict__ thr,
+                                                    int32_t* __restrict__ slice_thr) {
+    k_slice_otsu_body(hw_part(), proxy, nx, ny, nz, P, S, thr, slice_thr);
+}
 
 hipError_t launch_slice_otsu(const LaunchCtx& lc, const Geom& g, const uint8_t* proxy, DevState* S, int32_t* thr,
                              int32_t* slice_thr_out) {
     timer_begin(lc.timer, ST_OTSU, lc.stream);
     const int64_t grid = g.nz < 8192 ? g.nz : 8192;
-    hipLaunchKernelGGL(k_slice_otsu, dim3((unsigned)grid), dim3(256), 0, lc.stream, proxy, g.nx, g.ny, g.nz, g.W * 64,
+    launch_k<256, k_slice_otsu_body>(lc, k_slice_otsu, dim3((unsigned)grid), dim3(256), 0, proxy, g.nx, g.ny, g.nz, g.W * 64,
                        S, thr, slice_thr_out);
     timer_end(lc.timer, ST_OTSU, lc.stream);
     return hipGetLastError();
@@ -1442,7 +1549,7 @@ __device__ __forceinline__ void mo_reduce(double* sv, unsigned long long* sr, in
     }
 }
 
-__global__ __launch_bounds__(256) void k_multi_search(DevState* S, int classes) {
+__device__ __forceinline__ void k_multi_search_body(const VPart vp, DevState* S, int classes) {
     __shared__ unsigned long long P[257], Q[257];
     __shared__ double sv[256];
     __shared__ unsigned long long sr[256];
@@ -1463,7 +1570,7 @@ __global__ __launch_bounds__(256) void k_multi_search(DevState* S, int classes) 
     }
     double best = -1.0;
     unsigned long long rank = ~0ull;
-    const int p = (blockIdx.x % kMoPairBlocks) * blockDim.x + t;
+    const int p = (vp.b % kMoPairBlocks) * blockDim.x + t;
     const int t1 = p / 255, t2 = p % 255;
     if (classes == 3) {
         if (t1 < t2 && t2 < 255) {
@@ -1475,7 +1582,7 @@ __global__ __launch_bounds__(256) void k_multi_search(DevState* S, int classes) 
             }
         }
     } else if (t1 < t2 && t2 < 254) {
-        const int c = blockIdx.x / kMoPairBlocks;
+        const int c = vp.b / kMoPairBlocks;
         const int lo = max(t2 + 1, c * kMoChunk), hi = min(255, (c + 1) * kMoChunk);
         const unsigned long long W0 = P[t1 + 1], W1 = P[t2 + 1] - P[t1 + 1];
         const unsigned long long S0 = Q[t1 + 1], S1 = Q[t2 + 1] - Q[t1 + 1];
@@ -1498,12 +1605,15 @@ __global__ __launch_bounds__(256) void k_multi_search(DevState* S, int classes) 
     __syncthreads();
     mo_reduce(sv, sr, t);
     if (t == 0) {
-        S->mo_val[blockIdx.x] = sv[0];
-        S->mo_rank[blockIdx.x] = sr[0];
+        S->mo_val[vp.b] = sv[0];
+        S->mo_rank[vp.b] = sr[0];
     }
 }
+__global__ __launch_bounds__(256) void k_multi_search(DevState* S, int classes) {
+    k_multi_search_body(hw_part(), S, classes);
+}
 
-__global__ __launch_bounds__(256) void k_multi_pick(DevState* S, int classes, int parts) {
+__device__ __forceinline__ void k_multi_pick_body(const VPart vp, DevState* S, int classes, int parts) {
     __shared__ double sv[256];
     __shared__ unsigned long long sr[256];
     const int t = threadIdx.x;
@@ -1540,6 +1650,9 @@ __global__ __launch_bounds__(256) void k_multi_pick(DevState* S, int classes, in
         S->q_thr = (int32_t)((long long)S->qmin + c);
     }
 }
+__global__ __launch_bounds__(256) void k_multi_pick(DevState* S, int classes, int parts) {
+    k_multi_pick_body(hw_part(), S, classes, parts);
+}
 
 hipError_t launch_threshold(const LaunchCtx& lc, DevState* S, const roix_criterion* crit) {
     if (crit->thr != ROIX_THR_MULTI_OTSU) return launch_otsu(lc, S, crit->thr == ROIX_THR_FIXED);
@@ -1548,8 +1661,8 @@ hipError_t launch_threshold(const LaunchCtx& lc, DevState* S, const roix_criteri
     static_assert(kMoChunks * kMoChunk >= 255, "the chunks cover every t3");
     const int parts = classes == 4 ? kMoParts : kMoPairBlocks;
     timer_begin(lc.timer, ST_OTSU, lc.stream);
-    hipLaunchKernelGGL(k_multi_search, dim3(parts), dim3(256), 0, lc.stream, S, classes);
-    hipLaunchKernelGGL(k_multi_pick, dim3(1), dim3(256), 0, lc.stream, S, classes, parts);
+    launch_k<256, k_multi_search_body>(lc, k_multi_search, dim3(parts), dim3(256), 0, S, classes);
+    launch_k<256, k_multi_pick_body>(lc, k_multi_pick, dim3(1), dim3(256), 0, S, classes, parts);
     timer_end(lc.timer, ST_OTSU, lc.stream);
     return hipGetLastError();
 }

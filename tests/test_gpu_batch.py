@@ -1,6 +1,7 @@
-"""Batched form: many volumes of uneven size in one call must give exactly
-the outputs of separate plain calls -- on every repeat, with eager work in
-between, for every launch parameter, under both quantiser flows (the default
+"""Batched form: many volumes of uneven size in one call (one launch per
+stage for all of them) must give exactly the outputs of separate plain calls
+-- on every repeat, with eager work in between, for every launch parameter
+and arena size, under both quantiser flows (the default
 one, where volumes of at least 2^22 voxels with rows of a multiple of 4 take
 the one-pass 16-bit-proxy flow, and the one-pass flow forced on every float32
 volume with an absolute bound), and for the full 64-volume batch workload
@@ -26,9 +27,10 @@ def _volumes():
     # a uint16 and a cylinder volume make the batch mixed in dtype and criterion
     vols.append(synth.rings2048(nxy=96, nz=9))
     vols.append(synth.cylinder1024(n=80))
-    # volumes of at least 2^22 voxels with rows of a multiple of 4: the
-    # default flow takes the one-pass form on them (16-bit proxy with K <=
-    # 2^15, and its 1-byte fallback with K > 2^15), with outliers
+    # volumes of at least 2^22 voxels with rows of a multiple of 4: plain
+    # calls take the one-pass flow on them by default (16-bit proxy with K <=
+    # 2^15, and its 1-byte fallback with K > 2^15), with outliers; the
+    # "onepass" batches take it too
     big, _ = synth.ellipsoids(256, 96, 192, 2901, n_ell=5)
     vols.append(synth.Workload("256x96x192 f32 ellipsoids eb 1e-4", big, "abs", 1e-4,
                                synth.Criterion("otsu", 0.0, 6, "min_size", 64), None))
@@ -48,6 +50,7 @@ def batch_env(request):
     ctx = roix.Context(0, 3 << 30)
     if request.param == "onepass":
         ctx.set_param("fused16_min_voxels", 0)
+        ctx.set_param("batch_fused16_min_voxels", 0)
     items, plain = [], []
     for w in vols:
         crit = criterion(roix, w.criterion)
@@ -100,20 +103,37 @@ def test_batch_subsets_and_order(batch_env):
             _outputs_equal(items[i][4].collect(), plain[i])
 
 
-@pytest.mark.parametrize("streams,graph", [(1, 1), (2, 0), (3, 1), (8, 1), (8, 0)])
-def test_batch_parameters_do_not_change_outputs(batch_env, streams, graph):
+@pytest.mark.parametrize("group,graph", [(1, 1), (2, 0), (3, 1), (5, 1), (0, 0)])
+def test_batch_parameters_do_not_change_outputs(batch_env, group, graph):
+    # volumes per launch group (1: every volume alone), graph capture or not
     ctx, roix, torch, items, plain = batch_env
-    ctx.set_param("batch_streams", streams)
+    ctx.set_param("batch_group", group)
     ctx.set_param("batch_graph", graph)
-    log(f"[case] batch streams={streams} graph={graph}")
+    log(f"[case] batch group={group} graph={graph}")
     for it in items:
         it[4].stream.zero_()
     ctx.fused_batch(items)
     torch.cuda.synchronize()
     for i, it in enumerate(items):
         _outputs_equal(it[4].collect(), plain[i])
-    ctx.set_param("batch_streams", 4)
+    ctx.set_param("batch_group", 0)
     ctx.set_param("batch_graph", 1)
+
+
+def test_batch_small_arena_splits_into_groups(batch_env):
+    # an arena that holds only a few volumes at a time: the batch runs in
+    # groups, one after another, with the same outputs
+    ctx, roix, torch, items, plain = batch_env
+    need = max(roix.scratch_bytes(roix.dims_of(it[0]), roix.dtype_of(it[0]), it[3]) for it in items)
+    small = roix.Context(0, int(need * 2.5))
+    log("[case] batch in a small arena")
+    for it in items:
+        it[4].stream.zero_()
+    small.fused_batch(items)
+    torch.cuda.synchronize()
+    for i, it in enumerate(items):
+        _outputs_equal(it[4].collect(), plain[i])
+    small.close()
 
 
 def test_batch_rejects_bad_descriptor(batch_env):
@@ -139,8 +159,8 @@ def test_full_batch_workload_equals_plain():
         b = roix.bounds(dims, roix.F32, crit)
         caps = (b["rows"], b["stream_bytes"], min(b["outliers"], 1 << 24), min(b["components"], 1 << 20))
         items.append((t, w.eb_mode, w.eb_value, crit, roix.Outputs("cuda:0", *caps), roix.Outputs("cuda:0", *caps)))
-        need = max(need, roix.scratch_bytes(dims, roix.F32, crit))
-    ctx = roix.Context(0, need * 4)
+        need += roix.scratch_bytes(dims, roix.F32, crit)
+    ctx = roix.Context(0, need + (64 << 20))  # every volume's layout at once: one launch group
     log(f"[case] 64-volume batch, {sum(it[0].numel() for it in items) * 4 / 1e9:.2f} GB")
     for (t, ebm, ebv, crit, _, ref) in items:
         ctx.fused(t, ebm, ebv, crit, ref)
