@@ -935,7 +935,7 @@ def main():
     ap.add_argument("--batch-volumes", type=int, default=64)
     ap.add_argument("--batch-group", type=int, default=0,
                     help="volumes per launch group of the batched path (0: as many as the arena holds)")
-    ap.add_argument("--batch-graph", type=int, default=1, choices=[0, 1],
+    ap.add_argument("--batch-graph", type=int, default=0, choices=[0, 1],
                     help="1: capture the batch into a HIP graph and replay it; 0: launch eagerly")
     args = ap.parse_args()
     if args.pmc_summary:

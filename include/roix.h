@@ -498,7 +498,10 @@ roix_status roix_fused_batch(roix_ctx* ctx, int32_t n, const roix_volume_desc* v
  *                    seg_grid workgroups, at least 2048 each)
  *   "batch_group"    volumes per launch group of roix_fused_batch (0 = as
  *                    many as the arena holds; 1 = one volume at a time)
- *   "batch_graph"    1 = capture/replay batches as a HIP graph, 0 = launch eagerly
+ *   "batch_graph"    1 = capture/replay batches as a HIP graph, 0 = launch
+ *                    directly (default: a batch is about 70 launches, and
+ *                    their direct launch costs less host time than the
+ *                    graph's launch)
  *   "batch_fused16_min_voxels"  as fused16_min_voxels, for the volumes of a
  *                    batch (default 2^26: below it the one-pass flow's
  *                    per-workgroup class tables outweigh its saved read)

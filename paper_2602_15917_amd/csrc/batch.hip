@@ -107,6 +107,15 @@ bool pack(const std::vector<Recorder>& rec, std::vector<Merged>& ms, std::vector
     return true;
 }
 
+}  // namespace
+
+struct BatchPlan {
+    std::vector<uint8_t> key;
+    std::vector<Merged> all;
+};
+
+namespace {
+
 void issue(const std::vector<Merged>& ms, const uint8_t* dblob, hipStream_t s) {
     for (const Merged& m : ms)
         if (m.total)
@@ -124,34 +133,18 @@ roix_status ready(BatchState& b) {
 
 }  // namespace
 
-extern "C" roix_status roix_fused_batch(roix_ctx* ctx, int32_t n, const roix_volume_desc* vols, void* stream_) {
-    if (!ctx || n < 0 || (n > 0 && !vols)) return ROIX_EINVAL;
-    if (n == 0) return ROIX_OK;
-    std::vector<Geom> gs(n);
-    std::vector<int> kind(n);
-    std::vector<size_t> need(n);
-    for (int i = 0; i < n; ++i) {
-        const roix_volume_desc& d = vols[i];
-        if (!d.d_in || !geom_of(d.dims, &gs[i]) || !eb_ok(d.eb) || !crit_ok(&d.crit) || !out_ok(&d.out, true))
-            return ROIX_EINVAL;
-        if (d.dtype != ROIX_F32 && d.dtype != ROIX_U16) return ROIX_EINVAL;
-        if (!aligned(d.d_in, d.dtype == ROIX_F32 ? 4 : 2)) return ROIX_EINVAL;
-        kind[i] = proxy_kind(gs[i], (roix_dtype)d.dtype, ctx->batch_p16_min);
-        need[i] = fixed_bytes(gs[i], kind[i]) + (size_t)worst_runs(gs[i]) * kRunBytes;
-    }
-    // the argument tables live at the end of the arena, from a 256-byte
-    // boundary (the arena's size need not be a multiple of anything)
-    const size_t reserve = round_up(std::min<size_t>(ctx->arena_bytes / 4, (size_t)65536 + (size_t)n * 65536), 256);
-    if (ctx->arena_bytes < reserve + 4096) return ROIX_ENOMEM;
-    const size_t avail = (ctx->arena_bytes - reserve) & ~(size_t)255;
-    uint8_t* const base = (uint8_t*)ctx->arena;
-    uint8_t* const dblob = base + avail;
-    hipStream_t stream = (hipStream_t)stream_;
-    BatchState& b = ctx->batch;
-    if (ready(b) != ROIX_OK) return ROIX_EDEVICE;
-    // the previous batch's table copy has read the host tables
-    if (hipEventSynchronize(b.ev_copy) != hipSuccess) return ROIX_EDEVICE;
+namespace {
 
+// Record, merge and pack the batch into b.plan and the pinned tables.
+roix_status plan_batch(roix_ctx* ctx, int32_t n, const roix_volume_desc* vols, const std::vector<Geom>& gs,
+                       const std::vector<int>& kind, const std::vector<size_t>& need, size_t avail, size_t reserve,
+                       const std::vector<uint8_t>& pkey) {
+    BatchState& b = ctx->batch;
+    uint8_t* const base = (uint8_t*)ctx->arena;
+    hipStream_t stream = nullptr;  // recording launches nothing
+    auto plan = std::make_shared<BatchPlan>();
+    std::vector<Merged>& all = plan->all;
+    std::vector<uint8_t> blob;
     // groups of consecutive volumes whose worst-case layouts fit the arena
     // together (a volume too large for that gets the whole arena alone)
     std::vector<std::pair<int, int>> groups;
@@ -167,9 +160,6 @@ extern "C" roix_status roix_fused_batch(roix_ctx* ctx, int32_t n, const roix_vol
         i = j;
     }
 
-    std::vector<Merged> all;
-    std::vector<uint8_t>& blob = b.host;
-    blob.clear();
     for (const auto& gr : groups) {
         const int i0 = gr.first, i1 = gr.second;
         double tot = 0.0;
@@ -210,10 +200,11 @@ extern "C" roix_status roix_fused_batch(roix_ctx* ctx, int32_t n, const roix_vol
         all.insert(all.end(), ms.begin(), ms.end());
     }
     if (blob.size() > reserve) return ROIX_ENOMEM;
-
     // the tables go through pinned memory: an asynchronous copy from
     // pageable memory may have the runtime pin the caller's pages, which a
-    // host can refuse (the copy would then not happen)
+    // host can refuse (the copy would then not happen); the previous copy
+    // must have read the buffer before it changes
+    if (hipEventSynchronize(b.ev_copy) != hipSuccess) return ROIX_EDEVICE;
     if (b.pinned_cap < blob.size()) {
         if (b.pinned) hipHostFree(b.pinned);
         b.pinned = nullptr;
@@ -221,12 +212,64 @@ extern "C" roix_status roix_fused_batch(roix_ctx* ctx, int32_t n, const roix_vol
         const size_t cap = round_up(std::max<size_t>(blob.size(), (size_t)1 << 20), (size_t)1 << 16);
         if (hipHostMalloc((void**)&b.pinned, cap, hipHostMallocDefault) != hipSuccess) {
             b.pinned = nullptr;
+            b.plan.reset();
             return ROIX_ENOMEM;
         }
         b.pinned_cap = cap;
     }
     memcpy(b.pinned, blob.data(), blob.size());
-    ROIX_TRY(hipMemcpyAsync(dblob, b.pinned, blob.size(), hipMemcpyHostToDevice, stream));
+    b.pinned_bytes = blob.size();
+    plan->key = pkey;
+    b.plan = plan;
+    return ROIX_OK;
+}
+
+}  // namespace
+
+extern "C" roix_status roix_fused_batch(roix_ctx* ctx, int32_t n, const roix_volume_desc* vols, void* stream_) {
+    if (!ctx || n < 0 || (n > 0 && !vols)) return ROIX_EINVAL;
+    if (n == 0) return ROIX_OK;
+    std::vector<Geom> gs(n);
+    std::vector<int> kind(n);
+    std::vector<size_t> need(n);
+    for (int i = 0; i < n; ++i) {
+        const roix_volume_desc& d = vols[i];
+        if (!d.d_in || !geom_of(d.dims, &gs[i]) || !eb_ok(d.eb) || !crit_ok(&d.crit) || !out_ok(&d.out, true))
+            return ROIX_EINVAL;
+        if (d.dtype != ROIX_F32 && d.dtype != ROIX_U16) return ROIX_EINVAL;
+        if (!aligned(d.d_in, d.dtype == ROIX_F32 ? 4 : 2)) return ROIX_EINVAL;
+        kind[i] = proxy_kind(gs[i], (roix_dtype)d.dtype, ctx->batch_p16_min);
+        need[i] = fixed_bytes(gs[i], kind[i]) + (size_t)worst_runs(gs[i]) * kRunBytes;
+    }
+    // the argument tables live at the end of the arena, from a 256-byte
+    // boundary (the arena's size need not be a multiple of anything)
+    const size_t reserve = round_up(std::min<size_t>(ctx->arena_bytes / 4, (size_t)65536 + (size_t)n * 65536), 256);
+    if (ctx->arena_bytes < reserve + 4096) return ROIX_ENOMEM;
+    const size_t avail = (ctx->arena_bytes - reserve) & ~(size_t)255;
+    uint8_t* const base = (uint8_t*)ctx->arena;
+    uint8_t* const dblob = base + avail;
+    hipStream_t stream = (hipStream_t)stream_;
+    BatchState& b = ctx->batch;
+    if (ready(b) != ROIX_OK) return ROIX_EDEVICE;
+    // the tables depend only on the descriptors, the arena and the parameters
+    std::vector<uint8_t> pkey;
+    {
+        auto put = [&](const void* p, size_t k) { pkey.insert(pkey.end(), (const uint8_t*)p, (const uint8_t*)p + k); };
+        put(vols, sizeof(roix_volume_desc) * (size_t)n);
+        const int64_t prm[12] = {(int64_t)(uintptr_t)ctx->arena, (int64_t)ctx->arena_bytes, ctx->grid_stream,
+                                 ctx->grid_read, ctx->grid_emit, ctx->grid_mask, ctx->seg_grid, ctx->seg_runs,
+                                 ctx->stats_grid, (int64_t)ctx->p16_min, (int64_t)ctx->batch_p16_min,
+                                 ctx->batch_group};
+        put(prm, sizeof prm);
+    }
+    if (!b.plan || b.plan->key != pkey) {
+        const roix_status st = plan_batch(ctx, n, vols, gs, kind, need, avail, reserve, pkey);
+        if (st != ROIX_OK) return st;
+    }
+    const std::vector<Merged>& all = b.plan->all;
+    // the tables go to the device on every call: plain calls between two
+    // batches may have used the end of the arena
+    ROIX_TRY(hipMemcpyAsync(dblob, b.pinned, b.pinned_bytes, hipMemcpyHostToDevice, stream));
     ROIX_TRY(hipEventRecord(b.ev_copy, stream));
     if (!ctx->batch_graph) {
         issue(all, dblob, stream);

@@ -3,6 +3,7 @@
 // sequences that the plain, batched and streamed forms have in common.
 #pragma once
 
+#include <memory>
 #include <vector>
 
 #include "common.h"
@@ -39,10 +40,12 @@ struct Timer {
 struct BatchState {
     hipStream_t origin = nullptr;  // the graph is captured and launched here
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    std::vector<uint8_t> host;       // the argument tables, built here
-    uint8_t* pinned = nullptr;       // and copied to the device from this pinned buffer
-    size_t pinned_cap = 0;
+    uint8_t* pinned = nullptr;       // the argument tables, copied to the device from here
+    size_t pinned_cap = 0, pinned_bytes = 0;
     hipEvent_t ev_copy = nullptr;    // that copy has read `pinned`
+    // the last batch's merged launches, kept while its descriptors and the
+    // context's parameters stay the same (then the tables are too)
+    std::shared_ptr<struct BatchPlan> plan;
     std::vector<uint8_t> key;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -67,7 +70,7 @@ struct roix_ctx {
     // smallest float32 volume a batch quantises in one pass: below this the
     // per-workgroup class tables of that pass cost more than a second read
     uint64_t batch_p16_min = 1ull << 26;
-    int batch_graph = 1;
+    int batch_graph = 0;  // 1: replay batches as a HIP graph (slower to launch than the ~70 direct launches here)
     BatchState batch;
 };
 
