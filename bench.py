@@ -102,6 +102,27 @@ def pmc_summary(fetch_csv, write_csv, kt_csv):
             print(f"stage {st} {f:.6g} {sum(wv) / len(wv) * sw:.6g} {source_sha(st)}")
 
 
+def pmc_table(csvs):
+    """Per-kernel averages (per dispatch) of every counter in rocprofv3 --pmc
+    CSV files, for the library's kernels; with the LDS counters, the share
+    of LDS-active cycles stalled by bank conflicts."""
+    import csv
+    import re
+    acc = {}
+    for fn in csvs:
+        for r in csv.DictReader(open(fn)):
+            k = re.sub(r"\(.*", "", r["Kernel_Name"]).replace("void ", "").replace("roix::", "")
+            if not k.startswith("k_"):
+                continue
+            acc.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    for k in sorted(acc):
+        cs = {c: sum(v) / len(v) for c, v in acc[k].items()}
+        extra = ""
+        if cs.get("SQ_LDS_IDX_ACTIVE"):
+            extra = f" conflict_share={cs.get('SQ_LDS_BANK_CONFLICT', 0.0) / cs['SQ_LDS_IDX_ACTIVE']:.3f}"
+        print(f"kernel {k.replace(' ', '')} " + " ".join(f"{c}={v:.4g}" for c, v in sorted(cs.items())) + extra)
+
+
 def algorithmic_bytes(stage, N, s, n_codes, code_bytes, n_rows, nrows_all, W, p16):
     """Bytes a launch of `stage` must move at minimum (per call of the path).
     p16: the call took the one-pass flow with the 16-bit code proxy."""
@@ -903,6 +924,8 @@ def main():
     ap.add_argument("--no-stage-timing", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain device copy of 1 GiB (the counter calibration for traffic)")
+    ap.add_argument("--pmc-table", nargs="+", metavar="COUNTER_CSV",
+                    help="print per-kernel averages of the counters in rocprofv3 --pmc CSV files and exit")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL_STATS_CSV"),
                     help="summarise rocprofv3 counter runs of this script and exit")
     ap.add_argument("--workload", choices=["plain", "batched", "served", "decode", "background", "absq", "huffman"], default="plain",
@@ -940,6 +963,9 @@ def main():
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary)
+        return
+    if args.pmc_table:
+        pmc_table(args.pmc_table)
         return
     if args.workload in ("batched", "served"):
         r = section_batched(args) if args.workload == "batched" else section_served(args)
