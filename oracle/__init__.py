@@ -95,6 +95,8 @@ def _load():
         lib.oracle_background.argtypes = [vp, ci, vp, i64, i64, i64, i64, ci, vp]
         lib.oracle_background.restype = ci
         lib.oracle_abs_quantize.argtypes = [vp, u64, dbl, vp, vp]
+        lib.oracle_section.argtypes = [vp, ci, i64, i64, i64, ctypes.POINTER(Params), vp, u64, vp]
+        lib.oracle_section.restype = ci
         lib.oracle_abs_quantize.restype = ci
         lib.oracle_huff_lengths.argtypes = [vp, vp]
         lib.oracle_huff_lengths.restype = ci
@@ -258,6 +260,18 @@ def background(vol, bg, op="subtract"):
     st = _load().oracle_background(_p(vol), _dt(vol), _p(bg), bg.shape[0], nx, ny, nz,
                                    {"subtract": 0, "add": 1}[op], _p(out))
     return st, out
+
+
+def section(vol, p, row_table, n_codes):
+    """The normalised 8-bit pixel section of an extraction (Sec. 4.1.2, Eq. 1):
+    bin(q) of every span voxel in stream order.  Returns (status, uint8[n_codes])."""
+    vol = np.ascontiguousarray(vol)
+    nz, ny, nx = vol.shape
+    rt = np.ascontiguousarray(row_table, dtype=ROW_DTYPE)
+    out = np.zeros(max(int(n_codes), 1), np.uint8)
+    st = _load().oracle_section(_p(vol), _dt(vol), nx, ny, nz, ctypes.byref(p), _p(rt) if rt.size else None,
+                                len(rt), _p(out))
+    return st, out[:int(n_codes)]
 
 
 def abs_quantize(pixels, e_abs):

@@ -41,6 +41,8 @@
  *   background   background subtraction M = I - B of Sec. 4.1.1 (B a
  *                calibration plane or volume), and M + B to put a decoded
  *                volume back on its background
+ *   section      the normalised 8-bit pixel section of the extraction (Sec.
+ *                4.1.2, Eq. 1): the histogram level of every span voxel's code
  *   abs_quantize the paper's own absolute error-bounded quantisation of an
  *                8-bit pixel sequence (Sec. 4.2.3): the longest runs whose
  *                largest and smallest pixel differ by at most 2E, each
@@ -554,6 +556,30 @@ int oracle_stream(const void* in, int dtype, int64_t nx, int64_t ny, const or_pa
     *n_codes = nc;
     *n_outliers = no;
     if (nc * (uint64_t)bytes > stream_cap_bytes || no > outliers_cap) return OR_ETRUNC;
+    return OR_OK;
+}
+
+/* The normalised pixel section (Sec. 4.1.2, Eq. 1, feeding Sec. 4.2.3): the
+ * 8-bit level of every voxel of every span, in the stream's order (rows in
+ * table order, x from xs to xe - 1).  Eq. 1 scales intensities to 0..255; with
+ * the minimum subtracted (reading R4) a voxel's level is the histogram bin of
+ * its code, bin(q) = floor(256 (q - qmin) / K), computed exactly in integers,
+ * so the section holds the levels the threshold was taken on.  The code is
+ * the voxel's own q(x), escaped or not.  out receives n_codes bytes
+ * (rows[i].code_off + x - xs).  Returns the quantiser status, or OR_EINVAL
+ * for a row outside the volume. */
+int oracle_section(const void* in, int dtype, int64_t nx, int64_t ny, int64_t nz, const or_params* p,
+                   const or_row* rows, uint64_t n_rows, uint8_t* out) {
+    if (p->status != OR_OK) return p->status;
+    for (uint64_t i = 0; i < n_rows; ++i) {
+        const or_row* r = &rows[i];
+        if (r->z >= (uint64_t)nz || r->y >= (uint64_t)ny || r->xe > (uint64_t)nx || r->xs >= r->xe) return OR_EINVAL;
+        const uint64_t base = ((uint64_t)r->z * (uint64_t)ny + r->y) * (uint64_t)nx;
+        for (uint32_t x = r->xs; x < r->xe; ++x) {
+            const float v = voxel(in, dtype, base + x);
+            out[r->code_off + (x - r->xs)] = (uint8_t)bin_of(code_of(v, p), p);
+        }
+    }
     return OR_OK;
 }
 

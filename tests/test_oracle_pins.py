@@ -809,3 +809,72 @@ def test_per_slice_threshold():
     vol[2] = 0.5
     s = oracle.fused(vol, "abs", 1e-3, "otsu_slice", 0.0, 6, "min_size", 1)
     assert s["slice_thr"][2] == 255 and s["info"].flags & oracle.FLAG_DEGENERATE
+
+
+def _span_voxels(vol, rt):
+    """Values of every span voxel in stream order (numpy, independent of the oracle's loops)."""
+    parts = [vol[r["z"], r["y"], r["xs"]:r["xe"]] for r in rt]
+    return np.concatenate(parts) if parts else np.zeros(0, vol.dtype)
+
+
+def test_section_closed_form_on_grid_points():
+    # eb = 2^-10: x = k w gives q = k exactly, so each level is
+    # floor(256 (k - qmin) / K) in integers; one FIXED split keeping all
+    # voxels of a solid block makes every row one span
+    nz, ny, nx = 3, 4, 50
+    k = np.arange(nz * ny * nx, dtype=np.int64).reshape(nz, ny, nx) % 997 + 100
+    vol = (k.astype(np.float64) / 512.0).astype(np.float32)
+    r = oracle.fused(vol, "abs", 2.0 ** -10, "fixed", 0.0, 6, "largest", 1)
+    p, info = r["params"], r["info"]
+    assert info.n_codes == vol.size and p.qmin == int(k.min()) and p.K == int(k.max() - k.min() + 1)
+    st, sec = oracle.section(vol, p, r["rows"], info.n_codes)
+    assert st == 0
+    want = np.array([(256 * (int(q) - p.qmin)) // p.K for q in k.reshape(-1)], np.uint8)
+    assert np.array_equal(sec, want)
+    assert sec.min() == 0 and sec.max() == 255
+
+
+def test_section_agrees_with_the_stream_and_the_threshold():
+    # every non-escaped code u of the stream gives the level 256 u // K; the
+    # level of a voxel of the kept object is above the Otsu split and that of
+    # a voxel outside the mask is not (mask <=> bin > t*)
+    w = synth.ellipsoids128()
+    c = w.criterion
+    r = oracle.fused(w.volume, "abs", 2e-5, c.thr, 0.0, c.connectivity, c.keep, c.min_size)
+    p, info, rt = r["params"], r["info"], r["rows"]
+    assert info.n_outliers > 0 and p.width_bits == 16
+    st, sec = oracle.section(w.volume, p, rt, info.n_codes)
+    assert st == 0 and len(sec) == info.n_codes
+    u = np.frombuffer(r["stream"].tobytes(), np.uint16).astype(np.int64)
+    plain = u != p.esc
+    assert np.array_equal(sec[plain].astype(np.int64), (256 * u[plain]) // p.K)
+    # the escaped voxels: their own codes, from the values
+    x = _span_voxels(w.volume, rt)
+    st, q, _, _ = oracle.quantize(x[~plain], p)
+    assert np.array_equal(sec[~plain].astype(np.int64), (256 * (q.astype(np.int64) - p.qmin)) // p.K)
+    st, qa, _, _ = oracle.quantize(w.volume, p)
+    mask = qa >= info.q_thr
+    st, labels, keep, _ = oracle.label(mask.astype(np.uint8), c.connectivity, c.keep, c.min_size)
+    ks = _span_voxels(keep, rt).astype(bool)
+    ms = _span_voxels(mask, rt).astype(bool)
+    assert ks.any() and (~ms).any()
+    assert np.all(sec[ks] > info.otsu_bin) and np.all(sec[~ms] <= info.otsu_bin)
+
+
+def test_section_covering_every_voxel_has_the_histogram():
+    # spans over whole rows: the levels' counts are the 256-bin histogram
+    vol = synth.normal((6, 9, 40), 4242, 0.5, 0.1)
+    r = oracle.fused(vol, "abs", 1e-3, "fixed", -1.0, 26, "largest", 1)
+    p, info = r["params"], r["info"]
+    assert info.n_codes == vol.size
+    st, sec = oracle.section(vol, p, r["rows"], info.n_codes)
+    assert np.array_equal(np.bincount(sec, minlength=256).astype(np.uint64), r["hist"])
+
+
+def test_section_refuses_rows_outside_the_volume():
+    vol = synth.normal((2, 3, 8), 7, 0.5, 0.1)
+    r = oracle.fused(vol, "abs", 1e-3, "fixed", -1.0, 6, "largest", 1)
+    rt = r["rows"].copy()
+    rt[0]["xe"] = 9
+    st, _ = oracle.section(vol, r["params"], rt, r["info"].n_codes)
+    assert st == oracle.EINVAL
