@@ -369,6 +369,35 @@ roix_status roix_fused_background(roix_ctx* ctx, const float* d_in, roix_dims di
                                   int64_t bg_planes, roix_eb eb, const roix_criterion* crit,
                                   const roix_fused_out* out, float* d_work, void* stream);
 
+/* The normalised 8-bit pixel section of an extraction (Sec. 4.1.2, Eq. 1,
+ * which maps each voxel onto 0..255 with the volume's own range): for span
+ * voxel i of a completed roix_fused (or roix_extract) call, in the order of
+ * its code stream, section[i] = floor(256 (q - qmin) / K), the voxel's
+ * quantisation code q put on the 256 levels of the threshold histogram (so
+ * a kept voxel's level is above otsu_bin and a masked-out voxel's is not).
+ * This is the 8-bit sequence the paper's quantiser (roix_abs_quantize) takes.
+ * The levels come from the stored codes (u = q - qmin); an escaped code's
+ * voxel is read from d_in, found through the row table, and requantised.
+ *   d_in       the volume the extraction was made from (dims, dtype as there)
+ *   out        that call's outputs: d_qinfo, d_einfo, d_rows (rows_cap) and
+ *              d_stream (stream_cap_bytes, 16-byte aligned) are read
+ *   d_section  out: section_cap bytes, 16-byte aligned; n_codes are written
+ *   d_info     device: status, n_codes
+ * info.status: the extraction's own error if it had one (nothing written),
+ * ROIX_ETRUNC when n_codes > section_cap (nothing written), ROIX_EINVAL when
+ * the row table or the stream is not whole or does not cover every code.
+ * Needs no arena.  Asynchronous on `stream`.
+ * Errors: ROIX_EINVAL (NULL ctx/out/d_info/info pointers, bad dims or dtype,
+ * misaligned buffers, negative capacity), ROIX_EDEVICE. */
+typedef struct {
+    int32_t status;
+    int32_t pad;
+    uint64_t n_codes;
+} roix_section_info; /* 16 bytes */
+roix_status roix_section(roix_ctx* ctx, const void* d_in, roix_dtype dtype, roix_dims dims,
+                         const roix_fused_out* out, uint8_t* d_section, int64_t section_cap,
+                         roix_section_info* d_info, void* stream);
+
 /* Absolute error-bounded quantisation of an 8-bit pixel sequence, the
  * paper's own algorithm (Sec. 4.2.3): a group grows pixel by
  * pixel while the intervals [D - E, D + E] of its pixels intersect, and

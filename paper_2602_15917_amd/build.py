@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libroix.so")
-SOURCES = ["api.hip", "serve.hip", "k_quant.hip", "k_scan.hip", "k_label.hip", "k_extract.hip", "k_decode.hip", "k_background.hip", "k_absq.hip", "k_huff.hip", "tune.hip", "noalloc.hip", "batch.hip"]
+SOURCES = ["api.hip", "serve.hip", "k_quant.hip", "k_scan.hip", "k_label.hip", "k_extract.hip", "k_decode.hip", "k_background.hip", "k_absq.hip", "k_huff.hip", "tune.hip", "noalloc.hip", "batch.hip", "k_section.hip"]
 ARCH = os.environ.get("ROIX_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

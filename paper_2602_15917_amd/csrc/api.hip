@@ -31,7 +31,7 @@ void timer_end(Timer* t, int stage, hipStream_t s) {
 
 static const char* kStageNames[ST_COUNT] = {
     "init", "range", "resolve", "quantize", "quant_hist", "quant_range16", "otsu", "mask_runs", "scan", "runs_write",
-    "union", "flatten", "comp_stats", "keep", "spans", "emit", "emit_rows", "voxel_out", "finalize", "decode_index", "decode", "background", "abs_quantize", "huffman"};
+    "union", "flatten", "comp_stats", "keep", "spans", "emit", "emit_rows", "voxel_out", "finalize", "decode_index", "decode", "background", "abs_quantize", "huffman", "section"};
 
 }  // namespace roix
 
@@ -588,6 +588,22 @@ roix_status roix_abs_quantize(roix_ctx* ctx, const uint8_t* d_pixels, int64_t m,
     const double ef = e_abs >= 1024.0 ? 1024.0 : floor(e_abs);
     const uint32_t K = 2.0 * ef >= 255.0 ? 255u : (uint32_t)(2.0 * ef);
     ROIX_TRY(launch_absq(lctx(ctx, stream), d_pixels, m, K, d_q, ctx->arena, d_info));
+    return ROIX_OK;
+}
+
+roix_status roix_section(roix_ctx* ctx, const void* d_in, roix_dtype dtype, roix_dims dims,
+                         const roix_fused_out* out, uint8_t* d_section, int64_t section_cap,
+                         roix_section_info* d_info, void* stream) {
+    Geom g;
+    if (!ctx || !d_in || !out || !d_info || !geom_of(dims, &g) || section_cap < 0) return ROIX_EINVAL;
+    if (dtype != ROIX_F32 && dtype != ROIX_U16) return ROIX_EINVAL;
+    if (!aligned(d_in, dtype == ROIX_F32 ? 4 : 2) || !aligned(d_info, 8)) return ROIX_EINVAL;
+    if (!out->d_qinfo || !out->d_einfo || !aligned(out->d_qinfo, 8) || !aligned(out->d_einfo, 8)) return ROIX_EINVAL;
+    if (out->rows_cap < 0 || out->stream_cap_bytes < 0) return ROIX_EINVAL;
+    if (out->rows_cap > 0 && (!out->d_rows || !aligned(out->d_rows, 8))) return ROIX_EINVAL;
+    if (out->stream_cap_bytes > 0 && (!out->d_stream || !aligned(out->d_stream, 16))) return ROIX_EINVAL;
+    if (section_cap > 0 && (!d_section || !aligned(d_section, 16))) return ROIX_EINVAL;
+    ROIX_TRY(launch_section(lctx(ctx, stream), d_in, dtype, g, out, d_section, section_cap, d_info));
     return ROIX_OK;
 }
 

@@ -148,13 +148,14 @@ def load():
                                   P(TuneResult), vp]
     lib.roix_huff_decode.argtypes = [vp, vp, vp, vp, i64, i64, vp, vp, vp]
     lib.roix_abs_quantize_scratch_bytes.argtypes = [i64]
+    lib.roix_section.argtypes = [vp, vp, ci, Dims, P(FusedOut), vp, i64, vp, vp]
     lib.roix_abs_quantize_scratch_bytes.restype = sz
     for f in ("roix_ctx_create", "roix_ctx_destroy", "roix_bounds", "roix_quantize", "roix_segment",
               "roix_extract", "roix_fused", "roix_fused_noalloc", "roix_ctx_set_timing", "roix_ctx_read_timing", "roix_fused_batch",
               "roix_ctx_set_param", "roix_ctx_get_param", "roix_server_create", "roix_server_destroy",
               "roix_volume_open", "roix_slab_submit", "roix_volume_close", "roix_volume_abort", "roix_wait",
               "roix_server_stats", "roix_decode", "roix_background", "roix_fused_background", "roix_abs_quantize",
-              "roix_huff_encode", "roix_huff_decode", "roix_autotune"):
+              "roix_huff_encode", "roix_huff_decode", "roix_autotune", "roix_section"):
         getattr(lib, f).restype = ci
     _lib = lib
     return lib
@@ -245,6 +246,10 @@ def absq_info(info: torch.Tensor) -> "AbsqInfo":
     return _info(info, AbsqInfo)
 
 
+def section_info(info: torch.Tensor) -> "SectionInfo":
+    return _info(info, SectionInfo)
+
+
 def huff_info(info: torch.Tensor) -> "HuffInfo":
     return _info(info, HuffInfo)
 
@@ -321,6 +326,10 @@ class TuneResult(ctypes.Structure):
 
 
 TUNE_PARAMS = ("grid_stream", "grid_read", "grid_mask", "grid_emit", "seg_grid", "stats_grid", "seg_runs")
+
+
+class SectionInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("pad", ctypes.c_int32), ("n_codes", ctypes.c_uint64)]
 
 
 class AbsqInfo(ctypes.Structure):
@@ -420,6 +429,20 @@ class Context:
                                           ctypes.byref(c), ctypes.byref(out.c), _ptr(work), _stream(stream))
         _check(st, "roix_fused_background")
         return work
+
+    def section(self, vol: torch.Tensor, out: Outputs, dst: torch.Tensor | None = None,
+                info: torch.Tensor | None = None, stream=None):
+        """Enqueue the normalised 8-bit pixel section of the extraction in
+        `out`, made from `vol`.  Returns (section, info); the section holds
+        info.n_codes levels (dst defaults to the stream's capacity)."""
+        if dst is None:
+            dst = torch.empty(max(out.caps[1], 16), dtype=torch.uint8, device=vol.device)
+        if info is None:
+            info = torch.zeros(ctypes.sizeof(SectionInfo), dtype=torch.uint8, device=vol.device)
+        st = load().roix_section(self.h, _ptr(vol), dtype_of(vol), dims_of(vol), ctypes.byref(out.c), _ptr(dst),
+                                 dst.numel(), _ptr(info), _stream(stream))
+        _check(st, "roix_section")
+        return dst, info
 
     def abs_quantize(self, pixels: torch.Tensor, e_abs: float, dst: torch.Tensor | None = None,
                      info: torch.Tensor | None = None, stream=None):

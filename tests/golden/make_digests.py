@@ -22,6 +22,7 @@ import numpy as np  # noqa: E402
 import oracle  # noqa: E402
 import synth  # noqa: E402
 
+ABSQ_E = (2.0, 1.0, 5.0)
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "digests.json")
 
 
@@ -36,6 +37,13 @@ def digest(name, w):
                      comps_cap=1 << 20)
     dt = time.time() - t
     i, p = r["info"], r["params"]
+    # the Eq. 1 normalised 8-bit section of the extracted spans, and the
+    # paper's quantiser (Sec. 4.2.3) on it at the benchmark's tolerances
+    sst, sec = oracle.section(w.volume, p, r["rows"], i.n_codes)
+    absq = {}
+    for e in ABSQ_E:
+        ast, q, ng = oracle.abs_quantize(sec, e)
+        absq[repr(e)] = {"status": ast, "n_groups": int(ng), "sha256": sha(q)}
     return {
         "workload": w.name,
         "input_sha256": w.sha256(),
@@ -51,6 +59,9 @@ def digest(name, w):
                     "stream_bytes": i.stream_bytes},
         "sha256": {"rows": sha(r["rows"]), "stream": sha(r["stream"]), "outliers": sha(r["outliers"]),
                    "comps": sha(r["comps"])},
+        "section": {"status": sst, "n": int(len(sec)), "sha256": sha(sec),
+                    "level_counts_sha256": sha(np.bincount(sec, minlength=256).astype(np.uint64))},
+        "absq_on_section": absq,
     }
 
 

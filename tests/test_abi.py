@@ -99,6 +99,18 @@ def test_sync_argument_errors(lib):
     assert L.roix_decode(null, null, 0, null, 0, null, 0, null, null, d, 0.0, null, null, null) == roix.EINVAL
     assert L.roix_background(null, null, roix.F32, d, null, 1, 0, null, null) == roix.EINVAL
     assert L.roix_abs_quantize(null, null, 0, 1.0, null, null, null) == roix.EINVAL
+    # section: checked before any device call (a non-null stand-in context)
+    assert L.roix_section(null, fake, roix.F32, d, ctypes.byref(out), fake, 16, fake, null) == roix.EINVAL
+    so = roix.FusedOut(0, 0, 0, 64, 0, 0, 0, 0, 1 << 20, 0, 1 << 21, None)
+    assert L.roix_section(fake, fake, roix.F32, d, ctypes.byref(so), fake, 16, fake, null) == roix.EINVAL  # stream
+    so = roix.FusedOut(0, 0, 1 << 20, 64, 0, 0, 0, 0, 0, 0, 1 << 21, None)
+    assert L.roix_section(fake, fake, roix.F32, d, ctypes.byref(so), fake, 16, fake, null) == roix.EINVAL  # qinfo
+    so = roix.FusedOut(0, 0, (1 << 20) + 4, 64, 0, 0, 0, 0, 1 << 20, 0, 1 << 21, None)
+    assert L.roix_section(fake, fake, roix.F32, d, ctypes.byref(so), fake, 16, fake, null) == roix.EINVAL  # align
+    so = roix.FusedOut(0, 0, 1 << 20, 64, 0, 0, 0, 0, 1 << 20, 0, 1 << 21, None)
+    assert L.roix_section(fake, fake, roix.F32, d, ctypes.byref(so), (1 << 20) + 8, 16, fake, null) == roix.EINVAL
+    assert L.roix_section(fake, fake, roix.F32, d, ctypes.byref(so), fake, -1, fake, null) == roix.EINVAL
+    assert L.roix_section(fake, fake, 7, d, ctypes.byref(so), fake, 16, fake, null) == roix.EINVAL
     assert L.roix_huff_encode(null, null, 0, null, null, null, 0, null, null) == roix.EINVAL
     assert L.roix_huff_decode(null, null, null, null, 0, 0, null, null, null) == roix.EINVAL
     assert L.roix_autotune(null, null, roix.F32, d, eb, ctypes.byref(c), ctypes.byref(out), 1, None,

@@ -1,7 +1,8 @@
 """Full-size parity: the benchmark workload (1024^3 float32) and the 8 GB
 uint16 stack (2048 x 2048 x 1024) through the fused C-ABI call, in the launch
 configuration the benchmark times, compared bit-exactly with the CPU oracle
-through SHA-256 digests of every output section.  The digests are written by
+through SHA-256 digests of every output section; then the Eq. 1 normalised
+8-bit pixel section of the same extraction and the paper's quantiser on it.  The digests are written by
 tests/golden/make_digests.py, which runs only the oracle."""
 import hashlib
 import json
@@ -45,6 +46,28 @@ def test_fullsize_digests(name):
     ctx.fused(x, w.eb_mode, w.eb_value, crit, out)
     torch.cuda.synchronize()
     g = out.collect()
+    gsec = gold.get("section")
+    if gsec is not None:
+        # the Eq. 1 normalised section of the same extraction, and the
+        # paper's quantiser on it
+        log(f"[case] full-size {name}: section")
+        n = int(g["einfo"].n_codes)
+        sec, sinfo = ctx.section(x, out, torch.empty(n + 16, dtype=torch.uint8, device="cuda:0"))
+        torch.cuda.synchronize()
+        si = roix.section_info(sinfo)
+        assert (si.status, si.n_codes) == (gsec["status"], gsec["n"])
+        px = sec[:n]
+        assert sha(px.cpu().numpy()) == gsec["sha256"], "section"
+        ac = roix.Context(0, roix.abs_quantize_scratch_bytes(n))
+        for e, ga in gold["absq_on_section"].items():
+            log(f"[case] full-size {name}: abs_quantize on the section, E = {e}")
+            q, qi = ac.abs_quantize(px, float(e))
+            torch.cuda.synchronize()
+            a = roix.absq_info(qi)
+            assert (a.status, a.n_groups) == (ga["status"], ga["n_groups"]), e
+            assert sha(q.cpu().numpy()) == ga["sha256"], e
+        ac.close()
+        del sec, px
     ctx.close()
     q, s, e = g["qinfo"], g["sinfo"], g["einfo"]
     assert (q.status, s.status, e.status) == (0, 0, 0)
