@@ -153,6 +153,7 @@ LaunchCtx roix::lctx(roix_ctx* c, void* stream) {
     lc.seg_grid = c->seg_grid;
     lc.seg_runs = c->seg_runs;
     lc.stats_grid = c->stats_grid;
+    lc.cus = c->cus;
     return lc;
 }
 
@@ -371,8 +372,10 @@ roix_status roix_ctx_create(int device, size_t scratch_bytes, roix_ctx** out) {
     c->grid_stream = c->cus * 8;
     c->grid_read = c->cus * 4;
     // the emit kernels run best with every wave resident at once (no
-    // second, ragged round); the mask-word kernels with many more
-    c->grid_emit = c->cus * 4;
+    // second, ragged round: the 16-bit-proxy emit kernel holds 6 waves per
+    // SIMD, 6 workgroups of 4 waves per CU); the mask-word kernels with many
+    // more
+    c->grid_emit = c->cus * 6;
     c->grid_mask = c->cus * 32;
     c->seg_grid = c->cus * 2;
     c->stats_grid = c->cus;

@@ -382,6 +382,7 @@ struct LaunchCtx {
     int scan_grid = kScanBlocks;  // chunks of the device-sized scans (at most kScanBlocks)
     int grid_vox = 0;             // quantise + histogram pass (0: grid_stream); a batch scales it
     Recorder* rec = nullptr;      // batch: record the launches instead of making them
+    int cus = 0;                  // compute units of the device (0: unknown)
 };
 
 // Launch kernel `kern` (whose body is Body, block bound LB), or record it.

@@ -59,7 +59,7 @@ struct roix_ctx {
     size_t arena_bytes = 0;
     roix::Timer timer;
     int grid_stream = 2048;
-    int grid_emit = 1024;  // workgroups of the code-emit kernels
+    int grid_emit = 1536;  // workgroups of the code-emit kernels
     int grid_mask = 8192;  // workgroups of the mask-word and run kernels
     int grid_read = 512;
     int seg_grid = 512;

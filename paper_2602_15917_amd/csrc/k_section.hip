@@ -13,8 +13,6 @@
 
 namespace roix {
 
-constexpr int kSecCodes = 16;  // codes per thread and step: one 16-byte store
-
 // The call's status and code count, checked once before the pass.
 __global__ void k_section_check(const roix_quant_info* __restrict__ qi, const roix_extract_info* __restrict__ ei,
                                 int64_t rows_cap, int64_t stream_cap, int64_t out_cap, roix_section_info* info) {
@@ -62,7 +60,7 @@ __device__ __forceinline__ uint32_t sec_level(uint32_t u, const SecParams& p) {
 // The level of the escaped code c: its row is the last one whose first code
 // is at or before c; the voxel is requantised with the call's quantiser.
 template <typename T>
-__device__ uint32_t sec_escape(const T* __restrict__ in, int64_t nx, int64_t ny, int64_t nz,
+__device__ __attribute__((noinline)) uint32_t sec_escape(const T* __restrict__ in, int64_t nx, int64_t ny, int64_t nz,
                                const roix_row* __restrict__ rows, uint64_t nr, uint64_t c, const SecParams& p,
                                roix_section_info* info) {
     if (nr == 0) {
@@ -87,55 +85,90 @@ __device__ uint32_t sec_escape(const T* __restrict__ in, int64_t nx, int64_t ny,
     return lv > 255u ? 255u : lv;  // (only a volume other than the extracted one gives a code outside 0..K-1)
 }
 
-// code i of a 16-byte word group of B-byte codes
+constexpr int kSecCodes = 16;  // codes per unit of work: B 16-byte loads, one 16-byte store
+
+// code i of the B 16-byte loads of a unit
 template <int B>
 __device__ __forceinline__ uint32_t code_at(const uint4 (&w)[B], int i) {
-    const uint32_t word = i * B / 4;
-    const uint32_t v = (word & 3) == 0 ? w[word >> 2].x : (word & 3) == 1 ? w[word >> 2].y
-                     : (word & 3) == 2 ? w[word >> 2].z : w[word >> 2].w;
+    const int word = i * B / 4;
+    const uint4& q = w[word >> 2];
+    const uint32_t v = (word & 3) == 0 ? q.x : (word & 3) == 1 ? q.y : (word & 3) == 2 ? q.z : q.w;
     if (B == 4) return v;
     if (B == 2) return (v >> (16 * (i & 1))) & 0xFFFFu;
     return (v >> (8 * (i & 3))) & 0xFFu;
 }
 
+// The 16 levels of a unit, packed for one 16-byte store (escapes resolved).
+// Every index into the codes is static (the escapes are found through a bit
+// mask), so codes and levels stay in registers.
+template <typename T, int B>
+__device__ __forceinline__ v4u32_t levels16(const uint4 (&w)[B], uint64_t c0, const T* __restrict__ in, int64_t nx,
+                                            int64_t ny, int64_t nz, const roix_row* __restrict__ rows, uint64_t nr,
+                                            const SecParams& p, roix_section_info* info) {
+    uint32_t o[4] = {0u, 0u, 0u, 0u};
+    uint32_t emask = 0;
+#pragma unroll
+    for (int i = 0; i < kSecCodes; ++i) {
+        const uint32_t u = code_at<B>(w, i);
+        emask |= (uint32_t)(u == p.esc) << i;
+        o[i / 4] |= (u == p.esc ? 0u : sec_level(u, p)) << (8 * (i & 3));
+    }
+    while (emask) {
+        const int i = __builtin_ctz(emask);
+        emask &= emask - 1u;
+        const uint32_t sh = 8u * (uint32_t)(i & 3);
+        const uint32_t v = sec_escape(in, nx, ny, nz, rows, nr, c0 + (uint64_t)i, p, info) << sh;
+        const int k = i >> 2;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            if (m == k) o[m] = (o[m] & ~(0xFFu << sh)) | v;
+    }
+    v4u32_t t;
+    t.x = o[0];
+    t.y = o[1];
+    t.z = o[2];
+    t.w = o[3];
+    return t;
+}
+
+// Each thread takes units of 16 codes, kSecUnroll of them per step (a grid
+// stride apart, so that each store instruction of a wave is one contiguous
+// run and each load instruction one run with a stride of B 16-byte words),
+// all loads of a step issued before any use (4 units; 2 of 32-bit codes,
+// whose loads take twice the registers).
+template <int B>
+constexpr int sec_unroll() { return B == 4 ? 2 : 4; }
+
 template <typename T, int B>
 __device__ void section_pass(const T* __restrict__ in, int64_t nx, int64_t ny, int64_t nz,
                              const roix_row* __restrict__ rows, uint64_t nr, const uint8_t* __restrict__ stream,
                              uint64_t n, const SecParams& p, uint8_t* __restrict__ out, roix_section_info* info) {
-    const uint64_t ng = n / kSecCodes;
+    const uint64_t nu = n / kSecCodes;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += stride) {
-        uint4 w[B];
-        const uint4* src = reinterpret_cast<const uint4*>(stream + g * (kSecCodes * B));
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint4* src = reinterpret_cast<const uint4*>(stream);
+    constexpr int kSecUnroll = sec_unroll<B>();
+    for (uint64_t u0 = tid; u0 < nu; u0 += kSecUnroll * stride) {
+        uint4 w[kSecUnroll][B];
 #pragma unroll
-        for (int k = 0; k < B; ++k) w[k] = ld_stream(src + k);
-        uint32_t lv[kSecCodes];
-        bool any_esc = false;
+        for (int k = 0; k < kSecUnroll; ++k) {
+            const uint64_t u = u0 + k * stride;
+            if (u < nu) {
 #pragma unroll
-        for (int i = 0; i < kSecCodes; ++i) {
-            const uint32_t u = code_at<B>(w, i);
-            any_esc |= u == p.esc;
-            lv[i] = u == p.esc ? 0u : sec_level(u, p);
+                for (int j = 0; j < B; ++j) w[k][j] = ld_stream(src + u * B + j);
+            }
         }
-        if (any_esc) {
-            for (int i = 0; i < kSecCodes; ++i)
-                if (code_at<B>(w, i) == p.esc) lv[i] = sec_escape(in, nx, ny, nz, rows, nr, g * kSecCodes + i, p, info);
+#pragma unroll
+        for (int k = 0; k < kSecUnroll; ++k) {
+            const uint64_t u = u0 + k * stride;
+            if (u < nu) {
+                const v4u32_t t = levels16<T, B>(w[k], u * kSecCodes, in, nx, ny, nz, rows, nr, p, info);
+                __builtin_nontemporal_store(t, reinterpret_cast<v4u32_t*>(out + u * kSecCodes));
+            }
         }
-        uint4 o;
-        o.x = lv[0] | lv[1] << 8 | lv[2] << 16 | lv[3] << 24;
-        o.y = lv[4] | lv[5] << 8 | lv[6] << 16 | lv[7] << 24;
-        o.z = lv[8] | lv[9] << 8 | lv[10] << 16 | lv[11] << 24;
-        o.w = lv[12] | lv[13] << 8 | lv[14] << 16 | lv[15] << 24;
-        v4u32_t t;
-        t.x = o.x;
-        t.y = o.y;
-        t.z = o.z;
-        t.w = o.w;
-        __builtin_nontemporal_store(t, reinterpret_cast<v4u32_t*>(out + g * kSecCodes));
     }
     // the last n mod 16 codes, one thread each
-    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t c = ng * kSecCodes + t;
+    const uint64_t c = nu * kSecCodes + tid;
     if (c < n) {
         uint32_t u;
         if (B == 1) u = stream[c];
@@ -145,20 +178,43 @@ __device__ void section_pass(const T* __restrict__ in, int64_t nx, int64_t ny, i
     }
 }
 
-template <typename T>
+// One kernel per code width, each returning at once unless the call's codes
+// have its width: the width is device data, and a kernel of its own gives
+// each width its own register budget (and so its own occupancy).
+template <typename T, int B>
 __global__ __launch_bounds__(kBlock) void k_section(const T* __restrict__ in, int64_t nx, int64_t ny, int64_t nz,
                                                     const roix_quant_info* __restrict__ qi,
                                                     const roix_extract_info* __restrict__ ei,
                                                     const roix_row* __restrict__ rows,
                                                     const uint8_t* __restrict__ stream, uint8_t* __restrict__ out,
                                                     roix_section_info* info) {
-    if (info->status != ROIX_OK) return;
+    if (info->status != ROIX_OK || qi->width_bits != 8 * B) return;
     const SecParams p = sec_params(qi);
-    const uint64_t n = ei->n_codes, nr = ei->n_rows;
-    const int wb = qi->width_bits;
-    if (wb == 8) section_pass<T, 1>(in, nx, ny, nz, rows, nr, stream, n, p, out, info);
-    else if (wb == 16) section_pass<T, 2>(in, nx, ny, nz, rows, nr, stream, n, p, out, info);
-    else section_pass<T, 4>(in, nx, ny, nz, rows, nr, stream, n, p, out, info);
+    section_pass<T, B>(in, nx, ny, nz, rows, ei->n_rows, stream, ei->n_codes, p, out, info);
+}
+
+template <typename T, int B>
+static hipError_t launch_section_w(const LaunchCtx& lc, const T* in, const Geom& g, const roix_fused_out* o,
+                                   uint8_t* out, roix_section_info* info) {
+    // one workgroup per resident slot: every workgroup takes the same share
+    // of the grid-stride loop, so a grid of whole residency rounds keeps the
+    // last round from running on a fraction of the chip
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_section<T, B>, kBlock, 0);
+    if (e != hipSuccess) return e;
+    const int wgs = lc.cus > 0 && per_cu > 0 ? lc.cus * per_cu : lc.grid_stream;
+    hipLaunchKernelGGL((k_section<T, B>), dim3(wgs), dim3(kBlock), 0, lc.stream, in, g.nx, g.ny, g.nz, o->d_qinfo,
+                       o->d_einfo, o->d_rows, (const uint8_t*)o->d_stream, out, info);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_section_t(const LaunchCtx& lc, const T* in, const Geom& g, const roix_fused_out* o,
+                                   uint8_t* out, roix_section_info* info) {
+    hipError_t e;
+    if ((e = launch_section_w<T, 2>(lc, in, g, o, out, info)) != hipSuccess) return e;
+    if ((e = launch_section_w<T, 1>(lc, in, g, o, out, info)) != hipSuccess) return e;
+    return launch_section_w<T, 4>(lc, in, g, o, out, info);
 }
 
 hipError_t launch_section(const LaunchCtx& lc, const void* in, roix_dtype dt, const Geom& g,
@@ -166,15 +222,10 @@ hipError_t launch_section(const LaunchCtx& lc, const void* in, roix_dtype dt, co
     timer_begin(lc.timer, ST_SECTION, lc.stream);
     hipLaunchKernelGGL(k_section_check, dim3(1), dim3(1), 0, lc.stream, o->d_qinfo, o->d_einfo, o->rows_cap,
                        o->stream_cap_bytes, out_cap, info);
-    const dim3 grid(lc.grid_stream), block(kBlock);
-    if (dt == ROIX_F32)
-        hipLaunchKernelGGL(k_section<float>, grid, block, 0, lc.stream, (const float*)in, g.nx, g.ny, g.nz,
-                           o->d_qinfo, o->d_einfo, o->d_rows, (const uint8_t*)o->d_stream, out, info);
-    else
-        hipLaunchKernelGGL(k_section<uint16_t>, grid, block, 0, lc.stream, (const uint16_t*)in, g.nx, g.ny, g.nz,
-                           o->d_qinfo, o->d_einfo, o->d_rows, (const uint8_t*)o->d_stream, out, info);
+    const hipError_t e = dt == ROIX_F32 ? launch_section_t(lc, (const float*)in, g, o, out, info)
+                                        : launch_section_t(lc, (const uint16_t*)in, g, o, out, info);
     timer_end(lc.timer, ST_SECTION, lc.stream);
-    return hipGetLastError();
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 }  // namespace roix

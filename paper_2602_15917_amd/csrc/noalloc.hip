@@ -66,7 +66,7 @@ extern "C" roix_status roix_fused_noalloc(const void* d_in, roix_dtype dtype, ro
     lc.timer = nullptr;
     lc.grid_stream = a.cus * 8;
     lc.grid_read = a.cus * 4;
-    lc.grid_emit = a.cus * 4;
+    lc.grid_emit = a.cus * 6;
     lc.grid_mask = a.cus * 32;
     lc.seg_grid = a.cus * 2;
     lc.seg_runs = 0;
