@@ -63,7 +63,7 @@ def build(force: bool = True) -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build()
         lib = ctypes.CDLL(_LIB)
         vp, i64, u64, ci, dbl, f32 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int,
@@ -100,9 +100,9 @@ def _load():
         lib.oracle_abs_quantize.restype = ci
         lib.oracle_huff_lengths.argtypes = [vp, vp]
         lib.oracle_huff_lengths.restype = ci
-        lib.oracle_huff_encode.argtypes = [vp, u64, vp, vp, vp, u64, vp]
+        lib.oracle_huff_encode.argtypes = [vp, u64, vp, vp, vp, u64, vp, vp]
         lib.oracle_huff_encode.restype = ci
-        lib.oracle_huff_decode.argtypes = [vp, vp, vp, u64, u64, vp]
+        lib.oracle_huff_decode.argtypes = [vp, vp, vp, u64, u64, vp, vp]
         lib.oracle_huff_decode.restype = ci
         lib.oracle_fused.argtypes = [vp, ci, i64, i64, i64, ci, dbl, ci, dbl, ci, ci, i64, vp, i64, vp, i64, vp,
                                      i64, vp, i64, ctypes.POINTER(FusedInfo), vp]
@@ -285,6 +285,8 @@ def abs_quantize(pixels, e_abs):
 
 
 HUFF_BLOCK = 4096
+HUFF_SUB = 256  # bytes per sub-block of the optional sub-block index
+HUFF_SUBS = HUFF_BLOCK // HUFF_SUB
 
 
 def huff_lengths(hist):
@@ -295,10 +297,12 @@ def huff_lengths(hist):
     return st, ln
 
 
-def huff_encode(data, cap_words=None):
+def huff_encode(data, cap_words=None, with_sub=False):
     """Canonical Huffman coding of a byte sequence in blocks of 4096 bytes.
     Returns (status, lengths uint8[256], block offsets uint64[nblocks + 1]
-    in 32-bit words, payload uint32[words])."""
+    in 32-bit words, payload uint32[words]), and with with_sub the sub-block
+    index as a fifth item (uint16[16 nblocks]: code bits of each 256-byte
+    sub-block)."""
     d = np.ascontiguousarray(data, dtype=np.uint8).reshape(-1)
     nb = (d.size + HUFF_BLOCK - 1) // HUFF_BLOCK
     cap = nb * HUFF_BLOCK if cap_words is None else cap_words  # 32 bits per byte at most
@@ -306,17 +310,23 @@ def huff_encode(data, cap_words=None):
     off = np.zeros(nb + 1, np.uint64)
     pay = np.zeros(max(cap, 1), np.uint32)
     tot = np.zeros(1, np.uint64)
-    st = _load().oracle_huff_encode(_p(d) if d.size else None, d.size, _p(ln), _p(off), _p(pay), cap, _p(tot))
-    return st, ln, off, pay[: min(int(tot[0]), cap)].copy()
+    sub = np.zeros(max(HUFF_SUBS * nb, 1), np.uint16)
+    st = _load().oracle_huff_encode(_p(d) if d.size else None, d.size, _p(ln), _p(off), _p(pay), cap, _p(tot),
+                                    _p(sub) if with_sub else None)
+    r = (st, ln, off, pay[: min(int(tot[0]), cap)].copy())
+    return r + (sub[: HUFF_SUBS * nb].copy(),) if with_sub else r
 
 
-def huff_decode(lengths, block_off, payload, n):
-    """Inverse of huff_encode; (status, bytes)."""
+def huff_decode(lengths, block_off, payload, n, sub_bits=None):
+    """Inverse of huff_encode, from the block starts alone or, with the
+    sub-block index, from every sub-block's start; (status, bytes)."""
     ln = np.ascontiguousarray(lengths, dtype=np.uint8)
     off = np.ascontiguousarray(block_off, dtype=np.uint64)
     pay = np.ascontiguousarray(payload, dtype=np.uint32)
     out = np.zeros(max(n, 1), np.uint8)
-    st = _load().oracle_huff_decode(_p(ln), _p(off), _p(pay) if pay.size else None, pay.size, n, _p(out))
+    sub = None if sub_bits is None else np.ascontiguousarray(sub_bits, dtype=np.uint16)
+    st = _load().oracle_huff_decode(_p(ln), _p(off), _p(pay) if pay.size else None, pay.size, n, _p(out),
+                                    _p(sub) if sub is not None and sub.size else None)
     return st, out[:n].copy()
 
 

@@ -866,8 +866,17 @@ int oracle_abs_quantize(const uint8_t* D, uint64_t m, double e_abs, uint8_t* Q, 
  * Format: the input is cut into blocks of 4096 bytes; block b is written
  * from 32-bit word block_off[b] of the payload, its codes one after another
  * from the most significant bit of each word down, zero bits up to the next
- * word; block_off[nblocks] is the payload length in words. */
+ * word; block_off[nblocks] is the payload length in words.
+ * Sub-block index (optional): each block is also cut into 16 sub-blocks of
+ * 256 input bytes, and sub_bits[16 b + k] is the number of code bits of
+ * sub-block k of block b (0 for sub-blocks past the input's end).  The codes
+ * of consecutive sub-blocks follow each other with no padding, so the payload
+ * is the same with or without the index; sub-block k starts at bit
+ * sub_bits[16 b] + ... + sub_bits[16 b + k - 1] of its block, which lets a
+ * decoder start at every sub-block at once. */
 #define OR_HUFF_BLOCK 4096
+#define OR_HUFF_SUB 256
+#define OR_HUFF_SUBS (OR_HUFF_BLOCK / OR_HUFF_SUB)
 
 int oracle_huff_lengths(const uint64_t hist[256], uint8_t len[256]) {
     int sym[256], ns = 0;
@@ -924,10 +933,10 @@ static void huff_codes(const uint8_t len[256], uint32_t code[256]) {
 }
 
 /* Encode: lengths from the counts of `in`, then the blocks.  block_off has
- * nblocks + 1 entries.  OR_ETRUNC (and *total_words) when the payload does
- * not fit cap_words. */
+ * nblocks + 1 entries; sub_bits (16 nblocks entries) may be NULL.  OR_ETRUNC
+ * (and *total_words) when the payload does not fit cap_words. */
 int oracle_huff_encode(const uint8_t* in, uint64_t n, uint8_t len[256], uint64_t* block_off, uint32_t* payload,
-                       uint64_t cap_words, uint64_t* total_words) {
+                       uint64_t cap_words, uint64_t* total_words, uint16_t* sub_bits) {
     uint64_t hist[256] = {0};
     for (uint64_t i = 0; i < n; ++i) hist[in[i]]++;
     int st = oracle_huff_lengths(hist, len);
@@ -941,6 +950,15 @@ int oracle_huff_encode(const uint8_t* in, uint64_t n, uint8_t len[256], uint64_t
         uint64_t bits = 0;
         const uint64_t e = (b + 1) * OR_HUFF_BLOCK < n ? (b + 1) * OR_HUFF_BLOCK : n;
         for (uint64_t i = b * OR_HUFF_BLOCK; i < e; ++i) bits += len[in[i]];
+        if (sub_bits) {
+            for (int k = 0; k < OR_HUFF_SUBS; ++k) {
+                uint64_t sb = 0;
+                for (uint64_t i = b * OR_HUFF_BLOCK + (uint64_t)k * OR_HUFF_SUB;
+                     i < e && i < b * OR_HUFF_BLOCK + (uint64_t)(k + 1) * OR_HUFF_SUB; ++i)
+                    sb += len[in[i]];
+                sub_bits[b * OR_HUFF_SUBS + k] = (uint16_t)sb; /* at most 256 * 32 = 8192 */
+            }
+        }
         const uint64_t words = (bits + 31) / 32;
         if (word + words <= cap_words) {
             for (uint64_t k = 0; k < words; ++k) payload[word + k] = 0u;
@@ -958,10 +976,28 @@ int oracle_huff_encode(const uint8_t* in, uint64_t n, uint8_t len[256], uint64_t
     return word > cap_words ? OR_ETRUNC : OR_OK;
 }
 
+/* One code at bit p of a block's bits (nbits of them); the byte, and p
+ * moved past it; -1 when the bits match no code before their end. */
+static int huff_next(const uint8_t len[256], const uint32_t code[256], const uint32_t* words, uint64_t nbits,
+                     uint64_t* p) {
+    uint32_t c = 0;
+    for (int L = 1; L <= 32; ++L) {
+        if (*p >= nbits) return -1;
+        c = (c << 1) | ((words[*p / 32] >> (31 - *p % 32)) & 1u);
+        ++*p;
+        for (int s = 0; s < 256; ++s)
+            if (len[s] == L && code[s] == c) return s;
+    }
+    return -1;
+}
+
 /* Decode n bytes; OR_EINVAL on lengths that are no prefix code, offsets that
- * decrease or pass the payload, or bits that match no code. */
+ * decrease or pass the payload, or bits that match no code.  With sub_bits,
+ * every sub-block is decoded from its own start, and a sub-block whose codes
+ * do not take exactly its stated bits (or stated bits past the block's
+ * words) is OR_EINVAL too. */
 int oracle_huff_decode(const uint8_t len[256], const uint64_t* block_off, const uint32_t* payload,
-                       uint64_t payload_words, uint64_t n, uint8_t* out) {
+                       uint64_t payload_words, uint64_t n, uint8_t* out, const uint16_t* sub_bits) {
     uint32_t code[256];
     double kraft = 0.0;
     int used = 0;
@@ -978,24 +1014,32 @@ int oracle_huff_decode(const uint8_t len[256], const uint64_t* block_off, const 
     if (nb > 0 && block_off[0] != 0) return OR_EINVAL;
     for (uint64_t b = 0; b < nb; ++b) {
         if (block_off[b + 1] < block_off[b] || block_off[b + 1] > payload_words) return OR_EINVAL;
-        const uint64_t w0 = block_off[b], nbits = (block_off[b + 1] - w0) * 32;
-        uint64_t p = 0;
-        const uint64_t e = (b + 1) * OR_HUFF_BLOCK < n ? (b + 1) * OR_HUFF_BLOCK : n;
-        for (uint64_t i = b * OR_HUFF_BLOCK; i < e; ++i) {
-            uint32_t c = 0;
-            int L = 0, found = -1;
-            while (found < 0) {
-                if (L == 32 || p >= nbits) return OR_EINVAL;
-                c = (c << 1) | ((payload[w0 + p / 32] >> (31 - p % 32)) & 1u);
-                ++p;
-                ++L;
-                for (int s = 0; s < 256; ++s)
-                    if (len[s] == L && code[s] == c) {
-                        found = s;
-                        break;
-                    }
+        const uint32_t* words = payload + block_off[b];
+        const uint64_t nbits = (block_off[b + 1] - block_off[b]) * 32;
+        const uint64_t i0 = b * OR_HUFF_BLOCK, e = i0 + OR_HUFF_BLOCK < n ? i0 + OR_HUFF_BLOCK : n;
+        if (!sub_bits) {
+            uint64_t p = 0;
+            for (uint64_t i = i0; i < e; ++i) {
+                const int s = huff_next(len, code, words, nbits, &p);
+                if (s < 0) return OR_EINVAL;
+                out[i] = (uint8_t)s;
             }
-            out[i] = (uint8_t)found;
+            continue;
+        }
+        uint64_t start = 0; /* the sub-block's first bit */
+        for (int k = 0; k < OR_HUFF_SUBS; ++k) {
+            const uint64_t s0 = i0 + (uint64_t)k * OR_HUFF_SUB;
+            const uint64_t s1 = s0 + OR_HUFF_SUB < e ? s0 + OR_HUFF_SUB : e;
+            const uint64_t stated = sub_bits[b * OR_HUFF_SUBS + k];
+            if (start + stated > nbits) return OR_EINVAL;
+            uint64_t p = start;
+            for (uint64_t i = s0; i < s1; ++i) {
+                const int s = huff_next(len, code, words, start + stated, &p);
+                if (s < 0) return OR_EINVAL;
+                out[i] = (uint8_t)s;
+            }
+            if (p != start + stated) return OR_EINVAL;
+            start += stated;
         }
     }
     return OR_OK;

@@ -159,22 +159,33 @@ static void huffman_cases(void) {
             const uint64_t cap = n / 4 * 9 + 16;
             uint32_t* payload = calloc(cap, sizeof(uint32_t));
             uint64_t words = 0;
-            int st = oracle_huff_encode(in, n, len, off, payload, cap, &words);
+            uint16_t* sub = calloc(nb * OR_HUFF_SUBS + 1, sizeof(uint16_t));
+            int st = oracle_huff_encode(in, n, len, off, payload, cap, &words, sub);
             EXPECT(st == OR_OK || (n == 0 && st != OR_OK));
             if (st == OR_OK) {
                 uint8_t* back = malloc(n ? n : 1);
-                EXPECT(oracle_huff_decode(len, off, payload, words, n, back) == OR_OK);
+                EXPECT(oracle_huff_decode(len, off, payload, words, n, back, NULL) == OR_OK);
+                EXPECT(n == 0 || memcmp(back, in, n) == 0);
+                EXPECT(oracle_huff_decode(len, off, payload, words, n, back, sub) == OR_OK);
                 EXPECT(n == 0 || memcmp(back, in, n) == 0);
                 /* a payload cut short is refused, not read past its end */
-                if (words > 0) EXPECT(oracle_huff_decode(len, off, payload, words - 1, n, back) == OR_EINVAL);
+                if (words > 0) EXPECT(oracle_huff_decode(len, off, payload, words - 1, n, back, NULL) == OR_EINVAL);
+                if (words > 0) EXPECT(oracle_huff_decode(len, off, payload, words - 1, n, back, sub) == OR_EINVAL);
+                /* a sub-block length one bit off is refused */
+                if (nb > 0) {
+                    sub[0] += 1;
+                    EXPECT(oracle_huff_decode(len, off, payload, words, n, back, sub) == OR_EINVAL);
+                    sub[0] -= 1;
+                }
                 free(back);
                 /* a truncated capacity reports the size it needed */
                 uint64_t w2 = 0;
-                if (words > 0) EXPECT(oracle_huff_encode(in, n, len, off, payload, words - 1, &w2) == OR_ETRUNC);
+                if (words > 0) EXPECT(oracle_huff_encode(in, n, len, off, payload, words - 1, &w2, NULL) == OR_ETRUNC);
             }
             free(in);
             free(off);
             free(payload);
+            free(sub);
         }
 }
 

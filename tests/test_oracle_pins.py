@@ -694,6 +694,73 @@ def _canonical_decode(lengths, block_off, payload, n):
     return np.array(out, np.uint8)
 
 
+def _canonical_decode_sub(lengths, block_off, sub_bits, payload, n):
+    # decoder written from the sub-block index's definition: each 256-byte
+    # sub-block is decoded on its own, from the sum of the stated lengths of
+    # the sub-blocks before it in its block, and must take exactly its length
+    items = sorted((int(l), s) for s, l in enumerate(lengths) if l)
+    table, code, prev = {}, 0, items[0][0] if items else 0
+    for i, (l, s) in enumerate(items):
+        if i:
+            code = (code + 1) << (l - prev)
+        prev = l
+        table[(l, code)] = s
+    out = np.zeros(n, np.uint8)
+    for b in range(len(block_off) - 1):
+        bits = "".join(f"{int(w):032b}" for w in payload[int(block_off[b]): int(block_off[b + 1])])
+        for k in range(16):
+            start = int(sum(int(v) for v in sub_bits[16 * b: 16 * b + k]))
+            p = start
+            for i in range(4096 * b + 256 * k, min(4096 * b + 256 * (k + 1), n)):
+                c, l = 0, 0
+                while (l, c) not in table:
+                    c, l, p = (c << 1) | int(bits[p]), l + 1, p + 1
+                out[i] = table[(l, c)]
+            assert p - start == int(sub_bits[16 * b + k])
+    return out
+
+
+def test_huffman_sub_block_index():
+    # the index's closed form: a sub-block's bits are the sum of its bytes'
+    # code lengths (0 past the end); the payload does not change with it;
+    # decoding from every sub-block's start (the oracle's, and a decoder
+    # written from the definition) gives the input back, and an index one
+    # bit off anywhere is refused
+    rng = np.random.default_rng(101)
+    for n in (0, 1, 255, 256, 257, 4095, 4096, 4097, 9000):
+        for kind in range(3):
+            if kind == 0:
+                d = rng.integers(0, 256, n).astype(np.uint8)
+            elif kind == 1:
+                d = np.clip(np.round(rng.normal(100, 3, n)), 0, 255).astype(np.uint8)
+            else:
+                d = np.full(n, 42, np.uint8)
+            st, ln, off, pay, sub = oracle.huff_encode(d, with_sub=True)
+            st0, ln0, off0, pay0 = oracle.huff_encode(d)
+            assert st == st0 == oracle.OK and np.array_equal(pay, pay0) and np.array_equal(off, off0)
+            nb = (n + 4095) // 4096
+            assert sub.size == 16 * nb
+            pad = np.zeros(16 * nb * 256, np.int64)
+            pad[:n] = ln[d].astype(np.int64) + 0
+            want = pad.reshape(-1, 256).sum(axis=1)
+            assert np.array_equal(sub.astype(np.int64), want)
+            for b in range(nb):
+                bits = int(sub[16 * b: 16 * b + 16].astype(np.int64).sum())
+                assert int(off[b + 1] - off[b]) == (bits + 31) // 32
+            st, back = oracle.huff_decode(ln, off, pay, n, sub)
+            assert st == oracle.OK and np.array_equal(back, d)
+            if 0 < n <= 4097 and kind < 2:
+                assert np.array_equal(_canonical_decode_sub(ln, off, sub, pay, n), d)
+            if n > 0:
+                for j in (0, int(rng.integers(0, (n - 1) // 256 + 1))):
+                    for delta in (1, -1):
+                        bad = sub.astype(np.int64)
+                        bad[j] += delta
+                        if bad[j] < 0:
+                            continue
+                        assert oracle.huff_decode(ln, off, pay, n, bad.astype(np.uint16))[0] == oracle.EINVAL
+
+
 def test_huffman_hand_examples():
     g = json.load(open(os.path.join(GOLDEN, "hand_huffman.json")))
     for c in g["cases"]:
