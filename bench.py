@@ -447,11 +447,15 @@ def bench_huffman(args):
         torch.cuda.synchronize()
         return ev0.elapsed_time(ev1) / args.steps, r
 
-    ms_enc, (ln, off, pay, info) = timed(lambda: ctx.huff_encode(s, stream=stream))
+    ms_enc, (ln, off, pay, info, sub) = timed(lambda: ctx.huff_encode(s, stream=stream, with_sub=True))
     i = roix.huff_info(info)
     assert i.status == 0
     dst = torch.empty(n, dtype=torch.uint8, device=dev)
-    ms_dec, (back, dinfo) = timed(lambda: ctx.huff_decode(ln, off, pay, i.payload_words, n, dst, stream))
+    # from every 256-byte sub-block's start (the index), and from the block starts alone
+    ms_dec, (back, dinfo) = timed(lambda: ctx.huff_decode(ln, off, pay, i.payload_words, n, dst, stream, sub=sub))
+    assert roix.huff_info(dinfo).status == 0 and torch.equal(back, s)
+    dst.zero_()
+    ms_dec_blk, (back, dinfo) = timed(lambda: ctx.huff_decode(ln, off, pay, i.payload_words, n, dst, stream))
     assert roix.huff_info(dinfo).status == 0 and torch.equal(back, s)
     roi_plain = 32 * int(e.n_rows) + n + 4 * int(e.n_outliers)
     roi_huff = 32 * int(e.n_rows) + int(i.compressed_bytes) + 4 * int(e.n_outliers)
@@ -484,7 +488,10 @@ def bench_huffman(args):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round((n + 4 * int(i.payload_words)) / (ms_enc * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                      "traffic": None, "alg_bytes_per_launch": n + 4 * int(i.payload_words)},
-        "decode": {"ms": round(ms_dec, 4), "GBps_out": round(n / (ms_dec * 1e-3) / 1e9, 2)},
+        "decode": {"ms": round(ms_dec, 4), "GBps_out": round(n / (ms_dec * 1e-3) / 1e9, 2),
+                   "from": "every 256-byte sub-block's start (16 lanes per block)",
+                   "frac": round((n + 4 * int(i.payload_words)) / (ms_dec * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                   "block_lanes_ms": round(ms_dec_blk, 4)},
         "compression": {"stream_ratio": round(n / int(i.compressed_bytes), 4), "max_code_bits": int(i.max_len),
                         "roi_ratio_plain": round(vol_bytes / roi_plain, 3),
                         "roi_ratio_huffman": round(vol_bytes / roi_huff, 3),

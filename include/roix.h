@@ -447,11 +447,21 @@ roix_status roix_abs_quantize(roix_ctx* ctx, const uint8_t* d_pixels, int64_t m,
  * block_off[b] of the payload, its codes written one after another from the
  * most significant bit of each word down, zero bits to the end of its last
  * word; block_off[nblocks] is the payload length in words.
+ * Sub-block index (optional): every block is cut into 16 sub-blocks of 256
+ * input bytes and sub_bits[16 b + k] holds the code bits of sub-block k of
+ * block b (0 past the input's end; at most 8192).  Sub-blocks follow each
+ * other in the payload with no padding, so the payload is the same with or
+ * without the index; sub-block k starts at bit sub_bits[16 b] + ... +
+ * sub_bits[16 b + k - 1] of its block, which lets a decoder start at every
+ * sub-block at once.
  * The compressed form is lengths (256 bytes) + block_off (8 bytes per
- * block + 8) + payload (4 bytes per word): info.compressed_bytes.
+ * block + 8) + payload (4 bytes per word), + the index (32 bytes per block)
+ * when one is written: info.compressed_bytes.
  *   d_in          n bytes, 16-byte aligned
  *   d_lengths     out: 256 code lengths (0 = byte unused)
  *   d_block_off   out: nblocks + 1 offsets, nblocks = ceil(n / 4096)
+ *   d_sub_bits    out: 16 nblocks sub-block bit counts (2-byte aligned), or
+ *                 NULL for no index
  *   d_payload     out: payload_cap_words words; at most 32 bits per input
  *                 byte, so 4096 words per block always suffice
  *   d_info        device: status, max_len, n, n_blocks, payload_words,
@@ -473,18 +483,22 @@ typedef struct {
     uint64_t pad[3];
 } roix_huff_info; /* 64 bytes */
 roix_status roix_huff_encode(roix_ctx* ctx, const uint8_t* d_in, int64_t n, uint8_t* d_lengths,
-                             uint64_t* d_block_off, uint32_t* d_payload, int64_t payload_cap_words,
-                             roix_huff_info* d_info, void* stream);
+                             uint64_t* d_block_off, uint16_t* d_sub_bits, uint32_t* d_payload,
+                             int64_t payload_cap_words, roix_huff_info* d_info, void* stream);
 
 /* Decode n bytes from the format of roix_huff_encode into d_out (16-byte
- * aligned).  info.status is ROIX_EINVAL when the lengths are no prefix code
- * (a length above 32, Kraft sum above 1, none used for n > 0), the offsets
- * do not start at 0, decrease or pass payload_words, or a block's bits end
- * or match no code before its bytes are complete; d_out is then
- * unspecified.  One lane decodes a block.  Errors as roix_huff_encode. */
+ * aligned).  With the sub-block index (d_sub_bits, 16 nblocks entries) a
+ * lane decodes a 256-byte sub-block from the start the index gives (16 lanes
+ * per block); without it (NULL) a lane decodes a whole block.  info.status
+ * is ROIX_EINVAL when the lengths are no prefix code (a length above 32,
+ * Kraft sum above 1, none used for n > 0), the offsets do not start at 0,
+ * decrease or pass payload_words, a block's (sub-block's) bits end or match
+ * no code before its bytes are complete, or, with the index, a sub-block's
+ * codes do not take exactly its stated bits or a block's stated bits exceed
+ * its words; d_out is then unspecified.  Errors as roix_huff_encode. */
 roix_status roix_huff_decode(roix_ctx* ctx, const uint8_t* d_lengths, const uint64_t* d_block_off,
-                             const uint32_t* d_payload, int64_t payload_words, int64_t n, uint8_t* d_out,
-                             roix_huff_info* d_info, void* stream);
+                             const uint16_t* d_sub_bits, const uint32_t* d_payload, int64_t payload_words, int64_t n,
+                             uint8_t* d_out, roix_huff_info* d_info, void* stream);
 
 /* One volume of a batch: input, shape, bound, criterion and the caller's
  * output buffers (as for roix_fused). */

@@ -613,28 +613,28 @@ roix_status roix_section(roix_ctx* ctx, const void* d_in, roix_dtype dtype, roix
 static bool huff_n_ok(int64_t n) { return n >= 0 && n <= ((int64_t)1 << 40); }
 
 roix_status roix_huff_encode(roix_ctx* ctx, const uint8_t* d_in, int64_t n, uint8_t* d_lengths,
-                             uint64_t* d_block_off, uint32_t* d_payload, int64_t payload_cap_words,
-                             roix_huff_info* d_info, void* stream) {
+                             uint64_t* d_block_off, uint16_t* d_sub_bits, uint32_t* d_payload,
+                             int64_t payload_cap_words, roix_huff_info* d_info, void* stream) {
     if (!ctx || !d_lengths || !d_block_off || !d_info || !huff_n_ok(n) || payload_cap_words < 0) return ROIX_EINVAL;
-    if (!aligned(d_block_off, 8) || !aligned(d_info, 8)) return ROIX_EINVAL;
+    if (!aligned(d_block_off, 8) || !aligned(d_info, 8) || !aligned(d_sub_bits, 2)) return ROIX_EINVAL;
     if (n > 0 && (!d_in || !aligned(d_in, 16))) return ROIX_EINVAL;
     if (payload_cap_words > 0 && (!d_payload || !aligned(d_payload, 4))) return ROIX_EINVAL;
     if (ctx->arena_bytes < huff_scratch_bytes()) return ROIX_ENOMEM;
-    ROIX_TRY(launch_huff_encode(lctx(ctx, stream), d_in, n, d_lengths, (unsigned long long*)d_block_off, d_payload,
-                                payload_cap_words, ctx->arena, d_info));
+    ROIX_TRY(launch_huff_encode(lctx(ctx, stream), d_in, n, d_lengths, (unsigned long long*)d_block_off, d_sub_bits,
+                                d_payload, payload_cap_words, ctx->arena, d_info));
     return ROIX_OK;
 }
 
 roix_status roix_huff_decode(roix_ctx* ctx, const uint8_t* d_lengths, const uint64_t* d_block_off,
-                             const uint32_t* d_payload, int64_t payload_words, int64_t n, uint8_t* d_out,
-                             roix_huff_info* d_info, void* stream) {
+                             const uint16_t* d_sub_bits, const uint32_t* d_payload, int64_t payload_words, int64_t n,
+                             uint8_t* d_out, roix_huff_info* d_info, void* stream) {
     if (!ctx || !d_lengths || !d_block_off || !d_info || !huff_n_ok(n) || payload_words < 0) return ROIX_EINVAL;
-    if (!aligned(d_block_off, 8) || !aligned(d_info, 8)) return ROIX_EINVAL;
+    if (!aligned(d_block_off, 8) || !aligned(d_info, 8) || !aligned(d_sub_bits, 2)) return ROIX_EINVAL;
     if (n > 0 && (!d_out || !aligned(d_out, 16))) return ROIX_EINVAL;
     if (payload_words > 0 && (!d_payload || !aligned(d_payload, 4))) return ROIX_EINVAL;
     if (ctx->arena_bytes < huff_scratch_bytes()) return ROIX_ENOMEM;
-    ROIX_TRY(launch_huff_decode(lctx(ctx, stream), d_lengths, (const unsigned long long*)d_block_off, d_payload,
-                                payload_words, n, d_out, ctx->arena, d_info));
+    ROIX_TRY(launch_huff_decode(lctx(ctx, stream), d_lengths, (const unsigned long long*)d_block_off, d_sub_bits,
+                                d_payload, payload_words, n, d_out, ctx->arena, d_info));
     return ROIX_OK;
 }
 

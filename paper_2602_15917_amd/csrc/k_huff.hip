@@ -30,6 +30,8 @@ constexpr int kHfBlock = 4096;   // input bytes per block
 constexpr int kHfPeek = 11;      // bits of the decoder's lookup table
 constexpr int kHfRound = 8;      // decoder steps between refills (2 bytes each at most)
 constexpr int kHfRing = 36;      // LDS bytes of a lane's 32-byte output ring (stride against bank conflicts)
+constexpr int kHfSub = 256;      // input bytes per sub-block of the sub-block index
+constexpr int kHfSubs = kHfBlock / kHfSub;
 
 struct HfState {
     unsigned long long hist[256];
@@ -185,7 +187,8 @@ __global__ __launch_bounds__(256) void k_hf_build(HfState* S, uint8_t* lengths_o
 // Bit count of each block: lane l takes bytes 1024 i + 16 l .. + 15 of the
 // block (i = 0..3), so each load instruction reads 1 KB contiguously.
 __global__ __launch_bounds__(kWave) void k_hf_count(const uint8_t* __restrict__ in, unsigned long long n,
-                                                    const HfState* S, unsigned long long* block_words) {
+                                                    const HfState* S, unsigned long long* block_words,
+                                                    uint16_t* sub_bits) {
     __shared__ uint8_t len[256];
     for (int i = threadIdx.x; i < 256; i += kWave) len[i] = S->len[i];
     __syncthreads();
@@ -211,9 +214,16 @@ __global__ __launch_bounds__(kWave) void k_hf_count(const uint8_t* __restrict__ 
             const unsigned long long p = b * kHfBlock + 1024ull * i + 16ull * lane;
             const int cnt = p >= n ? 0 : (n - p >= 16 ? 16 : (int)(n - p));
             const uint32_t ww[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
+            uint32_t bi = 0u;
 #pragma unroll
             for (int k = 0; k < 16; ++k)
-                if (k < cnt) bits += len[(ww[k >> 2] >> (8 * (k & 3))) & 0xFFu];
+                if (k < cnt) bi += len[(ww[k >> 2] >> (8 * (k & 3))) & 0xFFu];
+            bits += bi;
+            if (sub_bits) {  // uniform: sub-block 4 i + l / 16 is lanes l / 16 * 16 .. + 15 of step i
+#pragma unroll
+                for (int o = 8; o > 0; o >>= 1) bi += __shfl_xor(bi, o);
+                if ((lane & 15) == 0) sub_bits[b * kHfSubs + 4 * i + lane / 16] = (uint16_t)bi;
+            }
         }
         bits = wave_sum(bits);
         if (lane == 0) block_words[b] = (bits + 31u) / 32u;
@@ -349,7 +359,7 @@ __global__ __launch_bounds__(kWave) void k_hf_encode(const uint8_t* __restrict__
 __global__ void k_hf_zero_off(unsigned long long* block_off) { block_off[0] = 0ull; }
 
 __global__ void k_hf_finalize(const HfState* S, const unsigned long long* block_off, unsigned long long n,
-                              unsigned long long cap_words, roix_huff_info* info) {
+                              unsigned long long cap_words, int with_sub, roix_huff_info* info) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const unsigned long long nb = (n + kHfBlock - 1) / kHfBlock;
     const unsigned long long words = block_off[nb];
@@ -360,7 +370,7 @@ __global__ void k_hf_finalize(const HfState* S, const unsigned long long* block_
     info->n = n;
     info->n_blocks = nb;
     info->payload_words = words;
-    info->compressed_bytes = 256ull + 8ull * (nb + 1) + 4ull * words;
+    info->compressed_bytes = 256ull + 8ull * (nb + 1) + 4ull * words + (with_sub ? 2ull * kHfSubs * nb : 0ull);
     info->pad[0] = info->pad[1] = info->pad[2] = 0ull;
 }
 
@@ -371,20 +381,24 @@ __global__ void k_hf_finalize(const HfState* S, const unsigned long long* block_
 // 16-20) and, when a second whole code follows inside the same kHfPeek
 // bits, that one's byte and length (bits 8-15, 21-25; length 0: none).
 // A first length of 0 marks a code longer than the table.
-struct HfDecode {
+template <int PK>
+struct HfDecodeP {
     uint32_t first[34];   // first canonical code of each length
     uint32_t count[34];   // codes of each length
     uint32_t index[34];   // position of a length's first byte in sym
     uint8_t sym[256];     // bytes by (length, value)
-    uint32_t peek[1 << kHfPeek];
+    uint32_t peek[1 << PK];
     int maxl;             // longest code length in use
 };
+using HfDecode = HfDecodeP<kHfPeek>;
 
-// The code of length <= lmax at the top of the kHfPeek-bit value e
-// (canonical: a length-L code c is valid when c - first[L] < count[L]).
-__device__ __forceinline__ bool hf_short_code(const HfDecode& T, uint32_t e, int lmax, int& L, uint32_t& s) {
+// The code of length <= lmax at the top of the PK-bit value e (canonical: a
+// length-L code c is valid when c - first[L] < count[L]).
+template <int PK>
+__device__ __forceinline__ bool hf_short_code(const HfDecodeP<PK>& T, uint32_t e, int lmax, int& L, uint32_t& s) {
+#pragma unroll 1
     for (L = 1; L <= lmax; ++L) {
-        const uint32_t c = e >> (kHfPeek - L);
+        const uint32_t c = e >> (PK - L);
         if (c - T.first[L] < T.count[L]) {
             s = T.sym[T.index[L] + (c - T.first[L])];
             return true;
@@ -410,14 +424,14 @@ __device__ __forceinline__ void hf_quad(const uint32_t* __restrict__ payload, un
     }
 }
 
-__global__ __launch_bounds__(256) void k_hf_decode(const uint8_t* lengths, const unsigned long long* block_off,
-                                                   const uint32_t* payload, unsigned long long payload_words,
-                                                   unsigned long long n, uint8_t* out, HfState* S, int vec) {
-    __shared__ HfDecode T;
+// The decoder tables of one workgroup (lookup table, canonical bounds),
+// built in LDS from the 256 code lengths; false (and EINVAL in S) when the
+// lengths are no prefix code.  Every thread of the workgroup calls it.
+template <int PK>
+__device__ __forceinline__ bool hf_tables(const uint8_t* lengths, unsigned long long n, HfDecodeP<PK>& T, HfState* S) {
     __shared__ int bad_table;
     __shared__ unsigned long long kraft;  // in units of 2^-32
     __shared__ uint8_t lens[256];
-    __shared__ __align__(16) uint8_t ring_sh[kHfRing * 256];
     const int t = threadIdx.x;
     const int Lt = lengths[t];
     lens[t] = (uint8_t)Lt;
@@ -459,30 +473,50 @@ __global__ __launch_bounds__(256) void k_hf_decode(const uint8_t* lengths, const
     __syncthreads();
     if (bad_table) {
         if (t == 0) atomicCAS(&S->status, 0, ROIX_EINVAL);
-        return;
+        return false;
     }
-    for (int e = t; e < (1 << kHfPeek); e += blockDim.x) {
+    for (int e = t; e < (1 << PK); e += blockDim.x) {
         uint32_t val = 0u, s1 = 0u, s2 = 0u;
         int L1 = 0, L2 = 0;
-        if (hf_short_code(T, (uint32_t)e, kHfPeek, L1, s1)) {
+        if (hf_short_code<PK>(T, (uint32_t)e, PK, L1, s1)) {
             val = s1 | ((uint32_t)L1 << 16);
-            if (L1 < kHfPeek && hf_short_code(T, ((uint32_t)e << L1) & ((1u << kHfPeek) - 1u), kHfPeek - L1, L2, s2))
+            if (L1 < PK && hf_short_code<PK>(T, ((uint32_t)e << L1) & ((1u << PK) - 1u), PK - L1, L2, s2))
                 val |= (s2 << 8) | ((uint32_t)L2 << 21);
         }
         T.peek[e] = val;
     }
     __syncthreads();
+    return true;
+}
+
+// A lane decodes one task: a whole block (SUB false), or with the sub-block
+// index one 256-byte sub-block (SUB true: 16 lanes per block, each starting
+// at the bit the index gives, so that a wave decodes 4 blocks at once).
+// Lanes keep a 64-bit bit window fed from 16-byte loads one quad ahead; an
+// 11-bit lookup table yields one or two codes, a canonical search the longer
+// ones.  A sub-block must take exactly its stated bits.
+template <bool SUB>
+__global__ __launch_bounds__(256) void k_hf_decode(const uint8_t* lengths, const unsigned long long* block_off,
+                                                   const uint16_t* sub_bits, const uint32_t* payload,
+                                                   unsigned long long payload_words, unsigned long long n,
+                                                   uint8_t* out, HfState* S, int vec) {
+    __shared__ HfDecode T;
+    __shared__ __align__(16) uint8_t ring_sh[kHfRing * 256];
+    if (!hf_tables<kHfPeek>(lengths, n, T, S)) return;
+    const int t = threadIdx.x;
     const unsigned long long nb = (n + kHfBlock - 1) / kHfBlock;
+    const unsigned long long ntasks = SUB ? nb * kHfSubs : nb;
     const int maxl = T.maxl;
     uint8_t* ring = ring_sh + kHfRing * t;  // this lane's output bytes, 16 at a time to HBM
     // The wave goes in rounds: at the top of a round each lane takes the
     // quad it loaded the round before, asks for the next, and stores 16
     // output bytes; then kHfRound steps decode from registers only (a lane
     // whose bits run short before its next quad arrives waits a round).
-    for (unsigned long long base = (unsigned long long)blockIdx.x * blockDim.x; base < nb;
+    for (unsigned long long base = (unsigned long long)blockIdx.x * blockDim.x; base < ntasks;
          base += (unsigned long long)gridDim.x * blockDim.x) {
-        const unsigned long long b = base + t;
-        bool live = b < nb;
+        const unsigned long long task = base + t;
+        bool live = task < ntasks;
+        const unsigned long long b = SUB ? task / kHfSubs : task;
         unsigned long long w0 = 0ull, w1 = 0ull;
         if (live) {
             w0 = block_off[b];
@@ -492,21 +526,53 @@ __global__ __launch_bounds__(256) void k_hf_decode(const uint8_t* lengths, const
                 live = false;
             }
         }
-        const unsigned long long i0 = b * kHfBlock;
-        uint32_t left = live ? (uint32_t)(i0 + kHfBlock < n ? kHfBlock : n - i0) : 0u;  // bytes to decode
-        uint32_t rem = (uint32_t)(w1 - w0);  // payload words not yet in the window
+        // the task's bytes [i0, i0 + left) and payload bits [bit0, bit0 + sb)
+        unsigned long long i0 = b * kHfBlock, bit0 = 32ull * w0, wa = w0, wend = w1;
+        uint32_t sb = 0u;
+        if (SUB) {
+            i0 += (unsigned long long)(task % kHfSubs) * kHfSub;
+            sb = live ? (uint32_t)sub_bits[task] : 0u;
+            // the sub-block's start: the stated bits of the block's sub-blocks
+            // before it (a scan over its 16 lanes, every lane taking part)
+            uint32_t incl = sb;
+#pragma unroll
+            for (int o = 1; o < kHfSubs; o <<= 1) {
+                const uint32_t y = __shfl_up(incl, o, kHfSubs);
+                if ((t & (kHfSubs - 1)) >= o) incl += y;
+            }
+            const uint32_t total = __shfl(incl, kHfSubs - 1, kHfSubs);
+            if (live && total > 32ull * (w1 - w0)) {
+                atomicCAS(&S->status, 0, ROIX_EINVAL);
+                live = false;
+            }
+            bit0 += incl - sb;
+            wa = bit0 / 32ull;
+            wend = (bit0 + sb + 31ull) / 32ull;
+        }
+        const unsigned long long iend = SUB ? i0 + kHfSub : i0 + kHfBlock;
+        uint32_t left = live && i0 < n ? (uint32_t)((iend < n ? iend : n) - i0) : 0u;  // bytes to decode
+        uint32_t rem = live ? (uint32_t)(wend - wa) : 0u;  // payload words not yet in the window
         // quad A holds payload words qa..qa+3 (the next one to take: ci),
         // quad B the four after it once valid, Lq the quad in flight
-        unsigned long long qa = w0 & ~3ull;
-        uint32_t ci = (uint32_t)(w0 & 3ull);
+        unsigned long long qa = wa & ~3ull;
+        uint32_t ci = (uint32_t)(wa & 3ull);
         uint32_t A[4] = {0u, 0u, 0u, 0u}, B[4] = {0u, 0u, 0u, 0u}, Lq[4] = {0u, 0u, 0u, 0u};
         bool bvalid = false, pending = false;
-        if (live && rem > 0u) hf_quad(payload, qa, w1, payload_words, vec, A);
+        if (live && rem > 0u) hf_quad(payload, qa, wend, payload_words, vec, A);
         // A arrives here: the steps below then wait on nothing but LDS
         __builtin_amdgcn_s_waitcnt(0);
         unsigned long long window = 0ull;  // bits, the next one most significant
         int have = 0;
+        if (SUB && rem > 0u) {  // the first word, less the bits before the sub-block
+            const uint32_t word = ci == 0u ? A[0] : ci == 1u ? A[1] : ci == 2u ? A[2] : A[3];
+            const int skip = (int)(bit0 & 31ull);
+            window = ((unsigned long long)word << 32) << skip;
+            have = 32 - skip;
+            ci += 1u;
+            rem -= 1u;
+        }
         bool ok = true;
+        uint32_t used = 0u;             // bits the task's codes took
         uint32_t wr = 0u, rd = 0u;      // ring bytes written, stored
         unsigned long long g = i0;      // output position of the next store
         while (__any(ok && left > 0u)) {
@@ -524,7 +590,7 @@ __global__ __launch_bounds__(256) void k_hf_decode(const uint8_t* lengths, const
                 bvalid = false;
             }
             if (!bvalid && rem > 4u - ci) {  // words past quad A
-                hf_quad(payload, qa + 4, w1, payload_words, vec, Lq);
+                hf_quad(payload, qa + 4, wend, payload_words, vec, Lq);
                 pending = true;
             }
             if (wr - rd >= 16u) {
@@ -567,12 +633,13 @@ __global__ __launch_bounds__(256) void k_hf_decode(const uint8_t* lengths, const
                 const bool pair = L2 != 0 && left > 1u && L + L2 <= have;
                 L += pair ? L2 : 0;
                 const uint32_t k = pair ? 2u : 1u;
-                if (L > 32 || L > have) {  // no code, or past the block's payload
+                if (L > 32 || L > have) {  // no code, or past the task's payload
                     ok = false;
                     continue;
                 }
                 window <<= L;
                 have -= L;
+                used += (uint32_t)L;
                 // both bytes always: a second byte of a single code lands
                 // past the ring's live bytes and is overwritten later
                 ring[wr & 31u] = (uint8_t)v;
@@ -582,7 +649,7 @@ __global__ __launch_bounds__(256) void k_hf_decode(const uint8_t* lengths, const
             }
         }
         if (!live) continue;
-        if (!ok) {
+        if (!ok || (SUB && used != sb)) {
             atomicCAS(&S->status, 0, ROIX_EINVAL);
             continue;
         }
@@ -592,7 +659,7 @@ __global__ __launch_bounds__(256) void k_hf_decode(const uint8_t* lengths, const
             g += 16;
             rd += 16u;
         }
-        for (uint32_t k = rd; k < wr; ++k) out[g + (k - rd)] = ring[k & 31u];  // the block's last bytes
+        for (uint32_t k = rd; k < wr; ++k) out[g + (k - rd)] = ring[k & 31u];  // the task's last bytes
     }
 }
 
@@ -613,9 +680,12 @@ static size_t hf_align(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t huff_scratch_bytes() { return hf_align(sizeof(HfState)) + hf_align((size_t)(kScanBlocks + 1) * 8); }
 
+
+
+
 hipError_t launch_huff_encode(const LaunchCtx& lc, const uint8_t* in, int64_t n, uint8_t* lengths,
-                              unsigned long long* block_off, uint32_t* payload, int64_t cap_words, void* scratch,
-                              roix_huff_info* info) {
+                              unsigned long long* block_off, uint16_t* sub_bits, uint32_t* payload, int64_t cap_words,
+                              void* scratch, roix_huff_info* info) {
     HfState* S = (HfState*)scratch;
     uint64_t* tmp = (uint64_t*)((uint8_t*)scratch + hf_align(sizeof(HfState)));
     const unsigned long long N = (unsigned long long)n;
@@ -629,7 +699,7 @@ hipError_t launch_huff_encode(const LaunchCtx& lc, const uint8_t* in, int64_t n,
     const int bgrid = (int)(nb < 1 ? 1 : nb < (int64_t)lc.grid_stream * 4 ? nb : (int64_t)lc.grid_stream * 4);
     if (nb > 0) {
         hipLaunchKernelGGL(k_hf_count, dim3(bgrid), dim3(kWave), 0, lc.stream, in, N, (const HfState*)S,
-                           block_off);
+                           block_off, sub_bits);
         hipError_t e = launch_scan_u64(lc, (const uint64_t*)block_off, (uint64_t*)block_off, nb,
                                        block_off + nb, tmp);
         if (e != hipSuccess) return e;
@@ -639,25 +709,31 @@ hipError_t launch_huff_encode(const LaunchCtx& lc, const uint8_t* in, int64_t n,
         hipLaunchKernelGGL(k_hf_zero_off, dim3(1), dim3(1), 0, lc.stream, block_off);
     }
     hipLaunchKernelGGL(k_hf_finalize, dim3(1), dim3(1), 0, lc.stream, (const HfState*)S,
-                       (const unsigned long long*)block_off, N, (unsigned long long)cap_words, info);
+                       (const unsigned long long*)block_off, N, (unsigned long long)cap_words, sub_bits ? 1 : 0,
+                       info);
     timer_end(lc.timer, ST_HUFF, lc.stream);
     return hipGetLastError();
 }
 
 hipError_t launch_huff_decode(const LaunchCtx& lc, const uint8_t* lengths, const unsigned long long* block_off,
-                              const uint32_t* payload, int64_t payload_words, int64_t n, uint8_t* out,
-                              void* scratch, roix_huff_info* info) {
+                              const uint16_t* sub_bits, const uint32_t* payload, int64_t payload_words, int64_t n,
+                              uint8_t* out, void* scratch, roix_huff_info* info) {
     HfState* S = (HfState*)scratch;
     const unsigned long long N = (unsigned long long)n;
     const int64_t nb = (n + kHfBlock - 1) / kHfBlock;
     timer_begin(lc.timer, ST_HUFF, lc.stream);
     hipLaunchKernelGGL(k_hf_clear, dim3(1), dim3(256), 0, lc.stream, S);
     if (nb > 0) {
-        const int64_t g = (nb + 255) / 256;
+        const int64_t tasks = sub_bits ? nb * kHfSubs : nb;
+        const int64_t g = (tasks + 255) / 256;
         const int grid = (int)(g < (int64_t)lc.grid_stream ? g : (int64_t)lc.grid_stream);
         const int vec = ((uintptr_t)payload & 15u) == 0u ? 1 : 0;
-        hipLaunchKernelGGL(k_hf_decode, dim3(grid), dim3(256), 0, lc.stream, lengths, block_off, payload,
-                           (unsigned long long)payload_words, N, out, S, vec);
+        if (sub_bits)
+            hipLaunchKernelGGL(k_hf_decode<true>, dim3(grid), dim3(256), 0, lc.stream, lengths, block_off, sub_bits,
+                               payload, (unsigned long long)payload_words, N, out, S, vec);
+        else
+            hipLaunchKernelGGL(k_hf_decode<false>, dim3(grid), dim3(256), 0, lc.stream, lengths, block_off, sub_bits,
+                               payload, (unsigned long long)payload_words, N, out, S, vec);
     }
     hipLaunchKernelGGL(k_hf_decode_finalize, dim3(1), dim3(1), 0, lc.stream, (const HfState*)S, N, info);
     timer_end(lc.timer, ST_HUFF, lc.stream);

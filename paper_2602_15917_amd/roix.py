@@ -143,10 +143,10 @@ def load():
     lib.roix_background.argtypes = [vp, vp, ci, Dims, vp, i64, ci, vp, vp]
     lib.roix_fused_background.argtypes = [vp, vp, Dims, vp, i64, Eb, P(CCriterion), P(FusedOut), vp, vp]
     lib.roix_abs_quantize.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp, vp]
-    lib.roix_huff_encode.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, vp]
+    lib.roix_huff_encode.argtypes = [vp, vp, i64, vp, vp, vp, vp, i64, vp, vp]
     lib.roix_autotune.argtypes = [vp, vp, ci, Dims, Eb, P(CCriterion), P(FusedOut), ctypes.c_int32, ctypes.c_char_p,
                                   P(TuneResult), vp]
-    lib.roix_huff_decode.argtypes = [vp, vp, vp, vp, i64, i64, vp, vp, vp]
+    lib.roix_huff_decode.argtypes = [vp, vp, vp, vp, vp, i64, i64, vp, vp, vp]
     lib.roix_abs_quantize_scratch_bytes.argtypes = [i64]
     lib.roix_section.argtypes = [vp, vp, ci, Dims, P(FusedOut), vp, i64, vp, vp]
     lib.roix_abs_quantize_scratch_bytes.restype = sz
@@ -317,6 +317,7 @@ class HuffInfo(ctypes.Structure):
 
 
 HUFF_BLOCK = 4096
+HUFF_SUBS = 16  # 256-byte sub-blocks per block in the sub-block index
 
 
 class TuneResult(ctypes.Structure):
@@ -471,10 +472,13 @@ class Context:
         _check(st, "roix_autotune")
         return res
 
-    def huff_encode(self, data: torch.Tensor, payload_cap_words: int | None = None, stream=None):
+    def huff_encode(self, data: torch.Tensor, payload_cap_words: int | None = None, stream=None,
+                    with_sub: bool = False):
         """Enqueue the Huffman stage over a contiguous uint8 tensor (taken
         flat).  Returns (lengths, block_off, payload, info); the payload holds
-        payload_cap_words words (default: enough for any input)."""
+        payload_cap_words words (default: enough for any input).  with_sub:
+        also the sub-block index, returned as a fifth item (int16 view of the
+        16 nblocks bit counts)."""
         if data.dtype != torch.uint8 or not data.is_contiguous():
             raise ValueError("huff_encode: a contiguous uint8 tensor")
         n = data.numel()
@@ -485,19 +489,23 @@ class Context:
         off = torch.zeros(nb + 1, dtype=torch.int64, device=dev)
         payload = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
         info = torch.zeros(ctypes.sizeof(HuffInfo), dtype=torch.uint8, device=dev)
-        st = load().roix_huff_encode(self.h, _ptr(data), n, _ptr(lengths), _ptr(off), _ptr(payload), cap,
-                                     _ptr(info), _stream(stream))
+        sub = torch.zeros(max(HUFF_SUBS * nb, 1), dtype=torch.int16, device=dev) if with_sub else None
+        st = load().roix_huff_encode(self.h, _ptr(data), n, _ptr(lengths), _ptr(off),
+                                     _ptr(sub) if with_sub else None, _ptr(payload), cap, _ptr(info),
+                                     _stream(stream))
         _check(st, "roix_huff_encode")
-        return lengths, off, payload, info
+        return (lengths, off, payload, info, sub) if with_sub else (lengths, off, payload, info)
 
     def huff_decode(self, lengths: torch.Tensor, off: torch.Tensor, payload: torch.Tensor, payload_words: int,
-                    n: int, dst: torch.Tensor | None = None, stream=None):
-        """Enqueue the decoder; returns (bytes, info)."""
+                    n: int, dst: torch.Tensor | None = None, stream=None, sub: torch.Tensor | None = None):
+        """Enqueue the decoder (from every sub-block's start when the
+        sub-block index `sub` is given); returns (bytes, info)."""
         if dst is None:
             dst = torch.empty(max(n, 1), dtype=torch.uint8, device=lengths.device)
         info = torch.zeros(ctypes.sizeof(HuffInfo), dtype=torch.uint8, device=lengths.device)
-        st = load().roix_huff_decode(self.h, _ptr(lengths), _ptr(off), _ptr(payload), int(payload_words), int(n),
-                                     _ptr(dst), _ptr(info), _stream(stream))
+        st = load().roix_huff_decode(self.h, _ptr(lengths), _ptr(off), _ptr(sub) if sub is not None else None,
+                                     _ptr(payload), int(payload_words), int(n), _ptr(dst), _ptr(info),
+                                     _stream(stream))
         _check(st, "roix_huff_decode")
         return dst[:n], info
 

@@ -111,8 +111,8 @@ def test_sync_argument_errors(lib):
     assert L.roix_section(fake, fake, roix.F32, d, ctypes.byref(so), (1 << 20) + 8, 16, fake, null) == roix.EINVAL
     assert L.roix_section(fake, fake, roix.F32, d, ctypes.byref(so), fake, -1, fake, null) == roix.EINVAL
     assert L.roix_section(fake, fake, 7, d, ctypes.byref(so), fake, 16, fake, null) == roix.EINVAL
-    assert L.roix_huff_encode(null, null, 0, null, null, null, 0, null, null) == roix.EINVAL
-    assert L.roix_huff_decode(null, null, null, null, 0, 0, null, null, null) == roix.EINVAL
+    assert L.roix_huff_encode(null, null, 0, null, null, null, null, 0, null, null) == roix.EINVAL
+    assert L.roix_huff_decode(null, null, null, null, null, 0, 0, null, null, null) == roix.EINVAL
     assert L.roix_autotune(null, null, roix.F32, d, eb, ctypes.byref(c), ctypes.byref(out), 1, None,
                            ctypes.byref(roix.TuneResult()), null) == roix.EINVAL
 

@@ -2,10 +2,12 @@
 block offsets and payload words identical to the oracle's on seeded byte
 sequences (uniform, peaked, constant, two-valued, heavy-tailed, the code
 stream of an extraction, the paper quantiser's output) at sizes across the
-4096-byte block edges; the GPU decoder returning the input, from the GPU's
-encoding and from the oracle's; lengths beyond 32 bits, a payload too
-small, corrupted offsets and tables; and at the full size of the benchmark
-stream, properties that hold at any size."""
+4096-byte block edges; the sub-block index (code bits of every 256-byte
+sub-block) identical to the oracle's; the GPU decoder returning the input,
+from the block starts alone and from every sub-block's start, from the
+GPU's encoding and from the oracle's; lengths beyond 32 bits, a payload too
+small, corrupted offsets, tables and sub-block indexes; and at the full size
+of the benchmark stream, properties that hold at any size."""
 import numpy as np
 import pytest
 
@@ -85,6 +87,61 @@ def test_huffman_equals_oracle(env, kind, n):
         torch.cuda.synchronize()
         assert roix.huff_info(dinfo).status == 0
         assert back.cpu().numpy().tobytes() == d.tobytes()
+
+
+SUB_SIZES = [0, 1, 255, 256, 257, 4095, 4096, 4097, 7096, 100_003, (1 << 20) + 5]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("n", SUB_SIZES)
+def test_huffman_sub_block_index(env, kind, n):
+    # the index equals the oracle's and the payload is unchanged by it; the
+    # sub-block decoder returns the input from the GPU's encoding and from
+    # the oracle's
+    ctx, roix, torch = env
+    d = data(kind, n, 8100 + n % 1013)
+    log(f"[case] huffman sub-block index kind={kind} n={n}")
+    st, oln, ooff, opay, osub = oracle.huff_encode(d, with_sub=True)
+    t = torch.from_numpy(d).to("cuda:0") if d.size else torch.zeros(16, dtype=torch.uint8, device="cuda:0")[:0]
+    ln, off, pay, info, sub = ctx.huff_encode(t, with_sub=True)
+    torch.cuda.synchronize()
+    i = roix.huff_info(info)
+    nb = len(ooff) - 1
+    assert st == 0 and i.status == 0
+    assert np.array_equal(ln.cpu().numpy(), oln) and np.array_equal(off.cpu().numpy().astype(np.uint64), ooff)
+    words = int(ooff[-1])
+    assert pay[:words].cpu().numpy().view(np.uint32).tobytes() == opay.tobytes()
+    assert np.array_equal(sub[: 16 * nb].cpu().numpy().view(np.uint16), osub)
+    assert i.compressed_bytes == 256 + 8 * len(ooff) + 4 * words + 32 * nb
+    ot = torch.from_numpy(ooff.astype(np.int64)).to("cuda:0")
+    pt = torch.from_numpy(opay.view(np.int32) if opay.size else np.zeros(1, np.int32)).to("cuda:0")
+    st_ = torch.from_numpy(osub.view(np.int16) if osub.size else np.zeros(1, np.int16)).to("cuda:0")
+    for l_, o_, p_, s_ in ((ln, off, pay, sub), (torch.from_numpy(oln).to("cuda:0"), ot, pt, st_)):
+        back, dinfo = ctx.huff_decode(l_, o_, p_, words, n, sub=s_)
+        torch.cuda.synchronize()
+        assert roix.huff_info(dinfo).status == 0
+        assert back.cpu().numpy().tobytes() == d.tobytes()
+
+
+@pytest.mark.parametrize("where", ["first", "middle", "last"])
+@pytest.mark.parametrize("delta", [1, -1])
+def test_huffman_sub_block_index_corrupted(env, where, delta):
+    # a sub-block length one bit off: the oracle and the GPU both refuse it
+    ctx, roix, torch = env
+    d = data("section", 50_000, 23)
+    st, oln, ooff, opay, osub = oracle.huff_encode(d, with_sub=True)
+    j = {"first": 0, "middle": 16 * 5 + 7, "last": (d.size - 1) // 256}[where]
+    bad = osub.astype(np.int64)
+    bad[j] += delta
+    bad = bad.astype(np.uint16)
+    assert oracle.huff_decode(oln, ooff, opay, d.size, bad)[0] == oracle.EINVAL
+    log(f"[case] huffman sub-block index {where} {delta:+d}")
+    back, dinfo = ctx.huff_decode(torch.from_numpy(oln).to("cuda:0"),
+                                  torch.from_numpy(ooff.astype(np.int64)).to("cuda:0"),
+                                  torch.from_numpy(opay.view(np.int32)).to("cuda:0"), int(ooff[-1]), d.size,
+                                  sub=torch.from_numpy(bad.view(np.int16)).to("cuda:0"))
+    torch.cuda.synchronize()
+    assert roix.huff_info(dinfo).status == roix.EINVAL
 
 
 @pytest.mark.parametrize("kind", ["section", "uniform", "two"])
@@ -181,6 +238,13 @@ def test_huffman_long_codes_and_wide_blocks(env, nsym):
     torch.cuda.synchronize()
     assert roix.huff_info(dinfo).status == 0
     assert back.cpu().numpy().tobytes() == d.tobytes()
+    # and from every sub-block's start (sub-blocks of up to 256 * 30 bits)
+    st, _, _, _, osub = oracle.huff_encode(d, with_sub=True)
+    back, dinfo = ctx.huff_decode(torch.as_tensor(ln).to("cuda:0"), torch.from_numpy(off.astype(np.int64)).to("cuda:0"),
+                                  pay, words, d.size, sub=torch.from_numpy(osub.view(np.int16)).to("cuda:0"))
+    torch.cuda.synchronize()
+    assert roix.huff_info(dinfo).status == 0
+    assert back.cpu().numpy().tobytes() == d.tobytes()
 
 
 def roix_status(env, name):
@@ -247,6 +311,24 @@ def test_huffman_full_size_stream(env):
     bits = int((hist.astype(object) * oln.astype(object)).sum())
     assert bits <= i.payload_words * 32 < bits + 32 * i.n_blocks
     back, dinfo = big.huff_decode(ln, off, pay, i.payload_words, n)
+    torch.cuda.synchronize()
+    assert roix.huff_info(dinfo).status == 0 and torch.equal(back, s)
+    # with the sub-block index: the same payload; every 256-byte sub-block's
+    # bits are the sum of its bytes' code lengths; the decoder returns the
+    # stream from every sub-block's start
+    log("[case] huffman full-size stream, sub-block index")
+    ln2, off2, pay2, info2, sub = big.huff_encode(s, with_sub=True)
+    torch.cuda.synchronize()
+    i2 = roix.huff_info(info2)
+    assert i2.status == 0 and i2.payload_words == i.payload_words
+    assert torch.equal(pay2[: i.payload_words], pay[: i.payload_words]) and torch.equal(off2, off)
+    lens = torch.from_numpy(oln.astype(np.int32)).to("cuda:0")
+    pad = torch.zeros(16 * int(i.n_blocks) * 256, dtype=torch.int32, device="cuda:0")
+    pad[:n] = lens[s.to(torch.int64)]
+    want = pad.view(-1, 256).sum(dim=1)
+    assert torch.equal(sub[: 16 * int(i.n_blocks)].to(torch.int32) & 0xFFFF, want)
+    back.zero_()
+    back, dinfo = big.huff_decode(ln2, off2, pay2, i2.payload_words, n, back, sub=sub)
     torch.cuda.synchronize()
     assert roix.huff_info(dinfo).status == 0 and torch.equal(back, s)
     big.close()
