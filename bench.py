@@ -900,6 +900,7 @@ def section_served(args):
                                                     for e, _ in ev if e[0] == "c")
         q = lambda v, p: round(float(np.percentile(v, p)), 3) if v else None
         return {"rate_per_s": rate, "requests": len(recs), "slab_requests": len(lat["slab"]), "unserved": unserved,
+                "p99_from_100_or_more": len(lat["slab"]) >= 100,
                 "trace_seconds": round(float(ev[-1][1]) * 1e-3, 1),
                 "slab_p50_ms": q(lat["slab"], 50), "slab_p99_ms": q(lat["slab"], 99),
                 "slab_max_ms": q(lat["slab"], 100), "stream_close_p50_ms": q(lat["stream_close"], 50),
@@ -910,7 +911,11 @@ def section_served(args):
     res = {}
     parity, host_plain_s = None, 0.0
     for i, rate in enumerate(rates):
-        r = replay(rate, None if i == 0 else args.served_seconds)
+        # the first rate runs the whole trace; the others run long enough for
+        # about 200 slab requests (about 80 % of the events are slabs), at
+        # least served_seconds and at most served_max_seconds
+        secs = max(args.served_seconds, min(args.served_max_seconds, 275.0 / rate)) if rate > 0 else None
+        r = replay(rate, None if i == 0 else secs)
         log(f"served rate {rate}/s: {r['slab_requests']} slabs, p50 {r['slab_p50_ms']} ms p99 {r['slab_p99_ms']} ms, "
             f"cube p50 {r['cube_p50_ms']} ms, {r['GBps']} GB/s")
         res[str(rate)] = r
@@ -1000,7 +1005,9 @@ def main():
                     help="Poisson arrival rates (requests/s); the first replays the whole trace and is checked "
                          "against plain calls")
     ap.add_argument("--served-seconds", type=float, default=30.0,
-                    help="trace seconds replayed at every rate after the first")
+                    help="least trace seconds replayed at every rate after the first")
+    ap.add_argument("--served-max-seconds", type=float, default=58.0,
+                    help="most trace seconds replayed at a rate (a rate runs for about 200 slab requests)")
     ap.add_argument("--served-budget-gib", type=float, default=64.0)
     ap.add_argument("--batch-steps", type=int, default=10, help="timed repeats of the batch and of the plain calls")
     ap.add_argument("--batch-volumes", type=int, default=64)

@@ -221,7 +221,10 @@ size_t roix_scratch_bytes(roix_dims dims, roix_dtype dtype, const roix_criterion
 /* Worst-case output capacities: rows <= nz*ny, stream <= 4*N bytes,
  * outliers <= N, components <= N (6-connectivity) or
  * ceil(nx/2)*ceil(ny/2)*ceil(nz/2) (26-connectivity).  Any pointer may be
- * NULL.  A caller that allocates these never sees ROIX_ETRUNC. */
+ * NULL.  A caller that allocates these never sees ROIX_ETRUNC.  The
+ * component bound (and so the criterion argument) is there because the
+ * fused call also writes the component table, whose worst case depends on
+ * the connectivity. */
 roix_status roix_bounds(roix_dims dims, roix_dtype dtype, const roix_criterion* crit, int64_t* max_rows,
                         int64_t* max_stream_bytes, int64_t* max_outliers, int64_t* max_components);
 
@@ -246,8 +249,13 @@ roix_status roix_segment(roix_ctx* ctx, const int32_t* d_codes, roix_dims dims, 
 /* Extract (Sec. 4.2.2): rows of d_keep and the packed codes of the voxels of
  * d_in inside each span, recomputed with the quantiser in d_qinfo.  Uses
  * out->d_rows, d_stream, d_outliers and d_einfo (the component and
- * segmentation fields are ignored).  Errors: ROIX_EINVAL (NULL arguments,
- * bad dims/dtype). */
+ * segmentation fields are ignored).  It takes the input rather than the code
+ * array of roix_quantize: a code is a function of its voxel and the
+ * resolved quantiser alone, so re-reading the span voxels (and recomputing
+ * the outlier test) gives the same codes while reading only the spans,
+ * where a code array would cost 4 bytes per voxel written and read again;
+ * outputs equal roix_fused's either way.  Errors: ROIX_EINVAL (NULL
+ * arguments, bad dims/dtype). */
 roix_status roix_extract(roix_ctx* ctx, const void* d_in, roix_dtype dtype, const uint8_t* d_keep,
                          roix_dims dims, const roix_quant_info* d_qinfo, const roix_fused_out* out,
                          void* stream);
@@ -501,7 +509,8 @@ roix_status roix_huff_decode(roix_ctx* ctx, const uint8_t* d_lengths, const uint
                              uint8_t* d_out, roix_huff_info* d_info, void* stream);
 
 /* One volume of a batch: input, shape, bound, criterion and the caller's
- * output buffers (as for roix_fused). */
+ * output buffers (as for roix_fused).  Each volume's outputs sit in its own
+ * descriptor, so one array describes the whole batch. */
 typedef struct {
     const void* d_in;
     int32_t dtype; /* roix_dtype */
@@ -519,10 +528,12 @@ typedef struct {
  * grid); the sequences are merged so that each kernel runs once for every
  * volume that needs it next, each workgroup finding its volume in a device
  * table of arguments.  Volumes whose worst-case layouts do not all fit the
- * arena at once run in consecutive groups.  The launch sequence is captured
- * into a HIP graph (batch_graph) and replayed while the batch's structure --
- * volume shapes, flows, grids -- is the same; buffer addresses may change
- * from call to call.  Asynchronous on `stream`; the argument tables are
+ * arena at once run in consecutive groups.  The merged sequence (about 70
+ * launches, whatever the number of volumes) is recorded once and kept while
+ * the batch's structure -- volume shapes, flows, grids, parameters -- is the
+ * same; buffer addresses may change from call to call.  It is issued as
+ * direct launches, or with batch_graph = 1 captured into a HIP graph and
+ * replayed.  Asynchronous on `stream`; the argument tables are
  * copied from pinned host memory the context keeps (allocated, or grown, on
  * the first batch that needs it).  Errors: ROIX_EINVAL (NULL ctx/vols, any
  * invalid descriptor), ROIX_ENOMEM (a volume does not fit the arena even
@@ -712,7 +723,9 @@ roix_status roix_slab_submit(roix_server* srv, int64_t vol_id, int64_t z0, int64
                              int ptr_is_device, int64_t* req_id);
 
 /* Enqueue the end of volume vol_id: the remaining stages and the outputs.
- * The volume's pool memory is released when the request completes.
+ * The volume's pool memory is released when the request completes.  The
+ * close is a request like a slab's: *req_id (nullable) is what roix_wait
+ * takes to learn when the outputs are complete and how long the close took.
  * Errors: ROIX_EINVAL (unknown volume), ROIX_ESEQ (slabs missing, or already
  * closed). */
 roix_status roix_volume_close(roix_server* srv, int64_t vol_id, int64_t* req_id);
