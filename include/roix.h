@@ -394,9 +394,14 @@ roix_status roix_fused_background(roix_ctx* ctx, const float* d_in, roix_dims di
  * info.status: the extraction's own error if it had one (nothing written),
  * ROIX_ETRUNC when n_codes > section_cap (nothing written), ROIX_EINVAL when
  * the row table or the stream is not whole or does not cover every code.
- * Needs no arena.  Asynchronous on `stream`.
+ * The context's arena holds a list of the escaped codes while the call runs
+ * (32 KB of counts, then 8 bytes per escape, split evenly over up to 4096
+ * workgroups; escapes beyond a workgroup's share are resolved in the
+ * streaming pass, with the same result, more slowly).  Asynchronous on
+ * `stream`.
  * Errors: ROIX_EINVAL (NULL ctx/out/d_info/info pointers, bad dims or dtype,
- * misaligned buffers, negative capacity), ROIX_EDEVICE. */
+ * misaligned buffers, negative capacity), ROIX_ENOMEM (arena under 32 KB),
+ * ROIX_EDEVICE. */
 typedef struct {
     int32_t status;
     int32_t pad;

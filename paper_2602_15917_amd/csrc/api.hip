@@ -606,7 +606,9 @@ roix_status roix_section(roix_ctx* ctx, const void* d_in, roix_dtype dtype, roix
     if (out->rows_cap > 0 && (!out->d_rows || !aligned(out->d_rows, 8))) return ROIX_EINVAL;
     if (out->stream_cap_bytes > 0 && (!out->d_stream || !aligned(out->d_stream, 16))) return ROIX_EINVAL;
     if (section_cap > 0 && (!d_section || !aligned(d_section, 16))) return ROIX_EINVAL;
-    ROIX_TRY(launch_section(lctx(ctx, stream), d_in, dtype, g, out, d_section, section_cap, d_info));
+    if (ctx->arena_bytes < section_scratch_bytes()) return ROIX_ENOMEM;
+    ROIX_TRY(launch_section(lctx(ctx, stream), d_in, dtype, g, out, d_section, section_cap, d_info, ctx->arena,
+                            ctx->arena_bytes));
     return ROIX_OK;
 }
 

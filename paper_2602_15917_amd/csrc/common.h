@@ -493,8 +493,10 @@ hipError_t launch_huff_encode(const LaunchCtx& lc, const uint8_t* in, int64_t n,
 hipError_t launch_huff_decode(const LaunchCtx& lc, const uint8_t* lengths, const unsigned long long* block_off,
                               const uint16_t* sub_bits, const uint32_t* payload, int64_t payload_words, int64_t n,
                               uint8_t* out, void* scratch, roix_huff_info* info);
+size_t section_scratch_bytes();  // the escape list's counter; the list takes the rest of the arena
 hipError_t launch_section(const LaunchCtx& lc, const void* in, roix_dtype dt, const Geom& g,
-                          const roix_fused_out* o, uint8_t* out, int64_t out_cap, roix_section_info* info);
+                          const roix_fused_out* o, uint8_t* out, int64_t out_cap, roix_section_info* info,
+                          void* scratch, size_t scratch_bytes);
 hipError_t launch_absq(const LaunchCtx& lc, const uint8_t* D, int64_t m, uint32_t K, uint8_t* Q, void* scratch,
                        roix_absq_info* info);
 hipError_t launch_flatten(const LaunchCtx& lc, const Layout& L);

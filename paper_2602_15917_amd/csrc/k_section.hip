@@ -7,15 +7,31 @@
 // stream (1, 2 or 4 bytes per code) and writes one byte per code, flat and
 // coalesced, with no row table in the way.  Only an escaped code (an
 // outlier, whose q is not stored) needs its voxel: a binary search over the
-// rows' first codes gives its row and the voxel is requantised.  Escapes are
-// rare, so this costs nothing on the common path.
+// rows' first codes gives its row and the voxel is requantised.  That search
+// is a chain of dependent loads which would stall its whole wave, so the
+// streaming pass only lists the escaped codes (in the context's arena, each
+// workgroup in a part of its own, counted in LDS) and a second kernel
+// resolves them, one thread each.
 #include "common.h"
 
 namespace roix {
 
 // The call's status and code count, checked once before the pass.
+// The escape list: workgroup w lists its escaped codes in
+// list[w * per .. (w + 1) * per) and their number in count[w] (which may
+// exceed per: the rest were resolved in place).
+struct SecEsc {
+    unsigned long long* count;  // ngroups entries
+    unsigned long long* list;
+    unsigned long long per;
+    uint32_t ngroups;
+};
+
 __global__ void k_section_check(const roix_quant_info* __restrict__ qi, const roix_extract_info* __restrict__ ei,
-                                int64_t rows_cap, int64_t stream_cap, int64_t out_cap, roix_section_info* info) {
+                                int64_t rows_cap, int64_t stream_cap, int64_t out_cap, roix_section_info* info,
+                                SecEsc esc) {
+    for (uint32_t w = threadIdx.x; w < esc.ngroups; w += blockDim.x) esc.count[w] = 0ull;
+    if (threadIdx.x != 0) return;
     int32_t st = qi->status != ROIX_OK ? qi->status : ei->status;
     const uint64_t n = ei->n_codes;
     if (st == ROIX_OK) {
@@ -104,7 +120,8 @@ __device__ __forceinline__ uint32_t code_at(const uint4 (&w)[B], int i) {
 template <typename T, int B>
 __device__ __forceinline__ v4u32_t levels16(const uint4 (&w)[B], uint64_t c0, const T* __restrict__ in, int64_t nx,
                                             int64_t ny, int64_t nz, const roix_row* __restrict__ rows, uint64_t nr,
-                                            const SecParams& p, roix_section_info* info) {
+                                            const SecParams& p, roix_section_info* info, const SecEsc& esc,
+                                            uint32_t* s_cnt) {
     uint32_t o[4] = {0u, 0u, 0u, 0u};
     uint32_t emask = 0;
 #pragma unroll
@@ -113,9 +130,14 @@ __device__ __forceinline__ v4u32_t levels16(const uint4 (&w)[B], uint64_t c0, co
         emask |= (uint32_t)(u == p.esc) << i;
         o[i / 4] |= (u == p.esc ? 0u : sec_level(u, p)) << (8 * (i & 3));
     }
-    while (emask) {
+    while (emask) {  // listed for the escape kernel (their level stays 0 here), or resolved in place
         const int i = __builtin_ctz(emask);
         emask &= emask - 1u;
+        const uint32_t slot = atomicAdd(s_cnt, 1u);
+        if (slot < esc.per) {
+            esc.list[(unsigned long long)blockIdx.x * esc.per + slot] = c0 + (uint64_t)i;
+            continue;
+        }
         const uint32_t sh = 8u * (uint32_t)(i & 3);
         const uint32_t v = sec_escape(in, nx, ny, nz, rows, nr, c0 + (uint64_t)i, p, info) << sh;
         const int k = i >> 2;
@@ -142,7 +164,8 @@ constexpr int sec_unroll() { return B == 4 ? 2 : 4; }
 template <typename T, int B>
 __device__ void section_pass(const T* __restrict__ in, int64_t nx, int64_t ny, int64_t nz,
                              const roix_row* __restrict__ rows, uint64_t nr, const uint8_t* __restrict__ stream,
-                             uint64_t n, const SecParams& p, uint8_t* __restrict__ out, roix_section_info* info) {
+                             uint64_t n, const SecParams& p, uint8_t* __restrict__ out, roix_section_info* info,
+                             const SecEsc& esc, uint32_t* s_cnt) {
     const uint64_t nu = n / kSecCodes;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -162,7 +185,7 @@ __device__ void section_pass(const T* __restrict__ in, int64_t nx, int64_t ny, i
         for (int k = 0; k < kSecUnroll; ++k) {
             const uint64_t u = u0 + k * stride;
             if (u < nu) {
-                const v4u32_t t = levels16<T, B>(w[k], u * kSecCodes, in, nx, ny, nz, rows, nr, p, info);
+                const v4u32_t t = levels16<T, B>(w[k], u * kSecCodes, in, nx, ny, nz, rows, nr, p, info, esc, s_cnt);
                 __builtin_nontemporal_store(t, reinterpret_cast<v4u32_t*>(out + u * kSecCodes));
             }
         }
@@ -187,43 +210,82 @@ __global__ __launch_bounds__(kBlock) void k_section(const T* __restrict__ in, in
                                                     const roix_extract_info* __restrict__ ei,
                                                     const roix_row* __restrict__ rows,
                                                     const uint8_t* __restrict__ stream, uint8_t* __restrict__ out,
-                                                    roix_section_info* info) {
-    if (info->status != ROIX_OK || qi->width_bits != 8 * B) return;
+                                                    roix_section_info* info, SecEsc esc) {
+    if (info->status != ROIX_OK || qi->width_bits != 8 * B) return;  // (uniform)
+    __shared__ uint32_t s_cnt;  // this workgroup's listed escapes
+    if (threadIdx.x == 0) s_cnt = 0u;
+    __syncthreads();
     const SecParams p = sec_params(qi);
-    section_pass<T, B>(in, nx, ny, nz, rows, ei->n_rows, stream, ei->n_codes, p, out, info);
+    section_pass<T, B>(in, nx, ny, nz, rows, ei->n_rows, stream, ei->n_codes, p, out, info, esc, &s_cnt);
+    __syncthreads();
+    if (threadIdx.x == 0) esc.count[blockIdx.x] = s_cnt;
+}
+
+// The listed escapes, a thread each: the row search, the voxel, its level.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_section_escapes(const T* __restrict__ in, int64_t nx, int64_t ny,
+                                                            int64_t nz, const roix_quant_info* __restrict__ qi,
+                                                            const roix_extract_info* __restrict__ ei,
+                                                            const roix_row* __restrict__ rows,
+                                                            uint8_t* __restrict__ out, roix_section_info* info,
+                                                            SecEsc esc) {
+    if (info->status != ROIX_OK) return;
+    const SecParams p = sec_params(qi);
+    const uint64_t nr = ei->n_rows;
+    for (uint32_t w = blockIdx.x; w < esc.ngroups; w += gridDim.x) {  // workgroup w's part of the list
+        const unsigned long long cnt = esc.count[w], m = cnt < esc.per ? cnt : esc.per;
+        for (unsigned long long i = threadIdx.x; i < m; i += blockDim.x) {
+            const uint64_t c = esc.list[(unsigned long long)w * esc.per + i];
+            out[c] = (uint8_t)sec_escape(in, nx, ny, nz, rows, nr, c, p, info);
+        }
+    }
 }
 
 template <typename T, int B>
 static hipError_t launch_section_w(const LaunchCtx& lc, const T* in, const Geom& g, const roix_fused_out* o,
-                                   uint8_t* out, roix_section_info* info) {
+                                   uint8_t* out, roix_section_info* info, const SecEsc& esc) {
     // one workgroup per resident slot: every workgroup takes the same share
     // of the grid-stride loop, so a grid of whole residency rounds keeps the
     // last round from running on a fraction of the chip
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_section<T, B>, kBlock, 0);
     if (e != hipSuccess) return e;
-    const int wgs = lc.cus > 0 && per_cu > 0 ? lc.cus * per_cu : lc.grid_stream;
+    int wgs = lc.cus > 0 && per_cu > 0 ? lc.cus * per_cu : lc.grid_stream;
+    wgs = wgs < (int)esc.ngroups ? wgs : (int)esc.ngroups;  // a part of the escape list each
     hipLaunchKernelGGL((k_section<T, B>), dim3(wgs), dim3(kBlock), 0, lc.stream, in, g.nx, g.ny, g.nz, o->d_qinfo,
-                       o->d_einfo, o->d_rows, (const uint8_t*)o->d_stream, out, info);
+                       o->d_einfo, o->d_rows, (const uint8_t*)o->d_stream, out, info, esc);
     return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t launch_section_t(const LaunchCtx& lc, const T* in, const Geom& g, const roix_fused_out* o,
-                                   uint8_t* out, roix_section_info* info) {
+                                   uint8_t* out, roix_section_info* info, const SecEsc& esc) {
     hipError_t e;
-    if ((e = launch_section_w<T, 2>(lc, in, g, o, out, info)) != hipSuccess) return e;
-    if ((e = launch_section_w<T, 1>(lc, in, g, o, out, info)) != hipSuccess) return e;
-    return launch_section_w<T, 4>(lc, in, g, o, out, info);
+    if ((e = launch_section_w<T, 2>(lc, in, g, o, out, info, esc)) != hipSuccess) return e;
+    if ((e = launch_section_w<T, 1>(lc, in, g, o, out, info, esc)) != hipSuccess) return e;
+    if ((e = launch_section_w<T, 4>(lc, in, g, o, out, info, esc)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_section_escapes<T>, dim3(esc.ngroups), dim3(kBlock), 0, lc.stream, in, g.nx, g.ny, g.nz,
+                       o->d_qinfo, o->d_einfo, o->d_rows, out, info, esc);
+    return hipGetLastError();
 }
 
+constexpr uint32_t kSecGroups = 4096;  // at most this many workgroups of the streaming pass (one count each)
+
+size_t section_scratch_bytes() { return (size_t)kSecGroups * 8; }
+
 hipError_t launch_section(const LaunchCtx& lc, const void* in, roix_dtype dt, const Geom& g,
-                          const roix_fused_out* o, uint8_t* out, int64_t out_cap, roix_section_info* info) {
+                          const roix_fused_out* o, uint8_t* out, int64_t out_cap, roix_section_info* info,
+                          void* scratch, size_t scratch_bytes) {
+    SecEsc esc;
+    esc.ngroups = kSecGroups;
+    esc.count = (unsigned long long*)scratch;
+    esc.list = (unsigned long long*)((uint8_t*)scratch + section_scratch_bytes());
+    esc.per = scratch_bytes > section_scratch_bytes() ? (scratch_bytes - section_scratch_bytes()) / 8 / kSecGroups : 0;
     timer_begin(lc.timer, ST_SECTION, lc.stream);
-    hipLaunchKernelGGL(k_section_check, dim3(1), dim3(1), 0, lc.stream, o->d_qinfo, o->d_einfo, o->rows_cap,
-                       o->stream_cap_bytes, out_cap, info);
-    const hipError_t e = dt == ROIX_F32 ? launch_section_t(lc, (const float*)in, g, o, out, info)
-                                        : launch_section_t(lc, (const uint16_t*)in, g, o, out, info);
+    hipLaunchKernelGGL(k_section_check, dim3(1), dim3(256), 0, lc.stream, o->d_qinfo, o->d_einfo, o->rows_cap,
+                       o->stream_cap_bytes, out_cap, info, esc);
+    const hipError_t e = dt == ROIX_F32 ? launch_section_t(lc, (const float*)in, g, o, out, info, esc)
+                                        : launch_section_t(lc, (const uint16_t*)in, g, o, out, info, esc);
     timer_end(lc.timer, ST_SECTION, lc.stream);
     return e != hipSuccess ? e : hipGetLastError();
 }

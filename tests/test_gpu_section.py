@@ -3,8 +3,9 @@ through the C ABI: roix_section on the outputs of a roix_fused call against
 the oracle's section of the same extraction, byte for byte, for code widths
 of 8, 16 and 32 bits, float32 and uint16 volumes, escaped codes, more codes
 than one sweep of the grid covers, ragged tails, an empty region of
-interest, a short output buffer and an extraction that failed; and the
-paper's quantiser on the section against the oracle's."""
+interest, a short output buffer, an extraction that failed and an escape
+list larger than the arena holds; and the paper's quantiser on the section
+against the oracle's."""
 import numpy as np
 import pytest
 
@@ -86,6 +87,31 @@ def test_section_equals_oracle(env, name):
     assert bad.size == 0, f"{bad.size} levels differ, first at {bad[0]}: gpu {got[bad[0]]} oracle {want[bad[0]]}"
     if name in WITH_ESCAPES:
         assert int(o["info"].n_outliers) > 0  # escaped codes went through the row search
+
+
+def test_section_escape_list_overflow(env):
+    # an arena with room for one listed escape per workgroup of the
+    # streaming pass: most of this extraction's 2556 escapes (in few
+    # workgroups: 157 645 codes) are resolved in the streaming pass, with the
+    # same levels
+    ctx, roix, torch = env
+    vol, ebm, ebv, c = make_case("normal w32 ragged rows")
+    crit = criterion(roix, c)
+    caps = default_caps(roix, vol, crit)
+    t = torch.from_numpy(vol).to("cuda:0")
+    out = roix.Outputs("cuda:0", *caps)
+    ctx.fused(t, ebm, ebv, crit, out)
+    small = roix.Context(0, 2 * 8 * 4096)
+    log("[case] section with one listed escape per workgroup")
+    sec, info = small.section(t, out)
+    torch.cuda.synchronize()
+    small.close()
+    o = oracle_fused(vol, ebm, ebv, crit, caps)
+    n = int(o["info"].n_codes)
+    assert int(o["info"].n_outliers) > 2000
+    assert roix.section_info(info).status == 0
+    st, want = oracle.section(vol, o["params"], o["rows"], n)
+    assert np.array_equal(sec[:n].cpu().numpy(), want)
 
 
 def test_section_empty_roi(env):
