@@ -1,10 +1,12 @@
 // k_scan.hip - exclusive prefix sums with a fixed workgroup count.
 //
-// Reduce-then-scan in three launches: kScanBlocks workgroups each reduce one
-// contiguous chunk, one workgroup scans the chunk sums, then every workgroup
-// rescans its chunk with its offset.  The element count may live in device
-// memory (the number of runs is only known on the device), so the grid never
-// depends on data and the whole sequence needs no host synchronisation.
+// Reduce-then-scan in two launches: G <= kScanBlocks workgroups each reduce
+// one contiguous chunk, then every workgroup sums the chunk sums before its
+// own (at most kScanBlocks - 1 of them, read from L2) and rescans its chunk
+// from that offset; the last workgroup also writes the total.  The element
+// count may live in device memory (the number of runs is only known on the
+// device), so the grid never depends on data and the whole sequence needs no
+// host synchronisation.
 #include "common.h"
 
 namespace roix {
@@ -65,37 +67,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const T* __restrict__ in
     k_scan_reduce_body<T>(hw_part(), in, n_host, n_dev, tmp);
 }
 
-// one workgroup of kScanBlocks threads over the G <= kScanBlocks chunk sums
-template <typename TT>
-__device__ __forceinline__ void k_scan_top_body(const VPart vp, uint64_t* tmp, TT* total_out, TT* out_end, DevState* cS,
-                                                          uint64_t cap, int cerr, int G) {
-    __shared__ uint64_t s[kScanBlocks];
-    const int t = threadIdx.x;
-    const uint64_t mine = t < G ? tmp[t] : 0ull;
-    s[t] = mine;
-    __syncthreads();
-    for (int o = 1; o < kScanBlocks; o <<= 1) {
-        uint64_t a = t >= o ? s[t - o] : 0ull;
-        __syncthreads();
-        s[t] += a;
-        __syncthreads();
-    }
-    uint64_t incl = s[t];
-    if (t < G) tmp[t] = incl - mine;  // exclusive
-    if (t == kScanBlocks - 1) {
-        tmp[kScanBlocks] = incl;
-        if (total_out) *total_out = (TT)incl;
-        if (out_end) *out_end = (TT)incl;
-        if (cS && incl > cap) fail(cS, cerr);
-    }
-}
-template <typename TT>
-__global__ __launch_bounds__(kScanBlocks) void k_scan_top(uint64_t* tmp, TT* total_out, TT* out_end, DevState* cS,
-                                                          uint64_t cap, int cerr, int G) {
-    k_scan_top_body<TT>(hw_part(), tmp, total_out, out_end, cS, cap, cerr, G);
-}
-
-// As k_scan_top, continuing from a device base: every offset is shifted by
+// The top level of the streamed-slab scan, continuing from a device base: every offset is shifted by
 // *base, then *lo_out = the old base and *base = *out_end = base + total.
 __global__ __launch_bounds__(kScanBlocks) void k_scan_top_base(uint64_t* tmp, uint32_t* base, uint32_t* lo_out,
                                                               uint32_t* out_end, DevState* cS, uint64_t cap,
@@ -124,10 +96,61 @@ __global__ __launch_bounds__(kScanBlocks) void k_scan_top_base(uint64_t* tmp, ui
     }
 }
 
-template <typename T>
+// The sum of tmp[0 .. b) (chunk sums before chunk b), by the whole workgroup.
+__device__ __forceinline__ uint64_t chunk_offset(const uint64_t* tmp, uint32_t b) {
+    uint64_t s = 0;
+    for (uint32_t i = threadIdx.x; i < b; i += blockDim.x) s += tmp[i];
+    s = wave_sum(s);
+    __shared__ uint64_t s_w[kBlock / kWave];
+    if (threadIdx.x % kWave == 0) s_w[threadIdx.x / kWave] = s;
+    __syncthreads();
+    uint64_t t = 0;
+#pragma unroll
+    for (int k = 0; k < kBlock / kWave; ++k) t += s_w[k];
+    __syncthreads();
+    return t;
+}
+
+template <typename T, typename TT>
 __device__ __forceinline__ void k_scan_down_body(const VPart vp, const T* in, T* out, int64_t n_host, const uint32_t* n_dev,
-                                                      const uint64_t* tmp) {
+                                                      const uint64_t* tmp, TT* total_out, TT* out_end, DevState* cS,
+                                                      uint64_t cap, int cerr) {
     const int64_t n = scan_n(n_host, n_dev);
+    const int64_t chunk = (n + vp.n - 1) / vp.n;
+    const int64_t lo = (int64_t)vp.b * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    __shared__ T s_w[kBlock / kWave];
+    const uint64_t off = chunk_offset(tmp, vp.b);
+    T carry = (T)off;
+    for (int64_t base = lo; base < hi; base += blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        T v = i < hi ? in[i] : (T)0;
+        T tot;
+        T e = block_excl_scan<T>(v, s_w, tot);
+        if (i < hi) out[i] = carry + e;
+        carry += tot;
+    }
+    if (vp.b == vp.n - 1 && threadIdx.x == 0) {  // the last chunk: the total
+        const uint64_t total = off + tmp[vp.b];
+        if (total_out) *total_out = (TT)total;
+        if (out_end) *out_end = (TT)total;
+        if (cS && total > cap) fail(cS, cerr);
+    }
+}
+template <typename T, typename TT>
+__global__ __launch_bounds__(kBlock) void k_scan_down(const T* in, T* out, int64_t n_host, const uint32_t* n_dev,
+                                                      const uint64_t* tmp, TT* total_out, TT* out_end, DevState* cS,
+                                                      uint64_t cap, int cerr) {
+    k_scan_down_body<T, TT>(hw_part(), in, out, n_host, n_dev, tmp, total_out, out_end, cS, cap, cerr);
+}
+
+// The same continuing from a device base (streamed slabs): every offset is
+// shifted by *base, then *lo_out = the old base and *base = *out_end =
+// base + total (one workgroup after the chunk sums).
+template <typename T>
+__device__ __forceinline__ void k_scan_down_plain_body(const VPart vp, const T* in, T* out, int64_t n_host,
+                                                            const uint64_t* tmp) {
+    const int64_t n = n_host;
     const int64_t chunk = (n + vp.n - 1) / vp.n;
     const int64_t lo = (int64_t)vp.b * chunk;
     const int64_t hi = lo + chunk < n ? lo + chunk : n;
@@ -143,9 +166,8 @@ __device__ __forceinline__ void k_scan_down_body(const VPart vp, const T* in, T*
     }
 }
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_scan_down(const T* in, T* out, int64_t n_host, const uint32_t* n_dev,
-                                                      const uint64_t* tmp) {
-    k_scan_down_body<T>(hw_part(), in, out, n_host, n_dev, tmp);
+__global__ __launch_bounds__(kBlock) void k_scan_down_plain(const T* in, T* out, int64_t n_host, const uint64_t* tmp) {
+    k_scan_down_plain_body<T>(hw_part(), in, out, n_host, tmp);
 }
 
 // the chunk count of a scan: kScanBlocks, or fewer for a batch's small volumes
@@ -160,10 +182,9 @@ hipError_t launch_scan_u32(const LaunchCtx& lc, const uint32_t* in, uint32_t* ou
     const int G = scan_grid(lc);
     launch_k<kBlock, k_scan_reduce_body<uint32_t>>(lc, k_scan_reduce<uint32_t>, dim3(G), dim3(kBlock), 0, in,
                                                    n_host, n_dev, tmp);
-    launch_k<kScanBlocks, k_scan_top_body<uint32_t>>(lc, k_scan_top<uint32_t>, dim3(1), dim3(kScanBlocks), 0, tmp,
-                                                     total_out, out_end, cap_S, cap, cap_err, G);
-    launch_k<kBlock, k_scan_down_body<uint32_t>>(lc, k_scan_down<uint32_t>, dim3(G), dim3(kBlock), 0, in, out,
-                                                 n_host, n_dev, (const uint64_t*)tmp);
+    launch_k<kBlock, k_scan_down_body<uint32_t, uint32_t>>(lc, k_scan_down<uint32_t, uint32_t>, dim3(G), dim3(kBlock), 0,
+                                                           in, out, n_host, n_dev, (const uint64_t*)tmp, total_out,
+                                                           out_end, cap_S, cap, cap_err);
     timer_end(lc.timer, ST_SCAN, lc.stream);
     return hipGetLastError();
 }
@@ -177,8 +198,8 @@ hipError_t launch_scan_u32_base(const LaunchCtx& lc, const uint32_t* in, uint32_
                        (const uint32_t*)nullptr, tmp);
     hipLaunchKernelGGL(k_scan_top_base, dim3(1), dim3(kScanBlocks), 0, lc.stream, tmp, base, lo_out, out_end, cap_S,
                        cap, cap_err);
-    hipLaunchKernelGGL(k_scan_down<uint32_t>, dim3(kScanBlocks), dim3(kBlock), 0, lc.stream, in, out, n_host,
-                       (const uint32_t*)nullptr, (const uint64_t*)tmp);
+    hipLaunchKernelGGL(k_scan_down_plain<uint32_t>, dim3(kScanBlocks), dim3(kBlock), 0, lc.stream, in, out, n_host,
+                       (const uint64_t*)tmp);
     timer_end(lc.timer, ST_SCAN, lc.stream);
     return hipGetLastError();
 }
@@ -189,12 +210,10 @@ hipError_t launch_scan_u64(const LaunchCtx& lc, const uint64_t* in, uint64_t* ou
     const int G = scan_grid(lc);
     launch_k<kBlock, k_scan_reduce_body<uint64_t>>(lc, k_scan_reduce<uint64_t>, dim3(G), dim3(kBlock), 0, in,
                                                    n_host, (const uint32_t*)nullptr, tmp);
-    launch_k<kScanBlocks, k_scan_top_body<unsigned long long>>(lc, k_scan_top<unsigned long long>, dim3(1),
-                                                               dim3(kScanBlocks), 0, tmp, total_out,
-                                                               (unsigned long long*)nullptr, (DevState*)nullptr, 0ull,
-                                                               0, G);
-    launch_k<kBlock, k_scan_down_body<uint64_t>>(lc, k_scan_down<uint64_t>, dim3(G), dim3(kBlock), 0, in, out,
-                                                 n_host, (const uint32_t*)nullptr, (const uint64_t*)tmp);
+    launch_k<kBlock, k_scan_down_body<uint64_t, unsigned long long>>(
+        lc, k_scan_down<uint64_t, unsigned long long>, dim3(G), dim3(kBlock), 0, in, out, n_host,
+        (const uint32_t*)nullptr, (const uint64_t*)tmp, total_out, (unsigned long long*)nullptr, (DevState*)nullptr,
+        0ull, 0);
     timer_end(lc.timer, ST_SCAN, lc.stream);
     return hipGetLastError();
 }
