@@ -2,8 +2,8 @@
 // path with one launch per stage for all of them.
 //
 // Each volume's plain launch sequence is recorded (body, grid, arguments) on
-// its own part of the arena, with its grids scaled to its share of the
-// group's voxels.  The sequences are merged: each step launches one body for
+// its own part of the arena; the voxel-proportional passes then split their
+// grid among the volumes of each merged launch by voxels.  The sequences are merged: each step launches one body for
 // every volume whose next launch it is, so each volume's launches keep their
 // order and a batch takes about as many launches as one volume, whatever
 // the number of volumes.  The argument tables of all launches go to the
@@ -162,9 +162,7 @@ roix_status plan_batch(roix_ctx* ctx, int32_t n, const roix_volume_desc* vols, c
 
     for (const auto& gr : groups) {
         const int i0 = gr.first, i1 = gr.second;
-        double tot = 0.0;
-        for (int i = i0; i < i1; ++i) tot += (double)gs[i].N;
-        std::vector<Recorder> rec((size_t)(i1 - i0));
+        std::vector<Recorder> rec((size_t)(i1 - i0)), half((size_t)(i1 - i0));
         size_t off = 0;
         for (int i = i0; i < i1; ++i) {
             const roix_volume_desc& d = vols[i];
@@ -174,28 +172,54 @@ roix_status plan_batch(roix_ctx* ctx, int32_t n, const roix_volume_desc* vols, c
             if (i1 - i0 == 1) k = proxy_kind_for(gs[i], (roix_dtype)d.dtype, bytes, ctx->batch_p16_min);
             if (!carve_at(base + off, bytes, gs[i], &L, k)) return ROIX_ENOMEM;
             off += bytes;
-            // the plain launch parameters; the passes whose work follows the
-            // voxels (range, quantise + histogram, mask words and runs) get
-            // the volume's share of their grid.  The others keep the plain
+            // the plain launch parameters, recorded twice: as they are, and
+            // with the grids of the passes whose work follows the voxels
+            // (range, quantise + histogram, mask words and runs) halved,
+            // which tells those launches apart.  The others keep the plain
             // grid: their work follows runs, components or codes, which only
             // the device knows, and a volume of few voxels may hold many.
-            LaunchCtx lc = lctx(ctx, stream);
-            lc.timer = nullptr;
-            lc.rec = &rec[(size_t)(i - i0)];
-            const double share = (double)gs[i].N / tot;
-            auto sc = [&](int v, int lo) {
-                const int s = (int)std::lround((double)v * share);
-                return std::max(lo, std::min(v, s));
-            };
-            lc.grid_read = sc(ctx->grid_read, 4);
-            lc.grid_mask = sc(ctx->grid_mask, 8);
-            lc.grid_vox = sc(ctx->grid_stream, 8);
-            const roix_status st = enqueue_fused(lc, gs[i], L, d.d_in, (roix_dtype)d.dtype, d.eb, &d.crit, &d.out);
-            if (st != ROIX_OK) return st;
-            if (rec[(size_t)(i - i0)].bad) return ROIX_EDEVICE;
+            for (int pass = 0; pass < 2; ++pass) {
+                LaunchCtx lc = lctx(ctx, stream);
+                lc.timer = nullptr;
+                lc.rec = pass == 0 ? &rec[(size_t)(i - i0)] : &half[(size_t)(i - i0)];
+                const double share = pass == 0 ? 1.0 : 0.5;
+                auto sc = [&](int v, int lo) {
+                    const int s = (int)std::lround((double)v * share);
+                    return std::max(lo, std::min(v, s));
+                };
+                lc.grid_read = sc(ctx->grid_read, 4);
+                lc.grid_mask = sc(ctx->grid_mask, 8);
+                lc.grid_vox = sc(ctx->grid_stream, 8);
+                const roix_status st =
+                    enqueue_fused(lc, gs[i], L, d.d_in, (roix_dtype)d.dtype, d.eb, &d.crit, &d.out);
+                if (st != ROIX_OK) return st;
+                if (lc.rec->bad) return ROIX_EDEVICE;
+            }
+            if (half[(size_t)(i - i0)].seq.size() != rec[(size_t)(i - i0)].seq.size()) return ROIX_EDEVICE;
         }
         std::vector<Merged> ms;
         merge(rec, ms);
+        // A merged launch of a voxel-proportional pass splits its plain grid
+        // among its own volumes by their voxels (volumes of one group take
+        // different kernels -- flows, row alignments -- so a share of the
+        // whole group's voxels would leave each such launch part of the chip).
+        for (const Merged& m : ms) {
+            bool prop = false;
+            uint32_t cap = 0;
+            double nsum = 0.0;
+            for (const auto& w : m.who) {
+                const uint32_t g = rec[(size_t)w.first].seq[w.second].grid;
+                prop = prop || half[(size_t)w.first].seq[w.second].grid < g;
+                cap = std::max(cap, g);
+                nsum += (double)gs[i0 + w.first].N;
+            }
+            if (!prop || nsum <= 0.0) continue;
+            for (const auto& w : m.who) {
+                uint32_t& g = rec[(size_t)w.first].seq[w.second].grid;
+                const double want = std::round((double)cap * (double)gs[i0 + w.first].N / nsum);
+                g = std::min(g, std::max<uint32_t>(std::min<uint32_t>(g, 8u), (uint32_t)want));
+            }
+        }
         if (!pack(rec, ms, blob)) return ROIX_EINVAL;
         all.insert(all.end(), ms.begin(), ms.end());
     }
