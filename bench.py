@@ -32,7 +32,7 @@ def log(msg):
 STAGE_SOURCE = {"range": "k_quant.hip", "quant_hist": "k_quant.hip", "quant_range16": "k_quant.hip",
                 "mask_runs": "k_label.hip", "emit": "k_extract.hip"}
 STAGE_KERNEL = {"range": "k_range<float>", "quant_hist": "k_quant_hist<float, false, false, 1, true>",
-                "quant_range16": "k_quant_range16<false>", "mask_runs": "k_mask_runs", "emit": "k_emit_codes_p16"}
+                "quant_range16": "k_quant_range16<false>", "mask_runs": "k_mask_runs", "emit": "k_emit_codes_f32"}
 CALIB_BYTES = 1 << 30
 
 

@@ -18,6 +18,7 @@ constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kHistCopies = 32;      // LDS-privatised histogram copies (one per half-wave lane)
 constexpr int kHistStride = 257;     // copy stride: lane c + bin b lands in bank (c + b) mod 32
 constexpr int kScanBlocks = 1024;    // fixed block count of the device-sized scans
+constexpr int kKeepGrid = 512;       // workgroups of the keep rule
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kQrFine = 1 << 15;  // code classes (q mod 2^15) of the fused 16-bit proxy pass
 constexpr int kQrBlocks = 256;    // workgroups of that pass (one LDS class table each)
@@ -79,6 +80,11 @@ struct DevState {
     int32_t n_classes;
     double mo_val[kMoParts];
     unsigned long long mo_rank[kMoParts];
+    // LARGEST: the keep workgroups done, and each one's largest size and the
+    // first component holding it
+    uint32_t done_keep, pad2;
+    unsigned long long keep_size[kKeepGrid];
+    uint32_t keep_cid[kKeepGrid];
 };
 
 // Per-call view of the scratch arena.
@@ -202,6 +208,27 @@ __device__ __forceinline__ uint32_t ld_relaxed(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_relaxed(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Hand-offs between the workgroups of one launch use no cache maintenance
+// (a device-scope fence writes back and invalidates a whole L2 on this
+// chip, and costs tens of microseconds when every workgroup issues one).
+// Instead the words handed over are written and read only with device-scope
+// atomic accesses, which are coherent across the XCDs' L2s, and a wave that
+// signals first waits for its own memory operations to complete; the signal
+// fences keep the compiler from moving memory accesses across the wait.
+__device__ __forceinline__ void wait_mem() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+template <typename T>
+__device__ __forceinline__ T ld_dev(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_dev(T* p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -456,9 +483,22 @@ hipError_t launch_serve_status(const LaunchCtx& lc, DevState* S, int save);
 // n_dev is not null (then n_host is only an upper bound).  total_out and
 // out_end (nullable) receive the sum of all elements.  With cap_S, a total
 // above cap fails cap_S with cap_err.
+// The component-id scan (ci non-null) also writes the entry of each
+// component below ci->cap (its root run's first voxel as the label, size 0,
+// an empty box, not kept) and clears its kept flag, unless the call has
+// failed.
+struct CompInit {
+    const uint32_t* xs;
+    const uint32_t* run_row;
+    int64_t nx;
+    roix_component* comps;
+    uint8_t* kept_flag;
+    uint64_t cap;
+};
 hipError_t launch_scan_u32(const LaunchCtx& lc, const uint32_t* in, uint32_t* out, int64_t n_host,
                            const uint32_t* n_dev, uint32_t* total_out, uint32_t* out_end, uint64_t* tmp,
-                           DevState* cap_S = nullptr, uint64_t cap = 0, int cap_err = 0);
+                           DevState* cap_S = nullptr, uint64_t cap = 0, int cap_err = 0,
+                           const CompInit* ci = nullptr);
 hipError_t launch_scan_u64(const LaunchCtx& lc, const uint64_t* in, uint64_t* out, int64_t n_host,
                            unsigned long long* total_out, uint64_t* tmp);
 // runs of rows [r0, r1); their numbers continue from run_off[r0]

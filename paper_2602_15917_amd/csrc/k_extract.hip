@@ -1009,9 +1009,21 @@ __device__ __forceinline__ void k_emit_codes_p16_body(const VPart vp, const floa
     else
         emit_codes_lean<float, 1, true>(vp, in, nx, L, o, px);
 }
-__global__ __launch_bounds__(kBlock) void k_emit_codes_p16(const float* __restrict__ in, int64_t nx, Layout L,
-                                                           EmitOut o, const uint16_t* __restrict__ px) {
-    k_emit_codes_p16_body(hw_part(), in, nx, L, o, px);
+// float32 volumes in one launch: the lean chunks from the 16-bit proxy (and
+// the image `in`) when the fused pass produced it, else from the values
+// `vals` (the image, or M with a background).  The branch is uniform.
+__device__ __forceinline__ void k_emit_codes_f32_body(const VPart vp, const float* __restrict__ in,
+                                                      const float* __restrict__ vals, int64_t nx, Layout L, EmitOut o,
+                                                      const uint16_t* __restrict__ px) {
+    if (px && !thread_exit_e(L.S) && L.S->p16)
+        k_emit_codes_p16_body(vp, in, nx, L, o, px);
+    else
+        k_emit_codes_body<float>(vp, vals, nx, L, o, 0);
+}
+__global__ __launch_bounds__(kBlock) void k_emit_codes_f32(const float* __restrict__ in, const float* __restrict__ vals,
+                                                           int64_t nx, Layout L, EmitOut o,
+                                                           const uint16_t* __restrict__ px) {
+    k_emit_codes_f32_body(hw_part(), in, vals, nx, L, o, px);
 }
 
 template <typename T>
@@ -1273,9 +1285,8 @@ hipError_t launch_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, cons
         const uint16_t* px = (L.fine_slots && g.W * 64 == g.nx) ? reinterpret_cast<const uint16_t*>(L.proxy) : nullptr;
         // with a background the kernels that read voxel values read M
         const float* vals = bg ? bg->work : (const float*)in;
-        launch_k<kBlock, k_emit_codes_body<float>>(lc, k_emit_codes<float>, grid_waves, block, 0, vals, g.nx, L, o, px ? 1 : 0);
-        if (px)
-            launch_k<kBlock, k_emit_codes_p16_body>(lc, k_emit_codes_p16, grid_waves, block, 0, (const float*)in, g.nx, L, o, px);
+        launch_k<kBlock, k_emit_codes_f32_body>(lc, k_emit_codes_f32, grid_waves, block, 0, (const float*)in, vals, g.nx,
+                                                L, o, px);
         if (bg) {
             hipError_t e = launch_background_if(lc, (const float*)in, *bg, g, L.S, 2);
             if (e != hipSuccess) return e;

@@ -1090,35 +1090,6 @@ __device__ __forceinline__ void wave_flush(bool pred, uint32_t root, const Acc& 
     if (pred && !match) tab_add(t, root, a, comps, comp_id);
 }
 
-// One thread per root run: the entry of its component (label = first voxel
-// of the root run, i.e. of the component).
-__device__ __forceinline__ void k_comp_init_body(const VPart vp, const uint32_t* __restrict__ xs,
-                                                      const uint32_t* __restrict__ run_row,
-                                                      const uint32_t* __restrict__ parent,
-                                                      const uint32_t* __restrict__ comp_id, int64_t nx,
-                                                      roix_component* comps, const DevState* S) {
-    if (thread_exit(S)) return;
-    const uint32_t n = S->n_runs;
-    const uint32_t nthreads = vp.n * blockDim.x;
-    for (uint32_t i = vp.b * blockDim.x + threadIdx.x; i < n; i += nthreads) {
-        if (parent[i] != i) continue;
-        roix_component* c = comps + comp_id[i];
-        c->label = (uint64_t)run_row[i] * (uint64_t)nx + xs[i];
-        c->size = 0;
-        c->x0 = c->y0 = c->z0 = 0xFFFFFFFFu;
-        c->x1 = c->y1 = c->z1 = 0u;
-        c->kept = 0u;
-        c->pad = 0u;
-    }
-}
-__global__ __launch_bounds__(kBlock) void k_comp_init(const uint32_t* __restrict__ xs,
-                                                      const uint32_t* __restrict__ run_row,
-                                                      const uint32_t* __restrict__ parent,
-                                                      const uint32_t* __restrict__ comp_id, int64_t nx,
-                                                      roix_component* comps, const DevState* S) {
-    k_comp_init_body(hw_part(), xs, run_row, parent, comp_id, nx, comps, S);
-}
-
 // Size and box of every component.  Each workgroup takes a contiguous range
 // of runs; a thread accumulates kStatRuns consecutive runs while their root
 // stays the same, and hands the accumulator to the workgroup table through
@@ -1219,8 +1190,6 @@ __global__ __launch_bounds__(kBlock) void k_comp_stats(const uint32_t* __restric
 
 hipError_t launch_comp_stats(const LaunchCtx& lc, const Geom& g, const Layout& L, roix_component* comps) {
     timer_begin(lc.timer, ST_COMPS, lc.stream);
-    launch_k<kBlock, k_comp_init_body>(lc, k_comp_init, dim3(grid_for((int64_t)L.run_cap, kBlock, lc.grid_stream)), dim3(kBlock), 0, (const uint32_t*)L.run_xs, (const uint32_t*)L.run_row, (const uint32_t*)L.parent,
-                       (const uint32_t*)L.comp_id, g.nx, comps, (const DevState*)L.S);
     launch_k<kBlock, k_comp_stats_body>(lc, k_comp_stats, dim3(grid_for((int64_t)L.run_cap, kBlock * kStatRuns, lc.stats_grid)),
                        dim3(kBlock), 0, (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe,
                        (const uint32_t*)L.run_row, (const uint32_t*)L.parent, (const uint32_t*)L.comp_id,
@@ -1231,31 +1200,103 @@ hipError_t launch_comp_stats(const LaunchCtx& lc, const Geom& g, const Layout& L
 
 // ------------------------------------------------------------- keep rule
 
-__device__ __forceinline__ void k_largest_max_body(const VPart vp, const roix_component* comps, DevState* S) {
-    if (block_exit_l(S)) return;
+// LARGEST in one launch: each workgroup leaves the largest size among its
+// components, with the first component holding it, in its slot; the last
+// workgroup to finish takes the largest size over the slots (the first
+// component on a tie) and keeps that component.  Every kept flag was cleared
+// when the component entries were written.
+static_assert(kKeepGrid % kBlock == 0, "keep slots per thread");
+__device__ __forceinline__ void k_keep_largest_body(const VPart vp, roix_component* comps, uint8_t* kept_flag,
+                                                    DevState* S) {
+    if (block_exit_l(S)) return;  // the status does not change during this launch: every workgroup leaves
+    __shared__ unsigned long long s_m[kBlock / kWave];
+    __shared__ uint32_t s_c[kBlock / kWave];
+    __shared__ int s_last;
     const uint32_t n = S->n_comps;
     unsigned long long m = 0;
-    for (uint32_t c = vp.b * blockDim.x + threadIdx.x; c < n; c += vp.n * blockDim.x)
-        m = comps[c].size > m ? comps[c].size : m;
-    m = wave_max(m);
-    if (threadIdx.x % kWave == 0 && m) atomicMax(&S->max_size, m);
-}
-__global__ __launch_bounds__(kBlock) void k_largest_max(const roix_component* comps, DevState* S) {
-    k_largest_max_body(hw_part(), comps, S);
-}
-
-__device__ __forceinline__ void k_largest_arg_body(const VPart vp, const roix_component* comps, DevState* S) {
-    if (block_exit_l(S)) return;
-    const uint32_t n = S->n_comps;
-    const unsigned long long m = S->max_size;
     uint32_t best = kNone;
-    for (uint32_t c = vp.b * blockDim.x + threadIdx.x; c < n; c += vp.n * blockDim.x)
-        if (comps[c].size == m && c < best) best = c;
-    best = wave_min(best);
-    if (threadIdx.x % kWave == 0 && best != kNone) atomicMin(&S->largest_cid, best);
+    for (uint32_t c = vp.b * blockDim.x + threadIdx.x; c < n; c += vp.n * blockDim.x) {
+        const unsigned long long sz = comps[c].size;
+        if (sz > m) {  // c ascending: the first of this thread's largest
+            m = sz;
+            best = c;
+        }
+    }
+    // (largest size, first component with it) over the workgroup
+    const unsigned long long wm = wave_max(m);
+    const uint32_t wc = wave_min(m == wm ? best : kNone);
+    const int w = threadIdx.x / kWave;
+    if (threadIdx.x % kWave == 0) {
+        s_m[w] = wm;
+        s_c[w] = wc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long bm = 0;
+        uint32_t bc = kNone;
+        for (int k = 0; k < kBlock / kWave; ++k)
+            if (s_m[k] > bm || (s_m[k] == bm && s_c[k] < bc)) {
+                bm = s_m[k];
+                bc = s_c[k];
+            }
+        st_dev(&S->keep_size[vp.b], bm);
+        st_dev(&S->keep_cid[vp.b], bc);
+        wait_mem();  // the slot is in place before the workgroup counts itself done
+        s_last = atomicAdd(&S->done_keep, 1u) == vp.n - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;  // uniform
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    // the slots, kKeepGrid / kBlock per thread, then across the workgroup
+    unsigned long long km[kKeepGrid / kBlock];
+    uint32_t kc[kKeepGrid / kBlock];
+#pragma unroll
+    for (int k = 0; k < kKeepGrid / kBlock; ++k) {
+        const uint32_t j = threadIdx.x + (uint32_t)(k * kBlock);
+        km[k] = j < vp.n ? ld_dev(&S->keep_size[j]) : 0ull;
+        kc[k] = j < vp.n ? ld_dev(&S->keep_cid[j]) : kNone;
+    }
+    unsigned long long tm = 0;
+    uint32_t tc = kNone;
+#pragma unroll
+    for (int k = 0; k < kKeepGrid / kBlock; ++k)
+        if (km[k] > tm || (km[k] == tm && kc[k] < tc)) {
+            tm = km[k];
+            tc = kc[k];
+        }
+    const unsigned long long gm = wave_max(tm);
+    const uint32_t gc = wave_min(tm == gm ? tc : kNone);
+    __syncthreads();  // the per-wave results of the first reduction have been read
+    if (threadIdx.x % kWave == 0) {
+        s_m[w] = gm;
+        s_c[w] = gc;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    unsigned long long bm = 0;
+    uint32_t bc = kNone;
+    for (int k = 0; k < kBlock / kWave; ++k)
+        if (s_m[k] > bm || (s_m[k] == bm && s_c[k] < bc)) {
+            bm = s_m[k];
+            bc = s_c[k];
+        }
+    S->max_size = bm;
+    if (bc == kNone) return;  // no component
+    S->largest_cid = bc;
+    roix_component* e = comps + bc;
+    e->kept = 1u;
+    kept_flag[bc] = 1;
+    S->n_kept = 1ull;
+    S->n_kept_voxels = e->size;
+    S->bbox[0] = e->x0;
+    S->bbox[1] = e->x1;
+    S->bbox[2] = e->y0;
+    S->bbox[3] = e->y1;
+    S->bbox[4] = e->z0;
+    S->bbox[5] = e->z1;
 }
-__global__ __launch_bounds__(kBlock) void k_largest_arg(const roix_component* comps, DevState* S) {
-    k_largest_arg_body(hw_part(), comps, S);
+__global__ __launch_bounds__(kBlock) void k_keep_largest(roix_component* comps, uint8_t* kept_flag, DevState* S) {
+    k_keep_largest_body(hw_part(), comps, kept_flag, S);
 }
 
 // kept flags, counts and the union box of kept components
@@ -1307,14 +1348,12 @@ __global__ __launch_bounds__(kBlock) void k_keep_apply(roix_component* comps, ui
 
 hipError_t launch_keep(const LaunchCtx& lc, const Layout& L, roix_component* comps, const roix_criterion* crit) {
     timer_begin(lc.timer, ST_KEEP, lc.stream);
-    const int largest = crit->keep == ROIX_KEEP_LARGEST;
-    const int grid = 512;
-    if (largest) {
-        launch_k<kBlock, k_largest_max_body>(lc, k_largest_max, dim3(grid), dim3(kBlock), 0, (const roix_component*)comps, L.S);
-        launch_k<kBlock, k_largest_arg_body>(lc, k_largest_arg, dim3(grid), dim3(kBlock), 0, (const roix_component*)comps, L.S);
-    }
-    launch_k<kBlock, k_keep_apply_body>(lc, k_keep_apply, dim3(grid), dim3(kBlock), 0, comps, L.kept_flag, largest,
-                       (unsigned long long)(crit->min_size > 0 ? crit->min_size : 1), L.S);
+    const int grid = kKeepGrid;
+    if (crit->keep == ROIX_KEEP_LARGEST)
+        launch_k<kBlock, k_keep_largest_body>(lc, k_keep_largest, dim3(grid), dim3(kBlock), 0, comps, L.kept_flag, L.S);
+    else
+        launch_k<kBlock, k_keep_apply_body>(lc, k_keep_apply, dim3(grid), dim3(kBlock), 0, comps, L.kept_flag, 0,
+                                            (unsigned long long)(crit->min_size > 0 ? crit->min_size : 1), L.S);
     timer_end(lc.timer, ST_KEEP, lc.stream);
     return hipGetLastError();
 }
