@@ -216,7 +216,7 @@ hipError_t roix::components_and_keep(const LaunchCtx& lc, const Geom& g, const L
                              L.scan_tmp, L.S, cap, ROIX_ETRUNC, &ci)) != hipSuccess)
         return e;
     if ((e = launch_comp_stats(lc, g, L, comps)) != hipSuccess) return e;
-    return launch_keep(lc, L, comps, crit);
+    return launch_keep(lc, g, L, comps, crit);
 }
 
 static hipError_t label_and_keep(const LaunchCtx& lc, const Geom& g, const Layout& L, const roix_criterion* crit,

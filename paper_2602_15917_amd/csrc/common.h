@@ -83,6 +83,9 @@ struct DevState {
     // LARGEST: the keep workgroups done, and each one's largest size and the
     // first component holding it
     uint32_t done_keep, pad2;
+    // LARGEST: the kept component's root run (kNone: none), for passes that
+    // test a run's root instead of looking up its component's kept flag
+    uint32_t kept_root, kept_by_root;
     unsigned long long keep_size[kKeepGrid];
     uint32_t keep_cid[kKeepGrid];
 };
@@ -230,6 +233,13 @@ __device__ __forceinline__ T ld_dev(const T* p) {
 template <typename T>
 __device__ __forceinline__ void st_dev(T* p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// LDS written by some lanes of a wave is read by others after this point.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <typename T>
@@ -541,7 +551,8 @@ hipError_t launch_absq(const LaunchCtx& lc, const uint8_t* D, int64_t m, uint32_
                        roix_absq_info* info);
 hipError_t launch_flatten(const LaunchCtx& lc, const Layout& L);
 hipError_t launch_comp_stats(const LaunchCtx& lc, const Geom& g, const Layout& L, roix_component* comps);
-hipError_t launch_keep(const LaunchCtx& lc, const Layout& L, roix_component* comps, const roix_criterion* crit);
+hipError_t launch_keep(const LaunchCtx& lc, const Geom& g, const Layout& L, roix_component* comps,
+                       const roix_criterion* crit);
 hipError_t launch_voxel_out(const LaunchCtx& lc, const Geom& g, const Layout& L, const roix_component* comps,
                             uint8_t* keep, int64_t* labels);
 

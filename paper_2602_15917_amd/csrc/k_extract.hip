@@ -33,9 +33,13 @@ __device__ __forceinline__ void put_span(const Layout& L, int64_t r, uint32_t xs
     L.row_packed[r] = has ? ((1ull << 40) | (uint64_t)(xe - xs)) : 0ull;
 }
 
-// from the runs: first and last run of a kept component
+// from the runs: first and last run of a kept component.  With one kept
+// component of known root run, a run is kept when its root (parent, after
+// the flattening) is that run: no lookup of the component's flag.
 __device__ __forceinline__ void k_spans_runs_body(const VPart vp, Layout L, int64_t nrows) {
     const bool dead = thread_exit_e(L.S);
+    const bool by_root = L.S->kept_by_root != 0;
+    const uint32_t kr = L.S->kept_root;
     const int64_t nthreads = (int64_t)vp.n * blockDim.x;
     for (int64_t r = (int64_t)vp.b * blockDim.x + threadIdx.x; r < nrows; r += nthreads) {
         uint32_t xs = 0, xe = 0;
@@ -43,7 +47,8 @@ __device__ __forceinline__ void k_spans_runs_body(const VPart vp, Layout L, int6
         if (!dead) {
             const uint32_t a0 = L.run_off[r], a1 = L.run_off[r + 1];
             for (uint32_t i = a0; i < a1; ++i) {
-                if (!L.kept_flag[L.comp_id[L.parent[i]]]) continue;
+                const uint32_t root = L.parent[i];
+                if (by_root ? root != kr : !L.kept_flag[L.comp_id[root]]) continue;
                 if (!has) xs = L.run_xs[i];
                 xe = L.run_xe[i];
                 has = true;

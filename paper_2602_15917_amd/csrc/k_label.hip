@@ -347,10 +347,15 @@ hipError_t launch_mask_runs(const LaunchCtx& lc, const Geom& g, const Layout& L,
 
 // ----------------------------------------------------------------- runs
 
-// Rows of at most 64 words: lane-per-word.  Each lane writes the runs that
+// Rows of at most 64 words: lane-per-word.  Each lane finds the runs that
 // start in its word; a run still open at the word's end closes at the first
 // 0-bit of a later word of the row (segmented suffix minimum across lanes) or
-// at nx.  Output slot = run_off[row] + runs starting earlier in the row.
+// at nx.  The runs of a step's rows are consecutive in the output, from
+// run_off of its first row, and a lane's runs follow those of the lanes
+// before it.  A step of many runs (noisy masks: up to 32 a word) is gathered
+// in LDS, kStage runs at a time, and written out as contiguous vectors; a
+// step of few runs is stored straight from the lanes.
+constexpr int kStage = 256;
 __device__ __forceinline__ void k_runs_write_lanes_body(const VPart vp, const uint64_t* __restrict__ maskbits, int64_t nx,
                                                              int64_t nrows, int64_t W,
                                                              const uint32_t* __restrict__ run_off,
@@ -359,21 +364,26 @@ __device__ __forceinline__ void k_runs_write_lanes_body(const VPart vp, const ui
                                                              uint32_t* __restrict__ parent,
                                                              uint32_t* __restrict__ run_row, int64_t row_base,
                                                              const DevState* S) {
+    __shared__ uint32_t s_xs[kBlock / kWave][kStage], s_xe[kBlock / kWave][kStage], s_rw[kBlock / kWave][kStage];
     if (thread_exit(S)) return;  // no barrier below; the status is the same for every lane of a wave
-    const int lane = threadIdx.x % kWave;
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
     const int64_t wave = ((int64_t)vp.b * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = (int64_t)vp.n * blockDim.x / kWave;
     const int64_t R = kWave / W;
     const uint32_t kBig = 0xFFFFFFFFu;
+    uint32_t* sx = s_xs[wv];
+    uint32_t* se = s_xe[wv];
+    uint32_t* sr = s_rw[wv];
     for (int64_t row0 = wave * R; row0 < nrows; row0 += nwaves * R) {
         const WordLane wl = word_lane(row0, W, nrows);
         const uint64_t m = wl.row >= 0 ? maskbits[wl.row * W + wl.w] : 0ull;
         const uint32_t prev_hi = __shfl_up((uint32_t)(m >> 32), 1);
         const uint64_t cin = (wl.w > 0) ? (uint64_t)(prev_hi >> 31) : 0ull;
-        uint64_t starts = m & ~((m << 1) | cin);
+        const uint64_t starts = m & ~((m << 1) | cin);
         const uint32_t cnt = (uint32_t)__popcll(starts);
         const uint32_t incl = wave_incl_scan(cnt);
-        const uint32_t before = __shfl(incl, wl.seg_first > 0 ? wl.seg_first - 1 : 0);
+        const uint32_t excl = incl - cnt;
+        const uint32_t T = (uint32_t)__shfl((int)incl, kWave - 1);
         // first 0-bit position of each word, then the minimum over later words of the row
         uint32_t smin = (wl.row >= 0 && m != ~0ull) ? (uint32_t)(64 * wl.w) + (uint32_t)__ffsll((unsigned long long)~m) - 1u
                                                    : kBig;
@@ -388,19 +398,50 @@ __device__ __forceinline__ void k_runs_write_lanes_body(const VPart vp, const ui
         const int nseg = __shfl_down(seg, 1);
         if (lane + 1 >= kWave || nseg != seg || wl.w == W - 1) next_zero = kBig;
         if (next_zero > (uint32_t)nx) next_zero = (uint32_t)nx;
-        if (wl.row < 0) continue;
-        uint32_t k = run_off[wl.row] + incl - cnt - (seg > 0 ? before : 0u);
-        while (starts) {
-            const int i = __ffsll((unsigned long long)starts) - 1;
-            starts &= starts - 1;
-            const uint64_t rest = ~m & (~0ull << i);
-            const uint32_t xs = (uint32_t)(64 * wl.w + i);
-            const uint32_t xe = rest ? (uint32_t)(64 * wl.w) + (uint32_t)__ffsll((unsigned long long)rest) - 1u : next_zero;
-            xs_out[k] = xs;
-            xe_out[k] = xe;
-            parent[k] = k;
-            run_row[k] = (uint32_t)(row_base + wl.row);
-            ++k;
+        if (T == 0) continue;  // uniform
+        const uint32_t kb = run_off[row0];  // the step's first run
+        const uint32_t rid = (uint32_t)(row_base + wl.row);
+        if (T <= (uint32_t)(2 * kWave)) {  // uniform: few runs a lane, stored straight from the lanes
+            uint64_t st = starts;
+            uint32_t k = kb + excl;
+            while (st) {
+                const int i = __ffsll((unsigned long long)st) - 1;
+                st &= st - 1;
+                const uint64_t rest = ~m & (~0ull << i);
+                xs_out[k] = (uint32_t)(64 * wl.w + i);
+                xe_out[k] = rest ? (uint32_t)(64 * wl.w) + (uint32_t)__ffsll((unsigned long long)rest) - 1u : next_zero;
+                parent[k] = k;
+                run_row[k] = rid;
+                ++k;
+            }
+            continue;
+        }
+        for (uint32_t r0 = 0; r0 < T; r0 += (uint32_t)kStage) {
+            // this round's runs of the lane into the wave's staging area
+            uint64_t st = starts;
+            uint32_t k = excl;
+            while (st) {
+                const int i = __ffsll((unsigned long long)st) - 1;
+                st &= st - 1;
+                if (k >= r0 + (uint32_t)kStage) break;
+                if (k >= r0) {
+                    const uint64_t rest = ~m & (~0ull << i);
+                    sx[k - r0] = (uint32_t)(64 * wl.w + i);
+                    se[k - r0] = rest ? (uint32_t)(64 * wl.w) + (uint32_t)__ffsll((unsigned long long)rest) - 1u : next_zero;
+                    sr[k - r0] = rid;
+                }
+                ++k;
+            }
+            wave_sync();
+            const uint32_t nr = T - r0 < (uint32_t)kStage ? T - r0 : (uint32_t)kStage;
+            for (uint32_t j = (uint32_t)lane; j < nr; j += kWave) {
+                const uint32_t g = kb + r0 + j;
+                xs_out[g] = sx[j];
+                xe_out[g] = se[j];
+                parent[g] = g;
+                run_row[g] = sr[j];
+            }
+            wave_sync();  // the area is refilled by the next round
         }
     }
 }
@@ -1203,11 +1244,12 @@ hipError_t launch_comp_stats(const LaunchCtx& lc, const Geom& g, const Layout& L
 // LARGEST in one launch: each workgroup leaves the largest size among its
 // components, with the first component holding it, in its slot; the last
 // workgroup to finish takes the largest size over the slots (the first
-// component on a tie) and keeps that component.  Every kept flag was cleared
-// when the component entries were written.
+// component on a tie) and keeps that component, and notes its root run.
+// Every kept flag was cleared when the component entries were written.
 static_assert(kKeepGrid % kBlock == 0, "keep slots per thread");
 __device__ __forceinline__ void k_keep_largest_body(const VPart vp, roix_component* comps, uint8_t* kept_flag,
-                                                    DevState* S) {
+                                                    const uint32_t* __restrict__ run_off,
+                                                    const uint32_t* __restrict__ run_xs, int64_t nx, DevState* S) {
     if (block_exit_l(S)) return;  // the status does not change during this launch: every workgroup leaves
     __shared__ unsigned long long s_m[kBlock / kWave];
     __shared__ uint32_t s_c[kBlock / kWave];
@@ -1294,9 +1336,26 @@ __device__ __forceinline__ void k_keep_largest_body(const VPart vp, roix_compone
     S->bbox[3] = e->y1;
     S->bbox[4] = e->z0;
     S->bbox[5] = e->z1;
+    // its root run: the run of row label / nx that starts at label % nx
+    const uint64_t lab = e->label;
+    const uint32_t row = (uint32_t)(lab / (uint64_t)nx), x = (uint32_t)(lab % (uint64_t)nx);
+    uint32_t a = run_off[row], b = run_off[row + 1];
+    while (b - a > 1) {  // runs of a row are in x order
+        const uint32_t mid = (a + b) >> 1;
+        if (run_xs[mid] <= x)
+            a = mid;
+        else
+            b = mid;
+    }
+    if (a < run_off[row + 1] && run_xs[a] == x) {
+        S->kept_root = a;
+        S->kept_by_root = 1u;
+    }
 }
-__global__ __launch_bounds__(kBlock) void k_keep_largest(roix_component* comps, uint8_t* kept_flag, DevState* S) {
-    k_keep_largest_body(hw_part(), comps, kept_flag, S);
+__global__ __launch_bounds__(kBlock) void k_keep_largest(roix_component* comps, uint8_t* kept_flag,
+                                                         const uint32_t* __restrict__ run_off,
+                                                         const uint32_t* __restrict__ run_xs, int64_t nx, DevState* S) {
+    k_keep_largest_body(hw_part(), comps, kept_flag, run_off, run_xs, nx, S);
 }
 
 // kept flags, counts and the union box of kept components
@@ -1346,11 +1405,13 @@ __global__ __launch_bounds__(kBlock) void k_keep_apply(roix_component* comps, ui
     k_keep_apply_body(hw_part(), comps, kept_flag, largest, min_size, S);
 }
 
-hipError_t launch_keep(const LaunchCtx& lc, const Layout& L, roix_component* comps, const roix_criterion* crit) {
+hipError_t launch_keep(const LaunchCtx& lc, const Geom& g, const Layout& L, roix_component* comps,
+                       const roix_criterion* crit) {
     timer_begin(lc.timer, ST_KEEP, lc.stream);
     const int grid = kKeepGrid;
     if (crit->keep == ROIX_KEEP_LARGEST)
-        launch_k<kBlock, k_keep_largest_body>(lc, k_keep_largest, dim3(grid), dim3(kBlock), 0, comps, L.kept_flag, L.S);
+        launch_k<kBlock, k_keep_largest_body>(lc, k_keep_largest, dim3(grid), dim3(kBlock), 0, comps, L.kept_flag,
+                                              (const uint32_t*)L.run_off, (const uint32_t*)L.run_xs, g.nx, L.S);
     else
         launch_k<kBlock, k_keep_apply_body>(lc, k_keep_apply, dim3(grid), dim3(kBlock), 0, comps, L.kept_flag, 0,
                                             (unsigned long long)(crit->min_size > 0 ? crit->min_size : 1), L.S);

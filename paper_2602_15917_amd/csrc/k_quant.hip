@@ -120,7 +120,11 @@ __device__ __forceinline__ void k_init_body(const VPart vp, DevState* S, double 
             }
         }
         S->hist[threadIdx.x] = 0ull;
-        if (threadIdx.x == 0) S->done_keep = 0u;
+        if (threadIdx.x == 0) {
+            S->done_keep = 0u;
+            S->kept_root = kNone;
+            S->kept_by_root = 0u;
+        }
     }
 }
 __global__ __launch_bounds__(kBlock) void k_init(DevState* S, double eb_abs) {
