@@ -195,9 +195,9 @@ static roix_status dev_err(hipError_t e) { return e == hipSuccess ? ROIX_OK : RO
 // mask -> runs -> union of a whole volume (everything between the proxy and
 // the flattening)
 static hipError_t label_runs(const LaunchCtx& lc, const Geom& g, const Layout& L, int connectivity,
-                             const int32_t* slice_thr = nullptr) {
+                             const int32_t* slice_thr = nullptr, const uint16_t* u16_in = nullptr) {
     hipError_t e;
-    if ((e = launch_mask_runs(lc, g, L, slice_thr)) != hipSuccess) return e;
+    if ((e = launch_mask_runs(lc, g, L, slice_thr, u16_in)) != hipSuccess) return e;
     if ((e = launch_scan_u32(lc, L.row_nruns, L.run_off, g.nrows, nullptr, &L.S->n_runs, L.run_off + g.nrows,
                              L.scan_tmp, L.S, L.run_cap, ROIX_ENOMEM)) != hipSuccess)
         return e;
@@ -220,10 +220,10 @@ hipError_t roix::components_and_keep(const LaunchCtx& lc, const Geom& g, const L
 }
 
 static hipError_t label_and_keep(const LaunchCtx& lc, const Geom& g, const Layout& L, const roix_criterion* crit,
-                                 roix_component* comps, int64_t comps_cap) {
+                                 roix_component* comps, int64_t comps_cap, const uint16_t* u16_in = nullptr) {
     hipError_t e;
     const int32_t* st = crit->thr == ROIX_THR_OTSU_SLICE ? L.slice_thr : nullptr;
-    if ((e = label_runs(lc, g, L, crit->connectivity, st)) != hipSuccess) return e;
+    if ((e = label_runs(lc, g, L, crit->connectivity, st, u16_in)) != hipSuccess) return e;
     return components_and_keep(lc, g, L, crit, comps, comps_cap);
 }
 
@@ -245,6 +245,10 @@ roix_status roix::enqueue_fused(const LaunchCtx& lc, const Geom& g, Layout L, co
     // per-slice thresholds compare 1-byte bins slice by slice: the two-pass flow
     const bool per_slice = crit->thr == ROIX_THR_OTSU_SLICE;
     const bool p16 = !per_slice && L.fine_slots && dtype == ROIX_F32 && eb.mode == ROIX_EB_ABS && aligned(d_in, 16);
+    // a uint16 volume of whole 64-voxel rows needs no proxy: the histogram
+    // pass only counts, and the mask pass compares the values themselves
+    // with the smallest value whose code reaches the threshold
+    const bool u16_direct = !per_slice && dtype == ROIX_U16 && g.W * 64 == g.nx && aligned(d_in, 16);
     if (p16) {
         ROIX_TRY(launch_init(lc, L.S, eb.value));
         ROIX_TRY(launch_quant_range16(lc, (const float*)d_in, g, L));
@@ -254,13 +258,17 @@ roix_status roix::enqueue_fused(const LaunchCtx& lc, const Geom& g, Layout L, co
         ROIX_TRY(launch_init(lc, L.S));
         ROIX_TRY(launch_range(lc, d_in, dtype, g.N, L.S));
         ROIX_TRY(launch_resolve_dt(lc, L.S, dtype, eb, crit));
-        ROIX_TRY(launch_quant_hist(lc, d_in, kind, g, L.S, L.proxy, fixed));
+        if (u16_direct)
+            ROIX_TRY(launch_hist_only(lc, d_in, dtype, g, L.S));
+        else
+            ROIX_TRY(launch_quant_hist(lc, d_in, kind, g, L.S, L.proxy, fixed));
     }
     if (per_slice)
         ROIX_TRY(launch_slice_otsu(lc, g, L.proxy, L.S, L.slice_thr, out->d_slice_thr));
     else
         ROIX_TRY(launch_threshold(lc, L.S, crit));
-    ROIX_TRY(label_and_keep(lc, g, L, crit, out->d_comps, out->comps_cap));
+    ROIX_TRY(label_and_keep(lc, g, L, crit, out->d_comps, out->comps_cap,
+                            u16_direct ? (const uint16_t*)d_in : nullptr));
     ROIX_TRY(launch_spans_from_runs(lc, g, L));
     ROIX_TRY(spans_and_emit(lc, g, L, d_in, dtype, out));
     ROIX_TRY(launch_finalize(lc, L.S, out->d_qinfo, out->d_sinfo, out->d_einfo, true));

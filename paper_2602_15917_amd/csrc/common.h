@@ -465,7 +465,10 @@ hipError_t launch_otsu(const LaunchCtx& lc, DevState* S, bool fixed);
 // the resolve step has set)
 hipError_t launch_threshold(const LaunchCtx& lc, DevState* S, const roix_criterion* crit);
 
-hipError_t launch_mask_runs(const LaunchCtx& lc, const Geom& g, const Layout& L, const int32_t* slice_thr = nullptr);
+// u16_in: the mask from a uint16 volume whose rows are whole 64-voxel words
+// (16-byte aligned) instead of the proxy
+hipError_t launch_mask_runs(const LaunchCtx& lc, const Geom& g, const Layout& L, const int32_t* slice_thr = nullptr,
+                            const uint16_t* u16_in = nullptr);
 // streamed volumes (FIXED threshold, ABS bound): mask parameters at open,
 // then per slab of rows [r0, r1) the range, mask words and run counts
 hipError_t launch_serve_open(const LaunchCtx& lc, DevState* S, double eb_value, double fixed_value);

@@ -153,6 +153,57 @@ __device__ __forceinline__ uint64_t mask_words64_16(const uint4 (&v)[8], uint32_
     return word;
 }
 
+// uint16 volumes read directly: a voxel is object when its code reaches the
+// threshold code, q(x) >= q_thr.  q(x) = rint(x r) never decreases with x,
+// so that holds exactly for x >= X, the smallest such value (65536: none).
+__device__ __forceinline__ uint32_t u16_threshold(float r, int32_t q_thr) {
+    if (qcode(65535.0f, r) < q_thr) return 65536u;
+    uint32_t lo = 0u, hi = 65535u;  // the answer lies in [lo, hi]
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (qcode((float)mid, r) >= q_thr)
+            hi = mid;
+        else
+            lo = mid + 1u;
+    }
+    return lo;
+}
+
+// 8 mask bits of 8 uint16 values >= X (X2 = X in both halves, X <= 65535):
+// the saturating difference X - x is zero exactly then, and bit 15 of
+// (d & 0x7FFF) + 0x7FFF, or of d, is set exactly when a half d is not zero.
+__device__ __forceinline__ uint32_t ge_u16x8(const uint4& v, uint32_t X2) {
+    const uint32_t d[4] = {v.x, v.y, v.z, v.w};
+    uint32_t z[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t r = __builtin_bit_cast(
+            uint32_t, __builtin_elementwise_sub_sat(__builtin_bit_cast(u16x2_t, X2), __builtin_bit_cast(u16x2_t, d[i])));
+        z[i] = ~(add_u16x2(r & 0x7FFF7FFFu, 0x7FFF7FFFu) | r) & 0x80008000u;
+    }
+    const uint32_t y = (z[0] >> 15) | (z[1] >> 13) | (z[2] >> 11) | (z[3] >> 9);
+    return (y & 0x55u) | ((y >> 15) & 0xAAu);
+}
+
+// the mask words of mask_load64_16's loads, for uint16 values (all 0 when X2 is 0xFFFFFFFF)
+__device__ __forceinline__ uint64_t mask_words64_u16(const uint4 (&v)[8], uint32_t X2, bool none) {
+    const int lane = threadIdx.x % kWave;
+    uint32_t lo = 0, hi = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) lo |= ge_u16x8(v[k], X2) << (8 * k);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) hi |= ge_u16x8(v[4 + k], X2) << (8 * k);
+    if (none) lo = hi = 0u;
+    const int ld = lane >> 3, src0 = (lane & 7) * 8, sh = 8 * (ld & 3);
+    uint64_t word = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const uint32_t a = (uint32_t)__shfl((int)lo, src0 + j), b = (uint32_t)__shfl((int)hi, src0 + j);
+        word |= (uint64_t)(((ld < 4 ? a : b) >> sh) & 0xFFu) << (8 * j);
+    }
+    return word;
+}
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     const int lane = threadIdx.x % kWave;
 #pragma unroll
@@ -196,8 +247,10 @@ __device__ __forceinline__ void slice_consts(const int32_t* __restrict__ thr, in
 // One 64-bit mask word per lane (SWAR byte compares on 64 proxy bytes), run
 // starts = 1-bits whose left neighbour (previous bit, or the previous lane's
 // top bit) is 0, per-row run counts by a segmented wave scan.  slice_thr
-// (1-byte proxy only): a threshold bin per z-slice instead of one.
-template <bool P16>
+// (1-byte proxy only): a threshold bin per z-slice instead of one.  MODE 0:
+// 1-byte bin proxy; 1: 16-bit code proxy; 2: the uint16 volume itself, rows
+// of whole 64-voxel words (its rows are then laid out as the 16-bit proxy's).
+template <int MODE>
 __device__ __forceinline__ void mask_runs_body(const VPart vp, const uint8_t* __restrict__ proxy, int64_t nx,
                                                int64_t nrows, int64_t W,
                                                DevState* S, uint64_t* __restrict__ maskbits,
@@ -209,6 +262,14 @@ __device__ __forceinline__ void mask_runs_body(const VPart vp, const uint8_t* __
     // 16-bit proxy: q - qmin >= q_thr - qmin
     const uint32_t Q2 = (0x8000u - ((uint32_t)S->qmin & 0x7FFFu)) * 0x00010001u;
     const uint32_t T2 = (0x8000u - (uint32_t)((int64_t)S->q_thr - (int64_t)S->qmin)) * 0x00010001u;
+    constexpr bool P16 = MODE != 0;
+    uint32_t X2 = 0u;
+    bool none = false;
+    if constexpr (MODE == 2) {
+        const uint32_t X = u16_threshold(S->r, S->q_thr);
+        none = X > 65535u;
+        X2 = (none ? 65535u : X) * 0x00010001u;
+    }
     const uint16_t* proxy16 = reinterpret_cast<const uint16_t*>(proxy);
     const uint64_t lastmask = (nx % 64) ? ((1ull << (nx % 64)) - 1ull) : ~0ull;
     const int lane = threadIdx.x % kWave;
@@ -249,7 +310,10 @@ __device__ __forceinline__ void mask_runs_body(const VPart vp, const uint8_t* __
             for (; row0 < nrows; row0 += stride) {
                 uint4 nxt[8];
                 mask_load64_16(proxy16, (row0 + stride) * W, rows_at(row0 + stride) * W, nxt);
-                finish(mask_words64_16(cur, Q2, T2), row0);
+                if constexpr (MODE == 2)
+                    finish(mask_words64_u16(cur, X2, none), row0);
+                else
+                    finish(mask_words64_16(cur, Q2, T2), row0);
 #pragma unroll
                 for (int k = 0; k < 8; ++k) cur[k] = nxt[k];
             }
@@ -288,7 +352,11 @@ __device__ __forceinline__ void mask_runs_body(const VPart vp, const uint8_t* __
                 const int64_t w = w0 + lane;
                 uint64_t m = 0;
                 if (w < W) {
-                    if constexpr (P16)
+                    if constexpr (MODE == 2) {
+                        const uint4* q = reinterpret_cast<const uint4*>(proxy16 + row * P + 64 * w);
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) m |= none ? 0ull : (uint64_t)ge_u16x8(q[k], X2) << (8 * k);
+                    } else if constexpr (P16)
                         m = mask_word16(proxy16 + row * P + 64 * w, Q2, T2);
                     else
                         m = mask_word(proxy + row * P + 64 * w, tl, tr);
@@ -317,30 +385,35 @@ __device__ __forceinline__ void mask_runs_body(const VPart vp, const uint8_t* __
     }
 }
 
-// The proxy's kind is device data (the fused pass decides it); the branch is uniform.
+// The proxy's kind is device data (the fused pass decides it); the branch is
+// uniform.  u16: `proxy` is the uint16 volume (host-known).
 __device__ __forceinline__ void k_mask_runs_body(const VPart vp, const uint8_t* __restrict__ proxy, int64_t nx, int64_t nrows,
                                                       int64_t W, DevState* S, uint64_t* __restrict__ maskbits,
                                                       uint32_t* __restrict__ row_nruns,
-                                                      const int32_t* __restrict__ slice_thr, int64_t ny) {
+                                                      const int32_t* __restrict__ slice_thr, int64_t ny, int u16) {
     if (block_exit_l(S)) return;
-    if (S->p16)
-        mask_runs_body<true>(vp, proxy, nx, nrows, W, S, maskbits, row_nruns, nullptr, ny);
+    if (u16)
+        mask_runs_body<2>(vp, proxy, nx, nrows, W, S, maskbits, row_nruns, nullptr, ny);
+    else if (S->p16)
+        mask_runs_body<1>(vp, proxy, nx, nrows, W, S, maskbits, row_nruns, nullptr, ny);
     else
-        mask_runs_body<false>(vp, proxy, nx, nrows, W, S, maskbits, row_nruns, slice_thr, ny);
+        mask_runs_body<0>(vp, proxy, nx, nrows, W, S, maskbits, row_nruns, slice_thr, ny);
 }
 __global__ __launch_bounds__(kBlock) void k_mask_runs(const uint8_t* __restrict__ proxy, int64_t nx, int64_t nrows,
                                                       int64_t W, DevState* S, uint64_t* __restrict__ maskbits,
                                                       uint32_t* __restrict__ row_nruns,
-                                                      const int32_t* __restrict__ slice_thr, int64_t ny) {
-    k_mask_runs_body(hw_part(), proxy, nx, nrows, W, S, maskbits, row_nruns, slice_thr, ny);
+                                                      const int32_t* __restrict__ slice_thr, int64_t ny, int u16) {
+    k_mask_runs_body(hw_part(), proxy, nx, nrows, W, S, maskbits, row_nruns, slice_thr, ny, u16);
 }
 
-hipError_t launch_mask_runs(const LaunchCtx& lc, const Geom& g, const Layout& L, const int32_t* slice_thr) {
+hipError_t launch_mask_runs(const LaunchCtx& lc, const Geom& g, const Layout& L, const int32_t* slice_thr,
+                            const uint16_t* u16_in) {
     timer_begin(lc.timer, ST_MASK_RUNS, lc.stream);
     const int64_t R = g.W <= kWave ? kWave / g.W : 1;
     int grid = grid_for((g.nrows + R - 1) / R, kBlock / kWave, lc.grid_mask);
-    launch_k<kBlock, k_mask_runs_body>(lc, k_mask_runs, dim3(grid), dim3(kBlock), 0, (const uint8_t*)L.proxy, g.nx, g.nrows,
-                       g.W, L.S, L.maskbits, L.row_nruns, slice_thr, g.ny);
+    const uint8_t* src = u16_in ? reinterpret_cast<const uint8_t*>(u16_in) : (const uint8_t*)L.proxy;
+    launch_k<kBlock, k_mask_runs_body>(lc, k_mask_runs, dim3(grid), dim3(kBlock), 0, src, g.nx, g.nrows,
+                       g.W, L.S, L.maskbits, L.row_nruns, slice_thr, g.ny, u16_in ? 1 : 0);
     timer_end(lc.timer, ST_MASK_RUNS, lc.stream);
     return hipGetLastError();
 }
