@@ -688,7 +688,9 @@ __device__ __forceinline__ void funnel8(const uint32_t (&a)[5], uint32_t sh, uin
     for (int i = 0; i < 4; ++i) w[i] = __builtin_amdgcn_alignbit(a[i + 1], a[i], sh);
 }
 
-template <int B>
+// VALS: px is a uint16 volume (element = voxel for any row width) and each
+// code comes from the quantiser, as in emit_chunk_near, on the same loads.
+template <int B, bool VALS = false>
 __device__ __forceinline__ void emit_chunk_p16(const uint16_t* __restrict__ px, const Layout& L, const EmitOut& o,
                                                uint64_t c0, uint32_t n, uint32_t nr, uint32_t rs, uint32_t d,
                                                uint32_t rid, uint64_t V0, bool& trunc) {
@@ -697,6 +699,15 @@ __device__ __forceinline__ void emit_chunk_p16(const uint16_t* __restrict__ px, 
     const int lane = threadIdx.x % kWave;
     const uint32_t Q2 = ((uint32_t)S->qmin & 0x7FFFu) * 0x00010001u;
     const uint32_t esc = S->esc;
+    const float qr = S->r, qw = S->w, eb32 = S->eb32;
+    const int32_t qmin = S->qmin;
+    // the code of value p and whether p is an outlier
+    auto vcode = [&](uint32_t p, bool& ob) -> uint32_t {
+        const float x = (float)p;
+        const int32_t q = qcode(x, qr);
+        ob = outlier(x, q, qw, eb32);
+        return ob ? esc : (uint32_t)(q - qmin);
+    };
     const uint16_t* base = px + V0;
     const uint64_t vlim64 = o.nvox - V0;  // elements from V0 to the end of the proxy
     const uint32_t vlim = uni(vlim64 > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)vlim64);
@@ -796,17 +807,29 @@ __device__ __forceinline__ void emit_chunk_p16(const uint16_t* __restrict__ px, 
                     w[i] = (w[i] & keep) | (wb[i] & ~keep);
                 }
             }
-            uint32_t c[4], fl = 0;
+            uint32_t c[4], om = 0;
+            if constexpr (VALS) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                fl |= w[i] & 0x80008000u;
-                c[i] = ((w[i] | 0x80008000u) - Q2) & 0x7FFF7FFFu;
-            }
-            // flag bits of codes 0..7 (none for a lane that phase 4 redoes)
-            uint32_t om = 0;
-            if (fl && !((bad >> k) & 1u)) {
+                for (int i = 0; i < 4; ++i) {
+                    bool o0, o1;
+                    const uint32_t u0 = vcode(w[i] & 0xFFFFu, o0), u1 = vcode(w[i] >> 16, o1);
+                    c[i] = u0 | (u1 << 16);
+                    om |= (o0 ? 1u : 0u) << (2 * i);
+                    om |= (o1 ? 1u : 0u) << (2 * i + 1);
+                }
+                if ((bad >> k) & 1u) om = 0;  // a lane that phase 4 redoes
+            } else {
+                uint32_t fl = 0;
 #pragma unroll
-                for (int i = 0; i < 8; ++i) om |= ((half16(w, i) >> 15) & 1u) << i;
+                for (int i = 0; i < 4; ++i) {
+                    fl |= w[i] & 0x80008000u;
+                    c[i] = ((w[i] | 0x80008000u) - Q2) & 0x7FFF7FFFu;
+                }
+                // flag bits of codes 0..7 (none for a lane that phase 4 redoes)
+                if (fl && !((bad >> k) & 1u)) {
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) om |= ((half16(w, i) >> 15) & 1u) << i;
+                }
             }
             if (tk0 + kP16Slice <= nfit) {  // uniform: the slice lies inside the chunk and the stream
                 if constexpr (B == 2) {
@@ -881,8 +904,14 @@ __device__ __forceinline__ void emit_chunk_p16(const uint16_t* __restrict__ px, 
                     const uint32_t rc = shfl32(rid, ji[i]);  // every lane executes it
                     if (!redo || t + (uint32_t)i >= n) continue;
                     const uint32_t p = (uint32_t)ld_stream(base + (t + (uint32_t)i + di[i]));
-                    const bool ob = (p >> 15) & 1u;
-                    const uint32_t code = ob ? esc : ((p | 0x8000u) - (Q2 & 0xFFFFu)) & 0x7FFFu;
+                    bool ob;
+                    uint32_t code;
+                    if constexpr (VALS) {
+                        code = vcode(p, ob);
+                    } else {
+                        ob = (p >> 15) & 1u;
+                        code = ob ? esc : ((p | 0x8000u) - (Q2 & 0xFFFFu)) & 0x7FFFu;
+                    }
                     if (ob) atomicAdd((unsigned long long*)&L.row_outl[rc], 1ull);
                     if (t + (uint32_t)i < nfit)
                         reinterpret_cast<C*>(cbase + (uint64_t)t * B)[i] = (C)code;
@@ -909,7 +938,7 @@ __device__ __forceinline__ void chunk_of(const Layout& L, uint64_t q, uint64_t n
 // spans (one per lane) within 2^30 voxels and queues every other chunk for
 // the general kernel, so that its register budget stays that of the lean
 // path.  B = bytes per code.
-template <typename T, int B, bool P16 = false>
+template <typename T, int B, bool P16 = false, bool VALS = false>
 __device__ __forceinline__ void emit_codes_lean(const VPart vp, const T* __restrict__ in, int64_t nx, const Layout& L,
                                                 const EmitOut& o, const uint16_t* __restrict__ px = nullptr) {
     DevState* S = L.S;
@@ -946,7 +975,7 @@ __device__ __forceinline__ void emit_codes_lean(const VPart vp, const T* __restr
         }
         if (near) {
             if constexpr (P16)
-                emit_chunk_p16<B>(px, L, o, c0, (uint32_t)(c1 - c0), nr, rs, d, rid, c0 + off0, trunc);
+                emit_chunk_p16<B, VALS>(px, L, o, c0, (uint32_t)(c1 - c0), nr, rs, d, rid, c0 + off0, trunc);
             else
                 emit_chunk_near<T, B>(in, L, o, c0, (uint32_t)(c1 - c0), nr, rs, d, rid, c0 + off0, trunc);
         } else if (lane == 0) {
@@ -991,6 +1020,18 @@ __device__ __forceinline__ void k_emit_codes_body(const VPart vp, const T* __res
     if (thread_exit_e(L.S)) return;  // no barrier below
     if (unless_p16 && L.S->p16) return;
     const int wb = L.S->width_bits;
+    if constexpr (sizeof(T) == 2) {
+        // 16-bit values: the 16-bit proxy kernel's loads (8 codes a lane, a
+        // 16-byte load and a dword per span), codes from the quantiser
+        const uint16_t* v16 = reinterpret_cast<const uint16_t*>(in);
+        if (wb == 16)
+            emit_codes_lean<T, 2, true, true>(vp, in, nx, L, o, v16);
+        else if (wb == 8)
+            emit_codes_lean<T, 1, true, true>(vp, in, nx, L, o, v16);
+        else
+            emit_codes_lean<T, 4>(vp, in, nx, L, o);
+        return;
+    }
     if (wb == 16)
         emit_codes_lean<T, 2>(vp, in, nx, L, o);
     else if (wb == 8)
