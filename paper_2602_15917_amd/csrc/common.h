@@ -47,6 +47,7 @@ struct DevState {
     uint32_t esc;
     int64_t K;
     uint32_t bin_mlo, bin_mhi;  // ceil(2^40 / K): bin = umulhi(u, mlo) + u * mhi when K <= 65536
+    uint32_t bin_a, bin_m24;    // K <= 46340: bin = ((u << a) * m24) >> 32 on 24-bit operands (m24 0: none)
     // threshold
     int32_t otsu_bin, q_thr, proxy_thr;
     uint32_t flags;
@@ -186,6 +187,15 @@ __device__ __forceinline__ uint32_t bin_slow(uint32_t u, uint32_t K, float binsc
 // below 1/K when K (K - 1) <= 2^32 (checked exhaustively for every K and u).
 __device__ __forceinline__ uint32_t bin_fast(uint32_t u, uint32_t mlo, uint32_t mhi) {
     return __umulhi(u, mlo) + u * mhi;
+}
+
+// exact bin for K <= 46340 with 24-bit operands (one full-rate multiply-high):
+// a and m = ceil(2^(40-a) / K) are chosen so that m < 2^24, (K - 1) 2^a <
+// 2^24 and K^2 2^a <= 2^32; the excess of ((u 2^a) m) / 2^32 over 256 u / K
+// is then below 1/K, so the floor is exact (checked exhaustively for every
+// K <= 46340 and u < K).
+__device__ __forceinline__ uint32_t bin24(uint32_t u, uint32_t a, uint32_t m) {
+    return (uint32_t)(((uint64_t)((u << a) & 0xFFFFFFu) * (uint64_t)(m & 0xFFFFFFu)) >> 32);
 }
 
 // Non-temporal loads for data streamed once (the volume): they do not

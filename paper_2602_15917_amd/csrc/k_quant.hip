@@ -273,6 +273,22 @@ __device__ void set_width(DevState* S) {
     const uint64_t M = ((1ull << 40) + (uint64_t)S->K - 1ull) / (uint64_t)S->K;
     S->bin_mlo = (uint32_t)M;
     S->bin_mhi = (uint32_t)(M >> 32);
+    // the 24-bit form: the smallest a with m < 2^24, when its other two
+    // conditions hold (bin24)
+    S->bin_a = 0u;
+    S->bin_m24 = 0u;
+    const uint64_t K = (uint64_t)S->K;
+    if (K >= 1 && K <= 46340) {
+        for (uint32_t a = 0; a <= 24; ++a) {
+            const uint64_t m = ((1ull << (40 - a)) + K - 1ull) / K;
+            if (m >= (1ull << 24)) continue;
+            if (K * K * (1ull << a) <= (1ull << 32) && ((K - 1ull) << a) < (1ull << 24)) {
+                S->bin_a = a;
+                S->bin_m24 = (uint32_t)m;
+            }
+            break;
+        }
+    }
 }
 
 __device__ __forceinline__ void qfail(DevState* S, int32_t st) {
@@ -428,13 +444,13 @@ hipError_t launch_quantize(const LaunchCtx& lc, const void* in, roix_dtype dt, u
 struct QH {
     float r;
     int32_t qmin, q_thr;
-    uint32_t K, mlo, mhi;
+    uint32_t K, mlo, mhi, a24, m24;
     float binscale;
 };
 
 // Code -> bin (and object flag for a fixed threshold) of one voxel; the
 // histogram count goes to this lane's LDS copy.  Returns the proxy byte.
-template <typename T, bool CODES, bool FIXED, bool FASTDIV>
+template <typename T, bool CODES, bool FIXED, int DIV>
 __device__ __forceinline__ uint32_t qh_one(T x, const QH& p, uint32_t* lh_copy, bool& bad) {
     int32_t q;
     if constexpr (CODES)
@@ -448,7 +464,7 @@ __device__ __forceinline__ uint32_t qh_one(T x, const QH& p, uint32_t* lh_copy, 
             u = 0u;
         }
     }
-    const uint32_t b = FASTDIV ? bin_fast(u, p.mlo, p.mhi) : bin_slow(u, p.K, p.binscale);
+    const uint32_t b = DIV == 2 ? bin24(u, p.a24, p.m24) : (DIV == 1 ? bin_fast(u, p.mlo, p.mhi) : bin_slow(u, p.K, p.binscale));
     atomicAdd(&lh_copy[b], 1u);
     if constexpr (FIXED)
         return q >= p.q_thr ? 1u : 0u;
@@ -458,7 +474,7 @@ __device__ __forceinline__ uint32_t qh_one(T x, const QH& p, uint32_t* lh_copy, 
 
 constexpr int kQhBatch = 8;  // 16-byte loads in flight per lane
 
-template <typename T, bool CODES, bool FIXED, bool FASTDIV>
+template <typename T, bool CODES, bool FIXED, int DIV>
 __device__ __forceinline__ void qh_vec(const uint4& raw, uint8_t* __restrict__ dst, int64_t vi, const QH& p,
                                        uint32_t* mine, bool& bad) {
     constexpr int VN = VecN<T>::n;
@@ -467,12 +483,12 @@ __device__ __forceinline__ void qh_vec(const uint4& raw, uint8_t* __restrict__ d
     if constexpr (VN == 4) {
         uint32_t pk = 0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) pk |= qh_one<T, CODES, FIXED, FASTDIV>(v[j], p, mine, bad) << (8 * j);
+        for (int j = 0; j < 4; ++j) pk |= qh_one<T, CODES, FIXED, DIV>(v[j], p, mine, bad) << (8 * j);
         if (dst) reinterpret_cast<uint32_t*>(dst)[vi] = pk;
     } else {
         uint64_t pk = 0;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) pk |= (uint64_t)qh_one<T, CODES, FIXED, FASTDIV>(v[j], p, mine, bad) << (8 * j);
+        for (int j = 0; j < 8; ++j) pk |= (uint64_t)qh_one<T, CODES, FIXED, DIV>(v[j], p, mine, bad) << (8 * j);
         if (dst) reinterpret_cast<uint64_t*>(dst)[vi] = pk;
     }
 }
@@ -483,7 +499,7 @@ __device__ __forceinline__ void qh_vec(const uint4& raw, uint8_t* __restrict__ d
 // step's first row and column (one scalar division per step) and its offset
 // in the step: q = floor(t / nx) for t < nx + kQhSlots * VN from a float
 // estimate and one correction.  The last N mod VN values go value by value.
-template <typename T, bool CODES, bool FIXED, bool FASTDIV, bool STORE>
+template <typename T, bool CODES, bool FIXED, int DIV, bool STORE>
 __device__ __forceinline__ void qh_flat(const VPart vp, const T* __restrict__ in, int64_t nx, int64_t nrows, int64_t P,
                                         const QH& p, uint32_t* mine, uint8_t* __restrict__ proxy, bool& bad) {
     constexpr int VN = VecN<T>::n;
@@ -517,7 +533,7 @@ __device__ __forceinline__ void qh_flat(const VPart vp, const T* __restrict__ in
                 uint32_t q = (uint32_t)((float)t * inv_nx);
                 if ((uint64_t)q * unx > t) --q;
                 if ((uint64_t)(q + 1) * unx <= t) ++q;
-                const uint32_t pb = qh_one<T, CODES, FIXED, FASTDIV>(v[j], p, mine, bad);
+                const uint32_t pb = qh_one<T, CODES, FIXED, DIV>(v[j], p, mine, bad);
                 if constexpr (STORE) proxy[(row0 + q) * P + (t - q * unx)] = (uint8_t)pb;
             }
         }
@@ -525,7 +541,7 @@ __device__ __forceinline__ void qh_flat(const VPart vp, const T* __restrict__ in
     if (wave == 0)
         for (int64_t f = nvec * VN + lane; f < N; f += kWave) {
             const int64_t row = f / nx, x = f - row * nx;
-            const uint32_t pb = qh_one<T, CODES, FIXED, FASTDIV>(ld_stream(in + f), p, mine, bad);
+            const uint32_t pb = qh_one<T, CODES, FIXED, DIV>(ld_stream(in + f), p, mine, bad);
             if constexpr (STORE) proxy[row * P + x] = (uint8_t)pb;
         }
 }
@@ -537,7 +553,7 @@ __device__ __forceinline__ void qh_flat(const VPart vp, const T* __restrict__ in
 // one at a time, so that every lane has kQhBatch loads in flight.
 // VEC 2: the flat path above.  VEC 0 (the volume itself not 16-byte
 // aligned): lane l takes voxels l, l + 64, ... of one row at a time.
-template <typename T, bool CODES, bool FIXED, bool FASTDIV, int VEC, bool STORE>
+template <typename T, bool CODES, bool FIXED, int DIV, int VEC, bool STORE>
 __device__ __forceinline__ void qh_rows(const VPart vp, const T* __restrict__ in, int64_t nx, int64_t nrows, int64_t P,
                                         const QH& p, uint32_t* mine, uint8_t* __restrict__ proxy, bool& bad) {
     constexpr int VN = VecN<T>::n;
@@ -546,7 +562,7 @@ __device__ __forceinline__ void qh_rows(const VPart vp, const T* __restrict__ in
     const int64_t wave = ((int64_t)vp.b * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = (int64_t)vp.n * blockDim.x / kWave;
     if constexpr (VEC == 2) {
-        qh_flat<T, CODES, FIXED, FASTDIV, STORE>(vp, in, nx, nrows, P, p, mine, proxy, bad);
+        qh_flat<T, CODES, FIXED, DIV, STORE>(vp, in, nx, nrows, P, p, mine, proxy, bad);
     } else if constexpr (VEC == 1) {
         const int64_t nv = nx / VN;
         int lg = 0;
@@ -567,7 +583,7 @@ __device__ __forceinline__ void qh_rows(const VPart vp, const T* __restrict__ in
                     const int64_t e = (int64_t)k * kWave + lane;
                     const int64_t row = row0 + (e >> lg), vi = e & ((1ll << lg) - 1);
                     if (vi >= nv || row >= nrows) continue;
-                    qh_vec<T, CODES, FIXED, FASTDIV>(raw[k], STORE ? proxy + row * P : nullptr, vi, p, mine, bad);
+                    qh_vec<T, CODES, FIXED, DIV>(raw[k], STORE ? proxy + row * P : nullptr, vi, p, mine, bad);
                 }
             }
         } else {
@@ -584,7 +600,7 @@ __device__ __forceinline__ void qh_rows(const VPart vp, const T* __restrict__ in
 #pragma unroll
                     for (int k = 0; k < kQhBatch; ++k) {
                         const int64_t vi = v0 + k * kWave + lane;
-                        if (vi < nv) qh_vec<T, CODES, FIXED, FASTDIV>(raw[k], dst, vi, p, mine, bad);
+                        if (vi < nv) qh_vec<T, CODES, FIXED, DIV>(raw[k], dst, vi, p, mine, bad);
                     }
                 }
             }
@@ -604,7 +620,7 @@ __device__ __forceinline__ void qh_rows(const VPart vp, const T* __restrict__ in
                 for (int k = 0; k < kQhBatch; ++k) {
                     const int64_t x = x0 + k * kWave + lane;
                     if (x >= nx) continue;
-                    const uint32_t pb = qh_one<T, CODES, FIXED, FASTDIV>(v[k], p, mine, bad);
+                    const uint32_t pb = qh_one<T, CODES, FIXED, DIV>(v[k], p, mine, bad);
                     if constexpr (STORE) dst[x] = (uint8_t)pb;
                 }
             }
@@ -631,13 +647,17 @@ __device__ __forceinline__ void k_quant_hist_body(const VPart vp, const T* __res
     p.K = (uint32_t)S->K;
     p.mlo = S->bin_mlo;
     p.mhi = S->bin_mhi;
+    p.a24 = S->bin_a;
+    p.m24 = S->bin_m24;
     p.binscale = S->binscale;
     uint32_t* mine = lh + (threadIdx.x % kHistCopies) * kHistStride;
     bool bad = false;
-    if (p.K <= 65536u)
-        qh_rows<T, CODES, FIXED, true, VEC, STORE>(vp, in, nx, nrows, P, p, mine, proxy, bad);
+    if (p.m24)
+        qh_rows<T, CODES, FIXED, 2, VEC, STORE>(vp, in, nx, nrows, P, p, mine, proxy, bad);
+    else if (p.K <= 65536u)
+        qh_rows<T, CODES, FIXED, 1, VEC, STORE>(vp, in, nx, nrows, P, p, mine, proxy, bad);
     else
-        qh_rows<T, CODES, FIXED, false, VEC, STORE>(vp, in, nx, nrows, P, p, mine, proxy, bad);
+        qh_rows<T, CODES, FIXED, 0, VEC, STORE>(vp, in, nx, nrows, P, p, mine, proxy, bad);
     if constexpr (CODES) {
         if (bad) fail(S, ROIX_EINVAL);
     }

@@ -148,3 +148,15 @@ def test_status_strings_and_stages(lib):
         assert L.roix_status_string(s)
     names = roix.stage_names()
     assert "quant_hist" in names and "emit" in names and len(names) == L.roix_stage_count()
+
+
+def test_bin_division_forms_exact(tmp_path):
+    # the kernels' multiply-high forms of floor(256 u / K), checked for every
+    # K <= 65536 and u < K by a small C program
+    import subprocess
+    src = os.path.join(os.path.dirname(__file__), "bin_division_check.c")
+    exe = str(tmp_path / "bin_division_check")
+    subprocess.run(["gcc", "-O2", "-o", exe, src], check=True)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout
+    assert r.stdout.split()[:2] == ["max_k24", "46340"], r.stdout
