@@ -197,6 +197,21 @@ __device__ __forceinline__ uint32_t bin_fast(uint32_t u, uint32_t mlo, uint32_t 
 __device__ __forceinline__ uint32_t bin24(uint32_t u, uint32_t a, uint32_t m) {
     return (uint32_t)(((uint64_t)((u << a) & 0xFFFFFFu) * (uint64_t)(m & 0xFFFFFFu)) >> 32);
 }
+// a and m of bin24 for K (the smallest a with m < 2^24); m = 0: no such form
+__device__ __forceinline__ void bin24_params(uint64_t K, uint32_t& a, uint32_t& m) {
+    a = 0u;
+    m = 0u;
+    if (K < 1 || K > 46340) return;
+    for (uint32_t t = 0; t <= 24; ++t) {
+        const uint64_t mt = ((1ull << (40 - t)) + K - 1ull) / K;
+        if (mt >= (1ull << 24)) continue;
+        if (K * K * (1ull << t) <= (1ull << 32) && ((K - 1ull) << t) < (1ull << 24)) {
+            a = t;
+            m = (uint32_t)mt;
+        }
+        return;
+    }
+}
 
 // Non-temporal loads for data streamed once (the volume): they do not
 // displace the reused run tables from the caches.

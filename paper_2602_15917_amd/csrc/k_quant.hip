@@ -273,22 +273,7 @@ __device__ void set_width(DevState* S) {
     const uint64_t M = ((1ull << 40) + (uint64_t)S->K - 1ull) / (uint64_t)S->K;
     S->bin_mlo = (uint32_t)M;
     S->bin_mhi = (uint32_t)(M >> 32);
-    // the 24-bit form: the smallest a with m < 2^24, when its other two
-    // conditions hold (bin24)
-    S->bin_a = 0u;
-    S->bin_m24 = 0u;
-    const uint64_t K = (uint64_t)S->K;
-    if (K >= 1 && K <= 46340) {
-        for (uint32_t a = 0; a <= 24; ++a) {
-            const uint64_t m = ((1ull << (40 - a)) + K - 1ull) / K;
-            if (m >= (1ull << 24)) continue;
-            if (K * K * (1ull << a) <= (1ull << 32) && ((K - 1ull) << a) < (1ull << 24)) {
-                S->bin_a = a;
-                S->bin_m24 = (uint32_t)m;
-            }
-            break;
-        }
-    }
+    bin24_params((uint64_t)S->K, S->bin_a, S->bin_m24);
 }
 
 __device__ __forceinline__ void qfail(DevState* S, int32_t st) {

@@ -48,7 +48,7 @@ __global__ void k_section_check(const roix_quant_info* __restrict__ qi, const ro
 }
 
 struct SecParams {
-    uint32_t K, mlo, mhi, esc;
+    uint32_t K, mlo, mhi, esc, a24, m24;
     float binscale, r;
     int32_t qmin;
     bool fast;
@@ -62,6 +62,7 @@ __device__ __forceinline__ SecParams sec_params(const roix_quant_info* __restric
     p.mlo = (uint32_t)M;
     p.mhi = (uint32_t)(M >> 32);
     p.fast = p.K <= 65536u;
+    bin24_params(p.K, p.a24, p.m24);
     p.binscale = (float)(256.0 / (double)p.K);
     p.esc = qi->esc;
     p.r = qi->r;
@@ -70,7 +71,12 @@ __device__ __forceinline__ SecParams sec_params(const roix_quant_info* __restric
 }
 
 __device__ __forceinline__ uint32_t sec_level(uint32_t u, const SecParams& p) {
-    return p.fast ? bin_fast(u, p.mlo, p.mhi) : bin_slow(u, p.K, p.binscale);
+    return p.m24 ? bin24(u, p.a24, p.m24) : (p.fast ? bin_fast(u, p.mlo, p.mhi) : bin_slow(u, p.K, p.binscale));
+}
+// the same with the form fixed at compile time (DIV 2: 24-bit, 1: 32-bit, 0: float estimate)
+template <int DIV>
+__device__ __forceinline__ uint32_t sec_level_d(uint32_t u, const SecParams& p) {
+    return DIV == 2 ? bin24(u, p.a24, p.m24) : (DIV == 1 ? bin_fast(u, p.mlo, p.mhi) : bin_slow(u, p.K, p.binscale));
 }
 
 // The level of the escaped code c: its row is the last one whose first code
@@ -117,7 +123,7 @@ __device__ __forceinline__ uint32_t code_at(const uint4 (&w)[B], int i) {
 // The 16 levels of a unit, packed for one 16-byte store (escapes resolved).
 // Every index into the codes is static (the escapes are found through a bit
 // mask), so codes and levels stay in registers.
-template <typename T, int B>
+template <typename T, int B, int DIV>
 __device__ __forceinline__ v4u32_t levels16(const uint4 (&w)[B], uint64_t c0, const T* __restrict__ in, int64_t nx,
                                             int64_t ny, int64_t nz, const roix_row* __restrict__ rows, uint64_t nr,
                                             const SecParams& p, roix_section_info* info, const SecEsc& esc,
@@ -128,7 +134,7 @@ __device__ __forceinline__ v4u32_t levels16(const uint4 (&w)[B], uint64_t c0, co
     for (int i = 0; i < kSecCodes; ++i) {
         const uint32_t u = code_at<B>(w, i);
         emask |= (uint32_t)(u == p.esc) << i;
-        o[i / 4] |= (u == p.esc ? 0u : sec_level(u, p)) << (8 * (i & 3));
+        o[i / 4] |= (u == p.esc ? 0u : sec_level_d<DIV>(u, p)) << (8 * (i & 3));
     }
     while (emask) {  // listed for the escape kernel (their level stays 0 here), or resolved in place
         const int i = __builtin_ctz(emask);
@@ -161,7 +167,7 @@ __device__ __forceinline__ v4u32_t levels16(const uint4 (&w)[B], uint64_t c0, co
 template <int B>
 constexpr int sec_unroll() { return B == 4 ? 2 : 4; }
 
-template <typename T, int B>
+template <typename T, int B, int DIV>
 __device__ void section_pass(const T* __restrict__ in, int64_t nx, int64_t ny, int64_t nz,
                              const roix_row* __restrict__ rows, uint64_t nr, const uint8_t* __restrict__ stream,
                              uint64_t n, const SecParams& p, uint8_t* __restrict__ out, roix_section_info* info,
@@ -185,7 +191,7 @@ __device__ void section_pass(const T* __restrict__ in, int64_t nx, int64_t ny, i
         for (int k = 0; k < kSecUnroll; ++k) {
             const uint64_t u = u0 + k * stride;
             if (u < nu) {
-                const v4u32_t t = levels16<T, B>(w[k], u * kSecCodes, in, nx, ny, nz, rows, nr, p, info, esc, s_cnt);
+                const v4u32_t t = levels16<T, B, DIV>(w[k], u * kSecCodes, in, nx, ny, nz, rows, nr, p, info, esc, s_cnt);
                 __builtin_nontemporal_store(t, reinterpret_cast<v4u32_t*>(out + u * kSecCodes));
             }
         }
@@ -216,7 +222,12 @@ __global__ __launch_bounds__(kBlock) void k_section(const T* __restrict__ in, in
     if (threadIdx.x == 0) s_cnt = 0u;
     __syncthreads();
     const SecParams p = sec_params(qi);
-    section_pass<T, B>(in, nx, ny, nz, rows, ei->n_rows, stream, ei->n_codes, p, out, info, esc, &s_cnt);
+    if (p.m24)  // uniform
+        section_pass<T, B, 2>(in, nx, ny, nz, rows, ei->n_rows, stream, ei->n_codes, p, out, info, esc, &s_cnt);
+    else if (p.fast)
+        section_pass<T, B, 1>(in, nx, ny, nz, rows, ei->n_rows, stream, ei->n_codes, p, out, info, esc, &s_cnt);
+    else
+        section_pass<T, B, 0>(in, nx, ny, nz, rows, ei->n_rows, stream, ei->n_codes, p, out, info, esc, &s_cnt);
     __syncthreads();
     if (threadIdx.x == 0) esc.count[blockIdx.x] = s_cnt;
 }
