@@ -218,16 +218,22 @@ __global__ __launch_bounds__(kBlock) void k_scan_down_plain(const T* in, T* out,
     k_scan_down_plain_body<T>(hw_part(), in, out, n_host, tmp);
 }
 
-// the chunk count of a scan: kScanBlocks, or fewer for a batch's small volumes
-static int scan_grid(const LaunchCtx& lc) {
-    return lc.scan_grid >= 1 && lc.scan_grid <= kScanBlocks ? lc.scan_grid : kScanBlocks;
+// the chunk count of a scan of at most n_host elements: one workgroup step
+// (kScanPer * kBlock elements) a chunk or more, at most kScanBlocks (and at
+// most lc.scan_grid), so that a small volume (or each volume of a batch)
+// launches only the workgroups it can use
+static int scan_grid(const LaunchCtx& lc, int64_t n_host) {
+    const int cap = lc.scan_grid >= 1 && lc.scan_grid <= kScanBlocks ? lc.scan_grid : kScanBlocks;
+    const int64_t per = (int64_t)kScanPer * kBlock;
+    const int64_t need = (n_host + per - 1) / per;
+    return need < 1 ? 1 : (need < cap ? (int)need : cap);
 }
 
 hipError_t launch_scan_u32(const LaunchCtx& lc, const uint32_t* in, uint32_t* out, int64_t n_host,
                            const uint32_t* n_dev, uint32_t* total_out, uint32_t* out_end, uint64_t* tmp,
                            DevState* cap_S, uint64_t cap, int cap_err, const CompInit* ci) {
     timer_begin(lc.timer, ST_SCAN, lc.stream);
-    const int G = scan_grid(lc);
+    const int G = scan_grid(lc, n_host);
     const CompInit none{nullptr, nullptr, 0, nullptr, nullptr, 0};
     launch_k<kBlock, k_scan_reduce_body<uint32_t>>(lc, k_scan_reduce<uint32_t>, dim3(G), dim3(kBlock), 0, in,
                                                    n_host, n_dev, tmp);
@@ -256,7 +262,7 @@ hipError_t launch_scan_u32_base(const LaunchCtx& lc, const uint32_t* in, uint32_
 hipError_t launch_scan_u64(const LaunchCtx& lc, const uint64_t* in, uint64_t* out, int64_t n_host,
                            unsigned long long* total_out, uint64_t* tmp) {
     timer_begin(lc.timer, ST_SCAN, lc.stream);
-    const int G = scan_grid(lc);
+    const int G = scan_grid(lc, n_host);
     launch_k<kBlock, k_scan_reduce_body<uint64_t>>(lc, k_scan_reduce<uint64_t>, dim3(G), dim3(kBlock), 0, in,
                                                    n_host, (const uint32_t*)nullptr, tmp);
     launch_k<kBlock, k_scan_down_body<uint64_t, unsigned long long>>(
