@@ -209,7 +209,7 @@ static hipError_t label_runs(const LaunchCtx& lc, const Geom& g, const Layout& L
 hipError_t roix::components_and_keep(const LaunchCtx& lc, const Geom& g, const Layout& L, const roix_criterion* crit,
                                      roix_component* comps, int64_t comps_cap) {
     hipError_t e;
-    if ((e = launch_flatten(lc, L)) != hipSuccess) return e;
+    if ((e = launch_flatten(lc, g, L)) != hipSuccess) return e;
     const uint64_t cap = (uint64_t)(comps ? comps_cap : 0);
     const CompInit ci{L.run_xs, L.run_row, g.nx, comps, L.kept_flag, cap};
     if ((e = launch_scan_u32(lc, L.comp_id, L.comp_id, (int64_t)L.run_cap, &L.S->n_runs, &L.S->n_comps, nullptr,

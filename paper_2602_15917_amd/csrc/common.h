@@ -577,7 +577,7 @@ hipError_t launch_section(const LaunchCtx& lc, const void* in, roix_dtype dt, co
                           void* scratch, size_t scratch_bytes);
 hipError_t launch_absq(const LaunchCtx& lc, const uint8_t* D, int64_t m, uint32_t K, uint8_t* Q, void* scratch,
                        roix_absq_info* info);
-hipError_t launch_flatten(const LaunchCtx& lc, const Layout& L);
+hipError_t launch_flatten(const LaunchCtx& lc, const Geom& g, const Layout& L);
 hipError_t launch_comp_stats(const LaunchCtx& lc, const Geom& g, const Layout& L, roix_component* comps);
 hipError_t launch_keep(const LaunchCtx& lc, const Geom& g, const Layout& L, roix_component* comps,
                        const roix_criterion* crit);

@@ -1322,7 +1322,9 @@ hipError_t launch_emit(const LaunchCtx& lc, const Geom& g, const Layout& L, cons
     o.nvox = L.nvals ? L.nvals : g.N;
     const dim3 block(kBlock);
     const dim3 grid_rows_t(grid_rows(g.nrows, kBlock, lc.grid_stream));
-    const dim3 grid_waves(lc.grid_emit);
+    // a wave per chunk of kEmitChunk codes, at most one code per voxel: a
+    // small volume launches only the waves its chunks can use
+    const dim3 grid_waves(grid_rows((int64_t)((g.N + kEmitChunk - 1) / kEmitChunk), kBlock / kWave, lc.grid_emit));
     timer_begin(lc.timer, ST_EMIT, lc.stream);
     launch_k<kBlock, k_emit_index_body>(lc, k_emit_index, grid_rows_t, block, 0, L, g.nx, g.nrows);
     // the lean kernel queues the chunks it leaves to the general kernel

@@ -34,6 +34,16 @@ static int grid_for(int64_t items, int per_block, int cap) {
     return (int)g;
 }
 
+// Workgroups of a pass over the runs (or components) of a volume of nrows
+// rows, planned for kPlanRuns runs a row: the run count is device data, and
+// the passes stride over any count, so the grid only sets their speed; a
+// small volume (or each small volume of a batch) then launches few
+// workgroups, a large one the cap.
+constexpr int kPlanRuns = 8;
+static int runs_grid(int64_t nrows, int runs_per_block, int cap) {
+    return grid_for(nrows * kPlanRuns, runs_per_block, cap);
+}
+
 // ------------------------------------------------------- mask bits + counts
 
 // Bytes of v above the threshold t, as 4 bits: with T = 255 - t, byte b > t
@@ -1060,7 +1070,9 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_cross_lds(const uint32_t* __r
 
 hipError_t launch_union(const LaunchCtx& lc, const Geom& g, const Layout& L, int conn) {
     timer_begin(lc.timer, ST_UNION, lc.stream);
-    const uint32_t G = (uint32_t)lc.seg_grid;
+    // segments of at least kSegMin runs: a volume planned to hold fewer
+    // segments than seg_grid launches one workgroup per planned segment
+    const uint32_t G = (uint32_t)runs_grid(g.nrows, kSegMin, lc.seg_grid);
     const uint32_t ny = (uint32_t)g.ny;
     const double inv_ny = 1.0 / (double)g.ny;
     const uint32_t tp = (uint32_t)lc.seg_runs;
@@ -1117,9 +1129,10 @@ __global__ __launch_bounds__(kBlock) void k_flatten(uint32_t* parent, uint32_t* 
     k_flatten_body(hw_part(), parent, root_flag, S);
 }
 
-hipError_t launch_flatten(const LaunchCtx& lc, const Layout& L) {
+hipError_t launch_flatten(const LaunchCtx& lc, const Geom& g, const Layout& L) {
     timer_begin(lc.timer, ST_FLATTEN, lc.stream);
-    launch_k<kBlock, k_flatten_body>(lc, k_flatten, dim3(lc.grid_stream), dim3(kBlock), 0, L.parent, L.comp_id,
+    launch_k<kBlock, k_flatten_body>(lc, k_flatten, dim3(runs_grid(g.nrows, kBlock, lc.grid_stream)), dim3(kBlock), 0,
+                       L.parent, L.comp_id,
                        (const DevState*)L.S);
     timer_end(lc.timer, ST_FLATTEN, lc.stream);
     return hipGetLastError();
@@ -1304,7 +1317,7 @@ __global__ __launch_bounds__(kBlock) void k_comp_stats(const uint32_t* __restric
 
 hipError_t launch_comp_stats(const LaunchCtx& lc, const Geom& g, const Layout& L, roix_component* comps) {
     timer_begin(lc.timer, ST_COMPS, lc.stream);
-    launch_k<kBlock, k_comp_stats_body>(lc, k_comp_stats, dim3(grid_for((int64_t)L.run_cap, kBlock * kStatRuns, lc.stats_grid)),
+    launch_k<kBlock, k_comp_stats_body>(lc, k_comp_stats, dim3(runs_grid(g.nrows, kBlock * kStatRuns, lc.stats_grid)),
                        dim3(kBlock), 0, (const uint32_t*)L.run_xs, (const uint32_t*)L.run_xe,
                        (const uint32_t*)L.run_row, (const uint32_t*)L.parent, (const uint32_t*)L.comp_id,
                        (uint32_t)g.ny, 1.0 / (double)g.ny, comps, (const DevState*)L.S);
@@ -1481,7 +1494,7 @@ __global__ __launch_bounds__(kBlock) void k_keep_apply(roix_component* comps, ui
 hipError_t launch_keep(const LaunchCtx& lc, const Geom& g, const Layout& L, roix_component* comps,
                        const roix_criterion* crit) {
     timer_begin(lc.timer, ST_KEEP, lc.stream);
-    const int grid = kKeepGrid;
+    const int grid = runs_grid(g.nrows, kBlock, kKeepGrid);  // components: at most one per run
     if (crit->keep == ROIX_KEEP_LARGEST)
         launch_k<kBlock, k_keep_largest_body>(lc, k_keep_largest, dim3(grid), dim3(kBlock), 0, comps, L.kept_flag,
                                               (const uint32_t*)L.run_off, (const uint32_t*)L.run_xs, g.nx, L.S);
