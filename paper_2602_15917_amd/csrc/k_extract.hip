@@ -986,7 +986,11 @@ __device__ __forceinline__ void emit_codes_lean(const VPart vp, const T* __restr
 }
 
 // The queued chunks: many short spans (lane windows with a cross-lane
-// search), or few spans whose voxels lie far apart (64-bit offsets).
+// search), or few spans whose voxels lie far apart (64-bit offsets).  A
+// chunk of many spans is shared by kGenSplit waves, each taking a quarter of
+// its codes (the lane windows clip to that range), so that a volume with few
+// chunks, all of short spans, is not left to a handful of waves.
+constexpr uint32_t kGenSplit = 4;
 template <typename T, int B>
 __device__ __forceinline__ void emit_codes_general(const VPart vp, const T* __restrict__ in, int64_t nx,
                                                    const Layout& L, const EmitOut& o) {
@@ -998,15 +1002,19 @@ __device__ __forceinline__ void emit_codes_general(const VPart vp, const T* __re
     const uint32_t nq = uni(S->n_slow);
     const uint32_t wave = uni((vp.b * blockDim.x + threadIdx.x) / kWave);
     const uint32_t nwaves = vp.n * blockDim.x / kWave;
-    for (uint32_t i = wave; i < nq; i += nwaves) {
-        const uint64_t q = uni(L.slow_chunks[i]);
+    for (uint32_t i = wave; i < nq * kGenSplit; i += nwaves) {
+        const uint64_t q = uni(L.slow_chunks[i / kGenSplit]);
+        const uint32_t part = i % kGenSplit;
         uint64_t c0, c1;
         uint32_t j0, j1;
         chunk_of(L, q, nchunks, n_codes, n_rows, c0, c1, j0, j1);
-        if (j1 - j0 < (uint32_t)kFastSpans)
-            emit_chunk_fast<T, B>(in, nx, L, o, c0, c1, j0, j1 - j0 + 1, trunc);
-        else
-            emit_chunk_many<T, B>(in, nx, L, o, c0, c1, j0, j1, trunc);
+        if (j1 - j0 < (uint32_t)kFastSpans) {
+            if (part == 0) emit_chunk_fast<T, B>(in, nx, L, o, c0, c1, j0, j1 - j0 + 1, trunc);
+        } else {
+            const uint64_t a = c0 + (uint64_t)part * (kEmitChunk / kGenSplit);
+            const uint64_t b = a + kEmitChunk / kGenSplit < c1 ? a + kEmitChunk / kGenSplit : c1;
+            if (a < b) emit_chunk_many<T, B>(in, nx, L, o, a, b, j0, j1, trunc);
+        }
     }
     if (trunc) atomicOr(&S->trunc, 1);
 }
