@@ -533,7 +533,7 @@ typedef struct {
  * grid); the sequences are merged so that each kernel runs once for every
  * volume that needs it next, each workgroup finding its volume in a device
  * table of arguments.  Volumes whose worst-case layouts do not all fit the
- * arena at once run in consecutive groups.  The merged sequence (about 70
+ * arena at once run in consecutive groups.  The merged sequence (about 30
  * launches, whatever the number of volumes) is recorded once and kept while
  * the batch's structure -- volume shapes, flows, grids, parameters -- is the
  * same; buffer addresses may change from call to call.  It is issued as
@@ -558,7 +558,7 @@ roix_status roix_fused_batch(roix_ctx* ctx, int32_t n, const roix_volume_desc* v
  *   "batch_group"    volumes per launch group of roix_fused_batch (0 = as
  *                    many as the arena holds; 1 = one volume at a time)
  *   "batch_graph"    1 = capture/replay batches as a HIP graph, 0 = launch
- *                    directly (default: a batch is about 70 launches, and
+ *                    directly (default: a batch is about 30 launches, and
  *                    their direct launch costs less host time than the
  *                    graph's launch)
  *   "batch_fused16_min_voxels"  as fused16_min_voxels, for the volumes of a
