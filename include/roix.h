@@ -483,7 +483,8 @@ roix_status roix_abs_quantize(roix_ctx* ctx, const uint8_t* d_pixels, int64_t m,
  * growing like the Fibonacci numbers over more than 33 bytes; the payload is
  * then unspecified), ROIX_ETRUNC when the payload exceeds payload_cap_words
  * (the offsets and sizes are still complete; blocks that do not fit are not
- * written).  The context's arena holds 4 KB of state while the call runs.
+ * written).  The context's arena holds about 20 KB of state and tables while
+ * the call runs.
  * Errors: ROIX_EINVAL (NULL or misaligned buffers, n outside 0..2^40,
  * negative capacity), ROIX_ENOMEM (arena too small), ROIX_EDEVICE. */
 typedef struct {

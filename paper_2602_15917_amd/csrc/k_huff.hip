@@ -30,6 +30,8 @@ constexpr int kHfBlock = 4096;   // input bytes per block
 constexpr int kHfPeek = 11;      // bits of the decoder's lookup table
 constexpr int kHfRound = 8;      // decoder steps between refills (2 bytes each at most)
 constexpr int kHfRing = 36;      // LDS bytes of a lane's 32-byte output ring (stride against bank conflicts)
+constexpr int kHf3Peek = 12;     // bits of the three-code lookup table of the sub-block decoder
+constexpr int kHf3Round = 5;     // its steps between refills (3 bytes each at most: 15 bytes a round)
 constexpr int kHfSub = 256;      // input bytes per sub-block of the sub-block index
 constexpr int kHfSubs = kHfBlock / kHfSub;
 
@@ -489,24 +491,72 @@ __device__ __forceinline__ bool hf_tables(const uint8_t* lengths, unsigned long 
     return true;
 }
 
+// The three-code lookup table of the sub-block decoder: entry e holds the
+// whole codes that start at the top of the kHf3Peek-bit value e, up to three
+// of them: their bytes (bits 0-23, the first code's lowest), their total
+// length (bits 24-27) and their count (bits 28-29; 0 when the first code is
+// longer than the table).  One thread per entry; each workgroup first builds
+// the canonical bounds (hf_tables also checks the lengths).
+__global__ __launch_bounds__(256) void k_hf_peek3(const uint8_t* lengths, unsigned long long n, uint32_t* tab,
+                                                  HfState* S) {
+    __shared__ HfDecode T;
+    if (!hf_tables<kHfPeek>(lengths, n, T, S)) return;
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (1u << kHf3Peek)) return;
+    uint32_t bytes = 0u, tot = 0u, cnt = 0u;
+    while (cnt < 3u) {
+        const uint32_t room = (uint32_t)kHf3Peek - tot;
+        uint32_t L = 1u, sym = 0u;
+        bool found = false;
+        for (; L <= room; ++L) {
+            const uint32_t c = (e >> (room - L)) & ((1u << L) - 1u);
+            if (c - T.first[L] < T.count[L]) {
+                sym = T.sym[T.index[L] + (c - T.first[L])];
+                found = true;
+                break;
+            }
+        }
+        if (!found) break;
+        bytes |= sym << (8u * cnt);
+        tot += L;
+        ++cnt;
+    }
+    tab[e] = bytes | (tot << 24) | (cnt << 28);
+}
+
 // A lane decodes one task: a whole block (SUB false), or with the sub-block
 // index one 256-byte sub-block (SUB true: 16 lanes per block, each starting
 // at the bit the index gives, so that a wave decodes 4 blocks at once).
 // Lanes keep a 64-bit bit window fed from 16-byte loads one quad ahead; an
 // 11-bit lookup table yields one or two codes, a canonical search the longer
 // ones.  A sub-block must take exactly its stated bits.
-template <bool SUB>
+// P3 (with SUB): each step first looks up the next kHf3Peek bits in the
+// three-code table tab3 (staged in LDS), and takes up to three codes at once
+// when they all belong to the task and lie in the window; otherwise one code
+// as above.  Rounds are then kHf3Round steps, so that the ring never holds
+// more than 31 bytes.
+template <bool SUB, bool P3 = false>
 __global__ __launch_bounds__(256) void k_hf_decode(const uint8_t* lengths, const unsigned long long* block_off,
                                                    const uint16_t* sub_bits, const uint32_t* payload,
                                                    unsigned long long payload_words, unsigned long long n,
-                                                   uint8_t* out, HfState* S, int vec) {
+                                                   uint8_t* out, HfState* S, int vec, const uint32_t* tab3) {
     __shared__ HfDecode T;
     __shared__ __align__(16) uint8_t ring_sh[kHfRing * 256];
+    __shared__ __align__(16) uint32_t P3t[P3 ? (1 << kHf3Peek) : 4];
     if (!hf_tables<kHfPeek>(lengths, n, T, S)) return;
     const int t = threadIdx.x;
+    if constexpr (P3) {
+        for (int i = t; i < (1 << kHf3Peek) / 4; i += blockDim.x)
+            reinterpret_cast<uint4*>(P3t)[i] = reinterpret_cast<const uint4*>(tab3)[i];
+        __syncthreads();
+    }
+    constexpr int kSteps = P3 ? kHf3Round : kHfRound;
     const unsigned long long nb = (n + kHfBlock - 1) / kHfBlock;
     const unsigned long long ntasks = SUB ? nb * kHfSubs : nb;
     const int maxl = T.maxl;
+    // with words still outside the window, a step decodes only when this many
+    // bits are in it (a code of the longest length; the three-code table's bits)
+    const int need = P3 && maxl < kHf3Peek ? kHf3Peek : maxl;
     uint8_t* ring = ring_sh + kHfRing * t;  // this lane's output bytes, 16 at a time to HBM
     // The wave goes in rounds: at the top of a round each lane takes the
     // quad it loaded the round before, asks for the next, and stores 16
@@ -600,7 +650,7 @@ __global__ __launch_bounds__(256) void k_hf_decode(const uint8_t* lengths, const
                 rd += 16u;
             }
 #pragma unroll 1
-            for (int it = 0; it < kHfRound; ++it) {
+            for (int it = 0; it < kSteps; ++it) {
                 // take a word into the window (no branch)
                 const bool take = have <= 32 && ci < 4u && rem > 0u;
                 const uint32_t word = ci == 0u ? A[0] : ci == 1u ? A[1] : ci == 2u ? A[2] : A[3];
@@ -616,7 +666,24 @@ __global__ __launch_bounds__(256) void k_hf_decode(const uint8_t* lengths, const
                 qa += shift ? 4ull : 0ull;
                 bvalid = bvalid && !shift;
                 // with words still outside the window, decode only what is sure to fit
-                if (!ok || left == 0u || (rem > 0u && have < maxl)) continue;
+                if (!ok || left == 0u || (rem > 0u && have < need)) continue;
+                if constexpr (P3) {
+                    const uint32_t e3 = P3t[window >> (64 - kHf3Peek)];
+                    const uint32_t c3 = e3 >> 28, L3 = (e3 >> 24) & 15u;
+                    if (c3 != 0u && c3 <= left && (int)L3 <= have) {  // up to three codes of the task
+                        window <<= L3;
+                        have -= (int)L3;
+                        used += L3;
+                        // all three bytes always: those past the codes' count land
+                        // past the ring's live bytes and are overwritten later
+                        ring[wr & 31u] = (uint8_t)e3;
+                        ring[(wr + 1u) & 31u] = (uint8_t)(e3 >> 8);
+                        ring[(wr + 2u) & 31u] = (uint8_t)(e3 >> 16);
+                        wr += c3;
+                        left -= c3;
+                        continue;
+                    }
+                }
                 const uint32_t pk = T.peek[window >> (64 - kHfPeek)];
                 int L = (int)((pk >> 16) & 31u);
                 uint32_t v = pk;
@@ -678,7 +745,11 @@ __global__ void k_hf_decode_finalize(const HfState* S, unsigned long long n, roi
 
 static size_t hf_align(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t huff_scratch_bytes() { return hf_align(sizeof(HfState)) + hf_align((size_t)(kScanBlocks + 1) * 8); }
+// the state, then the encoder's scan chunk sums or the decoder's three-code table
+size_t huff_scratch_bytes() {
+    const size_t scan = hf_align((size_t)(kScanBlocks + 1) * 8), tab3 = hf_align((size_t)(1 << kHf3Peek) * 4);
+    return hf_align(sizeof(HfState)) + (scan > tab3 ? scan : tab3);
+}
 
 
 
@@ -728,12 +799,17 @@ hipError_t launch_huff_decode(const LaunchCtx& lc, const uint8_t* lengths, const
         const int64_t g = (tasks + 255) / 256;
         const int grid = (int)(g < (int64_t)lc.grid_stream ? g : (int64_t)lc.grid_stream);
         const int vec = ((uintptr_t)payload & 15u) == 0u ? 1 : 0;
-        if (sub_bits)
-            hipLaunchKernelGGL(k_hf_decode<true>, dim3(grid), dim3(256), 0, lc.stream, lengths, block_off, sub_bits,
-                               payload, (unsigned long long)payload_words, N, out, S, vec);
-        else
-            hipLaunchKernelGGL(k_hf_decode<false>, dim3(grid), dim3(256), 0, lc.stream, lengths, block_off, sub_bits,
-                               payload, (unsigned long long)payload_words, N, out, S, vec);
+        if (sub_bits) {
+            uint32_t* tab3 = (uint32_t*)((uint8_t*)scratch + hf_align(sizeof(HfState)));
+            hipLaunchKernelGGL(k_hf_peek3, dim3((1 << kHf3Peek) / 256), dim3(256), 0, lc.stream, lengths, N, tab3, S);
+            hipLaunchKernelGGL((k_hf_decode<true, true>), dim3(grid), dim3(256), 0, lc.stream, lengths, block_off,
+                               sub_bits, payload, (unsigned long long)payload_words, N, out, S, vec,
+                               (const uint32_t*)tab3);
+        } else {
+            hipLaunchKernelGGL((k_hf_decode<false, false>), dim3(grid), dim3(256), 0, lc.stream, lengths, block_off,
+                               sub_bits, payload, (unsigned long long)payload_words, N, out, S, vec,
+                               (const uint32_t*)nullptr);
+        }
     }
     hipLaunchKernelGGL(k_hf_decode_finalize, dim3(1), dim3(1), 0, lc.stream, (const HfState*)S, N, info);
     timer_end(lc.timer, ST_HUFF, lc.stream);
