@@ -18,6 +18,8 @@ constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kHistCopies = 32;      // LDS-privatised histogram copies (one per half-wave lane)
 constexpr int kHistStride = 257;     // copy stride: lane c + bin b lands in bank (c + b) mod 32
 constexpr int kScanBlocks = 1024;    // fixed block count of the device-sized scans
+// MI355X's last-level (Infinity) cache, shared by the XCDs
+constexpr int64_t kLastLevelCache = 256ll << 20;
 constexpr int kKeepGrid = 512;       // workgroups of the keep rule
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kQrFine = 1 << 15;  // code classes (q mod 2^15) of the fused 16-bit proxy pass
@@ -265,6 +267,31 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Cross-lane moves by DPP (a VALU operand modifier, no LDS traffic).  Lane i
+// reads lane i + n (row_shl n) or i - n (row_shr n) of its row of 16 lanes,
+// the lane given by a quad pattern of its group of 4, lane 15 (31) broadcast
+// to the rows after it, or lane i - 1 of the wave (wave_shr 1).  A lane whose
+// source lies outside its row or wave, or whose row is not in ROWS, gets `old`.
+constexpr int kDppRowShl = 0x100, kDppRowShr = 0x110, kDppWaveShr1 = 0x138, kDppBcast15 = 0x142,
+              kDppBcast31 = 0x143, kDppQuadXor1 = 0xB1, kDppQuadXor2 = 0x4E;
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t old, uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWS, 0xF, false);
+}
+
+// Inclusive prefix sum over the 64 lanes: shifts 1, 2, 4, 8 inside each row
+// of 16, then the total of row 0 added to row 1 and of row 2 to row 3, then
+// that of rows 0-1 to rows 2-3.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    v += dpp_u32<kDppRowShr + 1>(0u, v);
+    v += dpp_u32<kDppRowShr + 2>(0u, v);
+    v += dpp_u32<kDppRowShr + 4>(0u, v);
+    v += dpp_u32<kDppRowShr + 8>(0u, v);
+    v += dpp_u32<kDppBcast15, 0xA>(0u, v);
+    v += dpp_u32<kDppBcast31, 0xC>(0u, v);
+    return v;
 }
 
 template <typename T>

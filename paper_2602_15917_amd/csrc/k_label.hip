@@ -146,21 +146,49 @@ __device__ __forceinline__ void mask_load64_16(const uint16_t* proxy, int64_t wb
     for (int k = 0; k < 8; ++k) v[k] = k * 8 + lane / 8 < nvalid ? ld_stream(src + k * 64) : make_uint4(0, 0, 0, 0);
 }
 
-__device__ __forceinline__ uint64_t mask_words64_16(const uint4 (&v)[8], uint32_t Q2, uint32_t T2) {
+// Word assembly for mask_load64_16's layout.  Lane 8 g + j holds in byte k
+// of (hi:lo) the 8 mask bits of bits 8 j .. 8 j + 7 of word 8 k + g.  An
+// 8 x 8 byte transpose inside each group of 8 lanes (three butterfly stages
+// by DPP: at lane distance 4, 2, 1 a lane sends the four bytes it replaces
+// and takes its partner's) leaves word 8 k + g whole in lane 8 g + k; one
+// lane permutation then hands word l to lane l.
+__device__ __forceinline__ uint64_t words_from_bytes8(uint32_t lo, uint32_t hi) {
     const int lane = threadIdx.x % kWave;
+    {  // distance 4: the low lanes send bytes 4-7, the high ones bytes 0-3
+        const bool up = lane & 4;
+        const uint32_t snd = up ? lo : hi;
+        const uint32_t from_above = dpp_u32<kDppRowShl + 4>(0u, snd), from_below = dpp_u32<kDppRowShr + 4>(0u, snd);
+        if (up)
+            lo = from_below;
+        else
+            hi = from_above;
+    }
+    {  // distance 2: bytes 2, 3, 6, 7 of the lanes with bit 1 clear, 0, 1, 4, 5 of the others
+        const bool up = lane & 2;
+        const uint32_t snd = __builtin_amdgcn_perm(hi, lo, up ? 0x05040100u : 0x07060302u);
+        const uint32_t got = dpp_u32<kDppQuadXor2>(0u, snd);
+        lo = __builtin_amdgcn_perm(got, lo, up ? 0x03020504u : 0x05040100u);
+        hi = __builtin_amdgcn_perm(got, hi, up ? 0x03020706u : 0x07060100u);
+    }
+    {  // distance 1: odd bytes of the even lanes, even bytes of the odd ones
+        const bool up = lane & 1;
+        const uint32_t snd = __builtin_amdgcn_perm(hi, lo, up ? 0x06040200u : 0x07050301u);
+        const uint32_t got = dpp_u32<kDppQuadXor1>(0u, snd);
+        lo = __builtin_amdgcn_perm(got, lo, up ? 0x03050104u : 0x05020400u);
+        hi = __builtin_amdgcn_perm(got, hi, up ? 0x03070106u : 0x07020600u);
+    }
+    const int src = 8 * (lane & 7) + (lane >> 3);
+    const uint32_t wlo = (uint32_t)__shfl((int)lo, src), whi = (uint32_t)__shfl((int)hi, src);
+    return (uint64_t)wlo | ((uint64_t)whi << 32);
+}
+
+__device__ __forceinline__ uint64_t mask_words64_16(const uint4 (&v)[8], uint32_t Q2, uint32_t T2) {
     uint32_t lo = 0, hi = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) lo |= ge_halves8(v[k], Q2, T2) << (8 * k);
 #pragma unroll
     for (int k = 0; k < 4; ++k) hi |= ge_halves8(v[4 + k], Q2, T2) << (8 * k);
-    const int ld = lane >> 3, src0 = (lane & 7) * 8, sh = 8 * (ld & 3);
-    uint64_t word = 0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const uint32_t a = (uint32_t)__shfl((int)lo, src0 + j), b = (uint32_t)__shfl((int)hi, src0 + j);
-        word |= (uint64_t)(((ld < 4 ? a : b) >> sh) & 0xFFu) << (8 * j);
-    }
-    return word;
+    return words_from_bytes8(lo, hi);
 }
 
 // uint16 volumes read directly: a voxel is object when its code reaches the
@@ -197,31 +225,13 @@ __device__ __forceinline__ uint32_t ge_u16x8(const uint4& v, uint32_t X2) {
 
 // the mask words of mask_load64_16's loads, for uint16 values (all 0 when X2 is 0xFFFFFFFF)
 __device__ __forceinline__ uint64_t mask_words64_u16(const uint4 (&v)[8], uint32_t X2, bool none) {
-    const int lane = threadIdx.x % kWave;
     uint32_t lo = 0, hi = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) lo |= ge_u16x8(v[k], X2) << (8 * k);
 #pragma unroll
     for (int k = 0; k < 4; ++k) hi |= ge_u16x8(v[4 + k], X2) << (8 * k);
     if (none) lo = hi = 0u;
-    const int ld = lane >> 3, src0 = (lane & 7) * 8, sh = 8 * (ld & 3);
-    uint64_t word = 0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const uint32_t a = (uint32_t)__shfl((int)lo, src0 + j), b = (uint32_t)__shfl((int)hi, src0 + j);
-        word |= (uint64_t)(((ld < 4 ? a : b) >> sh) & 0xFFu) << (8 * j);
-    }
-    return word;
-}
-
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    const int lane = threadIdx.x % kWave;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t y = __shfl_up(v, o);
-        if (lane >= o) v += y;
-    }
-    return v;
+    return words_from_bytes8(lo, hi);
 }
 
 // Lane-per-word mapping of a wave step: with W <= 64 words per row, a step
@@ -260,7 +270,7 @@ __device__ __forceinline__ void slice_consts(const int32_t* __restrict__ thr, in
 // (1-byte proxy only): a threshold bin per z-slice instead of one.  MODE 0:
 // 1-byte bin proxy; 1: 16-bit code proxy; 2: the uint16 volume itself, rows
 // of whole 64-voxel words (its rows are then laid out as the 16-bit proxy's).
-template <int MODE>
+template <int MODE, bool NT>
 __device__ __forceinline__ void mask_runs_body(const VPart vp, const uint8_t* __restrict__ proxy, int64_t nx,
                                                int64_t nrows, int64_t W,
                                                DevState* S, uint64_t* __restrict__ maskbits,
@@ -298,7 +308,7 @@ __device__ __forceinline__ void mask_runs_body(const VPart vp, const uint8_t* __
                 m = 0;
             else if (wl.w == W - 1)
                 m &= lastmask;
-            const uint32_t prev_hi = __shfl_up((uint32_t)(m >> 32), 1);
+            const uint32_t prev_hi = dpp_u32<kDppWaveShr1>(0u, (uint32_t)(m >> 32));
             const uint64_t cin = (wl.w > 0) ? (uint64_t)(prev_hi >> 31) : 0ull;
             const uint64_t starts = m & ~((m << 1) | cin);
             const uint32_t cnt = (uint32_t)__popcll(starts);
@@ -306,26 +316,55 @@ __device__ __forceinline__ void mask_runs_body(const VPart vp, const uint8_t* __
             const uint32_t incl = wave_incl_scan(cnt);
             const uint32_t before = __shfl(incl, wl.seg_first > 0 ? wl.seg_first - 1 : 0);
             if (wl.row >= 0) {
-                maskbits[wl.row * W + wl.w] = m;
+                if constexpr (NT)
+                    __builtin_nontemporal_store((unsigned long long)m,
+                                                reinterpret_cast<unsigned long long*>(maskbits + wl.row * W + wl.w));
+                else
+                    maskbits[wl.row * W + wl.w] = m;
                 if (wl.w == W - 1) row_nruns[wl.row] = incl - (wl.seg_first > 0 ? before : 0u);
             }
         };
         if constexpr (P16) {
-            // software pipeline: the next step's eight loads per lane are in
-            // flight while this step's words are formed
-            const int64_t stride = nwaves * R;
-            int64_t row0 = wave * R;
-            uint4 cur[8];
-            mask_load64_16(proxy16, row0 * W, rows_at(row0) * W, cur);
-            for (; row0 < nrows; row0 += stride) {
-                uint4 nxt[8];
-                mask_load64_16(proxy16, (row0 + stride) * W, rows_at(row0 + stride) * W, nxt);
+            auto words = [&](const uint4 (&v)[8]) {
                 if constexpr (MODE == 2)
-                    finish(mask_words64_u16(cur, X2, none), row0);
+                    return mask_words64_u16(v, X2, none);
                 else
-                    finish(mask_words64_16(cur, Q2, T2), row0);
+                    return mask_words64_16(v, Q2, T2);
+            };
+            int64_t s = wave;  // step s covers rows s R .. s R + R - 1
+            if (R * W == kWave) {
+                // Steps of exactly 64 words: every load unconditional, so the
+                // next step's eight loads stay in flight while this step's
+                // words are formed (two register sets taking turns).  With no
+                // next whole step the wave loads the volume's first step in
+                // its place (in L2, never used).
+                const int64_t nfull = nrows / R;
+                const uint4* vb = reinterpret_cast<const uint4*>(proxy16) + lane;
+                auto load = [&](int64_t st, uint4 (&v)[8]) {
+                    const uint4* p = st < nfull ? vb + st * (kWave * 8) : vb;
 #pragma unroll
-                for (int k = 0; k < 8; ++k) cur[k] = nxt[k];
+                    for (int k = 0; k < 8; ++k) v[k] = ld_stream(p + k * kWave);
+                };
+                uint4 a[8], b[8];
+                if (s < nfull) {
+                    load(s, a);
+                    for (;;) {
+                        load(s + nwaves, b);
+                        finish(words(a), s * R);
+                        s += nwaves;
+                        if (s >= nfull) break;
+                        load(s + nwaves, a);
+                        finish(words(b), s * R);
+                        s += nwaves;
+                        if (s >= nfull) break;
+                    }
+                }
+            }
+            // other row widths, and a last step of fewer rows
+            for (; s * R < nrows; s += nwaves) {
+                uint4 v[8];
+                mask_load64_16(proxy16, s * R * W, rows_at(s * R) * W, v);
+                finish(words(v), s * R);
             }
         } else {
             // two steps per iteration, all loads of both issued first
@@ -400,20 +439,33 @@ __device__ __forceinline__ void mask_runs_body(const VPart vp, const uint8_t* __
 __device__ __forceinline__ void k_mask_runs_body(const VPart vp, const uint8_t* __restrict__ proxy, int64_t nx, int64_t nrows,
                                                       int64_t W, DevState* S, uint64_t* __restrict__ maskbits,
                                                       uint32_t* __restrict__ row_nruns,
-                                                      const int32_t* __restrict__ slice_thr, int64_t ny, int u16) {
+                                                      const int32_t* __restrict__ slice_thr, int64_t ny, int u16,
+                                                      int nt_words) {
     if (block_exit_l(S)) return;
-    if (u16)
-        mask_runs_body<2>(vp, proxy, nx, nrows, W, S, maskbits, row_nruns, nullptr, ny);
-    else if (S->p16)
-        mask_runs_body<1>(vp, proxy, nx, nrows, W, S, maskbits, row_nruns, nullptr, ny);
-    else
-        mask_runs_body<0>(vp, proxy, nx, nrows, W, S, maskbits, row_nruns, slice_thr, ny);
+    // NT: mask words stored non-temporally
+    if (u16) {
+        if (nt_words)
+            mask_runs_body<2, true>(vp, proxy, nx, nrows, W, S, maskbits, row_nruns, nullptr, ny);
+        else
+            mask_runs_body<2, false>(vp, proxy, nx, nrows, W, S, maskbits, row_nruns, nullptr, ny);
+    } else if (S->p16) {
+        if (nt_words)
+            mask_runs_body<1, true>(vp, proxy, nx, nrows, W, S, maskbits, row_nruns, nullptr, ny);
+        else
+            mask_runs_body<1, false>(vp, proxy, nx, nrows, W, S, maskbits, row_nruns, nullptr, ny);
+    } else {
+        if (nt_words)
+            mask_runs_body<0, true>(vp, proxy, nx, nrows, W, S, maskbits, row_nruns, slice_thr, ny);
+        else
+            mask_runs_body<0, false>(vp, proxy, nx, nrows, W, S, maskbits, row_nruns, slice_thr, ny);
+    }
 }
 __global__ __launch_bounds__(kBlock) void k_mask_runs(const uint8_t* __restrict__ proxy, int64_t nx, int64_t nrows,
                                                       int64_t W, DevState* S, uint64_t* __restrict__ maskbits,
                                                       uint32_t* __restrict__ row_nruns,
-                                                      const int32_t* __restrict__ slice_thr, int64_t ny, int u16) {
-    k_mask_runs_body(hw_part(), proxy, nx, nrows, W, S, maskbits, row_nruns, slice_thr, ny, u16);
+                                                      const int32_t* __restrict__ slice_thr, int64_t ny, int u16,
+                                                      int nt_words) {
+    k_mask_runs_body(hw_part(), proxy, nx, nrows, W, S, maskbits, row_nruns, slice_thr, ny, u16, nt_words);
 }
 
 hipError_t launch_mask_runs(const LaunchCtx& lc, const Geom& g, const Layout& L, const int32_t* slice_thr,
@@ -422,8 +474,12 @@ hipError_t launch_mask_runs(const LaunchCtx& lc, const Geom& g, const Layout& L,
     const int64_t R = g.W <= kWave ? kWave / g.W : 1;
     int grid = grid_for((g.nrows + R - 1) / R, kBlock / kWave, lc.grid_mask);
     const uint8_t* src = u16_in ? reinterpret_cast<const uint8_t*>(u16_in) : (const uint8_t*)L.proxy;
+    // Mask words that fit the last-level cache are stored normally: the run
+    // pass reads them straight back.  Larger ones are streamed out, so they
+    // do not evict the proxy lines still to be read.
+    const int nt_words = g.nrows * g.W * (int64_t)sizeof(uint64_t) > kLastLevelCache ? 1 : 0;
     launch_k<kBlock, k_mask_runs_body>(lc, k_mask_runs, dim3(grid), dim3(kBlock), 0, src, g.nx, g.nrows,
-                       g.W, L.S, L.maskbits, L.row_nruns, slice_thr, g.ny, u16_in ? 1 : 0);
+                       g.W, L.S, L.maskbits, L.row_nruns, slice_thr, g.ny, u16_in ? 1 : 0, nt_words);
     timer_end(lc.timer, ST_MASK_RUNS, lc.stream);
     return hipGetLastError();
 }
@@ -460,7 +516,7 @@ __device__ __forceinline__ void k_runs_write_lanes_body(const VPart vp, const ui
     for (int64_t row0 = wave * R; row0 < nrows; row0 += nwaves * R) {
         const WordLane wl = word_lane(row0, W, nrows);
         const uint64_t m = wl.row >= 0 ? maskbits[wl.row * W + wl.w] : 0ull;
-        const uint32_t prev_hi = __shfl_up((uint32_t)(m >> 32), 1);
+        const uint32_t prev_hi = dpp_u32<kDppWaveShr1>(0u, (uint32_t)(m >> 32));
         const uint64_t cin = (wl.w > 0) ? (uint64_t)(prev_hi >> 31) : 0ull;
         const uint64_t starts = m & ~((m << 1) | cin);
         const uint32_t cnt = (uint32_t)__popcll(starts);
