@@ -950,7 +950,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_cross(const uint32_t* __restrict
 
 constexpr int kLSeg = 8192;    // runs of a staged segment
 constexpr int kLRows = 3072;   // row offsets staged per segment (rows + 1)
-constexpr int kHalo = 6144;    // runs of the earlier rows staged for level 2
+constexpr int kHalo = 12288;   // runs of the earlier rows staged for level 2
 constexpr int kHaloRows = 3072;
 
 __device__ __forceinline__ uint32_t px(uint32_t v) { return v & 0xFFFFu; }
@@ -1055,16 +1055,33 @@ __device__ __forceinline__ void k_seg_cross_lds_body(const VPart vp, const uint3
         for (int i = threadIdx.x; i < kCrossCap; i += blockDim.x) tab[i] = kEmpty;
         const uint32_t r0 = run_row[s0];  // rows after r0 hold only runs > s0
         const uint64_t rlast = (uint64_t)r0 + ny + 1;
-        // the halo: earlier runs of rows hr0 .. r0, the only rows a head run can reach back to
+        // The halo: the earlier runs a head run (rows r0 .. rh) can reach.
+        // Those lie in rows hr0 .. pe of the previous slice (r - ny - 1 ..
+        // r - ny + 1) and in rows r0 - 1 and r0 (r - 1).  A head shorter
+        // than a slice leaves a gap between the two windows, which is not
+        // staged; otherwise they merge into rows hr0 .. r0.
+        const uint32_t rh = (uint64_t)run_row[s1 - 1] < rlast ? run_row[s1 - 1] : (uint32_t)rlast;
         const uint32_t hr0 = r0 > ny ? r0 - ny - 1 : 0u;
+        const int64_t pe64 = (int64_t)rh + 1 - (int64_t)ny;  // last previous-slice row reached
+        const uint32_t sr = r0 > 0 ? r0 - 1 : 0u;             // first same-slice row reached
+        const bool gap = pe64 + 1 < (int64_t)sr;
+        const uint32_t sS = gap ? sr : r0 + 1;                           // window S: rows sS .. r0
+        const int64_t pe = gap ? pe64 : (int64_t)r0;                     // window P: rows hr0 .. pe
+        const uint32_t nPr = pe >= (int64_t)hr0 ? (uint32_t)(pe - hr0 + 1) : 0u;  // rows of P
         const uint32_t h0 = run_off[hr0];
-        const bool staged = s0 - h0 <= (uint32_t)kHalo && r0 - hr0 + 2 <= (uint32_t)kHaloRows;
+        const uint32_t nP = nPr ? (gap ? run_off[hr0 + nPr] : s0) - h0 : 0u;     // runs of P
+        const uint32_t hS0 = gap ? run_off[sS] : s0;
+        const uint32_t nS = s0 - hS0;                                            // runs of S
+        const uint32_t nSr = gap ? r0 - sS + 1 : 0u;
+        const bool staged = nP + nS <= (uint32_t)kHalo && nPr + nSr + 2 <= (uint32_t)kHaloRows;
         if (staged) {
-            for (uint32_t i = threadIdx.x; i < s0 - h0; i += blockDim.x) {
-                hx[i] = xs[h0 + i] | (xe[h0 + i] << 16);
-                hp[i] = parent[h0 + i];
+            for (uint32_t i = threadIdx.x; i < nP + nS; i += blockDim.x) {
+                const uint32_t b = i < nP ? h0 + i : hS0 + (i - nP);
+                hx[i] = xs[b] | (xe[b] << 16);
+                hp[i] = parent[b];
             }
-            for (uint32_t i = threadIdx.x; i < r0 - hr0 + 2; i += blockDim.x) hoff[i] = run_off[hr0 + i];
+            for (uint32_t i = threadIdx.x; i < nPr + nSr + 2; i += blockDim.x)
+                hoff[i] = i <= nPr ? run_off[hr0 + i] : run_off[sS + (i - nPr - 1)];
         }
         __syncthreads();
         uint32_t last_a = kNone, last_b = kNone;
@@ -1077,17 +1094,31 @@ __device__ __forceinline__ void k_seg_cross_lds_body(const VPart vp, const uint3
             uint32_t ra = kNone;
             for_back_rows<C26>(r, z, y, ny, [&](uint32_t rb) {
                 if (rb > r0) return;
-                const uint32_t b0 = staged ? hoff[rb - hr0] : run_off[rb];
-                uint32_t b1 = staged ? hoff[rb - hr0 + 1] : run_off[rb + 1];
+                // staged: run b sits at hx[b - hb]
+                uint32_t b0, b1, hb = 0;
+                if (!staged) {
+                    b0 = run_off[rb];
+                    b1 = run_off[rb + 1];
+                } else if (rb >= sS) {
+                    b0 = hoff[nPr + 1 + (rb - sS)];
+                    b1 = hoff[nPr + 2 + (rb - sS)];
+                    hb = hS0 - nP;
+                } else if ((int64_t)rb <= pe) {
+                    b0 = hoff[rb - hr0];
+                    b1 = hoff[rb - hr0 + 1];
+                    hb = h0;
+                } else {
+                    return;  // in the gap: no head run reaches it
+                }
                 if (b1 > s0) b1 = s0;
                 if (b0 >= b1) return;
-                const uint32_t bb = staged ? first_touch_p<C26>(hx, b0 - h0, b1 - h0, as) + h0
+                const uint32_t bb = staged ? first_touch_p<C26>(hx, b0 - hb, b1 - hb, as) + hb
                                            : first_touch<C26>(xe, b0, b1, as);
                 for (uint32_t b = bb; b < b1; ++b) {
-                    const uint32_t bs = staged ? px(hx[b - h0]) : xs[b];
+                    const uint32_t bs = staged ? px(hx[b - hb]) : xs[b];
                     if (C26 ? bs > ae : bs >= ae) break;
                     if (ra == kNone) ra = parent[a];
-                    const uint32_t rbb = staged ? hp[b - h0] : parent[b];
+                    const uint32_t rbb = staged ? hp[b - hb] : parent[b];
                     if (ra == last_a && rbb == last_b) continue;
                     last_a = ra;
                     last_b = rbb;
