@@ -511,15 +511,21 @@ __device__ __forceinline__ void qh_flat(const VPart vp, const T* __restrict__ in
             if (vi >= nvec) continue;
             T v[VN];
             unpack16<T>(raw[k], v);
+            // row (from row0) and column of the vector's first value, then
+            // stepped along value by value
             const uint32_t t0 = (uint32_t)(x0 + (vi - s0) * VN);
+            uint32_t q = (uint32_t)((float)t0 * inv_nx);
+            if ((uint64_t)q * unx > t0) --q;
+            if ((uint64_t)(q + 1) * unx <= t0) ++q;
+            uint32_t xc = t0 - q * unx;
 #pragma unroll
             for (int j = 0; j < VN; ++j) {
-                const uint32_t t = t0 + (uint32_t)j;
-                uint32_t q = (uint32_t)((float)t * inv_nx);
-                if ((uint64_t)q * unx > t) --q;
-                if ((uint64_t)(q + 1) * unx <= t) ++q;
                 const uint32_t pb = qh_one<T, CODES, FIXED, DIV>(v[j], p, mine, bad);
-                if constexpr (STORE) proxy[(row0 + q) * P + (t - q * unx)] = (uint8_t)pb;
+                if constexpr (STORE) proxy[(row0 + q) * P + xc] = (uint8_t)pb;
+                if (++xc == unx) {
+                    xc = 0;
+                    ++q;
+                }
             }
         }
     }
