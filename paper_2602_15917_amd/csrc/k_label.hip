@@ -526,16 +526,15 @@ __device__ __forceinline__ void k_runs_write_lanes_body(const VPart vp, const ui
         // first 0-bit position of each word, then the minimum over later words of the row
         uint32_t smin = (wl.row >= 0 && m != ~0ull) ? (uint32_t)(64 * wl.w) + (uint32_t)__ffsll((unsigned long long)~m) - 1u
                                                    : kBig;
-        const int seg = wl.seg_first;
+        // lane + o lies in this lane's row exactly when lane + o < seg_end
+        const int seg_end = wl.seg_first + (int)W;
 #pragma unroll
         for (int o = 1; o < kWave; o <<= 1) {
             const uint32_t other = __shfl_down(smin, o);
-            const int oseg = __shfl_down(seg, o);
-            if (lane + o < kWave && oseg == seg) smin = other < smin ? other : smin;
+            if (lane + o < seg_end) smin = other < smin ? other : smin;
         }
         uint32_t next_zero = __shfl_down(smin, 1);
-        const int nseg = __shfl_down(seg, 1);
-        if (lane + 1 >= kWave || nseg != seg || wl.w == W - 1) next_zero = kBig;
+        if (lane + 1 >= seg_end) next_zero = kBig;
         if (next_zero > (uint32_t)nx) next_zero = (uint32_t)nx;
         if (T == 0) continue;  // uniform
         const uint32_t kb = run_off[row0];  // the step's first run
