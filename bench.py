@@ -687,6 +687,7 @@ def section_batched(args):
     ctx = roix.Context(0, need + (64 << 20))
     ctx.set_param("batch_group", args.batch_group)
     ctx.set_param("batch_graph", args.batch_graph)
+    ctx.set_param("batch_lanes", args.batch_lanes)
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
@@ -1013,6 +1014,8 @@ def main():
     ap.add_argument("--batch-volumes", type=int, default=64)
     ap.add_argument("--batch-group", type=int, default=0,
                     help="volumes per launch group of the batched path (0: as many as the arena holds)")
+    ap.add_argument("--batch-lanes", type=int, default=2, choices=[1, 2, 3, 4],
+                    help="concurrent launch sequences of the batched call")
     ap.add_argument("--batch-graph", type=int, default=0, choices=[0, 1],
                     help="1: capture the batch into a HIP graph and replay it; 0: launch eagerly")
     args = ap.parse_args()

@@ -558,6 +558,13 @@ roix_status roix_fused_batch(roix_ctx* ctx, int32_t n, const roix_volume_desc* v
  *                    seg_grid workgroups, at least 2048 each)
  *   "batch_group"    volumes per launch group of roix_fused_batch (0 = as
  *                    many as the arena holds; 1 = one volume at a time)
+ *   "batch_lanes"    1..4 concurrent launch sequences of roix_fused_batch
+ *                    (default 2): volume i goes to lane i mod lanes, each lane
+ *                    on its own part of the arena; lane 0 runs on the caller's
+ *                    stream, the others on streams of the context that start
+ *                    after the call's earlier work on the caller's stream and
+ *                    that stream waits for before its next work.  One lane
+ *                    when batch_graph is 1 or a volume does not fit a part.
  *   "batch_graph"    1 = capture/replay batches as a HIP graph, 0 = launch
  *                    directly (default: a batch is about 30 launches, and
  *                    their direct launch costs less host time than the

@@ -662,6 +662,7 @@ roix_status roix_ctx_set_param(roix_ctx* ctx, const char* name, int64_t value) {
     else if (strcmp(name, "seg_runs") == 0 && value >= 0 && value <= 16384 && value % 256 == 0)
         ctx->seg_runs = (int)value;
     else if (strcmp(name, "batch_group") == 0 && value >= 0 && value <= (1 << 20)) ctx->batch_group = (int)value;
+    else if (strcmp(name, "batch_lanes") == 0 && value >= 1 && value <= 4) ctx->batch_lanes = (int)value;
     else if (strcmp(name, "batch_fused16_min_voxels") == 0 && value >= 0 && value <= (1ll << 40))
         ctx->batch_p16_min = (uint64_t)value;
     else if (strcmp(name, "batch_graph") == 0 && (value == 0 || value == 1)) ctx->batch_graph = (int)value;
@@ -681,6 +682,7 @@ roix_status roix_ctx_get_param(roix_ctx* ctx, const char* name, int64_t* value) 
     else if (strcmp(name, "stats_grid") == 0) *value = ctx->stats_grid;
     else if (strcmp(name, "seg_runs") == 0) *value = ctx->seg_runs;
     else if (strcmp(name, "batch_group") == 0) *value = ctx->batch_group;
+    else if (strcmp(name, "batch_lanes") == 0) *value = ctx->batch_lanes;
     else if (strcmp(name, "batch_fused16_min_voxels") == 0) *value = (int64_t)ctx->batch_p16_min;
     else if (strcmp(name, "batch_graph") == 0) *value = ctx->batch_graph;
     else if (strcmp(name, "compute_units") == 0) *value = ctx->cus;

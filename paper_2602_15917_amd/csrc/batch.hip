@@ -6,7 +6,8 @@
 // grid among the volumes of each merged launch by voxels.  The sequences are merged: each step launches one body for
 // every volume whose next launch it is, so each volume's launches keep their
 // order and a batch takes about as many launches as one volume, whatever
-// the number of volumes.  The argument tables of all launches go to the
+// the number of volumes (per lane: the volumes are dealt out to lanes, by
+// default two, whose sequences run concurrently on two streams).  The argument tables of all launches go to the
 // device in one copy; the launch sequence is captured into a HIP graph and
 // replayed while the batch's structure (bodies, grids, table offsets) is the
 // same -- the buffers may change from call to call.
@@ -26,6 +27,10 @@ void batch_destroy(BatchState& b) {
     if (b.ev_out) hipEventDestroy(b.ev_out);
     if (b.ev_copy) hipEventDestroy(b.ev_copy);
     if (b.origin) hipStreamDestroy(b.origin);
+    for (int l = 0; l < 3; ++l) {
+        if (b.lane_stream[l]) hipStreamDestroy(b.lane_stream[l]);
+        if (b.lane_done[l]) hipEventDestroy(b.lane_done[l]);
+    }
     if (b.pinned) hipHostFree(b.pinned);
     b = BatchState();
 }
@@ -111,7 +116,7 @@ bool pack(const std::vector<Recorder>& rec, std::vector<Merged>& ms, std::vector
 
 struct BatchPlan {
     std::vector<uint8_t> key;
-    std::vector<Merged> all;
+    std::vector<std::vector<Merged>> lanes;  // the merged launches of each lane, in order
 };
 
 namespace {
@@ -128,6 +133,12 @@ roix_status ready(BatchState& b) {
     if (!b.ev_out && hipEventCreateWithFlags(&b.ev_out, hipEventDisableTiming) != hipSuccess) return ROIX_EDEVICE;
     if (!b.ev_copy && hipEventCreateWithFlags(&b.ev_copy, hipEventDisableTiming) != hipSuccess) return ROIX_EDEVICE;
     if (!b.origin && hipStreamCreateWithFlags(&b.origin, hipStreamNonBlocking) != hipSuccess) return ROIX_EDEVICE;
+    for (int l = 0; l < 3; ++l) {
+        if (!b.lane_stream[l] && hipStreamCreateWithFlags(&b.lane_stream[l], hipStreamNonBlocking) != hipSuccess)
+            return ROIX_EDEVICE;
+        if (!b.lane_done[l] && hipEventCreateWithFlags(&b.lane_done[l], hipEventDisableTiming) != hipSuccess)
+            return ROIX_EDEVICE;
+    }
     return ROIX_OK;
 }
 
@@ -143,85 +154,105 @@ roix_status plan_batch(roix_ctx* ctx, int32_t n, const roix_volume_desc* vols, c
     uint8_t* const base = (uint8_t*)ctx->arena;
     hipStream_t stream = nullptr;  // recording launches nothing
     auto plan = std::make_shared<BatchPlan>();
-    std::vector<Merged>& all = plan->all;
     std::vector<uint8_t> blob;
-    // groups of consecutive volumes whose worst-case layouts fit the arena
-    // together (a volume too large for that gets the whole arena alone)
-    std::vector<std::pair<int, int>> groups;
-    for (int i = 0; i < n;) {
-        int j = i;
-        size_t used = 0;
-        while (j < n && (j == i || used + align256(need[j]) <= avail) &&
-               (ctx->batch_group <= 0 || j - i < ctx->batch_group)) {
-            used += align256(need[j]);
-            ++j;
+    // Lanes: volume i goes to lane i mod nl, each lane with its own part of
+    // the arena and its own launch sequence, the lanes running concurrently
+    // (so that one lane's stages bound by a few volumes' runs leave the chip
+    // to the other's).  One lane when the graph replays the batch or when a
+    // volume's worst-case layout does not fit a part.
+    int nl = ctx->batch_graph ? 1 : std::max(1, std::min<int>(ctx->batch_lanes, n));
+    size_t part = nl > 1 ? (avail / (size_t)nl) & ~(size_t)255 : avail;
+    for (int i = 0; i < n && nl > 1; ++i)
+        if (align256(need[i]) > part) {
+            nl = 1;
+            part = avail;
         }
-        groups.emplace_back(i, j);
-        i = j;
-    }
+    plan->lanes.resize((size_t)nl);
+    for (int l = 0; l < nl; ++l) {
+        std::vector<Merged>& all = plan->lanes[(size_t)l];
+        std::vector<int> idx;
+        for (int i = l; i < n; i += nl) idx.push_back(i);
+        const int m = (int)idx.size();
+        uint8_t* const lbase = base + (size_t)l * part;
+        // groups of consecutive volumes of the lane whose worst-case layouts fit
+        // its part together (a volume too large for that gets the whole part alone)
+        std::vector<std::pair<int, int>> groups;  // positions in idx
+        for (int a = 0; a < m;) {
+            int c = a;
+            size_t used = 0;
+            while (c < m && (c == a || used + align256(need[idx[c]]) <= part) &&
+                   (ctx->batch_group <= 0 || c - a < ctx->batch_group)) {
+                used += align256(need[idx[c]]);
+                ++c;
+            }
+            groups.emplace_back(a, c);
+            a = c;
+        }
 
-    for (const auto& gr : groups) {
-        const int i0 = gr.first, i1 = gr.second;
-        std::vector<Recorder> rec((size_t)(i1 - i0)), half((size_t)(i1 - i0));
-        size_t off = 0;
-        for (int i = i0; i < i1; ++i) {
-            const roix_volume_desc& d = vols[i];
-            const size_t bytes = (i1 - i0 == 1) ? avail : align256(need[i]);
-            Layout L;
-            int k = kind[i];
-            if (i1 - i0 == 1) k = proxy_kind_for(gs[i], (roix_dtype)d.dtype, bytes, ctx->batch_p16_min);
-            if (!carve_at(base + off, bytes, gs[i], &L, k)) return ROIX_ENOMEM;
-            off += bytes;
-            // the plain launch parameters, recorded twice: as they are, and
-            // with the grids of the passes whose work follows the voxels
-            // (range, quantise + histogram, mask words and runs) halved,
-            // which tells those launches apart.  The others keep the plain
-            // grid: their work follows runs, components or codes, which only
-            // the device knows, and a volume of few voxels may hold many.
-            for (int pass = 0; pass < 2; ++pass) {
-                LaunchCtx lc = lctx(ctx, stream);
-                lc.timer = nullptr;
-                lc.rec = pass == 0 ? &rec[(size_t)(i - i0)] : &half[(size_t)(i - i0)];
-                const double share = pass == 0 ? 1.0 : 0.5;
-                auto sc = [&](int v, int lo) {
-                    const int s = (int)std::lround((double)v * share);
-                    return std::max(lo, std::min(v, s));
-                };
-                lc.grid_read = sc(ctx->grid_read, 4);
-                lc.grid_mask = sc(ctx->grid_mask, 8);
-                lc.grid_vox = sc(ctx->grid_stream, 8);
-                const roix_status st =
-                    enqueue_fused(lc, gs[i], L, d.d_in, (roix_dtype)d.dtype, d.eb, &d.crit, &d.out);
-                if (st != ROIX_OK) return st;
-                if (lc.rec->bad) return ROIX_EDEVICE;
+        for (const auto& gr : groups) {
+            const int a0 = gr.first, a1 = gr.second;
+            std::vector<Recorder> rec((size_t)(a1 - a0)), half((size_t)(a1 - a0));
+            size_t off = 0;
+            for (int a = a0; a < a1; ++a) {
+                const int i = idx[a];
+                const roix_volume_desc& d = vols[i];
+                const size_t bytes = (a1 - a0 == 1) ? part : align256(need[i]);
+                Layout L;
+                int k = kind[i];
+                if (a1 - a0 == 1) k = proxy_kind_for(gs[i], (roix_dtype)d.dtype, bytes, ctx->batch_p16_min);
+                if (!carve_at(lbase + off, bytes, gs[i], &L, k)) return ROIX_ENOMEM;
+                off += bytes;
+                // the plain launch parameters, recorded twice: as they are, and
+                // with the grids of the passes whose work follows the voxels
+                // (range, quantise + histogram, mask words and runs) halved,
+                // which tells those launches apart.  The others keep the plain
+                // grid: their work follows runs, components or codes, which only
+                // the device knows, and a volume of few voxels may hold many.
+                for (int pass = 0; pass < 2; ++pass) {
+                    LaunchCtx lc = lctx(ctx, stream);
+                    lc.timer = nullptr;
+                    lc.rec = pass == 0 ? &rec[(size_t)(a - a0)] : &half[(size_t)(a - a0)];
+                    const double share = pass == 0 ? 1.0 : 0.5;
+                    auto sc = [&](int v, int lo) {
+                        const int s = (int)std::lround((double)v * share);
+                        return std::max(lo, std::min(v, s));
+                    };
+                    lc.grid_read = sc(ctx->grid_read, 4);
+                    lc.grid_mask = sc(ctx->grid_mask, 8);
+                    lc.grid_vox = sc(ctx->grid_stream, 8);
+                    const roix_status st =
+                        enqueue_fused(lc, gs[i], L, d.d_in, (roix_dtype)d.dtype, d.eb, &d.crit, &d.out);
+                    if (st != ROIX_OK) return st;
+                    if (lc.rec->bad) return ROIX_EDEVICE;
+                }
+                if (half[(size_t)(a - a0)].seq.size() != rec[(size_t)(a - a0)].seq.size()) return ROIX_EDEVICE;
             }
-            if (half[(size_t)(i - i0)].seq.size() != rec[(size_t)(i - i0)].seq.size()) return ROIX_EDEVICE;
+            std::vector<Merged> ms;
+            merge(rec, ms);
+            // A merged launch of a voxel-proportional pass splits its plain grid
+            // among its own volumes by their voxels (volumes of one group take
+            // different kernels -- flows, row alignments -- so a share of the
+            // whole group's voxels would leave each such launch part of the chip).
+            for (const Merged& m : ms) {
+                bool prop = false;
+                uint32_t cap = 0;
+                double nsum = 0.0;
+                for (const auto& w : m.who) {
+                    const uint32_t g = rec[(size_t)w.first].seq[w.second].grid;
+                    prop = prop || half[(size_t)w.first].seq[w.second].grid < g;
+                    cap = std::max(cap, g);
+                    nsum += (double)gs[idx[a0 + w.first]].N;
+                }
+                if (!prop || nsum <= 0.0) continue;
+                for (const auto& w : m.who) {
+                    uint32_t& g = rec[(size_t)w.first].seq[w.second].grid;
+                    const double want = std::round((double)cap * (double)gs[idx[a0 + w.first]].N / nsum);
+                    g = std::min(g, std::max<uint32_t>(std::min<uint32_t>(g, 8u), (uint32_t)want));
+                }
+            }
+            if (!pack(rec, ms, blob)) return ROIX_EINVAL;
+            all.insert(all.end(), ms.begin(), ms.end());
         }
-        std::vector<Merged> ms;
-        merge(rec, ms);
-        // A merged launch of a voxel-proportional pass splits its plain grid
-        // among its own volumes by their voxels (volumes of one group take
-        // different kernels -- flows, row alignments -- so a share of the
-        // whole group's voxels would leave each such launch part of the chip).
-        for (const Merged& m : ms) {
-            bool prop = false;
-            uint32_t cap = 0;
-            double nsum = 0.0;
-            for (const auto& w : m.who) {
-                const uint32_t g = rec[(size_t)w.first].seq[w.second].grid;
-                prop = prop || half[(size_t)w.first].seq[w.second].grid < g;
-                cap = std::max(cap, g);
-                nsum += (double)gs[i0 + w.first].N;
-            }
-            if (!prop || nsum <= 0.0) continue;
-            for (const auto& w : m.who) {
-                uint32_t& g = rec[(size_t)w.first].seq[w.second].grid;
-                const double want = std::round((double)cap * (double)gs[i0 + w.first].N / nsum);
-                g = std::min(g, std::max<uint32_t>(std::min<uint32_t>(g, 8u), (uint32_t)want));
-            }
-        }
-        if (!pack(rec, ms, blob)) return ROIX_EINVAL;
-        all.insert(all.end(), ms.begin(), ms.end());
     }
     if (blob.size() > reserve) return ROIX_ENOMEM;
     // the tables go through pinned memory: an asynchronous copy from
@@ -280,26 +311,37 @@ extern "C" roix_status roix_fused_batch(roix_ctx* ctx, int32_t n, const roix_vol
     {
         auto put = [&](const void* p, size_t k) { pkey.insert(pkey.end(), (const uint8_t*)p, (const uint8_t*)p + k); };
         put(vols, sizeof(roix_volume_desc) * (size_t)n);
-        const int64_t prm[12] = {(int64_t)(uintptr_t)ctx->arena, (int64_t)ctx->arena_bytes, ctx->grid_stream,
+        const int64_t prm[14] = {(int64_t)(uintptr_t)ctx->arena, (int64_t)ctx->arena_bytes, ctx->grid_stream,
                                  ctx->grid_read, ctx->grid_emit, ctx->grid_mask, ctx->seg_grid, ctx->seg_runs,
                                  ctx->stats_grid, (int64_t)ctx->p16_min, (int64_t)ctx->batch_p16_min,
-                                 ctx->batch_group};
+                                 ctx->batch_group, ctx->batch_lanes, ctx->batch_graph};
         put(prm, sizeof prm);
     }
     if (!b.plan || b.plan->key != pkey) {
         const roix_status st = plan_batch(ctx, n, vols, gs, kind, need, avail, reserve, pkey);
         if (st != ROIX_OK) return st;
     }
-    const std::vector<Merged>& all = b.plan->all;
+    const std::vector<std::vector<Merged>>& lanes = b.plan->lanes;
     // the tables go to the device on every call: plain calls between two
     // batches may have used the end of the arena
     ROIX_TRY(hipMemcpyAsync(dblob, b.pinned, b.pinned_bytes, hipMemcpyHostToDevice, stream));
     ROIX_TRY(hipEventRecord(b.ev_copy, stream));
     if (!ctx->batch_graph) {
-        issue(all, dblob, stream);
+        // lane 0 on the caller's stream, the others on the context's lane
+        // streams from the tables' copy on, the caller's stream waiting for
+        // every lane at the end
+        const int nl = (int)lanes.size();
+        if (nl > 1) ROIX_TRY(hipEventRecord(b.ev_in, stream));
+        for (int l = 1; l < nl; ++l) ROIX_TRY(hipStreamWaitEvent(b.lane_stream[l - 1], b.ev_in, 0));
+        for (int l = 0; l < nl; ++l) issue(lanes[(size_t)l], dblob, l == 0 ? stream : b.lane_stream[l - 1]);
         ROIX_TRY(hipGetLastError());
+        for (int l = 1; l < nl; ++l) {
+            ROIX_TRY(hipEventRecord(b.lane_done[l - 1], b.lane_stream[l - 1]));
+            ROIX_TRY(hipStreamWaitEvent(stream, b.lane_done[l - 1], 0));
+        }
         return ROIX_OK;
     }
+    const std::vector<Merged>& all = lanes[0];  // one lane under the graph
     // the graph depends on the bodies, grids and table offsets only
     std::vector<uint8_t> key;
     auto put = [&](const void* p, size_t k) { key.insert(key.end(), (const uint8_t*)p, (const uint8_t*)p + k); };

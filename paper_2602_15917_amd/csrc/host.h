@@ -49,6 +49,9 @@ struct BatchState {
     std::vector<uint8_t> key;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // lanes after the first run on these streams, joined back by the events
+    hipStream_t lane_stream[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t lane_done[3] = {nullptr, nullptr, nullptr};
 };
 void batch_destroy(BatchState& b);
 
@@ -67,6 +70,7 @@ struct roix_ctx {
     int stats_grid = 512;
     uint64_t p16_min = 1ull << 22;  // fused16_min_voxels
     int batch_group = 0;  // volumes per launch group of a batch (0: as many as the arena holds)
+    int batch_lanes = 2;  // concurrent launch sequences of a batch (volumes dealt out in turn)
     // smallest float32 volume a batch quantises in one pass: below this the
     // per-workgroup class tables of that pass cost more than a second read
     uint64_t batch_p16_min = 1ull << 26;

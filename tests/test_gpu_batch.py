@@ -103,13 +103,16 @@ def test_batch_subsets_and_order(batch_env):
             _outputs_equal(items[i][4].collect(), plain[i])
 
 
-@pytest.mark.parametrize("group,graph", [(1, 1), (2, 0), (3, 1), (5, 1), (0, 0)])
-def test_batch_parameters_do_not_change_outputs(batch_env, group, graph):
-    # volumes per launch group (1: every volume alone), graph capture or not
+@pytest.mark.parametrize("group,graph,lanes", [(1, 1, 2), (2, 0, 1), (3, 1, 2), (5, 1, 2), (0, 0, 1), (0, 0, 2),
+                                               (0, 0, 3), (2, 0, 4), (1, 0, 2)])
+def test_batch_parameters_do_not_change_outputs(batch_env, group, graph, lanes):
+    # volumes per launch group (1: every volume alone), graph capture or not,
+    # concurrent lanes (each on its own stream and part of the arena)
     ctx, roix, torch, items, plain = batch_env
     ctx.set_param("batch_group", group)
     ctx.set_param("batch_graph", graph)
-    log(f"[case] batch group={group} graph={graph}")
+    ctx.set_param("batch_lanes", lanes)
+    log(f"[case] batch group={group} graph={graph} lanes={lanes}")
     for it in items:
         it[4].stream.zero_()
     ctx.fused_batch(items)
@@ -118,6 +121,7 @@ def test_batch_parameters_do_not_change_outputs(batch_env, group, graph):
         _outputs_equal(it[4].collect(), plain[i])
     ctx.set_param("batch_group", 0)
     ctx.set_param("batch_graph", 1)
+    ctx.set_param("batch_lanes", 2)
 
 
 def test_batch_small_arena_splits_into_groups(batch_env):
